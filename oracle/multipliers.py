@@ -1,0 +1,152 @@
+"""Canonical multipliers: the minimum-norm solution of the stationarity equations
+of Section VII, at any horizon.
+
+With g^x_i, g^u_i from eq. (objective-gradients) evaluated at the recovered
+(x, u), eqs. (stage-stationarity) and (terminal-stationarity) with merged rows
+read
+
+    lambda_i = A_i^T lambda_{i+1} + E_i^T mu_i + g^x_i          (i = 0..N-1)
+    0        = B_i^T lambda_{i+1} + F_i^T mu_i + g^u_i
+    lambda_N = E_N^T mu_N + g^x_N,                 alpha = -lambda_0.
+
+They are affine "dynamics" running from lambda_N back to lambda_0 plus stagewise
+mixed equalities -- the dual relation of eq. (dual-base-system).  Minimising
+1/2 ||nu||^2 = 1/2 (sum_i |lambda_i|^2 + sum_i |mu_i|^2) subject to them is
+therefore itself an equality-constrained LQR problem in reversed time:
+
+    stage 0      : state in R^0, input mu_N, next state lambda_N = E_N^T mu_N + g^x_N
+    stage j=1..N : state lambda_{N-j+1}, input mu_{N-j} (i = N-j), next state
+                   lambda_i = A_i^T lambda_{i+1} + E_i^T mu_i + g^x_i,
+                   mixed rows B_i^T lambda_{i+1} + F_i^T mu_i + g^u_i = 0
+    terminal     : state lambda_0,
+    costs Q = I, R = I, no cross or linear terms.
+
+Its solution is unique (identity Hessian) and equals the minimum-norm
+multiplier vector; under LICQ it is the only multiplier vector.  It is solved
+with the sequential oracle itself.
+
+Accuracy.  In floating point the stationarity system inherits the optimality
+error of the computed (x, u) (about 1e-12 relative for the reduction), and
+where LICQ fails the minimum-norm multipliers amplify it.  Section VIII asks to
+verify the KKT residuals after reconstruction; here that residual also drives
+one step of iterative refinement: the correction delta of the primal solution
+solves the same constrained LQR with the residuals as data
+(``correction_problem``), and the multipliers are recomputed at w + delta.
+"""
+
+from __future__ import annotations
+
+from typing import Dict
+
+import numpy as np
+
+from workloads.generate import Problem
+
+from .relations import CONS_TOL, RANK_TOL
+from .sequential import solve_sequential
+
+# The stationarity system is consistent in exact arithmetic (Proposition 3); in
+# floating point its offsets inherit the primal solution's optimality error, so
+# the 0 = gamma test of the dual solve uses a looser relative threshold.
+DUAL_CONS_TOL = 1e-6
+
+
+def objective_gradients(prob, x, u):
+    """eq. (objective-gradients)."""
+    N = prob.N
+    gx = [prob.Q[i] @ x[i] + prob.M[i] @ u[i] + prob.q[i] for i in range(N)]
+    gu = [prob.M[i].T @ x[i] + prob.R[i] @ u[i] + prob.r[i] for i in range(N)]
+    gx.append(prob.Q[N] @ x[N] + prob.q[N])
+    return gx, gu
+
+
+def dual_problem(prob, x, u) -> Problem:
+    N = prob.N
+    nx, nu, nc = prob.nx, prob.nu, prob.nc
+    gx, gu = objective_gradients(prob, x, u)
+    Q, q, R, r, M, A, B, c, E, F, g = ([] for _ in range(11))
+    # stage 0: empty state, input mu_N
+    kN = nc[N]
+    Q.append(np.zeros((0, 0))); q.append(np.zeros(0))
+    R.append(np.eye(kN)); r.append(np.zeros(kN)); M.append(np.zeros((0, kN)))
+    A.append(np.zeros((nx[N], 0))); B.append(prob.E[N].T.copy()); c.append(gx[N].copy())
+    E.append(np.zeros((0, 0))); F.append(np.zeros((0, kN))); g.append(np.zeros(0))
+    for j in range(1, N + 1):
+        i = N - j
+        Q.append(np.eye(nx[i + 1])); q.append(np.zeros(nx[i + 1]))
+        R.append(np.eye(nc[i])); r.append(np.zeros(nc[i])); M.append(np.zeros((nx[i + 1], nc[i])))
+        A.append(prob.A[i].T.copy()); B.append(prob.E[i].T.copy()); c.append(gx[i].copy())
+        E.append(prob.B[i].T.copy()); F.append(prob.F[i].T.copy()); g.append(gu[i].copy())
+    # terminal: lambda_0
+    Q.append(np.eye(nx[0])); q.append(np.zeros(nx[0]))
+    E.append(np.zeros((0, nx[0]))); g.append(np.zeros(0))
+    return Problem(Q, q, R, r, M, A, B, c, E, F, g, np.zeros(0), {"dual_of": prob.meta})
+
+
+def minnorm_multipliers(prob, x, u, rank_tol: float = RANK_TOL, cons_tol: float = DUAL_CONS_TOL) -> Dict:
+    N = prob.N
+    d = dual_problem(prob, x, u)
+    sol = solve_sequential(d, rank_tol, cons_tol, check_lemma2=False)
+    if sol.status != "ok":
+        return {"status": "dual_" + sol.status, "lam": None, "mu": None}
+    lam = [None] * (N + 1)
+    mu = [None] * (N + 1)
+    for j in range(1, N + 2):
+        lam[N - j + 1] = sol.x[j]
+    for j in range(0, N + 1):
+        mu[N - j] = sol.u[j]
+    return {"status": "ok", "lam": lam, "mu": mu}
+
+
+def correction_problem(prob_h, sol):
+    """The problem solved by the correction delta = w(theta') - w(theta).
+
+    With (x, u, lambda, mu) the solution at theta and the data theta' of
+    ``prob_h``, delta minimises 1/2 delta^T H' delta + s^T delta subject to
+    J' delta + c'(w) = 0, where s = grad f'(w) + J'^T nu is the stationarity
+    residual of the old point in the new problem (adding J'^T nu to the linear
+    term changes the objective by a constant on the feasible set).  Every
+    linear term and offset of this problem is O(|theta' - theta|), so its
+    solution carries a small relative rounding error."""
+    p = prob_h.copy()
+    N = p.N
+    x, u, lam, mu = sol["x"], sol["u"], sol["lam"], sol["mu"]
+    qd, rd, cd, gd = [], [], [], []
+    for i in range(N):
+        qd.append(p.Q[i] @ x[i] + p.M[i] @ u[i] + p.q[i] - lam[i] + p.A[i].T @ lam[i + 1] + p.E[i].T @ mu[i])
+        rd.append(p.M[i].T @ x[i] + p.R[i] @ u[i] + p.r[i] + p.B[i].T @ lam[i + 1] + p.F[i].T @ mu[i])
+        cd.append(p.A[i] @ x[i] + p.B[i] @ u[i] + p.c[i] - x[i + 1])
+        gd.append(p.E[i] @ x[i] + p.F[i] @ u[i] + p.g[i])
+    qd.append(p.Q[N] @ x[N] + p.q[N] - lam[N] + p.E[N].T @ mu[N])
+    gd.append(p.E[N] @ x[N] + p.g[N])
+    p.q, p.r, p.c, p.g = qd, rd, cd, gd
+    p.x0 = p.x0 - x[0]
+    return p
+
+
+def solve_with_multipliers(prob, rank_tol: float = RANK_TOL, cons_tol: float = CONS_TOL,
+                           refine: int = 1) -> Dict:
+    """Primal solution of Algorithm 1 plus canonical multipliers, with ``refine``
+    steps of iterative refinement of the primal point."""
+    s = solve_sequential(prob, rank_tol, cons_tol)
+    out = {"status": s.status, "stage": s.stage, "x": s.x, "u": s.u, "seq": s}
+    if s.status != "ok":
+        out["lam"] = out["mu"] = None
+        return out
+    x, u = s.x, s.u
+    m = minnorm_multipliers(prob, x, u, rank_tol, DUAL_CONS_TOL)
+    for _ in range(refine):
+        if m["status"] != "ok":
+            break
+        cp = correction_problem(prob, {"x": x, "u": u, "lam": m["lam"], "mu": m["mu"]})
+        d = solve_sequential(cp, rank_tol, cons_tol)
+        if d.status != "ok":
+            break
+        x = [a + b for a, b in zip(x, d.x)]
+        u = [a + b for a, b in zip(u, d.u)]
+        m = minnorm_multipliers(prob, x, u, rank_tol, DUAL_CONS_TOL)
+    out["x"], out["u"] = x, u
+    out["lam"], out["mu"] = m["lam"], m["mu"]
+    if m["status"] != "ok":
+        out["status"] = m["status"]
+    return out
