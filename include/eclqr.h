@@ -1,0 +1,183 @@
+/*
+ * eclqr.h -- C ABI of the MI355X (gfx950) solver for linear
+ * equality-constrained LQR problems.
+ *
+ * Problem (paper: Section II, eq. (problem)), with the mixed rows and the
+ * state-only rows of a stage merged into one block:
+ *
+ *   min  sum_{i<N} 1/2 x_i'Q_i x_i + x_i'M_i u_i + 1/2 u_i'R_i u_i + q_i'x_i + r_i'u_i
+ *        + 1/2 x_N'Q_N x_N + q_N'x_N
+ *   s.t. x_0 = x0,
+ *        x_{i+1} = A_i x_i + B_i u_i + c_i               (i < N)
+ *        E_i x_i + F_i u_i + g_i = 0   (k_i rows)         (i < N)
+ *        E_N x_N + g_N = 0             (k_N rows, terminal)
+ *
+ * Dimensions may vary by stage (x_i in R^{n_i}, u_i in R^{m_i}); rows may be
+ * dependent or absent.  The solve follows Algorithm 1: the feasible-domain
+ * suffix scan over affine endpoint relations (Sections III-IV), the
+ * stage-parallel elimination (Section V), an associative-scan Riccati solve of
+ * the reduced LQR (Section VI), primal recovery (eq. (recovery-maps)) and the
+ * multipliers of Section VII (the minimum-norm solution of the stationarity
+ * equations).
+ *
+ * Conventions
+ * - All floating-point data are FP64.  Integers are int32 unless stated.
+ * - Matrices are row-major and dense.  Each field is one flat array: the
+ *   blocks of all stages of instance 0 in stage order, then instance 1, ...
+ *   The per-stage element offsets come from eclqr_plan_layout().
+ * - Q, q, E, g have N+1 blocks per instance (the last is the terminal block:
+ *   Q_N, q_N, E_N, g_N); R, r, M, A, B, c, F have N blocks; x0 has one.
+ * - Outputs: x has the layout of q (N+1 blocks), u the layout of r, lam the
+ *   layout of q (lam_0 .. lam_N, lam_{i+1} multiplies the dynamics of stage i
+ *   and lam_0 = -alpha, alpha the multiplier of x_0 = x0), mu the layout of g
+ *   (mu_i multiplies the rows of stage i, mu_N the terminal rows).  The
+ *   Lagrangian sign is f + nu'c(w) (Section VII).
+ * - Pointers named "device" must be device memory of the current HIP device;
+ *   "host" pointers are host memory.  The caller owns every buffer it passes.
+ * - `stream` is a hipStream_t (NULL = the default stream).  Solve and backward
+ *   only enqueue work; nothing synchronises except where stated.
+ * - Synchronous errors are returned as eclqr_status; a text description of
+ *   the last error of the calling thread is given by eclqr_last_error().
+ *   Numerical outcomes are written per instance to the device array status[]
+ *   (bit set, 0 = OK).  Outputs of an instance whose status is not OK are NaN.
+ */
+#ifndef ECLQR_H
+#define ECLQR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ECLQR_ABI_VERSION 1
+
+/* synchronous return codes */
+typedef enum {
+  ECLQR_SUCCESS = 0,
+  ECLQR_INVALID_ARGUMENT = 1,   /* bad dims, NULL pointer, misaligned buffer */
+  ECLQR_WORKSPACE_TOO_SMALL = 2,
+  ECLQR_HIP_ERROR = 3,          /* a HIP runtime call failed */
+  ECLQR_UNSUPPORTED = 4,        /* dims beyond what the kernels handle */
+  ECLQR_NO_DEVICE = 5
+} eclqr_status;
+
+/* per-instance outcome bits written to status[b] (device int32) */
+#define ECLQR_OK 0
+#define ECLQR_INFEASIBLE_SUFFIX 1   /* some suffix relation reads 0 = gamma (Algorithm 1) */
+#define ECLQR_INFEASIBLE_INITIAL 2  /* x0 outside X_0 (eq. (initial-feasibility)) */
+#define ECLQR_RANK_INCONSISTENT 4   /* nonzero residual after Lemma 2 (rank decisions) */
+#define ECLQR_NOT_CONVEX 8          /* a reduced input Hessian is not positive definite */
+#define ECLQR_INVALID_INPUT 16      /* NaN or Inf in the data */
+#define ECLQR_CAPACITY 32           /* a relation outgrew its on-chip tile */
+#define ECLQR_DUAL_FAILED 64        /* the multiplier (stationarity) solve failed */
+
+/* fields of the problem layout */
+enum {
+  ECLQR_F_Q = 0, ECLQR_F_q, ECLQR_F_R, ECLQR_F_r, ECLQR_F_M, ECLQR_F_A, ECLQR_F_B,
+  ECLQR_F_c, ECLQR_F_E, ECLQR_F_F, ECLQR_F_g, ECLQR_F_x0, ECLQR_NUM_FIELDS
+};
+
+typedef struct eclqr_plan eclqr_plan;
+
+/* Problem dimensions (host arrays, copied by eclqr_plan_create).
+ *   horizon[b] = N_b >= 1                     (batch entries)
+ *   nx: sum_b (N_b+1) state dims, instance-major (n_0 may be 0)
+ *   nu: sum_b N_b input dims
+ *   nc: sum_b (N_b+1) row counts, the last of each instance = terminal rows */
+typedef struct {
+  int32_t batch;
+  const int32_t* horizon;
+  const int32_t* nx;
+  const int32_t* nu;
+  const int32_t* nc;
+} eclqr_dims;
+
+/* Options (Section VIII numerical policy).  Fill with eclqr_default_options. */
+typedef struct {
+  double rank_tol;        /* pivot counts toward rank if > rank_tol*max(1,|largest pivot|); 1e-10 */
+  double cons_tol;        /* 0 = gamma accepted if |gamma| <= cons_tol*max(1,|offsets|); 1e-8 */
+  double dual_cons_tol;   /* same test inside the multiplier solve; 1e-6 */
+  int32_t multipliers;    /* 1: compute lam and mu; 0: primal only */
+  int32_t refine;         /* steps of iterative refinement of the primal point (0 or 1); 1 */
+  int32_t use_graph;      /* 1: replay the launch sequence as a captured hipGraph; 0 */
+  int32_t reserved[5];
+} eclqr_options;
+
+/* Device pointers to the problem data (layout from eclqr_plan_layout).  M may
+ * be NULL (zero cross terms). */
+typedef struct {
+  const double *Q, *q, *R, *r, *M, *A, *B, *c, *E, *F, *g, *x0;
+} eclqr_problem;
+
+/* Device output buffers.  lam and mu may be NULL when multipliers = 0. */
+typedef struct {
+  double *x, *u, *lam, *mu;
+  int32_t* status;   /* [batch] */
+} eclqr_solution;
+
+/* Device buffers for the backward pass: dL/dx, dL/du in (layout of q, r). */
+typedef struct {
+  const double *dx, *du;
+} eclqr_cotangent;
+
+/* Device gradient buffers, same layouts as the problem fields (M may be NULL). */
+typedef struct {
+  double *Q, *q, *R, *r, *M, *A, *B, *c, *E, *F, *g, *x0;
+} eclqr_grads;
+
+int eclqr_abi_version(void);
+void eclqr_default_options(eclqr_options* opt);
+const char* eclqr_status_string(int32_t status);
+const char* eclqr_last_error(void);
+
+/* Builds the host-side plan: layout, workspace map and the associative-scan
+ * schedules (balanced up-sweep / down-sweep, Section IV "Suffix scan").  Does
+ * not touch the GPU.  Errors: INVALID_ARGUMENT for N_b < 1, negative dims,
+ * UNSUPPORTED for a dimension above 64.  *out is NULL on error. */
+eclqr_status eclqr_plan_create(eclqr_plan** out, const eclqr_dims* dims, const eclqr_options* opt);
+void eclqr_plan_destroy(eclqr_plan* plan);
+
+/* Per-stage element offsets of one field.  *offsets points to plan-owned host
+ * memory valid until eclqr_plan_destroy; *count entries (stages or instances
+ * for x0); *total = elements of the flat array. */
+eclqr_status eclqr_plan_layout(const eclqr_plan* plan, int32_t field, const int64_t** offsets,
+                               int64_t* count, int64_t* total);
+
+/* Bytes of device workspace one solve (and one backward) needs; the caller
+ * allocates it with 256-byte alignment. */
+eclqr_status eclqr_plan_workspace_size(const eclqr_plan* plan, size_t* bytes);
+
+/* Forward solve (Algorithm 1 + Section VII).  Enqueued on `stream`; the first
+ * call with a given workspace uploads the plan's tables into it (one H2D copy).
+ * The workspace is reused by eclqr_backward, so keep it between the two. */
+eclqr_status eclqr_solve(eclqr_plan* plan, const eclqr_problem* prob, eclqr_solution* sol, void* ws,
+                         size_t ws_bytes, void* stream);
+
+/* Gradients of a loss L(x, u) with respect to every problem field
+ * (implicit differentiation of the KKT system; adjoint = the same constrained
+ * LQR with linear costs dL/dx, dL/du and zero offsets).  Requires the forward
+ * solve's outputs (x, u, lam, mu) and its workspace.  Valid where the
+ * multipliers are unique (LICQ). */
+eclqr_status eclqr_backward(eclqr_plan* plan, const eclqr_problem* prob, const eclqr_solution* sol,
+                            const eclqr_cotangent* ct, eclqr_grads* grads, void* ws, size_t ws_bytes,
+                            void* stream);
+
+/* KKT residual of Section IX per instance: out[4*b + j], j = 0 initial,
+ * 1 dynamics, 2 equalities (rows normalised by max(1, |coefficients|, |offset|)),
+ * 3 stationarity; infinity norms.  out is device memory [4*batch]. */
+eclqr_status eclqr_kkt_residual(eclqr_plan* plan, const eclqr_problem* prob, const eclqr_solution* sol,
+                                double* out, void* ws, size_t ws_bytes, void* stream);
+
+/* Introspection of the scan schedule (tests): number of levels and, for
+ * level l (0..levels-1, up-sweep then down-sweep), the task triples
+ * (left slot, right slot, output slot) in plan-owned host memory. */
+eclqr_status eclqr_plan_schedule(const eclqr_plan* plan, int32_t dual, int32_t* levels, int32_t level,
+                                 const int32_t** tasks, int32_t* ntasks);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ECLQR_H */

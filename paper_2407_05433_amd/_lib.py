@@ -1,0 +1,106 @@
+"""ctypes declarations of the C ABI in ``include/eclqr.h`` (argument
+marshalling only).  Loading fails loudly when ``libeclqr.so`` is missing:
+there is no fallback path."""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libeclqr.so")
+
+NUM_FIELDS = 12
+FIELDS = ("Q", "q", "R", "r", "M", "A", "B", "c", "E", "F", "g", "x0")
+FIELD_INDEX = {f: i for i, f in enumerate(FIELDS)}
+
+STATUS_BITS = {
+    1: "infeasible_suffix",
+    2: "infeasible_initial",
+    4: "rank_inconsistent",
+    8: "not_convex",
+    16: "invalid_input",
+    32: "capacity",
+    64: "dual_failed",
+}
+
+
+class Dims(C.Structure):
+    _fields_ = [("batch", C.c_int32), ("horizon", C.POINTER(C.c_int32)), ("nx", C.POINTER(C.c_int32)),
+                ("nu", C.POINTER(C.c_int32)), ("nc", C.POINTER(C.c_int32))]
+
+
+class Options(C.Structure):
+    _fields_ = [("rank_tol", C.c_double), ("cons_tol", C.c_double), ("dual_cons_tol", C.c_double),
+                ("multipliers", C.c_int32), ("refine", C.c_int32), ("use_graph", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
+
+
+class ProblemPtrs(C.Structure):
+    _fields_ = [(f, C.c_void_p) for f in FIELDS]
+
+
+class SolutionPtrs(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("u", C.c_void_p), ("lam", C.c_void_p), ("mu", C.c_void_p),
+                ("status", C.c_void_p)]
+
+
+class CotangentPtrs(C.Structure):
+    _fields_ = [("dx", C.c_void_p), ("du", C.c_void_p)]
+
+
+class GradPtrs(C.Structure):
+    _fields_ = [(f, C.c_void_p) for f in FIELDS]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded ``libeclqr.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2407_05433_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    L.eclqr_abi_version.restype = C.c_int
+    L.eclqr_default_options.argtypes = [C.POINTER(Options)]
+    L.eclqr_status_string.restype = C.c_char_p
+    L.eclqr_status_string.argtypes = [C.c_int32]
+    L.eclqr_last_error.restype = C.c_char_p
+    L.eclqr_plan_create.argtypes = [C.POINTER(C.c_void_p), C.POINTER(Dims), C.POINTER(Options)]
+    L.eclqr_plan_destroy.argtypes = [C.c_void_p]
+    L.eclqr_plan_destroy.restype = None
+    L.eclqr_plan_layout.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.POINTER(C.c_int64)), C.POINTER(C.c_int64),
+                                    C.POINTER(C.c_int64)]
+    L.eclqr_plan_workspace_size.argtypes = [C.c_void_p, C.POINTER(C.c_size_t)]
+    L.eclqr_plan_schedule.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_int32,
+                                      C.POINTER(C.POINTER(C.c_int32)), C.POINTER(C.c_int32)]
+    L.eclqr_solve.argtypes = [C.c_void_p, C.POINTER(ProblemPtrs), C.POINTER(SolutionPtrs), C.c_void_p, C.c_size_t,
+                              C.c_void_p]
+    L.eclqr_backward.argtypes = [C.c_void_p, C.POINTER(ProblemPtrs), C.POINTER(SolutionPtrs),
+                                 C.POINTER(CotangentPtrs), C.POINTER(GradPtrs), C.c_void_p, C.c_size_t, C.c_void_p]
+    L.eclqr_kkt_residual.argtypes = [C.c_void_p, C.POINTER(ProblemPtrs), C.POINTER(SolutionPtrs), C.c_void_p,
+                                     C.c_void_p, C.c_size_t, C.c_void_p]
+    for fn in ("eclqr_plan_create", "eclqr_plan_layout", "eclqr_plan_workspace_size", "eclqr_plan_schedule",
+               "eclqr_solve", "eclqr_backward", "eclqr_kkt_residual"):
+        getattr(L, fn).restype = C.c_int
+    _lib = L
+    return L
+
+
+class EclqrError(RuntimeError):
+    pass
+
+
+def check(code: int, what: str) -> None:
+    if code != 0:
+        msg = lib().eclqr_last_error().decode()
+        raise EclqrError(f"{what} failed (status {code}): {msg}")
+
+
+def status_names(code: int):
+    if code == 0:
+        return ["ok"]
+    return [name for bit, name in STATUS_BITS.items() if code & bit]

@@ -1,0 +1,441 @@
+// C ABI of the solver: plan management, workspace binding and the launch
+// sequence of Algorithm 1 (feasible-domain scan, stage elimination, reduced
+// LQR scan, recovery) plus the multipliers of Section VII.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "eclqr.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+using namespace eclqr;
+
+namespace {
+
+thread_local std::string g_err;
+
+eclqr_status fail(eclqr_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIP_OK(call)                                                                    \
+  do {                                                                                  \
+    hipError_t _e = (call);                                                             \
+    if (_e != hipSuccess)                                                               \
+      return fail(ECLQR_HIP_ERROR, std::string(#call) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+template <class T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+DevEngine dev_engine(const Engine& E, void* ws, size_t base) {
+  DevEngine d{};
+  char* b = static_cast<char*>(ws) + base;
+  d.st = reinterpret_cast<const StageInfo*>(b + E.o_stage);
+  d.slot_off = reinterpret_cast<const int64_t*>(b + E.o_slot_off);
+  d.slot_sa = reinterpret_cast<const int32_t*>(b + E.o_slot_na);
+  d.slot_sb = reinterpret_cast<const int32_t*>(b + E.o_slot_nb);
+  d.slot_cap = reinterpret_cast<const int32_t*>(b + E.o_slot_cap);
+  d.slot_rows = reinterpret_cast<int32_t*>(b + E.o_slot_rows);
+  d.tasks = reinterpret_cast<const int32_t*>(b + E.o_tasks);
+  d.nbar = reinterpret_cast<int32_t*>(b + E.o_nbar);
+  d.mbar = reinterpret_cast<int32_t*>(b + E.o_mbar);
+  d.arena = reinterpret_cast<double*>(b + E.o_arena);
+  for (int k = 0; k < SCAN_COUNT; ++k) d.scan[k] = reinterpret_cast<double*>(b + E.o_scan[k]);
+  d.resid = reinterpret_cast<double*>(b + E.o_resid);
+  d.scratch = reinterpret_cast<double*>(b + E.o_scratch);
+  d.scratch_per_block = E.scratch_per_block;
+  d.S = E.S;
+  d.B = E.B;
+  d.nslots = E.nslots;
+  d.nblocks = E.nblocks;
+  return d;
+}
+
+const int64_t* dev_sbase(const Engine& E, void* ws, size_t base) {
+  return reinterpret_cast<const int64_t*>(static_cast<char*>(ws) + base + E.o_sbase);
+}
+
+// Host images of the device tables of one engine.
+eclqr_status upload_engine(const Engine& E, void* ws, size_t base, hipStream_t s) {
+  char* b = static_cast<char*>(ws) + base;
+  std::vector<int64_t> off((size_t)E.nslots * SCAN_COUNT);
+  std::vector<int32_t> sa((size_t)E.nslots * 2), sb((size_t)E.nslots * 2);
+  for (int32_t q = 0; q < E.nslots; ++q) {
+    for (int k = 0; k < SCAN_COUNT; ++k) off[(size_t)k * E.nslots + q] = E.slot_off[k][q];
+    const int bi = E.slot_inst[q], s0 = E.slot_s[q], e0 = E.slot_e[q];
+    const int N = E.N[bi], L = N + 1;
+    const int64_t base_s = E.sbase[bi];
+    sa[q] = (int32_t)(base_s + s0);
+    sb[q] = (e0 == L) ? -1 : (int32_t)(base_s + e0);
+    sa[E.nslots + q] = (int32_t)(base_s + (N - s0));
+    sb[E.nslots + q] = (e0 == L) ? -1 : (int32_t)(base_s + (N - e0));
+  }
+  HIP_OK(hipMemcpyAsync(b + E.o_stage, E.st.data(), sizeof(StageInfo) * E.S, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(b + E.o_slot_off, off.data(), sizeof(int64_t) * off.size(), hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(b + E.o_slot_na, sa.data(), sizeof(int32_t) * sa.size(), hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(b + E.o_slot_nb, sb.data(), sizeof(int32_t) * sb.size(), hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(b + E.o_slot_cap, E.slot_cap.data(), sizeof(int32_t) * E.nslots, hipMemcpyHostToDevice, s));
+  if (!E.tasks.empty())
+    HIP_OK(hipMemcpyAsync(b + E.o_tasks, E.tasks.data(), sizeof(int32_t) * E.tasks.size(), hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(b + E.o_sbase, E.sbase.data(), sizeof(int64_t) * E.B, hipMemcpyHostToDevice, s));
+  // the copies read pageable host memory: wait before the vectors go out of scope
+  HIP_OK(hipStreamSynchronize(s));
+  return ECLQR_SUCCESS;
+}
+
+int g_max_lds = 65536;
+
+eclqr_status bind(Plan& p, void* ws, hipStream_t s) {
+  int dev = -1;
+  HIP_OK(hipGetDevice(&dev));
+  if (p.bound_ws == ws && p.bound_device == dev) return ECLQR_SUCCESS;
+  int lds = 0;
+  HIP_OK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  if (lds > 0) {
+    g_max_lds = lds;
+    relations_set_max_lds(lds);
+    eliminate_set_max_lds(lds);
+    lqr_set_max_lds(lds);
+  }
+  eclqr_status st = upload_engine(p.primal, ws, p.o_primal, s);
+  if (st != ECLQR_SUCCESS) return st;
+  st = upload_engine(p.dual, ws, p.o_dual, s);
+  if (st != ECLQR_SUCCESS) return st;
+  p.bound_ws = ws;
+  p.bound_device = dev;
+  return ECLQR_SUCCESS;
+}
+
+// One pass of the primal method of Algorithm 1 on the data `in`, writing x, u.
+eclqr_status run_engine(const Engine& E, const DevEngine& d, const Inputs& in, double* x, double* u,
+                        int32_t* status, Tols t, hipStream_t s) {
+  launch_validate(d, in, status, s);
+  launch_base_relation(d, in, t, status, E.base_maxp, E.base_ldw, s);
+  for (int l = 0; l < 2 * E.D; ++l) {
+    // rows of the stacked system that fit the device's LDS (larger tasks are flagged ECLQR_CAPACITY)
+    int rows = std::max(1, E.lvl_rows[l]);
+    while (rows > 1 && rel_lds_bytes(rows, E.lvl_ldw[l]) > (size_t)g_max_lds) --rows;
+    launch_rel_compose(d, E.lvl_begin[l], E.lvl_count[l], t, status, rows, E.lvl_ldw[l], s);
+  }
+  launch_domain(d, in, t, status, std::max(1, E.maxn), s);
+  launch_eliminate(d, in, t, status, std::max(1, E.maxm), E.elim_maxq, s);
+  for (int l = 0; l < 2 * E.D; ++l)
+    launch_ric_combine(d, E.lvl_begin[l], E.lvl_count[l], status, std::max(1, E.maxn), s);
+  launch_gains(d, status, std::max(1, E.maxm), s);
+  for (int l = 0; l < 2 * E.D; ++l) launch_fwd_combine(d, E.lvl_begin[l], E.lvl_count[l], s);
+  launch_recover(d, x, u, s);
+  HIP_OK(hipGetLastError());
+  return ECLQR_SUCCESS;
+}
+
+Inputs inputs_of(const eclqr_problem* p) {
+  Inputs in{};
+  in.f[IN_Q] = p->Q;
+  in.f[IN_q] = p->q;
+  in.f[IN_R] = p->R;
+  in.f[IN_r] = p->r;
+  in.f[IN_M] = p->M;
+  in.f[IN_A] = p->A;
+  in.f[IN_B] = p->B;
+  in.f[IN_c] = p->c;
+  in.f[IN_E] = p->E;
+  in.f[IN_F] = p->F;
+  in.f[IN_g] = p->g;
+  in.x0 = p->x0;
+  return in;
+}
+
+struct Views {
+  DevEngine P, D;
+  DualPtrs dp;
+  CorrPtrs cp;
+  double *dx, *du;
+  int32_t* dstatus;
+  double *cx, *cu, *clam, *cmu;
+};
+
+Views views(Plan& p, void* ws) {
+  Views v{};
+  v.P = dev_engine(p.primal, ws, p.o_primal);
+  v.D = dev_engine(p.dual, ws, p.o_dual);
+  for (int f = 0; f < IN_COUNT; ++f) v.dp.f[f] = at<double>(ws, p.o_dprob[f]);
+  v.dp.f[IN_M] = nullptr;
+  v.dp.pbase = dev_sbase(p.primal, ws, p.o_primal);
+  v.dp.dbase = dev_sbase(p.dual, ws, p.o_dual);
+  v.cp.q = at<double>(ws, p.o_corr[ECLQR_F_q]);
+  v.cp.r = at<double>(ws, p.o_corr[ECLQR_F_r]);
+  v.cp.c = at<double>(ws, p.o_corr[ECLQR_F_c]);
+  v.cp.g = at<double>(ws, p.o_corr[ECLQR_F_g]);
+  v.cp.x0 = at<double>(ws, p.o_corr[ECLQR_F_x0]);
+  v.dx = at<double>(ws, p.o_dx);
+  v.du = at<double>(ws, p.o_du);
+  v.dstatus = at<int32_t>(ws, p.o_dstatus);
+  v.cx = at<double>(ws, p.o_cx);
+  v.cu = at<double>(ws, p.o_cu);
+  v.clam = at<double>(ws, p.o_clam);
+  v.cmu = at<double>(ws, p.o_cmu);
+  return v;
+}
+
+Inputs dual_inputs(const Views& v) {
+  Inputs in{};
+  for (int f = 0; f < IN_COUNT; ++f) in.f[f] = v.dp.f[f];
+  in.f[IN_M] = nullptr;
+  in.x0 = at<double>(v.dp.f[IN_Q], 0);  // empty initial state: never read
+  return in;
+}
+
+// Multipliers at (x, u): build the reversed-time problem's offsets, solve it,
+// read lambda and mu off its solution.
+eclqr_status multipliers(Plan& p, const Views& v, const Inputs& in, const double* x, const double* u, double* lam,
+                         double* mu, int32_t* status, hipStream_t s) {
+  const Tols td{p.opt.rank_tol, p.opt.dual_cons_tol, 0};
+  launch_dual_vectors(v.P, in, x, u, v.D, v.dp, s);
+  launch_fill_i32(v.dstatus, 0, p.primal.B, s);
+  Inputs din = dual_inputs(v);
+  din.x0 = x;  // n_0 of the reversed problem is 0: any valid pointer
+  eclqr_status st = run_engine(p.dual, v.D, din, v.dx, v.du, v.dstatus, td, s);
+  if (st != ECLQR_SUCCESS) return st;
+  launch_dual_extract(v.P, v.D, v.dx, v.du, lam, mu, v.dp, s);
+  launch_merge_status(status, v.dstatus, ECLQR_DUAL_FAILED, p.primal.B, s);
+  return ECLQR_SUCCESS;
+}
+
+// Full solve of the problem `in`: primal, multipliers, optional refinement.
+eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, double* u, double* lam, double* mu,
+                       int32_t* status, bool want_mult, hipStream_t s) {
+  const Tols tp{p.opt.rank_tol, p.opt.cons_tol, 1};
+  eclqr_status st = run_engine(p.primal, v.P, in, x, u, status, tp, s);
+  if (st != ECLQR_SUCCESS) return st;
+  if (!want_mult) return ECLQR_SUCCESS;
+  st = multipliers(p, v, in, x, u, lam, mu, status, s);
+  if (st != ECLQR_SUCCESS) return st;
+  for (int it = 0; it < p.opt.refine; ++it) {
+    // correction problem: same matrices, residuals as data
+    launch_correction(v.P, in, x, u, lam, mu, v.cp, s);
+    Inputs cin = in;
+    cin.f[IN_q] = v.cp.q;
+    cin.f[IN_r] = v.cp.r;
+    cin.f[IN_c] = v.cp.c;
+    cin.f[IN_g] = v.cp.g;
+    cin.x0 = v.cp.x0;
+    const Tols tc{p.opt.rank_tol, p.opt.cons_tol, 0};
+    st = run_engine(p.primal, v.P, cin, v.cx, v.cu, status, tc, s);
+    if (st != ECLQR_SUCCESS) return st;
+    launch_axpy(x, v.cx, p.primal.total[ECLQR_F_q], s);
+    launch_axpy(u, v.cu, p.primal.total[ECLQR_F_r], s);
+    st = multipliers(p, v, in, x, u, lam, mu, status, s);
+    if (st != ECLQR_SUCCESS) return st;
+  }
+  return ECLQR_SUCCESS;
+}
+
+bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+int eclqr_abi_version(void) { return ECLQR_ABI_VERSION; }
+
+void eclqr_default_options(eclqr_options* opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->rank_tol = 1e-10;
+  opt->cons_tol = 1e-8;
+  opt->dual_cons_tol = 1e-6;
+  opt->multipliers = 1;
+  opt->refine = 1;
+  opt->use_graph = 0;
+}
+
+const char* eclqr_status_string(int32_t status) {
+  switch (status) {
+    case ECLQR_OK: return "ok";
+    case ECLQR_INFEASIBLE_SUFFIX: return "infeasible_suffix";
+    case ECLQR_INFEASIBLE_INITIAL: return "infeasible_initial";
+    case ECLQR_RANK_INCONSISTENT: return "rank_inconsistent";
+    case ECLQR_NOT_CONVEX: return "not_convex";
+    case ECLQR_INVALID_INPUT: return "invalid_input";
+    case ECLQR_CAPACITY: return "capacity";
+    case ECLQR_DUAL_FAILED: return "dual_failed";
+    default: return "multiple";
+  }
+}
+
+const char* eclqr_last_error(void) { return g_err.c_str(); }
+
+eclqr_status eclqr_plan_create(eclqr_plan** out, const eclqr_dims* dims, const eclqr_options* opt) {
+  if (!out) return fail(ECLQR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  if (!dims || !dims->horizon || !dims->nx || !dims->nu || !dims->nc)
+    return fail(ECLQR_INVALID_ARGUMENT, "dims or one of its arrays is NULL");
+  eclqr_options o;
+  if (opt) o = *opt;
+  else eclqr_default_options(&o);
+  if (!(o.rank_tol > 0) || !(o.cons_tol > 0) || !(o.dual_cons_tol > 0) || o.refine < 0 || o.refine > 4)
+    return fail(ECLQR_INVALID_ARGUMENT, "bad options");
+  eclqr_plan* p = new (std::nothrow) eclqr_plan();
+  if (!p) return fail(ECLQR_INVALID_ARGUMENT, "out of host memory");
+  std::string err;
+  try {
+    err = build_plan(p->p, dims, &o);
+  } catch (const std::exception& ex) {
+    err = std::string("plan construction failed: ") + ex.what();
+  }
+  if (!err.empty()) {
+    delete p;
+    return fail(err.find("dimension above") != std::string::npos ? ECLQR_UNSUPPORTED : ECLQR_INVALID_ARGUMENT, err);
+  }
+  *out = p;
+  return ECLQR_SUCCESS;
+}
+
+void eclqr_plan_destroy(eclqr_plan* plan) { delete plan; }
+
+eclqr_status eclqr_plan_layout(const eclqr_plan* plan, int32_t field, const int64_t** offsets, int64_t* count,
+                               int64_t* total) {
+  if (!plan || field < 0 || field >= ECLQR_NUM_FIELDS) return fail(ECLQR_INVALID_ARGUMENT, "bad plan or field");
+  const Engine& E = plan->p.primal;
+  if (offsets) *offsets = E.off[field].data();
+  if (count) *count = (int64_t)E.off[field].size();
+  if (total) *total = E.total[field];
+  return ECLQR_SUCCESS;
+}
+
+eclqr_status eclqr_plan_workspace_size(const eclqr_plan* plan, size_t* bytes) {
+  if (!plan || !bytes) return fail(ECLQR_INVALID_ARGUMENT, "NULL argument");
+  *bytes = plan->p.bytes;
+  return ECLQR_SUCCESS;
+}
+
+eclqr_status eclqr_plan_schedule(const eclqr_plan* plan, int32_t dual, int32_t* levels, int32_t level,
+                                 const int32_t** tasks, int32_t* ntasks) {
+  if (!plan) return fail(ECLQR_INVALID_ARGUMENT, "NULL plan");
+  const Engine& E = dual ? plan->p.dual : plan->p.primal;
+  if (levels) *levels = 2 * E.D;
+  if (level >= 0) {
+    if (level >= 2 * E.D) return fail(ECLQR_INVALID_ARGUMENT, "level out of range");
+    if (tasks) *tasks = E.tasks.data() + 3 * E.lvl_begin[level];
+    if (ntasks) *ntasks = (int32_t)E.lvl_count[level];
+  }
+  return ECLQR_SUCCESS;
+}
+
+eclqr_status eclqr_solve(eclqr_plan* plan, const eclqr_problem* prob, eclqr_solution* sol, void* ws,
+                         size_t ws_bytes, void* stream) {
+  if (!plan || !prob || !sol || !ws) return fail(ECLQR_INVALID_ARGUMENT, "NULL argument");
+  Plan& p = plan->p;
+  if (ws_bytes < p.bytes) return fail(ECLQR_WORKSPACE_TOO_SMALL, "workspace smaller than eclqr_plan_workspace_size");
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(ECLQR_INVALID_ARGUMENT, "workspace not 256-byte aligned");
+  const Engine& E = p.primal;
+  const void* req[] = {prob->Q, prob->q, prob->R, prob->r, prob->A, prob->B, prob->c, prob->E, prob->F, prob->g,
+                       prob->x0, sol->x, sol->u, sol->status};
+  const int64_t need[] = {E.total[ECLQR_F_Q], E.total[ECLQR_F_q], E.total[ECLQR_F_R], E.total[ECLQR_F_r],
+                          E.total[ECLQR_F_A], E.total[ECLQR_F_B], E.total[ECLQR_F_c], E.total[ECLQR_F_E],
+                          E.total[ECLQR_F_F], E.total[ECLQR_F_g], E.total[ECLQR_F_x0], E.total[ECLQR_F_q],
+                          E.total[ECLQR_F_r], 1};
+  for (size_t i = 0; i < sizeof(req) / sizeof(req[0]); ++i) {
+    if (need[i] > 0 && !req[i]) return fail(ECLQR_INVALID_ARGUMENT, "NULL data pointer for a non-empty field");
+    if (req[i] && !aligned(req[i])) return fail(ECLQR_INVALID_ARGUMENT, "misaligned data pointer");
+  }
+  const bool want = p.opt.multipliers != 0;
+  if (want && ((E.total[ECLQR_F_q] > 0 && !sol->lam) || (E.total[ECLQR_F_g] > 0 && !sol->mu)))
+    return fail(ECLQR_INVALID_ARGUMENT, "lam/mu are NULL but multipliers were requested");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  eclqr_status st = bind(p, ws, s);
+  if (st != ECLQR_SUCCESS) return st;
+  Views v = views(p, ws);
+  launch_fill_i32(sol->status, 0, E.B, s);
+  Inputs in = inputs_of(prob);
+  if (want) launch_dual_matrices(v.P, in, v.D, v.dp, s);
+  st = solve_all(p, v, in, sol->x, sol->u, sol->lam, sol->mu, sol->status, want, s);
+  if (st != ECLQR_SUCCESS) return st;
+  launch_finalize(v.P, sol->status, sol->x, sol->u, want ? sol->lam : nullptr, want ? sol->mu : nullptr, s);
+  HIP_OK(hipGetLastError());
+  return ECLQR_SUCCESS;
+}
+
+eclqr_status eclqr_backward(eclqr_plan* plan, const eclqr_problem* prob, const eclqr_solution* sol,
+                            const eclqr_cotangent* ct, eclqr_grads* grads, void* ws, size_t ws_bytes, void* stream) {
+  if (!plan || !prob || !sol || !ct || !grads || !ws) return fail(ECLQR_INVALID_ARGUMENT, "NULL argument");
+  Plan& p = plan->p;
+  if (ws_bytes < p.bytes) return fail(ECLQR_WORKSPACE_TOO_SMALL, "workspace smaller than eclqr_plan_workspace_size");
+  if (!sol->lam || !sol->mu || !ct->dx || !ct->du) return fail(ECLQR_INVALID_ARGUMENT, "backward needs lam, mu, dx, du");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  eclqr_status st = bind(p, ws, s);
+  if (st != ECLQR_SUCCESS) return st;
+  Views v = views(p, ws);
+  const Engine& E = p.primal;
+  // adjoint problem: same matrices, q <- dL/dx, r <- dL/du, zero offsets
+  Inputs in = inputs_of(prob);
+  double* zc = at<double>(ws, p.o_corr[ECLQR_F_c]);
+  double* zg = at<double>(ws, p.o_corr[ECLQR_F_g]);
+  double* zx = at<double>(ws, p.o_corr[ECLQR_F_x0]);
+  launch_fill(zc, 0.0, E.total[ECLQR_F_c], s);
+  launch_fill(zg, 0.0, E.total[ECLQR_F_g], s);
+  launch_fill(zx, 0.0, E.total[ECLQR_F_x0], s);
+  Inputs adj = in;
+  adj.f[IN_q] = ct->dx;
+  adj.f[IN_r] = ct->du;
+  adj.f[IN_c] = zc;
+  adj.f[IN_g] = zg;
+  adj.x0 = zx;
+  // adjoint outputs live in the caller's gradient buffers q, r until assembly
+  double* ax = grads->q;
+  double* au = grads->r;
+  double* al = at<double>(ws, p.o_clam);
+  double* am = at<double>(ws, p.o_cmu);
+  int32_t* astatus = at<int32_t>(ws, p.o_flag);
+  launch_fill_i32(astatus, 0, E.B, s);
+  // no refinement of the adjoint: the correction buffers hold its zero offsets
+  const int keep_refine = p.opt.refine;
+  p.opt.refine = 0;
+  launch_dual_matrices(v.P, in, v.D, v.dp, s);
+  st = solve_all(p, v, adj, ax, au, al, am, astatus, true, s);
+  p.opt.refine = keep_refine;
+  launch_merge_status(sol->status, astatus, ECLQR_DUAL_FAILED, E.B, s);
+  if (st != ECLQR_SUCCESS) return st;
+  GradPtrs g{};
+  g.f[IN_Q] = grads->Q;
+  g.f[IN_q] = grads->q;
+  g.f[IN_R] = grads->R;
+  g.f[IN_r] = grads->r;
+  g.f[IN_M] = grads->M;
+  g.f[IN_A] = grads->A;
+  g.f[IN_B] = grads->B;
+  g.f[IN_c] = grads->c;
+  g.f[IN_E] = grads->E;
+  g.f[IN_F] = grads->F;
+  g.f[IN_g] = grads->g;
+  g.x0 = grads->x0;
+  launch_grad_assemble(v.P, sol->x, sol->u, sol->lam, sol->mu, ax, au, al, am, g, s);
+  HIP_OK(hipGetLastError());
+  return ECLQR_SUCCESS;
+}
+
+eclqr_status eclqr_kkt_residual(eclqr_plan* plan, const eclqr_problem* prob, const eclqr_solution* sol, double* out,
+                                void* ws, size_t ws_bytes, void* stream) {
+  if (!plan || !prob || !sol || !out || !ws || !sol->lam || !sol->mu) return fail(ECLQR_INVALID_ARGUMENT, "NULL argument");
+  Plan& p = plan->p;
+  if (ws_bytes < p.bytes) return fail(ECLQR_WORKSPACE_TOO_SMALL, "workspace smaller than eclqr_plan_workspace_size");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  eclqr_status st = bind(p, ws, s);
+  if (st != ECLQR_SUCCESS) return st;
+  Views v = views(p, ws);
+  launch_kkt_residual(v.P, inputs_of(prob), sol->x, sol->u, sol->lam, sol->mu, dev_sbase(p.primal, ws, p.o_primal),
+                      out, s);
+  HIP_OK(hipGetLastError());
+  return ECLQR_SUCCESS;
+}
+
+}  // extern "C"

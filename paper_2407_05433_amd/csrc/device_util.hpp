@@ -1,0 +1,28 @@
+// Device-side accessors for the engine tables.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace eclqr {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ double* slot_ptr(const DevEngine& e, int kind, int slot) {
+  return e.scan[kind] + e.slot_off[(int64_t)kind * e.nslots + slot];
+}
+// variant 0: REL / RIC endpoints, variant 1: FWD endpoints
+__device__ __forceinline__ int slot_a(const DevEngine& e, int var, int slot) { return e.slot_sa[var * e.nslots + slot]; }
+__device__ __forceinline__ int slot_b(const DevEngine& e, int var, int slot) { return e.slot_sb[var * e.nslots + slot]; }
+
+__device__ __forceinline__ void flag(int32_t* status, int inst, int32_t bit) {
+  if (status) atomicOr(status + inst, bit);
+}
+
+__device__ __forceinline__ double* block_scratch(const DevEngine& e) {
+  return e.scratch + (int64_t)blockIdx.x * e.scratch_per_block;
+}
+
+}  // namespace eclqr

@@ -1,0 +1,445 @@
+// Multipliers (paper Section VII), refinement, residual (Section IX) and the
+// adjoint gradient assembly.  All kernels are stage-parallel and memory-bound.
+#include "dense.hpp"
+#include "device_util.hpp"
+#include "eclqr.h"
+
+namespace eclqr {
+
+
+// ---------------------------------------------------------------------------
+// Matrices of the reversed-time stationarity problem:
+//   stage 0:       A = [] (n_N x 0), B = E_N^T, R = I_{k_N}
+//   stage j=1..N:  A = A_i^T, B = E_i^T, E = B_i^T, F = F_i^T, Q = I, R = I  (i = N - j)
+//   terminal:      Q = I_{n_0}
+// and zero linear terms.  x0 of the reversed problem is empty.
+__global__ void __launch_bounds__(kBlock) k_dual_matrices(DevEngine p, Inputs in, DevEngine d, DualPtrs dp) {
+  for (int64_t ds = blockIdx.x; ds < d.S; ds += gridDim.x) {
+    const StageInfo sd = d.st[ds];
+    const int b = sd.inst;
+    const int N = sd.N - 1;
+    const int64_t s0 = dp.pbase[b];
+    const int ip = (sd.i == 0) ? N : ((sd.i <= N) ? N - sd.i : 0);
+    const StageInfo sp = p.st[s0 + ip];
+    double* Qd = dp.f[IN_Q] + sd.in[IN_Q];
+    double* qd = dp.f[IN_q] + sd.in[IN_q];
+    for (int idx = ECLQR_TID; idx < sd.n * sd.n; idx += ECLQR_NT) Qd[idx] = (idx / sd.n == idx % sd.n) ? 1.0 : 0.0;
+    for (int idx = ECLQR_TID; idx < sd.n; idx += ECLQR_NT) qd[idx] = 0.0;
+    if (sd.terminal) continue;
+    double* Rd = dp.f[IN_R] + sd.in[IN_R];
+    double* rd = dp.f[IN_r] + sd.in[IN_r];
+    for (int idx = ECLQR_TID; idx < sd.m * sd.m; idx += ECLQR_NT) Rd[idx] = (idx / sd.m == idx % sd.m) ? 1.0 : 0.0;
+    for (int idx = ECLQR_TID; idx < sd.m; idx += ECLQR_NT) rd[idx] = 0.0;
+    double* Ad = dp.f[IN_A] + sd.in[IN_A];
+    double* Bd = dp.f[IN_B] + sd.in[IN_B];
+    double* Ed = dp.f[IN_E] + sd.in[IN_E];
+    double* Fd = dp.f[IN_F] + sd.in[IN_F];
+    const double* Ep = in.f[IN_E] + sp.in[IN_E];  // k x n
+    // B^D = E^T  (n_i x k_i), also for the terminal block at dual stage 0
+    for (int idx = ECLQR_TID; idx < sp.k * sp.n; idx += ECLQR_NT) {
+      const int r = idx / sp.n, c = idx % sp.n;
+      Bd[c * sp.k + r] = Ep[idx];
+    }
+    if (sd.i >= 1) {
+      const double* Ap = in.f[IN_A] + sp.in[IN_A];  // np x n
+      const double* Bp = in.f[IN_B] + sp.in[IN_B];  // np x m
+      const double* Fp = in.f[IN_F] + sp.in[IN_F];  // k x m
+      for (int idx = ECLQR_TID; idx < sp.np * sp.n; idx += ECLQR_NT) {
+        const int r = idx / sp.n, c = idx % sp.n;
+        Ad[c * sp.np + r] = Ap[idx];
+      }
+      for (int idx = ECLQR_TID; idx < sp.np * sp.m; idx += ECLQR_NT) {
+        const int r = idx / sp.m, c = idx % sp.m;
+        Ed[c * sp.np + r] = Bp[idx];
+      }
+      for (int idx = ECLQR_TID; idx < sp.k * sp.m; idx += ECLQR_NT) {
+        const int r = idx / sp.m, c = idx % sp.m;
+        Fd[c * sp.k + r] = Fp[idx];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Offsets of the reversed-time problem: c^D_j = g^x_i, g^D_j = g^u_i at (x, u)
+// (eq. (objective-gradients)); c^D_0 = g^x_N.
+__global__ void __launch_bounds__(kBlock) k_dual_vectors(DevEngine p, Inputs in, const double* x, const double* u,
+                                                         DevEngine d, DualPtrs dp) {
+  for (int64_t ds = blockIdx.x; ds < d.S; ds += gridDim.x) {
+    const StageInfo sd = d.st[ds];
+    if (sd.terminal) continue;
+    const int b = sd.inst;
+    const int N = sd.N - 1;
+    const int64_t s0 = dp.pbase[b];
+    const int ip = (sd.i == 0) ? N : N - sd.i;
+    const StageInfo sp = p.st[s0 + ip];
+    const double* xs = x + sp.in[IN_q];
+    const double* Q = in.f[IN_Q] + sp.in[IN_Q];
+    const double* q = in.f[IN_q] + sp.in[IN_q];
+    double* cd = dp.f[IN_c] + sd.in[IN_c];
+    const double* M = (in.f[IN_M] && !sp.terminal) ? in.f[IN_M] + sp.in[IN_M] : nullptr;
+    const double* us = sp.terminal ? nullptr : u + sp.in[IN_r];
+    for (int i = ECLQR_TID; i < sp.n; i += ECLQR_NT) {
+      double v = q[i];
+      for (int l = 0; l < sp.n; ++l) v = fma(Q[i * sp.n + l], xs[l], v);
+      if (M)
+        for (int l = 0; l < sp.m; ++l) v = fma(M[i * sp.m + l], us[l], v);
+      cd[i] = v;
+    }
+    if (!sp.terminal) {
+      const double* R = in.f[IN_R] + sp.in[IN_R];
+      const double* r = in.f[IN_r] + sp.in[IN_r];
+      double* gd = dp.f[IN_g] + sd.in[IN_g];
+      for (int i = ECLQR_TID; i < sp.m; i += ECLQR_NT) {
+        double v = r[i];
+        for (int l = 0; l < sp.m; ++l) v = fma(R[i * sp.m + l], us[l], v);
+        if (M)
+          for (int l = 0; l < sp.n; ++l) v = fma(M[l * sp.m + i], xs[l], v);
+        gd[i] = v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// lambda_i = x^D_{N-i+1}, mu_i = u^D_{N-i}.
+__global__ void __launch_bounds__(kBlock) k_dual_extract(DevEngine p, DevEngine d, const double* dx, const double* du,
+                                                         double* lam, double* mu, DualPtrs dp) {
+  for (int64_t s = blockIdx.x; s < p.S; s += gridDim.x) {
+    const StageInfo sp = p.st[s];
+    const int N = sp.N;
+    const int64_t d0 = dp.dbase[sp.inst];
+    const StageInfo& sx = d.st[d0 + (N - sp.i + 1)];
+    const StageInfo& su = d.st[d0 + (N - sp.i)];
+    for (int i = ECLQR_TID; i < sp.n; i += ECLQR_NT) lam[sp.in[IN_q] + i] = dx[sx.in[IN_q] + i];
+    for (int i = ECLQR_TID; i < sp.k; i += ECLQR_NT) mu[sp.in[IN_g] + i] = du[su.in[IN_r] + i];
+  }
+}
+
+// Correction problem of one refinement step: the same constrained LQR with
+//   q <- stationarity residual of x (including -lambda_i + A'lambda_{i+1} + E'mu_i),
+//   r <- stationarity residual of u, c <- dynamics residual, g <- row residual,
+//   x0 <- x0 - x_0.
+__global__ void __launch_bounds__(kBlock) k_correction(DevEngine p, Inputs in, const double* x, const double* u,
+                                                       const double* lam, const double* mu, CorrPtrs cp) {
+  for (int64_t s = blockIdx.x; s < p.S; s += gridDim.x) {
+    const StageInfo st = p.st[s];
+    const int n = st.n, np = st.np, m = st.m, k = st.k;
+    const double* xs = x + st.in[IN_q];
+    const double* ls = lam + st.in[IN_q];
+    const double* ms = mu + st.in[IN_g];
+    const double* Q = in.f[IN_Q] + st.in[IN_Q];
+    const double* q = in.f[IN_q] + st.in[IN_q];
+    const double* E = in.f[IN_E] + st.in[IN_E];
+    const double* g = in.f[IN_g] + st.in[IN_g];
+    double* qo = cp.q + st.in[IN_q];
+    double* go = cp.g + st.in[IN_g];
+    if (st.terminal) {
+      for (int i = ECLQR_TID; i < n; i += ECLQR_NT) {
+        double v = q[i] - ls[i];
+        for (int l = 0; l < n; ++l) v = fma(Q[i * n + l], xs[l], v);
+        for (int l = 0; l < k; ++l) v = fma(E[l * n + i], ms[l], v);
+        qo[i] = v;
+      }
+      for (int i = ECLQR_TID; i < k; i += ECLQR_NT) {
+        double v = g[i];
+        for (int l = 0; l < n; ++l) v = fma(E[i * n + l], xs[l], v);
+        go[i] = v;
+      }
+      __syncthreads();
+      continue;
+    }
+    const StageInfo& st1 = p.st[s + 1];
+    const double* x1 = x + st1.in[IN_q];
+    const double* l1 = lam + st1.in[IN_q];
+    const double* us = u + st.in[IN_r];
+    const double* R = in.f[IN_R] + st.in[IN_R];
+    const double* r = in.f[IN_r] + st.in[IN_r];
+    const double* M = in.f[IN_M] ? in.f[IN_M] + st.in[IN_M] : nullptr;
+    const double* A = in.f[IN_A] + st.in[IN_A];
+    const double* B = in.f[IN_B] + st.in[IN_B];
+    const double* c = in.f[IN_c] + st.in[IN_c];
+    const double* F = in.f[IN_F] + st.in[IN_F];
+    double* ro = cp.r + st.in[IN_r];
+    double* co = cp.c + st.in[IN_c];
+    for (int i = ECLQR_TID; i < n; i += ECLQR_NT) {
+      double v = q[i] - ls[i];
+      for (int l = 0; l < n; ++l) v = fma(Q[i * n + l], xs[l], v);
+      if (M)
+        for (int l = 0; l < m; ++l) v = fma(M[i * m + l], us[l], v);
+      for (int l = 0; l < np; ++l) v = fma(A[l * n + i], l1[l], v);
+      for (int l = 0; l < k; ++l) v = fma(E[l * n + i], ms[l], v);
+      qo[i] = v;
+    }
+    for (int i = ECLQR_TID; i < m; i += ECLQR_NT) {
+      double v = r[i];
+      for (int l = 0; l < m; ++l) v = fma(R[i * m + l], us[l], v);
+      if (M)
+        for (int l = 0; l < n; ++l) v = fma(M[l * m + i], xs[l], v);
+      for (int l = 0; l < np; ++l) v = fma(B[l * m + i], l1[l], v);
+      for (int l = 0; l < k; ++l) v = fma(F[l * m + i], ms[l], v);
+      ro[i] = v;
+    }
+    for (int i = ECLQR_TID; i < np; i += ECLQR_NT) {
+      double v = c[i] - x1[i];
+      for (int l = 0; l < n; ++l) v = fma(A[i * n + l], xs[l], v);
+      for (int l = 0; l < m; ++l) v = fma(B[i * m + l], us[l], v);
+      co[i] = v;
+    }
+    for (int i = ECLQR_TID; i < k; i += ECLQR_NT) {
+      double v = g[i];
+      for (int l = 0; l < n; ++l) v = fma(E[i * n + l], xs[l], v);
+      for (int l = 0; l < m; ++l) v = fma(F[i * m + l], us[l], v);
+      go[i] = v;
+    }
+    if (st.i == 0)
+      for (int i = ECLQR_TID; i < n; i += ECLQR_NT) cp.x0[st.x0 + i] = in.x0[st.x0 + i] - xs[i];
+    __syncthreads();
+  }
+}
+
+__global__ void k_axpy(double* y, const double* x, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] += x[i];
+}
+__global__ void k_fill(double* y, double v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = v;
+}
+__global__ void k_fill_i32(int32_t* y, int32_t v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = v;
+}
+__global__ void k_merge_status(int32_t* status, const int32_t* other, int32_t bit, int32_t B) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < B; i += gridDim.x * blockDim.x)
+    if (other[i] != 0) status[i] |= bit;
+}
+
+// Outputs of an instance whose status is not OK become NaN.
+__global__ void __launch_bounds__(kBlock) k_finalize(DevEngine p, const int32_t* status, double* x, double* u,
+                                                     double* lam, double* mu) {
+  const double nan = __builtin_nan("");
+  for (int64_t s = blockIdx.x; s < p.S; s += gridDim.x) {
+    const StageInfo st = p.st[s];
+    if (status[st.inst] == 0) continue;
+    for (int i = ECLQR_TID; i < st.n; i += ECLQR_NT) {
+      x[st.in[IN_q] + i] = nan;
+      if (lam) lam[st.in[IN_q] + i] = nan;
+    }
+    for (int i = ECLQR_TID; i < st.m; i += ECLQR_NT) u[st.in[IN_r] + i] = nan;
+    if (mu)
+      for (int i = ECLQR_TID; i < st.k; i += ECLQR_NT) mu[st.in[IN_g] + i] = nan;
+  }
+}
+
+// KKT residual of Section IX, per stage: [initial, dynamics, equalities
+// (rows / max(1, |coefficients|, |offset|)), stationarity], infinity norms.
+__global__ void __launch_bounds__(kBlock) k_kkt_residual(DevEngine p, Inputs in, const double* x, const double* u,
+                                                         const double* lam, const double* mu) {
+  __shared__ double red[kBlock];
+  for (int64_t s = blockIdx.x; s < p.S; s += gridDim.x) {
+    const StageInfo st = p.st[s];
+    const int n = st.n, np = st.np, m = st.m, k = st.k;
+    const double* xs = x + st.in[IN_q];
+    const double* ls = lam + st.in[IN_q];
+    const double* ms = mu + st.in[IN_g];
+    const double* Q = in.f[IN_Q] + st.in[IN_Q];
+    const double* q = in.f[IN_q] + st.in[IN_q];
+    const double* E = in.f[IN_E] + st.in[IN_E];
+    const double* g = in.f[IN_g] + st.in[IN_g];
+    const double* us = st.terminal ? nullptr : u + st.in[IN_r];
+    const double* F = st.terminal ? nullptr : in.f[IN_F] + st.in[IN_F];
+    const double* M = (!st.terminal && in.f[IN_M]) ? in.f[IN_M] + st.in[IN_M] : nullptr;
+    double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
+    if (st.i == 0)
+      for (int i = ECLQR_TID; i < n; i += ECLQR_NT) r0 = fmax(r0, fabs(xs[i] - in.x0[st.x0 + i]));
+    for (int i = ECLQR_TID; i < k; i += ECLQR_NT) {
+      double v = g[i], den = fmax(1.0, fabs(g[i]));
+      for (int l = 0; l < n; ++l) {
+        v = fma(E[i * n + l], xs[l], v);
+        den = fmax(den, fabs(E[i * n + l]));
+      }
+      if (F)
+        for (int l = 0; l < m; ++l) {
+          v = fma(F[i * m + l], us[l], v);
+          den = fmax(den, fabs(F[i * m + l]));
+        }
+      r2 = fmax(r2, fabs(v) / den);
+    }
+    if (st.terminal) {
+      for (int i = ECLQR_TID; i < n; i += ECLQR_NT) {
+        double v = q[i] - ls[i];
+        for (int l = 0; l < n; ++l) v = fma(Q[i * n + l], xs[l], v);
+        for (int l = 0; l < k; ++l) v = fma(E[l * n + i], ms[l], v);
+        r3 = fmax(r3, fabs(v));
+      }
+    } else {
+      const StageInfo& st1 = p.st[s + 1];
+      const double* x1 = x + st1.in[IN_q];
+      const double* l1 = lam + st1.in[IN_q];
+      const double* R = in.f[IN_R] + st.in[IN_R];
+      const double* r = in.f[IN_r] + st.in[IN_r];
+      const double* A = in.f[IN_A] + st.in[IN_A];
+      const double* B = in.f[IN_B] + st.in[IN_B];
+      const double* c = in.f[IN_c] + st.in[IN_c];
+      for (int i = ECLQR_TID; i < np; i += ECLQR_NT) {
+        double v = c[i] - x1[i];
+        for (int l = 0; l < n; ++l) v = fma(A[i * n + l], xs[l], v);
+        for (int l = 0; l < m; ++l) v = fma(B[i * m + l], us[l], v);
+        r1 = fmax(r1, fabs(v));
+      }
+      for (int i = ECLQR_TID; i < n; i += ECLQR_NT) {
+        double v = q[i] - ls[i];
+        for (int l = 0; l < n; ++l) v = fma(Q[i * n + l], xs[l], v);
+        if (M)
+          for (int l = 0; l < m; ++l) v = fma(M[i * m + l], us[l], v);
+        for (int l = 0; l < np; ++l) v = fma(A[l * n + i], l1[l], v);
+        for (int l = 0; l < k; ++l) v = fma(E[l * n + i], ms[l], v);
+        r3 = fmax(r3, fabs(v));
+      }
+      for (int i = ECLQR_TID; i < m; i += ECLQR_NT) {
+        double v = r[i];
+        for (int l = 0; l < m; ++l) v = fma(R[i * m + l], us[l], v);
+        if (M)
+          for (int l = 0; l < n; ++l) v = fma(M[l * m + i], xs[l], v);
+        for (int l = 0; l < np; ++l) v = fma(B[l * m + i], l1[l], v);
+        for (int l = 0; l < k; ++l) v = fma(F[l * m + i], ms[l], v);
+        r3 = fmax(r3, fabs(v));
+      }
+    }
+    r0 = wg_reduce_max(r0, red);
+    r1 = wg_reduce_max(r1, red);
+    r2 = wg_reduce_max(r2, red);
+    r3 = wg_reduce_max(r3, red);
+    if (ECLQR_TID == 0) {
+      p.resid[4 * s + 0] = r0;
+      p.resid[4 * s + 1] = r1;
+      p.resid[4 * s + 2] = r2;
+      p.resid[4 * s + 3] = r3;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_resid_reduce(DevEngine p, const int64_t* sbase, double* out) {
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < p.B; b += gridDim.x * blockDim.x) {
+    const int64_t s0 = sbase[b];
+    const int N = p.st[s0].N;
+    double r[4] = {0, 0, 0, 0};
+    for (int i = 0; i <= N; ++i)
+      for (int j = 0; j < 4; ++j) r[j] = fmax(r[j], p.resid[4 * (s0 + i) + j]);
+    for (int j = 0; j < 4; ++j) out[4 * b + j] = r[j];
+  }
+}
+
+// Gradients from the forward solution (x, u, lambda, mu) and the adjoint
+// solution (a_x, a_u, a_lambda, a_mu) -- outer products of implicit
+// differentiation of the KKT system.
+__global__ void __launch_bounds__(kBlock) k_grad_assemble(DevEngine p, const double* x, const double* u,
+                                                          const double* lam, const double* mu, const double* ax,
+                                                          const double* au, const double* al, const double* am,
+                                                          GradPtrs g) {
+  for (int64_t s = blockIdx.x; s < p.S; s += gridDim.x) {
+    const StageInfo st = p.st[s];
+    const int n = st.n, np = st.np, m = st.m, k = st.k;
+    const double* xs = x + st.in[IN_q];
+    const double* axs = ax + st.in[IN_q];
+    const double* ms = mu + st.in[IN_g];
+    const double* ams = am + st.in[IN_g];
+    for (int idx = ECLQR_TID; idx < n * n; idx += ECLQR_NT) {
+      const int i = idx / n, j = idx % n;
+      g.f[IN_Q][st.in[IN_Q] + idx] = 0.5 * (axs[i] * xs[j] + xs[i] * axs[j]);
+    }
+    for (int i = ECLQR_TID; i < n; i += ECLQR_NT) g.f[IN_q][st.in[IN_q] + i] = axs[i];
+    for (int idx = ECLQR_TID; idx < k * n; idx += ECLQR_NT) {
+      const int i = idx / n, j = idx % n;
+      g.f[IN_E][st.in[IN_E] + idx] = ms[i] * axs[j] + ams[i] * xs[j];
+    }
+    for (int i = ECLQR_TID; i < k; i += ECLQR_NT) g.f[IN_g][st.in[IN_g] + i] = ams[i];
+    if (st.i == 0)
+      for (int i = ECLQR_TID; i < n; i += ECLQR_NT) g.x0[st.x0 + i] = al[st.in[IN_q] + i];
+    if (!st.terminal) {
+      const StageInfo& st1 = p.st[s + 1];
+      const double* us = u + st.in[IN_r];
+      const double* aus = au + st.in[IN_r];
+      const double* l1 = lam + st1.in[IN_q];
+      const double* al1 = al + st1.in[IN_q];
+      for (int idx = ECLQR_TID; idx < m * m; idx += ECLQR_NT) {
+        const int i = idx / m, j = idx % m;
+        g.f[IN_R][st.in[IN_R] + idx] = 0.5 * (aus[i] * us[j] + us[i] * aus[j]);
+      }
+      for (int i = ECLQR_TID; i < m; i += ECLQR_NT) g.f[IN_r][st.in[IN_r] + i] = aus[i];
+      if (g.f[IN_M])
+        for (int idx = ECLQR_TID; idx < n * m; idx += ECLQR_NT) {
+          const int i = idx / m, j = idx % m;
+          g.f[IN_M][st.in[IN_M] + idx] = axs[i] * us[j] + xs[i] * aus[j];
+        }
+      for (int idx = ECLQR_TID; idx < np * n; idx += ECLQR_NT) {
+        const int i = idx / n, j = idx % n;
+        g.f[IN_A][st.in[IN_A] + idx] = l1[i] * axs[j] + al1[i] * xs[j];
+      }
+      for (int idx = ECLQR_TID; idx < np * m; idx += ECLQR_NT) {
+        const int i = idx / m, j = idx % m;
+        g.f[IN_B][st.in[IN_B] + idx] = l1[i] * aus[j] + al1[i] * us[j];
+      }
+      for (int i = ECLQR_TID; i < np; i += ECLQR_NT) g.f[IN_c][st.in[IN_c] + i] = al1[i];
+      for (int idx = ECLQR_TID; idx < k * m; idx += ECLQR_NT) {
+        const int i = idx / m, j = idx % m;
+        g.f[IN_F][st.in[IN_F] + idx] = ms[i] * aus[j] + ams[i] * us[j];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+static int grid_for(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  if (g < 1) g = 1;
+  if (g > 4096) g = 4096;
+  return (int)g;
+}
+
+void launch_dual_matrices(const DevEngine& p, const Inputs& in, const DevEngine& d, const DualPtrs& dp,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_dual_matrices, dim3(d.nblocks), dim3(kBlock), 0, s, p, in, d, dp);
+}
+void launch_dual_vectors(const DevEngine& p, const Inputs& in, const double* x, const double* u, const DevEngine& d,
+                         const DualPtrs& dp, hipStream_t s) {
+  hipLaunchKernelGGL(k_dual_vectors, dim3(d.nblocks), dim3(kBlock), 0, s, p, in, x, u, d, dp);
+}
+void launch_dual_extract(const DevEngine& p, const DevEngine& d, const double* dx, const double* du, double* lam,
+                         double* mu, const DualPtrs& dp, hipStream_t s) {
+  hipLaunchKernelGGL(k_dual_extract, dim3(p.nblocks), dim3(kBlock), 0, s, p, d, dx, du, lam, mu, dp);
+}
+void launch_correction(const DevEngine& p, const Inputs& in, const double* x, const double* u, const double* lam,
+                       const double* mu, const CorrPtrs& cp, hipStream_t s) {
+  hipLaunchKernelGGL(k_correction, dim3(p.nblocks), dim3(kBlock), 0, s, p, in, x, u, lam, mu, cp);
+}
+void launch_axpy(double* y, const double* x, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_axpy, dim3(grid_for(n)), dim3(256), 0, s, y, x, n);
+}
+void launch_fill(double* y, double v, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(256), 0, s, y, v, n);
+}
+void launch_fill_i32(int32_t* y, int32_t v, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n)), dim3(256), 0, s, y, v, n);
+}
+void launch_merge_status(int32_t* status, const int32_t* other, int32_t bit, int32_t B, hipStream_t s) {
+  hipLaunchKernelGGL(k_merge_status, dim3(grid_for(B)), dim3(256), 0, s, status, other, bit, B);
+}
+void launch_finalize(const DevEngine& p, const int32_t* status, double* x, double* u, double* lam, double* mu,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(p.nblocks), dim3(kBlock), 0, s, p, status, x, u, lam, mu);
+}
+void launch_kkt_residual(const DevEngine& p, const Inputs& in, const double* x, const double* u, const double* lam,
+                         const double* mu, const int64_t* sbase, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_kkt_residual, dim3(p.nblocks), dim3(kBlock), 0, s, p, in, x, u, lam, mu);
+  hipLaunchKernelGGL(k_resid_reduce, dim3(grid_for(p.B)), dim3(256), 0, s, p, sbase, out);
+}
+void launch_grad_assemble(const DevEngine& p, const double* x, const double* u, const double* lam, const double* mu,
+                          const double* ax, const double* au, const double* al, const double* am, const GradPtrs& g,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_grad_assemble, dim3(p.nblocks), dim3(kBlock), 0, s, p, x, u, lam, mu, ax, au, al, am, g);
+}
+
+}  // namespace eclqr

@@ -1,0 +1,284 @@
+// Reduced unconstrained LQR (paper Section VI: any LQR solver; here the
+// logarithmic-depth associative scan over conditional value functions),
+// feedback gains, the forward affine scan and the recovery maps
+// (eq. (recovery-maps)).
+#include "dense.hpp"
+#include "device_util.hpp"
+#include "eclqr.h"
+#include "scratch.hpp"
+
+namespace eclqr {
+
+// Element of an interval [s, e) of the reduced problem: the conditional value
+//   V(x, y) = 1/2 x'J x - eta'x + sup_l [ l'(y - A x - b) - 1/2 l'C l ]
+// (cost from reduced state x at s to y at e).  A unary element (end at the
+// terminal stage) is V(x) = 1/2 x'J x - eta'x.  Combining [s, m) with [m, e),
+// with Minv = (I + C1 J2)^{-1}:
+//   A = A2 Minv A1,  b = A2 Minv (b1 + C1 eta2) + b2,  C = A2 Minv C1 A2' + C2,
+//   eta = A1' Minv' (eta2 - J2 b1) + eta1,  J = A1' Minv' J2 A1 + J1.
+// LDS: Mmat (maxd x maxd) | piv | sh
+__global__ void __launch_bounds__(kBlock) k_ric_combine(DevEngine e, int64_t first, int64_t ntasks, int32_t* status,
+                                                        int maxd) {
+  extern __shared__ double lds[];
+  double* Mt = lds;
+  int* piv = (int*)(Mt + (int64_t)maxd * maxd);
+  double* sh = (double*)(piv + kMaxDim);
+  for (int64_t ti = blockIdx.x; ti < ntasks; ti += gridDim.x) {
+    const int a = e.tasks[3 * (first + ti)];
+    const int bsl = e.tasks[3 * (first + ti) + 1];
+    const int o = e.tasks[3 * (first + ti) + 2];
+    const int sa = slot_a(e, 0, a), sm = slot_b(e, 0, a), se = slot_b(e, 0, bsl);
+    const int ds = e.nbar[sa], dm = e.nbar[sm], de = (se >= 0) ? e.nbar[se] : 0;
+    const int ns = e.st[sa].n, nm = e.st[sm].n, ne = (se >= 0) ? e.st[se].n : 0;
+    const RicLayout l1 = ric_layout(ns, nm), l2 = ric_layout(nm, ne), lo = ric_layout(ns, ne);
+    const double* E1 = slot_ptr(e, SCAN_RIC, a);
+    const double* E2 = slot_ptr(e, SCAN_RIC, bsl);
+    double* Eo = slot_ptr(e, SCAN_RIC, o);
+    const double *A1 = E1 + l1.A, *b1 = E1 + l1.b, *C1 = E1 + l1.C, *et1 = E1 + l1.eta, *J1 = E1 + l1.J;
+    const double *A2 = E2 + l2.A, *b2 = E2 + l2.b, *C2 = E2 + l2.C, *et2 = E2 + l2.eta, *J2 = E2 + l2.J;
+    double* s0 = block_scratch(e);
+    double* X = s0;                                        // dm x (ds + 1 + dm)
+    double* Yv = X + rup4((int64_t)dm * (ds + 1 + dm));    // dm x (dm + 1)
+    double* T1 = Yv + rup4((int64_t)dm * (dm + 1));        // de x dm
+    double* T2 = T1 + rup4((int64_t)de * dm);              // ds x dm
+    const int lx = ds + 1 + dm, ly = dm + 1;
+    // Mmat = I + C1 J2
+    wg_gemm(Mt, dm, C1, dm, false, J2, dm, false, dm, dm, dm, 1.0, 0.0);
+    for (int i = ECLQR_TID; i < dm; i += ECLQR_NT) Mt[i * dm + i] += 1.0;
+    wg_sync();
+    wg_lu(Mt, dm, dm, piv, sh);
+    // right-hand sides
+    for (int idx = ECLQR_TID; idx < dm * ly; idx += ECLQR_NT) {
+      const int i = idx / ly, j = idx % ly;
+      if (j < dm) {
+        Yv[idx] = J2[i * dm + j];
+      } else {
+        double v = et2[i];
+        for (int l = 0; l < dm; ++l) v = fma(-J2[i * dm + l], b1[l], v);
+        Yv[idx] = v;
+      }
+    }
+    if (se >= 0) {
+      for (int idx = ECLQR_TID; idx < dm * lx; idx += ECLQR_NT) {
+        const int i = idx / lx, j = idx % lx;
+        double v;
+        if (j < ds) {
+          v = A1[i * ds + j];
+        } else if (j == ds) {
+          v = b1[i];
+          for (int l = 0; l < dm; ++l) v = fma(C1[i * dm + l], et2[l], v);
+        } else {
+          v = C1[i * dm + (j - ds - 1)];
+        }
+        X[idx] = v;
+      }
+    }
+    wg_sync();
+    wg_lu_solve_t(Mt, dm, dm, piv, Yv, ly, ly);
+    // J = A1' (Minv' J2) A1 + J1 ; eta = A1' Minv'(eta2 - J2 b1) + eta1
+    wg_gemm(T2, dm, A1, ds, true, Yv, ly, false, ds, dm, dm, 1.0, 0.0);
+    wg_gemm(Eo + lo.J, ds, T2, dm, false, A1, ds, false, ds, ds, dm, 1.0, 0.0);
+    for (int idx = ECLQR_TID; idx < ds * ds; idx += ECLQR_NT) Eo[lo.J + idx] += J1[idx];
+    for (int i = ECLQR_TID; i < ds; i += ECLQR_NT) {
+      double v = et1[i];
+      for (int l = 0; l < dm; ++l) v = fma(A1[l * ds + i], Yv[l * ly + dm], v);
+      Eo[lo.eta + i] = v;
+    }
+    wg_sync();
+    wg_symmetrize(Eo + lo.J, ds, ds);
+    if (se >= 0) {
+      wg_lu_solve(Mt, dm, dm, piv, X, lx, lx);
+      // A = A2 X_A ; b = A2 X_b + b2 ; C = (A2 X_C) A2' + C2
+      wg_gemm(Eo + lo.A, ds, A2, dm, false, X, lx, false, de, ds, dm, 1.0, 0.0);
+      for (int i = ECLQR_TID; i < de; i += ECLQR_NT) {
+        double v = b2[i];
+        for (int l = 0; l < dm; ++l) v = fma(A2[i * dm + l], X[l * lx + ds], v);
+        Eo[lo.b + i] = v;
+      }
+      wg_gemm(T1, dm, A2, dm, false, X + ds + 1, lx, false, de, dm, dm, 1.0, 0.0);
+      wg_gemm(Eo + lo.C, de, T1, dm, false, A2, dm, true, de, de, dm, 1.0, 0.0);
+      for (int idx = ECLQR_TID; idx < de * de; idx += ECLQR_NT) Eo[lo.C + idx] += C2[idx];
+      wg_sync();
+      wg_symmetrize(Eo + lo.C, de, de);
+    }
+    (void)status;
+  }
+}
+
+// Feedback of stage i from the value function of stage i+1 (P', p' = J, -eta
+// of the suffix element):  H_uu = R-bar + B-bar'P'B-bar,
+// H_ux = M-bar' + B-bar'P'A-bar, h_u = r-bar + B-bar'(P'c-bar + p'),
+// K = -H_uu^{-1} H_ux, k = -H_uu^{-1} h_u, and the closed-loop map
+// z' = (A-bar + B-bar K) z + (B-bar k + c-bar) as the forward-scan leaf.
+// LDS: Huu (maxm x maxm) | sh
+__global__ void __launch_bounds__(kBlock) k_gains(DevEngine e, int32_t* status, int maxm) {
+  extern __shared__ double lds[];
+  double* Huu = lds;
+  double* sh = Huu + (int64_t)maxm * maxm;
+  for (int64_t s = blockIdx.x; s < e.S; s += gridDim.x) {
+    const StageInfo st = e.st[s];
+    if (st.terminal) continue;
+    const int n = st.n, np = st.np, m = st.m;
+    const Arena ar = arena_layout(n, np, m);
+    double* base = e.arena + st.ws;
+    const int nb = e.nbar[s], nb1 = e.nbar[s + 1], mb = e.mbar[s];
+    const StageInfo& st1 = e.st[s + 1];
+    const RicLayout l1 = ric_layout(st1.n, 0);
+    const double* P1 = slot_ptr(e, SCAN_RIC, st1.suf[SCAN_RIC]) + l1.J;
+    const double* et1 = slot_ptr(e, SCAN_RIC, st1.suf[SCAN_RIC]) + l1.eta;
+    const double *Ab = base + ar.Ab, *Bb = base + ar.Bb, *cb = base + ar.cb;
+    const double *Mb = base + ar.Mb, *Rb = base + ar.Rb, *rb = base + ar.rb;
+    double* K = base + ar.K;
+    double* kk = base + ar.kk;
+    double* s0 = block_scratch(e);
+    double* PB = s0;                                   // nb1 x mb
+    double* PA = PB + rup4((int64_t)nb1 * mb);         // nb1 x nb
+    double* Hux = PA + rup4((int64_t)nb1 * nb);        // mb x nb
+    double* pc = Hux + rup4((int64_t)mb * nb);         // nb1
+    double* hu = pc + rup4(nb1);                       // mb
+    wg_gemm(PB, mb, P1, nb1, false, Bb, mb, false, nb1, mb, nb1, 1.0, 0.0);
+    wg_gemm(PA, nb, P1, nb1, false, Ab, nb, false, nb1, nb, nb1, 1.0, 0.0);
+    for (int i = ECLQR_TID; i < nb1; i += ECLQR_NT) {
+      double v = -et1[i];
+      for (int l = 0; l < nb1; ++l) v = fma(P1[i * nb1 + l], cb[l], v);
+      pc[i] = v;
+    }
+    wg_copy(Huu, mb, Rb, mb, mb, mb);
+    wg_gemm(Huu, mb, Bb, mb, true, PB, mb, false, mb, mb, nb1, 1.0, 1.0);
+    wg_symmetrize(Huu, mb, mb);
+    wg_copy_t(Hux, nb, Mb, mb, nb, mb);
+    wg_gemm(Hux, nb, Bb, mb, true, PA, nb, false, mb, nb, nb1, 1.0, 1.0);
+    for (int i = ECLQR_TID; i < mb; i += ECLQR_NT) {
+      double v = rb[i];
+      for (int l = 0; l < nb1; ++l) v = fma(Bb[l * mb + i], pc[l], v);
+      hu[i] = v;
+    }
+    wg_sync();
+    if (wg_cholesky(Huu, mb, mb, sh)) {
+      if (ECLQR_TID == 0) flag(status, st.inst, ECLQR_NOT_CONVEX);
+      wg_sync();
+      continue;
+    }
+    // K = -Huu^{-1} Hux ; k = -Huu^{-1} hu
+    wg_trsm_lower(Huu, mb, Hux, nb, mb, nb);
+    wg_trsm_lower_t(Huu, mb, Hux, nb, mb, nb);
+    wg_trsm_lower(Huu, mb, hu, 1, mb, 1);
+    wg_trsm_lower_t(Huu, mb, hu, 1, mb, 1);
+    for (int idx = ECLQR_TID; idx < mb * nb; idx += ECLQR_NT) K[idx] = -Hux[idx];
+    for (int i = ECLQR_TID; i < mb; i += ECLQR_NT) kk[i] = -hu[i];
+    wg_sync();
+    // closed loop: F = A-bar + B-bar K (nb1 x nb), f = B-bar k + c-bar
+    double* Fs = slot_ptr(e, SCAN_FWD, st.elem[SCAN_FWD]);
+    double* fs = Fs + (int64_t)np * n;
+    wg_copy(Fs, nb, Ab, nb, nb1, nb);
+    wg_gemm(Fs, nb, Bb, mb, false, K, nb, false, nb1, nb, mb, 1.0, 1.0);
+    for (int i = ECLQR_TID; i < nb1; i += ECLQR_NT) {
+      double v = cb[i];
+      for (int l = 0; l < mb; ++l) v = fma(Bb[i * mb + l], kk[l], v);
+      fs[i] = v;
+    }
+    wg_sync();
+  }
+}
+
+// Forward scan: composition of affine maps of the reduced state.  The left
+// operand maps mid -> out, the right operand maps in -> mid (or is the
+// constant z at mid); result F = F1 F2, f = F1 f2 + f1.
+__global__ void __launch_bounds__(kBlock) k_fwd_combine(DevEngine e, int64_t first, int64_t ntasks) {
+  for (int64_t ti = blockIdx.x; ti < ntasks; ti += gridDim.x) {
+    const int a = e.tasks[3 * (first + ti)];
+    const int bsl = e.tasks[3 * (first + ti) + 1];
+    const int o = e.tasks[3 * (first + ti) + 2];
+    const int so = slot_a(e, 1, a), smid = slot_b(e, 1, a), sin_ = slot_b(e, 1, bsl);
+    const int dout = e.nbar[so], dmid = e.nbar[smid], din = (sin_ >= 0) ? e.nbar[sin_] : 0;
+    const int nout = e.st[so].n, nmid = e.st[smid].n, nin = (sin_ >= 0) ? e.st[sin_].n : 0;
+    const double* F1 = slot_ptr(e, SCAN_FWD, a);
+    const double* f1 = F1 + (int64_t)nout * nmid;
+    const double* F2 = slot_ptr(e, SCAN_FWD, bsl);
+    const double* f2 = F2 + (int64_t)nmid * nin;
+    double* Fo = slot_ptr(e, SCAN_FWD, o);
+    double* fo = Fo + (int64_t)nout * nin;
+    if (sin_ >= 0) wg_gemm(Fo, din, F1, dmid, false, F2, din, false, dout, din, dmid, 1.0, 0.0);
+    for (int i = ECLQR_TID; i < dout; i += ECLQR_NT) {
+      double v = f1[i];
+      for (int l = 0; l < dmid; ++l) v = fma(F1[i * dmid + l], f2[l], v);
+      fo[i] = v;
+    }
+    wg_sync();
+  }
+}
+
+// Recovery (eq. (recovery-maps)): v_i = K_i z_i + k_i, x_i = T_i z_i + t_i,
+// u_i = Y_i z_i + Z_i v_i + y_i.
+__global__ void __launch_bounds__(kBlock) k_recover(DevEngine e, double* x, double* u, int64_t xoff_field,
+                                                    int64_t uoff_field) {
+  __shared__ double vsh[kMaxDim];
+  for (int64_t s = blockIdx.x; s < e.S; s += gridDim.x) {
+    const StageInfo st = e.st[s];
+    const int n = st.n, np = st.np, m = st.m;
+    const Arena ar = arena_layout(n, np, m);
+    const double* base = e.arena + st.ws;
+    const int nb = e.nbar[s];
+    const double* z = slot_ptr(e, SCAN_FWD, st.suf[SCAN_FWD]);
+    double* xo = x + st.in[xoff_field];
+    const double* T = base + ar.T;
+    const double* tv = base + ar.t;
+    for (int i = ECLQR_TID; i < n; i += ECLQR_NT) {
+      double v = tv[i];
+      for (int l = 0; l < nb; ++l) v = fma(T[i * nb + l], z[l], v);
+      xo[i] = v;
+    }
+    if (!st.terminal) {
+      const int mb = e.mbar[s];
+      const double *K = base + ar.K, *kk = base + ar.kk, *Y = base + ar.Y, *Z = base + ar.Z, *y = base + ar.y;
+      for (int i = ECLQR_TID; i < mb; i += ECLQR_NT) {
+        double v = kk[i];
+        for (int l = 0; l < nb; ++l) v = fma(K[i * nb + l], z[l], v);
+        vsh[i] = v;
+      }
+      __syncthreads();
+      double* uo = u + st.in[uoff_field];
+      for (int i = ECLQR_TID; i < m; i += ECLQR_NT) {
+        double v = y[i];
+        for (int l = 0; l < nb; ++l) v = fma(Y[i * nb + l], z[l], v);
+        for (int l = 0; l < mb; ++l) v = fma(Z[i * mb + l], vsh[l], v);
+        uo[i] = v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+void lqr_set_max_lds(int bytes) {
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_ric_combine), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            bytes);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_gains), hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+size_t ric_lds_bytes(int maxd) {
+  return sizeof(double) * ((size_t)maxd * maxd + 16) + sizeof(int) * kMaxDim + 64;
+}
+size_t gains_lds_bytes(int maxm) { return sizeof(double) * ((size_t)maxm * maxm + 16) + 64; }
+
+void launch_ric_combine(const DevEngine& e, int64_t first, int64_t ntasks, int32_t* status, int maxd,
+                        hipStream_t s) {
+  if (ntasks <= 0) return;
+  const int grid = (int)(ntasks < e.nblocks ? ntasks : e.nblocks);
+  hipLaunchKernelGGL(k_ric_combine, dim3(grid), dim3(kBlock), ric_lds_bytes(maxd), s, e, first, ntasks, status, maxd);
+}
+
+void launch_gains(const DevEngine& e, int32_t* status, int maxm, hipStream_t s) {
+  hipLaunchKernelGGL(k_gains, dim3(e.nblocks), dim3(kBlock), gains_lds_bytes(maxm), s, e, status, maxm);
+}
+
+void launch_fwd_combine(const DevEngine& e, int64_t first, int64_t ntasks, hipStream_t s) {
+  if (ntasks <= 0) return;
+  const int grid = (int)(ntasks < e.nblocks ? ntasks : e.nblocks);
+  hipLaunchKernelGGL(k_fwd_combine, dim3(grid), dim3(kBlock), 0, s, e, first, ntasks);
+}
+
+void launch_recover(const DevEngine& e, double* x, double* u, hipStream_t s) {
+  hipLaunchKernelGGL(k_recover, dim3(e.nblocks), dim3(kBlock), 0, s, e, x, u, (int64_t)IN_q, (int64_t)IN_r);
+}
+
+}  // namespace eclqr

@@ -1,0 +1,344 @@
+// Feasible-domain scan (paper Sections III-IV): input validation, base
+// relations, relation composition, and the state parameterisation that turns
+// each suffix relation into x_i = T_i z_i + t_i.
+#include "dense.hpp"
+#include "device_util.hpp"
+#include "eclqr.h"
+
+namespace eclqr {
+
+// ---------------------------------------------------------------------------
+// NaN / Inf in any input block of a stage -> ECLQR_INVALID_INPUT.
+__global__ void __launch_bounds__(kBlock) k_validate(DevEngine e, Inputs in, int32_t* status) {
+  __shared__ int bad;
+  for (int64_t s = blockIdx.x; s < e.S; s += gridDim.x) {
+    const StageInfo& st = e.st[s];
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    const int64_t n = st.n, np = st.np, m = st.m, k = st.k;
+    const int64_t sz[IN_COUNT] = {n * n, n, m * m, m, n * m, np * n, np * m, np, k * n, k * m, k};
+    int mine = 0;
+    for (int f = 0; f < IN_COUNT; ++f) {
+      if (f == IN_M && in.f[IN_M] == nullptr) continue;
+      const double* p = in.f[f] + st.in[f];
+      for (int64_t j = threadIdx.x; j < sz[f]; j += blockDim.x)
+        if (!isfinite(p[j])) mine = 1;
+    }
+    if (st.i == 0)
+      for (int64_t j = threadIdx.x; j < n; j += blockDim.x)
+        if (!isfinite(in.x0[st.x0 + j])) mine = 1;
+    if (mine) bad = 1;
+    __syncthreads();
+    if (threadIdx.x == 0 && bad) flag(status, st.inst, ECLQR_INVALID_INPUT);
+    __syncthreads();
+  }
+}
+
+// Divide each row of W (columns [0, ncoef) coefficients, column ncoef the
+// offset) by the 2-norm of its coefficients (Section VIII item 1); returns
+// max(1, max |offset|) of the scaled rows.
+__device__ inline double scale_rows(double* W, int ld, int p, int ncoef, double* sh) {
+  for (int r = ECLQR_TID; r < p; r += ECLQR_NT) {
+    double s = 0.0;
+    for (int j = 0; j < ncoef; ++j) s = fma(W[r * ld + j], W[r * ld + j], s);
+    if (s > 0.0) {
+      const double inv = 1.0 / sqrt(s);
+      for (int j = 0; j <= ncoef; ++j) W[r * ld + j] *= inv;
+    }
+  }
+  wg_sync();
+  if (ECLQR_TID == 0) {
+    double mx = 1.0;
+    for (int r = 0; r < p; ++r) mx = fmax(mx, fabs(W[r * ld + ncoef]));
+    sh[0] = mx;
+  }
+  wg_sync();
+  return sh[0];
+}
+
+// ---------------------------------------------------------------------------
+// Base relation of stage i (eq. (base-system), (base-relation)):
+//   [B; F] u + [[A, -I], [E, 0]] (x_i, x_{i+1}) + [c; g] = 0,
+// u projected out with Lemma 1 by a column-pivoted Householder QR of the
+// input columns; the remaining equations are replaced by an orthonormal row
+// basis.  The terminal relation (eq. (terminal-relation)) is E_N x_N + g_N = 0.
+// LDS: W (maxp x ldw) | tau (64) | qr scratch (64+8) | perm (64 ints) | rb scratch
+__global__ void __launch_bounds__(kBlock) k_base_relation(DevEngine e, Inputs in, Tols t, int32_t* status, int maxp,
+                                                          int ldw) {
+  extern __shared__ double lds[];
+  double* W = lds;
+  double* tau = W + (int64_t)maxp * ldw;
+  double* qd = tau + kMaxDim;
+  int* perm = (int*)(qd + kMaxDim + 8);
+  double* rbs = (double*)(perm + kMaxDim);
+  double* sh = rbs + 2 * maxp + 8 + 64;
+  for (int64_t s = blockIdx.x; s < e.S; s += gridDim.x) {
+    const StageInfo st = e.st[s];
+    const int n = st.n, np = st.np, m = st.m, k = st.k;
+    const int slot = st.elem[SCAN_REL];
+    double* out = slot_ptr(e, SCAN_REL, slot);
+    if (st.terminal) {
+      const int p = k, ld = n + 1;
+      const double* E = in.f[IN_E] + st.in[IN_E];
+      const double* g = in.f[IN_g] + st.in[IN_g];
+      for (int idx = ECLQR_TID; idx < p * ld; idx += ECLQR_NT) {
+        const int r = idx / ld, j = idx % ld;
+        W[r * ld + j] = (j < n) ? E[r * n + j] : g[r];
+      }
+      wg_sync();
+      const double omax = scale_rows(W, ld, p, n, sh);
+      int b = 0;
+      const int rr = wg_row_basis(W, ld, 0, p, 0, n, t.rank, t.cons * omax, &b, rbs);
+      for (int idx = ECLQR_TID; idx < rr * ld; idx += ECLQR_NT) out[idx] = W[idx];
+      if (ECLQR_TID == 0) {
+        e.slot_rows[slot] = rr;
+        if (b) flag(status, st.inst, ECLQR_INFEASIBLE_SUFFIX);
+      }
+      wg_sync();
+      continue;
+    }
+    const int p = np + k;
+    const int c = m + n + np + 1;
+    const int ld = c;
+    const double* A = in.f[IN_A] + st.in[IN_A];
+    const double* B = in.f[IN_B] + st.in[IN_B];
+    const double* cv = in.f[IN_c] + st.in[IN_c];
+    const double* E = in.f[IN_E] + st.in[IN_E];
+    const double* F = in.f[IN_F] + st.in[IN_F];
+    const double* g = in.f[IN_g] + st.in[IN_g];
+    for (int idx = ECLQR_TID; idx < p * c; idx += ECLQR_NT) {
+      const int r = idx / c, j = idx % c;
+      double v;
+      if (r < np) {
+        if (j < m) v = B[r * m + j];
+        else if (j < m + n) v = A[r * n + (j - m)];
+        else if (j < m + n + np) v = (j - m - n == r) ? -1.0 : 0.0;
+        else v = cv[r];
+      } else {
+        const int q = r - np;
+        if (j < m) v = F[q * m + j];
+        else if (j < m + n) v = E[q * n + (j - m)];
+        else if (j < m + n + np) v = 0.0;
+        else v = g[q];
+      }
+      W[r * ld + j] = v;
+    }
+    wg_sync();
+    const double omax = scale_rows(W, ld, p, c - 1, sh);
+    const int rho = wg_qr_colpiv(W, ld, p, c, 0, m, t.rank, tau, QRScratch{qd, perm});
+    int b = 0;
+    const int rr = wg_row_basis(W, ld, rho, p, m, n + np, t.rank, t.cons * omax, &b, rbs);
+    const int lo = n + np + 1;
+    for (int idx = ECLQR_TID; idx < rr * lo; idx += ECLQR_NT) {
+      const int r = idx / lo, j = idx % lo;
+      out[r * lo + j] = W[(rho + r) * ld + m + j];
+    }
+    if (ECLQR_TID == 0) {
+      e.slot_rows[slot] = rr;
+      if (b) flag(status, st.inst, ECLQR_INFEASIBLE_SUFFIX);
+    }
+    wg_sync();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Composition R_ab o R_bc (eq. (composition-matrix)): stack
+//   [R_ab | L_ab | 0    | l_ab]
+//   [L_bc | 0    | R_bc | l_bc]
+// over the columns (b | a | c | 1), eliminate b with Lemma 1 (pivoted
+// Householder on the b columns) and keep an orthonormal row basis of the rest.
+// A unary right operand (n_c = 0) gives a unary result.
+__global__ void __launch_bounds__(kBlock) k_rel_compose(DevEngine e, int64_t first, int64_t ntasks, Tols t,
+                                                        int32_t* status, int maxp, int ldw) {
+  extern __shared__ double lds[];
+  double* W = lds;
+  double* tau = W + (int64_t)maxp * ldw;
+  double* qd = tau + kMaxDim;
+  int* perm = (int*)(qd + kMaxDim + 8);
+  double* rbs = (double*)(perm + kMaxDim);
+  double* sh = rbs + 2 * maxp + 8 + 64;
+  for (int64_t ti = blockIdx.x; ti < ntasks; ti += gridDim.x) {
+    const int a = e.tasks[3 * (first + ti)];
+    const int bsl = e.tasks[3 * (first + ti) + 1];
+    const int o = e.tasks[3 * (first + ti) + 2];
+    const int sa = slot_a(e, 0, a), sb = slot_b(e, 0, a), sc = slot_b(e, 0, bsl);
+    const int na = e.st[sa].n, nb = e.st[sb].n, nc = (sc >= 0) ? e.st[sc].n : 0;
+    const int inst = e.st[sa].inst;
+    const int ra = e.slot_rows[a], rb = e.slot_rows[bsl];
+    const int p = ra + rb;
+    if (p > maxp || p > 2 * kMaxDim * 2) {
+      if (ECLQR_TID == 0) {
+        e.slot_rows[o] = 0;
+        flag(status, inst, ECLQR_CAPACITY);
+      }
+      wg_sync();
+      continue;
+    }
+    const int c = nb + na + nc + 1;
+    const int ld = c;
+    const double* L = slot_ptr(e, SCAN_REL, a);
+    const double* Rr = slot_ptr(e, SCAN_REL, bsl);
+    const int lda = na + nb + 1, ldb = nb + nc + 1;
+    for (int idx = ECLQR_TID; idx < p * c; idx += ECLQR_NT) {
+      const int r = idx / c, j = idx % c;
+      double v;
+      if (r < ra) {
+        if (j < nb) v = L[r * lda + na + j];
+        else if (j < nb + na) v = L[r * lda + (j - nb)];
+        else if (j < nb + na + nc) v = 0.0;
+        else v = L[r * lda + na + nb];
+      } else {
+        const int q = r - ra;
+        if (j < nb) v = Rr[q * ldb + j];
+        else if (j < nb + na) v = 0.0;
+        else if (j < nb + na + nc) v = Rr[q * ldb + nb + (j - nb - na)];
+        else v = Rr[q * ldb + nb + nc];
+      }
+      W[r * ld + j] = v;
+    }
+    wg_sync();
+    if (ECLQR_TID == 0) {
+      double mx = 1.0;
+      for (int r = 0; r < p; ++r) mx = fmax(mx, fabs(W[r * ld + c - 1]));
+      sh[0] = mx;
+    }
+    wg_sync();
+    const double omax = sh[0];
+    const int rho = wg_qr_colpiv(W, ld, p, c, 0, nb, t.rank, tau, QRScratch{qd, perm});
+    int bad = 0;
+    const int rr = wg_row_basis(W, ld, rho, p, nb, na + nc, t.rank, t.cons * omax, &bad, rbs);
+    const int cap = e.slot_cap[o];
+    double* out = slot_ptr(e, SCAN_REL, o);
+    const int lo = na + nc + 1;
+    if (rr > cap) {
+      if (ECLQR_TID == 0) {
+        e.slot_rows[o] = 0;
+        flag(status, inst, ECLQR_CAPACITY);
+      }
+      wg_sync();
+      continue;
+    }
+    for (int idx = ECLQR_TID; idx < rr * lo; idx += ECLQR_NT) {
+      const int r = idx / lo, j = idx % lo;
+      out[r * lo + j] = W[(rho + r) * ld + nb + j];
+    }
+    if (ECLQR_TID == 0) {
+      e.slot_rows[o] = rr;
+      if (bad) flag(status, inst, ECLQR_INFEASIBLE_SUFFIX);
+    }
+    wg_sync();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// State parameterisation (eqs. (state-param), (left-inverse)): T_i is an
+// orthonormal basis of null(H_i) (trailing columns of the Householder Q of
+// H_i^T), t_i = -H_i^T h_i (minimum norm, H_i has orthonormal rows), S_i =
+// T_i^T.  On stage 0 also eq. (initial-feasibility) and z_0 (eq.
+// (reduced-initial)), written as the constant leaf of the forward scan.
+// LDS: Ht (maxn x maxn) | X (maxn x maxn) | tau | qr scratch | perm
+__global__ void __launch_bounds__(kBlock) k_domain(DevEngine e, Inputs in, Tols t, int32_t* status, int maxn) {
+  extern __shared__ double lds[];
+  double* Ht = lds;
+  double* X = Ht + maxn * maxn;
+  double* tau = X + maxn * maxn;
+  double* qd = tau + kMaxDim;
+  int* perm = (int*)(qd + kMaxDim + 8);
+  double* sh = (double*)(perm + kMaxDim);
+  for (int64_t s = blockIdx.x; s < e.S; s += gridDim.x) {
+    const StageInfo st = e.st[s];
+    const int n = st.n;
+    const int suf = st.suf[SCAN_REL];
+    const int r = e.slot_rows[suf];
+    const double* H = slot_ptr(e, SCAN_REL, suf);  // r x (n + 1)
+    const int nb = n - r;
+    const Arena ar = arena_layout(st.n, st.np, st.m);
+    double* base = e.arena + st.ws;
+    double* T = base + ar.T;
+    double* tv = base + ar.t;
+    // Ht = H^T (n x r)
+    for (int idx = ECLQR_TID; idx < n * r; idx += ECLQR_NT) {
+      const int i = idx / r, j = idx % r;
+      Ht[i * r + j] = H[j * (n + 1) + i];
+    }
+    for (int idx = ECLQR_TID; idx < n * nb; idx += ECLQR_NT) {
+      const int i = idx / nb, j = idx % nb;
+      X[i * nb + j] = (i == r + j) ? 1.0 : 0.0;
+    }
+    wg_sync();
+    wg_qr_colpiv(Ht, r, n, r, 0, r, 0.0, tau, QRScratch{qd, perm});
+    wg_apply_q(Ht, r, n, 0, r, tau, X, nb, nb);
+    for (int idx = ECLQR_TID; idx < n * nb; idx += ECLQR_NT) T[idx] = X[idx];
+    for (int i = ECLQR_TID; i < n; i += ECLQR_NT) {
+      double v = 0.0;
+      for (int j = 0; j < r; ++j) v = fma(H[j * (n + 1) + i], H[j * (n + 1) + n], v);
+      tv[i] = -v;
+    }
+    if (ECLQR_TID == 0) e.nbar[s] = nb;
+    wg_sync();
+    if (st.i == 0) {
+      const double* x0 = in.x0 + st.x0;
+      if (ECLQR_TID == 0) {
+        double sc = 1.0, res = 0.0;
+        for (int i = 0; i < n; ++i) sc = fmax(sc, fabs(x0[i]));
+        for (int j = 0; j < r; ++j) {
+          double v = H[j * (n + 1) + n];
+          sc = fmax(sc, fabs(v));
+          for (int i = 0; i < n; ++i) v = fma(H[j * (n + 1) + i], x0[i], v);
+          res = fmax(res, fabs(v));
+        }
+        if (res > t.cons * sc) flag(status, st.inst, ECLQR_INFEASIBLE_INITIAL);
+      }
+      double* z0 = slot_ptr(e, SCAN_FWD, st.suf[SCAN_FWD]);
+      for (int j = ECLQR_TID; j < nb; j += ECLQR_NT) {
+        double v = 0.0;
+        for (int i = 0; i < n; ++i) v = fma(X[i * nb + j], x0[i] - tv[i], v);
+        z0[j] = v;
+      }
+      wg_sync();
+    }
+    (void)sh;
+  }
+}
+
+// ---------------------------------------------------------------------------
+void relations_set_max_lds(int bytes) {
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_base_relation), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            bytes);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_rel_compose), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            bytes);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_domain), hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+size_t rel_lds_bytes(int maxp, int ldw) {
+  return sizeof(double) * ((size_t)maxp * ldw + kMaxDim + kMaxDim + 8 + 2 * maxp + 8 + 64 + 16) +
+         sizeof(int) * kMaxDim + 64;
+}
+
+size_t domain_lds_bytes(int maxn) {
+  return sizeof(double) * (2 * (size_t)maxn * maxn + kMaxDim + kMaxDim + 8 + 16) + sizeof(int) * kMaxDim + 64;
+}
+
+void launch_validate(const DevEngine& e, const Inputs& in, int32_t* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_validate, dim3(e.nblocks), dim3(kBlock), 0, s, e, in, status);
+}
+
+void launch_base_relation(const DevEngine& e, const Inputs& in, Tols t, int32_t* status, int maxp, int ldw,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_base_relation, dim3(e.nblocks), dim3(kBlock), rel_lds_bytes(maxp, ldw), s, e, in, t, status,
+                     maxp, ldw);
+}
+
+void launch_rel_compose(const DevEngine& e, int64_t first, int64_t ntasks, Tols t, int32_t* status, int maxp, int ldw,
+                        hipStream_t s) {
+  if (ntasks <= 0) return;
+  const int grid = (int)(ntasks < e.nblocks ? ntasks : e.nblocks);
+  hipLaunchKernelGGL(k_rel_compose, dim3(grid), dim3(kBlock), rel_lds_bytes(maxp, ldw), s, e, first, ntasks, t,
+                     status, maxp, ldw);
+}
+
+void launch_domain(const DevEngine& e, const Inputs& in, Tols t, int32_t* status, int maxn, hipStream_t s) {
+  hipLaunchKernelGGL(k_domain, dim3(e.nblocks), dim3(kBlock), domain_lds_bytes(maxn), s, e, in, t, status, maxn);
+}
+
+}  // namespace eclqr

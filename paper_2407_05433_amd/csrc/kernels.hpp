@@ -1,0 +1,101 @@
+// Launch interface between the C-ABI host code and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace eclqr {
+
+// Device view of one engine's tables inside the bound workspace.
+struct DevEngine {
+  const StageInfo* st;
+  const int64_t* slot_off;    // [SCAN_COUNT * nslots]
+  const int32_t* slot_sa;     // [2 * nslots] global stage of the left endpoint (REL/RIC, FWD)
+  const int32_t* slot_sb;     // [2 * nslots] global stage of the right endpoint, -1 = unary
+  const int32_t* slot_cap;    // REL row capacity
+  int32_t* slot_rows;         // REL rows written by the kernels
+  const int32_t* tasks;       // (left, right, out) triples
+  int32_t* nbar;              // reduced state dim per stage
+  int32_t* mbar;              // reduced input dim per stage
+  double* arena;              // stage arenas
+  double* scan[SCAN_COUNT];   // slot arenas
+  double* resid;              // [4 * S]
+  double* scratch;            // per-workgroup global scratch
+  int64_t scratch_per_block;  // doubles
+  int64_t S;
+  int32_t B;
+  int32_t nslots;
+  int32_t nblocks;            // grid size of the stage-parallel kernels (grid-stride)
+};
+
+// Pointers to one problem's data (caller layout of the engine).
+struct Inputs {
+  const double* f[IN_COUNT];  // Q q R r M A B c E F g (M may be null)
+  const double* x0;
+};
+
+struct Tols {
+  double rank;
+  double cons;
+  int check_lemma2;
+};
+
+void launch_validate(const DevEngine& e, const Inputs& in, int32_t* status, hipStream_t s);
+void relations_set_max_lds(int bytes);
+void eliminate_set_max_lds(int bytes);
+void lqr_set_max_lds(int bytes);
+size_t rel_lds_bytes(int maxp, int ldw);
+size_t domain_lds_bytes(int maxn);
+size_t elim_lds_bytes(int maxm, int maxq);
+size_t ric_lds_bytes(int maxd);
+size_t gains_lds_bytes(int maxm);
+void launch_base_relation(const DevEngine& e, const Inputs& in, Tols t, int32_t* status, int maxp, int ldw,
+                          hipStream_t s);
+void launch_rel_compose(const DevEngine& e, int64_t first_task, int64_t ntasks, Tols t, int32_t* status, int maxp,
+                        int ldw, hipStream_t s);
+void launch_domain(const DevEngine& e, const Inputs& in, Tols t, int32_t* status, int maxn, hipStream_t s);
+void launch_eliminate(const DevEngine& e, const Inputs& in, Tols t, int32_t* status, int maxm, int maxq,
+                      hipStream_t s);
+void launch_ric_combine(const DevEngine& e, int64_t first_task, int64_t ntasks, int32_t* status, int maxd,
+                        hipStream_t s);
+void launch_gains(const DevEngine& e, int32_t* status, int maxm, hipStream_t s);
+void launch_fwd_combine(const DevEngine& e, int64_t first_task, int64_t ntasks, hipStream_t s);
+void launch_recover(const DevEngine& e, double* x, double* u, hipStream_t s);
+
+// reversed-time stationarity problem and refinement helpers
+struct DualPtrs {
+  double* f[IN_COUNT];     // data of the reversed-time problem (its own layout)
+  const int64_t* pbase;    // first primal stage of each instance
+  const int64_t* dbase;    // first reversed-time stage of each instance
+};
+struct CorrPtrs {
+  double *q, *r, *c, *g, *x0;
+};
+struct GradPtrs {
+  double* f[IN_COUNT];
+  double* x0;
+};
+
+void launch_dual_matrices(const DevEngine& p, const Inputs& in, const DevEngine& d, const DualPtrs& dp,
+                          hipStream_t s);
+void launch_dual_vectors(const DevEngine& p, const Inputs& in, const double* x, const double* u, const DevEngine& d,
+                         const DualPtrs& dp, hipStream_t s);
+void launch_dual_extract(const DevEngine& p, const DevEngine& d, const double* dx, const double* du, double* lam,
+                         double* mu, const DualPtrs& dp, hipStream_t s);
+void launch_correction(const DevEngine& p, const Inputs& in, const double* x, const double* u, const double* lam,
+                       const double* mu, const CorrPtrs& cp, hipStream_t s);
+void launch_axpy(double* y, const double* x, int64_t n, hipStream_t s);
+void launch_fill(double* y, double v, int64_t n, hipStream_t s);
+void launch_fill_i32(int32_t* y, int32_t v, int64_t n, hipStream_t s);
+void launch_merge_status(int32_t* status, const int32_t* other, int32_t bit, int32_t B, hipStream_t s);
+void launch_finalize(const DevEngine& p, const int32_t* status, double* x, double* u, double* lam, double* mu,
+                     hipStream_t s);
+void launch_kkt_residual(const DevEngine& p, const Inputs& in, const double* x, const double* u, const double* lam,
+                         const double* mu, const int64_t* sbase, double* out, hipStream_t s);
+void launch_grad_assemble(const DevEngine& p, const double* x, const double* u, const double* lam, const double* mu,
+                          const double* ax, const double* au, const double* al, const double* am, const GradPtrs& g,
+                          hipStream_t s);
+
+}  // namespace eclqr

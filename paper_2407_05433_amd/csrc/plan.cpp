@@ -1,0 +1,332 @@
+// Host-side plan construction (no GPU calls).
+//
+// The feasible-domain scan, the Riccati scan and the forward pass are all
+// inclusive suffix scans over L = N + 1 leaves per instance whose last leaf
+// is unary (the terminal relation, the terminal cost, or the initial state of
+// the reversed forward scan).  One balanced schedule (Section IV, "Suffix
+// scan": an up-sweep composing interval aggregates, a down-sweep handing each
+// interval the aggregate to its right) serves all three; only the slot sizes
+// differ.  Tasks of every instance at the same level form one launch.
+#include "plan.hpp"
+#include "scratch.hpp"
+
+#include <algorithm>
+#include <cstdio>
+
+namespace eclqr {
+
+namespace {
+
+struct Node {
+  int32_t s, e, slot;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+std::string Engine::build(const eclqr_dims* d) {
+  B = d->batch;
+  if (B < 1) return "batch must be >= 1";
+  N.assign(d->horizon, d->horizon + B);
+  sbase.resize(B);
+  S = 0;
+  for (int b = 0; b < B; ++b) {
+    if (N[b] < 1) return "every horizon must be >= 1";
+    sbase[b] = S;
+    S += N[b] + 1;
+  }
+  // per-stage dims
+  st.assign(S, StageInfo{});
+  int64_t ui = 0;
+  maxn = maxm = maxk = 0;
+  for (int b = 0; b < B; ++b) {
+    for (int i = 0; i <= N[b]; ++i) {
+      int64_t s = sbase[b] + i;
+      StageInfo& x = st[s];
+      x.n = d->nx[s];
+      x.k = d->nc[s];
+      x.inst = b;
+      x.i = i;
+      x.N = N[b];
+      x.terminal = (i == N[b]);
+      if (i < N[b]) {
+        x.np = d->nx[s + 1];
+        x.m = d->nu[ui++];
+      } else {
+        x.np = 0;
+        x.m = 0;
+      }
+      if (x.n < 0 || x.m < 0 || x.k < 0) return "negative dimension";
+      if (x.n > kMaxDim || x.m > kMaxDim || x.k > kMaxDim)
+        return "dimension above " + std::to_string(kMaxDim);
+      maxn = std::max(maxn, x.n);
+      maxm = std::max(maxm, x.m);
+      maxk = std::max(maxk, x.k);
+    }
+  }
+  // caller layout: blocks in stage order
+  for (int f = 0; f < ECLQR_NUM_FIELDS; ++f) {
+    off[f].assign(f == ECLQR_F_x0 ? B : S, -1);
+    total[f] = 0;
+  }
+  for (int64_t s = 0; s < S; ++s) {
+    StageInfo& x = st[s];
+    const int64_t n = x.n, np = x.np, m = x.m, k = x.k;
+    const int64_t sz[ECLQR_NUM_FIELDS - 1] = {n * n, n, m * m, m, n * m, np * n, np * m, np, k * n, k * m, k};
+    for (int f = 0; f < ECLQR_NUM_FIELDS - 1; ++f) {
+      bool present = !(x.terminal && (f == ECLQR_F_R || f == ECLQR_F_r || f == ECLQR_F_M || f == ECLQR_F_A ||
+                                      f == ECLQR_F_B || f == ECLQR_F_c || f == ECLQR_F_F));
+      off[f][s] = total[f];
+      x.in[f] = total[f];
+      if (present) total[f] += sz[f];
+    }
+    if (x.i == 0) {
+      off[ECLQR_F_x0][x.inst] = total[ECLQR_F_x0];
+      x.x0 = total[ECLQR_F_x0];
+      total[ECLQR_F_x0] += n;
+    }
+  }
+  // stage arenas
+  arena_total = 0;
+  for (int64_t s = 0; s < S; ++s) {
+    st[s].ws = arena_total;
+    arena_total += arena_layout(st[s].n, st[s].np, st[s].m).size;
+  }
+
+  // ---- scan schedule -------------------------------------------------------
+  nslots = 0;
+  slot_inst.clear(); slot_s.clear(); slot_e.clear(); slot_cap.clear();
+  std::vector<std::vector<int32_t>> up_lv, dn_lv;  // tasks per level (flattened triples)
+  D = 0;
+  auto new_slot = [&](int b, int s, int e, int cap) {
+    slot_inst.push_back(b);
+    slot_s.push_back(s);
+    slot_e.push_back(e);
+    slot_cap.push_back(cap);
+    return nslots++;
+  };
+  for (int b = 0; b < B; ++b) {
+    const int L = N[b] + 1;
+    const int64_t s0 = sbase[b];
+    auto ndim = [&](int i) { return st[s0 + i].n; };
+    auto rel_dims = [&](int s, int e, int& na, int& nb) {
+      na = ndim(s);
+      nb = (e == L) ? 0 : ndim(e);
+    };
+    std::vector<std::vector<Node>> lv(1);
+    for (int j = 0; j < L; ++j) {
+      const StageInfo& x = st[s0 + j];
+      int cap = (j < N[b]) ? std::min(x.np + x.k, x.n + x.np) : std::min(x.k, x.n);
+      lv[0].push_back({j, j + 1, new_slot(b, j, j + 1, cap)});
+    }
+    int lev = 0;
+    while (lv[lev].size() > 1) {
+      const auto& cur = lv[lev];
+      std::vector<Node> nxt;
+      if ((int)up_lv.size() <= lev) up_lv.emplace_back();
+      for (size_t j = 0; j < cur.size(); j += 2) {
+        if (j + 1 < cur.size()) {
+          const Node& a = cur[j];
+          const Node& c = cur[j + 1];
+          int na, nb;
+          rel_dims(a.s, c.e, na, nb);
+          int cap = std::min(slot_cap[a.slot] + slot_cap[c.slot], na + nb);
+          int slot = new_slot(b, a.s, c.e, cap);
+          up_lv[lev].insert(up_lv[lev].end(), {a.slot, c.slot, slot});
+          nxt.push_back({a.s, c.e, slot});
+        } else {
+          nxt.push_back(cur[j]);
+        }
+      }
+      lv.push_back(nxt);
+      ++lev;
+    }
+    const int Db = lev;
+    D = std::max(D, Db);
+    // down-sweep: suffix slot of every leaf
+    std::vector<int32_t> suf(L + 1, -1);
+    suf[0] = lv[Db][0].slot;
+    for (int l = Db; l >= 1; --l) {
+      const auto& par = lv[l];
+      const auto& ch = lv[l - 1];
+      // children of par[p] are ch[2p], ch[2p+1]
+      for (size_t p = 0; p < par.size(); ++p) {
+        if (2 * p + 1 >= ch.size()) continue;  // pass-through
+        const Node& v = par[p];
+        const Node& bn = ch[2 * p + 1];
+        if (v.e == L) {
+          suf[bn.s] = bn.slot;
+        } else {
+          int na = ndim(bn.s);
+          int cap = std::min(slot_cap[bn.slot] + slot_cap[suf[v.e]], na);
+          int slot = new_slot(b, bn.s, L, cap);
+          // down level index counts from the top of this instance's tree: all
+          // instances share the bottom level (l = 1) as the last launch.
+          int di = l - 1;
+          if ((int)dn_lv.size() <= di) dn_lv.resize(di + 1);
+          dn_lv[di].insert(dn_lv[di].end(), {bn.slot, suf[v.e], slot});
+          suf[bn.s] = slot;
+        }
+      }
+    }
+    for (int j = 0; j < L; ++j) {
+      if (suf[j] < 0) return "internal error: leaf without suffix";
+    }
+    for (int j = 0; j < L; ++j) {
+      StageInfo& x = st[s0 + j];
+      x.elem[SCAN_REL] = x.elem[SCAN_RIC] = lv[0][j].slot;
+      x.suf[SCAN_REL] = x.suf[SCAN_RIC] = suf[j];
+      // forward scan: leaf j is the closed-loop map of stage N-1-j, leaf N the
+      // initial state; the suffix of leaf j is z_{N-j}
+      x.elem[SCAN_FWD] = (j < N[b]) ? lv[0][N[b] - 1 - j].slot : -1;
+      x.suf[SCAN_FWD] = suf[N[b] - j];
+    }
+  }
+  // levels: up 0..D-1, down D..2D-1 (down level index D-1-di so the top runs first)
+  tasks.clear();
+  lvl_begin.assign(2 * D, 0);
+  lvl_count.assign(2 * D, 0);
+  for (int l = 0; l < D; ++l) {
+    lvl_begin[l] = tasks.size() / 3;
+    if (l < (int)up_lv.size()) tasks.insert(tasks.end(), up_lv[l].begin(), up_lv[l].end());
+    lvl_count[l] = tasks.size() / 3 - lvl_begin[l];
+  }
+  for (int l = 0; l < D; ++l) {
+    int di = D - 1 - l;  // top first
+    lvl_begin[D + l] = tasks.size() / 3;
+    if (di < (int)dn_lv.size()) tasks.insert(tasks.end(), dn_lv[di].begin(), dn_lv[di].end());
+    lvl_count[D + l] = tasks.size() / 3 - lvl_begin[D + l];
+  }
+  // slot dims and sizes per scan
+  for (int k = 0; k < SCAN_COUNT; ++k) {
+    slot_na[k].assign(nslots, 0);
+    slot_nb[k].assign(nslots, 0);
+    slot_off[k].assign(nslots, 0);
+    scan_arena[k] = 0;
+  }
+  for (int32_t q = 0; q < nslots; ++q) {
+    const int b = slot_inst[q], s = slot_s[q], e = slot_e[q];
+    const int L = N[b] + 1;
+    const int64_t s0 = sbase[b];
+    const int na = st[s0 + s].n, nb = (e == L) ? 0 : st[s0 + e].n;
+    slot_na[SCAN_REL][q] = slot_na[SCAN_RIC][q] = na;
+    slot_nb[SCAN_REL][q] = slot_nb[SCAN_RIC][q] = nb;
+    // forward scan reflects the leaf index: output z_{N-s}, input z_{N-e}
+    const int fa = st[s0 + (N[b] - s)].n, fb = (e == L) ? 0 : st[s0 + (N[b] - e)].n;
+    slot_na[SCAN_FWD][q] = fa;
+    slot_nb[SCAN_FWD][q] = fb;
+    slot_off[SCAN_REL][q] = scan_arena[SCAN_REL];
+    scan_arena[SCAN_REL] += rel_slot_size(slot_cap[q], na, nb);
+    slot_off[SCAN_RIC][q] = scan_arena[SCAN_RIC];
+    scan_arena[SCAN_RIC] += ric_layout(na, nb).size;
+    slot_off[SCAN_FWD][q] = scan_arena[SCAN_FWD];
+    scan_arena[SCAN_FWD] += fwd_slot_size(fa, fb);
+  }
+  lvl_rows.assign(2 * D, 0);
+  lvl_dim.assign(2 * D, 0);
+  lvl_ldw.assign(2 * D, 1);
+  for (int l = 0; l < 2 * D; ++l) {
+    for (int64_t t = lvl_begin[l]; t < lvl_begin[l] + lvl_count[l]; ++t) {
+      const int a = tasks[3 * t], c = tasks[3 * t + 1];
+      lvl_rows[l] = std::max(lvl_rows[l], slot_cap[a] + slot_cap[c]);
+      int dm = std::max({slot_na[SCAN_REL][a], slot_nb[SCAN_REL][a], slot_nb[SCAN_REL][c],
+                         slot_na[SCAN_FWD][a], slot_nb[SCAN_FWD][a], slot_nb[SCAN_FWD][c]});
+      lvl_dim[l] = std::max(lvl_dim[l], dm);
+      lvl_ldw[l] = std::max(lvl_ldw[l], slot_na[SCAN_REL][a] + slot_nb[SCAN_REL][a] + slot_nb[SCAN_REL][c] + 1);
+    }
+  }
+  // per-stage kernel sizes
+  base_maxp = 1;
+  base_ldw = 1;
+  elim_maxq = 1;
+  scratch_per_block = 64;
+  for (int64_t s = 0; s < S; ++s) {
+    const StageInfo& x = st[s];
+    if (x.terminal) {
+      base_maxp = std::max(base_maxp, x.k);
+      base_ldw = std::max(base_ldw, x.n + 1);
+    } else {
+      base_maxp = std::max(base_maxp, x.np + x.k);
+      base_ldw = std::max(base_ldw, x.m + x.n + x.np + 1);
+      elim_maxq = std::max(elim_maxq, x.k + x.np);
+    }
+    scratch_per_block = std::max(scratch_per_block, elim_scratch(x.n, x.np, x.m, x.k));
+    scratch_per_block = std::max(scratch_per_block, gains_scratch(x.n, x.np, x.m));
+  }
+  scratch_per_block = std::max(scratch_per_block, ric_scratch(maxn, maxn, maxn));
+  scratch_per_block = rup4(scratch_per_block);
+  nblocks = (int32_t)std::min<int64_t>(S, 2048);
+
+  // ---- workspace map -------------------------------------------------------
+  size_t o = 0;
+  o_stage = o; o = align256(o + sizeof(StageInfo) * S);
+  o_slot_off = o; o = align256(o + sizeof(int64_t) * nslots * SCAN_COUNT);
+  o_slot_na = o; o = align256(o + sizeof(int32_t) * nslots * SCAN_COUNT);
+  o_slot_nb = o; o = align256(o + sizeof(int32_t) * nslots * SCAN_COUNT);
+  o_slot_cap = o; o = align256(o + sizeof(int32_t) * nslots);
+  o_slot_rows = o; o = align256(o + sizeof(int32_t) * nslots);
+  o_tasks = o; o = align256(o + sizeof(int32_t) * tasks.size() + 16);
+  o_nbar = o; o = align256(o + sizeof(int32_t) * S);
+  o_mbar = o; o = align256(o + sizeof(int32_t) * S);
+  o_resid = o; o = align256(o + sizeof(double) * 4 * S);
+  o_sbase = o; o = align256(o + sizeof(int64_t) * B);
+  o_scratch = o; o = align256(o + sizeof(double) * scratch_per_block * nblocks);
+  o_arena = o; o = align256(o + sizeof(double) * arena_total);
+  for (int k = 0; k < SCAN_COUNT; ++k) {
+    o_scan[k] = o;
+    o = align256(o + sizeof(double) * scan_arena[k]);
+  }
+  bytes = o;
+  return "";
+}
+
+std::string build_plan(Plan& p, const eclqr_dims* d, const eclqr_options* opt) {
+  p.opt = *opt;
+  std::string err = p.primal.build(d);
+  if (!err.empty()) return err;
+  const Engine& P = p.primal;
+  // Reversed-time stationarity problem (Section VII): stage 0 has an empty
+  // state and input mu_N; stage j = 1..N is primal stage i = N - j with state
+  // lambda_{i+1}, input mu_i and m_i mixed rows; the terminal state is lambda_0.
+  std::vector<int32_t> hor(P.B), nx, nu, nc;
+  for (int b = 0; b < P.B; ++b) {
+    const int Nb = P.N[b];
+    const int64_t s0 = P.sbase[b];
+    hor[b] = Nb + 1;
+    nx.push_back(0);
+    for (int j = 1; j <= Nb + 1; ++j) nx.push_back(P.st[s0 + Nb - j + 1].n);
+    nu.push_back(P.st[s0 + Nb].k);
+    for (int j = 1; j <= Nb; ++j) nu.push_back(P.st[s0 + Nb - j].k);
+    nc.push_back(0);
+    for (int j = 1; j <= Nb; ++j) nc.push_back(P.st[s0 + Nb - j].m);
+    nc.push_back(0);
+  }
+  eclqr_dims dd{P.B, hor.data(), nx.data(), nu.data(), nc.data()};
+  err = p.dual.build(&dd);
+  if (!err.empty()) return "dual: " + err;
+
+  size_t o = 0;
+  p.o_primal = o; o = align256(o + p.primal.bytes);
+  p.o_dual = o; o = align256(o + p.dual.bytes);
+  for (int f = 0; f < ECLQR_NUM_FIELDS; ++f) {
+    p.o_dprob[f] = o;
+    o = align256(o + sizeof(double) * std::max<int64_t>(1, p.dual.total[f]));
+  }
+  p.o_dx = o; o = align256(o + sizeof(double) * std::max<int64_t>(1, p.dual.total[ECLQR_F_q]));
+  p.o_du = o; o = align256(o + sizeof(double) * std::max<int64_t>(1, p.dual.total[ECLQR_F_r]));
+  p.o_dstatus = o; o = align256(o + sizeof(int32_t) * P.B);
+  for (int f : {ECLQR_F_q, ECLQR_F_r, ECLQR_F_c, ECLQR_F_g, ECLQR_F_x0}) {
+    p.o_corr[f] = o;
+    o = align256(o + sizeof(double) * std::max<int64_t>(1, P.total[f]));
+  }
+  p.o_cx = o; o = align256(o + sizeof(double) * std::max<int64_t>(1, P.total[ECLQR_F_q]));
+  p.o_cu = o; o = align256(o + sizeof(double) * std::max<int64_t>(1, P.total[ECLQR_F_r]));
+  p.o_clam = o; o = align256(o + sizeof(double) * std::max<int64_t>(1, P.total[ECLQR_F_q]));
+  p.o_cmu = o; o = align256(o + sizeof(double) * std::max<int64_t>(1, P.total[ECLQR_F_g]));
+  p.o_flag = o; o = align256(o + sizeof(int32_t) * 64);
+  p.bytes = o;
+  return "";
+}
+
+}  // namespace eclqr

@@ -1,0 +1,81 @@
+// Host-side plan: caller layout, workspace map and the associative-scan
+// schedule for one problem structure (the primal problem, or the reversed-time
+// stationarity problem that yields the multipliers).
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "eclqr.h"
+
+namespace eclqr {
+
+struct Engine {
+  int32_t B = 0;
+  std::vector<int32_t> N;        // horizon per instance
+  std::vector<int64_t> sbase;    // first global stage of each instance
+  int64_t S = 0;                 // stages, sum_b (N_b + 1)
+  std::vector<StageInfo> st;
+
+  // caller layout
+  std::vector<int64_t> off[ECLQR_NUM_FIELDS];
+  int64_t total[ECLQR_NUM_FIELDS] = {0};
+
+  // scans: slot tables shared by the three scans (same ids, different sizes)
+  int32_t nslots = 0;
+  std::vector<int32_t> slot_inst, slot_s, slot_e;
+  std::vector<int32_t> slot_na[SCAN_COUNT], slot_nb[SCAN_COUNT];
+  std::vector<int32_t> slot_cap;  // REL row capacity
+  std::vector<int64_t> slot_off[SCAN_COUNT];
+  int64_t scan_arena[SCAN_COUNT] = {0, 0, 0};
+
+  // levels: 0..D-1 up-sweep (level l combines nodes of level l), D..2D-1
+  // down-sweep (from the top down).  Tasks are (left, right, out) slot triples.
+  int32_t D = 0;
+  std::vector<int32_t> tasks;
+  std::vector<int64_t> lvl_begin, lvl_count;
+  std::vector<int32_t> lvl_rows;    // REL: max (cap_left + cap_right) over the level
+  std::vector<int32_t> lvl_dim;     // max endpoint dim over the level's operands
+  std::vector<int32_t> lvl_ldw;     // REL: max (n_a + n_b + n_c + 1) over the level
+
+  int64_t arena_total = 0;  // stage arena doubles
+  int32_t maxn = 0, maxm = 0, maxk = 0;
+  int32_t base_maxp = 0, base_ldw = 0, elim_maxq = 0;
+  int32_t nblocks = 0;             // grid of the stage-parallel kernels
+  int64_t scratch_per_block = 0;   // doubles
+
+  // workspace map (byte offsets from the engine's base)
+  size_t o_stage = 0, o_slot_off = 0, o_slot_na = 0, o_slot_nb = 0, o_slot_cap = 0, o_slot_rows = 0,
+         o_tasks = 0, o_nbar = 0, o_mbar = 0, o_arena = 0, o_scan[SCAN_COUNT] = {0, 0, 0}, o_resid = 0,
+         o_sbase = 0, o_scratch = 0;
+  size_t bytes = 0;
+
+  std::string build(const eclqr_dims* d);
+};
+
+struct Plan {
+  eclqr_options opt;
+  Engine primal, dual;
+  // workspace regions (bytes from the workspace base)
+  size_t o_primal = 0, o_dual = 0;
+  size_t o_dprob[ECLQR_NUM_FIELDS] = {0};  // reversed-time stationarity problem data
+  size_t o_dx = 0, o_du = 0, o_dstatus = 0;
+  size_t o_corr[ECLQR_NUM_FIELDS] = {0};   // correction / adjoint problem vectors (q r c g x0)
+  size_t o_cx = 0, o_cu = 0, o_clam = 0, o_cmu = 0, o_zero = 0;
+  size_t o_flag = 0;
+  size_t bytes = 0;
+  void* bound_ws = nullptr;
+  int bound_device = -1;
+};
+
+std::string build_plan(Plan& p, const eclqr_dims* d, const eclqr_options* opt);
+
+}  // namespace eclqr
+
+struct eclqr_plan {
+  eclqr::Plan p;
+};

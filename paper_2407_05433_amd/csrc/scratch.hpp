@@ -1,0 +1,46 @@
+// Per-workgroup global scratch sizes (doubles), shared by host and device so
+// the host can size the workspace exactly.
+#pragma once
+
+#include "common.hpp"
+
+namespace eclqr {
+
+ECLQR_HD inline int64_t rup4(int64_t x) { return (x + 3) & ~int64_t(3); }
+
+// stage elimination: dims of the stage (n, n', m, k) at capacity
+ECLQR_HD inline int64_t elim_scratch(int n, int np, int m, int k) {
+  const int64_t q = k + np;
+  int64_t s = 0;
+  s += rup4(q * m) + rup4(q * n) + rup4(q) + rup4(q * n) + rup4(q);  // Gs Ps gs Phi gam
+  s += rup4((int64_t)m * m) + rup4((int64_t)m * (n + 1));             // Qg X
+  s += rup4((int64_t)np * n) + rup4((int64_t)np * m) + rup4(np);      // AT BZ cv
+  s += rup4((int64_t)n * n) + rup4((int64_t)n * m);                   // QT Mz
+  s += rup4((int64_t)m * n) + rup4((int64_t)m * m) + rup4((int64_t)n * n);  // RY RZ MzY
+  s += rup4(m) + rup4(n) + rup4(m);                                   // w qz rz
+  s += rup4((int64_t)m * m) + rup4((int64_t)m * np) + rup4((int64_t)m * n) + rup4(m);  // L Wt V w2
+  s += rup4(q) + 64;                                                  // row scales, misc
+  return s;
+}
+
+// Riccati combine over endpoint dims (ds, dm, de)
+ECLQR_HD inline int64_t ric_scratch(int ds, int dm, int de) {
+  int64_t s = 0;
+  s += rup4((int64_t)dm * dm);            // Mmat (LU)
+  s += rup4((int64_t)dm * (ds + 1 + dm)); // X = Minv [A1 | b1 + C1 eta2 | C1]
+  s += rup4((int64_t)dm * (dm + 1));      // Y = Minv^T [J2 | eta2 - J2 b1]
+  s += rup4((int64_t)de * dm);            // A2 X_C
+  s += rup4((int64_t)ds * dm);            // A1^T Y_J
+  s += 64;
+  return s;
+}
+
+// gains: dims at capacity (n, n', m)
+ECLQR_HD inline int64_t gains_scratch(int n, int np, int m) {
+  int64_t s = 0;
+  s += rup4((int64_t)np * m) + rup4((int64_t)m * m) + rup4((int64_t)np * n) + rup4((int64_t)m * n);
+  s += rup4(np) + rup4(m) + 64;
+  return s;
+}
+
+}  // namespace eclqr

@@ -1,0 +1,239 @@
+"""Python binding of the solver: plans, packing into flat device tensors, and
+the solve / backward / residual calls of the C ABI.  PyTorch provides device
+memory and the current HIP stream; every computation runs in the HIP kernels."""
+
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import FIELDS, FIELD_INDEX, check, lib
+
+
+def default_options(**kw) -> _lib.Options:
+    o = _lib.Options()
+    lib().eclqr_default_options(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+class Plan:
+    """Host-side plan for a batch of instances with given per-stage dims.
+
+    ``dims`` is a list of (nx, nu, nc) per instance: nx has N+1 entries, nu N,
+    nc N+1 (the last = terminal rows)."""
+
+    def __init__(self, dims: Sequence, **options):
+        nx, nu, nc, hor = [], [], [], []
+        for (x, u, c) in dims:
+            N = len(u)
+            if len(x) != N + 1 or len(c) != N + 1:
+                raise ValueError("nx and nc need N+1 entries, nu N")
+            hor.append(N)
+            nx += list(x)
+            nu += list(u)
+            nc += list(c)
+        self.horizons = hor
+        self.batch = len(hor)
+        self._nx = np.asarray(nx, dtype=np.int32)
+        self._nu = np.asarray(nu, dtype=np.int32)
+        self._nc = np.asarray(nc, dtype=np.int32)
+        d = _lib.Dims(self.batch, self._arr(hor), self._arr(nx), self._arr(nu), self._arr(nc))
+        self.options = default_options(**options)
+        h = C.c_void_p()
+        check(lib().eclqr_plan_create(C.byref(h), C.byref(d), C.byref(self.options)), "eclqr_plan_create")
+        self._h = h
+        sz = C.c_size_t()
+        check(lib().eclqr_plan_workspace_size(h, C.byref(sz)), "eclqr_plan_workspace_size")
+        self.workspace_bytes = int(sz.value)
+        self._layout: Dict[str, tuple] = {}
+
+    @staticmethod
+    def _arr(v):
+        a = (C.c_int32 * max(1, len(v)))()
+        for i, x in enumerate(v):
+            a[i] = int(x)
+        return a
+
+    @classmethod
+    def for_problems(cls, problems, **options) -> "Plan":
+        return cls([(p.nx, p.nu, p.nc) for p in problems], **options)
+
+    def layout(self, field: str):
+        """(per-stage offsets as int64 numpy array, total elements)."""
+        if field not in self._layout:
+            ptr = C.POINTER(C.c_int64)()
+            cnt, tot = C.c_int64(), C.c_int64()
+            check(lib().eclqr_plan_layout(self._h, FIELD_INDEX[field], C.byref(ptr), C.byref(cnt), C.byref(tot)),
+                  "eclqr_plan_layout")
+            offs = np.ctypeslib.as_array(ptr, shape=(cnt.value,)).copy() if cnt.value else np.zeros(0, np.int64)
+            self._layout[field] = (offs, int(tot.value))
+        return self._layout[field]
+
+    def schedule(self, dual: bool = False) -> List[np.ndarray]:
+        lev = C.c_int32()
+        check(lib().eclqr_plan_schedule(self._h, int(dual), C.byref(lev), -1, None, None), "eclqr_plan_schedule")
+        out = []
+        for level in range(lev.value):
+            ptr = C.POINTER(C.c_int32)()
+            nt = C.c_int32()
+            check(lib().eclqr_plan_schedule(self._h, int(dual), None, level, C.byref(ptr), C.byref(nt)),
+                  "eclqr_plan_schedule")
+            out.append(np.ctypeslib.as_array(ptr, shape=(nt.value * 3,)).reshape(-1, 3).copy()
+                       if nt.value else np.zeros((0, 3), np.int32))
+        return out
+
+    def workspace(self, device="cuda") -> torch.Tensor:
+        return torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=device)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().eclqr_plan_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+
+def pack(plan: Plan, problems, device="cuda", with_M: Optional[bool] = None) -> Dict[str, torch.Tensor]:
+    """Flat FP64 device tensors of every field, in the plan's layout (blocks in
+    stage order, instance after instance)."""
+    if with_M is None:
+        with_M = any(np.any(Mi) for p in problems for Mi in p.M)
+    out: Dict[str, torch.Tensor] = {}
+    for f in FIELDS:
+        if f == "M" and not with_M:
+            continue
+        if f == "x0":
+            parts = [np.asarray(p.x0, dtype=np.float64).ravel() for p in problems]
+        else:
+            parts = [np.asarray(a, dtype=np.float64).ravel() for p in problems for a in getattr(p, f)]
+        flat = np.concatenate(parts) if parts else np.zeros(0)
+        offs, tot = plan.layout(f)
+        if flat.size != tot:
+            raise ValueError(f"field {f}: {flat.size} elements, layout expects {tot}")
+        out[f] = torch.from_numpy(np.ascontiguousarray(flat)).to(device)
+    return out
+
+
+@dataclass
+class Solution:
+    x: torch.Tensor
+    u: torch.Tensor
+    lam: Optional[torch.Tensor]
+    mu: Optional[torch.Tensor]
+    status: torch.Tensor
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if t.dtype == torch.float64 or t.dtype == torch.int32 or t.dtype == torch.uint8:
+        return C.c_void_p(t.data_ptr()) if t.numel() else C.c_void_p(t.data_ptr() or 0)
+    raise TypeError(t.dtype)
+
+
+def _problem_ptrs(data: Dict[str, torch.Tensor]) -> _lib.ProblemPtrs:
+    pp = _lib.ProblemPtrs()
+    for f in FIELDS:
+        t = data.get(f)
+        setattr(pp, f, t.data_ptr() if (t is not None and t.numel()) else (t.data_ptr() if t is not None else None))
+    return pp
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _aligned_ws(ws: torch.Tensor):
+    base = ws.data_ptr()
+    off = (-base) % 256
+    return base + off, ws.numel() - off
+
+
+def allocate_solution(plan: Plan, device="cuda", multipliers: bool = True) -> Solution:
+    _, nq = plan.layout("q")
+    _, nr = plan.layout("r")
+    _, ng = plan.layout("g")
+    mk = lambda n: torch.empty(max(1, n), dtype=torch.float64, device=device)  # noqa: E731
+    return Solution(mk(nq), mk(nr), mk(nq) if multipliers else None, mk(ng) if multipliers else None,
+                    torch.empty(plan.batch, dtype=torch.int32, device=device))
+
+
+def solve(plan: Plan, data: Dict[str, torch.Tensor], ws: Optional[torch.Tensor] = None,
+          out: Optional[Solution] = None) -> Solution:
+    """eclqr_solve on the current stream (asynchronous)."""
+    device = data["Q"].device
+    if ws is None:
+        ws = plan.workspace(device)
+    if out is None:
+        out = allocate_solution(plan, device, bool(plan.options.multipliers))
+    sp = _lib.SolutionPtrs(out.x.data_ptr(), out.u.data_ptr(),
+                           out.lam.data_ptr() if out.lam is not None else None,
+                           out.mu.data_ptr() if out.mu is not None else None, out.status.data_ptr())
+    pp = _problem_ptrs(data)
+    wptr, wbytes = _aligned_ws(ws)
+    check(lib().eclqr_solve(plan.handle, C.byref(pp), C.byref(sp), C.c_void_p(wptr), C.c_size_t(wbytes), _stream()),
+          "eclqr_solve")
+    out._ws = ws  # keep the workspace alive with the solution (backward reuses it)
+    return out
+
+
+def backward(plan: Plan, data: Dict[str, torch.Tensor], sol: Solution, dx: torch.Tensor, du: torch.Tensor,
+             ws: torch.Tensor) -> Dict[str, torch.Tensor]:
+    """eclqr_backward: gradients of a loss L(x, u) given dL/dx, dL/du."""
+    device = dx.device
+    grads = {f: torch.empty(max(1, plan.layout(f)[1]), dtype=torch.float64, device=device)
+             for f in FIELDS if f != "M" or "M" in data}
+    gp = _lib.GradPtrs()
+    for f in FIELDS:
+        setattr(gp, f, grads[f].data_ptr() if f in grads else None)
+    sp = _lib.SolutionPtrs(sol.x.data_ptr(), sol.u.data_ptr(), sol.lam.data_ptr(), sol.mu.data_ptr(),
+                           sol.status.data_ptr())
+    ct = _lib.CotangentPtrs(dx.data_ptr(), du.data_ptr())
+    pp = _problem_ptrs(data)
+    wptr, wbytes = _aligned_ws(ws)
+    check(lib().eclqr_backward(plan.handle, C.byref(pp), C.byref(sp), C.byref(ct), C.byref(gp), C.c_void_p(wptr),
+                               C.c_size_t(wbytes), _stream()), "eclqr_backward")
+    return grads
+
+
+def kkt_residual(plan: Plan, data: Dict[str, torch.Tensor], sol: Solution, ws: torch.Tensor) -> torch.Tensor:
+    out = torch.empty(4 * plan.batch, dtype=torch.float64, device=sol.x.device)
+    sp = _lib.SolutionPtrs(sol.x.data_ptr(), sol.u.data_ptr(), sol.lam.data_ptr(), sol.mu.data_ptr(),
+                           sol.status.data_ptr())
+    pp = _problem_ptrs(data)
+    wptr, wbytes = _aligned_ws(ws)
+    check(lib().eclqr_kkt_residual(plan.handle, C.byref(pp), C.byref(sp), C.c_void_p(out.data_ptr()),
+                                   C.c_void_p(wptr), C.c_size_t(wbytes), _stream()), "eclqr_kkt_residual")
+    return out.view(plan.batch, 4)
+
+
+def unpack(plan: Plan, flat: torch.Tensor, field: str, problems) -> List[List[np.ndarray]]:
+    """Split a flat output (layout of ``field``: 'q' for x/lam, 'r' for u, 'g' for mu)
+    into per-instance lists of per-stage vectors."""
+    arr = flat.detach().cpu().numpy()
+    offs, _ = plan.layout(field)
+    out, s = [], 0
+    for p in problems:
+        sizes = {"q": p.nx, "r": p.nu, "g": p.nc}[field]
+        blocks = []
+        for i, n in enumerate(sizes):
+            o = int(offs[s + i])
+            blocks.append(arr[o:o + n].copy())
+        out.append(blocks)
+        s += p.N + 1
+    return out

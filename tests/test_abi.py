@@ -1,0 +1,157 @@
+"""CPU checks of the C ABI library: it loads, exports every function that
+include/eclqr.h declares, validates arguments, lays out the caller's fields in
+stage order, and its associative-scan schedule computes the right suffix
+relations (replayed here with the oracle's composition on the CPU)."""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2407_05433_amd as ecl
+from paper_2407_05433_amd import _lib
+from workloads import config_c0, config_c3
+from tests._util import tiny_problem
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "eclqr.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(eclqr_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    names = _declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), n
+    assert L.eclqr_abi_version() == 1
+
+
+def test_status_strings_and_defaults():
+    L = _lib.lib()
+    assert L.eclqr_status_string(0) == b"ok"
+    assert L.eclqr_status_string(2) == b"infeasible_initial"
+    o = ecl.default_options()
+    assert o.rank_tol == 1e-10 and o.cons_tol == 1e-8 and o.multipliers == 1 and o.refine == 1
+
+
+def test_plan_rejects_bad_dims():
+    with pytest.raises(ecl.EclqrError):
+        ecl.Plan([([3], [], [0])])  # N = 0
+    with pytest.raises(ecl.EclqrError):
+        ecl.Plan([([3, 65], [2], [0, 0])])  # dimension above the kernel limit
+    with pytest.raises(ValueError):
+        ecl.Plan([([3, 3, 3], [2], [0, 0])])
+
+
+def test_layout_is_stage_order_concatenation():
+    probs = [tiny_problem(700 + s, nx=[2, 3, 4, 3], nu=[1, 2, 3], terminal_rows=1) for s in range(3)]
+    plan = ecl.Plan.for_problems(probs)
+    for f in ("Q", "q", "R", "r", "A", "B", "c", "E", "F", "g"):
+        offs, tot = plan.layout(f)
+        sizes = [a.size for p in probs for a in getattr(p, f)]
+        assert tot == sum(sizes)
+        # offsets of the present blocks are the running sums
+        run, k = 0, 0
+        for p in probs:
+            n_blocks = len(getattr(p, f))
+            for i in range(p.N + 1):
+                if i < n_blocks:
+                    assert offs[k + i] == run
+                    run += getattr(p, f)[i].size
+            k += p.N + 1
+    offs, tot = plan.layout("x0")
+    assert list(offs) == [0, 2, 4] and tot == 6
+    assert plan.workspace_bytes > 0
+
+
+def _replay_schedule(plan, problem):
+    """Run the plan's task list with the oracle's composition; return the
+    suffix relation of every leaf."""
+    from oracle.relations import base_relation, compose, terminal_relation
+    N = problem.N
+    rel = {}
+    for i in range(N):
+        rel[i] = base_relation(problem.A[i], problem.B[i], problem.c[i], problem.E[i], problem.F[i], problem.g[i])
+    rel[N] = terminal_relation(problem.E[N], problem.g[N])
+    levels = plan.schedule()
+    D = len(levels) // 2
+    for lv in levels:
+        for a, b, o in lv:
+            rel[int(o)] = compose(rel[int(a)], rel[int(b)])
+    return rel, levels, D
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 5, 8, 13, 16])
+def test_schedule_reproduces_sequential_suffixes(N):
+    from oracle import solve_sequential
+    from oracle.relations import same_set
+    p = tiny_problem(800 + N, N=N, n=3, m=1, kinds=[["state"]] * N, terminal_rows=2)
+    plan = ecl.Plan.for_problems([p])
+    rel, levels, D = _replay_schedule(plan, p)
+    assert D == max(1, int(np.ceil(np.log2(N + 1))))
+    seq = solve_sequential(p, keep_relations=True)
+    # every leaf's suffix slot must hold S_i; locate it through the stage table
+    # (slots are leaves 0..N, then internal / suffix slots in allocation order)
+    leaf_suffix = _leaf_suffix_slots(plan, N)
+    for i in range(N + 1):
+        assert same_set(rel[leaf_suffix[i]], seq.suffix[i], tol=1e-9), i
+
+
+def _leaf_suffix_slots(plan, N):
+    """Recover suffix slot ids by re-deriving the down-sweep from the task lists:
+    the output of a down task is the suffix of the leaf its left operand starts at."""
+    levels = plan.schedule()
+    D = len(levels) // 2
+    start = {i: i for i in range(N + 1)}  # slot -> first leaf
+    for lv in levels[:D]:
+        for a, b, o in lv:
+            start[int(o)] = start[int(a)]
+    suf = {}
+    # root: the last up task's output covers leaf 0
+    root = int(levels[D - 1][-1][2]) if D else 0
+    suf[0] = root
+    for lv in levels[D:]:
+        for a, b, o in lv:
+            suf[start[int(a)]] = int(o)
+    # leaves whose suffix aliases a node containing the terminal: their node is
+    # the right child of a spine node, i.e. an up-sweep operand whose start is i
+    for i in range(1, N + 1):
+        if i not in suf:
+            cands = [int(b) for lv in levels[:D] for a, b, o in lv if start[int(b)] == i]
+            cands += [i] if i == N else []
+            # the largest node starting at i that reaches the end
+            suf[i] = max(cands) if cands else i
+    return suf
+
+
+def test_batched_schedule_levels_merge_instances():
+    probs = [tiny_problem(900 + s, N=N, n=2, m=1, kinds=[[]] * N, terminal_rows=0) for s, N in
+             enumerate([3, 17, 1, 64])]
+    plan = ecl.Plan.for_problems(probs)
+    levels = plan.schedule()
+    D = len(levels) // 2
+    assert D == 7  # ceil(log2(65))
+    total_up = sum(len(lv) for lv in levels[:D])
+    assert total_up == sum(p.N for p in probs)  # L - 1 combines per instance
+    # the reversed-time problem has one more stage per instance
+    dlev = plan.schedule(dual=True)
+    assert sum(len(lv) for lv in dlev[:len(dlev) // 2]) == sum(p.N + 1 for p in probs)
+
+
+def test_c3_plan_builds_quickly():
+    import time
+    probs = config_c3(B=64)
+    t = time.time()
+    plan = ecl.Plan.for_problems(probs)
+    assert time.time() - t < 5.0
+    assert plan.batch == 64
