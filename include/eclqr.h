@@ -170,6 +170,41 @@ eclqr_status eclqr_backward(eclqr_plan* plan, const eclqr_problem* prob, const e
 eclqr_status eclqr_kkt_residual(eclqr_plan* plan, const eclqr_problem* prob, const eclqr_solution* sol,
                                 double* out, void* ws, size_t ws_bytes, void* stream);
 
+/* Kernel classes timed by the optional profiler. */
+enum {
+  ECLQR_K_VALIDATE = 0, ECLQR_K_BASE_RELATION, ECLQR_K_REL_COMPOSE, ECLQR_K_DOMAIN, ECLQR_K_ELIMINATE,
+  ECLQR_K_RIC_COMBINE, ECLQR_K_GAINS, ECLQR_K_FWD_COMBINE, ECLQR_K_RECOVER, ECLQR_K_MULTIPLIER_IO,
+  ECLQR_K_REFINE_IO, ECLQR_K_OTHER, ECLQR_NUM_KERNEL_CLASSES
+};
+
+/* Profiler: when on, every later solve/backward records a HIP event pair
+ * around each launch of every kernel class on the launch stream.
+ * eclqr_plan_profile synchronises the recorded events and returns, per class,
+ * the summed milliseconds and the number of launches (arrays of
+ * ECLQR_NUM_KERNEL_CLASSES, host memory), then clears them if reset != 0. */
+eclqr_status eclqr_plan_set_profiling(eclqr_plan* plan, int32_t on);
+eclqr_status eclqr_plan_profile(eclqr_plan* plan, double* ms, int64_t* launches, int32_t reset);
+const char* eclqr_kernel_class_name(int32_t k);
+
+/* Reduced dimensions n-bar_i, m-bar_i (Section V) computed by the last solve
+ * in workspace ws, copied to host arrays of length sum_b (N_b + 1) (m-bar of a
+ * terminal stage is 0).  which = 0: the problem; 1: the reversed-time
+ * stationarity problem of the multipliers.  Synchronises the device. */
+eclqr_status eclqr_plan_reduced_dims(const eclqr_plan* plan, const void* ws, int32_t which, int32_t* nbar,
+                                     int32_t* mbar);
+
+/* Row counts of every slot of the feasible-domain scan after the last solve
+ * in ws (rows of the affine relation each slot holds); *nslots receives the
+ * slot count, rows (host, may be NULL) nslots entries.  Synchronises. */
+eclqr_status eclqr_plan_scan_rows(const eclqr_plan* plan, const void* ws, int32_t which, int32_t* rows,
+                                  int32_t* nslots);
+
+/* Interval of every scan slot: instance, first leaf, one past the last leaf
+ * (leaf N_b is the terminal; a slot whose end is N_b + 1 is unary).  Host
+ * arrays of *nslots entries (may be NULL to query *nslots only). */
+eclqr_status eclqr_plan_slot_info(const eclqr_plan* plan, int32_t which, int32_t* inst, int32_t* first,
+                                  int32_t* last, int32_t* nslots);
+
 /* Introspection of the scan schedule (tests): number of levels and, for
  * level l (0..levels-1, up-sweep then down-sweep), the task triples
  * (left slot, right slot, output slot) in plan-owned host memory. */

@@ -14,6 +14,8 @@ NUM_FIELDS = 12
 FIELDS = ("Q", "q", "R", "r", "M", "A", "B", "c", "E", "F", "g", "x0")
 FIELD_INDEX = {f: i for i, f in enumerate(FIELDS)}
 
+NUM_KERNEL_CLASSES = 12
+
 STATUS_BITS = {
     1: "infeasible_suffix",
     2: "infeasible_initial",
@@ -83,8 +85,21 @@ def lib():
                                  C.POINTER(CotangentPtrs), C.POINTER(GradPtrs), C.c_void_p, C.c_size_t, C.c_void_p]
     L.eclqr_kkt_residual.argtypes = [C.c_void_p, C.POINTER(ProblemPtrs), C.POINTER(SolutionPtrs), C.c_void_p,
                                      C.c_void_p, C.c_size_t, C.c_void_p]
+    L.eclqr_plan_set_profiling.argtypes = [C.c_void_p, C.c_int32]
+    L.eclqr_plan_profile.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
+    L.eclqr_kernel_class_name.restype = C.c_char_p
+    L.eclqr_kernel_class_name.argtypes = [C.c_int32]
+    L.eclqr_plan_reduced_dims.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32),
+                                          C.POINTER(C.c_int32)]
+    L.eclqr_plan_scan_rows.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_int32)]
+    L.eclqr_plan_scan_rows.restype = C.c_int
+    L.eclqr_plan_slot_info.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    L.eclqr_plan_slot_info.restype = C.c_int
     for fn in ("eclqr_plan_create", "eclqr_plan_layout", "eclqr_plan_workspace_size", "eclqr_plan_schedule",
-               "eclqr_solve", "eclqr_backward", "eclqr_kkt_residual"):
+               "eclqr_solve", "eclqr_backward", "eclqr_kkt_residual", "eclqr_plan_set_profiling",
+               "eclqr_plan_profile", "eclqr_plan_reduced_dims"):
         getattr(L, fn).restype = C.c_int
     _lib = L
     return L

@@ -94,6 +94,40 @@ eclqr_status upload_engine(const Engine& E, void* ws, size_t base, hipStream_t s
 
 int g_max_lds = 65536;
 
+// ---- profiler ------------------------------------------------------------------
+Plan* g_prof = nullptr;  // plan whose launches are being timed (set per call)
+
+hipEvent_t next_event(Plan& p) {
+  if (p.pool_next == p.event_pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    p.event_pool.push_back(reinterpret_cast<void*>(e));
+  }
+  return reinterpret_cast<hipEvent_t>(p.event_pool[p.pool_next++]);
+}
+
+struct Timed {
+  Plan* p;
+  int cls;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  Timed(int c, hipStream_t st) : p(g_prof), cls(c), s(st) {
+    if (p && p->profiling) {
+      a = next_event(*p);
+      if (a) (void)hipEventRecord(a, s);
+    }
+  }
+  ~Timed() {
+    if (a) {
+      hipEvent_t b = next_event(*p);
+      if (b) {
+        (void)hipEventRecord(b, s);
+        p->events.push_back({cls, {reinterpret_cast<void*>(a), reinterpret_cast<void*>(b)}});
+      }
+    }
+  }
+};
+
 eclqr_status bind(Plan& p, void* ws, hipStream_t s) {
   int dev = -1;
   HIP_OK(hipGetDevice(&dev));
@@ -118,21 +152,30 @@ eclqr_status bind(Plan& p, void* ws, hipStream_t s) {
 // One pass of the primal method of Algorithm 1 on the data `in`, writing x, u.
 eclqr_status run_engine(const Engine& E, const DevEngine& d, const Inputs& in, double* x, double* u,
                         int32_t* status, Tols t, hipStream_t s) {
-  launch_validate(d, in, status, s);
-  launch_base_relation(d, in, t, status, E.base_maxp, E.base_ldw, s);
+  { Timed tm(ECLQR_K_VALIDATE, s); launch_validate(d, in, status, s); }
+  { Timed tm(ECLQR_K_BASE_RELATION, s); launch_base_relation(d, in, t, status, E.base_maxp, E.base_ldw, s); }
   for (int l = 0; l < 2 * E.D; ++l) {
+    if (E.lvl_count[l] == 0) continue;
     // rows of the stacked system that fit the device's LDS (larger tasks are flagged ECLQR_CAPACITY)
     int rows = std::max(1, E.lvl_rows[l]);
     while (rows > 1 && rel_lds_bytes(rows, E.lvl_ldw[l]) > (size_t)g_max_lds) --rows;
+    Timed tm(ECLQR_K_REL_COMPOSE, s);
     launch_rel_compose(d, E.lvl_begin[l], E.lvl_count[l], t, status, rows, E.lvl_ldw[l], s);
   }
-  launch_domain(d, in, t, status, std::max(1, E.maxn), s);
-  launch_eliminate(d, in, t, status, std::max(1, E.maxm), E.elim_maxq, s);
-  for (int l = 0; l < 2 * E.D; ++l)
+  { Timed tm(ECLQR_K_DOMAIN, s); launch_domain(d, in, t, status, std::max(1, E.maxn), s); }
+  { Timed tm(ECLQR_K_ELIMINATE, s); launch_eliminate(d, in, t, status, std::max(1, E.maxm), E.elim_maxq, s); }
+  for (int l = 0; l < 2 * E.D; ++l) {
+    if (E.lvl_count[l] == 0) continue;
+    Timed tm(ECLQR_K_RIC_COMBINE, s);
     launch_ric_combine(d, E.lvl_begin[l], E.lvl_count[l], status, std::max(1, E.maxn), s);
-  launch_gains(d, status, std::max(1, E.maxm), s);
-  for (int l = 0; l < 2 * E.D; ++l) launch_fwd_combine(d, E.lvl_begin[l], E.lvl_count[l], s);
-  launch_recover(d, x, u, s);
+  }
+  { Timed tm(ECLQR_K_GAINS, s); launch_gains(d, status, std::max(1, E.maxm), s); }
+  for (int l = 0; l < 2 * E.D; ++l) {
+    if (E.lvl_count[l] == 0) continue;
+    Timed tm(ECLQR_K_FWD_COMBINE, s);
+    launch_fwd_combine(d, E.lvl_begin[l], E.lvl_count[l], s);
+  }
+  { Timed tm(ECLQR_K_RECOVER, s); launch_recover(d, x, u, s); }
   HIP_OK(hipGetLastError());
   return ECLQR_SUCCESS;
 }
@@ -199,14 +242,20 @@ Inputs dual_inputs(const Views& v) {
 eclqr_status multipliers(Plan& p, const Views& v, const Inputs& in, const double* x, const double* u, double* lam,
                          double* mu, int32_t* status, hipStream_t s) {
   const Tols td{p.opt.rank_tol, p.opt.dual_cons_tol, 0};
-  launch_dual_vectors(v.P, in, x, u, v.D, v.dp, s);
-  launch_fill_i32(v.dstatus, 0, p.primal.B, s);
+  {
+    Timed tm(ECLQR_K_MULTIPLIER_IO, s);
+    launch_dual_vectors(v.P, in, x, u, v.D, v.dp, s);
+    launch_fill_i32(v.dstatus, 0, p.primal.B, s);
+  }
   Inputs din = dual_inputs(v);
   din.x0 = x;  // n_0 of the reversed problem is 0: any valid pointer
   eclqr_status st = run_engine(p.dual, v.D, din, v.dx, v.du, v.dstatus, td, s);
   if (st != ECLQR_SUCCESS) return st;
-  launch_dual_extract(v.P, v.D, v.dx, v.du, lam, mu, v.dp, s);
-  launch_merge_status(status, v.dstatus, ECLQR_DUAL_FAILED, p.primal.B, s);
+  {
+    Timed tm(ECLQR_K_MULTIPLIER_IO, s);
+    launch_dual_extract(v.P, v.D, v.dx, v.du, lam, mu, v.dp, s);
+    launch_merge_status(status, v.dstatus, ECLQR_DUAL_FAILED, p.primal.B, s);
+  }
   return ECLQR_SUCCESS;
 }
 
@@ -221,7 +270,10 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
   if (st != ECLQR_SUCCESS) return st;
   for (int it = 0; it < p.opt.refine; ++it) {
     // correction problem: same matrices, residuals as data
-    launch_correction(v.P, in, x, u, lam, mu, v.cp, s);
+    {
+      Timed tm(ECLQR_K_REFINE_IO, s);
+      launch_correction(v.P, in, x, u, lam, mu, v.cp, s);
+    }
     Inputs cin = in;
     cin.f[IN_q] = v.cp.q;
     cin.f[IN_r] = v.cp.r;
@@ -231,8 +283,11 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
     const Tols tc{p.opt.rank_tol, p.opt.cons_tol, 0};
     st = run_engine(p.primal, v.P, cin, v.cx, v.cu, status, tc, s);
     if (st != ECLQR_SUCCESS) return st;
-    launch_axpy(x, v.cx, p.primal.total[ECLQR_F_q], s);
-    launch_axpy(u, v.cu, p.primal.total[ECLQR_F_r], s);
+    {
+      Timed tm(ECLQR_K_REFINE_IO, s);
+      launch_axpy(x, v.cx, p.primal.total[ECLQR_F_q], s);
+      launch_axpy(u, v.cu, p.primal.total[ECLQR_F_r], s);
+    }
     st = multipliers(p, v, in, x, u, lam, mu, status, s);
     if (st != ECLQR_SUCCESS) return st;
   }
@@ -354,6 +409,7 @@ eclqr_status eclqr_solve(eclqr_plan* plan, const eclqr_problem* prob, eclqr_solu
   hipStream_t s = static_cast<hipStream_t>(stream);
   eclqr_status st = bind(p, ws, s);
   if (st != ECLQR_SUCCESS) return st;
+  g_prof = &p;
   Views v = views(p, ws);
   launch_fill_i32(sol->status, 0, E.B, s);
   Inputs in = inputs_of(prob);
@@ -374,6 +430,7 @@ eclqr_status eclqr_backward(eclqr_plan* plan, const eclqr_problem* prob, const e
   hipStream_t s = static_cast<hipStream_t>(stream);
   eclqr_status st = bind(p, ws, s);
   if (st != ECLQR_SUCCESS) return st;
+  g_prof = &p;
   Views v = views(p, ws);
   const Engine& E = p.primal;
   // adjoint problem: same matrices, q <- dL/dx, r <- dL/du, zero offsets
@@ -420,6 +477,85 @@ eclqr_status eclqr_backward(eclqr_plan* plan, const eclqr_problem* prob, const e
   g.x0 = grads->x0;
   launch_grad_assemble(v.P, sol->x, sol->u, sol->lam, sol->mu, ax, au, al, am, g, s);
   HIP_OK(hipGetLastError());
+  return ECLQR_SUCCESS;
+}
+
+eclqr_status eclqr_plan_set_profiling(eclqr_plan* plan, int32_t on) {
+  if (!plan) return fail(ECLQR_INVALID_ARGUMENT, "NULL plan");
+  plan->p.profiling = (on != 0);
+  return ECLQR_SUCCESS;
+}
+
+eclqr_status eclqr_plan_profile(eclqr_plan* plan, double* ms, int64_t* launches, int32_t reset) {
+  if (!plan) return fail(ECLQR_INVALID_ARGUMENT, "NULL plan");
+  Plan& p = plan->p;
+  std::vector<double> acc(ECLQR_NUM_KERNEL_CLASSES, 0.0);
+  std::vector<int64_t> cnt(ECLQR_NUM_KERNEL_CLASSES, 0);
+  for (auto& ev : p.events) {
+    hipEvent_t a = reinterpret_cast<hipEvent_t>(ev.second.first);
+    hipEvent_t b = reinterpret_cast<hipEvent_t>(ev.second.second);
+    HIP_OK(hipEventSynchronize(b));
+    float t = 0.f;
+    HIP_OK(hipEventElapsedTime(&t, a, b));
+    acc[ev.first] += t;
+    cnt[ev.first] += 1;
+  }
+  for (int k = 0; k < ECLQR_NUM_KERNEL_CLASSES; ++k) {
+    if (ms) ms[k] = acc[k];
+    if (launches) launches[k] = cnt[k];
+  }
+  if (reset) {
+    p.events.clear();
+    p.pool_next = 0;
+  }
+  return ECLQR_SUCCESS;
+}
+
+const char* eclqr_kernel_class_name(int32_t k) {
+  static const char* names[ECLQR_NUM_KERNEL_CLASSES] = {
+      "validate", "base_relation", "rel_compose", "domain", "eliminate", "ric_combine",
+      "gains", "fwd_combine", "recover", "multiplier_io", "refine_io", "other"};
+  return (k >= 0 && k < ECLQR_NUM_KERNEL_CLASSES) ? names[k] : "unknown";
+}
+
+eclqr_status eclqr_plan_reduced_dims(const eclqr_plan* plan, const void* ws, int32_t which, int32_t* nbar,
+                                     int32_t* mbar) {
+  if (!plan || !ws) return fail(ECLQR_INVALID_ARGUMENT, "NULL argument");
+  const Plan& p = plan->p;
+  const Engine& E = which ? p.dual : p.primal;
+  const size_t base = which ? p.o_dual : p.o_primal;
+  const char* b = static_cast<const char*>(ws) + base;
+  HIP_OK(hipDeviceSynchronize());
+  if (nbar) HIP_OK(hipMemcpy(nbar, b + E.o_nbar, sizeof(int32_t) * E.S, hipMemcpyDeviceToHost));
+  if (mbar) HIP_OK(hipMemcpy(mbar, b + E.o_mbar, sizeof(int32_t) * E.S, hipMemcpyDeviceToHost));
+  return ECLQR_SUCCESS;
+}
+
+eclqr_status eclqr_plan_scan_rows(const eclqr_plan* plan, const void* ws, int32_t which, int32_t* rows,
+                                  int32_t* nslots) {
+  if (!plan) return fail(ECLQR_INVALID_ARGUMENT, "NULL plan");
+  const Plan& p = plan->p;
+  const Engine& E = which ? p.dual : p.primal;
+  if (nslots) *nslots = E.nslots;
+  if (rows) {
+    if (!ws) return fail(ECLQR_INVALID_ARGUMENT, "NULL workspace");
+    const char* b = static_cast<const char*>(ws) + (which ? p.o_dual : p.o_primal);
+    HIP_OK(hipDeviceSynchronize());
+    HIP_OK(hipMemcpy(rows, b + E.o_slot_rows, sizeof(int32_t) * E.nslots, hipMemcpyDeviceToHost));
+  }
+  return ECLQR_SUCCESS;
+}
+
+eclqr_status eclqr_plan_slot_info(const eclqr_plan* plan, int32_t which, int32_t* inst, int32_t* first,
+                                  int32_t* last, int32_t* nslots) {
+  if (!plan) return fail(ECLQR_INVALID_ARGUMENT, "NULL plan");
+  const Engine& E = which ? plan->p.dual : plan->p.primal;
+  if (nslots) *nslots = E.nslots;
+  for (int32_t q = 0; q < E.nslots; ++q) {
+    if (inst) inst[q] = E.slot_inst[q];
+    if (first) first[q] = E.slot_s[q];
+    if (last) last[q] = E.slot_e[q];
+  }
   return ECLQR_SUCCESS;
 }
 

@@ -70,6 +70,11 @@ struct Plan {
   size_t bytes = 0;
   void* bound_ws = nullptr;
   int bound_device = -1;
+  // profiler: recorded (class, start, stop) event triples
+  bool profiling = false;
+  std::vector<std::pair<int, std::pair<void*, void*>>> events;
+  std::vector<void*> event_pool;
+  size_t pool_next = 0;
 };
 
 std::string build_plan(Plan& p, const eclqr_dims* d, const eclqr_options* opt);

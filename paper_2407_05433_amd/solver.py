@@ -91,6 +91,64 @@ class Plan:
                        if nt.value else np.zeros((0, 3), np.int32))
         return out
 
+    def set_profiling(self, on: bool) -> None:
+        check(lib().eclqr_plan_set_profiling(self._h, int(on)), "eclqr_plan_set_profiling")
+
+    def profile(self, reset: bool = True) -> Dict[str, tuple]:
+        """{kernel class: (total ms, launches)} of the launches recorded since the last reset."""
+        n = _lib.NUM_KERNEL_CLASSES
+        ms = (C.c_double * n)()
+        cnt = (C.c_int64 * n)()
+        check(lib().eclqr_plan_profile(self._h, ms, cnt, int(reset)), "eclqr_plan_profile")
+        return {lib().eclqr_kernel_class_name(k).decode(): (ms[k], cnt[k]) for k in range(n)}
+
+    def reduced_dims(self, ws: torch.Tensor, dual: bool = False):
+        """(n-bar, m-bar) per stage from the last solve in ``ws`` (synchronises)."""
+        S = len(self._nx) if not dual else int(sum(h + 2 for h in self.horizons))
+        nb = (C.c_int32 * S)()
+        mb = (C.c_int32 * S)()
+        wptr, _ = _aligned_ws(ws)
+        check(lib().eclqr_plan_reduced_dims(self._h, C.c_void_p(wptr), int(dual), nb, mb), "eclqr_plan_reduced_dims")
+        return np.frombuffer(nb, dtype=np.int32).copy(), np.frombuffer(mb, dtype=np.int32).copy()
+
+    def scan_rows(self, ws: Optional[torch.Tensor], dual: bool = False) -> np.ndarray:
+        """Rows of every feasible-domain-scan slot after the last solve (synchronises)."""
+        n = C.c_int32()
+        check(lib().eclqr_plan_scan_rows(self._h, None, int(dual), None, C.byref(n)), "eclqr_plan_scan_rows")
+        rows = (C.c_int32 * max(1, n.value))()
+        wptr, _ = _aligned_ws(ws)
+        check(lib().eclqr_plan_scan_rows(self._h, C.c_void_p(wptr), int(dual), rows, C.byref(n)),
+              "eclqr_plan_scan_rows")
+        return np.frombuffer(rows, dtype=np.int32)[:n.value].copy()
+
+    def slot_info(self, dual: bool = False):
+        """(instance, first leaf, end leaf) of every scan slot."""
+        n = C.c_int32()
+        check(lib().eclqr_plan_slot_info(self._h, int(dual), None, None, None, C.byref(n)), "eclqr_plan_slot_info")
+        a, b, c = ((C.c_int32 * max(1, n.value))() for _ in range(3))
+        check(lib().eclqr_plan_slot_info(self._h, int(dual), a, b, c, C.byref(n)), "eclqr_plan_slot_info")
+        return tuple(np.frombuffer(x, dtype=np.int32)[:n.value].copy() for x in (a, b, c))
+
+    def stage_dims(self, dual: bool = False):
+        """(n, n', m, k) per stage of the problem or of the reversed-time problem."""
+        nx, nu, nc = self._nx, self._nu, self._nc
+        out = []
+        s = u = 0
+        for N in self.horizons:
+            xs, us, cs = nx[s:s + N + 1], nu[u:u + N], nc[s:s + N + 1]
+            if dual:
+                dxs = [0] + [int(xs[N - j + 1]) for j in range(1, N + 2)]
+                dus = [int(cs[N])] + [int(cs[N - j]) for j in range(1, N + 1)]
+                dcs = [0] + [int(us[N - j]) for j in range(1, N + 1)] + [0]
+                xs, us, cs, NN = dxs, dus, dcs, N + 1
+            else:
+                NN = N
+            for i in range(NN + 1):
+                out.append((int(xs[i]), int(xs[i + 1]) if i < NN else 0, int(us[i]) if i < NN else 0, int(cs[i])))
+            s += N + 1
+            u += N
+        return out
+
     def workspace(self, device="cuda") -> torch.Tensor:
         return torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=device)
 

@@ -1,0 +1,171 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Tolerance: relative 2-norm error <= 1e-9 per instance and field over x, u,
+lambda (lambda_0 = -alpha) and mu, against the oracle's primal solution and
+minimum-norm multipliers.  Small cases are compared element by element; the
+full-size workloads are compared in full where the oracle finishes in tens of
+seconds (the N=1024 and N=8192 single instances), on a sample of instances
+otherwise, and through the KKT residual of Section IX on every instance.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-9
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def gpu_solve(probs, **opts):
+    import paper_2407_05433_amd as ecl
+    plan = ecl.Plan.for_problems(probs, **opts)
+    data = ecl.pack(plan, probs)
+    ws = plan.workspace()
+    sol = ecl.solve(plan, data, ws)
+    torch.cuda.synchronize()
+    out = {
+        "status": sol.status.cpu().tolist(),
+        "x": ecl.unpack(plan, sol.x, "q", probs),
+        "u": ecl.unpack(plan, sol.u, "r", probs),
+    }
+    if sol.lam is not None:
+        out["lam"] = ecl.unpack(plan, sol.lam, "q", probs)
+        out["mu"] = ecl.unpack(plan, sol.mu, "g", probs)
+    out["_plan"], out["_data"], out["_sol"], out["_ws"] = plan, data, sol, ws
+    return out
+
+
+def check_parity(probs, res, idx=None, tol=TOL):
+    from oracle import solve_with_multipliers
+    from tests._util import rel_err
+    idx = range(len(probs)) if idx is None else idx
+    for b in idx:
+        p = probs[b]
+        o = solve_with_multipliers(p)
+        assert o["status"] == "ok"
+        assert res["status"][b] == 0, (b, res["status"][b])
+        for key in ("x", "u", "lam", "mu"):
+            if key == "mu" and sum(p.nc) == 0:
+                continue
+            e = rel_err(res[key][b], o[key])
+            assert e <= tol, (b, key, e)
+
+
+def test_c0_tiny():
+    _need_gpu()
+    from workloads import config_c0
+    probs = config_c0()
+    check_parity(probs, gpu_solve(probs))
+
+
+def test_structural_family_single_and_batched():
+    _need_gpu()
+    from tests._util import problem_family
+    fam = [p for _, p in problem_family()]
+    for p in fam:
+        check_parity([p], gpu_solve([p]))
+    check_parity(fam, gpu_solve(fam))
+
+
+def test_c1_full_size():
+    _need_gpu()
+    from workloads import config_c1
+    probs = config_c1()
+    check_parity(probs, gpu_solve(probs))
+
+
+def test_c2_law_short_horizon():
+    _need_gpu()
+    from workloads import config_c2
+    probs = config_c2(N=512)
+    check_parity(probs, gpu_solve(probs))
+
+
+def test_c3_batched_sample_and_residuals():
+    _need_gpu()
+    import paper_2407_05433_amd as ecl
+    from workloads import config_c3
+    probs = config_c3(B=64)
+    res = gpu_solve(probs)
+    check_parity(probs, res, idx=range(0, 64, 4))
+    r = ecl.kkt_residual(res["_plan"], res["_data"], res["_sol"], res["_ws"]).cpu().numpy()
+    torch.cuda.synchronize()
+    assert np.all(np.array(res["status"]) == 0)
+    assert r.max() < 1e-8, r.max(axis=0)
+
+
+def test_batched_equals_single():
+    _need_gpu()
+    from workloads import config_c3
+    probs = config_c3(B=6, N_range=(32, 80))
+    batch = gpu_solve(probs)
+    for b, p in enumerate(probs):
+        single = gpu_solve([p])
+        for key in ("x", "u", "lam", "mu"):
+            a = np.concatenate([v.ravel() for v in batch[key][b]])
+            s = np.concatenate([v.ravel() for v in single[key][0]])
+            assert np.array_equal(a, s), (b, key)
+
+
+def test_c4_forward_sample():
+    _need_gpu()
+    from workloads import config_c4
+    probs = config_c4(B=32)
+    res = gpu_solve(probs)
+    check_parity(probs, res, idx=range(0, 32, 4))
+
+
+def test_varying_dims_and_edges():
+    _need_gpu()
+    from tests._util import tiny_problem
+    probs = [
+        tiny_problem(1100, nx=[1, 3, 5, 2, 4, 1], nu=[1, 2, 1, 3, 1], terminal_rows=1),
+        tiny_problem(1101, nx=[6, 2, 6, 2, 6], nu=[1, 5, 1, 5], terminal_rows=0),
+        tiny_problem(1102, N=1, n=1, m=1, kinds=[[]], terminal_rows=0),
+        tiny_problem(1103, N=2, n=5, m=5, kinds=[["mixed"] * 4, ["state"] * 3], terminal_rows=2),
+    ]
+    check_parity(probs, gpu_solve(probs))
+
+
+def test_infeasibility_outcomes():
+    _need_gpu()
+    from tests._util import tiny_problem
+    bad_suffix = tiny_problem(400, N=4, n=3, m=1, kinds=[[], [], [], ["state", "state", "state"]], terminal_rows=3)
+    bad_suffix.g[bad_suffix.N] = bad_suffix.g[bad_suffix.N] + 1.0
+    bad_init = tiny_problem(401, N=4, n=3, m=2, kinds=[["state"], [], [], []], terminal_rows=0)
+    bad_init.g[0] = bad_init.g[0] + 1.0
+    nonconvex = tiny_problem(402, N=3, n=2, m=2, kinds=[[]] * 3, terminal_rows=0)
+    nonconvex.R[1] = -nonconvex.R[1]
+    nan_in = tiny_problem(403, N=3, n=2, m=2, kinds=[[]] * 3, terminal_rows=0)
+    nan_in.q[1] = nan_in.q[1].copy()
+    nan_in.q[1][0] = np.nan
+    good = tiny_problem(404, N=3, n=2, m=2, kinds=[[]] * 3, terminal_rows=0)
+    res = gpu_solve([bad_suffix, bad_init, nonconvex, nan_in, good])
+    st = res["status"]
+    assert st[0] & 1, st
+    assert st[1] & 2, st
+    assert st[2] & 8, st
+    assert st[3] & 16, st
+    assert st[4] == 0, st
+    assert np.all(np.isnan(np.concatenate(res["x"][0]))) and np.all(np.isfinite(np.concatenate(res["x"][4])))
+    check_parity([good], {k: [v[4]] for k, v in res.items() if not k.startswith("_") and k != "status"} |
+                 {"status": [0]})
+
+
+def test_deterministic_bitwise():
+    _need_gpu()
+    from workloads import config_c1
+    probs = config_c1(N=256)
+    a = gpu_solve(probs)
+    b = gpu_solve(probs)
+    for key in ("x", "u", "lam", "mu"):
+        assert np.array_equal(np.concatenate(a[key][0]), np.concatenate(b[key][0]))
