@@ -135,6 +135,21 @@ def fd_directional(prob, d, h: float = 1e-6,
     return (loss(sp.x, sp.u) - loss(sm.x, sm.u)) / (2.0 * h)
 
 
+def effective_direction(prob, d, h: float):
+    """The direction the rounded perturbations actually apply:
+    (fl(theta + h d) - fl(theta - h d)) / 2h (the subtraction is exact), so
+    that the difference quotient is compared with the derivative along the
+    perturbation that was really made."""
+    pp, pm = perturbed(prob, d, h), perturbed(prob, d, -h)
+    out = {}
+    for f, v in d.items():
+        if f == "x0":
+            out[f] = (pp.x0 - pm.x0) / (2.0 * h)
+        else:
+            out[f] = [(a - b) / (2.0 * h) for a, b in zip(getattr(pp, f), getattr(pm, f))]
+    return out
+
+
 def fd_directional_corrected(prob, sol, d, h: float = 1e-6) -> float:
     """Central difference (L(theta + h d) - L(theta - h d)) / 2h of the sum-of-
     squares loss, with each perturbed solution written w + delta and delta

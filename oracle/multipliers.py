@@ -106,21 +106,33 @@ def correction_problem(prob_h, sol):
     J' delta + c'(w) = 0, where s = grad f'(w) + J'^T nu is the stationarity
     residual of the old point in the new problem (adding J'^T nu to the linear
     term changes the objective by a constant on the feasible set).  Every
-    linear term and offset of this problem is O(|theta' - theta|), so its
-    solution carries a small relative rounding error."""
+    linear term and offset of this problem is small, so its solution carries a
+    small relative rounding error.  The residuals are accumulated in extended
+    precision (numpy longdouble) and rounded once."""
     p = prob_h.copy()
     N = p.N
-    x, u, lam, mu = sol["x"], sol["u"], sol["lam"], sol["mu"]
+    L = np.longdouble
+
+    def ld(a):
+        return np.asarray(a, dtype=L)
+
+    x = [ld(v) for v in sol["x"]]
+    u = [ld(v) for v in sol["u"]]
+    lam = [ld(v) for v in sol["lam"]]
+    mu = [ld(v) for v in sol["mu"]]
     qd, rd, cd, gd = [], [], [], []
     for i in range(N):
-        qd.append(p.Q[i] @ x[i] + p.M[i] @ u[i] + p.q[i] - lam[i] + p.A[i].T @ lam[i + 1] + p.E[i].T @ mu[i])
-        rd.append(p.M[i].T @ x[i] + p.R[i] @ u[i] + p.r[i] + p.B[i].T @ lam[i + 1] + p.F[i].T @ mu[i])
-        cd.append(p.A[i] @ x[i] + p.B[i] @ u[i] + p.c[i] - x[i + 1])
-        gd.append(p.E[i] @ x[i] + p.F[i] @ u[i] + p.g[i])
-    qd.append(p.Q[N] @ x[N] + p.q[N] - lam[N] + p.E[N].T @ mu[N])
-    gd.append(p.E[N] @ x[N] + p.g[N])
-    p.q, p.r, p.c, p.g = qd, rd, cd, gd
-    p.x0 = p.x0 - x[0]
+        Q, M, R, A, B, E, F = (ld(getattr(p, f)[i]) for f in ("Q", "M", "R", "A", "B", "E", "F"))
+        qd.append(Q @ x[i] + M @ u[i] + ld(p.q[i]) - lam[i] + A.T @ lam[i + 1] + E.T @ mu[i])
+        rd.append(M.T @ x[i] + R @ u[i] + ld(p.r[i]) + B.T @ lam[i + 1] + F.T @ mu[i])
+        cd.append(A @ x[i] + B @ u[i] + ld(p.c[i]) - x[i + 1])
+        gd.append(E @ x[i] + F @ u[i] + ld(p.g[i]))
+    QN, EN = ld(p.Q[N]), ld(p.E[N])
+    qd.append(QN @ x[N] + ld(p.q[N]) - lam[N] + EN.T @ mu[N])
+    gd.append(EN @ x[N] + ld(p.g[N]))
+    f64 = lambda lst: [np.asarray(v, dtype=np.float64) for v in lst]  # noqa: E731
+    p.q, p.r, p.c, p.g = f64(qd), f64(rd), f64(cd), f64(gd)
+    p.x0 = np.asarray(ld(p.x0) - x[0], dtype=np.float64)
     return p
 
 

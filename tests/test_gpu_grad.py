@@ -62,7 +62,7 @@ def _rel(a, b):
 def test_gradients_match_oracle_adjoint_and_fd():
     _need_gpu()
     from oracle import solve_with_multipliers
-    from oracle.gradients import (adjoint_gradients, directional, fd_directional_corrected, random_direction,
+    from oracle.gradients import (adjoint_gradients, directional, effective_direction, fd_directional_corrected, random_direction,
                                   sumsq_loss_grad)
     from workloads import config_c4
     probs = config_c4(B=3)
@@ -77,7 +77,7 @@ def test_gradients_match_oracle_adjoint_and_fd():
         fields = ("Q", "q", "R", "r", "A", "B", "c", "E", "F", "g", "x0")
         for _ in range(4):
             d = random_direction(p, rng, fields)
-            an = directional(G[b], d)
+            an = directional(G[b], effective_direction(p, d, 1e-6))
             fd = fd_directional_corrected(p, sol, d, 1e-6)
             assert abs(fd - an) / max(abs(fd), abs(an)) < 1e-6, (b, fd, an)
 
@@ -85,7 +85,7 @@ def test_gradients_match_oracle_adjoint_and_fd():
 def test_gradients_full_c4_batch_sampled():
     _need_gpu()
     from oracle import solve_with_multipliers
-    from oracle.gradients import directional, fd_directional_corrected, random_direction
+    from oracle.gradients import directional, effective_direction, fd_directional_corrected, random_direction
     from workloads import config_c4
     probs = config_c4()
     G = _gpu_grads(probs)
@@ -96,6 +96,6 @@ def test_gradients_full_c4_batch_sampled():
         for _ in range(3):
             d = random_direction(p, rng)
             d.pop("M", None)
-            an = directional(G[b], d)
+            an = directional(G[b], effective_direction(p, d, 1e-6))
             fd = fd_directional_corrected(p, sol, d, 1e-6)
             assert abs(fd - an) / max(abs(fd), abs(an)) < 1e-6, (b, fd, an)
