@@ -71,7 +71,8 @@ typedef enum {
 #define ECLQR_NOT_CONVEX 8          /* a reduced input Hessian is not positive definite */
 #define ECLQR_INVALID_INPUT 16      /* NaN or Inf in the data */
 #define ECLQR_CAPACITY 32           /* a relation outgrew its on-chip tile */
-#define ECLQR_DUAL_FAILED 64        /* the multiplier (stationarity) solve failed */
+#define ECLQR_DUAL_FAILED 64        /* the multiplier (stationarity) solve failed; its own
+                                       outcome bits are repeated in bits 8..15 */
 
 /* fields of the problem layout */
 enum {

@@ -118,4 +118,6 @@ def check(code: int, what: str) -> None:
 def status_names(code: int):
     if code == 0:
         return ["ok"]
-    return [name for bit, name in STATUS_BITS.items() if code & bit]
+    out = [name for bit, name in STATUS_BITS.items() if code & bit]
+    out += ["dual:" + name for bit, name in STATUS_BITS.items() if (code >> 8) & bit]
+    return out

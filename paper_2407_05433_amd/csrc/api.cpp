@@ -93,6 +93,7 @@ eclqr_status upload_engine(const Engine& E, void* ws, size_t base, hipStream_t s
 }
 
 int g_max_lds = 65536;
+constexpr double kPreRefineConsTol = 1e-3;
 
 // ---- profiler ------------------------------------------------------------------
 Plan* g_prof = nullptr;  // plan whose launches are being timed (set per call)
@@ -240,8 +241,8 @@ Inputs dual_inputs(const Views& v) {
 // Multipliers at (x, u): build the reversed-time problem's offsets, solve it,
 // read lambda and mu off its solution.
 eclqr_status multipliers(Plan& p, const Views& v, const Inputs& in, const double* x, const double* u, double* lam,
-                         double* mu, int32_t* status, hipStream_t s) {
-  const Tols td{p.opt.rank_tol, p.opt.dual_cons_tol, 0};
+                         double* mu, int32_t* status, hipStream_t s, double cons_tol, bool report) {
+  const Tols td{p.opt.rank_tol, cons_tol, 0};
   {
     Timed tm(ECLQR_K_MULTIPLIER_IO, s);
     launch_dual_vectors(v.P, in, x, u, v.D, v.dp, s);
@@ -254,7 +255,7 @@ eclqr_status multipliers(Plan& p, const Views& v, const Inputs& in, const double
   {
     Timed tm(ECLQR_K_MULTIPLIER_IO, s);
     launch_dual_extract(v.P, v.D, v.dx, v.du, lam, mu, v.dp, s);
-    launch_merge_status(status, v.dstatus, ECLQR_DUAL_FAILED, p.primal.B, s);
+    if (report) launch_merge_status(status, v.dstatus, ECLQR_DUAL_FAILED, p.primal.B, s);
   }
   return ECLQR_SUCCESS;
 }
@@ -266,9 +267,14 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
   eclqr_status st = run_engine(p.primal, v.P, in, x, u, status, tp, s);
   if (st != ECLQR_SUCCESS) return st;
   if (!want_mult) return ECLQR_SUCCESS;
-  st = multipliers(p, v, in, x, u, lam, mu, status, s);
+  // Before refinement the stationarity system inherits the primal point's
+  // optimality error; that pass only feeds the correction problem, so its
+  // consistency test is loose and its outcome is not reported.
+  const int nref = p.opt.refine;
+  st = multipliers(p, v, in, x, u, lam, mu, status, s, nref > 0 ? kPreRefineConsTol : p.opt.dual_cons_tol,
+                   nref == 0);
   if (st != ECLQR_SUCCESS) return st;
-  for (int it = 0; it < p.opt.refine; ++it) {
+  for (int it = 0; it < nref; ++it) {
     // correction problem: same matrices, residuals as data
     {
       Timed tm(ECLQR_K_REFINE_IO, s);
@@ -288,7 +294,8 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
       launch_axpy(x, v.cx, p.primal.total[ECLQR_F_q], s);
       launch_axpy(u, v.cu, p.primal.total[ECLQR_F_r], s);
     }
-    st = multipliers(p, v, in, x, u, lam, mu, status, s);
+    const bool last = (it + 1 == nref);
+    st = multipliers(p, v, in, x, u, lam, mu, status, s, last ? p.opt.dual_cons_tol : kPreRefineConsTol, last);
     if (st != ECLQR_SUCCESS) return st;
   }
   return ECLQR_SUCCESS;

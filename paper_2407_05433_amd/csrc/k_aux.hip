@@ -210,9 +210,10 @@ __global__ void k_fill_i32(int32_t* y, int32_t v, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     y[i] = v;
 }
+// A failed reversed-time solve sets `bit` and keeps its own outcome bits in bits 8..15.
 __global__ void k_merge_status(int32_t* status, const int32_t* other, int32_t bit, int32_t B) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < B; i += gridDim.x * blockDim.x)
-    if (other[i] != 0) status[i] |= bit;
+    if (other[i] != 0) status[i] |= bit | ((other[i] & 0xff) << 8);
 }
 
 // Outputs of an instance whose status is not OK become NaN.

@@ -8,7 +8,8 @@ import pytest
 
 from oracle import solve_with_multipliers
 from oracle.dense import dense_kkt, split_dual, split_primal
-from oracle.gradients import (adjoint_gradients, directional, fd_directional, fd_directional_corrected,
+from oracle.gradients import (adjoint_gradients, directional, effective_direction, fd_directional,
+                              fd_directional_corrected,
                               random_direction, sumsq_loss_grad)
 from tests._util import rel_err, tiny_problem
 
