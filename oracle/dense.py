@@ -134,3 +134,48 @@ def minnorm_multipliers_dense(prob, x, u) -> Dict[str, list]:
     grad = H @ w + h
     nu = -np.linalg.pinv(J.T, rcond=1e-12) @ grad
     return split_dual(prob, nu, layout)
+
+
+def sparse_jacobian(prob):
+    """J and H, h, b of dense_kkt as scipy.sparse matrices (any size)."""
+    import scipy.sparse as sp
+    N = prob.N
+    nx, nu, nc = prob.nx, prob.nu, prob.nc
+    xo, uo, nw, ao, lo, mo, nnu = _offsets(prob)
+    rows, cols, vals = [], [], []
+
+    def put(r0, c0, M):
+        M = np.asarray(M)
+        if M.size == 0:
+            return
+        rr, cc = np.nonzero(M)
+        rows.append(rr + r0); cols.append(cc + c0); vals.append(M[rr, cc])
+
+    put(ao, xo[0], np.eye(nx[0]))
+    for i in range(N):
+        put(lo[i + 1], xo[i], prob.A[i]); put(lo[i + 1], uo[i], prob.B[i])
+        put(lo[i + 1], xo[i + 1], -np.eye(nx[i + 1]))
+        put(mo[i], xo[i], prob.E[i]); put(mo[i], uo[i], prob.F[i])
+    put(mo[N], xo[N], prob.E[N])
+    r = np.concatenate(rows) if rows else np.zeros(0, int)
+    c = np.concatenate(cols) if cols else np.zeros(0, int)
+    v = np.concatenate(vals) if vals else np.zeros(0)
+    J = sp.csr_matrix((v, (r, c)), shape=(nnu, nw))
+    return J, (xo, uo, ao, lo, mo)
+
+
+def minnorm_multipliers_lsqr(prob, x, u, tol: float = 1e-15, maxiter: int = 200000):
+    """Minimum-norm least-squares solution of J^T nu = -grad f(w) at the given
+    primal point, by LSQR on the sparse J^T (started at zero, LSQR returns the
+    minimum-norm solution)."""
+    from scipy.sparse.linalg import lsqr
+    N = prob.N
+    J, layout = sparse_jacobian(prob)
+    grad = []
+    for i in range(N):
+        grad.append(prob.Q[i] @ x[i] + prob.M[i] @ u[i] + prob.q[i])
+        grad.append(prob.M[i].T @ x[i] + prob.R[i] @ u[i] + prob.r[i])
+    grad.append(prob.Q[N] @ x[N] + prob.q[N])
+    g = np.concatenate(grad)
+    res = lsqr(J.T.tocsr(), -g, atol=tol, btol=tol, conlim=1e14, iter_lim=maxiter)
+    return split_dual(prob, res[0], layout), res

@@ -49,6 +49,10 @@ from .sequential import solve_sequential
 # floating point its offsets inherit the primal solution's optimality error, so
 # the 0 = gamma test of the dual solve uses a looser relative threshold.
 DUAL_CONS_TOL = 1e-6
+# Before refinement the primal point's optimality error can exceed that test on
+# degenerate instances; the multipliers of that pass only build the correction
+# problem, so the pass uses a loose threshold.
+PRE_REFINE_CONS_TOL = 1e-3
 
 
 def objective_gradients(prob, x, u):
@@ -137,17 +141,33 @@ def correction_problem(prob_h, sol):
 
 
 def solve_with_multipliers(prob, rank_tol: float = RANK_TOL, cons_tol: float = CONS_TOL,
-                           refine: int = 1) -> Dict:
+                           refine: int = 1, lsqr_fallback: bool = True) -> Dict:
     """Primal solution of Algorithm 1 plus canonical multipliers, with ``refine``
-    steps of iterative refinement of the primal point."""
+    steps of iterative refinement of the primal point.  Where the reversed-time
+    reduction loses accuracy (it propagates the dual state through long chains
+    of constraints and flags the loss as an inconsistency), the multipliers
+    fall back to the plain definition: the minimum-norm least-squares solution
+    of J^T nu = -grad f by LSQR."""
+    from .dense import minnorm_multipliers_lsqr
     s = solve_sequential(prob, rank_tol, cons_tol)
     out = {"status": s.status, "stage": s.stage, "x": s.x, "u": s.u, "seq": s}
     if s.status != "ok":
         out["lam"] = out["mu"] = None
         return out
+    routes = []
+
+    def mult(x, u, tol):
+        m = minnorm_multipliers(prob, x, u, rank_tol, tol)
+        if m["status"] != "ok" and lsqr_fallback:
+            d, _ = minnorm_multipliers_lsqr(prob, x, u)
+            routes.append("lsqr")
+            return {"status": "ok", "lam": d["lam"], "mu": d["mu"]}
+        routes.append("reversed-time reduction")
+        return m
+
     x, u = s.x, s.u
-    m = minnorm_multipliers(prob, x, u, rank_tol, DUAL_CONS_TOL)
-    for _ in range(refine):
+    m = mult(x, u, PRE_REFINE_CONS_TOL if refine > 0 else DUAL_CONS_TOL)
+    for it in range(refine):
         if m["status"] != "ok":
             break
         cp = correction_problem(prob, {"x": x, "u": u, "lam": m["lam"], "mu": m["mu"]})
@@ -156,9 +176,10 @@ def solve_with_multipliers(prob, rank_tol: float = RANK_TOL, cons_tol: float = C
             break
         x = [a + b for a, b in zip(x, d.x)]
         u = [a + b for a, b in zip(u, d.u)]
-        m = minnorm_multipliers(prob, x, u, rank_tol, DUAL_CONS_TOL)
+        m = mult(x, u, DUAL_CONS_TOL if it + 1 == refine else PRE_REFINE_CONS_TOL)
     out["x"], out["u"] = x, u
     out["lam"], out["mu"] = m["lam"], m["mu"]
+    out["multiplier_route"] = routes[-1] if routes else None
     if m["status"] != "ok":
         out["status"] = m["status"]
     return out

@@ -326,3 +326,29 @@ def test_objective_matches_definition():
     H, h, J, b, _ = dense_kkt(p)
     w = np.concatenate([np.concatenate([s.x[i], s.u[i]]) for i in range(p.N)] + [s.x[p.N]])
     assert abs(w_obj - (0.5 * w @ H @ w + h @ w)) < 1e-10
+
+
+@pytest.mark.parametrize("name", ["redundant-1", "pinned-state", "with-M", "state-heavy"])
+def test_lsqr_multipliers_match_pinv(name):
+    """The LSQR fallback returns the minimum-norm least-squares multipliers."""
+    from oracle.dense import minnorm_multipliers_lsqr
+    p = dict(FAMILY)[name]
+    s = solve_with_multipliers(p)
+    ref = minnorm_multipliers_dense(p, s["x"], s["u"])
+    d, _ = minnorm_multipliers_lsqr(p, s["x"], s["u"])
+    assert rel_err(d["lam"], ref["lam"]) < 1e-10
+    if sum(p.nc):
+        assert rel_err(d["mu"], ref["mu"]) < 1e-10
+
+
+def test_degenerate_batched_instance_uses_lsqr_route():
+    """A heavily state-constrained instance of the batched workload whose
+    reversed-time reduction loses accuracy: the oracle's multipliers still
+    match the null-space method."""
+    from workloads import config_c3
+    p = config_c3(B=9)[8]
+    s = solve_with_multipliers(p)
+    assert s["status"] == "ok"
+    ns = solve_nullspace(p)
+    assert rel_err(s["lam"], ns["lam"]) < 1e-10 and rel_err(s["mu"], ns["mu"]) < 1e-10
+    assert rel_err(s["x"], ns["x"]) < 1e-10
