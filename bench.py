@@ -3,8 +3,9 @@
     python bench.py [--steps K] [--warmup W] [--workload c1|c2|c3|c4|paper]
 
 A step is one solve of the whole hot path (feasible-domain scan, stage
-elimination, reduced-LQR scan, recovery, multipliers with one refinement step)
-of one batch of synthetic instances already resident in HBM.  Prints one JSON
+elimination, reduced-LQR scan, recovery, multipliers, and iterative
+refinement that each instance stops once its correction is below 1e-8 of its
+solution, at most 3 steps) of one batch of synthetic instances already resident in HBM.  Prints one JSON
 line; the per-kernel breakdown and the secondary workloads go to stderr and to
 the "secondary" object.
 """
@@ -132,7 +133,8 @@ def main():
         if n:
             log(f"[bench]   {k:14s} {ms:8.3f} ms/solve  {n:6.1f} launches/solve")
     # roofline of the dominant kernel class (algorithmic FP64 flops / its time)
-    work = flopmodel.solve_flops(plan, problems, ws)
+    rsteps = plan.refine_steps(ws)
+    work = flopmodel.solve_flops(plan, problems, ws, steps=rsteps)
     dom = max((k for k in prof if prof[k][1] > 0 and k in work), key=lambda k: prof[k][0])
     dom_ms = prof[dom][0]
     dom_launches = prof[dom][1]
@@ -159,7 +161,9 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "instances": len(problems),
-                   "stages": stages, "multipliers": True, "refine": 1},
+                   "stages": stages, "multipliers": True,
+                   "refine": {"max_steps": int(plan.options.refine), "tol": float(plan.options.refine_tol),
+                              "steps_taken": {str(int(k)): int(v) for k, v in zip(*np.unique(rsteps, return_counts=True))}}},
         "roofline": roof,
         "kernel_ms_per_solve": {k: v[0] for k, v in prof.items() if v[1]},
     }

@@ -100,8 +100,10 @@ typedef struct {
   double rank_tol;        /* pivot counts toward rank if > rank_tol*max(1,|largest pivot|); 1e-10 */
   double cons_tol;        /* 0 = gamma accepted if |gamma| <= cons_tol*max(1,|offsets|); 1e-8 */
   double dual_cons_tol;   /* same test inside the multiplier solve; 1e-6 */
+  double refine_tol;      /* an instance stops refining once ||correction|| <= refine_tol*||(x,u)||; 1e-8 */
   int32_t multipliers;    /* 1: compute lam and mu; 0: primal only */
-  int32_t refine;         /* steps of iterative refinement of the primal point (0 or 1); 1 */
+  int32_t refine;         /* most steps of iterative refinement per instance (0..4); 3.  With
+                           * multipliers, every instance takes at least one step when refine > 0 */
   int32_t use_graph;      /* 1: replay the launch sequence as a captured hipGraph; 0 */
   int32_t reserved[5];
 } eclqr_options;
@@ -193,6 +195,10 @@ const char* eclqr_kernel_class_name(int32_t k);
  * stationarity problem of the multipliers.  Synchronises the device. */
 eclqr_status eclqr_plan_reduced_dims(const eclqr_plan* plan, const void* ws, int32_t which, int32_t* nbar,
                                      int32_t* mbar);
+
+/* Refinement steps each instance took in the last solve in ws (host array of
+ * batch entries).  Synchronises the device. */
+eclqr_status eclqr_plan_refine_steps(const eclqr_plan* plan, const void* ws, int32_t* steps);
 
 /* Row counts of every slot of the feasible-domain scan after the last solve
  * in ws (rows of the affine relation each slot holds); *nslots receives the

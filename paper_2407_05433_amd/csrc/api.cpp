@@ -93,7 +93,6 @@ eclqr_status upload_engine(const Engine& E, void* ws, size_t base, hipStream_t s
 }
 
 int g_max_lds = 65536;
-constexpr double kPreRefineConsTol = 1e-3;
 
 // ---- profiler ------------------------------------------------------------------
 Plan* g_prof = nullptr;  // plan whose launches are being timed (set per call)
@@ -205,6 +204,11 @@ struct Views {
   double *dx, *du;
   int32_t* dstatus;
   double *cx, *cu, *clam, *cmu;
+  int32_t* gate;
+  int32_t* rsteps;
+  double* rnorm;
+  const int64_t* psbase;
+  const double* zero;
 };
 
 Views views(Plan& p, void* ws) {
@@ -227,6 +231,13 @@ Views views(Plan& p, void* ws) {
   v.cu = at<double>(ws, p.o_cu);
   v.clam = at<double>(ws, p.o_clam);
   v.cmu = at<double>(ws, p.o_cmu);
+  v.gate = at<int32_t>(ws, p.o_gate);
+  v.rsteps = at<int32_t>(ws, p.o_rsteps);
+  v.rnorm = at<double>(ws, p.o_rnorm);
+  v.psbase = dev_sbase(p.primal, ws, p.o_primal);
+  v.zero = at<double>(ws, p.o_zero);
+  v.P.gate = v.gate;
+  v.D.gate = v.gate;
   return v;
 }
 
@@ -239,10 +250,13 @@ Inputs dual_inputs(const Views& v) {
 }
 
 // Multipliers at (x, u): build the reversed-time problem's offsets, solve it,
-// read lambda and mu off its solution.
+// read lambda and mu off its solution.  The consistency tolerance only sets
+// outcome bits (the computed values do not depend on it); the outcome is merged
+// into `status` for the instances whose gate equals `report_gate` (every
+// instance when report_gate < 0, none when it is kGateDone).
 eclqr_status multipliers(Plan& p, const Views& v, const Inputs& in, const double* x, const double* u, double* lam,
-                         double* mu, int32_t* status, hipStream_t s, double cons_tol, bool report) {
-  const Tols td{p.opt.rank_tol, cons_tol, 0};
+                         double* mu, int32_t* status, hipStream_t s, int32_t report_gate) {
+  const Tols td{p.opt.rank_tol, p.opt.dual_cons_tol, 0};
   {
     Timed tm(ECLQR_K_MULTIPLIER_IO, s);
     launch_dual_vectors(v.P, in, x, u, v.D, v.dp, s);
@@ -255,7 +269,9 @@ eclqr_status multipliers(Plan& p, const Views& v, const Inputs& in, const double
   {
     Timed tm(ECLQR_K_MULTIPLIER_IO, s);
     launch_dual_extract(v.P, v.D, v.dx, v.du, lam, mu, v.dp, s);
-    if (report) launch_merge_status(status, v.dstatus, ECLQR_DUAL_FAILED, p.primal.B, s);
+    if (report_gate != kGateDone)
+      launch_merge_status(status, v.dstatus, ECLQR_DUAL_FAILED, p.primal.B, report_gate < 0 ? nullptr : v.gate,
+                          report_gate, s);
   }
   return ECLQR_SUCCESS;
 }
@@ -264,18 +280,29 @@ eclqr_status multipliers(Plan& p, const Views& v, const Inputs& in, const double
 eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, double* u, double* lam, double* mu,
                        int32_t* status, bool want_mult, hipStream_t s) {
   const Tols tp{p.opt.rank_tol, p.opt.cons_tol, 1};
+  {
+    Timed tm(ECLQR_K_REFINE_IO, s);
+    launch_fill_i32(v.gate, kGateActive, p.primal.B, s);
+    launch_fill_i32(v.rsteps, 0, p.primal.B, s);
+  }
   eclqr_status st = run_engine(p.primal, v.P, in, x, u, status, tp, s);
   if (st != ECLQR_SUCCESS) return st;
   if (!want_mult) return ECLQR_SUCCESS;
   // Before refinement the stationarity system inherits the primal point's
-  // optimality error; that pass only feeds the correction problem, so its
-  // consistency test is loose and its outcome is not reported.
+  // optimality error; that pass only feeds the correction problem and its
+  // outcome is not reported.
   const int nref = p.opt.refine;
-  st = multipliers(p, v, in, x, u, lam, mu, status, s, nref > 0 ? kPreRefineConsTol : p.opt.dual_cons_tol,
-                   nref == 0);
+  st = multipliers(p, v, in, x, u, lam, mu, status, s, nref > 0 ? kGateDone : -1);
   if (st != ECLQR_SUCCESS) return st;
+  // Each step: correction problem (same matrices, residuals as data), update,
+  // per-instance convergence test, multipliers at the updated point.  An
+  // instance whose correction is small is final after this step and skipped
+  // by every later step.
   for (int it = 0; it < nref; ++it) {
-    // correction problem: same matrices, residuals as data
+    if (it > 0) {
+      Timed tm(ECLQR_K_REFINE_IO, s);
+      launch_gate_advance(v.gate, p.primal.B, s);
+    }
     {
       Timed tm(ECLQR_K_REFINE_IO, s);
       launch_correction(v.P, in, x, u, lam, mu, v.cp, s);
@@ -291,12 +318,15 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
     if (st != ECLQR_SUCCESS) return st;
     {
       Timed tm(ECLQR_K_REFINE_IO, s);
-      launch_axpy(x, v.cx, p.primal.total[ECLQR_F_q], s);
-      launch_axpy(u, v.cu, p.primal.total[ECLQR_F_r], s);
+      launch_refine_update(v.P, x, u, v.cx, v.cu, v.rnorm, s);
+      launch_refine_decide(v.P, v.psbase, v.rnorm, p.opt.refine_tol, it + 1 == nref, v.gate, v.rsteps, s);
     }
-    const bool last = (it + 1 == nref);
-    st = multipliers(p, v, in, x, u, lam, mu, status, s, last ? p.opt.dual_cons_tol : kPreRefineConsTol, last);
+    st = multipliers(p, v, in, x, u, lam, mu, status, s, kGateFinal);
     if (st != ECLQR_SUCCESS) return st;
+  }
+  if (nref > 0) {
+    Timed tm(ECLQR_K_REFINE_IO, s);
+    launch_fill_i32(v.gate, kGateActive, p.primal.B, s);  // later launches on this workspace run every instance
   }
   return ECLQR_SUCCESS;
 }
@@ -315,8 +345,9 @@ void eclqr_default_options(eclqr_options* opt) {
   opt->rank_tol = 1e-10;
   opt->cons_tol = 1e-8;
   opt->dual_cons_tol = 1e-6;
+  opt->refine_tol = 1e-8;
   opt->multipliers = 1;
-  opt->refine = 1;
+  opt->refine = 3;
   opt->use_graph = 0;
 }
 
@@ -344,7 +375,8 @@ eclqr_status eclqr_plan_create(eclqr_plan** out, const eclqr_dims* dims, const e
   eclqr_options o;
   if (opt) o = *opt;
   else eclqr_default_options(&o);
-  if (!(o.rank_tol > 0) || !(o.cons_tol > 0) || !(o.dual_cons_tol > 0) || o.refine < 0 || o.refine > 4)
+  if (!(o.rank_tol > 0) || !(o.cons_tol > 0) || !(o.dual_cons_tol > 0) || !(o.refine_tol >= 0) || o.refine < 0 ||
+      o.refine > 4)
     return fail(ECLQR_INVALID_ARGUMENT, "bad options");
   eclqr_plan* p = new (std::nothrow) eclqr_plan();
   if (!p) return fail(ECLQR_INVALID_ARGUMENT, "out of host memory");
@@ -442,18 +474,14 @@ eclqr_status eclqr_backward(eclqr_plan* plan, const eclqr_problem* prob, const e
   const Engine& E = p.primal;
   // adjoint problem: same matrices, q <- dL/dx, r <- dL/du, zero offsets
   Inputs in = inputs_of(prob);
-  double* zc = at<double>(ws, p.o_corr[ECLQR_F_c]);
-  double* zg = at<double>(ws, p.o_corr[ECLQR_F_g]);
-  double* zx = at<double>(ws, p.o_corr[ECLQR_F_x0]);
-  launch_fill(zc, 0.0, E.total[ECLQR_F_c], s);
-  launch_fill(zg, 0.0, E.total[ECLQR_F_g], s);
-  launch_fill(zx, 0.0, E.total[ECLQR_F_x0], s);
+  double* zero = at<double>(ws, p.o_zero);
+  launch_fill(zero, 0.0, std::max(E.total[ECLQR_F_c], std::max(E.total[ECLQR_F_g], E.total[ECLQR_F_x0])), s);
   Inputs adj = in;
   adj.f[IN_q] = ct->dx;
   adj.f[IN_r] = ct->du;
-  adj.f[IN_c] = zc;
-  adj.f[IN_g] = zg;
-  adj.x0 = zx;
+  adj.f[IN_c] = zero;
+  adj.f[IN_g] = zero;
+  adj.x0 = zero;
   // adjoint outputs live in the caller's gradient buffers q, r until assembly
   double* ax = grads->q;
   double* au = grads->r;
@@ -461,13 +489,13 @@ eclqr_status eclqr_backward(eclqr_plan* plan, const eclqr_problem* prob, const e
   double* am = at<double>(ws, p.o_cmu);
   int32_t* astatus = at<int32_t>(ws, p.o_flag);
   launch_fill_i32(astatus, 0, E.B, s);
-  // no refinement of the adjoint: the correction buffers hold its zero offsets
+  // the adjoint is solved without refinement
   const int keep_refine = p.opt.refine;
   p.opt.refine = 0;
   launch_dual_matrices(v.P, in, v.D, v.dp, s);
   st = solve_all(p, v, adj, ax, au, al, am, astatus, true, s);
   p.opt.refine = keep_refine;
-  launch_merge_status(sol->status, astatus, ECLQR_DUAL_FAILED, E.B, s);
+  launch_merge_status(sol->status, astatus, ECLQR_DUAL_FAILED, E.B, nullptr, 0, s);
   if (st != ECLQR_SUCCESS) return st;
   GradPtrs g{};
   g.f[IN_Q] = grads->Q;
@@ -535,6 +563,15 @@ eclqr_status eclqr_plan_reduced_dims(const eclqr_plan* plan, const void* ws, int
   HIP_OK(hipDeviceSynchronize());
   if (nbar) HIP_OK(hipMemcpy(nbar, b + E.o_nbar, sizeof(int32_t) * E.S, hipMemcpyDeviceToHost));
   if (mbar) HIP_OK(hipMemcpy(mbar, b + E.o_mbar, sizeof(int32_t) * E.S, hipMemcpyDeviceToHost));
+  return ECLQR_SUCCESS;
+}
+
+eclqr_status eclqr_plan_refine_steps(const eclqr_plan* plan, const void* ws, int32_t* steps) {
+  if (!plan || !ws || !steps) return fail(ECLQR_INVALID_ARGUMENT, "NULL argument");
+  const Plan& p = plan->p;
+  HIP_OK(hipDeviceSynchronize());
+  HIP_OK(hipMemcpy(steps, static_cast<const char*>(ws) + p.o_rsteps, sizeof(int32_t) * p.primal.B,
+                   hipMemcpyDeviceToHost));
   return ECLQR_SUCCESS;
 }
 

@@ -322,14 +322,15 @@ __device__ inline int wg_row_basis(double* W, int ld, int r0, int p, int k0, int
 }
 
 // In-place Cholesky S = L L^T of an n x n SPD matrix (lower triangle holds L,
-// upper triangle zeroed).  Returns 0 on success, 1 if a pivot is not positive.
-__device__ inline int wg_cholesky(double* S, int ld, int n, double* sh /* 2 doubles */) {
+// upper triangle zeroed).  Returns 0 on success, 1 if a pivot (before the
+// square root) is not above `floor`.
+__device__ inline int wg_cholesky(double* S, int ld, int n, double* sh /* 2 doubles */, double floor = 0.0) {
   if (ECLQR_TID == 0) sh[0] = 0.0;
   wg_sync();
   for (int j = 0; j < n; ++j) {
     if (ECLQR_TID == 0) {
       const double d = S[j * ld + j];
-      if (!(d > 0.0)) {
+      if (!(d > floor)) {
         sh[0] = 1.0;
         sh[1] = 1.0;
       } else {
@@ -356,6 +357,56 @@ __device__ inline int wg_cholesky(double* S, int ld, int n, double* sh /* 2 doub
   }
   wg_sync();
   return 0;
+}
+
+// Pivoted Cholesky of a symmetric positive semidefinite n x n matrix S
+// (read only): K (n x r, row-major, ldk) with S ~= K K^T, rows in the original
+// order, columns in pivot order.  Stops when the largest remaining diagonal is
+// <= tol * (largest diagonal of S).  rem: n doubles, used: n ints.  Returns r.
+__device__ inline int wg_pchol(const double* S, int ld, int n, double tol, double* K, int ldk, double* rem, int* used,
+                               double* sh /* 2 doubles */) {
+  for (int i = ECLQR_TID; i < n; i += ECLQR_NT) {
+    rem[i] = S[i * ld + i];
+    used[i] = 0;
+  }
+  wg_sync();
+  double ref = 0.0;
+  for (int i = 0; i < n; ++i) ref = fmax(ref, rem[i]);
+  int r = 0;
+  for (int j = 0; j < n; ++j) {
+    if (ECLQR_TID == 0) {
+      int best = -1;
+      double bv = 0.0;
+      for (int i = 0; i < n; ++i)
+        if (!used[i] && (best < 0 || rem[i] > bv)) {
+          best = i;
+          bv = rem[i];
+        }
+      sh[0] = (best >= 0 && bv > tol * ref && bv > 0.0) ? (double)best : -1.0;
+      if (best >= 0 && sh[0] >= 0.0) used[best] = 1;
+    }
+    wg_sync();
+    const int p = (int)sh[0];
+    if (p < 0) break;
+    const double dp = sqrt(rem[p]);
+    for (int i = ECLQR_TID; i < n; i += ECLQR_NT) {
+      double v = 0.0;
+      if (i == p) {
+        v = dp;
+      } else if (!used[i]) {
+        v = S[i * ld + p];
+        for (int l = 0; l < j; ++l) v = fma(-K[i * ldk + l], K[p * ldk + l], v);
+        v /= dp;
+      }
+      K[i * ldk + j] = v;
+    }
+    wg_sync();
+    for (int i = ECLQR_TID; i < n; i += ECLQR_NT)
+      if (!used[i]) rem[i] = fma(-K[i * ldk + j], K[i * ldk + j], rem[i]);
+    r = j + 1;
+    wg_sync();
+  }
+  return r;
 }
 
 // Solve L X = B (lower triangular L, n x n) in place on B (n x nc).

@@ -21,6 +21,9 @@ __device__ __forceinline__ void flag(int32_t* status, int inst, int32_t bit) {
   if (status) atomicOr(status + inst, bit);
 }
 
+// true when the instance has finished refining and must not be touched
+__device__ __forceinline__ bool gated(const DevEngine& e, int inst) { return e.gate && e.gate[inst] == kGateDone; }
+
 __device__ __forceinline__ double* block_scratch(const DevEngine& e) {
   return e.scratch + (int64_t)blockIdx.x * e.scratch_per_block;
 }

@@ -1,5 +1,7 @@
 // Multipliers (paper Section VII), refinement, residual (Section IX) and the
 // adjoint gradient assembly.  All kernels are stage-parallel and memory-bound.
+#include <algorithm>
+
 #include "dense.hpp"
 #include "device_util.hpp"
 #include "eclqr.h"
@@ -67,7 +69,7 @@ __global__ void __launch_bounds__(kBlock) k_dual_vectors(DevEngine p, Inputs in,
                                                          DevEngine d, DualPtrs dp) {
   for (int64_t ds = blockIdx.x; ds < d.S; ds += gridDim.x) {
     const StageInfo sd = d.st[ds];
-    if (sd.terminal) continue;
+    if (sd.terminal || gated(d, sd.inst)) continue;
     const int b = sd.inst;
     const int N = sd.N - 1;
     const int64_t s0 = dp.pbase[b];
@@ -107,6 +109,7 @@ __global__ void __launch_bounds__(kBlock) k_dual_extract(DevEngine p, DevEngine 
                                                          double* lam, double* mu, DualPtrs dp) {
   for (int64_t s = blockIdx.x; s < p.S; s += gridDim.x) {
     const StageInfo sp = p.st[s];
+    if (gated(p, sp.inst)) continue;
     const int N = sp.N;
     const int64_t d0 = dp.dbase[sp.inst];
     const StageInfo& sx = d.st[d0 + (N - sp.i + 1)];
@@ -124,6 +127,7 @@ __global__ void __launch_bounds__(kBlock) k_correction(DevEngine p, Inputs in, c
                                                        const double* lam, const double* mu, CorrPtrs cp) {
   for (int64_t s = blockIdx.x; s < p.S; s += gridDim.x) {
     const StageInfo st = p.st[s];
+    if (gated(p, st.inst)) continue;
     const int n = st.n, np = st.np, m = st.m, k = st.k;
     const double* xs = x + st.in[IN_q];
     const double* ls = lam + st.in[IN_q];
@@ -198,9 +202,77 @@ __global__ void __launch_bounds__(kBlock) k_correction(DevEngine p, Inputs in, c
   }
 }
 
-__global__ void k_axpy(double* y, const double* x, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    y[i] += x[i];
+// x += dx, u += du for instances still refining; per stage, the squared norms
+// of the correction and of the updated iterate (one wavefront per stage).
+__global__ void __launch_bounds__(kBlock) k_refine_update(DevEngine p, double* x, double* u, const double* dx,
+                                                          const double* du, double* norms) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
+  for (int64_t s = (int64_t)blockIdx.x * waves + wave; s < p.S; s += (int64_t)gridDim.x * waves) {
+    const StageInfo st = p.st[s];
+    if (gated(p, st.inst)) continue;
+    double d2 = 0.0, w2 = 0.0;
+    for (int i = lane; i < st.n; i += 64) {
+      const double d = dx[st.in[IN_q] + i];
+      const double w = x[st.in[IN_q] + i] + d;
+      x[st.in[IN_q] + i] = w;
+      d2 = fma(d, d, d2);
+      w2 = fma(w, w, w2);
+    }
+    if (!st.terminal)
+      for (int i = lane; i < st.m; i += 64) {
+        const double d = du[st.in[IN_r] + i];
+        const double w = u[st.in[IN_r] + i] + d;
+        u[st.in[IN_r] + i] = w;
+        d2 = fma(d, d, d2);
+        w2 = fma(w, w, w2);
+      }
+    for (int off = 32; off > 0; off >>= 1) {
+      d2 += __shfl_xor(d2, off, 64);
+      w2 += __shfl_xor(w2, off, 64);
+    }
+    if (lane == 0) {
+      norms[2 * s] = d2;
+      norms[2 * s + 1] = w2;
+    }
+  }
+}
+
+// One workgroup per instance: fixed-order sums of the stage norms; an instance
+// still refining becomes final when ||correction|| <= tol ||iterate|| or on the
+// last step.
+__global__ void __launch_bounds__(kBlock) k_refine_decide(DevEngine p, const int64_t* sbase, const double* norms,
+                                                          double tol, int last, int32_t* gate, int32_t* steps) {
+  __shared__ double sd[kBlock], sw[kBlock];
+  for (int b = blockIdx.x; b < p.B; b += gridDim.x) {
+    if (gate[b] != kGateActive) continue;
+    const int64_t s0 = sbase[b];
+    const int L = p.st[s0].N + 1;
+    double d2 = 0.0, w2 = 0.0;
+    for (int j = threadIdx.x; j < L; j += blockDim.x) {
+      d2 += norms[2 * (s0 + j)];
+      w2 += norms[2 * (s0 + j) + 1];
+    }
+    sd[threadIdx.x] = d2;
+    sw[threadIdx.x] = w2;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+      if ((int)threadIdx.x < h) {
+        sd[threadIdx.x] += sd[threadIdx.x + h];
+        sw[threadIdx.x] += sw[threadIdx.x + h];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      steps[b] += 1;
+      if (last || sd[0] <= tol * tol * sw[0]) gate[b] = kGateFinal;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_gate_advance(int32_t* gate, int32_t B) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < B; i += gridDim.x * blockDim.x)
+    if (gate[i] == kGateFinal) gate[i] = kGateDone;
 }
 __global__ void k_fill(double* y, double v, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -211,9 +283,10 @@ __global__ void k_fill_i32(int32_t* y, int32_t v, int64_t n) {
     y[i] = v;
 }
 // A failed reversed-time solve sets `bit` and keeps its own outcome bits in bits 8..15.
-__global__ void k_merge_status(int32_t* status, const int32_t* other, int32_t bit, int32_t B) {
+__global__ void k_merge_status(int32_t* status, const int32_t* other, int32_t bit, int32_t B, const int32_t* gate,
+                               int32_t want) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < B; i += gridDim.x * blockDim.x)
-    if (other[i] != 0) status[i] |= bit | ((other[i] & 0xff) << 8);
+    if (other[i] != 0 && (!gate || gate[i] == want)) status[i] |= bit | ((other[i] & 0xff) << 8);
 }
 
 // Outputs of an instance whose status is not OK become NaN.
@@ -416,8 +489,18 @@ void launch_correction(const DevEngine& p, const Inputs& in, const double* x, co
                        const double* mu, const CorrPtrs& cp, hipStream_t s) {
   hipLaunchKernelGGL(k_correction, dim3(p.nblocks), dim3(kBlock), 0, s, p, in, x, u, lam, mu, cp);
 }
-void launch_axpy(double* y, const double* x, int64_t n, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_axpy, dim3(grid_for(n)), dim3(256), 0, s, y, x, n);
+void launch_refine_update(const DevEngine& p, double* x, double* u, const double* dx, const double* du,
+                          double* norms, hipStream_t s) {
+  const int64_t g = std::min<int64_t>(4096, std::max<int64_t>(1, (p.S + 3) / 4));
+  hipLaunchKernelGGL(k_refine_update, dim3((unsigned)g), dim3(kBlock), 0, s, p, x, u, dx, du, norms);
+}
+void launch_refine_decide(const DevEngine& p, const int64_t* sbase, const double* norms, double tol, int last,
+                          int32_t* gate, int32_t* steps, hipStream_t s) {
+  const int g = std::min(4096, std::max(1, p.B));
+  hipLaunchKernelGGL(k_refine_decide, dim3(g), dim3(kBlock), 0, s, p, sbase, norms, tol, last, gate, steps);
+}
+void launch_gate_advance(int32_t* gate, int32_t B, hipStream_t s) {
+  hipLaunchKernelGGL(k_gate_advance, dim3(grid_for(B)), dim3(256), 0, s, gate, B);
 }
 void launch_fill(double* y, double v, int64_t n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(256), 0, s, y, v, n);
@@ -425,8 +508,9 @@ void launch_fill(double* y, double v, int64_t n, hipStream_t s) {
 void launch_fill_i32(int32_t* y, int32_t v, int64_t n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n)), dim3(256), 0, s, y, v, n);
 }
-void launch_merge_status(int32_t* status, const int32_t* other, int32_t bit, int32_t B, hipStream_t s) {
-  hipLaunchKernelGGL(k_merge_status, dim3(grid_for(B)), dim3(256), 0, s, status, other, bit, B);
+void launch_merge_status(int32_t* status, const int32_t* other, int32_t bit, int32_t B, const int32_t* gate,
+                         int32_t want, hipStream_t s) {
+  hipLaunchKernelGGL(k_merge_status, dim3(grid_for(B)), dim3(256), 0, s, status, other, bit, B, gate, want);
 }
 void launch_finalize(const DevEngine& p, const int32_t* status, double* x, double* u, double* lam, double* mu,
                      hipStream_t s) {

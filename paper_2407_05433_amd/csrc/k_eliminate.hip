@@ -44,6 +44,7 @@ __global__ void __launch_bounds__(kBlock) k_eliminate(DevEngine e, Inputs in, To
   double* red = sh + 16;
   for (int64_t s = blockIdx.x; s < e.S; s += gridDim.x) {
     const StageInfo st = e.st[s];
+    if (gated(e, st.inst)) continue;
     const int n = st.n, np = st.np, m = st.m, k = st.k;
     const Arena ar = arena_layout(n, np, m);
     double* base = e.arena + st.ws;

@@ -12,22 +12,203 @@ namespace eclqr {
 // Element of an interval [s, e) of the reduced problem: the conditional value
 //   V(x, y) = 1/2 x'J x - eta'x + sup_l [ l'(y - A x - b) - 1/2 l'C l ]
 // (cost from reduced state x at s to y at e).  A unary element (end at the
-// terminal stage) is V(x) = 1/2 x'J x - eta'x.  Combining [s, m) with [m, e),
-// with Minv = (I + C1 J2)^{-1}:
+// terminal stage) is V(x) = 1/2 x'J x - eta'x.  Combining [s, m) with [m, e):
 //   A = A2 Minv A1,  b = A2 Minv (b1 + C1 eta2) + b2,  C = A2 Minv C1 A2' + C2,
-//   eta = A1' Minv' (eta2 - J2 b1) + eta1,  J = A1' Minv' J2 A1 + J1.
-// LDS: Mmat (maxd x maxd) | piv | sh
+//   eta = A1' Minv' (eta2 - J2 b1) + eta1,  J = A1' Minv' J2 A1 + J1,
+// Minv = (I + C1 J2)^{-1}.
+//
+// Value functions of nearly uncontrollable reduced systems reach 1e11..1e14,
+// where an LU factorisation of I + C1 J2 loses most digits.  With J2 = L L'
+// (Cholesky) and G = I + L'C1 L = Rg Rg' (G >= I), I + J2 C1 = L G L^{-1}, so
+//   J   = J1 + (Rg^{-1} L'A1)'(Rg^{-1} L'A1),
+//   xi  = L^{-1} eta2,  d = G^{-1}(xi - L'b1),  eta = eta1 + A1' L d,
+//   A   = A2 L^{-T} G^{-1} L'A1,  b = A2 L^{-T}(xi - d) + b2,
+// and with C1 = K K' (pivoted Cholesky) and G2 = I + K'J2 K = R2 R2',
+//   C   = C2 + (A2 K R2^{-T})(A2 K R2^{-T})'.
+// Every factor is applied as a triangular or SPD solve; no difference of two
+// large terms is formed.  When J2 is not numerically positive definite the
+// LU form is used.
+namespace {
+
+__device__ void combine_lu(const double* A1, const double* b1, const double* C1, const double* et1, const double* J1,
+                           const double* A2, const double* b2, const double* C2, const double* et2, const double* J2,
+                           double* Eo, const RicLayout& lo, int ds, int dm, int de, bool binary, double* pool,
+                           int* piv, double* sh) {
+  double* Mt = pool;                                      // dm x dm
+  double* X = Mt + rup4((int64_t)dm * dm);                // dm x (ds + 1 + dm)
+  double* Yv = X + rup4((int64_t)dm * (ds + 1 + dm));     // dm x (dm + 1)
+  double* T1 = Yv + rup4((int64_t)dm * (dm + 1));         // de x dm
+  double* T2 = T1 + rup4((int64_t)de * dm);               // ds x dm
+  const int lx = ds + 1 + dm, ly = dm + 1;
+  wg_gemm(Mt, dm, C1, dm, false, J2, dm, false, dm, dm, dm, 1.0, 0.0);
+  for (int i = ECLQR_TID; i < dm; i += ECLQR_NT) Mt[i * dm + i] += 1.0;
+  wg_sync();
+  wg_lu(Mt, dm, dm, piv, sh);
+  for (int idx = ECLQR_TID; idx < dm * ly; idx += ECLQR_NT) {
+    const int i = idx / ly, j = idx % ly;
+    if (j < dm) {
+      Yv[idx] = J2[i * dm + j];
+    } else {
+      double v = et2[i];
+      for (int l = 0; l < dm; ++l) v = fma(-J2[i * dm + l], b1[l], v);
+      Yv[idx] = v;
+    }
+  }
+  if (binary) {
+    for (int idx = ECLQR_TID; idx < dm * lx; idx += ECLQR_NT) {
+      const int i = idx / lx, j = idx % lx;
+      double v;
+      if (j < ds) {
+        v = A1[i * ds + j];
+      } else if (j == ds) {
+        v = b1[i];
+        for (int l = 0; l < dm; ++l) v = fma(C1[i * dm + l], et2[l], v);
+      } else {
+        v = C1[i * dm + (j - ds - 1)];
+      }
+      X[idx] = v;
+    }
+  }
+  wg_sync();
+  wg_lu_solve_t(Mt, dm, dm, piv, Yv, ly, ly);
+  wg_gemm(T2, dm, A1, ds, true, Yv, ly, false, ds, dm, dm, 1.0, 0.0);
+  wg_gemm(Eo + lo.J, ds, T2, dm, false, A1, ds, false, ds, ds, dm, 1.0, 0.0);
+  for (int idx = ECLQR_TID; idx < ds * ds; idx += ECLQR_NT) Eo[lo.J + idx] += J1[idx];
+  for (int i = ECLQR_TID; i < ds; i += ECLQR_NT) {
+    double v = et1[i];
+    for (int l = 0; l < dm; ++l) v = fma(A1[l * ds + i], Yv[l * ly + dm], v);
+    Eo[lo.eta + i] = v;
+  }
+  wg_sync();
+  wg_symmetrize(Eo + lo.J, ds, ds);
+  if (binary) {
+    wg_lu_solve(Mt, dm, dm, piv, X, lx, lx);
+    wg_gemm(Eo + lo.A, ds, A2, dm, false, X, lx, false, de, ds, dm, 1.0, 0.0);
+    for (int i = ECLQR_TID; i < de; i += ECLQR_NT) {
+      double v = b2[i];
+      for (int l = 0; l < dm; ++l) v = fma(A2[i * dm + l], X[l * lx + ds], v);
+      Eo[lo.b + i] = v;
+    }
+    wg_gemm(T1, dm, A2, dm, false, X + ds + 1, lx, false, de, dm, dm, 1.0, 0.0);
+    wg_gemm(Eo + lo.C, de, T1, dm, false, A2, dm, true, de, de, dm, 1.0, 0.0);
+    for (int idx = ECLQR_TID; idx < de * de; idx += ECLQR_NT) Eo[lo.C + idx] += C2[idx];
+    wg_sync();
+    wg_symmetrize(Eo + lo.C, de, de);
+  }
+}
+
+// Factored combine; returns false (having written nothing) when J2 or G is not
+// numerically positive definite.
+__device__ bool combine_factored(const double* A1, const double* b1, const double* C1, const double* et1,
+                                 const double* J1, const double* A2, const double* b2, const double* C2,
+                                 const double* et2, const double* J2, double* Eo, const RicLayout& lo, int ds, int dm,
+                                 int de, bool binary, double* pool, int* used, double* sh) {
+  const int64_t dd = rup4((int64_t)dm * dm);
+  double* Lj = pool;                          // dm x dm   L (J2 = L L')
+  double* Gm = Lj + dd;                       // dm x dm   G, then Rg
+  double* Tm = Gm + dd;                       // dm x dm   C1 L, later J2 K
+  double* Mm = Tm + dd;                       // dm x dm   Rg^{-1} L', later R2^{-1} K'
+  double* Km = Mm + dd;                       // dm x dm   K (C1 = K K')
+  double* G2 = Km + dd;                       // dm x dm   G2, then R2
+  double* Yb = G2 + dd;                       // dm x (ds + 1)
+  double* AN = Yb + rup4((int64_t)dm * (ds + 1));  // de x dm
+  double* xi = AN + rup4((int64_t)de * dm);   // dm
+  double* tv = xi + rup4(dm);                 // dm
+  double* wv = tv + rup4(dm);                 // dm
+  double* rem = wv + rup4(dm);                // dm
+  double mx = 0.0;
+  for (int i = 0; i < dm; ++i) mx = fmax(mx, J2[i * dm + i]);
+  if (!(mx > 0.0)) return false;
+  wg_copy(Lj, dm, J2, dm, dm, dm);
+  if (wg_cholesky(Lj, dm, dm, sh, 1e-15 * mx)) return false;
+  // G = I + L'(C1 L)
+  wg_gemm(Tm, dm, C1, dm, false, Lj, dm, false, dm, dm, dm, 1.0, 0.0);
+  wg_gemm(Gm, dm, Lj, dm, true, Tm, dm, false, dm, dm, dm, 1.0, 0.0);
+  for (int i = ECLQR_TID; i < dm; i += ECLQR_NT) Gm[i * dm + i] += 1.0;
+  wg_sync();
+  wg_symmetrize(Gm, dm, dm);
+  if (wg_cholesky(Gm, dm, dm, sh)) return false;
+  // xi = L^{-1} eta2 ; tv = d = G^{-1}(xi - L'b1) ; wv = L d
+  for (int i = ECLQR_TID; i < dm; i += ECLQR_NT) xi[i] = et2[i];
+  wg_sync();
+  wg_trsm_lower(Lj, dm, xi, 1, dm, 1);
+  for (int i = ECLQR_TID; i < dm; i += ECLQR_NT) {
+    double v = xi[i];
+    for (int l = i; l < dm; ++l) v = fma(-Lj[l * dm + i], b1[l], v);
+    tv[i] = v;
+  }
+  wg_sync();
+  wg_trsm_lower(Gm, dm, tv, 1, dm, 1);
+  wg_trsm_lower_t(Gm, dm, tv, 1, dm, 1);
+  for (int i = ECLQR_TID; i < dm; i += ECLQR_NT) {
+    double v = 0.0;
+    for (int l = 0; l <= i; ++l) v = fma(Lj[i * dm + l], tv[l], v);
+    wv[i] = v;
+  }
+  wg_sync();
+  for (int i = ECLQR_TID; i < ds; i += ECLQR_NT) {
+    double v = et1[i];
+    for (int l = 0; l < dm; ++l) v = fma(A1[l * ds + i], wv[l], v);
+    Eo[lo.eta + i] = v;
+  }
+  // Mm = Rg^{-1} L' ; Yb[:, :ds] = Mm A1 ; J = J1 + Yb'Yb
+  wg_copy_t(Mm, dm, Lj, dm, dm, dm);
+  wg_trsm_lower(Gm, dm, Mm, dm, dm, dm);
+  const int ly = ds + 1;
+  wg_gemm(Yb, ly, Mm, dm, false, A1, ds, false, dm, ds, dm, 1.0, 0.0);
+  wg_gemm(Eo + lo.J, ds, Yb, ly, true, Yb, ly, false, ds, ds, dm, 1.0, 0.0);
+  for (int idx = ECLQR_TID; idx < ds * ds; idx += ECLQR_NT) Eo[lo.J + idx] += J1[idx];
+  wg_sync();
+  wg_symmetrize(Eo + lo.J, ds, ds);
+  if (!binary) return true;
+  // Yb = L^{-T} [Rg^{-T} Mm A1 | xi - d] ; A = A2 Yb[:, :ds] ; b = A2 Yb[:, ds] + b2
+  for (int i = ECLQR_TID; i < dm; i += ECLQR_NT) Yb[i * ly + ds] = xi[i] - tv[i];
+  wg_sync();
+  wg_trsm_lower_t(Gm, dm, Yb, ly, dm, ds);
+  wg_trsm_lower_t(Lj, dm, Yb, ly, dm, ly);
+  wg_gemm(Eo + lo.A, ds, A2, dm, false, Yb, ly, false, de, ds, dm, 1.0, 0.0);
+  for (int i = ECLQR_TID; i < de; i += ECLQR_NT) {
+    double v = b2[i];
+    for (int l = 0; l < dm; ++l) v = fma(A2[i * dm + l], Yb[l * ly + ds], v);
+    Eo[lo.b + i] = v;
+  }
+  // C = C2 + (A2 K R2^{-T})(A2 K R2^{-T})'
+  const int r = wg_pchol(C1, dm, dm, 1e-15, Km, dm, rem, used, sh);
+  if (r > 0) {
+    wg_gemm(Tm, r, J2, dm, false, Km, dm, false, dm, r, dm, 1.0, 0.0);
+    wg_gemm(G2, r, Km, dm, true, Tm, r, false, r, r, dm, 1.0, 0.0);
+    for (int i = ECLQR_TID; i < r; i += ECLQR_NT) G2[i * r + i] += 1.0;
+    wg_sync();
+    wg_symmetrize(G2, r, r);
+    if (wg_cholesky(G2, r, r, sh)) return false;
+    wg_copy_t(Mm, dm, Km, dm, dm, r);           // K' (r x dm)
+    wg_trsm_lower(G2, r, Mm, dm, r, dm);
+    wg_gemm(AN, r, A2, dm, false, Mm, dm, true, de, r, dm, 1.0, 0.0);
+    wg_gemm(Eo + lo.C, de, AN, r, false, AN, r, true, de, de, r, 1.0, 0.0);
+  } else {
+    wg_fill(Eo + lo.C, de, de, de, 0.0);
+  }
+  for (int idx = ECLQR_TID; idx < de * de; idx += ECLQR_NT) Eo[lo.C + idx] += C2[idx];
+  wg_sync();
+  wg_symmetrize(Eo + lo.C, de, de);
+  return true;
+}
+
+}  // namespace
+
+// LDS: [pool (when it fits) | piv/used ints | sh]
 __global__ void __launch_bounds__(kBlock) k_ric_combine(DevEngine e, int64_t first, int64_t ntasks, int32_t* status,
-                                                        int maxd) {
+                                                        int maxd, int pool_in_lds) {
   extern __shared__ double lds[];
-  double* Mt = lds;
-  int* piv = (int*)(Mt + (int64_t)maxd * maxd);
+  const int64_t pool_sz = pool_in_lds ? ric_pool(maxd) : 0;
+  int* piv = (int*)(lds + pool_sz);
   double* sh = (double*)(piv + kMaxDim);
   for (int64_t ti = blockIdx.x; ti < ntasks; ti += gridDim.x) {
     const int a = e.tasks[3 * (first + ti)];
     const int bsl = e.tasks[3 * (first + ti) + 1];
     const int o = e.tasks[3 * (first + ti) + 2];
     const int sa = slot_a(e, 0, a), sm = slot_b(e, 0, a), se = slot_b(e, 0, bsl);
+    if (gated(e, e.st[sa].inst)) continue;
     const int ds = e.nbar[sa], dm = e.nbar[sm], de = (se >= 0) ? e.nbar[se] : 0;
     const int ns = e.st[sa].n, nm = e.st[sm].n, ne = (se >= 0) ? e.st[se].n : 0;
     const RicLayout l1 = ric_layout(ns, nm), l2 = ric_layout(nm, ne), lo = ric_layout(ns, ne);
@@ -36,71 +217,10 @@ __global__ void __launch_bounds__(kBlock) k_ric_combine(DevEngine e, int64_t fir
     double* Eo = slot_ptr(e, SCAN_RIC, o);
     const double *A1 = E1 + l1.A, *b1 = E1 + l1.b, *C1 = E1 + l1.C, *et1 = E1 + l1.eta, *J1 = E1 + l1.J;
     const double *A2 = E2 + l2.A, *b2 = E2 + l2.b, *C2 = E2 + l2.C, *et2 = E2 + l2.eta, *J2 = E2 + l2.J;
-    double* s0 = block_scratch(e);
-    double* X = s0;                                        // dm x (ds + 1 + dm)
-    double* Yv = X + rup4((int64_t)dm * (ds + 1 + dm));    // dm x (dm + 1)
-    double* T1 = Yv + rup4((int64_t)dm * (dm + 1));        // de x dm
-    double* T2 = T1 + rup4((int64_t)de * dm);              // ds x dm
-    const int lx = ds + 1 + dm, ly = dm + 1;
-    // Mmat = I + C1 J2
-    wg_gemm(Mt, dm, C1, dm, false, J2, dm, false, dm, dm, dm, 1.0, 0.0);
-    for (int i = ECLQR_TID; i < dm; i += ECLQR_NT) Mt[i * dm + i] += 1.0;
-    wg_sync();
-    wg_lu(Mt, dm, dm, piv, sh);
-    // right-hand sides
-    for (int idx = ECLQR_TID; idx < dm * ly; idx += ECLQR_NT) {
-      const int i = idx / ly, j = idx % ly;
-      if (j < dm) {
-        Yv[idx] = J2[i * dm + j];
-      } else {
-        double v = et2[i];
-        for (int l = 0; l < dm; ++l) v = fma(-J2[i * dm + l], b1[l], v);
-        Yv[idx] = v;
-      }
-    }
-    if (se >= 0) {
-      for (int idx = ECLQR_TID; idx < dm * lx; idx += ECLQR_NT) {
-        const int i = idx / lx, j = idx % lx;
-        double v;
-        if (j < ds) {
-          v = A1[i * ds + j];
-        } else if (j == ds) {
-          v = b1[i];
-          for (int l = 0; l < dm; ++l) v = fma(C1[i * dm + l], et2[l], v);
-        } else {
-          v = C1[i * dm + (j - ds - 1)];
-        }
-        X[idx] = v;
-      }
-    }
-    wg_sync();
-    wg_lu_solve_t(Mt, dm, dm, piv, Yv, ly, ly);
-    // J = A1' (Minv' J2) A1 + J1 ; eta = A1' Minv'(eta2 - J2 b1) + eta1
-    wg_gemm(T2, dm, A1, ds, true, Yv, ly, false, ds, dm, dm, 1.0, 0.0);
-    wg_gemm(Eo + lo.J, ds, T2, dm, false, A1, ds, false, ds, ds, dm, 1.0, 0.0);
-    for (int idx = ECLQR_TID; idx < ds * ds; idx += ECLQR_NT) Eo[lo.J + idx] += J1[idx];
-    for (int i = ECLQR_TID; i < ds; i += ECLQR_NT) {
-      double v = et1[i];
-      for (int l = 0; l < dm; ++l) v = fma(A1[l * ds + i], Yv[l * ly + dm], v);
-      Eo[lo.eta + i] = v;
-    }
-    wg_sync();
-    wg_symmetrize(Eo + lo.J, ds, ds);
-    if (se >= 0) {
-      wg_lu_solve(Mt, dm, dm, piv, X, lx, lx);
-      // A = A2 X_A ; b = A2 X_b + b2 ; C = (A2 X_C) A2' + C2
-      wg_gemm(Eo + lo.A, ds, A2, dm, false, X, lx, false, de, ds, dm, 1.0, 0.0);
-      for (int i = ECLQR_TID; i < de; i += ECLQR_NT) {
-        double v = b2[i];
-        for (int l = 0; l < dm; ++l) v = fma(A2[i * dm + l], X[l * lx + ds], v);
-        Eo[lo.b + i] = v;
-      }
-      wg_gemm(T1, dm, A2, dm, false, X + ds + 1, lx, false, de, dm, dm, 1.0, 0.0);
-      wg_gemm(Eo + lo.C, de, T1, dm, false, A2, dm, true, de, de, dm, 1.0, 0.0);
-      for (int idx = ECLQR_TID; idx < de * de; idx += ECLQR_NT) Eo[lo.C + idx] += C2[idx];
-      wg_sync();
-      wg_symmetrize(Eo + lo.C, de, de);
-    }
+    double* pool = pool_in_lds ? lds : block_scratch(e);
+    const bool binary = se >= 0;
+    if (!combine_factored(A1, b1, C1, et1, J1, A2, b2, C2, et2, J2, Eo, lo, ds, dm, de, binary, pool, piv, sh))
+      combine_lu(A1, b1, C1, et1, J1, A2, b2, C2, et2, J2, Eo, lo, ds, dm, de, binary, pool, piv, sh);
     (void)status;
   }
 }
@@ -117,7 +237,7 @@ __global__ void __launch_bounds__(kBlock) k_gains(DevEngine e, int32_t* status, 
   double* sh = Huu + (int64_t)maxm * maxm;
   for (int64_t s = blockIdx.x; s < e.S; s += gridDim.x) {
     const StageInfo st = e.st[s];
-    if (st.terminal) continue;
+    if (st.terminal || gated(e, st.inst)) continue;
     const int n = st.n, np = st.np, m = st.m;
     const Arena ar = arena_layout(n, np, m);
     double* base = e.arena + st.ws;
@@ -190,6 +310,7 @@ __global__ void __launch_bounds__(kBlock) k_fwd_combine(DevEngine e, int64_t fir
     const int bsl = e.tasks[3 * (first + ti) + 1];
     const int o = e.tasks[3 * (first + ti) + 2];
     const int so = slot_a(e, 1, a), smid = slot_b(e, 1, a), sin_ = slot_b(e, 1, bsl);
+    if (gated(e, e.st[so].inst)) continue;
     const int dout = e.nbar[so], dmid = e.nbar[smid], din = (sin_ >= 0) ? e.nbar[sin_] : 0;
     const int nout = e.st[so].n, nmid = e.st[smid].n, nin = (sin_ >= 0) ? e.st[sin_].n : 0;
     const double* F1 = slot_ptr(e, SCAN_FWD, a);
@@ -215,6 +336,7 @@ __global__ void __launch_bounds__(kBlock) k_recover(DevEngine e, double* x, doub
   __shared__ double vsh[kMaxDim];
   for (int64_t s = blockIdx.x; s < e.S; s += gridDim.x) {
     const StageInfo st = e.st[s];
+    if (gated(e, st.inst)) continue;
     const int n = st.n, np = st.np, m = st.m;
     const Arena ar = arena_layout(n, np, m);
     const double* base = e.arena + st.ws;
@@ -249,14 +371,20 @@ __global__ void __launch_bounds__(kBlock) k_recover(DevEngine e, double* x, doub
   }
 }
 
+static int g_lqr_max_lds = 65536;
+
 void lqr_set_max_lds(int bytes) {
+  g_lqr_max_lds = bytes;
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_ric_combine), hipFuncAttributeMaxDynamicSharedMemorySize,
                             bytes);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_gains), hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
+static bool ric_pool_fits(int maxd) {
+  return sizeof(double) * ((size_t)ric_pool(maxd) + 16) + sizeof(int) * kMaxDim + 64 <= (size_t)g_lqr_max_lds;
+}
 size_t ric_lds_bytes(int maxd) {
-  return sizeof(double) * ((size_t)maxd * maxd + 16) + sizeof(int) * kMaxDim + 64;
+  return sizeof(double) * ((ric_pool_fits(maxd) ? (size_t)ric_pool(maxd) : 0) + 16) + sizeof(int) * kMaxDim + 64;
 }
 size_t gains_lds_bytes(int maxm) { return sizeof(double) * ((size_t)maxm * maxm + 16) + 64; }
 
@@ -264,7 +392,8 @@ void launch_ric_combine(const DevEngine& e, int64_t first, int64_t ntasks, int32
                         hipStream_t s) {
   if (ntasks <= 0) return;
   const int grid = (int)(ntasks < e.nblocks ? ntasks : e.nblocks);
-  hipLaunchKernelGGL(k_ric_combine, dim3(grid), dim3(kBlock), ric_lds_bytes(maxd), s, e, first, ntasks, status, maxd);
+  hipLaunchKernelGGL(k_ric_combine, dim3(grid), dim3(kBlock), ric_lds_bytes(maxd), s, e, first, ntasks, status, maxd,
+                     ric_pool_fits(maxd) ? 1 : 0);
 }
 
 void launch_gains(const DevEngine& e, int32_t* status, int maxm, hipStream_t s) {

@@ -13,6 +13,7 @@ __global__ void __launch_bounds__(kBlock) k_validate(DevEngine e, Inputs in, int
   __shared__ int bad;
   for (int64_t s = blockIdx.x; s < e.S; s += gridDim.x) {
     const StageInfo& st = e.st[s];
+    if (gated(e, st.inst)) continue;
     if (threadIdx.x == 0) bad = 0;
     __syncthreads();
     const int64_t n = st.n, np = st.np, m = st.m, k = st.k;
@@ -74,6 +75,7 @@ __global__ void __launch_bounds__(kBlock) k_base_relation(DevEngine e, Inputs in
   double* sh = rbs + 2 * maxp + 8 + 64;
   for (int64_t s = blockIdx.x; s < e.S; s += gridDim.x) {
     const StageInfo st = e.st[s];
+    if (gated(e, st.inst)) continue;
     const int n = st.n, np = st.np, m = st.m, k = st.k;
     const int slot = st.elem[SCAN_REL];
     double* out = slot_ptr(e, SCAN_REL, slot);
@@ -162,6 +164,7 @@ __global__ void __launch_bounds__(kBlock) k_rel_compose(DevEngine e, int64_t fir
     const int bsl = e.tasks[3 * (first + ti) + 1];
     const int o = e.tasks[3 * (first + ti) + 2];
     const int sa = slot_a(e, 0, a), sb = slot_b(e, 0, a), sc = slot_b(e, 0, bsl);
+    if (gated(e, e.st[sa].inst)) continue;
     const int na = e.st[sa].n, nb = e.st[sb].n, nc = (sc >= 0) ? e.st[sc].n : 0;
     const int inst = e.st[sa].inst;
     const int ra = e.slot_rows[a], rb = e.slot_rows[bsl];
@@ -247,6 +250,7 @@ __global__ void __launch_bounds__(kBlock) k_domain(DevEngine e, Inputs in, Tols 
   double* sh = (double*)(perm + kMaxDim);
   for (int64_t s = blockIdx.x; s < e.S; s += gridDim.x) {
     const StageInfo st = e.st[s];
+    if (gated(e, st.inst)) continue;
     const int n = st.n;
     const int suf = st.suf[SCAN_REL];
     const int r = e.slot_rows[suf];

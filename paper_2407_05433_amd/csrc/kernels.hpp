@@ -22,6 +22,7 @@ struct DevEngine {
   double* arena;              // stage arenas
   double* scan[SCAN_COUNT];   // slot arenas
   double* resid;              // [4 * S]
+  const int32_t* gate;        // per-instance refinement state, null = every instance runs
   double* scratch;            // per-workgroup global scratch
   int64_t scratch_per_block;  // doubles
   int64_t S;
@@ -86,10 +87,20 @@ void launch_dual_extract(const DevEngine& p, const DevEngine& d, const double* d
                          double* mu, const DualPtrs& dp, hipStream_t s);
 void launch_correction(const DevEngine& p, const Inputs& in, const double* x, const double* u, const double* lam,
                        const double* mu, const CorrPtrs& cp, hipStream_t s);
-void launch_axpy(double* y, const double* x, int64_t n, hipStream_t s);
+// refinement control: an instance in state kGateDone is skipped by every kernel
+constexpr int32_t kGateActive = 0;  // still refining: its reversed-time outcome is not reported
+constexpr int32_t kGateFinal = 1;   // this step's update is its last: report the reversed-time outcome
+constexpr int32_t kGateDone = 2;    // converged in an earlier step
+void launch_refine_update(const DevEngine& p, double* x, double* u, const double* dx, const double* du,
+                          double* norms, hipStream_t s);
+void launch_refine_decide(const DevEngine& p, const int64_t* sbase, const double* norms, double tol, int last,
+                          int32_t* gate, int32_t* steps, hipStream_t s);
+void launch_gate_advance(int32_t* gate, int32_t B, hipStream_t s);
 void launch_fill(double* y, double v, int64_t n, hipStream_t s);
 void launch_fill_i32(int32_t* y, int32_t v, int64_t n, hipStream_t s);
-void launch_merge_status(int32_t* status, const int32_t* other, int32_t bit, int32_t B, hipStream_t s);
+// merges only instances whose gate equals `want` (all instances if gate is null)
+void launch_merge_status(int32_t* status, const int32_t* other, int32_t bit, int32_t B, const int32_t* gate,
+                         int32_t want, hipStream_t s);
 void launch_finalize(const DevEngine& p, const int32_t* status, double* x, double* u, double* lam, double* mu,
                      hipStream_t s);
 void launch_kkt_residual(const DevEngine& p, const Inputs& in, const double* x, const double* u, const double* lam,

@@ -254,7 +254,7 @@ std::string Engine::build(const eclqr_dims* d) {
     scratch_per_block = std::max(scratch_per_block, elim_scratch(x.n, x.np, x.m, x.k));
     scratch_per_block = std::max(scratch_per_block, gains_scratch(x.n, x.np, x.m));
   }
-  scratch_per_block = std::max(scratch_per_block, ric_scratch(maxn, maxn, maxn));
+  scratch_per_block = std::max(scratch_per_block, ric_pool(maxn));
   scratch_per_block = rup4(scratch_per_block);
   nblocks = (int32_t)std::min<int64_t>(S, 2048);
 
@@ -324,7 +324,14 @@ std::string build_plan(Plan& p, const eclqr_dims* d, const eclqr_options* opt) {
   p.o_cu = o; o = align256(o + sizeof(double) * std::max<int64_t>(1, P.total[ECLQR_F_r]));
   p.o_clam = o; o = align256(o + sizeof(double) * std::max<int64_t>(1, P.total[ECLQR_F_q]));
   p.o_cmu = o; o = align256(o + sizeof(double) * std::max<int64_t>(1, P.total[ECLQR_F_g]));
-  p.o_flag = o; o = align256(o + sizeof(int32_t) * 64);
+  p.o_flag = o; o = align256(o + sizeof(int32_t) * std::max<int32_t>(1, P.B));
+  p.o_gate = o; o = align256(o + sizeof(int32_t) * std::max<int32_t>(1, P.B));
+  p.o_rnorm = o; o = align256(o + sizeof(double) * 2 * std::max<int64_t>(1, P.S));
+  p.o_rsteps = o; o = align256(o + sizeof(int32_t) * std::max<int32_t>(1, P.B));
+  {
+    const int64_t nz = std::max<int64_t>(1, std::max(P.total[ECLQR_F_c], std::max(P.total[ECLQR_F_g], P.total[ECLQR_F_x0])));
+    p.o_zero = o; o = align256(o + sizeof(double) * nz);
+  }
   p.bytes = o;
   return "";
 }

@@ -66,7 +66,10 @@ struct Plan {
   size_t o_dx = 0, o_du = 0, o_dstatus = 0;
   size_t o_corr[ECLQR_NUM_FIELDS] = {0};   // correction / adjoint problem vectors (q r c g x0)
   size_t o_cx = 0, o_cu = 0, o_clam = 0, o_cmu = 0, o_zero = 0;
-  size_t o_flag = 0;
+  size_t o_flag = 0;   // per-instance status of the adjoint solve
+  size_t o_gate = 0;   // per-instance refinement state (kGate*)
+  size_t o_rnorm = 0;  // per-stage squared norms of correction and iterate
+  size_t o_rsteps = 0; // per-instance count of refinement steps taken
   size_t bytes = 0;
   void* bound_ws = nullptr;
   int bound_device = -1;

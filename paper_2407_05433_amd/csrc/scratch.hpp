@@ -23,16 +23,12 @@ ECLQR_HD inline int64_t elim_scratch(int n, int np, int m, int k) {
   return s;
 }
 
-// Riccati combine over endpoint dims (ds, dm, de)
-ECLQR_HD inline int64_t ric_scratch(int ds, int dm, int de) {
-  int64_t s = 0;
-  s += rup4((int64_t)dm * dm);            // Mmat (LU)
-  s += rup4((int64_t)dm * (ds + 1 + dm)); // X = Minv [A1 | b1 + C1 eta2 | C1]
-  s += rup4((int64_t)dm * (dm + 1));      // Y = Minv^T [J2 | eta2 - J2 b1]
-  s += rup4((int64_t)de * dm);            // A2 X_C
-  s += rup4((int64_t)ds * dm);            // A1^T Y_J
-  s += 64;
-  return s;
+// Working pool of one value-function combine with every endpoint dim <= d:
+// the factored path uses six d x d blocks, d x (d+1), d x d and four vectors;
+// the LU fallback fits in the same pool.
+ECLQR_HD inline int64_t ric_pool(int d) {
+  const int64_t dd = rup4((int64_t)d * d);
+  return 7 * dd + rup4((int64_t)d * (d + 1)) + 4 * rup4(d) + 64;
 }
 
 // gains: dims at capacity (n, n', m)

@@ -6,8 +6,10 @@ combines.  Reduced dimensions and relation row counts are read back from the
 workspace after a solve.  Householder QR of a p x c matrix with r reflections
 counts sum_{j<r} 4 (p - j)(c - j); row-pivoted Gram-Schmidt of p rows over kc
 columns choosing r rows counts sum_{j<r} (4 j kc + 4 (p - j - 1)(kc + 1)).
-One solve with multipliers and one refinement step runs the primal engine
-twice (solve, correction) and the reversed-time engine twice.
+A solve with multipliers in which instance b takes s_b refinement steps runs
+the primal engine 1 + s_b times on b (solve, corrections) and the
+reversed-time engine 1 + s_b times (multipliers after the solve and after
+every step).
 """
 
 from __future__ import annotations
@@ -30,13 +32,15 @@ def _gs(p, kc, r):
     return 2.0 * kc * r * (r - 1) + 4.0 * (kc + 1) * (r * (p - 1) - r * (r - 1) / 2.0)
 
 
-def engine_flops(plan, ws, dual: bool) -> Dict[str, float]:
+def engine_flops(plan, ws, dual: bool, weight=None) -> Dict[str, float]:
+    """Flops per kernel class of one engine pass; instance b counted weight[b] times."""
     dims = plan.stage_dims(dual)
     nbar, mbar = plan.reduced_dims(ws, dual)
     rows = plan.scan_rows(ws, dual)
     inst, first, last = plan.slot_info(dual)
     horizons = [h + 1 for h in plan.horizons] if dual else list(plan.horizons)
     sbase = np.concatenate([[0], np.cumsum([h + 1 for h in horizons])[:-1]]).astype(np.int64)
+    W = np.ones(len(horizons)) if weight is None else np.asarray(weight, dtype=np.float64)
     F = defaultdict(float)
     leaf_base = np.full(len(horizons), -1, dtype=np.int64)
     for q in range(len(inst) - 1, -1, -1):
@@ -50,10 +54,11 @@ def engine_flops(plan, ws, dual: bool) -> Dict[str, float]:
         i = s - int(sbase[b])
         # domain parameterisation: QR of H^T (n x r), T formation, t
         r = n - nb
-        F["domain"] += _qr(n, r, r) + 4.0 * nb * (r * n - r * (r - 1) / 2.0) + 2.0 * n * r
+        w = W[b]
+        F["domain"] += w * (_qr(n, r, r) + 4.0 * nb * (r * n - r * (r - 1) / 2.0) + 2.0 * n * r)
         if i == horizons[b]:
-            F["eliminate"] += 2.0 * n * n * nb + 2.0 * nb * n * nb + 2.0 * n * n + 2.0 * n * nb
-            F["base_relation"] += _gs(k, n, rows[leaf_base[b] + i])
+            F["eliminate"] += w * (2.0 * n * n * nb + 2.0 * nb * n * nb + 2.0 * n * n + 2.0 * n * nb)
+            F["base_relation"] += w * _gs(k, n, rows[leaf_base[b] + i])
             continue
         nb1, mb = int(nbar[s + 1]), int(mbar[s])
         r1 = np_ - nb1
@@ -73,17 +78,17 @@ def engine_flops(plan, ws, dual: bool) -> Dict[str, float]:
         f += 2.0 * n * n + 2.0 * m * m + 2.0 * nb * n + 2.0 * nb * m * 2 + 2.0 * mb * m  # vectors
         f += mb ** 3 / 3.0 + mb * mb * (nb1 + nb + 1)         # Cholesky of R-bar, L^{-1} [B^T M^T r]
         f += 2.0 * nb1 * nb * mb + 2.0 * nb1 * nb1 * mb + 2.0 * nb * nb * mb + 2.0 * (nb1 + nb) * mb
-        F["eliminate"] += f
+        F["eliminate"] += w * f
         # base relation: QR of [B; F] over the input columns, row basis of the rest
         p = np_ + k
         c = m + n + np_ + 1
         rho_u = min(m, p)
-        F["base_relation"] += _qr(p, c, rho_u) + _gs(p - rho_u, n + np_, rows[leaf_base[b] + i])
+        F["base_relation"] += w * (_qr(p, c, rho_u) + _gs(p - rho_u, n + np_, rows[leaf_base[b] + i]))
         # gains
         g = 2.0 * nb1 * nb1 * (mb + nb) + 2.0 * mb * mb * nb1 + 2.0 * mb * nb * nb1 + mb ** 3 / 3.0
         g += 2.0 * mb * mb * (nb + 1) + 2.0 * nb1 * mb * nb + 2.0 * nb1 * (nb1 + mb)
-        F["gains"] += g
-        F["recover"] += 2.0 * (n * nb + m * (nb + mb) + mb * nb)
+        F["gains"] += w * g
+        F["recover"] += w * 2.0 * (n * nb + m * (nb + mb) + mb * nb)
 
     # scan combines
     levels = plan.schedule(dual)
@@ -96,6 +101,7 @@ def engine_flops(plan, ws, dual: bool) -> Dict[str, float]:
     for lv in levels:
         for a, bb, o in lv:
             b = int(inst[a])
+            w = W[b]
             L = horizons[b] + 1
             s0, mid, e0 = int(first[a]), int(last[a]), int(last[bb])
             # relation composition
@@ -103,7 +109,7 @@ def engine_flops(plan, ws, dual: bool) -> Dict[str, float]:
             p = int(rows[a] + rows[bb])
             rr = int(rows[o])
             rho = min(nb_, max(p - rr, 0))
-            F["rel_compose"] += _qr(p, na + nb_ + nc + 1, rho) + _gs(p - rho, na + nc, rr)
+            F["rel_compose"] += w * (_qr(p, na + nb_ + nc + 1, rho) + _gs(p - rho, na + nc, rr))
             # value-function combine
             ds, dm, de = rdim(b, s0), rdim(b, mid), (rdim(b, e0) if e0 < L else 0)
             f = 2.0 * dm ** 3 + 2.0 / 3.0 * dm ** 3 + 2.0 * dm * dm * (dm + 1) + 2.0 * dm * dm
@@ -111,24 +117,23 @@ def engine_flops(plan, ws, dual: bool) -> Dict[str, float]:
             if e0 < L:
                 f += 2.0 * dm * dm * (ds + 1 + dm) + 2.0 * dm * dm + 2.0 * de * ds * dm + 2.0 * de * dm
                 f += 2.0 * de * dm * dm + 2.0 * de * de * dm
-            F["ric_combine"] += f
+            F["ric_combine"] += w * f
             # forward map composition: slot interval reflected (output z_{N-s}, input z_{N-e})
             N = horizons[b]
             do, dmid = rdim(b, N - s0), rdim(b, N - mid)
             din = rdim(b, N - e0) if e0 < L else 0
-            F["fwd_combine"] += 2.0 * do * dmid * (din + 1)
+            F["fwd_combine"] += w * 2.0 * do * dmid * (din + 1)
     return dict(F)
 
 
-def solve_flops(plan, problems, ws, multipliers: bool = True, refine: int = 1) -> Dict[str, float]:
-    """Flops per kernel class of one solve (primal, multipliers, refinement)."""
-    prim = engine_flops(plan, ws, False)
-    runs_p = 1 + (refine if multipliers else 0)
+def solve_flops(plan, problems, ws, multipliers: bool = True, steps=None) -> Dict[str, float]:
+    """Flops per kernel class of one solve (primal, multipliers, refinement);
+    ``steps`` = refinement steps per instance (``Plan.refine_steps``)."""
+    runs = np.ones(plan.batch) if not multipliers else 1.0 + np.asarray(steps, dtype=np.float64)
     out = defaultdict(float)
-    for k, v in prim.items():
-        out[k] += runs_p * v
+    for k, v in engine_flops(plan, ws, False, runs).items():
+        out[k] += v
     if multipliers:
-        dual = engine_flops(plan, ws, True)
-        for k, v in dual.items():
-            out[k] += (1 + refine) * v
+        for k, v in engine_flops(plan, ws, True, runs).items():
+            out[k] += v
     return dict(out)

@@ -111,6 +111,13 @@ class Plan:
         check(lib().eclqr_plan_reduced_dims(self._h, C.c_void_p(wptr), int(dual), nb, mb), "eclqr_plan_reduced_dims")
         return np.frombuffer(nb, dtype=np.int32).copy(), np.frombuffer(mb, dtype=np.int32).copy()
 
+    def refine_steps(self, ws: torch.Tensor) -> np.ndarray:
+        """Refinement steps each instance took in the last solve in ``ws`` (synchronises)."""
+        out = (C.c_int32 * max(1, self.batch))()
+        wptr, _ = _aligned_ws(ws)
+        check(lib().eclqr_plan_refine_steps(self._h, C.c_void_p(wptr), out), "eclqr_plan_refine_steps")
+        return np.frombuffer(out, dtype=np.int32)[:self.batch].copy()
+
     def scan_rows(self, ws: Optional[torch.Tensor], dual: bool = False) -> np.ndarray:
         """Rows of every feasible-domain-scan slot after the last solve (synchronises)."""
         n = C.c_int32()
