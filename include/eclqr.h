@@ -101,6 +101,8 @@ typedef struct {
   double cons_tol;        /* 0 = gamma accepted if |gamma| <= cons_tol*max(1,|offsets|); 1e-8 */
   double dual_cons_tol;   /* same test inside the multiplier solve; 1e-6 */
   double refine_tol;      /* an instance stops refining once ||correction|| <= refine_tol*||(x,u)||; 1e-8 */
+  double accept_tol;      /* an instance whose componentwise KKT backward error after the first solve is
+                           * <= accept_tol takes no refinement step; 1e-13 (0: always refine) */
   int32_t multipliers;    /* 1: compute lam and mu; 0: primal only */
   int32_t refine;         /* most steps of iterative refinement per instance (0..4); 3.  With
                            * multipliers, every instance takes at least one step when refine > 0 */
@@ -199,6 +201,11 @@ eclqr_status eclqr_plan_reduced_dims(const eclqr_plan* plan, const void* ws, int
 /* Refinement steps each instance took in the last solve in ws (host array of
  * batch entries).  Synchronises the device. */
 eclqr_status eclqr_plan_refine_steps(const eclqr_plan* plan, const void* ws, int32_t* steps);
+
+/* Componentwise KKT backward error of each instance after the first solve of
+ * the last eclqr_solve in ws: max over rows of |residual| / sum |terms|
+ * (host array of batch entries; 0 when refine = 0).  Synchronises. */
+eclqr_status eclqr_plan_backward_error(const eclqr_plan* plan, const void* ws, double* omega);
 
 /* Row counts of every slot of the feasible-domain scan after the last solve
  * in ws (rows of the affine relation each slot holds); *nslots receives the

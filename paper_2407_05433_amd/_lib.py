@@ -34,7 +34,7 @@ class Dims(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("rank_tol", C.c_double), ("cons_tol", C.c_double), ("dual_cons_tol", C.c_double),
-                ("refine_tol", C.c_double), ("multipliers", C.c_int32), ("refine", C.c_int32), ("use_graph", C.c_int32),
+                ("refine_tol", C.c_double), ("accept_tol", C.c_double), ("multipliers", C.c_int32), ("refine", C.c_int32), ("use_graph", C.c_int32),
                 ("reserved", C.c_int32 * 5)]
 
 
@@ -95,6 +95,8 @@ def lib():
                                        C.POINTER(C.c_int32)]
     L.eclqr_plan_refine_steps.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]
     L.eclqr_plan_refine_steps.restype = C.c_int
+    L.eclqr_plan_backward_error.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]
+    L.eclqr_plan_backward_error.restype = C.c_int
     L.eclqr_plan_scan_rows.restype = C.c_int
     L.eclqr_plan_slot_info.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                        C.POINTER(C.c_int32), C.POINTER(C.c_int32)]

@@ -206,6 +206,7 @@ struct Views {
   double *cx, *cu, *clam, *cmu;
   int32_t* gate;
   int32_t* rsteps;
+  unsigned long long* omega;
   double* rnorm;
   const int64_t* psbase;
   const double* zero;
@@ -233,6 +234,7 @@ Views views(Plan& p, void* ws) {
   v.cmu = at<double>(ws, p.o_cmu);
   v.gate = at<int32_t>(ws, p.o_gate);
   v.rsteps = at<int32_t>(ws, p.o_rsteps);
+  v.omega = at<unsigned long long>(ws, p.o_omega);
   v.rnorm = at<double>(ws, p.o_rnorm);
   v.psbase = dev_sbase(p.primal, ws, p.o_primal);
   v.zero = at<double>(ws, p.o_zero);
@@ -284,6 +286,7 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
     Timed tm(ECLQR_K_REFINE_IO, s);
     launch_fill_i32(v.gate, kGateActive, p.primal.B, s);
     launch_fill_i32(v.rsteps, 0, p.primal.B, s);
+    launch_fill_u64(v.omega, 0ull, p.primal.B, s);
   }
   eclqr_status st = run_engine(p.primal, v.P, in, x, u, status, tp, s);
   if (st != ECLQR_SUCCESS) return st;
@@ -294,12 +297,20 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
   const int nref = p.opt.refine;
   st = multipliers(p, v, in, x, u, lam, mu, status, s, nref > 0 ? kGateDone : -1);
   if (st != ECLQR_SUCCESS) return st;
+  if (nref == 0) return ECLQR_SUCCESS;
+  // An instance whose first solve is already backward stable (componentwise
+  // KKT backward error <= accept_tol, multipliers found) is final as it is.
+  {
+    Timed tm(ECLQR_K_REFINE_IO, s);
+    launch_backward_error(v.P, in, x, u, lam, mu, v.omega, s);
+    launch_accept(v.omega, v.dstatus, p.opt.accept_tol, v.gate, p.primal.B, s);
+  }
   // Each step: correction problem (same matrices, residuals as data), update,
   // per-instance convergence test, multipliers at the updated point.  An
   // instance whose correction is small is final after this step and skipped
   // by every later step.
   for (int it = 0; it < nref; ++it) {
-    if (it > 0) {
+    {
       Timed tm(ECLQR_K_REFINE_IO, s);
       launch_gate_advance(v.gate, p.primal.B, s);
     }
@@ -324,7 +335,7 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
     st = multipliers(p, v, in, x, u, lam, mu, status, s, kGateFinal);
     if (st != ECLQR_SUCCESS) return st;
   }
-  if (nref > 0) {
+  {
     Timed tm(ECLQR_K_REFINE_IO, s);
     launch_fill_i32(v.gate, kGateActive, p.primal.B, s);  // later launches on this workspace run every instance
   }
@@ -346,6 +357,7 @@ void eclqr_default_options(eclqr_options* opt) {
   opt->cons_tol = 1e-8;
   opt->dual_cons_tol = 1e-6;
   opt->refine_tol = 1e-8;
+  opt->accept_tol = 1e-13;
   opt->multipliers = 1;
   opt->refine = 3;
   opt->use_graph = 0;
@@ -375,7 +387,7 @@ eclqr_status eclqr_plan_create(eclqr_plan** out, const eclqr_dims* dims, const e
   eclqr_options o;
   if (opt) o = *opt;
   else eclqr_default_options(&o);
-  if (!(o.rank_tol > 0) || !(o.cons_tol > 0) || !(o.dual_cons_tol > 0) || !(o.refine_tol >= 0) || o.refine < 0 ||
+  if (!(o.rank_tol > 0) || !(o.cons_tol > 0) || !(o.dual_cons_tol > 0) || !(o.refine_tol >= 0) || !(o.accept_tol >= 0) || o.refine < 0 ||
       o.refine > 4)
     return fail(ECLQR_INVALID_ARGUMENT, "bad options");
   eclqr_plan* p = new (std::nothrow) eclqr_plan();
@@ -571,6 +583,15 @@ eclqr_status eclqr_plan_refine_steps(const eclqr_plan* plan, const void* ws, int
   const Plan& p = plan->p;
   HIP_OK(hipDeviceSynchronize());
   HIP_OK(hipMemcpy(steps, static_cast<const char*>(ws) + p.o_rsteps, sizeof(int32_t) * p.primal.B,
+                   hipMemcpyDeviceToHost));
+  return ECLQR_SUCCESS;
+}
+
+eclqr_status eclqr_plan_backward_error(const eclqr_plan* plan, const void* ws, double* omega) {
+  if (!plan || !ws || !omega) return fail(ECLQR_INVALID_ARGUMENT, "NULL argument");
+  const Plan& p = plan->p;
+  HIP_OK(hipDeviceSynchronize());
+  HIP_OK(hipMemcpy(omega, static_cast<const char*>(ws) + p.o_omega, sizeof(double) * p.primal.B,
                    hipMemcpyDeviceToHost));
   return ECLQR_SUCCESS;
 }

@@ -270,11 +270,156 @@ __global__ void __launch_bounds__(kBlock) k_refine_decide(DevEngine p, const int
   }
 }
 
+// Componentwise backward error of the KKT system at (x, u, lambda, mu):
+// max over rows of |residual| / (sum of |terms|), over stationarity in x and
+// u, dynamics, equality rows and the initial condition.  One wavefront per
+// stage; the per-instance maximum is accumulated with an integer atomic max
+// on the bit pattern (order independent, so deterministic).
+__global__ void __launch_bounds__(kBlock) k_backward_error(DevEngine p, Inputs in, const double* x, const double* u,
+                                                           const double* lam, const double* mu,
+                                                           unsigned long long* omega) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
+  for (int64_t s = (int64_t)blockIdx.x * waves + wave; s < p.S; s += (int64_t)gridDim.x * waves) {
+    const StageInfo st = p.st[s];
+    if (gated(p, st.inst)) continue;
+    const int n = st.n, np = st.np, m = st.m, k = st.k;
+    const double* xs = x + st.in[IN_q];
+    const double* ls = lam + st.in[IN_q];
+    const double* ms = mu + st.in[IN_g];
+    const double* Q = in.f[IN_Q] + st.in[IN_Q];
+    const double* q = in.f[IN_q] + st.in[IN_q];
+    const double* E = in.f[IN_E] + st.in[IN_E];
+    const double* g = in.f[IN_g] + st.in[IN_g];
+    const bool term = st.terminal;
+    const double* us = term ? nullptr : u + st.in[IN_r];
+    const double* F = term ? nullptr : in.f[IN_F] + st.in[IN_F];
+    const double* M = (!term && in.f[IN_M]) ? in.f[IN_M] + st.in[IN_M] : nullptr;
+    const double* A = term ? nullptr : in.f[IN_A] + st.in[IN_A];
+    const double* B = term ? nullptr : in.f[IN_B] + st.in[IN_B];
+    const double* R = term ? nullptr : in.f[IN_R] + st.in[IN_R];
+    const double* r = term ? nullptr : in.f[IN_r] + st.in[IN_r];
+    const double* c = term ? nullptr : in.f[IN_c] + st.in[IN_c];
+    const double* x1 = term ? nullptr : x + p.st[s + 1].in[IN_q];
+    const double* l1 = term ? nullptr : lam + p.st[s + 1].in[IN_q];
+    double w = 0.0;
+    auto acc = [&](double res, double mag) {
+      const double e = (mag > 0.0) ? fabs(res) / mag : (res == 0.0 ? 0.0 : HUGE_VAL);
+      w = (e > w || e != e) ? e : w;
+    };
+    for (int i = lane; i < n; i += 64) {  // stationarity in x_i
+      double v = q[i] - ls[i], a = fabs(q[i]) + fabs(ls[i]);
+      for (int l = 0; l < n; ++l) {
+        const double t = Q[i * n + l] * xs[l];
+        v += t;
+        a += fabs(t);
+      }
+      for (int l = 0; l < k; ++l) {
+        const double t = E[l * n + i] * ms[l];
+        v += t;
+        a += fabs(t);
+      }
+      if (!term) {
+        if (M)
+          for (int l = 0; l < m; ++l) {
+            const double t = M[i * m + l] * us[l];
+            v += t;
+            a += fabs(t);
+          }
+        for (int l = 0; l < np; ++l) {
+          const double t = A[l * n + i] * l1[l];
+          v += t;
+          a += fabs(t);
+        }
+      }
+      acc(v, a);
+    }
+    for (int i = lane; i < k; i += 64) {  // equality rows
+      double v = g[i], a = fabs(g[i]);
+      for (int l = 0; l < n; ++l) {
+        const double t = E[i * n + l] * xs[l];
+        v += t;
+        a += fabs(t);
+      }
+      if (!term)
+        for (int l = 0; l < m; ++l) {
+          const double t = F[i * m + l] * us[l];
+          v += t;
+          a += fabs(t);
+        }
+      acc(v, a);
+    }
+    if (!term) {
+      for (int i = lane; i < m; i += 64) {  // stationarity in u_i
+        double v = r[i], a = fabs(r[i]);
+        for (int l = 0; l < m; ++l) {
+          const double t = R[i * m + l] * us[l];
+          v += t;
+          a += fabs(t);
+        }
+        if (M)
+          for (int l = 0; l < n; ++l) {
+            const double t = M[l * m + i] * xs[l];
+            v += t;
+            a += fabs(t);
+          }
+        for (int l = 0; l < np; ++l) {
+          const double t = B[l * m + i] * l1[l];
+          v += t;
+          a += fabs(t);
+        }
+        for (int l = 0; l < k; ++l) {
+          const double t = F[l * m + i] * ms[l];
+          v += t;
+          a += fabs(t);
+        }
+        acc(v, a);
+      }
+      for (int i = lane; i < np; i += 64) {  // dynamics
+        double v = c[i] - x1[i], a = fabs(c[i]) + fabs(x1[i]);
+        for (int l = 0; l < n; ++l) {
+          const double t = A[i * n + l] * xs[l];
+          v += t;
+          a += fabs(t);
+        }
+        for (int l = 0; l < m; ++l) {
+          const double t = B[i * m + l] * us[l];
+          v += t;
+          a += fabs(t);
+        }
+        acc(v, a);
+      }
+    }
+    if (st.i == 0)
+      for (int i = lane; i < n; i += 64) acc(xs[i] - in.x0[st.x0 + i], fabs(xs[i]) + fabs(in.x0[st.x0 + i]));
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(w, off, 64);
+      w = (o > w || o != o) ? o : w;
+    }
+    if (lane == 0) {
+      const double wv = (w != w) ? HUGE_VAL : w;
+      atomicMax(omega + st.inst, (unsigned long long)__double_as_longlong(wv));
+    }
+  }
+}
+
+// Instances still refining whose backward error is <= tol and whose
+// reversed-time solve succeeded are final without a refinement step.
+__global__ void k_accept(const unsigned long long* omega, const int32_t* dstatus, double tol, int32_t* gate,
+                         int32_t B) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < B; i += gridDim.x * blockDim.x)
+    if (gate[i] == kGateActive && dstatus[i] == 0 && __longlong_as_double((long long)omega[i]) <= tol)
+      gate[i] = kGateFinal;
+}
+
 __global__ void k_gate_advance(int32_t* gate, int32_t B) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < B; i += gridDim.x * blockDim.x)
     if (gate[i] == kGateFinal) gate[i] = kGateDone;
 }
 __global__ void k_fill(double* y, double v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = v;
+}
+__global__ void k_fill_u64(unsigned long long* y, unsigned long long v, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     y[i] = v;
 }
@@ -498,6 +643,18 @@ void launch_refine_decide(const DevEngine& p, const int64_t* sbase, const double
                           int32_t* gate, int32_t* steps, hipStream_t s) {
   const int g = std::min(4096, std::max(1, p.B));
   hipLaunchKernelGGL(k_refine_decide, dim3(g), dim3(kBlock), 0, s, p, sbase, norms, tol, last, gate, steps);
+}
+void launch_backward_error(const DevEngine& p, const Inputs& in, const double* x, const double* u, const double* lam,
+                           const double* mu, unsigned long long* omega, hipStream_t s) {
+  const int64_t g = std::min<int64_t>(4096, std::max<int64_t>(1, (p.S + 3) / 4));
+  hipLaunchKernelGGL(k_backward_error, dim3((unsigned)g), dim3(kBlock), 0, s, p, in, x, u, lam, mu, omega);
+}
+void launch_accept(const unsigned long long* omega, const int32_t* dstatus, double tol, int32_t* gate, int32_t B,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_accept, dim3(grid_for(B)), dim3(256), 0, s, omega, dstatus, tol, gate, B);
+}
+void launch_fill_u64(unsigned long long* y, unsigned long long v, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n)), dim3(256), 0, s, y, v, n);
 }
 void launch_gate_advance(int32_t* gate, int32_t B, hipStream_t s) {
   hipLaunchKernelGGL(k_gate_advance, dim3(grid_for(B)), dim3(256), 0, s, gate, B);

@@ -96,6 +96,13 @@ void launch_refine_update(const DevEngine& p, double* x, double* u, const double
 void launch_refine_decide(const DevEngine& p, const int64_t* sbase, const double* norms, double tol, int last,
                           int32_t* gate, int32_t* steps, hipStream_t s);
 void launch_gate_advance(int32_t* gate, int32_t B, hipStream_t s);
+// per-instance componentwise backward error (as the bit pattern of a
+// non-negative double, max-accumulated: clear to 0 first)
+void launch_backward_error(const DevEngine& p, const Inputs& in, const double* x, const double* u, const double* lam,
+                           const double* mu, unsigned long long* omega, hipStream_t s);
+void launch_accept(const unsigned long long* omega, const int32_t* dstatus, double tol, int32_t* gate, int32_t B,
+                   hipStream_t s);
+void launch_fill_u64(unsigned long long* y, unsigned long long v, int64_t n, hipStream_t s);
 void launch_fill(double* y, double v, int64_t n, hipStream_t s);
 void launch_fill_i32(int32_t* y, int32_t v, int64_t n, hipStream_t s);
 // merges only instances whose gate equals `want` (all instances if gate is null)

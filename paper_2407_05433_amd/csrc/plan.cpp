@@ -328,6 +328,7 @@ std::string build_plan(Plan& p, const eclqr_dims* d, const eclqr_options* opt) {
   p.o_gate = o; o = align256(o + sizeof(int32_t) * std::max<int32_t>(1, P.B));
   p.o_rnorm = o; o = align256(o + sizeof(double) * 2 * std::max<int64_t>(1, P.S));
   p.o_rsteps = o; o = align256(o + sizeof(int32_t) * std::max<int32_t>(1, P.B));
+  p.o_omega = o; o = align256(o + sizeof(double) * std::max<int32_t>(1, P.B));
   {
     const int64_t nz = std::max<int64_t>(1, std::max(P.total[ECLQR_F_c], std::max(P.total[ECLQR_F_g], P.total[ECLQR_F_x0])));
     p.o_zero = o; o = align256(o + sizeof(double) * nz);

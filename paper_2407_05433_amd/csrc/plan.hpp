@@ -70,6 +70,7 @@ struct Plan {
   size_t o_gate = 0;   // per-instance refinement state (kGate*)
   size_t o_rnorm = 0;  // per-stage squared norms of correction and iterate
   size_t o_rsteps = 0; // per-instance count of refinement steps taken
+  size_t o_omega = 0;  // per-instance backward error after the first solve (double bits)
   size_t bytes = 0;
   void* bound_ws = nullptr;
   int bound_device = -1;

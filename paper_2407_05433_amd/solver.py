@@ -118,6 +118,13 @@ class Plan:
         check(lib().eclqr_plan_refine_steps(self._h, C.c_void_p(wptr), out), "eclqr_plan_refine_steps")
         return np.frombuffer(out, dtype=np.int32)[:self.batch].copy()
 
+    def backward_error(self, ws: torch.Tensor) -> np.ndarray:
+        """Componentwise KKT backward error of each instance after the first solve (synchronises)."""
+        out = (C.c_double * max(1, self.batch))()
+        wptr, _ = _aligned_ws(ws)
+        check(lib().eclqr_plan_backward_error(self._h, C.c_void_p(wptr), out), "eclqr_plan_backward_error")
+        return np.frombuffer(out, dtype=np.float64)[:self.batch].copy()
+
     def scan_rows(self, ws: Optional[torch.Tensor], dual: bool = False) -> np.ndarray:
         """Rows of every feasible-domain-scan slot after the last solve (synchronises)."""
         n = C.c_int32()
