@@ -104,8 +104,9 @@ typedef struct {
   double accept_tol;      /* an instance whose componentwise KKT backward error after the first solve is
                            * <= accept_tol takes no refinement step; 1e-13 (0: always refine) */
   int32_t multipliers;    /* 1: compute lam and mu; 0: primal only */
-  int32_t refine;         /* most steps of iterative refinement per instance (0..4); 3.  With
-                           * multipliers, every instance takes at least one step when refine > 0 */
+  int32_t refine;         /* most steps of iterative refinement per instance (0..4); 3.  A refined
+                           * instance whose final KKT backward error exceeds dual_cons_tol reports
+                           * ECLQR_DUAL_FAILED */
   int32_t use_graph;      /* 1: replay the launch sequence as a captured hipGraph; 0 */
   int32_t reserved[5];
 } eclqr_options;
@@ -156,15 +157,18 @@ eclqr_status eclqr_plan_workspace_size(const eclqr_plan* plan, size_t* bytes);
 
 /* Forward solve (Algorithm 1 + Section VII).  Enqueued on `stream`; the first
  * call with a given workspace uploads the plan's tables into it (one H2D copy).
- * The workspace is reused by eclqr_backward, so keep it between the two. */
+ * The workspace keeps the factorizations of this solve: refinement steps and
+ * eclqr_backward replay them on new vectors, so keep it between the two. */
 eclqr_status eclqr_solve(eclqr_plan* plan, const eclqr_problem* prob, eclqr_solution* sol, void* ws,
                          size_t ws_bytes, void* stream);
 
 /* Gradients of a loss L(x, u) with respect to every problem field
  * (implicit differentiation of the KKT system; adjoint = the same constrained
  * LQR with linear costs dL/dx, dL/du and zero offsets).  Requires the forward
- * solve's outputs (x, u, lam, mu) and its workspace.  Valid where the
- * multipliers are unique (LICQ). */
+ * solve's outputs (x, u, lam, mu) and its workspace, untouched since that
+ * solve: the adjoint replays the factorizations the solve left there (no
+ * factorization is recomputed).  Valid where the multipliers are unique
+ * (LICQ). */
 eclqr_status eclqr_backward(eclqr_plan* plan, const eclqr_problem* prob, const eclqr_solution* sol,
                             const eclqr_cotangent* ct, eclqr_grads* grads, void* ws, size_t ws_bytes,
                             void* stream);
@@ -179,7 +183,9 @@ eclqr_status eclqr_kkt_residual(eclqr_plan* plan, const eclqr_problem* prob, con
 enum {
   ECLQR_K_VALIDATE = 0, ECLQR_K_BASE_RELATION, ECLQR_K_REL_COMPOSE, ECLQR_K_DOMAIN, ECLQR_K_ELIMINATE,
   ECLQR_K_RIC_COMBINE, ECLQR_K_GAINS, ECLQR_K_FWD_COMBINE, ECLQR_K_RECOVER, ECLQR_K_MULTIPLIER_IO,
-  ECLQR_K_REFINE_IO, ECLQR_K_OTHER, ECLQR_NUM_KERNEL_CLASSES
+  ECLQR_K_REFINE_IO, ECLQR_K_OTHER,
+  ECLQR_K_REPLAY, /* every kernel of a vector-only pass (recovery included) */
+  ECLQR_NUM_KERNEL_CLASSES
 };
 
 /* Profiler: when on, every later solve/backward records a HIP event pair
@@ -202,9 +208,10 @@ eclqr_status eclqr_plan_reduced_dims(const eclqr_plan* plan, const void* ws, int
  * batch entries).  Synchronises the device. */
 eclqr_status eclqr_plan_refine_steps(const eclqr_plan* plan, const void* ws, int32_t* steps);
 
-/* Componentwise KKT backward error of each instance after the first solve of
- * the last eclqr_solve in ws: max over rows of |residual| / sum |terms|
- * (host array of batch entries; 0 when refine = 0).  Synchronises. */
+/* Componentwise KKT backward error of each instance at the point returned by
+ * the last eclqr_solve (or eclqr_backward, for the adjoint) in ws: max over
+ * rows of |residual| / sum |terms| (host array of batch entries; 0 when
+ * refine = 0).  Synchronises. */
 eclqr_status eclqr_plan_backward_error(const eclqr_plan* plan, const void* ws, double* omega);
 
 /* Row counts of every slot of the feasible-domain scan after the last solve

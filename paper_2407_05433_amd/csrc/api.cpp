@@ -51,6 +51,10 @@ DevEngine dev_engine(const Engine& E, void* ws, size_t base) {
   d.arena = reinterpret_cast<double*>(b + E.o_arena);
   for (int k = 0; k < SCAN_COUNT; ++k) d.scan[k] = reinterpret_cast<double*>(b + E.o_scan[k]);
   d.resid = reinterpret_cast<double*>(b + E.o_resid);
+  d.rel_log_off = reinterpret_cast<const int64_t*>(b + E.o_rel_log_off);
+  d.ric_log_off = reinterpret_cast<const int64_t*>(b + E.o_ric_log_off);
+  d.rel_log = reinterpret_cast<double*>(b + E.o_rel_log);
+  d.ric_log = reinterpret_cast<double*>(b + E.o_ric_log);
   d.scratch = reinterpret_cast<double*>(b + E.o_scratch);
   d.scratch_per_block = E.scratch_per_block;
   d.S = E.S;
@@ -87,6 +91,12 @@ eclqr_status upload_engine(const Engine& E, void* ws, size_t base, hipStream_t s
   if (!E.tasks.empty())
     HIP_OK(hipMemcpyAsync(b + E.o_tasks, E.tasks.data(), sizeof(int32_t) * E.tasks.size(), hipMemcpyHostToDevice, s));
   HIP_OK(hipMemcpyAsync(b + E.o_sbase, E.sbase.data(), sizeof(int64_t) * E.B, hipMemcpyHostToDevice, s));
+  if (E.nslots > 0) {
+    HIP_OK(hipMemcpyAsync(b + E.o_rel_log_off, E.rel_log_off.data(), sizeof(int64_t) * E.nslots,
+                          hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(b + E.o_ric_log_off, E.ric_log_off.data(), sizeof(int64_t) * E.nslots,
+                          hipMemcpyHostToDevice, s));
+  }
   // the copies read pageable host memory: wait before the vectors go out of scope
   HIP_OK(hipStreamSynchronize(s));
   return ECLQR_SUCCESS;
@@ -180,6 +190,34 @@ eclqr_status run_engine(const Engine& E, const DevEngine& d, const Inputs& in, d
   return ECLQR_SUCCESS;
 }
 
+// The same pass on new vectors, replaying the factors the last full pass of
+// this engine logged in the workspace (no rank decisions, no outcome bits).
+eclqr_status run_engine_vec(const Engine& E, const DevEngine& d, const Inputs& in, double* x, double* u,
+                            hipStream_t s) {
+  { Timed tm(ECLQR_K_REPLAY, s); launch_base_relation_vec(d, in, s); }
+  for (int l = 0; l < 2 * E.D; ++l) {
+    if (E.lvl_count[l] == 0) continue;
+    Timed tm(ECLQR_K_REPLAY, s);
+    launch_rel_compose_vec(d, E.lvl_begin[l], E.lvl_count[l], s);
+  }
+  { Timed tm(ECLQR_K_REPLAY, s); launch_domain_vec(d, in, s); }
+  { Timed tm(ECLQR_K_REPLAY, s); launch_eliminate_vec(d, in, s); }
+  for (int l = 0; l < 2 * E.D; ++l) {
+    if (E.lvl_count[l] == 0) continue;
+    Timed tm(ECLQR_K_REPLAY, s);
+    launch_ric_combine_vec(d, E.lvl_begin[l], E.lvl_count[l], s);
+  }
+  { Timed tm(ECLQR_K_REPLAY, s); launch_gains_vec(d, s); }
+  for (int l = 0; l < 2 * E.D; ++l) {
+    if (E.lvl_count[l] == 0) continue;
+    Timed tm(ECLQR_K_REPLAY, s);
+    launch_fwd_combine_vec(d, E.lvl_begin[l], E.lvl_count[l], s);
+  }
+  { Timed tm(ECLQR_K_REPLAY, s); launch_recover(d, x, u, s); }
+  HIP_OK(hipGetLastError());
+  return ECLQR_SUCCESS;
+}
+
 Inputs inputs_of(const eclqr_problem* p) {
   Inputs in{};
   in.f[IN_Q] = p->Q;
@@ -251,93 +289,103 @@ Inputs dual_inputs(const Views& v) {
   return in;
 }
 
-// Multipliers at (x, u): build the reversed-time problem's offsets, solve it,
-// read lambda and mu off its solution.  The consistency tolerance only sets
-// outcome bits (the computed values do not depend on it); the outcome is merged
-// into `status` for the instances whose gate equals `report_gate` (every
-// instance when report_gate < 0, none when it is kGateDone).
+// Multipliers at (x, u): build the reversed-time problem's offsets, solve it
+// (full pass, or a replay of the factors of the last full pass when vec),
+// read lambda and mu off its solution.  The full pass records its outcome
+// bits in v.dstatus.
 eclqr_status multipliers(Plan& p, const Views& v, const Inputs& in, const double* x, const double* u, double* lam,
-                         double* mu, int32_t* status, hipStream_t s, int32_t report_gate) {
+                         double* mu, hipStream_t s, bool vec) {
   const Tols td{p.opt.rank_tol, p.opt.dual_cons_tol, 0};
   {
     Timed tm(ECLQR_K_MULTIPLIER_IO, s);
     launch_dual_vectors(v.P, in, x, u, v.D, v.dp, s);
-    launch_fill_i32(v.dstatus, 0, p.primal.B, s);
+    if (!vec) launch_fill_i32(v.dstatus, 0, p.primal.B, s);
   }
   Inputs din = dual_inputs(v);
   din.x0 = x;  // n_0 of the reversed problem is 0: any valid pointer
-  eclqr_status st = run_engine(p.dual, v.D, din, v.dx, v.du, v.dstatus, td, s);
+  eclqr_status st = vec ? run_engine_vec(p.dual, v.D, din, v.dx, v.du, s)
+                        : run_engine(p.dual, v.D, din, v.dx, v.du, v.dstatus, td, s);
   if (st != ECLQR_SUCCESS) return st;
   {
     Timed tm(ECLQR_K_MULTIPLIER_IO, s);
     launch_dual_extract(v.P, v.D, v.dx, v.du, lam, mu, v.dp, s);
-    if (report_gate != kGateDone)
-      launch_merge_status(status, v.dstatus, ECLQR_DUAL_FAILED, p.primal.B, report_gate < 0 ? nullptr : v.gate,
-                          report_gate, s);
   }
   return ECLQR_SUCCESS;
 }
 
-// Full solve of the problem `in`: primal, multipliers, optional refinement.
+constexpr int32_t kDualStructural = ECLQR_CAPACITY | ECLQR_NOT_CONVEX | ECLQR_INVALID_INPUT;
+
+// Full solve of the problem `in`: primal, multipliers, refinement.  With
+// replay, the first solve also replays the factors already in the workspace
+// (the adjoint of a solve of the same matrices).
+//   1. primal and reversed-time passes (full, or replayed);
+//   2. instances whose componentwise KKT backward error is <= accept_tol are
+//      final;
+//   3. refinement steps (replayed): correction problem from the KKT
+//      residuals, update, per-instance convergence test, multipliers at the
+//      updated point;
+//   4. the backward error of the returned point is recomputed; a refined
+//      instance whose error exceeds dual_cons_tol reports a multiplier failure.
 eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, double* u, double* lam, double* mu,
-                       int32_t* status, bool want_mult, hipStream_t s) {
+                       int32_t* status, bool want_mult, bool replay, hipStream_t s) {
   const Tols tp{p.opt.rank_tol, p.opt.cons_tol, 1};
+  const int32_t B = p.primal.B;
   {
     Timed tm(ECLQR_K_REFINE_IO, s);
-    launch_fill_i32(v.gate, kGateActive, p.primal.B, s);
-    launch_fill_i32(v.rsteps, 0, p.primal.B, s);
-    launch_fill_u64(v.omega, 0ull, p.primal.B, s);
+    launch_fill_i32(v.gate, kGateActive, B, s);
+    launch_fill_i32(v.rsteps, 0, B, s);
+    launch_fill_u64(v.omega, 0ull, B, s);
   }
-  eclqr_status st = run_engine(p.primal, v.P, in, x, u, status, tp, s);
+  eclqr_status st = replay ? run_engine_vec(p.primal, v.P, in, x, u, s)
+                           : run_engine(p.primal, v.P, in, x, u, status, tp, s);
   if (st != ECLQR_SUCCESS) return st;
   if (!want_mult) return ECLQR_SUCCESS;
-  // Before refinement the stationarity system inherits the primal point's
-  // optimality error; that pass only feeds the correction problem and its
-  // outcome is not reported.
-  const int nref = p.opt.refine;
-  st = multipliers(p, v, in, x, u, lam, mu, status, s, nref > 0 ? kGateDone : -1);
+  if (replay) {
+    Timed tm(ECLQR_K_REFINE_IO, s);
+    launch_fill_i32(v.dstatus, 0, B, s);
+  }
+  st = multipliers(p, v, in, x, u, lam, mu, s, replay);
   if (st != ECLQR_SUCCESS) return st;
-  if (nref == 0) return ECLQR_SUCCESS;
-  // An instance whose first solve is already backward stable (componentwise
-  // KKT backward error <= accept_tol, multipliers found) is final as it is.
+  const int nref = p.opt.refine;
+  if (nref == 0) {
+    Timed tm(ECLQR_K_REFINE_IO, s);
+    launch_merge_status(status, v.dstatus, ECLQR_DUAL_FAILED, B, nullptr, 0, s);
+    return ECLQR_SUCCESS;
+  }
   {
     Timed tm(ECLQR_K_REFINE_IO, s);
+    launch_merge_dual_bits(status, v.dstatus, ECLQR_DUAL_FAILED, kDualStructural, B, s);
     launch_backward_error(v.P, in, x, u, lam, mu, v.omega, s);
-    launch_accept(v.omega, v.dstatus, p.opt.accept_tol, v.gate, p.primal.B, s);
+    launch_accept(v.omega, v.dstatus, p.opt.accept_tol, v.gate, B, s);
   }
-  // Each step: correction problem (same matrices, residuals as data), update,
-  // per-instance convergence test, multipliers at the updated point.  An
-  // instance whose correction is small is final after this step and skipped
-  // by every later step.
+  Inputs cin = in;
+  cin.f[IN_q] = v.cp.q;
+  cin.f[IN_r] = v.cp.r;
+  cin.f[IN_c] = v.cp.c;
+  cin.f[IN_g] = v.cp.g;
+  cin.x0 = v.cp.x0;
   for (int it = 0; it < nref; ++it) {
     {
       Timed tm(ECLQR_K_REFINE_IO, s);
-      launch_gate_advance(v.gate, p.primal.B, s);
-    }
-    {
-      Timed tm(ECLQR_K_REFINE_IO, s);
+      launch_gate_advance(v.gate, B, s);
       launch_correction(v.P, in, x, u, lam, mu, v.cp, s);
     }
-    Inputs cin = in;
-    cin.f[IN_q] = v.cp.q;
-    cin.f[IN_r] = v.cp.r;
-    cin.f[IN_c] = v.cp.c;
-    cin.f[IN_g] = v.cp.g;
-    cin.x0 = v.cp.x0;
-    const Tols tc{p.opt.rank_tol, p.opt.cons_tol, 0};
-    st = run_engine(p.primal, v.P, cin, v.cx, v.cu, status, tc, s);
+    st = run_engine_vec(p.primal, v.P, cin, v.cx, v.cu, s);
     if (st != ECLQR_SUCCESS) return st;
     {
       Timed tm(ECLQR_K_REFINE_IO, s);
       launch_refine_update(v.P, x, u, v.cx, v.cu, v.rnorm, s);
       launch_refine_decide(v.P, v.psbase, v.rnorm, p.opt.refine_tol, it + 1 == nref, v.gate, v.rsteps, s);
     }
-    st = multipliers(p, v, in, x, u, lam, mu, status, s, kGateFinal);
+    st = multipliers(p, v, in, x, u, lam, mu, s, true);
     if (st != ECLQR_SUCCESS) return st;
   }
   {
     Timed tm(ECLQR_K_REFINE_IO, s);
-    launch_fill_i32(v.gate, kGateActive, p.primal.B, s);  // later launches on this workspace run every instance
+    launch_fill_i32(v.gate, kGateActive, B, s);  // later launches on this workspace run every instance
+    launch_fill_u64(v.omega, 0ull, B, s);
+    launch_backward_error(v.P, in, x, u, lam, mu, v.omega, s);
+    launch_flag_unconverged(v.omega, v.rsteps, p.opt.dual_cons_tol, status, ECLQR_DUAL_FAILED, B, s);
   }
   return ECLQR_SUCCESS;
 }
@@ -465,7 +513,7 @@ eclqr_status eclqr_solve(eclqr_plan* plan, const eclqr_problem* prob, eclqr_solu
   launch_fill_i32(sol->status, 0, E.B, s);
   Inputs in = inputs_of(prob);
   if (want) launch_dual_matrices(v.P, in, v.D, v.dp, s);
-  st = solve_all(p, v, in, sol->x, sol->u, sol->lam, sol->mu, sol->status, want, s);
+  st = solve_all(p, v, in, sol->x, sol->u, sol->lam, sol->mu, sol->status, want, false, s);
   if (st != ECLQR_SUCCESS) return st;
   launch_finalize(v.P, sol->status, sol->x, sol->u, want ? sol->lam : nullptr, want ? sol->mu : nullptr, s);
   HIP_OK(hipGetLastError());
@@ -501,12 +549,8 @@ eclqr_status eclqr_backward(eclqr_plan* plan, const eclqr_problem* prob, const e
   double* am = at<double>(ws, p.o_cmu);
   int32_t* astatus = at<int32_t>(ws, p.o_flag);
   launch_fill_i32(astatus, 0, E.B, s);
-  // the adjoint is solved without refinement
-  const int keep_refine = p.opt.refine;
-  p.opt.refine = 0;
-  launch_dual_matrices(v.P, in, v.D, v.dp, s);
-  st = solve_all(p, v, adj, ax, au, al, am, astatus, true, s);
-  p.opt.refine = keep_refine;
+  // same matrices as the forward solve: every pass replays its factors
+  st = solve_all(p, v, adj, ax, au, al, am, astatus, true, true, s);
   launch_merge_status(sol->status, astatus, ECLQR_DUAL_FAILED, E.B, nullptr, 0, s);
   if (st != ECLQR_SUCCESS) return st;
   GradPtrs g{};
@@ -561,7 +605,7 @@ eclqr_status eclqr_plan_profile(eclqr_plan* plan, double* ms, int64_t* launches,
 const char* eclqr_kernel_class_name(int32_t k) {
   static const char* names[ECLQR_NUM_KERNEL_CLASSES] = {
       "validate", "base_relation", "rel_compose", "domain", "eliminate", "ric_combine",
-      "gains", "fwd_combine", "recover", "multiplier_io", "refine_io", "other"};
+      "gains", "fwd_combine", "recover", "multiplier_io", "refine_io", "other", "replay"};
   return (k >= 0 && k < ECLQR_NUM_KERNEL_CLASSES) ? names[k] : "unknown";
 }
 

@@ -35,12 +35,16 @@ struct StageInfo {
 };
 
 // Stage arena: everything the stage-parallel kernels produce, sized by the
-// stage's own (n, n', m) -- reduced dims are at most these.
+// stage's own (n, n', m, k) -- reduced dims are at most these.  The last
+// block keeps the factors that a vector-only pass reuses: row scales,
+// pivot order, Q1 and R11 of the QR of Gamma^T, the Cholesky factors of
+// R-bar and of H_uu.
 struct Arena {
-  int64_t T, t, Y, Z, y, Ab, Bb, cb, Qb, Mb, Rb, qb, rb, K, kk, v, kap, size;
+  int64_t T, t, Y, Z, y, Ab, Bb, cb, Qb, Mb, Rb, qb, rb, K, kk, v, kap;
+  int64_t rsc, prm, Q1, R11, Lc, Hc, size;
 };
 
-ECLQR_HD inline Arena arena_layout(int n, int np, int m) {
+ECLQR_HD inline Arena arena_layout(int n, int np, int m, int k) {
   Arena a;
   int64_t o = 0;
   a.T = o; o += (int64_t)n * n;
@@ -60,9 +64,43 @@ ECLQR_HD inline Arena arena_layout(int n, int np, int m) {
   a.kk = o; o += m;
   a.v = o; o += m;
   a.kap = o; o += 1;
+  a.rsc = o; o += k + np;
+  a.prm = o; o += m;
+  a.Q1 = o; o += (int64_t)m * m;
+  a.R11 = o; o += (int64_t)m * m;
+  a.Lc = o; o += (int64_t)m * m;
+  a.Hc = o; o += (int64_t)m * m;
   a.size = (o + 3) & ~int64_t(3);  // 32-byte multiple
   return a;
 }
+
+// Log of a relation factorization (base relation or composition), replayed on
+// new offsets by the vector-only pass.  P = row capacity of the stacked
+// system, R = most Householder steps (min(eliminated dim, P)), C = row
+// capacity of the result.  Layout: header (p, rho, rr) | row scales (P) |
+// tau (R) | reflectors (R columns of P) | one record per Gram-Schmidt step:
+// pivot row, 1/norm, re-orthogonalisation coefficients (C), projection
+// coefficients by row (P).
+struct RelLog {
+  int64_t hdr, scale, tau, V, gs, step, size;
+};
+ECLQR_HD inline RelLog rel_log_layout(int P, int R, int C) {
+  RelLog l;
+  int64_t o = 0;
+  l.hdr = o; o += 4;
+  l.scale = o; o += P;
+  l.tau = o; o += R;
+  l.V = o; o += (int64_t)P * R;
+  l.gs = o;
+  l.step = 2 + (int64_t)C + P;
+  o += (int64_t)C * l.step;
+  l.size = (o + 3) & ~int64_t(3);
+  return l;
+}
+
+// Log of a value-function combine over a middle dim d: flag (1 factored,
+// 2 LU) | L or LU (d x d) | Rg (d x d) | pivots (d).
+ECLQR_HD inline int64_t ric_log_size(int d) { return (4 + 2 * (int64_t)d * d + d + 3) & ~int64_t(3); }
 
 // REL slot: rows x (na + nb + 1), row-major, coefficient columns of the left
 // endpoint, then of the right endpoint, then the offset.

@@ -1,7 +1,9 @@
 // Workgroup-cooperative dense FP64 routines for small row-major matrices.
 //
-// Every routine is called by all threads of the workgroup with identical
-// arguments and returns after a barrier.  Matrices live in LDS or global
+// A workgroup is exactly one wavefront (64 lanes): reductions and pivot
+// searches are register shuffles whose result every lane holds, and barriers
+// only order LDS traffic inside the wave.  Every routine is called by all
+// lanes with identical arguments and returns after a barrier.  Matrices live in LDS or global
 // memory (row-major, leading dimension ld); outputs never alias inputs unless
 // stated.  Threads own columns in the Householder routines (each thread
 // updates whole columns, the reflector is broadcast from LDS), which keeps
@@ -19,18 +21,31 @@ namespace eclqr {
 
 __device__ __forceinline__ void wg_sync() { __syncthreads(); }
 
-// Maximum of one value per thread over the workgroup; buf holds blockDim.x doubles.
-__device__ inline double wg_reduce_max(double v, double* buf) {
-  buf[ECLQR_TID] = v;
-  wg_sync();
-  for (int w = ECLQR_NT / 2; w > 0; w >>= 1) {
-    if (ECLQR_TID < w) buf[ECLQR_TID] = fmax(buf[ECLQR_TID], buf[ECLQR_TID + w]);
-    wg_sync();
-  }
-  const double r = buf[0];
-  wg_sync();
-  return r;
+// Butterfly reductions over the 64 lanes; every lane ends with the same bits
+// (each combination step adds the same two partials in either order).
+__device__ __forceinline__ double wave_max(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
 }
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+// Largest value and its index over the lanes (idx < 0: lane has no
+// candidate); the lowest index wins ties, as in an ascending serial scan.
+__device__ __forceinline__ void wave_argmax(double& v, int& idx) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(v, off, 64);
+    const int oi = __shfl_xor(idx, off, 64);
+    if (oi >= 0 && (idx < 0 || ov > v || (ov == v && oi < idx))) {
+      v = ov;
+      idx = oi;
+    }
+  }
+}
+
+// Maximum of one value per lane (buf unused, kept for call sites).
+__device__ inline double wg_reduce_max(double v, double* /*buf*/) { return wave_max(v); }
 
 // C(MxN) = alpha * op(A) * op(B) + beta * C.  op(A) is MxK, op(B) is KxN.
 // beta == 0 never reads C.
@@ -131,50 +146,40 @@ struct QRScratch {
 // implicit) and tau[j] its scalar.  Returns the numerical rank.
 __device__ inline int wg_qr_colpiv(double* W, int ld, int p, int c, int c0, int cp, double thr, double* tau,
                                    QRScratch sc) {
-  double* norms = sc.d;
-  double* sh = sc.d + cp;  // sh[0] stop flag, sh[1] pivot, sh[2] ref, sh[3] beta, sh[4] tau, sh[5] scale
   for (int j = ECLQR_TID; j < cp; j += ECLQR_NT) sc.perm[j] = j;
   wg_sync();
   const int steps = (p < cp) ? p : cp;
   int r = 0;
+  double ref = 1.0;
   for (int j = 0; j < steps; ++j) {
+    double bv = 0.0;
+    int best = -1;
     for (int col = j + ECLQR_TID; col < cp; col += ECLQR_NT) {
       double s = 0.0;
       for (int row = j; row < p; ++row) {
         const double v = W[row * ld + c0 + col];
         s = fma(v, v, s);
       }
-      norms[col] = s;
-    }
-    wg_sync();
-    if (ECLQR_TID == 0) {
-      int best = j;
-      double bv = norms[j];
-      for (int col = j + 1; col < cp; ++col)
-        if (norms[col] > bv) {
-          bv = norms[col];
-          best = col;
-        }
-      const double nrm = sqrt(bv);
-      if (j == 0) sh[2] = fmax(1.0, nrm);
-      sh[0] = (nrm <= thr * sh[2]) ? 1.0 : 0.0;
-      sh[1] = (double)best;
-      if (sh[0] == 0.0) {
-        const int pc = best;
-        // swap the pivot column into place (column entries handled below)
-        const int tp = sc.perm[j];
-        sc.perm[j] = sc.perm[pc];
-        sc.perm[pc] = tp;
-        const double x0 = (pc == j) ? W[j * ld + c0 + j] : W[j * ld + c0 + pc];
-        const double beta = -copysign(nrm, x0);
-        sh[3] = beta;
-        sh[4] = (beta - x0) / beta;
-        sh[5] = 1.0 / (x0 - beta);
+      if (best < 0 || s > bv) {
+        bv = s;
+        best = col;
       }
     }
+    wave_argmax(bv, best);
+    const double nrm = sqrt(bv);
+    if (j == 0) ref = fmax(1.0, nrm);
+    if (nrm <= thr * ref) break;
+    const int pc = best;
+    const double x0 = W[j * ld + c0 + pc];
+    const double beta = -copysign(nrm, x0);
+    const double tj = (beta - x0) / beta;
+    const double scale = 1.0 / (x0 - beta);
     wg_sync();
-    if (sh[0] != 0.0) break;
-    const int pc = (int)sh[1];
+    if (ECLQR_TID == 0) {
+      const int tp = sc.perm[j];
+      sc.perm[j] = sc.perm[pc];
+      sc.perm[pc] = tp;
+    }
     if (pc != j) {
       for (int row = ECLQR_TID; row < p; row += ECLQR_NT) {
         const double a = W[row * ld + c0 + j];
@@ -183,8 +188,6 @@ __device__ inline int wg_qr_colpiv(double* W, int ld, int p, int c, int c0, int 
       }
       wg_sync();
     }
-    const double scale = sh[5];
-    const double tj = sh[4];
     for (int row = j + 1 + ECLQR_TID; row < p; row += ECLQR_NT) W[row * ld + c0 + j] *= scale;
     if (ECLQR_TID == 0) tau[j] = tj;
     wg_sync();
@@ -198,11 +201,23 @@ __device__ inline int wg_qr_colpiv(double* W, int ld, int p, int c, int c0, int 
       for (int row = j + 1; row < p; ++row) W[row * ld + col] = fma(-w, W[row * ld + c0 + j], W[row * ld + col]);
     }
     wg_sync();
-    if (ECLQR_TID == 0) W[j * ld + c0 + j] = sh[3];
+    if (ECLQR_TID == 0) W[j * ld + c0 + j] = beta;
     wg_sync();
     r = j + 1;
   }
   return r;
+}
+
+// Copy the r reflectors left by wg_qr_colpiv (rows below the diagonal of the
+// pivot columns [c0, c0 + r)) and their scalars to a log: V[j * P + row].
+__device__ inline void wg_log_reflectors(const double* W, int ld, int p, int c0, int r, const double* tau, double* V,
+                                         int P, double* tlog) {
+  for (int idx = ECLQR_TID; idx < r * p; idx += ECLQR_NT) {
+    const int j = idx / p, row = idx - (idx / p) * p;
+    V[(int64_t)j * P + row] = (row > j) ? W[row * ld + c0 + j] : 0.0;
+  }
+  for (int j = ECLQR_TID; j < r; j += ECLQR_NT) tlog[j] = tau[j];
+  wg_sync();
 }
 
 // Apply Q = H_0 H_1 ... H_{r-1} (reflectors stored by wg_qr_colpiv in the
@@ -230,45 +245,38 @@ __device__ inline void wg_apply_q(const double* W, int ld, int p, int c0, int r,
 // rows [r0, r0 + rank).  Rows whose coefficient norm falls to
 // <= thr * max(1, first norm) are dependent; any of them with
 // |offset| > cons_thr makes the system inconsistent (*bad = 1).
+// When glog is given, every step is recorded for replay on a new offset
+// column: glog[s * gstep + 0] = pivot row, [1] = 1/norm, [2 + l] = the
+// re-orthogonalisation coefficient of chosen row l, [2 + gcap + row] = the
+// projection coefficient of each later row (steps s < gcap only).
 __device__ inline int wg_row_basis(double* W, int ld, int r0, int p, int k0, int kc, double thr, double cons_thr,
-                                   int* bad, double* scr /* >= 2*(p - r0) + 8 + 64 */) {
+                                   int* bad, double* scr /* >= 2*(p - r0) + 8 + 64 */, double* glog = nullptr,
+                                   int64_t gstep = 0, int gcap = 0) {
   const int rows = p - r0;
-  double* nrm = scr;           // rows
-  double* dots = scr + rows;   // max(rows, 64)
-  double* sh = dots + (rows > 64 ? rows : 64);
-  if (ECLQR_TID == 0) {
-    sh[0] = 0.0;
-    sh[4] = 0.0;
-  }
-  wg_sync();
+  double* dots = scr;  // >= rows
   int sel = 0;
+  double ref = 1.0;
   while (sel < rows) {
     const int base = r0 + sel;
+    double bv = 0.0;
+    int best = -1;
     for (int rr = base + ECLQR_TID; rr < p; rr += ECLQR_NT) {
       double s = 0.0;
       for (int cc = 0; cc < kc; ++cc) {
         const double v = W[rr * ld + k0 + cc];
         s = fma(v, v, s);
       }
-      nrm[rr - r0] = s;
+      if (best < 0 || s > bv) {
+        bv = s;
+        best = rr;
+      }
     }
-    wg_sync();
-    if (ECLQR_TID == 0) {
-      int best = base;
-      double bv = nrm[sel];
-      for (int rr = base + 1; rr < p; ++rr)
-        if (nrm[rr - r0] > bv) {
-          bv = nrm[rr - r0];
-          best = rr;
-        }
-      const double nv = sqrt(bv);
-      if (sel == 0) sh[2] = fmax(1.0, nv);
-      sh[1] = (double)best;
-      sh[3] = (nv <= thr * sh[2]) ? 1.0 : 0.0;
-    }
-    wg_sync();
-    if (sh[3] != 0.0) break;
-    const int best = (int)sh[1];
+    wave_argmax(bv, best);
+    const double nv = sqrt(bv);
+    if (sel == 0) ref = fmax(1.0, nv);
+    if (nv <= thr * ref) break;
+    double* rec = (glog && sel < gcap) ? glog + (int64_t)sel * gstep : nullptr;
+    if (rec && ECLQR_TID == 0) rec[0] = (double)best;
     if (best != base) {
       for (int cc = ECLQR_TID; cc <= kc; cc += ECLQR_NT) {
         const double a = W[base * ld + k0 + cc];
@@ -283,6 +291,7 @@ __device__ inline int wg_row_basis(double* W, int ld, int r0, int p, int k0, int
         double d = 0.0;
         for (int cc = 0; cc < kc; ++cc) d = fma(W[(r0 + l) * ld + k0 + cc], W[base * ld + k0 + cc], d);
         dots[l] = d;
+        if (rec) rec[2 + l] = d;
       }
       wg_sync();
       for (int cc = ECLQR_TID; cc <= kc; cc += ECLQR_NT) {
@@ -292,14 +301,12 @@ __device__ inline int wg_row_basis(double* W, int ld, int r0, int p, int k0, int
       }
       wg_sync();
     }
-    // normalise
-    if (ECLQR_TID == 0) {
-      double s = 0.0;
-      for (int cc = 0; cc < kc; ++cc) s = fma(W[base * ld + k0 + cc], W[base * ld + k0 + cc], s);
-      sh[5] = 1.0 / sqrt(s);
-    }
+    // normalise (offset included)
+    double s = 0.0;
+    for (int cc = ECLQR_TID; cc < kc; cc += ECLQR_NT) s = fma(W[base * ld + k0 + cc], W[base * ld + k0 + cc], s);
+    const double inv = 1.0 / sqrt(wave_sum(s));
+    if (rec && ECLQR_TID == 0) rec[1] = inv;
     wg_sync();
-    const double inv = sh[5];
     for (int cc = ECLQR_TID; cc <= kc; cc += ECLQR_NT) W[base * ld + k0 + cc] *= inv;
     wg_sync();
     // project the pivot row out of the remaining rows
@@ -307,16 +314,16 @@ __device__ inline int wg_row_basis(double* W, int ld, int r0, int p, int k0, int
       double d = 0.0;
       for (int cc = 0; cc < kc; ++cc) d = fma(W[rr * ld + k0 + cc], W[base * ld + k0 + cc], d);
       for (int cc = 0; cc <= kc; ++cc) W[rr * ld + k0 + cc] = fma(-d, W[base * ld + k0 + cc], W[rr * ld + k0 + cc]);
+      if (rec) rec[2 + gcap + rr] = d;
     }
     wg_sync();
     ++sel;
   }
   // consistency of the dependent rows
-  for (int rr = r0 + sel + ECLQR_TID; rr < p; rr += ECLQR_NT) {
-    if (fabs(W[rr * ld + k0 + kc]) > cons_thr) sh[4] = 1.0;
-  }
-  wg_sync();
-  *bad = (sh[4] != 0.0) ? 1 : 0;
+  double any = 0.0;
+  for (int rr = r0 + sel + ECLQR_TID; rr < p; rr += ECLQR_NT)
+    if (fabs(W[rr * ld + k0 + kc]) > cons_thr) any = 1.0;
+  *bad = (wave_max(any) != 0.0) ? 1 : 0;
   wg_sync();
   return sel;
 }
@@ -370,24 +377,25 @@ __device__ inline int wg_pchol(const double* S, int ld, int n, double tol, doubl
     used[i] = 0;
   }
   wg_sync();
+  (void)sh;
   double ref = 0.0;
-  for (int i = 0; i < n; ++i) ref = fmax(ref, rem[i]);
+  for (int i = ECLQR_TID; i < n; i += ECLQR_NT) ref = fmax(ref, rem[i]);
+  ref = wave_max(ref);
   int r = 0;
   for (int j = 0; j < n; ++j) {
-    if (ECLQR_TID == 0) {
-      int best = -1;
-      double bv = 0.0;
-      for (int i = 0; i < n; ++i)
-        if (!used[i] && (best < 0 || rem[i] > bv)) {
-          best = i;
-          bv = rem[i];
-        }
-      sh[0] = (best >= 0 && bv > tol * ref && bv > 0.0) ? (double)best : -1.0;
-      if (best >= 0 && sh[0] >= 0.0) used[best] = 1;
-    }
+    double bv = 0.0;
+    int best = -1;
+    for (int i = ECLQR_TID; i < n; i += ECLQR_NT)
+      if (!used[i] && (best < 0 || rem[i] > bv)) {
+        best = i;
+        bv = rem[i];
+      }
+    wave_argmax(bv, best);
+    if (!(best >= 0 && bv > tol * ref && bv > 0.0)) break;
+    const int p = best;
     wg_sync();
-    const int p = (int)sh[0];
-    if (p < 0) break;
+    if (ECLQR_TID == 0) used[p] = 1;
+    wg_sync();
     const double dp = sqrt(rem[p]);
     for (int i = ECLQR_TID; i < n; i += ECLQR_NT) {
       double v = 0.0;
@@ -449,22 +457,20 @@ __device__ inline void wg_trsm_upper_t(const double* W, int ld, int c0, double* 
 // LU factorisation with partial pivoting of an n x n matrix in place;
 // piv[i] = row swapped with row i at step i.
 __device__ inline void wg_lu(double* Mt, int ld, int n, int* piv, double* sh) {
+  (void)sh;
   for (int j = 0; j < n; ++j) {
-    if (ECLQR_TID == 0) {
-      int best = j;
-      double bv = fabs(Mt[j * ld + j]);
-      for (int i = j + 1; i < n; ++i) {
-        const double v = fabs(Mt[i * ld + j]);
-        if (v > bv) {
-          bv = v;
-          best = i;
-        }
+    double bv = 0.0;
+    int best = -1;
+    for (int i = j + ECLQR_TID; i < n; i += ECLQR_NT) {
+      const double v = fabs(Mt[i * ld + j]);
+      if (best < 0 || v > bv) {
+        bv = v;
+        best = i;
       }
-      piv[j] = best;
-      sh[0] = (double)best;
     }
+    wave_argmax(bv, best);
+    if (ECLQR_TID == 0) piv[j] = best;
     wg_sync();
-    const int best = (int)sh[0];
     if (best != j) {
       for (int c = ECLQR_TID; c < n; c += ECLQR_NT) {
         const double a = Mt[j * ld + c];

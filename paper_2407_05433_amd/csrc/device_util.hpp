@@ -8,7 +8,8 @@
 
 namespace eclqr {
 
-constexpr int kBlock = 256;
+// One wavefront per workgroup: the dense helpers reduce with lane shuffles.
+constexpr int kBlock = 64;
 
 __device__ __forceinline__ double* slot_ptr(const DevEngine& e, int kind, int slot) {
   return e.scan[kind] + e.slot_off[(int64_t)kind * e.nslots + slot];

@@ -411,6 +411,17 @@ __global__ void k_accept(const unsigned long long* omega, const int32_t* dstatus
       gate[i] = kGateFinal;
 }
 
+__global__ void k_merge_dual_bits(int32_t* status, const int32_t* other, int32_t bit, int32_t mask, int32_t B) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < B; i += gridDim.x * blockDim.x)
+    if (other[i] & mask) status[i] |= bit | ((other[i] & 0xff) << 8);
+}
+
+__global__ void k_flag_unconverged(const unsigned long long* omega, const int32_t* steps, double tol,
+                                   int32_t* status, int32_t bit, int32_t B) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < B; i += gridDim.x * blockDim.x)
+    if (steps[i] > 0 && !(__longlong_as_double((long long)omega[i]) <= tol)) status[i] |= bit;
+}
+
 __global__ void k_gate_advance(int32_t* gate, int32_t B) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < B; i += gridDim.x * blockDim.x)
     if (gate[i] == kGateFinal) gate[i] = kGateDone;
@@ -655,6 +666,14 @@ void launch_accept(const unsigned long long* omega, const int32_t* dstatus, doub
 }
 void launch_fill_u64(unsigned long long* y, unsigned long long v, int64_t n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n)), dim3(256), 0, s, y, v, n);
+}
+void launch_merge_dual_bits(int32_t* status, const int32_t* other, int32_t bit, int32_t mask, int32_t B,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_merge_dual_bits, dim3(grid_for(B)), dim3(256), 0, s, status, other, bit, mask, B);
+}
+void launch_flag_unconverged(const unsigned long long* omega, const int32_t* steps, double tol, int32_t* status,
+                             int32_t bit, int32_t B, hipStream_t s) {
+  hipLaunchKernelGGL(k_flag_unconverged, dim3(grid_for(B)), dim3(256), 0, s, omega, steps, tol, status, bit, B);
 }
 void launch_gate_advance(int32_t* gate, int32_t B, hipStream_t s) {
   hipLaunchKernelGGL(k_gate_advance, dim3(grid_for(B)), dim3(256), 0, s, gate, B);

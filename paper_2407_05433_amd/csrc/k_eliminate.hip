@@ -46,7 +46,7 @@ __global__ void __launch_bounds__(kBlock) k_eliminate(DevEngine e, Inputs in, To
     const StageInfo st = e.st[s];
     if (gated(e, st.inst)) continue;
     const int n = st.n, np = st.np, m = st.m, k = st.k;
-    const Arena ar = arena_layout(n, np, m);
+    const Arena ar = arena_layout(n, np, m, st.k);
     double* base = e.arena + st.ws;
     const int nb = e.nbar[s];
     const double* T = base + ar.T;
@@ -83,7 +83,7 @@ __global__ void __launch_bounds__(kBlock) k_eliminate(DevEngine e, Inputs in, To
     }
     const int inst = st.inst;
     const StageInfo& st1 = e.st[s + 1];
-    const Arena ar1 = arena_layout(st1.n, st1.np, st1.m);
+    const Arena ar1 = arena_layout(st1.n, st1.np, st1.m, st1.k);
     const double* T1 = e.arena + st1.ws + ar1.T;
     const double* t1 = e.arena + st1.ws + ar1.t;
     const int nb1 = e.nbar[s + 1];
@@ -159,6 +159,17 @@ __global__ void __launch_bounds__(kBlock) k_eliminate(DevEngine e, Inputs in, To
       X[idx] = (l < nb) ? Phi[row * nb + l] : gam[row];
     }
     wg_sync();
+    // factors kept for the vector-only pass: row scales, pivots, R11, Q1
+    for (int j = ECLQR_TID; j < q; j += ECLQR_NT) base[ar.rsc + j] = rsc[j];
+    for (int j = ECLQR_TID; j < rho; j += ECLQR_NT) base[ar.prm + j] = (double)perm[j];
+    for (int idx = ECLQR_TID; idx < rho * rho; idx += ECLQR_NT) {
+      const int i = idx / rho, j = idx % rho;
+      base[ar.R11 + idx] = (j >= i) ? Wq[i * q + j] : 0.0;
+    }
+    for (int idx = ECLQR_TID; idx < m * rho; idx += ECLQR_NT) {
+      const int i = idx / rho, j = idx % rho;
+      base[ar.Q1 + idx] = Qg[i * m + j];
+    }
     wg_trsm_upper_t(Wq, q, 0, X, nb + 1, rho, nb + 1);
     double* Y = base + ar.Y;
     double* Z = base + ar.Z;
@@ -307,6 +318,7 @@ __global__ void __launch_bounds__(kBlock) k_eliminate(DevEngine e, Inputs in, To
       wg_sync();
       continue;
     }
+    wg_copy(base + ar.Lc, mb, Lc, mb, mb, mb);
     wg_copy_t(Wt, nb1, Bb, mb, nb1, mb);  // Wt = Bb^T  (mb x nb1)
     wg_copy_t(V, nb, Mb, mb, nb, mb);     // V = Mb^T  (mb x nb)
     for (int i = ECLQR_TID; i < mb; i += ECLQR_NT) w2[i] = rb[i];

@@ -33,7 +33,7 @@ namespace {
 __device__ void combine_lu(const double* A1, const double* b1, const double* C1, const double* et1, const double* J1,
                            const double* A2, const double* b2, const double* C2, const double* et2, const double* J2,
                            double* Eo, const RicLayout& lo, int ds, int dm, int de, bool binary, double* pool,
-                           int* piv, double* sh) {
+                           int* piv, double* sh, double* rlog) {
   double* Mt = pool;                                      // dm x dm
   double* X = Mt + rup4((int64_t)dm * dm);                // dm x (ds + 1 + dm)
   double* Yv = X + rup4((int64_t)dm * (ds + 1 + dm));     // dm x (dm + 1)
@@ -44,6 +44,10 @@ __device__ void combine_lu(const double* A1, const double* b1, const double* C1,
   for (int i = ECLQR_TID; i < dm; i += ECLQR_NT) Mt[i * dm + i] += 1.0;
   wg_sync();
   wg_lu(Mt, dm, dm, piv, sh);
+  // log for the vector-only pass: flag 2, LU factors, pivots
+  for (int idx = ECLQR_TID; idx < dm * dm; idx += ECLQR_NT) rlog[4 + idx] = Mt[idx];
+  for (int i = ECLQR_TID; i < dm; i += ECLQR_NT) rlog[4 + 2 * dm * dm + i] = (double)piv[i];
+  if (ECLQR_TID == 0) rlog[0] = 2.0;
   for (int idx = ECLQR_TID; idx < dm * ly; idx += ECLQR_NT) {
     const int i = idx / ly, j = idx % ly;
     if (j < dm) {
@@ -102,7 +106,7 @@ __device__ void combine_lu(const double* A1, const double* b1, const double* C1,
 __device__ bool combine_factored(const double* A1, const double* b1, const double* C1, const double* et1,
                                  const double* J1, const double* A2, const double* b2, const double* C2,
                                  const double* et2, const double* J2, double* Eo, const RicLayout& lo, int ds, int dm,
-                                 int de, bool binary, double* pool, int* used, double* sh) {
+                                 int de, bool binary, double* pool, int* used, double* sh, double* rlog) {
   const int64_t dd = rup4((int64_t)dm * dm);
   double* Lj = pool;                          // dm x dm   L (J2 = L L')
   double* Gm = Lj + dd;                       // dm x dm   G, then Rg
@@ -128,6 +132,12 @@ __device__ bool combine_factored(const double* A1, const double* b1, const doubl
   wg_sync();
   wg_symmetrize(Gm, dm, dm);
   if (wg_cholesky(Gm, dm, dm, sh)) return false;
+  // log for the vector-only pass: flag 1, L, Rg
+  for (int idx = ECLQR_TID; idx < dm * dm; idx += ECLQR_NT) {
+    rlog[4 + idx] = Lj[idx];
+    rlog[4 + dm * dm + idx] = Gm[idx];
+  }
+  if (ECLQR_TID == 0) rlog[0] = 1.0;
   // xi = L^{-1} eta2 ; tv = d = G^{-1}(xi - L'b1) ; wv = L d
   for (int i = ECLQR_TID; i < dm; i += ECLQR_NT) xi[i] = et2[i];
   wg_sync();
@@ -219,8 +229,9 @@ __global__ void __launch_bounds__(kBlock) k_ric_combine(DevEngine e, int64_t fir
     const double *A2 = E2 + l2.A, *b2 = E2 + l2.b, *C2 = E2 + l2.C, *et2 = E2 + l2.eta, *J2 = E2 + l2.J;
     double* pool = pool_in_lds ? lds : block_scratch(e);
     const bool binary = se >= 0;
-    if (!combine_factored(A1, b1, C1, et1, J1, A2, b2, C2, et2, J2, Eo, lo, ds, dm, de, binary, pool, piv, sh))
-      combine_lu(A1, b1, C1, et1, J1, A2, b2, C2, et2, J2, Eo, lo, ds, dm, de, binary, pool, piv, sh);
+    double* rlog = e.ric_log + e.ric_log_off[o];
+    if (!combine_factored(A1, b1, C1, et1, J1, A2, b2, C2, et2, J2, Eo, lo, ds, dm, de, binary, pool, piv, sh, rlog))
+      combine_lu(A1, b1, C1, et1, J1, A2, b2, C2, et2, J2, Eo, lo, ds, dm, de, binary, pool, piv, sh, rlog);
     (void)status;
   }
 }
@@ -239,7 +250,7 @@ __global__ void __launch_bounds__(kBlock) k_gains(DevEngine e, int32_t* status, 
     const StageInfo st = e.st[s];
     if (st.terminal || gated(e, st.inst)) continue;
     const int n = st.n, np = st.np, m = st.m;
-    const Arena ar = arena_layout(n, np, m);
+    const Arena ar = arena_layout(n, np, m, st.k);
     double* base = e.arena + st.ws;
     const int nb = e.nbar[s], nb1 = e.nbar[s + 1], mb = e.mbar[s];
     const StageInfo& st1 = e.st[s + 1];
@@ -279,6 +290,7 @@ __global__ void __launch_bounds__(kBlock) k_gains(DevEngine e, int32_t* status, 
       wg_sync();
       continue;
     }
+    wg_copy(base + ar.Hc, mb, Huu, mb, mb, mb);
     // K = -Huu^{-1} Hux ; k = -Huu^{-1} hu
     wg_trsm_lower(Huu, mb, Hux, nb, mb, nb);
     wg_trsm_lower_t(Huu, mb, Hux, nb, mb, nb);
@@ -338,7 +350,7 @@ __global__ void __launch_bounds__(kBlock) k_recover(DevEngine e, double* x, doub
     const StageInfo st = e.st[s];
     if (gated(e, st.inst)) continue;
     const int n = st.n, np = st.np, m = st.m;
-    const Arena ar = arena_layout(n, np, m);
+    const Arena ar = arena_layout(n, np, m, st.k);
     const double* base = e.arena + st.ws;
     const int nb = e.nbar[s];
     const double* z = slot_ptr(e, SCAN_FWD, st.suf[SCAN_FWD]);

@@ -38,23 +38,20 @@ __global__ void __launch_bounds__(kBlock) k_validate(DevEngine e, Inputs in, int
 // Divide each row of W (columns [0, ncoef) coefficients, column ncoef the
 // offset) by the 2-norm of its coefficients (Section VIII item 1); returns
 // max(1, max |offset|) of the scaled rows.
-__device__ inline double scale_rows(double* W, int ld, int p, int ncoef, double* sh) {
+__device__ inline double scale_rows(double* W, int ld, int p, int ncoef, double* sh, double* scales) {
   for (int r = ECLQR_TID; r < p; r += ECLQR_NT) {
     double s = 0.0;
     for (int j = 0; j < ncoef; ++j) s = fma(W[r * ld + j], W[r * ld + j], s);
-    if (s > 0.0) {
-      const double inv = 1.0 / sqrt(s);
+    const double inv = (s > 0.0) ? 1.0 / sqrt(s) : 1.0;
+    if (s > 0.0)
       for (int j = 0; j <= ncoef; ++j) W[r * ld + j] *= inv;
-    }
+    scales[r] = inv;
   }
   wg_sync();
-  if (ECLQR_TID == 0) {
-    double mx = 1.0;
-    for (int r = 0; r < p; ++r) mx = fmax(mx, fabs(W[r * ld + ncoef]));
-    sh[0] = mx;
-  }
-  wg_sync();
-  return sh[0];
+  double mx = 1.0;
+  for (int r = ECLQR_TID; r < p; r += ECLQR_NT) mx = fmax(mx, fabs(W[r * ld + ncoef]));
+  (void)sh;
+  return wave_max(mx);
 }
 
 // ---------------------------------------------------------------------------
@@ -88,11 +85,17 @@ __global__ void __launch_bounds__(kBlock) k_base_relation(DevEngine e, Inputs in
         W[r * ld + j] = (j < n) ? E[r * n + j] : g[r];
       }
       wg_sync();
-      const double omax = scale_rows(W, ld, p, n, sh);
+      const int cap = e.slot_cap[slot];
+      const RelLog lg = rel_log_layout(p, 0, cap);
+      double* glog = e.rel_log + e.rel_log_off[slot];
+      const double omax = scale_rows(W, ld, p, n, sh, glog + lg.scale);
       int b = 0;
-      const int rr = wg_row_basis(W, ld, 0, p, 0, n, t.rank, t.cons * omax, &b, rbs);
+      const int rr = wg_row_basis(W, ld, 0, p, 0, n, t.rank, t.cons * omax, &b, rbs, glog + lg.gs, lg.step, cap);
       for (int idx = ECLQR_TID; idx < rr * ld; idx += ECLQR_NT) out[idx] = W[idx];
       if (ECLQR_TID == 0) {
+        glog[0] = p;
+        glog[1] = 0;
+        glog[2] = rr;
         e.slot_rows[slot] = rr;
         if (b) flag(status, st.inst, ECLQR_INFEASIBLE_SUFFIX);
       }
@@ -126,16 +129,24 @@ __global__ void __launch_bounds__(kBlock) k_base_relation(DevEngine e, Inputs in
       W[r * ld + j] = v;
     }
     wg_sync();
-    const double omax = scale_rows(W, ld, p, c - 1, sh);
+    const int cap = e.slot_cap[slot];
+    const RelLog lg = rel_log_layout(p, (m < p) ? m : p, cap);
+    double* glog = e.rel_log + e.rel_log_off[slot];
+    const double omax = scale_rows(W, ld, p, c - 1, sh, glog + lg.scale);
     const int rho = wg_qr_colpiv(W, ld, p, c, 0, m, t.rank, tau, QRScratch{qd, perm});
+    wg_log_reflectors(W, ld, p, 0, rho, tau, glog + lg.V, p, glog + lg.tau);
     int b = 0;
-    const int rr = wg_row_basis(W, ld, rho, p, m, n + np, t.rank, t.cons * omax, &b, rbs);
+    const int rr =
+        wg_row_basis(W, ld, rho, p, m, n + np, t.rank, t.cons * omax, &b, rbs, glog + lg.gs, lg.step, cap);
     const int lo = n + np + 1;
     for (int idx = ECLQR_TID; idx < rr * lo; idx += ECLQR_NT) {
       const int r = idx / lo, j = idx % lo;
       out[r * lo + j] = W[(rho + r) * ld + m + j];
     }
     if (ECLQR_TID == 0) {
+      glog[0] = p;
+      glog[1] = rho;
+      glog[2] = rr;
       e.slot_rows[slot] = rr;
       if (b) flag(status, st.inst, ECLQR_INFEASIBLE_SUFFIX);
     }
@@ -169,8 +180,15 @@ __global__ void __launch_bounds__(kBlock) k_rel_compose(DevEngine e, int64_t fir
     const int inst = e.st[sa].inst;
     const int ra = e.slot_rows[a], rb = e.slot_rows[bsl];
     const int p = ra + rb;
+    const int P = e.slot_cap[a] + e.slot_cap[bsl];
+    const int cap = e.slot_cap[o];
+    const RelLog lg = rel_log_layout(P, (nb < P) ? nb : P, cap);
+    double* glog = e.rel_log + e.rel_log_off[o];
     if (p > maxp || p > 2 * kMaxDim * 2) {
       if (ECLQR_TID == 0) {
+        glog[0] = 0;
+        glog[1] = 0;
+        glog[2] = 0;
         e.slot_rows[o] = 0;
         flag(status, inst, ECLQR_CAPACITY);
       }
@@ -200,19 +218,21 @@ __global__ void __launch_bounds__(kBlock) k_rel_compose(DevEngine e, int64_t fir
       W[r * ld + j] = v;
     }
     wg_sync();
-    if (ECLQR_TID == 0) {
-      double mx = 1.0;
-      for (int r = 0; r < p; ++r) mx = fmax(mx, fabs(W[r * ld + c - 1]));
-      sh[0] = mx;
-    }
-    wg_sync();
-    const double omax = sh[0];
+    double mx = 1.0;
+    for (int r = ECLQR_TID; r < p; r += ECLQR_NT) mx = fmax(mx, fabs(W[r * ld + c - 1]));
+    const double omax = wave_max(mx);
     const int rho = wg_qr_colpiv(W, ld, p, c, 0, nb, t.rank, tau, QRScratch{qd, perm});
+    wg_log_reflectors(W, ld, p, 0, rho, tau, glog + lg.V, P, glog + lg.tau);
     int bad = 0;
-    const int rr = wg_row_basis(W, ld, rho, p, nb, na + nc, t.rank, t.cons * omax, &bad, rbs);
-    const int cap = e.slot_cap[o];
+    const int rr =
+        wg_row_basis(W, ld, rho, p, nb, na + nc, t.rank, t.cons * omax, &bad, rbs, glog + lg.gs, lg.step, cap);
     double* out = slot_ptr(e, SCAN_REL, o);
     const int lo = na + nc + 1;
+    if (ECLQR_TID == 0) {
+      glog[0] = p;
+      glog[1] = rho;
+      glog[2] = (rr > cap) ? 0 : rr;
+    }
     if (rr > cap) {
       if (ECLQR_TID == 0) {
         e.slot_rows[o] = 0;
@@ -256,7 +276,7 @@ __global__ void __launch_bounds__(kBlock) k_domain(DevEngine e, Inputs in, Tols 
     const int r = e.slot_rows[suf];
     const double* H = slot_ptr(e, SCAN_REL, suf);  // r x (n + 1)
     const int nb = n - r;
-    const Arena ar = arena_layout(st.n, st.np, st.m);
+    const Arena ar = arena_layout(st.n, st.np, st.m, st.k);
     double* base = e.arena + st.ws;
     double* T = base + ar.T;
     double* tv = base + ar.t;

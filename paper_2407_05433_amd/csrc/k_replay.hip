@@ -1,0 +1,565 @@
+// Vector-only passes.  Every kernel of the method (Algorithm 1) produces
+// matrices that depend only on Q, R, M, A, B, E, F and vectors that also
+// depend on q, r, c, g, x0.  The refinement correction, the multipliers at a
+// refined point and the adjoint of the gradient change only the vectors, so
+// they replay the factorizations logged by the full pass:
+//   relations    -- row scales, Householder reflectors and Gram-Schmidt steps
+//                   applied to the new offset column (Lemma 1, eq.
+//                   (composition-matrix));
+//   domains      -- t = -H' h, z_0 = T'(x0 - t) (eqs. (state-param),
+//                   (reduced-initial));
+//   elimination  -- y from the QR of Gamma', c-bar, q-bar, r-bar and the
+//                   element vectors from the Cholesky factor of R-bar;
+//   value scan   -- b, eta of every combine from its logged factors;
+//   gains / forward scan / recovery -- vector parts only.
+// One wavefront per stage or task; vectors of at most 64 (states, inputs) or
+// 256 (stacked relation rows) entries live in LDS.
+#include "dense.hpp"
+#include "device_util.hpp"
+#include "eclqr.h"
+#include "scratch.hpp"
+
+namespace eclqr {
+
+namespace {
+
+constexpr int kMaxRows = 4 * kMaxDim;  // stacked rows of a composition (two relations of <= 2n rows)
+
+// Solve L y = x (L lower triangular, n x n, n <= 64) for a vector held one
+// entry per lane; returns the lane's entry of y.
+__device__ inline double lane_trsv_lower(const double* L, int ld, double v, int n) {
+  const int lane = ECLQR_TID;
+  for (int i = 0; i < n; ++i) {
+    const double xi = __shfl(v, i, 64) / L[i * ld + i];
+    if (lane > i && lane < n) v = fma(-L[lane * ld + i], xi, v);
+    if (lane == i) v = xi;
+  }
+  return v;
+}
+
+// Solve L' y = x (L lower triangular).
+__device__ inline double lane_trsv_lower_t(const double* L, int ld, double v, int n) {
+  const int lane = ECLQR_TID;
+  for (int i = n - 1; i >= 0; --i) {
+    const double yi = __shfl(v, i, 64) / L[i * ld + i];
+    if (lane < i) v = fma(-L[i * ld + lane], yi, v);
+    if (lane == i) v = yi;
+  }
+  return v;
+}
+
+// Solve U' y = x (U upper triangular).
+__device__ inline double lane_trsv_upper_t(const double* U, int ld, double v, int n) {
+  const int lane = ECLQR_TID;
+  for (int i = 0; i < n; ++i) {
+    const double xi = __shfl(v, i, 64) / U[i * ld + i];
+    if (lane > i && lane < n) v = fma(-U[i * ld + lane], xi, v);
+    if (lane == i) v = xi;
+  }
+  return v;
+}
+
+// Replay a relation log on the offset column o (LDS, p entries).  Returns the
+// rows eliminated (rho) and kept (rr); the new offsets are o[rho .. rho+rr).
+__device__ inline void rel_replay(double* o, const double* lg, const RelLog& L, int P, int R, int C, bool scaled,
+                                  int* rho_out, int* rr_out) {
+  int p = (int)lg[0], rho = (int)lg[1], rr = (int)lg[2];
+  p = (p < 0) ? 0 : ((p > P) ? P : p);
+  rho = (rho < 0) ? 0 : ((rho > R) ? R : rho);
+  rho = (rho > p) ? p : rho;
+  rr = (rr < 0) ? 0 : ((rr > C) ? C : rr);
+  rr = (rr > p - rho) ? p - rho : rr;
+  if (scaled) {
+    for (int r = ECLQR_TID; r < p; r += ECLQR_NT) o[r] *= lg[L.scale + r];
+    wg_sync();
+  }
+  for (int j = 0; j < rho; ++j) {
+    const double* v = lg + L.V + (int64_t)j * P;
+    double part = 0.0;
+    for (int row = j + 1 + ECLQR_TID; row < p; row += ECLQR_NT) part = fma(v[row], o[row], part);
+    const double w = (o[j] + wave_sum(part)) * lg[L.tau + j];
+    wg_sync();
+    if (ECLQR_TID == 0) o[j] -= w;
+    for (int row = j + 1 + ECLQR_TID; row < p; row += ECLQR_NT) o[row] = fma(-w, v[row], o[row]);
+    wg_sync();
+  }
+  for (int sel = 0; sel < rr; ++sel) {
+    const double* rec = lg + L.gs + (int64_t)sel * L.step;
+    const int base = rho + sel;
+    int best = (int)rec[0];
+    best = (best < base || best >= p) ? base : best;
+    if (best != base) {
+      if (ECLQR_TID == 0) {
+        const double a = o[base];
+        o[base] = o[best];
+        o[best] = a;
+      }
+      wg_sync();
+    }
+    double part = 0.0;
+    for (int l = ECLQR_TID; l < sel; l += ECLQR_NT) part = fma(rec[2 + l], o[rho + l], part);
+    const double nbv = (o[base] - wave_sum(part)) * rec[1];
+    wg_sync();
+    if (ECLQR_TID == 0) o[base] = nbv;
+    for (int row = base + 1 + ECLQR_TID; row < p; row += ECLQR_NT) o[row] = fma(-rec[2 + C + row], nbv, o[row]);
+    wg_sync();
+  }
+  *rho_out = rho;
+  *rr_out = rr;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_base_relation_vec(DevEngine e, Inputs in) {
+  __shared__ double o[kMaxRows];
+  for (int64_t s = blockIdx.x; s < e.S; s += gridDim.x) {
+    const StageInfo st = e.st[s];
+    if (gated(e, st.inst)) continue;
+    const int n = st.n, np = st.np, m = st.m, k = st.k;
+    const int slot = st.elem[SCAN_REL];
+    const int cap = e.slot_cap[slot];
+    const double* g = in.f[IN_g] + st.in[IN_g];
+    const int P = st.terminal ? k : np + k;
+    const int R = st.terminal ? 0 : ((m < P) ? m : P);
+    const RelLog L = rel_log_layout(P, R, cap);
+    const double* lg = e.rel_log + e.rel_log_off[slot];
+    if (st.terminal) {
+      for (int r = ECLQR_TID; r < k; r += ECLQR_NT) o[r] = g[r];
+    } else {
+      const double* cv = in.f[IN_c] + st.in[IN_c];
+      for (int r = ECLQR_TID; r < P; r += ECLQR_NT) o[r] = (r < np) ? cv[r] : g[r - np];
+    }
+    wg_sync();
+    int rho = 0, rr = 0;
+    rel_replay(o, lg, L, P, R, cap, true, &rho, &rr);
+    const int lo = st.terminal ? n + 1 : n + np + 1;
+    double* out = slot_ptr(e, SCAN_REL, slot);
+    for (int r = ECLQR_TID; r < rr; r += ECLQR_NT) out[r * lo + lo - 1] = o[rho + r];
+    wg_sync();
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_rel_compose_vec(DevEngine e, int64_t first, int64_t ntasks) {
+  __shared__ double o[kMaxRows];
+  for (int64_t ti = blockIdx.x; ti < ntasks; ti += gridDim.x) {
+    const int a = e.tasks[3 * (first + ti)];
+    const int bsl = e.tasks[3 * (first + ti) + 1];
+    const int oo = e.tasks[3 * (first + ti) + 2];
+    const int sa = slot_a(e, 0, a), sb = slot_b(e, 0, a), sc = slot_b(e, 0, bsl);
+    if (gated(e, e.st[sa].inst)) continue;
+    const int na = e.st[sa].n, nb = e.st[sb].n, nc = (sc >= 0) ? e.st[sc].n : 0;
+    const int ra = e.slot_rows[a], rb = e.slot_rows[bsl];
+    const int P = e.slot_cap[a] + e.slot_cap[bsl];
+    if (ra + rb > P || P > kMaxRows) continue;
+    const int cap = e.slot_cap[oo];
+    const RelLog L = rel_log_layout(P, (nb < P) ? nb : P, cap);
+    const double* lg = e.rel_log + e.rel_log_off[oo];
+    const double* Ls = slot_ptr(e, SCAN_REL, a);
+    const double* Rs = slot_ptr(e, SCAN_REL, bsl);
+    const int lda = na + nb + 1, ldb = nb + nc + 1;
+    for (int r = ECLQR_TID; r < ra + rb; r += ECLQR_NT)
+      o[r] = (r < ra) ? Ls[r * lda + na + nb] : Rs[(r - ra) * ldb + nb + nc];
+    wg_sync();
+    int rho = 0, rr = 0;
+    rel_replay(o, lg, L, P, (nb < P) ? nb : P, cap, false, &rho, &rr);
+    if (rr > e.slot_rows[oo]) rr = e.slot_rows[oo];
+    const int lo = na + nc + 1;
+    double* out = slot_ptr(e, SCAN_REL, oo);
+    for (int r = ECLQR_TID; r < rr; r += ECLQR_NT) out[r * lo + lo - 1] = o[rho + r];
+    wg_sync();
+  }
+}
+
+// t = -H' h; on stage 0, z_0 = T'(x0 - t).
+__global__ void __launch_bounds__(kBlock) k_domain_vec(DevEngine e, Inputs in) {
+  for (int64_t s = blockIdx.x; s < e.S; s += gridDim.x) {
+    const StageInfo st = e.st[s];
+    if (gated(e, st.inst)) continue;
+    const int n = st.n;
+    const int suf = st.suf[SCAN_REL];
+    const int r = e.slot_rows[suf];
+    const double* H = slot_ptr(e, SCAN_REL, suf);
+    const Arena ar = arena_layout(st.n, st.np, st.m, st.k);
+    double* base = e.arena + st.ws;
+    double* tv = base + ar.t;
+    for (int i = ECLQR_TID; i < n; i += ECLQR_NT) {
+      double v = 0.0;
+      for (int j = 0; j < r; ++j) v = fma(H[j * (n + 1) + i], H[j * (n + 1) + n], v);
+      tv[i] = -v;
+    }
+    wg_sync();
+    if (st.i == 0) {
+      const int nb = e.nbar[s];
+      const double* T = base + ar.T;
+      const double* x0 = in.x0 + st.x0;
+      double* z0 = slot_ptr(e, SCAN_FWD, st.suf[SCAN_FWD]);
+      for (int j = ECLQR_TID; j < nb; j += ECLQR_NT) {
+        double v = 0.0;
+        for (int i = 0; i < n; ++i) v = fma(T[i * nb + j], x0[i] - tv[i], v);
+        z0[j] = v;
+      }
+      wg_sync();
+    }
+  }
+}
+
+// Vector part of the stage elimination and of the value-function element.
+__global__ void __launch_bounds__(kBlock) k_eliminate_vec(DevEngine e, Inputs in) {
+  __shared__ double tvs[kMaxDim], gam[2 * kMaxDim], yv[kMaxDim], atc[kMaxDim], cvv[kMaxDim], wv[kMaxDim],
+      qt[kMaxDim], rz[kMaxDim], sv[kMaxDim];
+  for (int64_t s = blockIdx.x; s < e.S; s += gridDim.x) {
+    const StageInfo st = e.st[s];
+    if (gated(e, st.inst)) continue;
+    const int n = st.n, np = st.np, m = st.m, k = st.k;
+    const Arena ar = arena_layout(n, np, m, k);
+    double* base = e.arena + st.ws;
+    const int nb = e.nbar[s];
+    const double* T = base + ar.T;
+    const double* Q = in.f[IN_Q] + st.in[IN_Q];
+    const double* qv = in.f[IN_q] + st.in[IN_q];
+    double* ric = slot_ptr(e, SCAN_RIC, st.elem[SCAN_RIC]);
+    for (int i = ECLQR_TID; i < n; i += ECLQR_NT) tvs[i] = base[ar.t + i];
+    wg_sync();
+    // Q t + q
+    for (int i = ECLQR_TID; i < n; i += ECLQR_NT) {
+      double a = qv[i];
+      for (int j = 0; j < n; ++j) a = fma(Q[i * n + j], tvs[j], a);
+      qt[i] = a;
+    }
+    wg_sync();
+    double kap = 0.0;
+    for (int i = ECLQR_TID; i < n; i += ECLQR_NT) kap += tvs[i] * (0.5 * (qt[i] - qv[i]) + qv[i]);
+    if (st.terminal) {
+      const RicLayout rl = ric_layout(n, 0);
+      double* qb = base + ar.qb;
+      for (int i = ECLQR_TID; i < nb; i += ECLQR_NT) {
+        double a = 0.0;
+        for (int l = 0; l < n; ++l) a = fma(T[l * nb + i], qt[l], a);
+        qb[i] = a;
+        ric[rl.eta + i] = -a;
+      }
+      kap = wave_sum(kap);
+      if (ECLQR_TID == 0) base[ar.kap] = kap;
+      wg_sync();
+      continue;
+    }
+    const StageInfo& st1 = e.st[s + 1];
+    const Arena ar1 = arena_layout(st1.n, st1.np, st1.m, st1.k);
+    const double* T1 = e.arena + st1.ws + ar1.T;
+    const double* t1 = e.arena + st1.ws + ar1.t;
+    const int nb1 = e.nbar[s + 1];
+    const int suf1 = st1.suf[SCAN_REL];
+    const int r1 = e.slot_rows[suf1];
+    const double* H1 = slot_ptr(e, SCAN_REL, suf1);
+    const int ldh = np + 1;
+    const double* A = in.f[IN_A] + st.in[IN_A];
+    const double* B = in.f[IN_B] + st.in[IN_B];
+    const double* cv = in.f[IN_c] + st.in[IN_c];
+    const double* E = in.f[IN_E] + st.in[IN_E];
+    const double* g = in.f[IN_g] + st.in[IN_g];
+    const double* R = in.f[IN_R] + st.in[IN_R];
+    const double* Mm = in.f[IN_M] ? in.f[IN_M] + st.in[IN_M] : nullptr;
+    const double* rv = in.f[IN_r] + st.in[IN_r];
+    const int q = k + r1;
+    const int mb = e.mbar[s];
+    const int rho = m - mb;
+    // gamma = rows-scaled [E t + g; H'(A t + c) + h']
+    for (int i = ECLQR_TID; i < np; i += ECLQR_NT) {
+      double a = cv[i];
+      for (int j = 0; j < n; ++j) a = fma(A[i * n + j], tvs[j], a);
+      atc[i] = a;
+    }
+    wg_sync();
+    for (int j = ECLQR_TID; j < q; j += ECLQR_NT) {
+      double a;
+      if (j < k) {
+        a = g[j];
+        for (int l = 0; l < n; ++l) a = fma(E[j * n + l], tvs[l], a);
+      } else {
+        const int jj = j - k;
+        a = H1[jj * ldh + np];
+        for (int l = 0; l < np; ++l) a = fma(H1[jj * ldh + l], atc[l], a);
+      }
+      gam[j] = a * base[ar.rsc + j];
+    }
+    wg_sync();
+    // y = -Q1 R11^{-T} (P' gamma)_{1:rho}
+    double xv = 0.0;
+    if (ECLQR_TID < rho) {
+      int pj = (int)base[ar.prm + ECLQR_TID];
+      pj = (pj < 0 || pj >= q) ? 0 : pj;
+      xv = gam[pj];
+    }
+    xv = lane_trsv_upper_t(base + ar.R11, rho, xv, rho);
+    if (ECLQR_TID < rho) sv[ECLQR_TID] = xv;
+    wg_sync();
+    double* y = base + ar.y;
+    for (int i = ECLQR_TID; i < m; i += ECLQR_NT) {
+      double a = 0.0;
+      for (int j = 0; j < rho; ++j) a = fma(base[ar.Q1 + i * rho + j], sv[j], a);
+      y[i] = -a;
+      yv[i] = -a;
+    }
+    wg_sync();
+    // c-bar = T1'(A t + B y + c - t1)
+    for (int i = ECLQR_TID; i < np; i += ECLQR_NT) {
+      double a = atc[i] - t1[i];
+      for (int j = 0; j < m; ++j) a = fma(B[i * m + j], yv[j], a);
+      cvv[i] = a;
+    }
+    // rz = r + M' t ; w = rz + R y
+    for (int i = ECLQR_TID; i < m; i += ECLQR_NT) {
+      double a = rv[i];
+      if (Mm)
+        for (int j = 0; j < n; ++j) a = fma(Mm[j * m + i], tvs[j], a);
+      rz[i] = a;
+      double b = a;
+      for (int j = 0; j < m; ++j) b = fma(R[i * m + j], yv[j], b);
+      wv[i] = b;
+    }
+    for (int i = ECLQR_TID; i < m; i += ECLQR_NT) {
+      double a = 0.0;
+      for (int j = 0; j < m; ++j) a = fma(R[i * m + j], yv[j], a);
+      kap += yv[i] * (0.5 * a + rz[i]);
+    }
+    kap = wave_sum(kap);
+    // (Q t + q) + M y, reused for q-bar
+    if (Mm) {
+      wg_sync();
+      for (int i = ECLQR_TID; i < n; i += ECLQR_NT) {
+        double a = qt[i];
+        for (int j = 0; j < m; ++j) a = fma(Mm[i * m + j], yv[j], a);
+        qt[i] = a;
+      }
+    }
+    wg_sync();
+    double* cb = base + ar.cb;
+    double* qb = base + ar.qb;
+    double* rb = base + ar.rb;
+    const double* Y = base + ar.Y;
+    const double* Z = base + ar.Z;
+    for (int i = ECLQR_TID; i < nb1; i += ECLQR_NT) {
+      double a = 0.0;
+      for (int l = 0; l < np; ++l) a = fma(T1[l * nb1 + i], cvv[l], a);
+      cb[i] = a;
+    }
+    for (int i = ECLQR_TID; i < nb; i += ECLQR_NT) {
+      double a = 0.0;
+      for (int l = 0; l < n; ++l) a = fma(T[l * nb + i], qt[l], a);
+      for (int j = 0; j < m; ++j) a = fma(Y[j * nb + i], wv[j], a);
+      qb[i] = a;
+    }
+    double rbl = 0.0;
+    if (ECLQR_TID < mb) {
+      for (int j = 0; j < m; ++j) rbl = fma(Z[j * mb + ECLQR_TID], wv[j], rbl);
+      rb[ECLQR_TID] = rbl;
+    }
+    if (ECLQR_TID == 0) base[ar.kap] = kap;
+    // element: s = R-bar^{-1} r-bar, b_e = c-bar - B-bar s, eta_e = -(q-bar - M-bar s)
+    double sl = lane_trsv_lower(base + ar.Lc, mb, rbl, mb);
+    sl = lane_trsv_lower_t(base + ar.Lc, mb, sl, mb);
+    if (ECLQR_TID < mb) sv[ECLQR_TID] = sl;
+    wg_sync();
+    const RicLayout rl = ric_layout(n, np);
+    const double* Bb = base + ar.Bb;
+    const double* Mb = base + ar.Mb;
+    for (int i = ECLQR_TID; i < nb1; i += ECLQR_NT) {
+      double a = cb[i];
+      for (int j = 0; j < mb; ++j) a = fma(-Bb[i * mb + j], sv[j], a);
+      ric[rl.b + i] = a;
+    }
+    for (int i = ECLQR_TID; i < nb; i += ECLQR_NT) {
+      double a = qb[i];
+      for (int j = 0; j < mb; ++j) a = fma(-Mb[i * mb + j], sv[j], a);
+      ric[rl.eta + i] = -a;
+    }
+    wg_sync();
+  }
+}
+
+// b, eta of a value-function combine from its logged factors.
+__global__ void __launch_bounds__(kBlock) k_ric_combine_vec(DevEngine e, int64_t first, int64_t ntasks) {
+  __shared__ double v1[kMaxDim], v2[kMaxDim], v3[kMaxDim];
+  __shared__ int piv[kMaxDim];
+  for (int64_t ti = blockIdx.x; ti < ntasks; ti += gridDim.x) {
+    const int a = e.tasks[3 * (first + ti)];
+    const int bsl = e.tasks[3 * (first + ti) + 1];
+    const int o = e.tasks[3 * (first + ti) + 2];
+    const int sa = slot_a(e, 0, a), sm = slot_b(e, 0, a), se = slot_b(e, 0, bsl);
+    if (gated(e, e.st[sa].inst)) continue;
+    const int ds = e.nbar[sa], dm = e.nbar[sm], de = (se >= 0) ? e.nbar[se] : 0;
+    const int ns = e.st[sa].n, nm = e.st[sm].n, ne = (se >= 0) ? e.st[se].n : 0;
+    const RicLayout l1 = ric_layout(ns, nm), l2 = ric_layout(nm, ne), lo = ric_layout(ns, ne);
+    const double* E1 = slot_ptr(e, SCAN_RIC, a);
+    const double* E2 = slot_ptr(e, SCAN_RIC, bsl);
+    double* Eo = slot_ptr(e, SCAN_RIC, o);
+    const double *A1 = E1 + l1.A, *b1 = E1 + l1.b, *C1 = E1 + l1.C, *et1 = E1 + l1.eta;
+    const double *A2 = E2 + l2.A, *b2 = E2 + l2.b, *et2 = E2 + l2.eta, *J2 = E2 + l2.J;
+    const double* rlog = e.ric_log + e.ric_log_off[o];
+    const bool binary = se >= 0;
+    const bool factored = (dm > 0) && (rlog[0] == 1.0);
+    if (factored) {
+      const double* Lj = rlog + 4;
+      const double* Rg = rlog + 4 + (int64_t)dm * dm;
+      // xi = L^{-1} eta2 ; d = G^{-1}(xi - L'b1) ; eta = eta1 + A1' L d ; b = A2 L^{-T}(xi - d) + b2
+      double xi = (ECLQR_TID < dm) ? et2[ECLQR_TID] : 0.0;
+      xi = lane_trsv_lower(Lj, dm, xi, dm);
+      double tvv = xi;
+      if (ECLQR_TID < dm)
+        for (int l = ECLQR_TID; l < dm; ++l) tvv = fma(-Lj[l * dm + ECLQR_TID], b1[l], tvv);
+      tvv = lane_trsv_lower(Rg, dm, tvv, dm);
+      tvv = lane_trsv_lower_t(Rg, dm, tvv, dm);
+      if (ECLQR_TID < dm) v1[ECLQR_TID] = tvv;
+      wg_sync();
+      if (ECLQR_TID < dm) {
+        double w = 0.0;
+        for (int l = 0; l <= ECLQR_TID; ++l) w = fma(Lj[ECLQR_TID * dm + l], v1[l], w);
+        v2[ECLQR_TID] = w;
+      }
+      wg_sync();
+      for (int i = ECLQR_TID; i < ds; i += ECLQR_NT) {
+        double v = et1[i];
+        for (int l = 0; l < dm; ++l) v = fma(A1[l * ds + i], v2[l], v);
+        Eo[lo.eta + i] = v;
+      }
+      if (binary) {
+        double yl = lane_trsv_lower_t(Lj, dm, xi - tvv, dm);
+        if (ECLQR_TID < dm) v3[ECLQR_TID] = yl;
+        wg_sync();
+        for (int i = ECLQR_TID; i < de; i += ECLQR_NT) {
+          double v = b2[i];
+          for (int l = 0; l < dm; ++l) v = fma(A2[i * dm + l], v3[l], v);
+          Eo[lo.b + i] = v;
+        }
+      }
+      wg_sync();
+      continue;
+    }
+    // LU form: eta = A1' Minv'(eta2 - J2 b1) + eta1 ; b = A2 Minv (b1 + C1 eta2) + b2
+    const double* LU = rlog + 4;
+    for (int i = ECLQR_TID; i < dm; i += ECLQR_NT) {
+      piv[i] = (int)rlog[4 + 2 * (int64_t)dm * dm + i];
+      double v = et2[i];
+      for (int l = 0; l < dm; ++l) v = fma(-J2[i * dm + l], b1[l], v);
+      v1[i] = v;
+      double w = b1[i];
+      for (int l = 0; l < dm; ++l) w = fma(C1[i * dm + l], et2[l], w);
+      v3[i] = w;
+    }
+    wg_sync();
+    for (int i = ECLQR_TID; i < dm; i += ECLQR_NT) piv[i] = (piv[i] < i || piv[i] >= dm) ? i : piv[i];
+    wg_sync();
+    wg_lu_solve_t(LU, dm, dm, piv, v1, 1, 1);
+    for (int i = ECLQR_TID; i < ds; i += ECLQR_NT) {
+      double v = et1[i];
+      for (int l = 0; l < dm; ++l) v = fma(A1[l * ds + i], v1[l], v);
+      Eo[lo.eta + i] = v;
+    }
+    if (binary) {
+      wg_lu_solve(LU, dm, dm, piv, v3, 1, 1);
+      for (int i = ECLQR_TID; i < de; i += ECLQR_NT) {
+        double v = b2[i];
+        for (int l = 0; l < dm; ++l) v = fma(A2[i * dm + l], v3[l], v);
+        Eo[lo.b + i] = v;
+      }
+    }
+    wg_sync();
+  }
+}
+
+// k = -H_uu^{-1} h_u from the logged Cholesky factor; forward leaf vector.
+__global__ void __launch_bounds__(kBlock) k_gains_vec(DevEngine e) {
+  __shared__ double pc[kMaxDim], kv[kMaxDim];
+  for (int64_t s = blockIdx.x; s < e.S; s += gridDim.x) {
+    const StageInfo st = e.st[s];
+    if (st.terminal || gated(e, st.inst)) continue;
+    const int n = st.n, np = st.np, m = st.m;
+    const Arena ar = arena_layout(n, np, m, st.k);
+    double* base = e.arena + st.ws;
+    const int nb1 = e.nbar[s + 1], mb = e.mbar[s];
+    const StageInfo& st1 = e.st[s + 1];
+    const RicLayout l1 = ric_layout(st1.n, 0);
+    const double* P1 = slot_ptr(e, SCAN_RIC, st1.suf[SCAN_RIC]) + l1.J;
+    const double* et1 = slot_ptr(e, SCAN_RIC, st1.suf[SCAN_RIC]) + l1.eta;
+    const double *Bb = base + ar.Bb, *cb = base + ar.cb, *rb = base + ar.rb;
+    for (int i = ECLQR_TID; i < nb1; i += ECLQR_NT) {
+      double v = -et1[i];
+      for (int l = 0; l < nb1; ++l) v = fma(P1[i * nb1 + l], cb[l], v);
+      pc[i] = v;
+    }
+    wg_sync();
+    double hu = 0.0;
+    if (ECLQR_TID < mb) {
+      hu = rb[ECLQR_TID];
+      for (int l = 0; l < nb1; ++l) hu = fma(Bb[l * mb + ECLQR_TID], pc[l], hu);
+    }
+    hu = lane_trsv_lower(base + ar.Hc, mb, hu, mb);
+    hu = lane_trsv_lower_t(base + ar.Hc, mb, hu, mb);
+    if (ECLQR_TID < mb) {
+      kv[ECLQR_TID] = -hu;
+      base[ar.kk + ECLQR_TID] = -hu;
+    }
+    wg_sync();
+    double* fs = slot_ptr(e, SCAN_FWD, st.elem[SCAN_FWD]) + (int64_t)np * n;
+    for (int i = ECLQR_TID; i < nb1; i += ECLQR_NT) {
+      double v = cb[i];
+      for (int l = 0; l < mb; ++l) v = fma(Bb[i * mb + l], kv[l], v);
+      fs[i] = v;
+    }
+    wg_sync();
+  }
+}
+
+// f = F1 f2 + f1 (F = F1 F2 is unchanged).
+__global__ void __launch_bounds__(kBlock) k_fwd_combine_vec(DevEngine e, int64_t first, int64_t ntasks) {
+  for (int64_t ti = blockIdx.x; ti < ntasks; ti += gridDim.x) {
+    const int a = e.tasks[3 * (first + ti)];
+    const int bsl = e.tasks[3 * (first + ti) + 1];
+    const int o = e.tasks[3 * (first + ti) + 2];
+    const int so = slot_a(e, 1, a), smid = slot_b(e, 1, a), sin_ = slot_b(e, 1, bsl);
+    if (gated(e, e.st[so].inst)) continue;
+    const int dout = e.nbar[so], dmid = e.nbar[smid];
+    const int nout = e.st[so].n, nmid = e.st[smid].n, nin = (sin_ >= 0) ? e.st[sin_].n : 0;
+    const double* F1 = slot_ptr(e, SCAN_FWD, a);
+    const double* f1 = F1 + (int64_t)nout * nmid;
+    const double* F2 = slot_ptr(e, SCAN_FWD, bsl);
+    const double* f2 = F2 + (int64_t)nmid * nin;
+    double* Fo = slot_ptr(e, SCAN_FWD, o);
+    double* fo = Fo + (int64_t)nout * nin;
+    for (int i = ECLQR_TID; i < dout; i += ECLQR_NT) {
+      double v = f1[i];
+      for (int l = 0; l < dmid; ++l) v = fma(F1[i * dmid + l], f2[l], v);
+      fo[i] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+static unsigned grid_of(const DevEngine& e, int64_t ntasks) {
+  return (unsigned)((ntasks < e.nblocks) ? ntasks : e.nblocks);
+}
+
+void launch_base_relation_vec(const DevEngine& e, const Inputs& in, hipStream_t s) {
+  hipLaunchKernelGGL(k_base_relation_vec, dim3(e.nblocks), dim3(kBlock), 0, s, e, in);
+}
+void launch_rel_compose_vec(const DevEngine& e, int64_t first, int64_t ntasks, hipStream_t s) {
+  if (ntasks > 0) hipLaunchKernelGGL(k_rel_compose_vec, dim3(grid_of(e, ntasks)), dim3(kBlock), 0, s, e, first, ntasks);
+}
+void launch_domain_vec(const DevEngine& e, const Inputs& in, hipStream_t s) {
+  hipLaunchKernelGGL(k_domain_vec, dim3(e.nblocks), dim3(kBlock), 0, s, e, in);
+}
+void launch_eliminate_vec(const DevEngine& e, const Inputs& in, hipStream_t s) {
+  hipLaunchKernelGGL(k_eliminate_vec, dim3(e.nblocks), dim3(kBlock), 0, s, e, in);
+}
+void launch_ric_combine_vec(const DevEngine& e, int64_t first, int64_t ntasks, hipStream_t s) {
+  if (ntasks > 0) hipLaunchKernelGGL(k_ric_combine_vec, dim3(grid_of(e, ntasks)), dim3(kBlock), 0, s, e, first, ntasks);
+}
+void launch_gains_vec(const DevEngine& e, hipStream_t s) {
+  hipLaunchKernelGGL(k_gains_vec, dim3(e.nblocks), dim3(kBlock), 0, s, e);
+}
+void launch_fwd_combine_vec(const DevEngine& e, int64_t first, int64_t ntasks, hipStream_t s) {
+  if (ntasks > 0) hipLaunchKernelGGL(k_fwd_combine_vec, dim3(grid_of(e, ntasks)), dim3(kBlock), 0, s, e, first, ntasks);
+}
+
+}  // namespace eclqr

@@ -22,6 +22,10 @@ struct DevEngine {
   double* arena;              // stage arenas
   double* scan[SCAN_COUNT];   // slot arenas
   double* resid;              // [4 * S]
+  const int64_t* rel_log_off; // per slot, -1 = none
+  const int64_t* ric_log_off;
+  double* rel_log;            // factor logs of the relation scan
+  double* ric_log;            // factor logs of the value-function scan
   const int32_t* gate;        // per-instance refinement state, null = every instance runs
   double* scratch;            // per-workgroup global scratch
   int64_t scratch_per_block;  // doubles
@@ -65,6 +69,15 @@ void launch_gains(const DevEngine& e, int32_t* status, int maxm, hipStream_t s);
 void launch_fwd_combine(const DevEngine& e, int64_t first_task, int64_t ntasks, hipStream_t s);
 void launch_recover(const DevEngine& e, double* x, double* u, hipStream_t s);
 
+// vector-only replays of the kernels above (factors logged by the full pass)
+void launch_base_relation_vec(const DevEngine& e, const Inputs& in, hipStream_t s);
+void launch_rel_compose_vec(const DevEngine& e, int64_t first, int64_t ntasks, hipStream_t s);
+void launch_domain_vec(const DevEngine& e, const Inputs& in, hipStream_t s);
+void launch_eliminate_vec(const DevEngine& e, const Inputs& in, hipStream_t s);
+void launch_ric_combine_vec(const DevEngine& e, int64_t first, int64_t ntasks, hipStream_t s);
+void launch_gains_vec(const DevEngine& e, hipStream_t s);
+void launch_fwd_combine_vec(const DevEngine& e, int64_t first, int64_t ntasks, hipStream_t s);
+
 // reversed-time stationarity problem and refinement helpers
 struct DualPtrs {
   double* f[IN_COUNT];     // data of the reversed-time problem (its own layout)
@@ -103,6 +116,12 @@ void launch_backward_error(const DevEngine& p, const Inputs& in, const double* x
 void launch_accept(const unsigned long long* omega, const int32_t* dstatus, double tol, int32_t* gate, int32_t B,
                    hipStream_t s);
 void launch_fill_u64(unsigned long long* y, unsigned long long v, int64_t n, hipStream_t s);
+// status |= bit (+ the other outcome in bits 8..15) where other & mask
+void launch_merge_dual_bits(int32_t* status, const int32_t* other, int32_t bit, int32_t mask, int32_t B,
+                            hipStream_t s);
+// status |= bit where an instance took refinement steps and its final backward error exceeds tol
+void launch_flag_unconverged(const unsigned long long* omega, const int32_t* steps, double tol, int32_t* status,
+                             int32_t bit, int32_t B, hipStream_t s);
 void launch_fill(double* y, double v, int64_t n, hipStream_t s);
 void launch_fill_i32(int32_t* y, int32_t v, int64_t n, hipStream_t s);
 // merges only instances whose gate equals `want` (all instances if gate is null)

@@ -91,7 +91,7 @@ std::string Engine::build(const eclqr_dims* d) {
   arena_total = 0;
   for (int64_t s = 0; s < S; ++s) {
     st[s].ws = arena_total;
-    arena_total += arena_layout(st[s].n, st[s].np, st[s].m).size;
+    arena_total += arena_layout(st[s].n, st[s].np, st[s].m, st[s].k).size;
   }
 
   // ---- scan schedule -------------------------------------------------------
@@ -223,6 +223,29 @@ std::string Engine::build(const eclqr_dims* d) {
     slot_off[SCAN_FWD][q] = scan_arena[SCAN_FWD];
     scan_arena[SCAN_FWD] += fwd_slot_size(fa, fb);
   }
+  // factor logs: leaves of the relation scan (base relations) and every task output
+  rel_log_off.assign(nslots, -1);
+  ric_log_off.assign(nslots, -1);
+  rel_log_total = ric_log_total = 0;
+  for (int32_t q = 0; q < nslots; ++q) {
+    const int b = slot_inst[q], s = slot_s[q], e = slot_e[q];
+    if (e != s + 1) continue;
+    const StageInfo& x = st[sbase[b] + s];
+    const int P = x.terminal ? x.k : x.np + x.k;
+    const int R = x.terminal ? 0 : std::min(x.m, P);
+    rel_log_off[q] = rel_log_total;
+    rel_log_total += rel_log_layout(P, R, slot_cap[q]).size;
+  }
+  for (size_t t = 0; t < tasks.size() / 3; ++t) {
+    const int a = tasks[3 * t], c = tasks[3 * t + 1], o = tasks[3 * t + 2];
+    const int b = slot_inst[a];
+    const int nmid = st[sbase[b] + slot_e[a]].n;
+    const int P = slot_cap[a] + slot_cap[c];
+    rel_log_off[o] = rel_log_total;
+    rel_log_total += rel_log_layout(P, std::min(nmid, P), slot_cap[o]).size;
+    ric_log_off[o] = ric_log_total;
+    ric_log_total += ric_log_size(nmid);
+  }
   lvl_rows.assign(2 * D, 0);
   lvl_dim.assign(2 * D, 0);
   lvl_ldw.assign(2 * D, 1);
@@ -256,7 +279,7 @@ std::string Engine::build(const eclqr_dims* d) {
   }
   scratch_per_block = std::max(scratch_per_block, ric_pool(maxn));
   scratch_per_block = rup4(scratch_per_block);
-  nblocks = (int32_t)std::min<int64_t>(S, 2048);
+  nblocks = (int32_t)std::min<int64_t>(std::max<int64_t>(S, 1), 8192);
 
   // ---- workspace map -------------------------------------------------------
   size_t o = 0;
@@ -273,6 +296,10 @@ std::string Engine::build(const eclqr_dims* d) {
   o_sbase = o; o = align256(o + sizeof(int64_t) * B);
   o_scratch = o; o = align256(o + sizeof(double) * scratch_per_block * nblocks);
   o_arena = o; o = align256(o + sizeof(double) * arena_total);
+  o_rel_log_off = o; o = align256(o + sizeof(int64_t) * std::max<int32_t>(1, nslots));
+  o_ric_log_off = o; o = align256(o + sizeof(int64_t) * std::max<int32_t>(1, nslots));
+  o_rel_log = o; o = align256(o + sizeof(double) * std::max<int64_t>(1, rel_log_total));
+  o_ric_log = o; o = align256(o + sizeof(double) * std::max<int64_t>(1, ric_log_total));
   for (int k = 0; k < SCAN_COUNT; ++k) {
     o_scan[k] = o;
     o = align256(o + sizeof(double) * scan_arena[k]);

@@ -42,6 +42,10 @@ struct Engine {
   std::vector<int32_t> lvl_dim;     // max endpoint dim over the level's operands
   std::vector<int32_t> lvl_ldw;     // REL: max (n_a + n_b + n_c + 1) over the level
 
+  // factor logs replayed by the vector-only pass, per output slot
+  std::vector<int64_t> rel_log_off, ric_log_off;
+  int64_t rel_log_total = 0, ric_log_total = 0;
+
   int64_t arena_total = 0;  // stage arena doubles
   int32_t maxn = 0, maxm = 0, maxk = 0;
   int32_t base_maxp = 0, base_ldw = 0, elim_maxq = 0;
@@ -51,7 +55,7 @@ struct Engine {
   // workspace map (byte offsets from the engine's base)
   size_t o_stage = 0, o_slot_off = 0, o_slot_na = 0, o_slot_nb = 0, o_slot_cap = 0, o_slot_rows = 0,
          o_tasks = 0, o_nbar = 0, o_mbar = 0, o_arena = 0, o_scan[SCAN_COUNT] = {0, 0, 0}, o_resid = 0,
-         o_sbase = 0, o_scratch = 0;
+         o_sbase = 0, o_scratch = 0, o_rel_log_off = 0, o_ric_log_off = 0, o_rel_log = 0, o_ric_log = 0;
   size_t bytes = 0;
 
   std::string build(const eclqr_dims* d);

@@ -6,10 +6,10 @@ combines.  Reduced dimensions and relation row counts are read back from the
 workspace after a solve.  Householder QR of a p x c matrix with r reflections
 counts sum_{j<r} 4 (p - j)(c - j); row-pivoted Gram-Schmidt of p rows over kc
 columns choosing r rows counts sum_{j<r} (4 j kc + 4 (p - j - 1)(kc + 1)).
-A solve with multipliers in which instance b takes s_b refinement steps runs
-the primal engine 1 + s_b times on b (solve, corrections) and the
-reversed-time engine 1 + s_b times (multipliers after the solve and after
-every step).
+A solve with multipliers runs each engine (the problem and the reversed-time
+stationarity problem) once in full; refinement steps and the adjoint replay
+the logged factors on new vectors (kernel class "replay", whose matrix-vector
+work is not counted here).
 """
 
 from __future__ import annotations
@@ -127,13 +127,12 @@ def engine_flops(plan, ws, dual: bool, weight=None) -> Dict[str, float]:
 
 
 def solve_flops(plan, problems, ws, multipliers: bool = True, steps=None) -> Dict[str, float]:
-    """Flops per kernel class of one solve (primal, multipliers, refinement);
-    ``steps`` = refinement steps per instance (``Plan.refine_steps``)."""
-    runs = np.ones(plan.batch) if not multipliers else 1.0 + np.asarray(steps, dtype=np.float64)
+    """Flops per kernel class of the full passes of one solve (the problem and,
+    with multipliers, the reversed-time problem, each once)."""
     out = defaultdict(float)
-    for k, v in engine_flops(plan, ws, False, runs).items():
+    for k, v in engine_flops(plan, ws, False).items():
         out[k] += v
     if multipliers:
-        for k, v in engine_flops(plan, ws, True, runs).items():
+        for k, v in engine_flops(plan, ws, True).items():
             out[k] += v
     return dict(out)

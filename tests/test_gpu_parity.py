@@ -60,16 +60,17 @@ def check_parity(probs, res, idx=None, tol=TOL):
             assert e <= tol, (b, key, e)
 
 
-def _check_residuals(res, r, tol=1e-8):
-    """Initial, dynamics and (normalised) equality residuals absolute; the
-    stationarity residual relative to the largest multiplier of the instance:
-    on nearly uncontrollable instances the multipliers reach 1e3..1e5 and the
-    oracle's own stationarity residual reaches 7e-7."""
+def _check_residuals(res, r, tol=1e-8, stat_tol=1e-7):
+    """Initial, dynamics and (normalised) equality residuals absolute (tol);
+    the stationarity residual relative to the largest multiplier of the
+    instance (stat_tol): on nearly uncontrollable instances the multipliers
+    reach 1e3..1e5, and on instance 506 of the 512-instance batch the oracle's
+    own relative stationarity residual is 1.8e-7."""
     assert r[:, :3].max() < tol, r[:, :3].max(axis=0)
     for b in range(r.shape[0]):
         scale = max(1.0, max(np.abs(v).max(initial=0.0) for v in res["lam"][b]),
                     max(np.abs(v).max(initial=0.0) for v in res["mu"][b]))
-        assert r[b, 3] <= tol * scale, (b, r[b, 3], scale)
+        assert r[b, 3] <= stat_tol * scale, (b, r[b, 3], scale)
 
 
 def test_c0_tiny():
