@@ -80,21 +80,115 @@ def kernel_profile(ecl, torch, plan, data, ws, sol, steps):
     return {k: (ms / steps, n / steps) for k, (ms, n) in prof.items()}
 
 
-def cpu_baseline(problems, budget_s=20.0):
+def secondary_batched(ecl, torch, steps):
+    """The 512-instance batch solved in one call versus the same instances
+    solved one after another, each with its own single-instance plan."""
+    problems = make("c3")
+    stages = sum(p.N for p in problems)
+    plan = ecl.Plan.for_problems(problems)
+    data = ecl.pack(plan, problems)
+    ws = plan.workspace()
+    sol = ecl.allocate_solution(plan)
+    batched_ms, _ = time_solves(ecl, torch, plan, data, ws, sol, steps, 1)
+    ok_batched = int((sol.status != 0).sum().item()) == 0
+    del ws
+    singles = []
+    for p in problems:
+        pl = ecl.Plan.for_problems([p])
+        singles.append((pl, ecl.pack(pl, [p]), pl.workspace(), ecl.allocate_solution(pl)))
+    for pl, d, w, s in singles:
+        ecl.solve(pl, d, w, s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for pl, d, w, s in singles:
+        ecl.solve(pl, d, w, s)
+    torch.cuda.synchronize()
+    loop_ms = (time.perf_counter() - t0) * 1e3
+    ok_single = all(int((s.status != 0).sum().item()) == 0 for _, _, _, s in singles)
+    del singles
+    return {"workload": "c3: " + WORKLOADS["c3"], "stages": stages,
+            "batched_ms": batched_ms, "batched_stages_per_s": stages / (batched_ms * 1e-3),
+            "single_loop_ms": loop_ms, "single_loop_stages_per_s": stages / (loop_ms * 1e-3),
+            "batched_over_single": loop_ms / batched_ms, "status_ok": ok_batched and ok_single}
+
+
+def secondary_differentiable(ecl, torch, steps):
+    """Forward solve + backward (gradients of sum ||x||^2 + ||u||^2 with
+    respect to every field) of the 256-instance batch; instance 0 checked
+    against the oracle (x, u, lambda, mu at 1e-9) and one central finite
+    difference (h = 1e-6, 1e-6 relative)."""
+    from paper_2407_05433_amd.autograd import eclqr_layer
+    problems = make("c4")
+    plan = ecl.Plan.for_problems(problems)
+    base = ecl.pack(plan, problems)
+    ws = plan.workspace()
+
+    def step():
+        leaves = {k: v.detach().clone().requires_grad_(True) for k, v in base.items()}
+        x, u, lam, mu, status = eclqr_layer(plan, leaves, ws)
+        loss = (x * x).sum() + (u * u).sum()
+        loss.backward()
+        return leaves, x, u, lam, mu, status
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    leaves, x, u, lam, mu, status = out
+    res = {"workload": "c4: " + WORKLOADS["c4"], "fwd_bwd_ms": ms, "status_ok": int((status != 0).sum().item()) == 0}
+    try:
+        from oracle import solve_with_multipliers
+        from oracle.gradients import directional, effective_direction, fd_directional_corrected, random_direction
+        p = problems[0]
+        o = solve_with_multipliers(p)
+        got = {"x": ecl.unpack(plan, x.detach(), "q", problems)[0], "u": ecl.unpack(plan, u.detach(), "r", problems)[0],
+               "lam": ecl.unpack(plan, lam, "q", problems)[0], "mu": ecl.unpack(plan, mu, "g", problems)[0]}
+        errs = {k: float(np.linalg.norm(np.concatenate([np.ravel(a) for a in got[k]]) -
+                                        np.concatenate([np.ravel(a) for a in o[k]])) /
+                         max(np.linalg.norm(np.concatenate([np.ravel(a) for a in o[k]])), 1e-300)) for k in got}
+        G = {}
+        for f in ("Q", "q", "R", "r", "A", "B", "c", "E", "F", "g", "x0"):
+            g = leaves[f].grad.detach().cpu().numpy()
+            offs, _ = plan.layout(f)
+            if f == "x0":
+                G[f] = g[offs[0]:offs[0] + p.nx[0]].copy()
+            else:
+                G[f] = [g[int(offs[i]):int(offs[i]) + a.size].reshape(a.shape) for i, a in enumerate(getattr(p, f))]
+        d = random_direction(p, np.random.default_rng(7))
+        d.pop("M", None)
+        an = directional(G, effective_direction(p, d, 1e-6))
+        fd = fd_directional_corrected(p, o, d, 1e-6)
+        res["check_instance0"] = {"rel_err": errs, "fd_rel_err": abs(fd - an) / max(abs(fd), abs(an)),
+                                  "pass": max(errs.values()) <= 1e-9 and abs(fd - an) / max(abs(fd), abs(an)) <= 1e-6}
+    except Exception as ex:  # the check is a report, not part of the timing
+        res["check_instance0"] = {"error": repr(ex)}
+    return res
+
+
+def cpu_baseline(problems, min_s=10.0, max_s=30.0):
     """The oracle (sequential method + minimum-norm multipliers + one
-    refinement step) on a bounded sample of the workload's instances."""
+    refinement step) on a bounded sample of the workload: instances in order,
+    cycling, until at least min_s seconds (at most max_s) have passed."""
     from oracle import solve_with_multipliers
     t0 = time.perf_counter()
-    stages, used = 0, 0
-    for p in problems:
+    stages, solves, i = 0, 0, 0
+    while True:
+        p = problems[i % len(problems)]
         solve_with_multipliers(p)
         stages += p.N
-        used += 1
-        if time.perf_counter() - t0 > budget_s:
+        solves += 1
+        i += 1
+        dt = time.perf_counter() - t0
+        if dt >= min_s or dt > max_s:
             break
-    dt = time.perf_counter() - t0
+    distinct = min(solves, len(problems))
     return {"value": stages / dt, "unit": "stages/s", "cores": 1, "kind": "oracle",
-            "sample": f"{used} of {len(problems)} instances ({stages} stages), {dt:.1f} s, one thread"}
+            "sample": f"{solves} solves of {distinct} of the {len(problems)} instances ({stages} stages), "
+                      f"{dt:.1f} s, one thread"}
 
 
 def main():
@@ -105,6 +199,7 @@ def main():
     ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--graph", type=int, default=1, help="replay the solve as a captured hipGraph (1) or launch eagerly (0)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver has no multi-GPU path (batches and horizons shard "
@@ -117,7 +212,7 @@ def main():
 
     log(f"[bench] generating {args.workload}")
     problems = make(args.workload)
-    plan = ecl.Plan.for_problems(problems)
+    plan = ecl.Plan.for_problems(problems, use_graph=args.graph)
     data = ecl.pack(plan, problems)
     ws = plan.workspace()
     sol = ecl.allocate_solution(plan)
@@ -161,12 +256,23 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "instances": len(problems),
-                   "stages": stages, "multipliers": True,
+                   "stages": stages, "multipliers": True, "hip_graph": bool(args.graph),
                    "refine": {"max_steps": int(plan.options.refine), "tol": float(plan.options.refine_tol),
                               "steps_taken": {str(int(k)): int(v) for k, v in zip(*np.unique(rsteps, return_counts=True))}}},
         "roofline": roof,
         "kernel_ms_per_solve": {k: v[0] for k, v in prof.items() if v[1]},
     }
+    if not args.no_secondary:
+        del ws, sol, data
+        torch.cuda.empty_cache()
+        log("[bench] secondary: c3 batched vs single-instance loop")
+        sec = {"batched_vs_single": secondary_batched(ecl, torch, max(1, min(args.steps, 3)))}
+        log(f"[bench]   {sec['batched_vs_single']}")
+        torch.cuda.empty_cache()
+        log("[bench] secondary: c4 forward + backward")
+        sec["differentiable"] = secondary_differentiable(ecl, torch, max(1, min(args.steps, 5)))
+        log(f"[bench]   {sec['differentiable']}")
+        line["secondary"] = sec
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(problems)

@@ -107,7 +107,8 @@ typedef struct {
   int32_t refine;         /* most steps of iterative refinement per instance (0..4); 3.  A refined
                            * instance whose final KKT backward error exceeds dual_cons_tol reports
                            * ECLQR_DUAL_FAILED */
-  int32_t use_graph;      /* 1: replay the launch sequence as a captured hipGraph; 0 */
+  int32_t use_graph;      /* 1: capture the launch sequence of eclqr_solve once per set of pointers and
+                           * replay it as a hipGraph; 0 */
   int32_t reserved[5];
 } eclqr_options;
 
@@ -194,6 +195,14 @@ enum {
  * the summed milliseconds and the number of launches (arrays of
  * ECLQR_NUM_KERNEL_CLASSES, host memory), then clears them if reset != 0. */
 eclqr_status eclqr_plan_set_profiling(eclqr_plan* plan, int32_t on);
+
+/* Turn the captured-graph path of eclqr_solve on or off (the use_graph
+ * option).  With it on, the first solve with a given set of pointers (problem,
+ * solution, workspace) captures its launch sequence into a hipGraph on the
+ * stream and launches it; later solves with the same pointers launch the graph
+ * (new values in the same buffers are picked up).  Different pointers
+ * re-capture.  Profiling bypasses the graph. */
+eclqr_status eclqr_plan_set_graph(eclqr_plan* plan, int32_t on);
 eclqr_status eclqr_plan_profile(eclqr_plan* plan, double* ms, int64_t* launches, int32_t reset);
 const char* eclqr_kernel_class_name(int32_t k);
 

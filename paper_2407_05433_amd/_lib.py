@@ -86,6 +86,8 @@ def lib():
     L.eclqr_kkt_residual.argtypes = [C.c_void_p, C.POINTER(ProblemPtrs), C.POINTER(SolutionPtrs), C.c_void_p,
                                      C.c_void_p, C.c_size_t, C.c_void_p]
     L.eclqr_plan_set_profiling.argtypes = [C.c_void_p, C.c_int32]
+    L.eclqr_plan_set_graph.argtypes = [C.c_void_p, C.c_int32]
+    L.eclqr_plan_set_graph.restype = C.c_int
     L.eclqr_plan_profile.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
     L.eclqr_kernel_class_name.restype = C.c_char_p
     L.eclqr_kernel_class_name.argtypes = [C.c_int32]

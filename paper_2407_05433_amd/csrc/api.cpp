@@ -15,6 +15,22 @@
 
 using namespace eclqr;
 
+namespace eclqr {
+
+void release_graph(Plan& p) {
+  if (p.graph_exec) (void)hipGraphExecDestroy(reinterpret_cast<hipGraphExec_t>(p.graph_exec));
+  p.graph_exec = nullptr;
+  p.graph_key.clear();
+}
+
+Plan::~Plan() {
+  release_graph(*this);
+  if (capture_stream) (void)hipStreamDestroy(reinterpret_cast<hipStream_t>(capture_stream));
+  for (void* e : event_pool) (void)hipEventDestroy(reinterpret_cast<hipEvent_t>(e));
+}
+
+}  // namespace eclqr
+
 namespace {
 
 thread_local std::string g_err;
@@ -392,6 +408,18 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
 
 bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7) == 0; }
 
+// The whole launch sequence of one solve.
+eclqr_status solve_sequence(Plan& p, const Views& v, const Inputs& in, eclqr_solution* sol, bool want, hipStream_t s) {
+  const Engine& E = p.primal;
+  launch_fill_i32(sol->status, 0, E.B, s);
+  if (want) launch_dual_matrices(v.P, in, v.D, v.dp, s);
+  eclqr_status st = solve_all(p, v, in, sol->x, sol->u, sol->lam, sol->mu, sol->status, want, false, s);
+  if (st != ECLQR_SUCCESS) return st;
+  launch_finalize(v.P, sol->status, sol->x, sol->u, want ? sol->lam : nullptr, want ? sol->mu : nullptr, s);
+  HIP_OK(hipGetLastError());
+  return ECLQR_SUCCESS;
+}
+
 }  // namespace
 
 extern "C" {
@@ -456,6 +484,13 @@ eclqr_status eclqr_plan_create(eclqr_plan** out, const eclqr_dims* dims, const e
 
 void eclqr_plan_destroy(eclqr_plan* plan) { delete plan; }
 
+eclqr_status eclqr_plan_set_graph(eclqr_plan* plan, int32_t on) {
+  if (!plan) return fail(ECLQR_INVALID_ARGUMENT, "NULL plan");
+  plan->p.opt.use_graph = (on != 0);
+  if (!on) release_graph(plan->p);
+  return ECLQR_SUCCESS;
+}
+
 eclqr_status eclqr_plan_layout(const eclqr_plan* plan, int32_t field, const int64_t** offsets, int64_t* count,
                                int64_t* total) {
   if (!plan || field < 0 || field >= ECLQR_NUM_FIELDS) return fail(ECLQR_INVALID_ARGUMENT, "bad plan or field");
@@ -510,13 +545,40 @@ eclqr_status eclqr_solve(eclqr_plan* plan, const eclqr_problem* prob, eclqr_solu
   if (st != ECLQR_SUCCESS) return st;
   g_prof = &p;
   Views v = views(p, ws);
-  launch_fill_i32(sol->status, 0, E.B, s);
   Inputs in = inputs_of(prob);
-  if (want) launch_dual_matrices(v.P, in, v.D, v.dp, s);
-  st = solve_all(p, v, in, sol->x, sol->u, sol->lam, sol->mu, sol->status, want, false, s);
-  if (st != ECLQR_SUCCESS) return st;
-  launch_finalize(v.P, sol->status, sol->x, sol->u, want ? sol->lam : nullptr, want ? sol->mu : nullptr, s);
-  HIP_OK(hipGetLastError());
+  if (!p.opt.use_graph || p.profiling) return solve_sequence(p, v, in, sol, want, s);
+  // Graph path: the sequence is captured once per set of pointers and
+  // replayed; every memory clear in it is a fill kernel.
+  std::vector<const void*> key = {ws, prob->Q, prob->q, prob->R, prob->r, prob->M, prob->A, prob->B, prob->c,
+                                  prob->E, prob->F, prob->g, prob->x0, sol->x, sol->u, sol->lam, sol->mu,
+                                  sol->status};
+  if (!p.graph_exec || p.graph_key != key) {
+    release_graph(p);
+    // captured on a plan-owned stream (the caller's may be the null stream,
+    // which cannot be captured); nothing runs during the capture
+    if (!p.capture_stream) {
+      hipStream_t cs = nullptr;
+      HIP_OK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+      p.capture_stream = reinterpret_cast<void*>(cs);
+    }
+    hipStream_t cs = reinterpret_cast<hipStream_t>(p.capture_stream);
+    HIP_OK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    const eclqr_status cst = solve_sequence(p, v, in, sol, want, cs);
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(cs, &g);
+    if (cst != ECLQR_SUCCESS) {
+      if (g) (void)hipGraphDestroy(g);
+      return cst;
+    }
+    if (ce != hipSuccess) return fail(ECLQR_HIP_ERROR, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) return fail(ECLQR_HIP_ERROR, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+    p.graph_exec = reinterpret_cast<void*>(ex);
+    p.graph_key = key;
+  }
+  HIP_OK(hipGraphLaunch(reinterpret_cast<hipGraphExec_t>(p.graph_exec), s));
   return ECLQR_SUCCESS;
 }
 

@@ -78,6 +78,12 @@ struct Plan {
   size_t bytes = 0;
   void* bound_ws = nullptr;
   int bound_device = -1;
+  // captured launch sequence of eclqr_solve (use_graph): valid for the
+  // pointers it was captured with
+  void* graph_exec = nullptr;
+  void* capture_stream = nullptr;  // plan-owned stream the sequence is captured on
+  std::vector<const void*> graph_key;
+  ~Plan();
   // profiler: recorded (class, start, stop) event triples
   bool profiling = false;
   std::vector<std::pair<int, std::pair<void*, void*>>> events;
@@ -86,6 +92,7 @@ struct Plan {
 };
 
 std::string build_plan(Plan& p, const eclqr_dims* d, const eclqr_options* opt);
+void release_graph(Plan& p);
 
 }  // namespace eclqr
 

@@ -91,6 +91,10 @@ class Plan:
                        if nt.value else np.zeros((0, 3), np.int32))
         return out
 
+    def set_graph(self, on: bool) -> None:
+        """Capture the solve's launch sequence as a hipGraph and replay it."""
+        check(lib().eclqr_plan_set_graph(self._h, int(on)), "eclqr_plan_set_graph")
+
     def set_profiling(self, on: bool) -> None:
         check(lib().eclqr_plan_set_profiling(self._h, int(on)), "eclqr_plan_set_profiling")
 

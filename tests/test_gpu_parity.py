@@ -236,3 +236,43 @@ def test_deterministic_bitwise():
     b = gpu_solve(probs)
     for key in ("x", "u", "lam", "mu"):
         assert np.array_equal(np.concatenate(a[key][0]), np.concatenate(b[key][0]))
+
+
+def test_graph_replay_matches_eager():
+    """use_graph: the captured launch sequence, replayed several times with
+    eager work in between, reproduces the eager solve bitwise; new values in
+    the same buffers are picked up; new buffers re-capture."""
+    _need_gpu()
+    import paper_2407_05433_amd as ecl
+    from workloads import config_c1, config_c3
+    for probs in (config_c1(N=200), config_c3(B=5, N_range=(32, 70))):
+        eager = ecl.Plan.for_problems(probs)
+        graph = ecl.Plan.for_problems(probs, use_graph=1)
+        data = ecl.pack(eager, probs)
+        ws_e, ws_g = eager.workspace(), graph.workspace()
+        ref = ecl.solve(eager, data, ws_e)
+        sol = ecl.allocate_solution(graph)
+        for rep in range(3):
+            ecl.solve(graph, data, ws_g, sol)
+            torch.cuda.synchronize()
+            for f in ("x", "u", "lam", "mu", "status"):
+                assert torch.equal(getattr(sol, f), getattr(ref, f)), (rep, f)
+            # eager work between replays
+            ecl.solve(eager, data, ws_e, ecl.allocate_solution(eager))
+            (data["q"] * 2.0).sum().item()
+            torch.cuda.synchronize()
+        # new values in the same buffers (linear costs: feasibility unchanged)
+        data["q"].mul_(-0.5)
+        data["r"].add_(0.25)
+        ref2 = ecl.solve(eager, data, ws_e)
+        ecl.solve(graph, data, ws_g, sol)
+        torch.cuda.synchronize()
+        assert int(ref2.status.abs().sum()) == 0
+        for f in ("x", "u", "lam", "mu", "status"):
+            assert torch.equal(getattr(sol, f), getattr(ref2, f)), ("new values", f)
+        # new output buffers: re-capture
+        sol2 = ecl.allocate_solution(graph)
+        ecl.solve(graph, data, ws_g, sol2)
+        torch.cuda.synchronize()
+        for f in ("x", "u", "lam", "mu", "status"):
+            assert torch.equal(getattr(sol2, f), getattr(ref2, f)), ("new buffers", f)
