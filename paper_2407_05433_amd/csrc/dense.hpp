@@ -47,24 +47,70 @@ __device__ __forceinline__ void wave_argmax(double& v, int& idx) {
 // Maximum of one value per lane (buf unused, kept for call sites).
 __device__ inline double wg_reduce_max(double v, double* /*buf*/) { return wave_max(v); }
 
+// Per-lane strided kernels.  LDS and global loads of a later iteration cannot
+// move above an earlier store the compiler cannot prove disjoint, so in-place
+// updates load a batch of operands into registers before storing it, and dot
+// products keep four independent accumulators.
+__device__ __forceinline__ double lane_dot(const double* a, int sa, const double* b, int sb, int n) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int i = 0;
+  for (; i + 4 <= n; i += 4) {
+    s0 = fma(a[i * sa], b[i * sb], s0);
+    s1 = fma(a[(i + 1) * sa], b[(i + 1) * sb], s1);
+    s2 = fma(a[(i + 2) * sa], b[(i + 2) * sb], s2);
+    s3 = fma(a[(i + 3) * sa], b[(i + 3) * sb], s3);
+  }
+  for (; i < n; ++i) s0 = fma(a[i * sa], b[i * sb], s0);
+  return (s0 + s1) + (s2 + s3);
+}
+
+// y[i] += alpha x[i], i < n (x and y disjoint).
+__device__ __forceinline__ void lane_axpy(double* y, int sy, const double* x, int sx, int n, double alpha) {
+  int i = 0;
+  for (; i + 8 <= n; i += 8) {
+    double xv[8], yv[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      xv[t] = x[(i + t) * sx];
+      yv[t] = y[(i + t) * sy];
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) y[(i + t) * sy] = fma(alpha, xv[t], yv[t]);
+  }
+  for (; i < n; ++i) y[i * sy] = fma(alpha, x[i * sx], y[i * sy]);
+}
+
 // C(MxN) = alpha * op(A) * op(B) + beta * C.  op(A) is MxK, op(B) is KxN.
 // beta == 0 never reads C.
 __device__ inline void wg_gemm(double* C, int ldc, const double* A, int lda, bool tA, const double* B, int ldb,
                                bool tB, int M, int N, int K, double alpha, double beta) {
-  for (int idx = ECLQR_TID; idx < M * N; idx += ECLQR_NT) {
-    const int i = idx / N, j = idx - (idx / N) * N;
-    double acc = 0.0;
-    if (!tA && !tB) {
-      for (int k = 0; k < K; ++k) acc = fma(A[i * lda + k], B[k * ldb + j], acc);
-    } else if (tA && !tB) {
-      for (int k = 0; k < K; ++k) acc = fma(A[k * lda + i], B[k * ldb + j], acc);
-    } else if (!tA && tB) {
-      for (int k = 0; k < K; ++k) acc = fma(A[i * lda + k], B[j * ldb + k], acc);
-    } else {
-      for (int k = 0; k < K; ++k) acc = fma(A[k * lda + i], B[j * ldb + k], acc);
+  const int sa = tA ? lda : 1, sb = tB ? 1 : ldb;
+  const int total = M * N;
+  // four outputs per lane per round, all loads of a round before its stores
+  for (int r0 = ECLQR_TID; r0 < total; r0 += 4 * ECLQR_NT) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    double prev[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int idx = r0 + t * ECLQR_NT;
+      if (idx < total) {
+        const int i = idx / N, j = idx - (idx / N) * N;
+        const double* a = tA ? A + i : A + (int64_t)i * lda;
+        const double* b = tB ? B + (int64_t)j * ldb : B + j;
+        double s = 0.0;
+        for (int k = 0; k < K; ++k) s = fma(a[k * sa], b[k * sb], s);
+        acc[t] = s;
+        if (beta != 0.0) prev[t] = beta * C[i * ldc + j];
+      }
     }
-    const double prev = (beta == 0.0) ? 0.0 : beta * C[i * ldc + j];
-    C[i * ldc + j] = alpha * acc + prev;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int idx = r0 + t * ECLQR_NT;
+      if (idx < total) {
+        const int i = idx / N, j = idx - (idx / N) * N;
+        C[i * ldc + j] = alpha * acc[t] + prev[t];
+      }
+    }
   }
   wg_sync();
 }
@@ -86,18 +132,42 @@ __device__ inline void wg_gemv(double* y, const double* A, int lda, bool tA, con
 }
 
 __device__ inline void wg_copy(double* dst, int ldd, const double* src, int lds, int rows, int cols) {
-  for (int idx = ECLQR_TID; idx < rows * cols; idx += ECLQR_NT) {
-    const int i = idx / cols, j = idx - (idx / cols) * cols;
-    dst[i * ldd + j] = src[i * lds + j];
+  const int total = rows * cols;
+  for (int r0 = ECLQR_TID; r0 < total; r0 += 4 * ECLQR_NT) {
+    double v[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int idx = r0 + t * ECLQR_NT;
+      const int i = idx / cols, j = idx - (idx / cols) * cols;
+      v[t] = (idx < total) ? src[i * lds + j] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int idx = r0 + t * ECLQR_NT;
+      const int i = idx / cols, j = idx - (idx / cols) * cols;
+      if (idx < total) dst[i * ldd + j] = v[t];
+    }
   }
   wg_sync();
 }
 
 __device__ inline void wg_copy_t(double* dst, int ldd, const double* src, int lds, int rows, int cols) {
   // dst (cols x rows) = src(rows x cols)^T
-  for (int idx = ECLQR_TID; idx < rows * cols; idx += ECLQR_NT) {
-    const int i = idx / cols, j = idx - (idx / cols) * cols;
-    dst[j * ldd + i] = src[i * lds + j];
+  const int total = rows * cols;
+  for (int r0 = ECLQR_TID; r0 < total; r0 += 4 * ECLQR_NT) {
+    double v[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int idx = r0 + t * ECLQR_NT;
+      const int i = idx / cols, j = idx - (idx / cols) * cols;
+      v[t] = (idx < total) ? src[i * lds + j] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int idx = r0 + t * ECLQR_NT;
+      const int i = idx / cols, j = idx - (idx / cols) * cols;
+      if (idx < total) dst[j * ldd + i] = v[t];
+    }
   }
   wg_sync();
 }
@@ -155,11 +225,8 @@ __device__ inline int wg_qr_colpiv(double* W, int ld, int p, int c, int c0, int 
     double bv = 0.0;
     int best = -1;
     for (int col = j + ECLQR_TID; col < cp; col += ECLQR_NT) {
-      double s = 0.0;
-      for (int row = j; row < p; ++row) {
-        const double v = W[row * ld + c0 + col];
-        s = fma(v, v, s);
-      }
+      const double* cv = W + j * ld + c0 + col;
+      const double s = lane_dot(cv, ld, cv, ld, p - j);
       if (best < 0 || s > bv) {
         bv = s;
         best = col;
@@ -194,11 +261,11 @@ __device__ inline int wg_qr_colpiv(double* W, int ld, int p, int c, int c0, int 
     for (int col = ECLQR_TID; col < c; col += ECLQR_NT) {
       // skip this and the earlier pivot columns (they hold reflectors below the diagonal)
       if (col >= c0 && col <= c0 + j) continue;
-      double w = W[j * ld + col];
-      for (int row = j + 1; row < p; ++row) w = fma(W[row * ld + c0 + j], W[row * ld + col], w);
-      w *= tj;
+      const double* v = W + (j + 1) * ld + c0 + j;
+      double* y = W + (j + 1) * ld + col;
+      const double w = (W[j * ld + col] + lane_dot(v, ld, y, ld, p - j - 1)) * tj;
       W[j * ld + col] -= w;
-      for (int row = j + 1; row < p; ++row) W[row * ld + col] = fma(-w, W[row * ld + c0 + j], W[row * ld + col]);
+      lane_axpy(y, ld, v, ld, p - j - 1, -w);
     }
     wg_sync();
     if (ECLQR_TID == 0) W[j * ld + c0 + j] = beta;
@@ -261,11 +328,8 @@ __device__ inline int wg_row_basis(double* W, int ld, int r0, int p, int k0, int
     double bv = 0.0;
     int best = -1;
     for (int rr = base + ECLQR_TID; rr < p; rr += ECLQR_NT) {
-      double s = 0.0;
-      for (int cc = 0; cc < kc; ++cc) {
-        const double v = W[rr * ld + k0 + cc];
-        s = fma(v, v, s);
-      }
+      const double* rv = W + rr * ld + k0;
+      const double s = lane_dot(rv, 1, rv, 1, kc);
       if (best < 0 || s > bv) {
         bv = s;
         best = rr;
@@ -288,17 +352,13 @@ __device__ inline int wg_row_basis(double* W, int ld, int r0, int p, int k0, int
     // re-orthogonalise the pivot row against the chosen rows (one pass)
     if (sel > 0) {
       for (int l = ECLQR_TID; l < sel; l += ECLQR_NT) {
-        double d = 0.0;
-        for (int cc = 0; cc < kc; ++cc) d = fma(W[(r0 + l) * ld + k0 + cc], W[base * ld + k0 + cc], d);
+        const double d = lane_dot(W + (r0 + l) * ld + k0, 1, W + base * ld + k0, 1, kc);
         dots[l] = d;
         if (rec) rec[2 + l] = d;
       }
       wg_sync();
-      for (int cc = ECLQR_TID; cc <= kc; cc += ECLQR_NT) {
-        double v = W[base * ld + k0 + cc];
-        for (int l = 0; l < sel; ++l) v = fma(-dots[l], W[(r0 + l) * ld + k0 + cc], v);
-        W[base * ld + k0 + cc] = v;
-      }
+      for (int cc = ECLQR_TID; cc <= kc; cc += ECLQR_NT)
+        W[base * ld + k0 + cc] -= lane_dot(dots, 1, W + r0 * ld + k0 + cc, ld, sel);
       wg_sync();
     }
     // normalise (offset included)
@@ -311,9 +371,10 @@ __device__ inline int wg_row_basis(double* W, int ld, int r0, int p, int k0, int
     wg_sync();
     // project the pivot row out of the remaining rows
     for (int rr = base + 1 + ECLQR_TID; rr < p; rr += ECLQR_NT) {
-      double d = 0.0;
-      for (int cc = 0; cc < kc; ++cc) d = fma(W[rr * ld + k0 + cc], W[base * ld + k0 + cc], d);
-      for (int cc = 0; cc <= kc; ++cc) W[rr * ld + k0 + cc] = fma(-d, W[base * ld + k0 + cc], W[rr * ld + k0 + cc]);
+      double* row = W + rr * ld + k0;
+      const double* piv = W + base * ld + k0;
+      const double d = lane_dot(row, 1, piv, 1, kc);
+      lane_axpy(row, 1, piv, 1, kc + 1, -d);
       if (rec) rec[2 + gcap + rr] = d;
     }
     wg_sync();
@@ -331,37 +392,26 @@ __device__ inline int wg_row_basis(double* W, int ld, int r0, int p, int k0, int
 // In-place Cholesky S = L L^T of an n x n SPD matrix (lower triangle holds L,
 // upper triangle zeroed).  Returns 0 on success, 1 if a pivot (before the
 // square root) is not above `floor`.
-__device__ inline int wg_cholesky(double* S, int ld, int n, double* sh /* 2 doubles */, double floor = 0.0) {
-  if (ECLQR_TID == 0) sh[0] = 0.0;
-  wg_sync();
+__device__ inline int wg_cholesky(double* S, int ld, int n, double* sh /* unused */, double floor = 0.0) {
+  (void)sh;
   for (int j = 0; j < n; ++j) {
-    if (ECLQR_TID == 0) {
-      const double d = S[j * ld + j];
-      if (!(d > floor)) {
-        sh[0] = 1.0;
-        sh[1] = 1.0;
-      } else {
-        sh[1] = sqrt(d);
-      }
-      S[j * ld + j] = sh[1];
+    const double d = S[j * ld + j];
+    if (!(d > floor)) {
+      wg_sync();
+      return 1;
     }
+    const double dj = sqrt(d);
     wg_sync();
-    if (sh[0] != 0.0) return 1;
-    const double dj = sh[1];
+    if (ECLQR_TID == 0) S[j * ld + j] = dj;
     for (int i = j + 1 + ECLQR_TID; i < n; i += ECLQR_NT) S[i * ld + j] /= dj;
     wg_sync();
-    // trailing update of the lower triangle
-    const int m = n - j - 1;
-    for (int idx = ECLQR_TID; idx < m * m; idx += ECLQR_NT) {
-      const int a = j + 1 + idx / m, b = j + 1 + idx % m;
-      if (b <= a) S[a * ld + b] = fma(-S[a * ld + j], S[b * ld + j], S[a * ld + b]);
-    }
+    // trailing update of the lower triangle, one row per lane
+    for (int a2 = j + 1 + ECLQR_TID; a2 < n; a2 += ECLQR_NT)
+      lane_axpy(S + a2 * ld + j + 1, 1, S + (j + 1) * ld + j, ld, a2 - j, -S[a2 * ld + j]);
     wg_sync();
   }
-  for (int idx = ECLQR_TID; idx < n * n; idx += ECLQR_NT) {
-    const int a = idx / n, b = idx % n;
-    if (b > a) S[a * ld + b] = 0.0;
-  }
+  for (int a2 = ECLQR_TID; a2 < n; a2 += ECLQR_NT)
+    for (int b = a2 + 1; b < n; ++b) S[a2 * ld + b] = 0.0;
   wg_sync();
   return 0;
 }
@@ -420,11 +470,8 @@ __device__ inline int wg_pchol(const double* S, int ld, int n, double tol, doubl
 // Solve L X = B (lower triangular L, n x n) in place on B (n x nc).
 __device__ inline void wg_trsm_lower(const double* L, int ldl, double* X, int ldx, int n, int nc) {
   for (int col = ECLQR_TID; col < nc; col += ECLQR_NT) {
-    for (int i = 0; i < n; ++i) {
-      double v = X[i * ldx + col];
-      for (int k = 0; k < i; ++k) v = fma(-L[i * ldl + k], X[k * ldx + col], v);
-      X[i * ldx + col] = v / L[i * ldl + i];
-    }
+    for (int i = 0; i < n; ++i)
+      X[i * ldx + col] = (X[i * ldx + col] - lane_dot(L + i * ldl, 1, X + col, ldx, i)) / L[i * ldl + i];
   }
   wg_sync();
 }
@@ -432,11 +479,10 @@ __device__ inline void wg_trsm_lower(const double* L, int ldl, double* X, int ld
 // Solve L^T X = B (L lower triangular) in place on B (n x nc).
 __device__ inline void wg_trsm_lower_t(const double* L, int ldl, double* X, int ldx, int n, int nc) {
   for (int col = ECLQR_TID; col < nc; col += ECLQR_NT) {
-    for (int i = n - 1; i >= 0; --i) {
-      double v = X[i * ldx + col];
-      for (int k = i + 1; k < n; ++k) v = fma(-L[k * ldl + i], X[k * ldx + col], v);
-      X[i * ldx + col] = v / L[i * ldl + i];
-    }
+    for (int i = n - 1; i >= 0; --i)
+      X[i * ldx + col] = (X[i * ldx + col] - lane_dot(L + (i + 1) * ldl + i, ldl, X + (i + 1) * ldx + col, ldx,
+                                                      n - i - 1)) /
+                         L[i * ldl + i];
   }
   wg_sync();
 }
@@ -445,11 +491,8 @@ __device__ inline void wg_trsm_lower_t(const double* L, int ldl, double* X, int 
 // wider matrix: U(i, j) = W[i*ld + c0 + j]) in place on X (r x nc).
 __device__ inline void wg_trsm_upper_t(const double* W, int ld, int c0, double* X, int ldx, int r, int nc) {
   for (int col = ECLQR_TID; col < nc; col += ECLQR_NT) {
-    for (int i = 0; i < r; ++i) {
-      double v = X[i * ldx + col];
-      for (int k = 0; k < i; ++k) v = fma(-W[k * ld + c0 + i], X[k * ldx + col], v);
-      X[i * ldx + col] = v / W[i * ld + c0 + i];
-    }
+    for (int i = 0; i < r; ++i)
+      X[i * ldx + col] = (X[i * ldx + col] - lane_dot(W + c0 + i, ld, X + col, ldx, i)) / W[i * ld + c0 + i];
   }
   wg_sync();
 }
@@ -482,11 +525,9 @@ __device__ inline void wg_lu(double* Mt, int ld, int n, int* piv, double* sh) {
     const double d = Mt[j * ld + j];
     for (int i = j + 1 + ECLQR_TID; i < n; i += ECLQR_NT) Mt[i * ld + j] /= d;
     wg_sync();
-    const int m = n - j - 1;
-    for (int idx = ECLQR_TID; idx < m * m; idx += ECLQR_NT) {
-      const int a = j + 1 + idx / m, b = j + 1 + idx % m;
-      Mt[a * ld + b] = fma(-Mt[a * ld + j], Mt[j * ld + b], Mt[a * ld + b]);
-    }
+    // trailing update, one row per lane
+    for (int a = j + 1 + ECLQR_TID; a < n; a += ECLQR_NT)
+      lane_axpy(Mt + a * ld + j + 1, 1, Mt + j * ld + j + 1, 1, n - j - 1, -Mt[a * ld + j]);
     wg_sync();
   }
 }
