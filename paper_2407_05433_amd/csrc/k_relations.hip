@@ -96,6 +96,7 @@ __global__ void __launch_bounds__(kBlock) k_base_relation(DevEngine e, Inputs in
         glog[0] = p;
         glog[1] = 0;
         glog[2] = rr;
+        glog[3] = 0;
         e.slot_rows[slot] = rr;
         if (b) flag(status, st.inst, ECLQR_INFEASIBLE_SUFFIX);
       }
@@ -147,11 +148,44 @@ __global__ void __launch_bounds__(kBlock) k_base_relation(DevEngine e, Inputs in
       glog[0] = p;
       glog[1] = rho;
       glog[2] = rr;
+      glog[3] = 0;
       e.slot_rows[slot] = rr;
       if (b) flag(status, st.inst, ECLQR_INFEASIBLE_SUFFIX);
     }
     wg_sync();
   }
+}
+
+// Composition of two full-rank relations (rows = endpoint dims, orthonormal
+// coefficient rows, so the coefficient matrix is orthogonal): the endpoint
+// values are -H' h.  Writes the point relation over (a, c) to out and sets
+// *bad when the shared endpoint disagrees beyond cons * max(1, |values|).
+// xs: LDS scratch of na + 2 nb + nc doubles.
+__device__ inline void point_compose(const double* L, int lda, int ra, const double* Rr, int ldb, int rb, int na, int nb,
+                                     int nc, double* xs, double cons, double* out, int* bad) {
+  const int ldl = lda + 1, ldr = ldb + 1;
+  double* xl = xs;            // (a*, b*) from the left relation
+  double* xr = xs + lda;      // (b*, c*) from the right relation
+  for (int i = ECLQR_TID; i < lda; i += ECLQR_NT) xl[i] = -lane_dot(L + i, ldl, L + lda, ldl, ra);
+  for (int i = ECLQR_TID; i < ldb; i += ECLQR_NT) xr[i] = -lane_dot(Rr + i, ldr, Rr + ldb, ldr, rb);
+  wg_sync();
+  double dif = 0.0, sc = 1.0;
+  for (int i = ECLQR_TID; i < nb; i += ECLQR_NT) {
+    dif = fmax(dif, fabs(xl[na + i] - xr[i]));
+    sc = fmax(sc, fmax(fabs(xl[na + i]), fabs(xr[i])));
+  }
+  dif = wave_max(dif);
+  sc = wave_max(sc);
+  *bad = (dif > cons * sc) ? 1 : 0;
+  const int lo = na + nc + 1;
+  for (int idx = ECLQR_TID; idx < (na + nc) * lo; idx += ECLQR_NT) {
+    const int r = idx / lo, j = idx - (idx / lo) * lo;
+    double v;
+    if (j < na + nc) v = (j == r) ? 1.0 : 0.0;
+    else v = (r < na) ? -xl[r] : -xr[nb + (r - na)];
+    out[idx] = v;
+  }
+  wg_sync();
 }
 
 // ---------------------------------------------------------------------------
@@ -178,6 +212,7 @@ __global__ void __launch_bounds__(kBlock) k_rel_compose(DevEngine e, int64_t fir
     if (gated(e, e.st[sa].inst)) continue;
     const int na = e.st[sa].n, nb = e.st[sb].n, nc = (sc >= 0) ? e.st[sc].n : 0;
     const int inst = e.st[sa].inst;
+    int bad_full = 0;
     const int ra = e.slot_rows[a], rb = e.slot_rows[bsl];
     const int p = ra + rb;
     const int P = e.slot_cap[a] + e.slot_cap[bsl];
@@ -189,16 +224,34 @@ __global__ void __launch_bounds__(kBlock) k_rel_compose(DevEngine e, int64_t fir
         glog[0] = 0;
         glog[1] = 0;
         glog[2] = 0;
+        glog[3] = 0;
         e.slot_rows[o] = 0;
         flag(status, inst, ECLQR_CAPACITY);
       }
       wg_sync();
       continue;
     }
-    const int c = nb + na + nc + 1;
-    const int ld = c;
     const double* L = slot_ptr(e, SCAN_REL, a);
     const double* Rr = slot_ptr(e, SCAN_REL, bsl);
+    if (ra == na + nb && rb == nb + nc && na + nc <= e.slot_cap[o]) {
+      // Both relations have full rank: each pins its endpoints to one point,
+      // (a*, b*) = -H_L' h_L and (b*, c*) = -H_R' h_R (orthonormal rows), the
+      // two b* must agree, and the composition is the point relation
+      // [I 0; 0 I](a, c) - (a*, c*) = 0.
+      point_compose(L, na + nb, ra, Rr, nb + nc, rb, na, nb, nc, W, t.cons, slot_ptr(e, SCAN_REL, o), &bad_full);
+      if (ECLQR_TID == 0) {
+        glog[0] = 0;
+        glog[1] = 0;
+        glog[2] = na + nc;
+        glog[3] = 1;
+        e.slot_rows[o] = na + nc;
+        if (bad_full) flag(status, inst, ECLQR_INFEASIBLE_SUFFIX);
+      }
+      wg_sync();
+      continue;
+    }
+    const int c = nb + na + nc + 1;
+    const int ld = c;
     const int lda = na + nb + 1, ldb = nb + nc + 1;
     for (int idx = ECLQR_TID; idx < p * c; idx += ECLQR_NT) {
       const int r = idx / c, j = idx % c;
@@ -232,6 +285,7 @@ __global__ void __launch_bounds__(kBlock) k_rel_compose(DevEngine e, int64_t fir
       glog[0] = p;
       glog[1] = rho;
       glog[2] = (rr > cap) ? 0 : rr;
+      glog[3] = 0;
     }
     if (rr > cap) {
       if (ECLQR_TID == 0) {

@@ -158,6 +158,19 @@ __global__ void __launch_bounds__(kBlock) k_rel_compose_vec(DevEngine e, int64_t
     const double* Ls = slot_ptr(e, SCAN_REL, a);
     const double* Rs = slot_ptr(e, SCAN_REL, bsl);
     const int lda = na + nb + 1, ldb = nb + nc + 1;
+    if (lg[3] == 1.0) {
+      // composition of two full-rank relations: offsets -(a*, c*)
+      if (ra != na + nb || rb != nb + nc) continue;
+      const int lo = na + nc + 1;
+      double* out = slot_ptr(e, SCAN_REL, oo);
+      for (int r = ECLQR_TID; r < na + nc; r += ECLQR_NT) {
+        const double x = (r < na) ? -lane_dot(Ls + r, lda, Ls + lda - 1, lda, ra)
+                                  : -lane_dot(Rs + nb + (r - na), ldb, Rs + ldb - 1, ldb, rb);
+        out[r * lo + lo - 1] = -x;
+      }
+      wg_sync();
+      continue;
+    }
     for (int r = ECLQR_TID; r < ra + rb; r += ECLQR_NT)
       o[r] = (r < ra) ? Ls[r * lda + na + nb] : Rs[(r - ra) * ldb + nb + nc];
     wg_sync();
