@@ -181,19 +181,20 @@ eclqr_status run_engine(const Engine& E, const DevEngine& d, const Inputs& in, d
   { Timed tm(ECLQR_K_VALIDATE, s); launch_validate(d, in, status, s); }
   { Timed tm(ECLQR_K_BASE_RELATION, s); launch_base_relation(d, in, t, status, E.base_maxp, E.base_ldw, s); }
   for (int l = 0; l < 2 * E.D; ++l) {
-    if (E.lvl_count[l] == 0) continue;
-    // rows of the stacked system that fit the device's LDS (larger tasks are flagged ECLQR_CAPACITY)
-    int rows = std::max(1, E.lvl_rows[l]);
-    while (rows > 1 && rel_lds_bytes(rows, E.lvl_ldw[l]) > (size_t)g_max_lds) --rows;
-    Timed tm(ECLQR_K_REL_COMPOSE, s);
-    launch_rel_compose(d, E.lvl_begin[l], E.lvl_count[l], t, status, rows, E.lvl_ldw[l], s);
+    for (int k = E.lvl_bkt_first[l]; k < E.lvl_bkt_first[l] + E.lvl_bkt_n[l]; ++k) {
+      // rows of the stacked system that fit the device's LDS (larger tasks are flagged ECLQR_CAPACITY)
+      int rows = std::max(1, E.bkt_rows[k]);
+      while (rows > 1 && rel_lds_bytes(rows, E.bkt_ldw[k]) > (size_t)g_max_lds) --rows;
+      Timed tm(ECLQR_K_REL_COMPOSE, s);
+      launch_rel_compose(d, E.bkt_begin[k], E.bkt_count[k], t, status, rows, E.bkt_ldw[k], s);
+    }
   }
   { Timed tm(ECLQR_K_DOMAIN, s); launch_domain(d, in, t, status, std::max(1, E.maxn), s); }
   { Timed tm(ECLQR_K_ELIMINATE, s); launch_eliminate(d, in, t, status, std::max(1, E.maxm), E.elim_maxq, s); }
   for (int l = 0; l < 2 * E.D; ++l) {
     if (E.lvl_count[l] == 0) continue;
     Timed tm(ECLQR_K_RIC_COMBINE, s);
-    launch_ric_combine(d, E.lvl_begin[l], E.lvl_count[l], status, std::max(1, E.maxn), s);
+    launch_ric_combine(d, E.lvl_begin[l], E.lvl_count[l], status, std::max(1, E.lvl_dim[l]), s);
   }
   { Timed tm(ECLQR_K_GAINS, s); launch_gains(d, status, std::max(1, E.maxm), s); }
   for (int l = 0; l < 2 * E.D; ++l) {

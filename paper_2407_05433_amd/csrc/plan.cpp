@@ -11,6 +11,7 @@
 #include "scratch.hpp"
 
 #include <algorithm>
+#include <array>
 #include <cstdio>
 
 namespace eclqr {
@@ -246,18 +247,70 @@ std::string Engine::build(const eclqr_dims* d) {
     ric_log_off[o] = ric_log_total;
     ric_log_total += ric_log_size(nmid);
   }
+  // Launch buckets of the relation composition: the tasks of a wide level
+  // (>= 2048 tasks) sorted by the LDS their composition needs and split where
+  // that need doubles (buckets of fewer than 512 tasks join the next larger
+  // one), so small tasks of a batch are not launched with the LDS of its
+  // largest one.
   lvl_rows.assign(2 * D, 0);
   lvl_dim.assign(2 * D, 0);
   lvl_ldw.assign(2 * D, 1);
+  bkt_begin.clear();
+  bkt_count.clear();
+  bkt_rows.clear();
+  bkt_ldw.clear();
+  bkt_dim.clear();
+  lvl_bkt_first.assign(2 * D, 0);
+  lvl_bkt_n.assign(2 * D, 0);
+  auto task_ldw = [&](int a, int c) { return slot_na[SCAN_REL][a] + slot_nb[SCAN_REL][a] + slot_nb[SCAN_REL][c] + 1; };
+  auto task_need = [&](int a, int c) { return (int64_t)(slot_cap[a] + slot_cap[c]) * task_ldw(a, c); };
+  auto task_dim = [&](int a, int c) {
+    return std::max({slot_na[SCAN_REL][a], slot_nb[SCAN_REL][a], slot_nb[SCAN_REL][c], slot_na[SCAN_FWD][a],
+                     slot_nb[SCAN_FWD][a], slot_nb[SCAN_FWD][c]});
+  };
+  auto lg2 = [](int64_t v) {
+    int k = 0;
+    while ((int64_t(1) << (k + 1)) <= v) ++k;
+    return k;
+  };
   for (int l = 0; l < 2 * D; ++l) {
-    for (int64_t t = lvl_begin[l]; t < lvl_begin[l] + lvl_count[l]; ++t) {
-      const int a = tasks[3 * t], c = tasks[3 * t + 1];
-      lvl_rows[l] = std::max(lvl_rows[l], slot_cap[a] + slot_cap[c]);
-      int dm = std::max({slot_na[SCAN_REL][a], slot_nb[SCAN_REL][a], slot_nb[SCAN_REL][c],
-                         slot_na[SCAN_FWD][a], slot_nb[SCAN_FWD][a], slot_nb[SCAN_FWD][c]});
-      lvl_dim[l] = std::max(lvl_dim[l], dm);
-      lvl_ldw[l] = std::max(lvl_ldw[l], slot_na[SCAN_REL][a] + slot_nb[SCAN_REL][a] + slot_nb[SCAN_REL][c] + 1);
+    const int64_t b0 = lvl_begin[l], nt = lvl_count[l];
+    std::vector<std::array<int32_t, 3>> tv((size_t)nt);
+    for (int64_t t = 0; t < nt; ++t) tv[t] = {tasks[3 * (b0 + t)], tasks[3 * (b0 + t) + 1], tasks[3 * (b0 + t) + 2]};
+    std::stable_sort(tv.begin(), tv.end(), [&](const std::array<int32_t, 3>& x, const std::array<int32_t, 3>& y) {
+      return task_need(x[0], x[1]) < task_need(y[0], y[1]);
+    });
+    for (int64_t t = 0; t < nt; ++t)
+      for (int k = 0; k < 3; ++k) tasks[3 * (b0 + t) + k] = tv[t][k];
+    lvl_bkt_first[l] = (int32_t)bkt_begin.size();
+    int64_t t = 0;
+    while (t < nt) {
+      int64_t u = t + 1;
+      const int cls = lg2(std::max<int64_t>(1, task_need(tv[t][0], tv[t][1])));
+      if (nt >= 2048) {
+        while (u < nt && lg2(std::max<int64_t>(1, task_need(tv[u][0], tv[u][1]))) == cls) ++u;
+        while (u < nt && u - t < 512) ++u;
+        if (nt - u < 512) u = nt;
+      } else {
+        u = nt;
+      }
+      int rows = 0, ldw = 1, dim = 0;
+      for (int64_t v = t; v < u; ++v) {
+        rows = std::max(rows, slot_cap[tv[v][0]] + slot_cap[tv[v][1]]);
+        ldw = std::max(ldw, task_ldw(tv[v][0], tv[v][1]));
+        dim = std::max(dim, task_dim(tv[v][0], tv[v][1]));
+      }
+      bkt_begin.push_back(b0 + t);
+      bkt_count.push_back(u - t);
+      bkt_rows.push_back(rows);
+      bkt_ldw.push_back(ldw);
+      bkt_dim.push_back(dim);
+      lvl_rows[l] = std::max(lvl_rows[l], rows);
+      lvl_ldw[l] = std::max(lvl_ldw[l], ldw);
+      lvl_dim[l] = std::max(lvl_dim[l], dim);
+      t = u;
     }
+    lvl_bkt_n[l] = (int32_t)bkt_begin.size() - lvl_bkt_first[l];
   }
   // per-stage kernel sizes
   base_maxp = 1;

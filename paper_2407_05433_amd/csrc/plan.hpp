@@ -41,6 +41,10 @@ struct Engine {
   std::vector<int32_t> lvl_rows;    // REL: max (cap_left + cap_right) over the level
   std::vector<int32_t> lvl_dim;     // max endpoint dim over the level's operands
   std::vector<int32_t> lvl_ldw;     // REL: max (n_a + n_b + n_c + 1) over the level
+  // launch buckets of each level: task ranges with their own LDS sizing
+  std::vector<int64_t> bkt_begin, bkt_count;
+  std::vector<int32_t> bkt_rows, bkt_ldw, bkt_dim;
+  std::vector<int32_t> lvl_bkt_first, lvl_bkt_n;
 
   // factor logs replayed by the vector-only pass, per output slot
   std::vector<int64_t> rel_log_off, ric_log_off;
