@@ -200,6 +200,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--graph", type=int, default=1, help="replay the solve as a captured hipGraph (1) or launch eagerly (0)")
+    ap.add_argument("--autotune", type=int, default=1, help="choose the launch configuration by timing first (untimed)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver has no multi-GPU path (batches and horizons shard "
@@ -218,6 +219,8 @@ def main():
     sol = ecl.allocate_solution(plan)
     stages = sum(p.N for p in problems)
     log(f"[bench] {len(problems)} instances, {stages} stages, workspace {plan.workspace_bytes / 2**20:.1f} MiB")
+    tuning = ecl.autotune(plan, data, ws, sol) if args.autotune else ecl.get_tuning(plan)
+    log(f"[bench] launch configuration {tuning}")
     wall_ms, ev_ms = time_solves(ecl, torch, plan, data, ws, sol, args.steps, args.warmup)
     st = sol.status.cpu().numpy()
     if np.any(st != 0):
@@ -256,7 +259,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "instances": len(problems),
-                   "stages": stages, "multipliers": True, "hip_graph": bool(args.graph),
+                   "stages": stages, "multipliers": True, "launch": tuning,
                    "refine": {"max_steps": int(plan.options.refine), "tol": float(plan.options.refine_tol),
                               "steps_taken": {str(int(k)): int(v) for k, v in zip(*np.unique(rsteps, return_counts=True))}}},
         "roofline": roof,

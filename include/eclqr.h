@@ -196,6 +196,26 @@ enum {
  * ECLQR_NUM_KERNEL_CLASSES, host memory), then clears them if reset != 0. */
 eclqr_status eclqr_plan_set_profiling(eclqr_plan* plan, int32_t on);
 
+/* Launch configuration of a plan. */
+typedef struct {
+  int32_t use_graph;      /* replay the solve as a captured hipGraph */
+  int32_t level_buckets;  /* relation-scan levels with >= 2048 tasks launch in LDS-size buckets */
+  int32_t pool_in_lds;    /* value-function combines keep their working pool in LDS when it fits */
+  int32_t grid_divisor;   /* grid of the stage-parallel kernels = its maximum / grid_divisor (1..64) */
+  double ms_per_solve;    /* time of the configuration chosen by eclqr_plan_autotune (0 if never tuned) */
+  int32_t reserved[4];
+} eclqr_tuning;
+
+/* Time the caller's problem under alternative launch configurations
+ * (coordinate search over the fields of eclqr_tuning, 1 warm-up + 3 timed
+ * solves each, an alternative kept only if 2% faster) and keep the fastest in
+ * the plan.  Synchronous: enqueues solves on `stream` and waits for them.  The
+ * solution buffers hold the last solve's result on return. */
+eclqr_status eclqr_plan_autotune(eclqr_plan* plan, const eclqr_problem* prob, eclqr_solution* sol, void* ws,
+                                 size_t ws_bytes, void* stream, eclqr_tuning* out);
+eclqr_status eclqr_plan_get_tuning(const eclqr_plan* plan, eclqr_tuning* out);
+eclqr_status eclqr_plan_set_tuning(eclqr_plan* plan, const eclqr_tuning* t);
+
 /* Turn the captured-graph path of eclqr_solve on or off (the use_graph
  * option).  With it on, the first solve with a given set of pointers (problem,
  * solution, workspace) captures its launch sequence into a hipGraph on the

@@ -38,6 +38,11 @@ class Options(C.Structure):
                 ("reserved", C.c_int32 * 5)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("use_graph", C.c_int32), ("level_buckets", C.c_int32), ("pool_in_lds", C.c_int32),
+                ("grid_divisor", C.c_int32), ("ms_per_solve", C.c_double), ("reserved", C.c_int32 * 4)]
+
+
 class ProblemPtrs(C.Structure):
     _fields_ = [(f, C.c_void_p) for f in FIELDS]
 
@@ -87,6 +92,12 @@ def lib():
                                      C.c_void_p, C.c_size_t, C.c_void_p]
     L.eclqr_plan_set_profiling.argtypes = [C.c_void_p, C.c_int32]
     L.eclqr_plan_set_graph.argtypes = [C.c_void_p, C.c_int32]
+    L.eclqr_plan_autotune.argtypes = [C.c_void_p, C.POINTER(ProblemPtrs), C.POINTER(SolutionPtrs), C.c_void_p,
+                                      C.c_size_t, C.c_void_p, C.POINTER(Tuning)]
+    L.eclqr_plan_get_tuning.argtypes = [C.c_void_p, C.POINTER(Tuning)]
+    L.eclqr_plan_set_tuning.argtypes = [C.c_void_p, C.POINTER(Tuning)]
+    for fn in ("eclqr_plan_autotune", "eclqr_plan_get_tuning", "eclqr_plan_set_tuning"):
+        getattr(L, fn).restype = C.c_int
     L.eclqr_plan_set_graph.restype = C.c_int
     L.eclqr_plan_profile.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
     L.eclqr_kernel_class_name.restype = C.c_char_p

@@ -52,6 +52,8 @@ T* at(void* ws, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
 }
 
+int32_t g_pool_lds = 1, g_grid_div = 1, g_buckets = 1;  // tuning of the plan being launched
+
 DevEngine dev_engine(const Engine& E, void* ws, size_t base) {
   DevEngine d{};
   char* b = static_cast<char*>(ws) + base;
@@ -76,7 +78,8 @@ DevEngine dev_engine(const Engine& E, void* ws, size_t base) {
   d.S = E.S;
   d.B = E.B;
   d.nslots = E.nslots;
-  d.nblocks = E.nblocks;
+  d.nblocks = std::max<int32_t>(1, E.nblocks / std::max<int32_t>(1, g_grid_div));
+  d.pool_lds = g_pool_lds;
   return d;
 }
 
@@ -181,12 +184,18 @@ eclqr_status run_engine(const Engine& E, const DevEngine& d, const Inputs& in, d
   { Timed tm(ECLQR_K_VALIDATE, s); launch_validate(d, in, status, s); }
   { Timed tm(ECLQR_K_BASE_RELATION, s); launch_base_relation(d, in, t, status, E.base_maxp, E.base_ldw, s); }
   for (int l = 0; l < 2 * E.D; ++l) {
-    for (int k = E.lvl_bkt_first[l]; k < E.lvl_bkt_first[l] + E.lvl_bkt_n[l]; ++k) {
+    if (E.lvl_count[l] == 0) continue;
+    const int nb = g_buckets ? E.lvl_bkt_n[l] : 1;
+    for (int k = 0; k < nb; ++k) {
+      const int bk = E.lvl_bkt_first[l] + k;
+      const int64_t first = g_buckets ? E.bkt_begin[bk] : E.lvl_begin[l];
+      const int64_t count = g_buckets ? E.bkt_count[bk] : E.lvl_count[l];
+      const int ldw = g_buckets ? E.bkt_ldw[bk] : E.lvl_ldw[l];
       // rows of the stacked system that fit the device's LDS (larger tasks are flagged ECLQR_CAPACITY)
-      int rows = std::max(1, E.bkt_rows[k]);
-      while (rows > 1 && rel_lds_bytes(rows, E.bkt_ldw[k]) > (size_t)g_max_lds) --rows;
+      int rows = std::max(1, g_buckets ? E.bkt_rows[bk] : E.lvl_rows[l]);
+      while (rows > 1 && rel_lds_bytes(rows, ldw) > (size_t)g_max_lds) --rows;
       Timed tm(ECLQR_K_REL_COMPOSE, s);
-      launch_rel_compose(d, E.bkt_begin[k], E.bkt_count[k], t, status, rows, E.bkt_ldw[k], s);
+      launch_rel_compose(d, first, count, t, status, rows, ldw, s);
     }
   }
   { Timed tm(ECLQR_K_DOMAIN, s); launch_domain(d, in, t, status, std::max(1, E.maxn), s); }
@@ -268,6 +277,9 @@ struct Views {
 };
 
 Views views(Plan& p, void* ws) {
+  g_pool_lds = p.pool_lds;
+  g_grid_div = p.grid_divisor;
+  g_buckets = p.level_buckets;
   Views v{};
   v.P = dev_engine(p.primal, ws, p.o_primal);
   v.D = dev_engine(p.dual, ws, p.o_dual);
@@ -728,6 +740,91 @@ eclqr_status eclqr_plan_slot_info(const eclqr_plan* plan, int32_t which, int32_t
     if (first) first[q] = E.slot_s[q];
     if (last) last[q] = E.slot_e[q];
   }
+  return ECLQR_SUCCESS;
+}
+
+eclqr_status eclqr_plan_get_tuning(const eclqr_plan* plan, eclqr_tuning* out) {
+  if (!plan || !out) return fail(ECLQR_INVALID_ARGUMENT, "NULL argument");
+  const Plan& p = plan->p;
+  std::memset(out, 0, sizeof(*out));
+  out->use_graph = p.opt.use_graph;
+  out->level_buckets = p.level_buckets;
+  out->pool_in_lds = p.pool_lds;
+  out->grid_divisor = p.grid_divisor;
+  out->ms_per_solve = p.tuned_ms;
+  return ECLQR_SUCCESS;
+}
+
+eclqr_status eclqr_plan_set_tuning(eclqr_plan* plan, const eclqr_tuning* t) {
+  if (!plan || !t) return fail(ECLQR_INVALID_ARGUMENT, "NULL argument");
+  if (t->grid_divisor < 1 || t->grid_divisor > 64) return fail(ECLQR_INVALID_ARGUMENT, "grid_divisor out of [1, 64]");
+  Plan& p = plan->p;
+  p.opt.use_graph = t->use_graph != 0;
+  p.level_buckets = t->level_buckets != 0;
+  p.pool_lds = t->pool_in_lds != 0;
+  p.grid_divisor = t->grid_divisor;
+  release_graph(p);
+  return ECLQR_SUCCESS;
+}
+
+eclqr_status eclqr_plan_autotune(eclqr_plan* plan, const eclqr_problem* prob, eclqr_solution* sol, void* ws,
+                                 size_t ws_bytes, void* stream, eclqr_tuning* out) {
+  if (!plan) return fail(ECLQR_INVALID_ARGUMENT, "NULL plan");
+  Plan& p = plan->p;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool prof = p.profiling;
+  p.profiling = false;
+  hipEvent_t ea = nullptr, eb = nullptr;
+  HIP_OK(hipEventCreate(&ea));
+  HIP_OK(hipEventCreate(&eb));
+  auto measure = [&](double* ms) -> eclqr_status {
+    eclqr_status st = eclqr_solve(plan, prob, sol, ws, ws_bytes, stream);  // warm-up (and capture)
+    if (st != ECLQR_SUCCESS) return st;
+    HIP_OK(hipEventRecord(ea, s));
+    for (int r = 0; r < 3; ++r) {
+      st = eclqr_solve(plan, prob, sol, ws, ws_bytes, stream);
+      if (st != ECLQR_SUCCESS) return st;
+    }
+    HIP_OK(hipEventRecord(eb, s));
+    HIP_OK(hipEventSynchronize(eb));
+    float t = 0.f;
+    HIP_OK(hipEventElapsedTime(&t, ea, eb));
+    *ms = t / 3.0;
+    return ECLQR_SUCCESS;
+  };
+  // coordinate search: each knob keeps its alternative value only if it is
+  // at least 2% faster than the best configuration so far
+  double best = 0.0;
+  eclqr_status st = measure(&best);
+  struct Knob {
+    int32_t* v;
+    int32_t alt;
+  };
+  int32_t graph = p.opt.use_graph;
+  Knob knobs[] = {{&p.level_buckets, p.level_buckets ? 0 : 1}, {&p.pool_lds, p.pool_lds ? 0 : 1},
+                  {&p.grid_divisor, p.grid_divisor == 1 ? 4 : 1}, {&graph, graph ? 0 : 1}};
+  for (Knob& k : knobs) {
+    if (st != ECLQR_SUCCESS) break;
+    const int32_t old = *k.v;
+    *k.v = k.alt;
+    p.opt.use_graph = graph;
+    release_graph(p);
+    double ms = 0.0;
+    st = measure(&ms);
+    if (st == ECLQR_SUCCESS && ms < 0.98 * best) {
+      best = ms;
+    } else {
+      *k.v = old;
+      p.opt.use_graph = graph;
+      release_graph(p);
+    }
+  }
+  (void)hipEventDestroy(ea);
+  (void)hipEventDestroy(eb);
+  p.profiling = prof;
+  if (st != ECLQR_SUCCESS) return st;
+  p.tuned_ms = best;
+  if (out) return eclqr_plan_get_tuning(plan, out);
   return ECLQR_SUCCESS;
 }
 

@@ -404,8 +404,9 @@ void launch_ric_combine(const DevEngine& e, int64_t first, int64_t ntasks, int32
                         hipStream_t s) {
   if (ntasks <= 0) return;
   const int grid = (int)(ntasks < e.nblocks ? ntasks : e.nblocks);
-  hipLaunchKernelGGL(k_ric_combine, dim3(grid), dim3(kBlock), ric_lds_bytes(maxd), s, e, first, ntasks, status, maxd,
-                     ric_pool_fits(maxd) ? 1 : 0);
+  const int in_lds = (e.pool_lds && ric_pool_fits(maxd)) ? 1 : 0;
+  const size_t lds = in_lds ? ric_lds_bytes(maxd) : sizeof(double) * 16 + sizeof(int) * kMaxDim + 64;
+  hipLaunchKernelGGL(k_ric_combine, dim3(grid), dim3(kBlock), lds, s, e, first, ntasks, status, maxd, in_lds);
 }
 
 void launch_gains(const DevEngine& e, int32_t* status, int maxm, hipStream_t s) {

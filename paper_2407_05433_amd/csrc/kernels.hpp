@@ -33,6 +33,7 @@ struct DevEngine {
   int32_t B;
   int32_t nslots;
   int32_t nblocks;            // grid size of the stage-parallel kernels (grid-stride)
+  int32_t pool_lds;           // 1: value-function combines keep their pool in LDS when it fits
 };
 
 // Pointers to one problem's data (caller layout of the engine).

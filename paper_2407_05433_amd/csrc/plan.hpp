@@ -84,6 +84,11 @@ struct Plan {
   int bound_device = -1;
   // captured launch sequence of eclqr_solve (use_graph): valid for the
   // pointers it was captured with
+  // tuning (eclqr_plan_autotune / eclqr_plan_set_tuning)
+  int32_t level_buckets = 1;  // relation levels launch in LDS-size buckets
+  int32_t pool_lds = 1;       // value-function combine pool in LDS when it fits
+  int32_t grid_divisor = 1;   // grid of the stage-parallel kernels = nblocks / divisor
+  double tuned_ms = 0.0;
   void* graph_exec = nullptr;
   void* capture_stream = nullptr;  // plan-owned stream the sequence is captured on
   std::vector<const void*> graph_key;

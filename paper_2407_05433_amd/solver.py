@@ -313,3 +313,40 @@ def unpack(plan: Plan, flat: torch.Tensor, field: str, problems) -> List[List[np
         out.append(blocks)
         s += p.N + 1
     return out
+
+
+def _tuning_dict(t: _lib.Tuning) -> Dict[str, float]:
+    return {"use_graph": int(t.use_graph), "level_buckets": int(t.level_buckets), "pool_in_lds": int(t.pool_in_lds),
+            "grid_divisor": int(t.grid_divisor), "ms_per_solve": float(t.ms_per_solve)}
+
+
+def autotune(plan: Plan, data: Dict[str, torch.Tensor], ws: torch.Tensor, out: Optional[Solution] = None) -> Dict:
+    """eclqr_plan_autotune on the current stream (synchronous): times the
+    problem under alternative launch configurations and keeps the fastest."""
+    if out is None:
+        out = allocate_solution(plan, data["Q"].device, bool(plan.options.multipliers))
+    sp = _lib.SolutionPtrs(out.x.data_ptr(), out.u.data_ptr(),
+                           out.lam.data_ptr() if out.lam is not None else None,
+                           out.mu.data_ptr() if out.mu is not None else None, out.status.data_ptr())
+    pp = _problem_ptrs(data)
+    wptr, wbytes = _aligned_ws(ws)
+    t = _lib.Tuning()
+    check(lib().eclqr_plan_autotune(plan.handle, C.byref(pp), C.byref(sp), C.c_void_p(wptr), C.c_size_t(wbytes),
+                                    _stream(), C.byref(t)), "eclqr_plan_autotune")
+    return _tuning_dict(t)
+
+
+def get_tuning(plan: Plan) -> Dict:
+    t = _lib.Tuning()
+    check(lib().eclqr_plan_get_tuning(plan.handle, C.byref(t)), "eclqr_plan_get_tuning")
+    return _tuning_dict(t)
+
+
+def set_tuning(plan: Plan, **kw) -> None:
+    t = _lib.Tuning()
+    check(lib().eclqr_plan_get_tuning(plan.handle, C.byref(t)), "eclqr_plan_get_tuning")
+    for k, v in kw.items():
+        if not hasattr(t, k):
+            raise KeyError(k)
+        setattr(t, k, v)
+    check(lib().eclqr_plan_set_tuning(plan.handle, C.byref(t)), "eclqr_plan_set_tuning")

@@ -276,3 +276,26 @@ def test_graph_replay_matches_eager():
         torch.cuda.synchronize()
         for f in ("x", "u", "lam", "mu", "status"):
             assert torch.equal(getattr(sol2, f), getattr(ref2, f)), ("new buffers", f)
+
+
+def test_autotune_keeps_results():
+    """eclqr_plan_autotune picks a launch configuration by timing; every
+    configuration it can choose computes the same solution (bitwise)."""
+    _need_gpu()
+    import paper_2407_05433_amd as ecl
+    from workloads import config_c3
+    probs = config_c3(B=8, N_range=(32, 90))
+    plan = ecl.Plan.for_problems(probs)
+    data = ecl.pack(plan, probs)
+    ws = plan.workspace()
+    ref = ecl.solve(plan, data, ws)
+    torch.cuda.synchronize()
+    ref = {f: getattr(ref, f).clone() for f in ("x", "u", "lam", "mu", "status")}
+    tuned = ecl.autotune(plan, data, ws)
+    assert tuned["ms_per_solve"] > 0
+    for cfg in ({"level_buckets": 0}, {"pool_in_lds": 0}, {"grid_divisor": 4}, {"use_graph": 1}, tuned):
+        ecl.set_tuning(plan, **{k: v for k, v in cfg.items() if k != "ms_per_solve"})
+        sol = ecl.solve(plan, data, ws)
+        torch.cuda.synchronize()
+        for f in ("x", "u", "lam", "mu", "status"):
+            assert torch.equal(getattr(sol, f), ref[f]), (cfg, f)
