@@ -203,7 +203,9 @@ typedef struct {
   int32_t pool_in_lds;    /* value-function combines keep their working pool in LDS when it fits */
   int32_t grid_divisor;   /* grid of the stage-parallel kernels = its maximum / grid_divisor (1..64) */
   double ms_per_solve;    /* time of the configuration chosen by eclqr_plan_autotune (0 if never tuned) */
-  int32_t reserved[4];
+  int32_t register_compose; /* relation compositions that fit (<= 64 stacked rows, <= 128 columns) keep the
+                             * stacked system in registers instead of LDS */
+  int32_t reserved[3];
 } eclqr_tuning;
 
 /* Time the caller's problem under alternative launch configurations

@@ -52,7 +52,7 @@ T* at(void* ws, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
 }
 
-int32_t g_pool_lds = 1, g_grid_div = 1, g_buckets = 1;  // tuning of the plan being launched
+int32_t g_pool_lds = 1, g_grid_div = 1, g_buckets = 1, g_reg = 1;  // tuning of the plan being launched
 
 DevEngine dev_engine(const Engine& E, void* ws, size_t base) {
   DevEngine d{};
@@ -80,6 +80,7 @@ DevEngine dev_engine(const Engine& E, void* ws, size_t base) {
   d.nslots = E.nslots;
   d.nblocks = std::max<int32_t>(1, E.nblocks / std::max<int32_t>(1, g_grid_div));
   d.pool_lds = g_pool_lds;
+  d.reg_compose = g_reg;
   return d;
 }
 
@@ -184,18 +185,27 @@ eclqr_status run_engine(const Engine& E, const DevEngine& d, const Inputs& in, d
   { Timed tm(ECLQR_K_VALIDATE, s); launch_validate(d, in, status, s); }
   { Timed tm(ECLQR_K_BASE_RELATION, s); launch_base_relation(d, in, t, status, E.base_maxp, E.base_ldw, s); }
   for (int l = 0; l < 2 * E.D; ++l) {
-    if (E.lvl_count[l] == 0) continue;
-    const int nb = g_buckets ? E.lvl_bkt_n[l] : 1;
-    for (int k = 0; k < nb; ++k) {
-      const int bk = E.lvl_bkt_first[l] + k;
-      const int64_t first = g_buckets ? E.bkt_begin[bk] : E.lvl_begin[l];
-      const int64_t count = g_buckets ? E.bkt_count[bk] : E.lvl_count[l];
-      const int ldw = g_buckets ? E.bkt_ldw[bk] : E.lvl_ldw[l];
+    // one launch per bucket, or (without buckets) per run of buckets of the
+    // same register fit: a task's kernel depends only on its own sizes
+    const int b0 = E.lvl_bkt_first[l], b1 = b0 + E.lvl_bkt_n[l];
+    for (int k = b0; k < b1;) {
+      int k1 = k + 1;
+      if (!g_buckets)
+        while (k1 < b1 && E.bkt_fit[k1] == E.bkt_fit[k]) ++k1;
+      int rows = 1, ldw = 1, kc = 0;
+      for (int q = k; q < k1; ++q) {
+        rows = std::max(rows, E.bkt_rows[q]);
+        ldw = std::max(ldw, E.bkt_ldw[q]);
+        kc = std::max(kc, E.bkt_kc[q]);
+      }
+      const int64_t first = E.bkt_begin[k];
+      const int64_t count = E.bkt_begin[k1 - 1] + E.bkt_count[k1 - 1] - first;
       // rows of the stacked system that fit the device's LDS (larger tasks are flagged ECLQR_CAPACITY)
-      int rows = std::max(1, g_buckets ? E.bkt_rows[bk] : E.lvl_rows[l]);
-      while (rows > 1 && rel_lds_bytes(rows, ldw) > (size_t)g_max_lds) --rows;
+      if (!E.bkt_fit[k])
+        while (rows > 1 && rel_lds_bytes(rows, ldw) > (size_t)g_max_lds) --rows;
       Timed tm(ECLQR_K_REL_COMPOSE, s);
-      launch_rel_compose(d, first, count, t, status, rows, ldw, s);
+      launch_rel_compose(d, first, count, t, status, rows, ldw, kc, s);
+      k = k1;
     }
   }
   { Timed tm(ECLQR_K_DOMAIN, s); launch_domain(d, in, t, status, std::max(1, E.maxn), s); }
@@ -280,6 +290,7 @@ Views views(Plan& p, void* ws) {
   g_pool_lds = p.pool_lds;
   g_grid_div = p.grid_divisor;
   g_buckets = p.level_buckets;
+  g_reg = p.reg_compose;
   Views v{};
   v.P = dev_engine(p.primal, ws, p.o_primal);
   v.D = dev_engine(p.dual, ws, p.o_dual);
@@ -751,6 +762,7 @@ eclqr_status eclqr_plan_get_tuning(const eclqr_plan* plan, eclqr_tuning* out) {
   out->level_buckets = p.level_buckets;
   out->pool_in_lds = p.pool_lds;
   out->grid_divisor = p.grid_divisor;
+  out->register_compose = p.reg_compose;
   out->ms_per_solve = p.tuned_ms;
   return ECLQR_SUCCESS;
 }
@@ -763,6 +775,7 @@ eclqr_status eclqr_plan_set_tuning(eclqr_plan* plan, const eclqr_tuning* t) {
   p.level_buckets = t->level_buckets != 0;
   p.pool_lds = t->pool_in_lds != 0;
   p.grid_divisor = t->grid_divisor;
+  p.reg_compose = t->register_compose != 0;
   release_graph(p);
   return ECLQR_SUCCESS;
 }
@@ -801,7 +814,8 @@ eclqr_status eclqr_plan_autotune(eclqr_plan* plan, const eclqr_problem* prob, ec
     int32_t alt;
   };
   int32_t graph = p.opt.use_graph;
-  Knob knobs[] = {{&p.level_buckets, p.level_buckets ? 0 : 1}, {&p.pool_lds, p.pool_lds ? 0 : 1},
+  Knob knobs[] = {{&p.reg_compose, p.reg_compose ? 0 : 1},
+                  {&p.level_buckets, p.level_buckets ? 0 : 1}, {&p.pool_lds, p.pool_lds ? 0 : 1},
                   {&p.grid_divisor, p.grid_divisor == 1 ? 4 : 1}, {&graph, graph ? 0 : 1}};
   for (Knob& k : knobs) {
     if (st != ECLQR_SUCCESS) break;

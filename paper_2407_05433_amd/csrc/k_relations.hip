@@ -4,6 +4,7 @@
 #include "dense.hpp"
 #include "device_util.hpp"
 #include "eclqr.h"
+#include "relreg.hpp"
 
 namespace eclqr {
 
@@ -307,6 +308,140 @@ __global__ void __launch_bounds__(kBlock) k_rel_compose(DevEngine e, int64_t fir
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// The composition of k_rel_compose with the stacked system in registers
+// (tasks with at most PR stacked rows, 64 NC columns and KC coefficient
+// columns after the elimination).  Logs in the phase-2 replay format.
+template <int PR, int NC, int KC>
+__global__ void __launch_bounds__(kBlock) k_rel_compose_reg(DevEngine e, int64_t first, int64_t ntasks, Tols t,
+                                                            int32_t* status) {
+  constexpr int QROWS = (PR > KC) ? PR : KC;
+  __shared__ double Qb[QROWS * (KC + 1)];
+  __shared__ double vbuf[PR];
+  __shared__ double pb[KC + 1];
+  __shared__ double dots[KC];
+  const int lane = ECLQR_TID;
+  for (int64_t ti = blockIdx.x; ti < ntasks; ti += gridDim.x) {
+    const int a = e.tasks[3 * (first + ti)];
+    const int bsl = e.tasks[3 * (first + ti) + 1];
+    const int o = e.tasks[3 * (first + ti) + 2];
+    const int sa = slot_a(e, 0, a), sb = slot_b(e, 0, a), sc = slot_b(e, 0, bsl);
+    if (gated(e, e.st[sa].inst)) continue;
+    const int na = e.st[sa].n, nb = e.st[sb].n, nc = (sc >= 0) ? e.st[sc].n : 0;
+    const int inst = e.st[sa].inst;
+    const int ra = e.slot_rows[a], rb = e.slot_rows[bsl];
+    const int p = ra + rb;
+    const int P = e.slot_cap[a] + e.slot_cap[bsl];
+    const int cap = e.slot_cap[o];
+    const RelLog lg = rel_log_layout(P, (nb < P) ? nb : P, cap);
+    double* glog = e.rel_log + e.rel_log_off[o];
+    const double* L = slot_ptr(e, SCAN_REL, a);
+    const double* Rr = slot_ptr(e, SCAN_REL, bsl);
+    double* out = slot_ptr(e, SCAN_REL, o);
+    const int c = nb + na + nc + 1, kc = na + nc;
+    if (ra == na + nb && rb == nb + nc && kc <= cap) {
+      int bad_full = 0;
+      point_compose(L, na + nb, ra, Rr, nb + nc, rb, na, nb, nc, Qb, t.cons, out, &bad_full);
+      if (lane == 0) {
+        glog[0] = 0;
+        glog[1] = 0;
+        glog[2] = kc;
+        glog[3] = 1;
+        e.slot_rows[o] = kc;
+        if (bad_full) flag(status, inst, ECLQR_INFEASIBLE_SUFFIX);
+      }
+      wg_sync();
+      continue;
+    }
+    if (p > PR || c > 64 * NC || kc > KC || cap > KC) {
+      if (lane == 0) {
+        glog[0] = 0;
+        glog[1] = 0;
+        glog[2] = 0;
+        glog[3] = 0;
+        e.slot_rows[o] = 0;
+        flag(status, inst, ECLQR_CAPACITY);
+      }
+      wg_sync();
+      continue;
+    }
+    // stacked system over the columns (b | a | c | 1), one column per lane
+    const int lda = na + nb + 1, ldb = nb + nc + 1;
+    double col[NC][PR];
+    double om = 0.0;
+#pragma unroll
+    for (int tt = 0; tt < NC; ++tt) {
+      const int j = lane + 64 * tt;
+#pragma unroll
+      for (int r = 0; r < PR; ++r) {
+        double v = 0.0;
+        if (r < p && j < c) {
+          if (r < ra) {
+            if (j < nb) v = L[r * lda + na + j];
+            else if (j < nb + na) v = L[r * lda + (j - nb)];
+            else if (j < nb + na + nc) v = 0.0;
+            else v = L[r * lda + na + nb];
+          } else {
+            const int q = r - ra;
+            if (j < nb) v = Rr[q * ldb + j];
+            else if (j < nb + na) v = 0.0;
+            else if (j < nb + na + nc) v = Rr[q * ldb + nb + (j - nb - na)];
+            else v = Rr[q * ldb + nb + nc];
+          }
+        }
+        col[tt][r] = v;
+        if (j == c - 1) om = fmax(om, fabs(v));
+      }
+    }
+    const double omax = fmax(1.0, wave_max(om));
+    const int R = (nb < P) ? nb : P;
+    const int rho = rr_phase1<PR, NC>(col, p, c, nb, t.rank, vbuf, glog + lg.V, P, glog + lg.tau, R);
+    // rows rho.. of the (a | c | 1) columns, one row per lane
+    const int q = p - rho;
+#pragma unroll
+    for (int tt = 0; tt < NC; ++tt) {
+      const int j = lane + 64 * tt;
+      if (j >= nb && j < c) {
+        const int k = (j == c - 1) ? KC : j - nb;
+#pragma unroll
+        for (int r = 0; r < PR; ++r)
+          if (r >= rho && r < p) Qb[(r - rho) * (KC + 1) + k] = col[tt][r];
+      }
+    }
+    for (int idx = lane; idx < q * (KC + 1); idx += 64) {
+      const int k = idx % (KC + 1);
+      if (k >= kc && k < KC) Qb[idx] = 0.0;
+    }
+    wg_sync();
+    double row[KC];
+    double off = 0.0;
+#pragma unroll
+    for (int k = 0; k < KC; ++k) row[k] = (lane < q) ? Qb[lane * (KC + 1) + k] : 0.0;
+    if (lane < q) off = Qb[lane * (KC + 1) + KC];
+    wg_sync();
+    int bad = 0, over = 0;
+    const int rr = rr_phase2<KC>(row, off, q, t.rank, t.cons * omax, Qb, pb, dots, cap, glog + lg.gs, lg.step, &bad,
+                                 &over);
+    const int lo = kc + 1;
+    if (!over)
+      for (int idx = lane; idx < rr * lo; idx += 64) {
+        const int r = idx / lo, j = idx - (idx / lo) * lo;
+        out[idx] = Qb[r * (KC + 1) + ((j < kc) ? j : KC)];
+      }
+    if (lane == 0) {
+      glog[0] = p;
+      glog[1] = rho;
+      glog[2] = over ? 0 : rr;
+      glog[3] = 2;
+      e.slot_rows[o] = over ? 0 : rr;
+      if (over) flag(status, inst, ECLQR_CAPACITY);
+      else if (bad) flag(status, inst, ECLQR_INFEASIBLE_SUFFIX);
+    }
+    wg_sync();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // State parameterisation (eqs. (state-param), (left-inverse)): T_i is an
 // orthonormal basis of null(H_i) (trailing columns of the Householder Q of
@@ -408,9 +543,25 @@ void launch_base_relation(const DevEngine& e, const Inputs& in, Tols t, int32_t*
 }
 
 void launch_rel_compose(const DevEngine& e, int64_t first, int64_t ntasks, Tols t, int32_t* status, int maxp, int ldw,
-                        hipStream_t s) {
+                        int maxkc, hipStream_t s) {
   if (ntasks <= 0) return;
   const int grid = (int)(ntasks < e.nblocks ? ntasks : e.nblocks);
+  // register-resident variant when every task of the launch fits it
+  if (e.reg_compose && maxp <= 64 && ldw <= 128 && maxkc <= 64) {
+    const bool r32 = maxp <= 32, c1 = ldw <= 64, k32 = maxkc <= 32;
+#define ECLQR_REG(PRV, NCV, KCV) \
+  hipLaunchKernelGGL((k_rel_compose_reg<PRV, NCV, KCV>), dim3(grid), dim3(kBlock), 0, s, e, first, ntasks, t, status)
+    if (r32 && c1 && k32) ECLQR_REG(32, 1, 32);
+    else if (r32 && c1) ECLQR_REG(32, 1, 64);
+    else if (r32 && k32) ECLQR_REG(32, 2, 32);
+    else if (r32) ECLQR_REG(32, 2, 64);
+    else if (c1 && k32) ECLQR_REG(64, 1, 32);
+    else if (c1) ECLQR_REG(64, 1, 64);
+    else if (k32) ECLQR_REG(64, 2, 32);
+    else ECLQR_REG(64, 2, 64);
+#undef ECLQR_REG
+    return;
+  }
   hipLaunchKernelGGL(k_rel_compose, dim3(grid), dim3(kBlock), rel_lds_bytes(maxp, ldw), s, e, first, ntasks, t,
                      status, maxp, ldw);
 }

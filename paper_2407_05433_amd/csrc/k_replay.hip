@@ -108,6 +108,52 @@ __device__ inline void rel_replay(double* o, const double* lg, const RelLog& L, 
   *rr_out = rr;
 }
 
+// Replay of the register-resident factorization's log: the reflectors as
+// above, then the phase-2 records with the remaining rows' offsets held one
+// per lane (q <= 64) and the chosen rows' offsets in selection order.
+__device__ inline void rel_replay_reg(double* o, const double* lg, const RelLog& L, int P, int R, int C, int* rho_out,
+                                      int* rr_out) {
+  const int lane = ECLQR_TID;
+  int p = (int)lg[0], rho = (int)lg[1], rr = (int)lg[2];
+  p = (p < 0) ? 0 : ((p > P) ? P : p);
+  rho = (rho < 0) ? 0 : ((rho > R) ? R : rho);
+  rho = (rho > p) ? p : rho;
+  int q = p - rho;
+  q = (q > 64) ? 64 : q;
+  rr = (rr < 0) ? 0 : ((rr > C) ? C : rr);
+  rr = (rr > q) ? q : rr;
+  rr = (rr > 64) ? 64 : rr;
+  for (int j = 0; j < rho; ++j) {
+    const double* v = lg + L.V + (int64_t)j * P;
+    double part = 0.0;
+    for (int row = j + 1 + lane; row < p; row += ECLQR_NT) part = fma(v[row], o[row], part);
+    const double w = (o[j] + wave_sum(part)) * lg[L.tau + j];
+    wg_sync();
+    if (lane == 0) o[j] -= w;
+    for (int row = j + 1 + lane; row < p; row += ECLQR_NT) o[row] = fma(-w, v[row], o[row]);
+    wg_sync();
+  }
+  double v = (lane < q) ? o[rho + lane] : 0.0;
+  bool chosen = lane >= q;
+  double qoff = 0.0;
+  for (int sel = 0; sel < rr; ++sel) {
+    const double* rec = lg + L.gs + (int64_t)sel * L.step;
+    int piv = (int)rec[0];
+    piv = (piv < 0 || piv >= q) ? 0 : piv;
+    const double vp = __shfl(v, piv, 64);
+    const double part = (lane < sel) ? rec[2 + lane] * qoff : 0.0;
+    const double nv = (vp - wave_sum(part)) * rec[1];
+    if (lane == sel) qoff = nv;
+    if (lane == piv) chosen = true;
+    if (!chosen) v = fma(-rec[2 + C + lane], nv, v);
+  }
+  wg_sync();
+  if (lane < rr) o[rho + lane] = qoff;
+  wg_sync();
+  *rho_out = rho;
+  *rr_out = rr;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -175,7 +221,8 @@ __global__ void __launch_bounds__(kBlock) k_rel_compose_vec(DevEngine e, int64_t
       o[r] = (r < ra) ? Ls[r * lda + na + nb] : Rs[(r - ra) * ldb + nb + nc];
     wg_sync();
     int rho = 0, rr = 0;
-    rel_replay(o, lg, L, P, (nb < P) ? nb : P, cap, false, &rho, &rr);
+    if (lg[3] == 2.0) rel_replay_reg(o, lg, L, P, (nb < P) ? nb : P, cap, &rho, &rr);
+    else rel_replay(o, lg, L, P, (nb < P) ? nb : P, cap, false, &rho, &rr);
     if (rr > e.slot_rows[oo]) rr = e.slot_rows[oo];
     const int lo = na + nc + 1;
     double* out = slot_ptr(e, SCAN_REL, oo);

@@ -34,6 +34,7 @@ struct DevEngine {
   int32_t nslots;
   int32_t nblocks;            // grid size of the stage-parallel kernels (grid-stride)
   int32_t pool_lds;           // 1: value-function combines keep their pool in LDS when it fits
+  int32_t reg_compose;        // 1: relation compositions that fit run register-resident
 };
 
 // Pointers to one problem's data (caller layout of the engine).
@@ -59,8 +60,9 @@ size_t ric_lds_bytes(int maxd);
 size_t gains_lds_bytes(int maxm);
 void launch_base_relation(const DevEngine& e, const Inputs& in, Tols t, int32_t* status, int maxp, int ldw,
                           hipStream_t s);
+// maxkc: most coefficient columns (n_a + n_c) of a result in the launch
 void launch_rel_compose(const DevEngine& e, int64_t first_task, int64_t ntasks, Tols t, int32_t* status, int maxp,
-                        int ldw, hipStream_t s);
+                        int ldw, int maxkc, hipStream_t s);
 void launch_domain(const DevEngine& e, const Inputs& in, Tols t, int32_t* status, int maxn, hipStream_t s);
 void launch_eliminate(const DevEngine& e, const Inputs& in, Tols t, int32_t* status, int maxm, int maxq,
                       hipStream_t s);

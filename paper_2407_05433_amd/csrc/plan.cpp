@@ -255,6 +255,9 @@ std::string Engine::build(const eclqr_dims* d) {
   lvl_rows.assign(2 * D, 0);
   lvl_dim.assign(2 * D, 0);
   lvl_ldw.assign(2 * D, 1);
+  lvl_kc.assign(2 * D, 0);
+  bkt_kc.clear();
+  bkt_fit.clear();
   bkt_begin.clear();
   bkt_count.clear();
   bkt_rows.clear();
@@ -277,7 +280,14 @@ std::string Engine::build(const eclqr_dims* d) {
     const int64_t b0 = lvl_begin[l], nt = lvl_count[l];
     std::vector<std::array<int32_t, 3>> tv((size_t)nt);
     for (int64_t t = 0; t < nt; ++t) tv[t] = {tasks[3 * (b0 + t)], tasks[3 * (b0 + t) + 1], tasks[3 * (b0 + t) + 2]};
+    // tasks that fit the register-resident composition first, each part by size
+    auto fits = [&](int a, int c) {
+      return slot_cap[a] + slot_cap[c] <= 64 && task_ldw(a, c) <= 128 &&
+             slot_na[SCAN_REL][a] + slot_nb[SCAN_REL][c] <= 64;
+    };
     std::stable_sort(tv.begin(), tv.end(), [&](const std::array<int32_t, 3>& x, const std::array<int32_t, 3>& y) {
+      const bool fx = fits(x[0], x[1]), fy = fits(y[0], y[1]);
+      if (fx != fy) return fx;
       return task_need(x[0], x[1]) < task_need(y[0], y[1]);
     });
     for (int64_t t = 0; t < nt; ++t)
@@ -287,24 +297,32 @@ std::string Engine::build(const eclqr_dims* d) {
     while (t < nt) {
       int64_t u = t + 1;
       const int cls = lg2(std::max<int64_t>(1, task_need(tv[t][0], tv[t][1])));
+      const bool fit = fits(tv[t][0], tv[t][1]);
+      // end of this fit class
+      int64_t end = t + 1;
+      while (end < nt && fits(tv[end][0], tv[end][1]) == fit) ++end;
       if (nt >= 2048) {
-        while (u < nt && lg2(std::max<int64_t>(1, task_need(tv[u][0], tv[u][1]))) == cls) ++u;
-        while (u < nt && u - t < 512) ++u;
-        if (nt - u < 512) u = nt;
+        while (u < end && lg2(std::max<int64_t>(1, task_need(tv[u][0], tv[u][1]))) == cls) ++u;
+        while (u < end && u - t < 512) ++u;
+        if (end - u < 512) u = end;
       } else {
-        u = nt;
+        u = end;
       }
-      int rows = 0, ldw = 1, dim = 0;
+      int rows = 0, ldw = 1, dim = 0, kc = 0;
       for (int64_t v = t; v < u; ++v) {
         rows = std::max(rows, slot_cap[tv[v][0]] + slot_cap[tv[v][1]]);
         ldw = std::max(ldw, task_ldw(tv[v][0], tv[v][1]));
         dim = std::max(dim, task_dim(tv[v][0], tv[v][1]));
+        kc = std::max(kc, slot_na[SCAN_REL][tv[v][0]] + slot_nb[SCAN_REL][tv[v][1]]);
       }
       bkt_begin.push_back(b0 + t);
       bkt_count.push_back(u - t);
       bkt_rows.push_back(rows);
       bkt_ldw.push_back(ldw);
       bkt_dim.push_back(dim);
+      bkt_kc.push_back(kc);
+      bkt_fit.push_back(fit ? 1 : 0);
+      lvl_kc[l] = std::max(lvl_kc[l], kc);
       lvl_rows[l] = std::max(lvl_rows[l], rows);
       lvl_ldw[l] = std::max(lvl_ldw[l], ldw);
       lvl_dim[l] = std::max(lvl_dim[l], dim);

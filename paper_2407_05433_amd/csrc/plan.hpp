@@ -43,7 +43,9 @@ struct Engine {
   std::vector<int32_t> lvl_ldw;     // REL: max (n_a + n_b + n_c + 1) over the level
   // launch buckets of each level: task ranges with their own LDS sizing
   std::vector<int64_t> bkt_begin, bkt_count;
-  std::vector<int32_t> bkt_rows, bkt_ldw, bkt_dim;
+  std::vector<int32_t> bkt_rows, bkt_ldw, bkt_dim, bkt_kc;
+  std::vector<int32_t> bkt_fit;     // every task of the bucket fits the register-resident composition
+  std::vector<int32_t> lvl_kc;      // REL: max (n_a + n_c) over the level
   std::vector<int32_t> lvl_bkt_first, lvl_bkt_n;
 
   // factor logs replayed by the vector-only pass, per output slot
@@ -88,6 +90,7 @@ struct Plan {
   int32_t level_buckets = 1;  // relation levels launch in LDS-size buckets
   int32_t pool_lds = 1;       // value-function combine pool in LDS when it fits
   int32_t grid_divisor = 1;   // grid of the stage-parallel kernels = nblocks / divisor
+  int32_t reg_compose = 1;    // register-resident relation compositions where they fit
   double tuned_ms = 0.0;
   void* graph_exec = nullptr;
   void* capture_stream = nullptr;  // plan-owned stream the sequence is captured on

@@ -291,11 +291,21 @@ def test_autotune_keeps_results():
     ref = ecl.solve(plan, data, ws)
     torch.cuda.synchronize()
     ref = {f: getattr(ref, f).clone() for f in ("x", "u", "lam", "mu", "status")}
+    base = ecl.get_tuning(plan)
     tuned = ecl.autotune(plan, data, ws)
     assert tuned["ms_per_solve"] > 0
-    for cfg in ({"level_buckets": 0}, {"pool_in_lds": 0}, {"grid_divisor": 4}, {"use_graph": 1}, tuned):
-        ecl.set_tuning(plan, **{k: v for k, v in cfg.items() if k != "ms_per_solve"})
+    for cfg in ({"level_buckets": 0}, {"pool_in_lds": 0}, {"grid_divisor": 4}, {"use_graph": 1},
+                {"register_compose": 0}, tuned):
+        full = dict(base)
+        full.update(cfg)
+        ecl.set_tuning(plan, **{k: v for k, v in full.items() if k != "ms_per_solve"})
         sol = ecl.solve(plan, data, ws)
         torch.cuda.synchronize()
         for f in ("x", "u", "lam", "mu", "status"):
-            assert torch.equal(getattr(sol, f), ref[f]), (cfg, f)
+            if full["register_compose"] == base["register_compose"]:
+                assert torch.equal(getattr(sol, f), ref[f]), (cfg, f)
+            else:
+                # the LDS and register compositions differ in rounding only
+                a, b = getattr(sol, f).double(), ref[f].double()
+                err = float((a - b).norm() / max(float(b.norm()), 1e-300))
+                assert err <= 1e-8, (cfg, f, err)
