@@ -21,6 +21,17 @@ namespace eclqr {
 
 __device__ __forceinline__ void wg_sync() { __syncthreads(); }
 
+// Orders LDS traffic between the lanes of the one-wavefront workgroup.  The
+// LDS instructions of a wave execute in issue order, so it is enough that the
+// compiler moves no memory operation across this point; unlike wg_sync it
+// does not wait for outstanding global stores.  Only for code whose
+// cross-lane data lives in LDS or registers (global memory written in the
+// section is not read back in it).
+__device__ __forceinline__ void lds_sync() {
+  __builtin_amdgcn_wave_barrier();
+  __asm__ volatile("" ::: "memory");
+}
+
 // Butterfly reductions over the 64 lanes; every lane ends with the same bits
 // (each combination step adds the same two partials in either order).
 __device__ __forceinline__ double wave_max(double v) {
@@ -217,7 +228,7 @@ struct QRScratch {
 __device__ inline int wg_qr_colpiv(double* W, int ld, int p, int c, int c0, int cp, double thr, double* tau,
                                    QRScratch sc) {
   for (int j = ECLQR_TID; j < cp; j += ECLQR_NT) sc.perm[j] = j;
-  wg_sync();
+  lds_sync();
   const int steps = (p < cp) ? p : cp;
   int r = 0;
   double ref = 1.0;
@@ -241,7 +252,7 @@ __device__ inline int wg_qr_colpiv(double* W, int ld, int p, int c, int c0, int 
     const double beta = -copysign(nrm, x0);
     const double tj = (beta - x0) / beta;
     const double scale = 1.0 / (x0 - beta);
-    wg_sync();
+    lds_sync();
     if (ECLQR_TID == 0) {
       const int tp = sc.perm[j];
       sc.perm[j] = sc.perm[pc];
@@ -253,11 +264,11 @@ __device__ inline int wg_qr_colpiv(double* W, int ld, int p, int c, int c0, int 
         W[row * ld + c0 + j] = W[row * ld + c0 + pc];
         W[row * ld + c0 + pc] = a;
       }
-      wg_sync();
+      lds_sync();
     }
     for (int row = j + 1 + ECLQR_TID; row < p; row += ECLQR_NT) W[row * ld + c0 + j] *= scale;
     if (ECLQR_TID == 0) tau[j] = tj;
-    wg_sync();
+    lds_sync();
     for (int col = ECLQR_TID; col < c; col += ECLQR_NT) {
       // skip this and the earlier pivot columns (they hold reflectors below the diagonal)
       if (col >= c0 && col <= c0 + j) continue;
@@ -267,9 +278,9 @@ __device__ inline int wg_qr_colpiv(double* W, int ld, int p, int c, int c0, int 
       W[j * ld + col] -= w;
       lane_axpy(y, ld, v, ld, p - j - 1, -w);
     }
-    wg_sync();
+    lds_sync();
     if (ECLQR_TID == 0) W[j * ld + c0 + j] = beta;
-    wg_sync();
+    lds_sync();
     r = j + 1;
   }
   return r;
@@ -284,7 +295,7 @@ __device__ inline void wg_log_reflectors(const double* W, int ld, int p, int c0,
     V[(int64_t)j * P + row] = (row > j) ? W[row * ld + c0 + j] : 0.0;
   }
   for (int j = ECLQR_TID; j < r; j += ECLQR_NT) tlog[j] = tau[j];
-  wg_sync();
+  lds_sync();
 }
 
 // Apply Q = H_0 H_1 ... H_{r-1} (reflectors stored by wg_qr_colpiv in the
@@ -347,7 +358,7 @@ __device__ inline int wg_row_basis(double* W, int ld, int r0, int p, int k0, int
         W[base * ld + k0 + cc] = W[best * ld + k0 + cc];
         W[best * ld + k0 + cc] = a;
       }
-      wg_sync();
+      lds_sync();
     }
     // re-orthogonalise the pivot row against the chosen rows (one pass)
     if (sel > 0) {
@@ -356,19 +367,19 @@ __device__ inline int wg_row_basis(double* W, int ld, int r0, int p, int k0, int
         dots[l] = d;
         if (rec) rec[2 + l] = d;
       }
-      wg_sync();
+      lds_sync();
       for (int cc = ECLQR_TID; cc <= kc; cc += ECLQR_NT)
         W[base * ld + k0 + cc] -= lane_dot(dots, 1, W + r0 * ld + k0 + cc, ld, sel);
-      wg_sync();
+      lds_sync();
     }
     // normalise (offset included)
     double s = 0.0;
     for (int cc = ECLQR_TID; cc < kc; cc += ECLQR_NT) s = fma(W[base * ld + k0 + cc], W[base * ld + k0 + cc], s);
     const double inv = 1.0 / sqrt(wave_sum(s));
     if (rec && ECLQR_TID == 0) rec[1] = inv;
-    wg_sync();
+    lds_sync();
     for (int cc = ECLQR_TID; cc <= kc; cc += ECLQR_NT) W[base * ld + k0 + cc] *= inv;
-    wg_sync();
+    lds_sync();
     // project the pivot row out of the remaining rows
     for (int rr = base + 1 + ECLQR_TID; rr < p; rr += ECLQR_NT) {
       double* row = W + rr * ld + k0;
@@ -377,7 +388,7 @@ __device__ inline int wg_row_basis(double* W, int ld, int r0, int p, int k0, int
       lane_axpy(row, 1, piv, 1, kc + 1, -d);
       if (rec) rec[2 + gcap + rr] = d;
     }
-    wg_sync();
+    lds_sync();
     ++sel;
   }
   // consistency of the dependent rows
@@ -385,7 +396,7 @@ __device__ inline int wg_row_basis(double* W, int ld, int r0, int p, int k0, int
   for (int rr = r0 + sel + ECLQR_TID; rr < p; rr += ECLQR_NT)
     if (fabs(W[rr * ld + k0 + kc]) > cons_thr) any = 1.0;
   *bad = (wave_max(any) != 0.0) ? 1 : 0;
-  wg_sync();
+  lds_sync();
   return sel;
 }
 

@@ -351,7 +351,7 @@ __global__ void __launch_bounds__(kBlock) k_rel_compose_reg(DevEngine e, int64_t
         e.slot_rows[o] = kc;
         if (bad_full) flag(status, inst, ECLQR_INFEASIBLE_SUFFIX);
       }
-      wg_sync();
+      lds_sync();
       continue;
     }
     if (p > PR || c > 64 * NC || kc > KC || cap > KC) {
@@ -363,7 +363,7 @@ __global__ void __launch_bounds__(kBlock) k_rel_compose_reg(DevEngine e, int64_t
         e.slot_rows[o] = 0;
         flag(status, inst, ECLQR_CAPACITY);
       }
-      wg_sync();
+      lds_sync();
       continue;
     }
     // stacked system over the columns (b | a | c | 1), one column per lane
@@ -413,13 +413,13 @@ __global__ void __launch_bounds__(kBlock) k_rel_compose_reg(DevEngine e, int64_t
       const int k = idx % (KC + 1);
       if (k >= kc && k < KC) Qb[idx] = 0.0;
     }
-    wg_sync();
+    lds_sync();
     double row[KC];
     double off = 0.0;
 #pragma unroll
     for (int k = 0; k < KC; ++k) row[k] = (lane < q) ? Qb[lane * (KC + 1) + k] : 0.0;
     if (lane < q) off = Qb[lane * (KC + 1) + KC];
-    wg_sync();
+    lds_sync();
     int bad = 0, over = 0;
     const int rr = rr_phase2<KC>(row, off, q, t.rank, t.cons * omax, Qb, pb, dots, cap, glog + lg.gs, lg.step, &bad,
                                  &over);
@@ -438,7 +438,7 @@ __global__ void __launch_bounds__(kBlock) k_rel_compose_reg(DevEngine e, int64_t
       if (over) flag(status, inst, ECLQR_CAPACITY);
       else if (bad) flag(status, inst, ECLQR_INFEASIBLE_SUFFIX);
     }
-    wg_sync();
+    lds_sync();
   }
 }
 

@@ -69,7 +69,7 @@ __device__ inline int rr_phase1(double (&col)[NC][PR], int p, int c, int nb, dou
           used[t] = true;
         }
     }
-    wg_sync();
+    lds_sync();
     const double x0 = vbuf[j];
     const double beta = -copysign(nrm, x0);
     const double tj = (beta - x0) / beta;
@@ -98,7 +98,7 @@ __device__ inline int rr_phase1(double (&col)[NC][PR], int p, int c, int nb, dou
         }
       }
     }
-    wg_sync();
+    lds_sync();
     rho = j + 1;
   }
   return rho;
@@ -141,16 +141,16 @@ __device__ inline int rr_phase2(double (&row)[KC], double& off, int q, double th
       chosen = true;
       rec[0] = (double)best;
     }
-    wg_sync();
+    lds_sync();
     if (sel > 0) {
       for (int l = lane; l < sel; l += 64) {
         const double d = lane_dot(Q + (int64_t)l * (KC + 1), 1, pb, 1, KC);
         dots[l] = d;
         rec[2 + l] = d;
       }
-      wg_sync();
+      lds_sync();
       for (int k = lane; k <= KC; k += 64) pb[k] -= lane_dot(dots, 1, Q + k, KC + 1, sel);
-      wg_sync();
+      lds_sync();
     }
     double part = 0.0;
     for (int k = lane; k < KC; k += 64) part = fma(pb[k], pb[k], part);
@@ -158,7 +158,7 @@ __device__ inline int rr_phase2(double (&row)[KC], double& off, int q, double th
     if (lane == 0) rec[1] = inv;
     double* qs = Q + (int64_t)sel * (KC + 1);
     for (int k = lane; k <= KC; k += 64) qs[k] = pb[k] * inv;
-    wg_sync();
+    lds_sync();
     if (!chosen) {
       double d0 = 0.0, d1 = 0.0;
 #pragma unroll
@@ -176,7 +176,7 @@ __device__ inline int rr_phase2(double (&row)[KC], double& off, int q, double th
   }
   const double any = (!chosen && fabs(off) > cons_thr) ? 1.0 : 0.0;
   *bad = (wave_max(any) != 0.0) ? 1 : 0;
-  wg_sync();
+  lds_sync();
   return sel;
 }
 
