@@ -201,6 +201,8 @@ def main():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--graph", type=int, default=1, help="replay the solve as a captured hipGraph (1) or launch eagerly (0)")
     ap.add_argument("--autotune", type=int, default=1, help="choose the launch configuration by timing first (untimed)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device once (reference for hardware byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver has no multi-GPU path (batches and horizons shard "
@@ -208,6 +210,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_mib": args.copy_calibration, "bytes_read": n * 8, "bytes_written": n * 8}))
+        return
     import paper_2407_05433_amd as ecl
     from paper_2407_05433_amd import flops as flopmodel
 

@@ -343,8 +343,7 @@ __global__ void __launch_bounds__(kBlock) k_fwd_combine(DevEngine e, int64_t fir
 
 // Recovery (eq. (recovery-maps)): v_i = K_i z_i + k_i, x_i = T_i z_i + t_i,
 // u_i = Y_i z_i + Z_i v_i + y_i.
-__global__ void __launch_bounds__(kBlock) k_recover(DevEngine e, double* x, double* u, int64_t xoff_field,
-                                                    int64_t uoff_field) {
+__global__ void __launch_bounds__(kBlock) k_recover(DevEngine e, double* x, double* u) {
   __shared__ double vsh[kMaxDim];
   for (int64_t s = blockIdx.x; s < e.S; s += gridDim.x) {
     const StageInfo st = e.st[s];
@@ -354,7 +353,7 @@ __global__ void __launch_bounds__(kBlock) k_recover(DevEngine e, double* x, doub
     const double* base = e.arena + st.ws;
     const int nb = e.nbar[s];
     const double* z = slot_ptr(e, SCAN_FWD, st.suf[SCAN_FWD]);
-    double* xo = x + st.in[xoff_field];
+    double* xo = x + st.in[IN_q];
     const double* T = base + ar.T;
     const double* tv = base + ar.t;
     for (int i = ECLQR_TID; i < n; i += ECLQR_NT) {
@@ -371,7 +370,7 @@ __global__ void __launch_bounds__(kBlock) k_recover(DevEngine e, double* x, doub
         vsh[i] = v;
       }
       __syncthreads();
-      double* uo = u + st.in[uoff_field];
+      double* uo = u + st.in[IN_r];
       for (int i = ECLQR_TID; i < m; i += ECLQR_NT) {
         double v = y[i];
         for (int l = 0; l < nb; ++l) v = fma(Y[i * nb + l], z[l], v);
@@ -420,7 +419,7 @@ void launch_fwd_combine(const DevEngine& e, int64_t first, int64_t ntasks, hipSt
 }
 
 void launch_recover(const DevEngine& e, double* x, double* u, hipStream_t s) {
-  hipLaunchKernelGGL(k_recover, dim3(e.nblocks), dim3(kBlock), 0, s, e, x, u, (int64_t)IN_q, (int64_t)IN_r);
+  hipLaunchKernelGGL(k_recover, dim3(e.nblocks), dim3(kBlock), 0, s, e, x, u);
 }
 
 }  // namespace eclqr

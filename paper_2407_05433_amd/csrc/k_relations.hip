@@ -548,13 +548,15 @@ void launch_rel_compose(const DevEngine& e, int64_t first, int64_t ntasks, Tols 
   const int grid = (int)(ntasks < e.nblocks ? ntasks : e.nblocks);
   // register-resident variant when every task of the launch fits it
   if (e.reg_compose && maxp <= 64 && ldw <= 128 && maxkc <= 64) {
-    const bool r32 = maxp <= 32, c1 = ldw <= 64, k32 = maxkc <= 32;
+    const bool r32 = maxp <= 32, r48 = maxp <= 48, c1 = ldw <= 64, k32 = maxkc <= 32;
 #define ECLQR_REG(PRV, NCV, KCV) \
   hipLaunchKernelGGL((k_rel_compose_reg<PRV, NCV, KCV>), dim3(grid), dim3(kBlock), 0, s, e, first, ntasks, t, status)
     if (r32 && c1 && k32) ECLQR_REG(32, 1, 32);
     else if (r32 && c1) ECLQR_REG(32, 1, 64);
     else if (r32 && k32) ECLQR_REG(32, 2, 32);
     else if (r32) ECLQR_REG(32, 2, 64);
+    else if (r48 && c1 && k32) ECLQR_REG(48, 1, 32);
+    else if (r48 && k32) ECLQR_REG(48, 2, 32);
     else if (c1 && k32) ECLQR_REG(64, 1, 32);
     else if (c1) ECLQR_REG(64, 1, 64);
     else if (k32) ECLQR_REG(64, 2, 32);
