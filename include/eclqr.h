@@ -200,7 +200,9 @@ eclqr_status eclqr_plan_set_profiling(eclqr_plan* plan, int32_t on);
 typedef struct {
   int32_t use_graph;      /* replay the solve as a captured hipGraph */
   int32_t level_buckets;  /* relation-scan levels with >= 2048 tasks launch in LDS-size buckets */
-  int32_t pool_in_lds;    /* value-function combines keep their working pool in LDS when it fits */
+  int32_t pool_in_lds;    /* value-function combines: 0 work pool in global scratch, 1 pool in LDS, 2 operands,
+                             result and pool in LDS (default); a mode whose LDS does not fit falls back to the
+                             next lower one */
   int32_t grid_divisor;   /* grid of the stage-parallel kernels = its maximum / grid_divisor (1..64) */
   double ms_per_solve;    /* time of the configuration chosen by eclqr_plan_autotune (0 if never tuned) */
   int32_t register_compose; /* relation compositions that fit (<= 64 stacked rows, <= 128 columns) keep the
@@ -250,6 +252,14 @@ eclqr_status eclqr_plan_backward_error(const eclqr_plan* plan, const void* ws, d
  * slot count, rows (host, may be NULL) nslots entries.  Synchronises. */
 eclqr_status eclqr_plan_scan_rows(const eclqr_plan* plan, const void* ws, int32_t which, int32_t* rows,
                                   int32_t* nslots);
+
+/* Form of the value-function combine that produced every scan slot in the
+ * last solve in ws (reduced LQR scan, Section VI): 0 none (a leaf, or an
+ * instance that was skipped), 1 Cholesky-factored, 2 LU (the middle value
+ * function was not numerically positive definite).  forms (host, may be NULL)
+ * receives *nslots entries.  Synchronises. */
+eclqr_status eclqr_plan_combine_forms(const eclqr_plan* plan, const void* ws, int32_t which, int32_t* forms,
+                                      int32_t* nslots);
 
 /* Interval of every scan slot: instance, first leaf, one past the last leaf
  * (leaf N_b is the terminal; a slot whose end is N_b + 1 is unary).  Host

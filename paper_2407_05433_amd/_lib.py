@@ -105,6 +105,9 @@ def lib():
     L.eclqr_kernel_class_name.argtypes = [C.c_int32]
     L.eclqr_plan_reduced_dims.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32),
                                           C.POINTER(C.c_int32)]
+    L.eclqr_plan_combine_forms.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32),
+                                           C.POINTER(C.c_int32)]
+    L.eclqr_plan_combine_forms.restype = C.c_int
     L.eclqr_plan_scan_rows.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32),
                                        C.POINTER(C.c_int32)]
     L.eclqr_plan_refine_steps.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]

@@ -52,7 +52,7 @@ T* at(void* ws, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
 }
 
-int32_t g_pool_lds = 1, g_grid_div = 1, g_buckets = 1, g_reg = 1;  // tuning of the plan being launched
+int32_t g_pool_lds = 2, g_grid_div = 1, g_buckets = 1, g_reg = 1;  // tuning of the plan being launched
 
 DevEngine dev_engine(const Engine& E, void* ws, size_t base) {
   DevEngine d{};
@@ -169,11 +169,13 @@ eclqr_status bind(Plan& p, void* ws, hipStream_t s) {
     relations_set_max_lds(lds);
     eliminate_set_max_lds(lds);
     lqr_set_max_lds(lds);
+    replay_set_max_lds(lds);
   }
   eclqr_status st = upload_engine(p.primal, ws, p.o_primal, s);
   if (st != ECLQR_SUCCESS) return st;
   st = upload_engine(p.dual, ws, p.o_dual, s);
   if (st != ECLQR_SUCCESS) return st;
+  launch_fill_i32(reinterpret_cast<int32_t*>(static_cast<char*>(ws) + p.o_live), 1, 1, s);
   p.bound_ws = ws;
   p.bound_device = dev;
   return ECLQR_SUCCESS;
@@ -230,18 +232,18 @@ eclqr_status run_engine(const Engine& E, const DevEngine& d, const Inputs& in, d
 // this engine logged in the workspace (no rank decisions, no outcome bits).
 eclqr_status run_engine_vec(const Engine& E, const DevEngine& d, const Inputs& in, double* x, double* u,
                             hipStream_t s) {
-  { Timed tm(ECLQR_K_REPLAY, s); launch_base_relation_vec(d, in, s); }
+  { Timed tm(ECLQR_K_REPLAY, s); launch_base_relation_vec(d, in, E.base_rel_log, s); }
   for (int l = 0; l < 2 * E.D; ++l) {
     if (E.lvl_count[l] == 0) continue;
     Timed tm(ECLQR_K_REPLAY, s);
-    launch_rel_compose_vec(d, E.lvl_begin[l], E.lvl_count[l], s);
+    launch_rel_compose_vec(d, E.lvl_begin[l], E.lvl_count[l], E.lvl_rel_log[l], s);
   }
   { Timed tm(ECLQR_K_REPLAY, s); launch_domain_vec(d, in, s); }
   { Timed tm(ECLQR_K_REPLAY, s); launch_eliminate_vec(d, in, s); }
   for (int l = 0; l < 2 * E.D; ++l) {
     if (E.lvl_count[l] == 0) continue;
     Timed tm(ECLQR_K_REPLAY, s);
-    launch_ric_combine_vec(d, E.lvl_begin[l], E.lvl_count[l], s);
+    launch_ric_combine_vec(d, E.lvl_begin[l], E.lvl_count[l], std::max(1, E.lvl_dim[l]), s);
   }
   { Timed tm(ECLQR_K_REPLAY, s); launch_gains_vec(d, s); }
   for (int l = 0; l < 2 * E.D; ++l) {
@@ -279,6 +281,7 @@ struct Views {
   int32_t* dstatus;
   double *cx, *cu, *clam, *cmu;
   int32_t* gate;
+  int32_t* live;
   int32_t* rsteps;
   unsigned long long* omega;
   double* rnorm;
@@ -318,6 +321,9 @@ Views views(Plan& p, void* ws) {
   v.zero = at<double>(ws, p.o_zero);
   v.P.gate = v.gate;
   v.D.gate = v.gate;
+  v.live = at<int32_t>(ws, p.o_live);
+  v.P.live = v.live;
+  v.D.live = v.live;
   return v;
 }
 
@@ -373,6 +379,7 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
   {
     Timed tm(ECLQR_K_REFINE_IO, s);
     launch_fill_i32(v.gate, kGateActive, B, s);
+    launch_fill_i32(v.live, 1, 1, s);
     launch_fill_i32(v.rsteps, 0, B, s);
     launch_fill_u64(v.omega, 0ull, B, s);
   }
@@ -407,7 +414,7 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
   for (int it = 0; it < nref; ++it) {
     {
       Timed tm(ECLQR_K_REFINE_IO, s);
-      launch_gate_advance(v.gate, B, s);
+      launch_gate_advance(v.gate, v.live, B, s);
       launch_correction(v.P, in, x, u, lam, mu, v.cp, s);
     }
     st = run_engine_vec(p.primal, v.P, cin, v.cx, v.cu, s);
@@ -423,6 +430,7 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
   {
     Timed tm(ECLQR_K_REFINE_IO, s);
     launch_fill_i32(v.gate, kGateActive, B, s);  // later launches on this workspace run every instance
+    launch_fill_i32(v.live, 1, 1, s);
     launch_fill_u64(v.omega, 0ull, B, s);
     launch_backward_error(v.P, in, x, u, lam, mu, v.omega, s);
     launch_flag_unconverged(v.omega, v.rsteps, p.opt.dual_cons_tol, status, ECLQR_DUAL_FAILED, B, s);
@@ -741,6 +749,26 @@ eclqr_status eclqr_plan_scan_rows(const eclqr_plan* plan, const void* ws, int32_
   return ECLQR_SUCCESS;
 }
 
+eclqr_status eclqr_plan_combine_forms(const eclqr_plan* plan, const void* ws, int32_t which, int32_t* forms,
+                                      int32_t* nslots) {
+  if (!plan) return fail(ECLQR_INVALID_ARGUMENT, "NULL plan");
+  const Plan& p = plan->p;
+  const Engine& E = which ? p.dual : p.primal;
+  if (nslots) *nslots = E.nslots;
+  if (!forms) return ECLQR_SUCCESS;
+  if (!ws) return fail(ECLQR_INVALID_ARGUMENT, "NULL workspace");
+  const char* b = static_cast<const char*>(ws) + (which ? p.o_dual : p.o_primal);
+  std::vector<double> lg((size_t)std::max<int64_t>(1, E.ric_log_total));
+  HIP_OK(hipDeviceSynchronize());
+  HIP_OK(hipMemcpy(lg.data(), b + E.o_ric_log, sizeof(double) * lg.size(), hipMemcpyDeviceToHost));
+  for (int32_t q = 0; q < E.nslots; ++q) {
+    const int64_t o = E.ric_log_off[q];
+    const double f = (o >= 0 && o < (int64_t)lg.size()) ? lg[(size_t)o] : 0.0;
+    forms[q] = (f == 1.0) ? 1 : ((f == 2.0) ? 2 : 0);
+  }
+  return ECLQR_SUCCESS;
+}
+
 eclqr_status eclqr_plan_slot_info(const eclqr_plan* plan, int32_t which, int32_t* inst, int32_t* first,
                                   int32_t* last, int32_t* nslots) {
   if (!plan) return fail(ECLQR_INVALID_ARGUMENT, "NULL plan");
@@ -770,10 +798,11 @@ eclqr_status eclqr_plan_get_tuning(const eclqr_plan* plan, eclqr_tuning* out) {
 eclqr_status eclqr_plan_set_tuning(eclqr_plan* plan, const eclqr_tuning* t) {
   if (!plan || !t) return fail(ECLQR_INVALID_ARGUMENT, "NULL argument");
   if (t->grid_divisor < 1 || t->grid_divisor > 64) return fail(ECLQR_INVALID_ARGUMENT, "grid_divisor out of [1, 64]");
+  if (t->pool_in_lds < 0 || t->pool_in_lds > 2) return fail(ECLQR_INVALID_ARGUMENT, "pool_in_lds out of [0, 2]");
   Plan& p = plan->p;
   p.opt.use_graph = t->use_graph != 0;
   p.level_buckets = t->level_buckets != 0;
-  p.pool_lds = t->pool_in_lds != 0;
+  p.pool_lds = t->pool_in_lds;
   p.grid_divisor = t->grid_divisor;
   p.reg_compose = t->register_compose != 0;
   release_graph(p);
@@ -815,7 +844,7 @@ eclqr_status eclqr_plan_autotune(eclqr_plan* plan, const eclqr_problem* prob, ec
   };
   int32_t graph = p.opt.use_graph;
   Knob knobs[] = {{&p.reg_compose, p.reg_compose ? 0 : 1},
-                  {&p.level_buckets, p.level_buckets ? 0 : 1}, {&p.pool_lds, p.pool_lds ? 0 : 1},
+                  {&p.level_buckets, p.level_buckets ? 0 : 1}, {&p.pool_lds, p.pool_lds == 2 ? 1 : 2},
                   {&p.grid_divisor, p.grid_divisor == 1 ? 4 : 1}, {&graph, graph ? 0 : 1}};
   for (Knob& k : knobs) {
     if (st != ECLQR_SUCCESS) break;

@@ -32,36 +32,133 @@ __device__ __forceinline__ void lds_sync() {
   __asm__ volatile("" ::: "memory");
 }
 
-// Butterfly reductions over the 64 lanes; every lane ends with the same bits
-// (each combination step adds the same two partials in either order).
-__device__ __forceinline__ double wave_max(double v) {
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-  return v;
+// Barrier selected at compile time: routines called on LDS-resident operands
+// only (kL) need no wait for outstanding global stores.
+template <bool kL>
+__device__ __forceinline__ void bsync() {
+  if constexpr (kL) lds_sync();
+  else wg_sync();
 }
+
+// Wave reductions by DPP lane moves (VALU, no LDS traffic).  Within each row
+// of 16 lanes, quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror and
+// row_mirror pair every lane with a partner holding a disjoint partial, so
+// after four steps all 16 lanes hold the row's result.  row_bcast15 (rows 1,
+// 3 take lane 15 of the row below) and row_bcast31 (rows 2, 3 take lane 31)
+// leave the wave's result in lane 63, which v_readlane hands to every lane:
+// all lanes end with the same bits.  Called by all 64 lanes (full EXEC).
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ int dpp_i(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, kCtrl, kRowMask, 0xF, false);
+}
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ double dpp_d(double old, double v) {
+  const long long o = __double_as_longlong(old), x = __double_as_longlong(v);
+  const int lo = dpp_i<kCtrl, kRowMask>((int)(o & 0xffffffffll), (int)(x & 0xffffffffll));
+  const int hi = dpp_i<kCtrl, kRowMask>((int)(o >> 32), (int)(x >> 32));
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+// Value of `v` in lane `lane` (wave-uniform lane index).
+__device__ __forceinline__ double wave_bcast(double v, int lane) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), lane);
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+__device__ __forceinline__ int wave_bcast_i(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+
+constexpr int kDppX1 = 0xB1, kDppX2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140, kDppBcast15 = 0x142,
+              kDppBcast31 = 0x143;
+
 __device__ __forceinline__ double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v += dpp_d<kDppX1, 0xF>(0.0, v);
+  v += dpp_d<kDppX2, 0xF>(0.0, v);
+  v += dpp_d<kDppHalfMirror, 0xF>(0.0, v);
+  v += dpp_d<kDppMirror, 0xF>(0.0, v);
+  v += dpp_d<kDppBcast15, 0xA>(0.0, v);
+  v += dpp_d<kDppBcast31, 0xC>(0.0, v);
+  return wave_bcast(v, 63);
+}
+__device__ __forceinline__ double wave_max(double v) {
+  const double lo = -HUGE_VAL;
+  v = fmax(v, dpp_d<kDppX1, 0xF>(lo, v));
+  v = fmax(v, dpp_d<kDppX2, 0xF>(lo, v));
+  v = fmax(v, dpp_d<kDppHalfMirror, 0xF>(lo, v));
+  v = fmax(v, dpp_d<kDppMirror, 0xF>(lo, v));
+  v = fmax(v, dpp_d<kDppBcast15, 0xA>(lo, v));
+  v = fmax(v, dpp_d<kDppBcast31, 0xC>(lo, v));
+  return wave_bcast(v, 63);
 }
 // Largest value and its index over the lanes (idx < 0: lane has no
 // candidate); the lowest index wins ties, as in an ascending serial scan.
-__device__ __forceinline__ void wave_argmax(double& v, int& idx) {
-  for (int off = 32; off > 0; off >>= 1) {
-    const double ov = __shfl_xor(v, off, 64);
-    const int oi = __shfl_xor(idx, off, 64);
-    if (oi >= 0 && (idx < 0 || ov > v || (ov == v && oi < idx))) {
-      v = ov;
-      idx = oi;
-    }
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ void argmax_step(double& v, int& idx) {
+  const double ov = dpp_d<kCtrl, kRowMask>(v, v);
+  const int oi = dpp_i<kCtrl, kRowMask>(-1, idx);
+  if (oi >= 0 && (idx < 0 || ov > v || (ov == v && oi < idx))) {
+    v = ov;
+    idx = oi;
   }
+}
+__device__ __forceinline__ void wave_argmax(double& v, int& idx) {
+  argmax_step<kDppX1, 0xF>(v, idx);
+  argmax_step<kDppX2, 0xF>(v, idx);
+  argmax_step<kDppHalfMirror, 0xF>(v, idx);
+  argmax_step<kDppMirror, 0xF>(v, idx);
+  argmax_step<kDppBcast15, 0xA>(v, idx);
+  argmax_step<kDppBcast31, 0xC>(v, idx);
+  v = wave_bcast(v, 63);
+  idx = wave_bcast_i(idx, 63);
+}
+
+// Triangular solves with the vector held one entry per lane (lane i holds
+// entry i, n <= 64; lanes >= n keep their value).  Each step hands the newly
+// solved entry to every lane by v_readlane; diagonals are inverted up front so
+// the chain carries a multiply rather than a divide.
+// L y = x, L lower triangular.
+__device__ __forceinline__ double lane_trsv_lower(const double* L, int ld, double v, int n) {
+  const int lane = ECLQR_TID;
+  const double rd = (lane < n) ? 1.0 / L[lane * ld + lane] : 0.0;
+  for (int i = 0; i < n; ++i) {
+    if (lane == i) v *= rd;
+    const double xi = wave_bcast(v, i);
+    if (lane > i && lane < n) v = fma(-L[lane * ld + i], xi, v);
+  }
+  return v;
+}
+// L' y = x, L lower triangular.
+__device__ __forceinline__ double lane_trsv_lower_t(const double* L, int ld, double v, int n) {
+  const int lane = ECLQR_TID;
+  const double rd = (lane < n) ? 1.0 / L[lane * ld + lane] : 0.0;
+  for (int i = n - 1; i >= 0; --i) {
+    if (lane == i) v *= rd;
+    const double yi = wave_bcast(v, i);
+    if (lane < i) v = fma(-L[i * ld + lane], yi, v);
+  }
+  return v;
+}
+// U' y = x, U upper triangular.
+__device__ __forceinline__ double lane_trsv_upper_t(const double* U, int ld, double v, int n) {
+  const int lane = ECLQR_TID;
+  const double rd = (lane < n) ? 1.0 / U[lane * ld + lane] : 0.0;
+  for (int i = 0; i < n; ++i) {
+    if (lane == i) v *= rd;
+    const double xi = wave_bcast(v, i);
+    if (lane > i && lane < n) v = fma(-U[i * ld + lane], xi, v);
+  }
+  return v;
 }
 
 // Maximum of one value per lane (buf unused, kept for call sites).
-__device__ inline double wg_reduce_max(double v, double* /*buf*/) { return wave_max(v); }
+__device__ __forceinline__ double wg_reduce_max(double v, double* /*buf*/) { return wave_max(v); }
 
 // Per-lane strided kernels.  LDS and global loads of a later iteration cannot
 // move above an earlier store the compiler cannot prove disjoint, so in-place
 // updates load a batch of operands into registers before storing it, and dot
 // products keep four independent accumulators.
+// The tails of these loops run as at most one 4-, one 2- and one 1-element
+// step, each issuing its loads before its arithmetic (a plain remainder loop
+// waits on every load in turn); the arithmetic order is that of a plain loop.
 __device__ __forceinline__ double lane_dot(const double* a, int sa, const double* b, int sb, int n) {
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   int i = 0;
@@ -71,8 +168,48 @@ __device__ __forceinline__ double lane_dot(const double* a, int sa, const double
     s2 = fma(a[(i + 2) * sa], b[(i + 2) * sb], s2);
     s3 = fma(a[(i + 3) * sa], b[(i + 3) * sb], s3);
   }
-  for (; i < n; ++i) s0 = fma(a[i * sa], b[i * sb], s0);
+  if (i + 2 <= n) {
+    const double a0 = a[i * sa], b0 = b[i * sb], a1 = a[(i + 1) * sa], b1 = b[(i + 1) * sb];
+    s0 = fma(a1, b1, fma(a0, b0, s0));
+    i += 2;
+  }
+  if (i < n) s0 = fma(a[i * sa], b[i * sb], s0);
   return (s0 + s1) + (s2 + s3);
+}
+
+// acc + sgn * sum_{k<n} a[k] b[k] as one FMA chain in ascending k.
+template <bool kNeg>
+__device__ __forceinline__ double lane_chain(double acc, const double* a, int sa, const double* b, int sb, int n) {
+  int k = 0;
+  for (; k + 8 <= n; k += 8) {
+    double av[8], bv[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      av[t] = a[(k + t) * sa];
+      bv[t] = b[(k + t) * sb];
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) acc = fma(kNeg ? -av[t] : av[t], bv[t], acc);
+  }
+  if (k + 4 <= n) {
+    double av[4], bv[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      av[t] = a[(k + t) * sa];
+      bv[t] = b[(k + t) * sb];
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc = fma(kNeg ? -av[t] : av[t], bv[t], acc);
+    k += 4;
+  }
+  if (k + 2 <= n) {
+    const double a0 = a[k * sa], b0 = b[k * sb], a1 = a[(k + 1) * sa], b1 = b[(k + 1) * sb];
+    acc = fma(kNeg ? -a0 : a0, b0, acc);
+    acc = fma(kNeg ? -a1 : a1, b1, acc);
+    k += 2;
+  }
+  if (k < n) acc = fma(kNeg ? -a[k * sa] : a[k * sa], b[k * sb], acc);
+  return acc;
 }
 
 // y[i] += alpha x[i], i < n (x and y disjoint).
@@ -88,46 +225,81 @@ __device__ __forceinline__ void lane_axpy(double* y, int sy, const double* x, in
 #pragma unroll
     for (int t = 0; t < 8; ++t) y[(i + t) * sy] = fma(alpha, xv[t], yv[t]);
   }
-  for (; i < n; ++i) y[i * sy] = fma(alpha, x[i * sx], y[i * sy]);
+  if (i + 4 <= n) {
+    double xv[4], yv[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      xv[t] = x[(i + t) * sx];
+      yv[t] = y[(i + t) * sy];
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) y[(i + t) * sy] = fma(alpha, xv[t], yv[t]);
+    i += 4;
+  }
+  if (i + 2 <= n) {
+    const double x0 = x[i * sx], y0 = y[i * sy], x1 = x[(i + 1) * sx], y1 = y[(i + 1) * sy];
+    y[i * sy] = fma(alpha, x0, y0);
+    y[(i + 1) * sy] = fma(alpha, x1, y1);
+    i += 2;
+  }
+  if (i < n) y[i * sy] = fma(alpha, x[i * sx], y[i * sy]);
 }
 
 // C(MxN) = alpha * op(A) * op(B) + beta * C.  op(A) is MxK, op(B) is KxN.
-// beta == 0 never reads C.
-__device__ inline void wg_gemm(double* C, int ldc, const double* A, int lda, bool tA, const double* B, int ldb,
+// beta == 0 never reads C.  Each lane computes up to four outputs per round
+// with their accumulations interleaved (the loads of four k steps of all four
+// are independent and in flight together); every output is one FMA chain in
+// ascending k.
+template <bool kL = false>
+__device__ __forceinline__ void wg_gemm(double* C, int ldc, const double* A, int lda, bool tA, const double* B, int ldb,
                                bool tB, int M, int N, int K, double alpha, double beta) {
   const int sa = tA ? lda : 1, sb = tB ? 1 : ldb;
   const int total = M * N;
-  // four outputs per lane per round, all loads of a round before its stores
   for (int r0 = ECLQR_TID; r0 < total; r0 += 4 * ECLQR_NT) {
+    const double* ap[4];
+    const double* bp[4];
+    int co[4];
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    double prev[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      const int idx = r0 + t * ECLQR_NT;
-      if (idx < total) {
-        const int i = idx / N, j = idx - (idx / N) * N;
-        const double* a = tA ? A + i : A + (int64_t)i * lda;
-        const double* b = tB ? B + (int64_t)j * ldb : B + j;
-        double s = 0.0;
-        for (int k = 0; k < K; ++k) s = fma(a[k * sa], b[k * sb], s);
-        acc[t] = s;
-        if (beta != 0.0) prev[t] = beta * C[i * ldc + j];
-      }
+      const int want = r0 + t * ECLQR_NT;
+      const int idx = (want < total) ? want : r0;  // surplus slots recompute a valid output and drop it
+      const int i = idx / N, j = idx - (idx / N) * N;
+      ap[t] = tA ? A + i : A + (int64_t)i * lda;
+      bp[t] = tB ? B + (int64_t)j * ldb : B + j;
+      co[t] = (want < total) ? i * ldc + j : -1;
     }
+    int k = 0;
+    for (; k + 2 <= K; k += 2) {
+      double av[4][2], bv[4][2];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int idx = r0 + t * ECLQR_NT;
-      if (idx < total) {
-        const int i = idx / N, j = idx - (idx / N) * N;
-        C[i * ldc + j] = alpha * acc[t] + prev[t];
-      }
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          av[t][q] = ap[t][(k + q) * sa];
+          bv[t][q] = bp[t][(k + q) * sb];
+        }
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) acc[t] = fma(av[t][q], bv[t][q], acc[t]);
     }
+    for (; k < K; ++k)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[t] = fma(ap[t][k * sa], bp[t][k * sb], acc[t]);
+    double prev[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) prev[t] = (co[t] >= 0 && beta != 0.0) ? beta * C[co[t]] : 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (co[t] >= 0) C[co[t]] = alpha * acc[t] + prev[t];
   }
-  wg_sync();
+  bsync<kL>();
 }
 
 // y(M) = alpha * op(A) x + beta * y.   op(A) is MxK.
-__device__ inline void wg_gemv(double* y, const double* A, int lda, bool tA, const double* x, int M, int K,
+template <bool kL = false>
+__device__ __forceinline__ void wg_gemv(double* y, const double* A, int lda, bool tA, const double* x, int M, int K,
                                double alpha, double beta) {
   for (int i = ECLQR_TID; i < M; i += ECLQR_NT) {
     double acc = 0.0;
@@ -139,10 +311,11 @@ __device__ inline void wg_gemv(double* y, const double* A, int lda, bool tA, con
     const double prev = (beta == 0.0) ? 0.0 : beta * y[i];
     y[i] = alpha * acc + prev;
   }
-  wg_sync();
+  bsync<kL>();
 }
 
-__device__ inline void wg_copy(double* dst, int ldd, const double* src, int lds, int rows, int cols) {
+template <bool kL = false>
+__device__ __forceinline__ void wg_copy(double* dst, int ldd, const double* src, int lds, int rows, int cols) {
   const int total = rows * cols;
   for (int r0 = ECLQR_TID; r0 < total; r0 += 4 * ECLQR_NT) {
     double v[4];
@@ -159,10 +332,11 @@ __device__ inline void wg_copy(double* dst, int ldd, const double* src, int lds,
       if (idx < total) dst[i * ldd + j] = v[t];
     }
   }
-  wg_sync();
+  bsync<kL>();
 }
 
-__device__ inline void wg_copy_t(double* dst, int ldd, const double* src, int lds, int rows, int cols) {
+template <bool kL = false>
+__device__ __forceinline__ void wg_copy_t(double* dst, int ldd, const double* src, int lds, int rows, int cols) {
   // dst (cols x rows) = src(rows x cols)^T
   const int total = rows * cols;
   for (int r0 = ECLQR_TID; r0 < total; r0 += 4 * ECLQR_NT) {
@@ -180,27 +354,30 @@ __device__ inline void wg_copy_t(double* dst, int ldd, const double* src, int ld
       if (idx < total) dst[j * ldd + i] = v[t];
     }
   }
-  wg_sync();
+  bsync<kL>();
 }
 
-__device__ inline void wg_fill(double* dst, int ldd, int rows, int cols, double v) {
+template <bool kL = false>
+__device__ __forceinline__ void wg_fill(double* dst, int ldd, int rows, int cols, double v) {
   for (int idx = ECLQR_TID; idx < rows * cols; idx += ECLQR_NT) {
     const int i = idx / cols, j = idx - (idx / cols) * cols;
     dst[i * ldd + j] = v;
   }
-  wg_sync();
+  bsync<kL>();
 }
 
-__device__ inline void wg_identity(double* dst, int ldd, int n) {
+template <bool kL = false>
+__device__ __forceinline__ void wg_identity(double* dst, int ldd, int n) {
   for (int idx = ECLQR_TID; idx < n * n; idx += ECLQR_NT) {
     const int i = idx / n, j = idx - (idx / n) * n;
     dst[i * ldd + j] = (i == j) ? 1.0 : 0.0;
   }
-  wg_sync();
+  bsync<kL>();
 }
 
 // Symmetrise a square matrix in place: S = (S + S^T)/2.
-__device__ inline void wg_symmetrize(double* S, int ld, int n) {
+template <bool kL = false>
+__device__ __forceinline__ void wg_symmetrize(double* S, int ld, int n) {
   for (int idx = ECLQR_TID; idx < n * n; idx += ECLQR_NT) {
     const int i = idx / n, j = idx - (idx / n) * n;
     if (i < j) {
@@ -209,7 +386,7 @@ __device__ inline void wg_symmetrize(double* S, int ld, int n) {
       S[j * ld + i] = v;
     }
   }
-  wg_sync();
+  bsync<kL>();
 }
 
 // Scratch needed by wg_qr_colpiv: (cp + 8) doubles and cp ints.
@@ -225,7 +402,7 @@ struct QRScratch {
 // in place (perm[j] = original candidate index), W[j][c0+j] = R_jj, rows
 // below the diagonal of pivot column j hold the Householder vector (v_j = 1
 // implicit) and tau[j] its scalar.  Returns the numerical rank.
-__device__ inline int wg_qr_colpiv(double* W, int ld, int p, int c, int c0, int cp, double thr, double* tau,
+__device__ __forceinline__ int wg_qr_colpiv(double* W, int ld, int p, int c, int c0, int cp, double thr, double* tau,
                                    QRScratch sc) {
   for (int j = ECLQR_TID; j < cp; j += ECLQR_NT) sc.perm[j] = j;
   lds_sync();
@@ -288,7 +465,7 @@ __device__ inline int wg_qr_colpiv(double* W, int ld, int p, int c, int c0, int 
 
 // Copy the r reflectors left by wg_qr_colpiv (rows below the diagonal of the
 // pivot columns [c0, c0 + r)) and their scalars to a log: V[j * P + row].
-__device__ inline void wg_log_reflectors(const double* W, int ld, int p, int c0, int r, const double* tau, double* V,
+__device__ __forceinline__ void wg_log_reflectors(const double* W, int ld, int p, int c0, int r, const double* tau, double* V,
                                          int P, double* tlog) {
   for (int idx = ECLQR_TID; idx < r * p; idx += ECLQR_NT) {
     const int j = idx / p, row = idx - (idx / p) * p;
@@ -301,7 +478,7 @@ __device__ inline void wg_log_reflectors(const double* W, int ld, int p, int c0,
 // Apply Q = H_0 H_1 ... H_{r-1} (reflectors stored by wg_qr_colpiv in the
 // pivot columns [c0, c0 + r) of W, rows j+1.. of column c0+j) to the p x nc
 // matrix X (row-major, ldx) from the left: X <- Q X.
-__device__ inline void wg_apply_q(const double* W, int ld, int p, int c0, int r, const double* tau, double* X,
+__device__ __forceinline__ void wg_apply_q(const double* W, int ld, int p, int c0, int r, const double* tau, double* X,
                                   int ldx, int nc) {
   for (int col = ECLQR_TID; col < nc; col += ECLQR_NT) {
     for (int j = r - 1; j >= 0; --j) {
@@ -327,7 +504,7 @@ __device__ inline void wg_apply_q(const double* W, int ld, int p, int c0, int r,
 // column: glog[s * gstep + 0] = pivot row, [1] = 1/norm, [2 + l] = the
 // re-orthogonalisation coefficient of chosen row l, [2 + gcap + row] = the
 // projection coefficient of each later row (steps s < gcap only).
-__device__ inline int wg_row_basis(double* W, int ld, int r0, int p, int k0, int kc, double thr, double cons_thr,
+__device__ __forceinline__ int wg_row_basis(double* W, int ld, int r0, int p, int k0, int kc, double thr, double cons_thr,
                                    int* bad, double* scr /* >= 2*(p - r0) + 8 + 64 */, double* glog = nullptr,
                                    int64_t gstep = 0, int gcap = 0) {
   const int rows = p - r0;
@@ -402,115 +579,116 @@ __device__ inline int wg_row_basis(double* W, int ld, int r0, int p, int k0, int
 
 // In-place Cholesky S = L L^T of an n x n SPD matrix (lower triangle holds L,
 // upper triangle zeroed).  Returns 0 on success, 1 if a pivot (before the
-// square root) is not above `floor`.
-__device__ inline int wg_cholesky(double* S, int ld, int n, double* sh /* unused */, double floor = 0.0) {
+// square root) is not above `floor`.  Right-looking, one row per lane for the
+// column scaling and the trailing update (lane_axpy: batched, predicated).
+template <bool kL = false>
+__device__ __forceinline__ int wg_cholesky(double* S, int ld, int n, double* sh /* unused */, double floor = 0.0) {
   (void)sh;
   for (int j = 0; j < n; ++j) {
     const double d = S[j * ld + j];
     if (!(d > floor)) {
-      wg_sync();
+      bsync<kL>();
       return 1;
     }
     const double dj = sqrt(d);
-    wg_sync();
-    if (ECLQR_TID == 0) S[j * ld + j] = dj;
     for (int i = j + 1 + ECLQR_TID; i < n; i += ECLQR_NT) S[i * ld + j] /= dj;
-    wg_sync();
+    if (ECLQR_TID == 0) S[j * ld + j] = dj;
+    bsync<kL>();
     // trailing update of the lower triangle, one row per lane
     for (int a2 = j + 1 + ECLQR_TID; a2 < n; a2 += ECLQR_NT)
       lane_axpy(S + a2 * ld + j + 1, 1, S + (j + 1) * ld + j, ld, a2 - j, -S[a2 * ld + j]);
-    wg_sync();
+    bsync<kL>();
   }
   for (int a2 = ECLQR_TID; a2 < n; a2 += ECLQR_NT)
     for (int b = a2 + 1; b < n; ++b) S[a2 * ld + b] = 0.0;
-  wg_sync();
+  bsync<kL>();
   return 0;
 }
 
 // Pivoted Cholesky of a symmetric positive semidefinite n x n matrix S
-// (read only): K (n x r, row-major, ldk) with S ~= K K^T, rows in the original
-// order, columns in pivot order.  Stops when the largest remaining diagonal is
-// <= tol * (largest diagonal of S).  rem: n doubles, used: n ints.  Returns r.
-__device__ inline int wg_pchol(const double* S, int ld, int n, double tol, double* K, int ldk, double* rem, int* used,
-                               double* sh /* 2 doubles */) {
-  for (int i = ECLQR_TID; i < n; i += ECLQR_NT) {
-    rem[i] = S[i * ld + i];
-    used[i] = 0;
-  }
-  wg_sync();
+// (read only, n <= 64): K (n x r, row-major, ldk) with S ~= K K^T, rows in the
+// original order, columns in pivot order.  Stops when the largest remaining
+// diagonal is <= tol * (largest diagonal of S).  Row i is lane i: its
+// remaining diagonal and "used" flag live in registers.  rem, used, sh unused.
+template <bool kL = false>
+__device__ __forceinline__ int wg_pchol(const double* S, int ld, int n, double tol, double* K, int ldk, double* rem, int* used,
+                               double* sh) {
+  (void)rem;
+  (void)used;
   (void)sh;
-  double ref = 0.0;
-  for (int i = ECLQR_TID; i < n; i += ECLQR_NT) ref = fmax(ref, rem[i]);
-  ref = wave_max(ref);
+  const int lane = ECLQR_TID;
+  const bool row = lane < n;
+  double rm = row ? S[lane * ld + lane] : 0.0;
+  bool done = !row;
+  const double ref = wave_max(row ? rm : 0.0);
   int r = 0;
   for (int j = 0; j < n; ++j) {
-    double bv = 0.0;
-    int best = -1;
-    for (int i = ECLQR_TID; i < n; i += ECLQR_NT)
-      if (!used[i] && (best < 0 || rem[i] > bv)) {
-        best = i;
-        bv = rem[i];
-      }
+    double bv = done ? 0.0 : rm;
+    int best = done ? -1 : lane;
     wave_argmax(bv, best);
     if (!(best >= 0 && bv > tol * ref && bv > 0.0)) break;
     const int p = best;
-    wg_sync();
-    if (ECLQR_TID == 0) used[p] = 1;
-    wg_sync();
-    const double dp = sqrt(rem[p]);
-    for (int i = ECLQR_TID; i < n; i += ECLQR_NT) {
-      double v = 0.0;
-      if (i == p) {
+    const double dp = sqrt(bv);
+    double v = 0.0;
+    if (row) {
+      if (lane == p) {
         v = dp;
-      } else if (!used[i]) {
-        v = S[i * ld + p];
-        for (int l = 0; l < j; ++l) v = fma(-K[i * ldk + l], K[p * ldk + l], v);
-        v /= dp;
+      } else if (!done) {
+        v = lane_chain<true>(S[lane * ld + p], K + lane * ldk, 1, K + p * ldk, 1, j) / dp;
       }
-      K[i * ldk + j] = v;
+      K[lane * ldk + j] = v;
     }
-    wg_sync();
-    for (int i = ECLQR_TID; i < n; i += ECLQR_NT)
-      if (!used[i]) rem[i] = fma(-K[i * ldk + j], K[i * ldk + j], rem[i]);
+    if (lane == p) done = true;
+    if (!done) rm = fma(-v, v, rm);
     r = j + 1;
-    wg_sync();
+    bsync<kL>();
   }
   return r;
 }
 
-// Solve L X = B (lower triangular L, n x n) in place on B (n x nc).
-__device__ inline void wg_trsm_lower(const double* L, int ldl, double* X, int ldx, int n, int nc) {
+// Solve L X = B (lower triangular L, n x n) in place on B (n x nc); one
+// column per lane, each entry one FMA chain in ascending k times the
+// reciprocal of the diagonal (which does not depend on the solve, so its
+// latency overlaps the chain).
+template <bool kL = false>
+__device__ __forceinline__ void wg_trsm_lower(const double* L, int ldl, double* X, int ldx, int n, int nc) {
   for (int col = ECLQR_TID; col < nc; col += ECLQR_NT) {
-    for (int i = 0; i < n; ++i)
-      X[i * ldx + col] = (X[i * ldx + col] - lane_dot(L + i * ldl, 1, X + col, ldx, i)) / L[i * ldl + i];
+    for (int i = 0; i < n; ++i) {
+      const double rd = 1.0 / L[i * ldl + i];
+      X[i * ldx + col] = lane_chain<true>(X[i * ldx + col], L + i * ldl, 1, X + col, ldx, i) * rd;
+    }
   }
-  wg_sync();
+  bsync<kL>();
 }
 
 // Solve L^T X = B (L lower triangular) in place on B (n x nc).
-__device__ inline void wg_trsm_lower_t(const double* L, int ldl, double* X, int ldx, int n, int nc) {
+template <bool kL = false>
+__device__ __forceinline__ void wg_trsm_lower_t(const double* L, int ldl, double* X, int ldx, int n, int nc) {
   for (int col = ECLQR_TID; col < nc; col += ECLQR_NT) {
-    for (int i = n - 1; i >= 0; --i)
-      X[i * ldx + col] = (X[i * ldx + col] - lane_dot(L + (i + 1) * ldl + i, ldl, X + (i + 1) * ldx + col, ldx,
-                                                      n - i - 1)) /
-                         L[i * ldl + i];
+    for (int i = n - 1; i >= 0; --i) {
+      const double rd = 1.0 / L[i * ldl + i];
+      X[i * ldx + col] =
+          lane_chain<true>(X[i * ldx + col], L + (i + 1) * ldl + i, ldl, X + (i + 1) * ldx + col, ldx, n - i - 1) * rd;
+    }
   }
-  wg_sync();
+  bsync<kL>();
 }
 
 // Solve U^T X = B with U upper triangular (r x r, diagonal U[j][c0+j] inside a
 // wider matrix: U(i, j) = W[i*ld + c0 + j]) in place on X (r x nc).
-__device__ inline void wg_trsm_upper_t(const double* W, int ld, int c0, double* X, int ldx, int r, int nc) {
+template <bool kL = false>
+__device__ __forceinline__ void wg_trsm_upper_t(const double* W, int ld, int c0, double* X, int ldx, int r, int nc) {
   for (int col = ECLQR_TID; col < nc; col += ECLQR_NT) {
     for (int i = 0; i < r; ++i)
       X[i * ldx + col] = (X[i * ldx + col] - lane_dot(W + c0 + i, ld, X + col, ldx, i)) / W[i * ld + c0 + i];
   }
-  wg_sync();
+  bsync<kL>();
 }
 
 // LU factorisation with partial pivoting of an n x n matrix in place;
 // piv[i] = row swapped with row i at step i.
-__device__ inline void wg_lu(double* Mt, int ld, int n, int* piv, double* sh) {
+template <bool kL = false>
+__device__ __forceinline__ void wg_lu(double* Mt, int ld, int n, int* piv, double* sh) {
   (void)sh;
   for (int j = 0; j < n; ++j) {
     double bv = 0.0;
@@ -524,27 +702,28 @@ __device__ inline void wg_lu(double* Mt, int ld, int n, int* piv, double* sh) {
     }
     wave_argmax(bv, best);
     if (ECLQR_TID == 0) piv[j] = best;
-    wg_sync();
+    bsync<kL>();
     if (best != j) {
       for (int c = ECLQR_TID; c < n; c += ECLQR_NT) {
         const double a = Mt[j * ld + c];
         Mt[j * ld + c] = Mt[best * ld + c];
         Mt[best * ld + c] = a;
       }
-      wg_sync();
+      bsync<kL>();
     }
     const double d = Mt[j * ld + j];
     for (int i = j + 1 + ECLQR_TID; i < n; i += ECLQR_NT) Mt[i * ld + j] /= d;
-    wg_sync();
+    bsync<kL>();
     // trailing update, one row per lane
     for (int a = j + 1 + ECLQR_TID; a < n; a += ECLQR_NT)
       lane_axpy(Mt + a * ld + j + 1, 1, Mt + j * ld + j + 1, 1, n - j - 1, -Mt[a * ld + j]);
-    wg_sync();
+    bsync<kL>();
   }
 }
 
 // Solve (P L U) X = B in place on B (n x nc), factors from wg_lu.
-__device__ inline void wg_lu_solve(const double* LU, int ld, int n, const int* piv, double* X, int ldx, int nc) {
+template <bool kL = false>
+__device__ __forceinline__ void wg_lu_solve(const double* LU, int ld, int n, const int* piv, double* X, int ldx, int nc) {
   for (int col = ECLQR_TID; col < nc; col += ECLQR_NT) {
     for (int i = 0; i < n; ++i) {
       const int pi = piv[i];
@@ -565,11 +744,12 @@ __device__ inline void wg_lu_solve(const double* LU, int ld, int n, const int* p
       X[i * ldx + col] = v / LU[i * ld + i];
     }
   }
-  wg_sync();
+  bsync<kL>();
 }
 
 // Solve (P L U)^T X = B in place on B (n x nc):  U^T L^T P^T X = B.
-__device__ inline void wg_lu_solve_t(const double* LU, int ld, int n, const int* piv, double* X, int ldx, int nc) {
+template <bool kL = false>
+__device__ __forceinline__ void wg_lu_solve_t(const double* LU, int ld, int n, const int* piv, double* X, int ldx, int nc) {
   for (int col = ECLQR_TID; col < nc; col += ECLQR_NT) {
     for (int i = 0; i < n; ++i) {  // U^T y = b
       double v = X[i * ldx + col];
@@ -590,7 +770,7 @@ __device__ inline void wg_lu_solve_t(const double* LU, int ld, int n, const int*
       }
     }
   }
-  wg_sync();
+  bsync<kL>();
 }
 
 }  // namespace eclqr

@@ -25,6 +25,10 @@ __device__ __forceinline__ void flag(int32_t* status, int inst, int32_t bit) {
 // true when the instance has finished refining and must not be touched
 __device__ __forceinline__ bool gated(const DevEngine& e, int inst) { return e.gate && e.gate[inst] == kGateDone; }
 
+// true when no instance is refining: every task of a refinement-step kernel
+// would be gated, so the kernel returns before reading its task list
+__device__ __forceinline__ bool none_live(const DevEngine& e) { return e.live && *e.live == 0; }
+
 __device__ __forceinline__ double* block_scratch(const DevEngine& e) {
   return e.scratch + (int64_t)blockIdx.x * e.scratch_per_block;
 }

@@ -67,6 +67,7 @@ __global__ void __launch_bounds__(kBlock) k_dual_matrices(DevEngine p, Inputs in
 // (eq. (objective-gradients)); c^D_0 = g^x_N.
 __global__ void __launch_bounds__(kBlock) k_dual_vectors(DevEngine p, Inputs in, const double* x, const double* u,
                                                          DevEngine d, DualPtrs dp) {
+  if (none_live(p)) return;
   for (int64_t ds = blockIdx.x; ds < d.S; ds += gridDim.x) {
     const StageInfo sd = d.st[ds];
     if (sd.terminal || gated(d, sd.inst)) continue;
@@ -83,9 +84,9 @@ __global__ void __launch_bounds__(kBlock) k_dual_vectors(DevEngine p, Inputs in,
     const double* us = sp.terminal ? nullptr : u + sp.in[IN_r];
     for (int i = ECLQR_TID; i < sp.n; i += ECLQR_NT) {
       double v = q[i];
-      for (int l = 0; l < sp.n; ++l) v = fma(Q[i * sp.n + l], xs[l], v);
+      v = lane_chain<false>(v, Q + i * sp.n, 1, xs, 1, sp.n);
       if (M)
-        for (int l = 0; l < sp.m; ++l) v = fma(M[i * sp.m + l], us[l], v);
+        v = lane_chain<false>(v, M + i * sp.m, 1, us, 1, sp.m);
       cd[i] = v;
     }
     if (!sp.terminal) {
@@ -94,9 +95,9 @@ __global__ void __launch_bounds__(kBlock) k_dual_vectors(DevEngine p, Inputs in,
       double* gd = dp.f[IN_g] + sd.in[IN_g];
       for (int i = ECLQR_TID; i < sp.m; i += ECLQR_NT) {
         double v = r[i];
-        for (int l = 0; l < sp.m; ++l) v = fma(R[i * sp.m + l], us[l], v);
+        v = lane_chain<false>(v, R + i * sp.m, 1, us, 1, sp.m);
         if (M)
-          for (int l = 0; l < sp.n; ++l) v = fma(M[l * sp.m + i], xs[l], v);
+          v = lane_chain<false>(v, M + i, sp.m, xs, 1, sp.n);
         gd[i] = v;
       }
     }
@@ -107,6 +108,7 @@ __global__ void __launch_bounds__(kBlock) k_dual_vectors(DevEngine p, Inputs in,
 // lambda_i = x^D_{N-i+1}, mu_i = u^D_{N-i}.
 __global__ void __launch_bounds__(kBlock) k_dual_extract(DevEngine p, DevEngine d, const double* dx, const double* du,
                                                          double* lam, double* mu, DualPtrs dp) {
+  if (none_live(p)) return;
   for (int64_t s = blockIdx.x; s < p.S; s += gridDim.x) {
     const StageInfo sp = p.st[s];
     if (gated(p, sp.inst)) continue;
@@ -125,6 +127,7 @@ __global__ void __launch_bounds__(kBlock) k_dual_extract(DevEngine p, DevEngine 
 //   x0 <- x0 - x_0.
 __global__ void __launch_bounds__(kBlock) k_correction(DevEngine p, Inputs in, const double* x, const double* u,
                                                        const double* lam, const double* mu, CorrPtrs cp) {
+  if (none_live(p)) return;
   for (int64_t s = blockIdx.x; s < p.S; s += gridDim.x) {
     const StageInfo st = p.st[s];
     if (gated(p, st.inst)) continue;
@@ -141,13 +144,13 @@ __global__ void __launch_bounds__(kBlock) k_correction(DevEngine p, Inputs in, c
     if (st.terminal) {
       for (int i = ECLQR_TID; i < n; i += ECLQR_NT) {
         double v = q[i] - ls[i];
-        for (int l = 0; l < n; ++l) v = fma(Q[i * n + l], xs[l], v);
-        for (int l = 0; l < k; ++l) v = fma(E[l * n + i], ms[l], v);
+        v = lane_chain<false>(v, Q + i * n, 1, xs, 1, n);
+        v = lane_chain<false>(v, E + i, n, ms, 1, k);
         qo[i] = v;
       }
       for (int i = ECLQR_TID; i < k; i += ECLQR_NT) {
         double v = g[i];
-        for (int l = 0; l < n; ++l) v = fma(E[i * n + l], xs[l], v);
+        v = lane_chain<false>(v, E + i * n, 1, xs, 1, n);
         go[i] = v;
       }
       __syncthreads();
@@ -168,32 +171,32 @@ __global__ void __launch_bounds__(kBlock) k_correction(DevEngine p, Inputs in, c
     double* co = cp.c + st.in[IN_c];
     for (int i = ECLQR_TID; i < n; i += ECLQR_NT) {
       double v = q[i] - ls[i];
-      for (int l = 0; l < n; ++l) v = fma(Q[i * n + l], xs[l], v);
+      v = lane_chain<false>(v, Q + i * n, 1, xs, 1, n);
       if (M)
-        for (int l = 0; l < m; ++l) v = fma(M[i * m + l], us[l], v);
-      for (int l = 0; l < np; ++l) v = fma(A[l * n + i], l1[l], v);
-      for (int l = 0; l < k; ++l) v = fma(E[l * n + i], ms[l], v);
+        v = lane_chain<false>(v, M + i * m, 1, us, 1, m);
+      v = lane_chain<false>(v, A + i, n, l1, 1, np);
+      v = lane_chain<false>(v, E + i, n, ms, 1, k);
       qo[i] = v;
     }
     for (int i = ECLQR_TID; i < m; i += ECLQR_NT) {
       double v = r[i];
-      for (int l = 0; l < m; ++l) v = fma(R[i * m + l], us[l], v);
+      v = lane_chain<false>(v, R + i * m, 1, us, 1, m);
       if (M)
-        for (int l = 0; l < n; ++l) v = fma(M[l * m + i], xs[l], v);
-      for (int l = 0; l < np; ++l) v = fma(B[l * m + i], l1[l], v);
-      for (int l = 0; l < k; ++l) v = fma(F[l * m + i], ms[l], v);
+        v = lane_chain<false>(v, M + i, m, xs, 1, n);
+      v = lane_chain<false>(v, B + i, m, l1, 1, np);
+      v = lane_chain<false>(v, F + i, m, ms, 1, k);
       ro[i] = v;
     }
     for (int i = ECLQR_TID; i < np; i += ECLQR_NT) {
       double v = c[i] - x1[i];
-      for (int l = 0; l < n; ++l) v = fma(A[i * n + l], xs[l], v);
-      for (int l = 0; l < m; ++l) v = fma(B[i * m + l], us[l], v);
+      v = lane_chain<false>(v, A + i * n, 1, xs, 1, n);
+      v = lane_chain<false>(v, B + i * m, 1, us, 1, m);
       co[i] = v;
     }
     for (int i = ECLQR_TID; i < k; i += ECLQR_NT) {
       double v = g[i];
-      for (int l = 0; l < n; ++l) v = fma(E[i * n + l], xs[l], v);
-      for (int l = 0; l < m; ++l) v = fma(F[i * m + l], us[l], v);
+      v = lane_chain<false>(v, E + i * n, 1, xs, 1, n);
+      v = lane_chain<false>(v, F + i * m, 1, us, 1, m);
       go[i] = v;
     }
     if (st.i == 0)
@@ -206,6 +209,7 @@ __global__ void __launch_bounds__(kBlock) k_correction(DevEngine p, Inputs in, c
 // of the correction and of the updated iterate (one wavefront per stage).
 __global__ void __launch_bounds__(kBlock) k_refine_update(DevEngine p, double* x, double* u, const double* dx,
                                                           const double* du, double* norms) {
+  if (none_live(p)) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
   for (int64_t s = (int64_t)blockIdx.x * waves + wave; s < p.S; s += (int64_t)gridDim.x * waves) {
     const StageInfo st = p.st[s];
@@ -226,10 +230,8 @@ __global__ void __launch_bounds__(kBlock) k_refine_update(DevEngine p, double* x
         d2 = fma(d, d, d2);
         w2 = fma(w, w, w2);
       }
-    for (int off = 32; off > 0; off >>= 1) {
-      d2 += __shfl_xor(d2, off, 64);
-      w2 += __shfl_xor(w2, off, 64);
-    }
+    d2 = wave_sum(d2);
+    w2 = wave_sum(w2);
     if (lane == 0) {
       norms[2 * s] = d2;
       norms[2 * s + 1] = w2;
@@ -242,6 +244,7 @@ __global__ void __launch_bounds__(kBlock) k_refine_update(DevEngine p, double* x
 // last step.
 __global__ void __launch_bounds__(kBlock) k_refine_decide(DevEngine p, const int64_t* sbase, const double* norms,
                                                           double tol, int last, int32_t* gate, int32_t* steps) {
+  if (none_live(p)) return;
   __shared__ double sd[kBlock], sw[kBlock];
   for (int b = blockIdx.x; b < p.B; b += gridDim.x) {
     if (gate[b] != kGateActive) continue;
@@ -422,9 +425,23 @@ __global__ void k_flag_unconverged(const unsigned long long* omega, const int32_
     if (steps[i] > 0 && !(__longlong_as_double((long long)omega[i]) <= tol)) status[i] |= bit;
 }
 
-__global__ void k_gate_advance(int32_t* gate, int32_t B) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < B; i += gridDim.x * blockDim.x)
-    if (gate[i] == kGateFinal) gate[i] = kGateDone;
+// One workgroup: FINAL -> DONE, and the count of instances still ACTIVE.
+__global__ void k_gate_advance(int32_t* gate, int32_t* live, int32_t B) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  int c = 0;
+  for (int i = threadIdx.x; i < B; i += blockDim.x) {
+    int g = gate[i];
+    if (g == kGateFinal) {
+      g = kGateDone;
+      gate[i] = g;
+    }
+    c += (g == kGateActive) ? 1 : 0;
+  }
+  atomicAdd(&cnt, c);
+  __syncthreads();
+  if (threadIdx.x == 0) *live = cnt;
 }
 __global__ void k_fill(double* y, double v, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -499,8 +516,8 @@ __global__ void __launch_bounds__(kBlock) k_kkt_residual(DevEngine p, Inputs in,
     if (st.terminal) {
       for (int i = ECLQR_TID; i < n; i += ECLQR_NT) {
         double v = q[i] - ls[i];
-        for (int l = 0; l < n; ++l) v = fma(Q[i * n + l], xs[l], v);
-        for (int l = 0; l < k; ++l) v = fma(E[l * n + i], ms[l], v);
+        v = lane_chain<false>(v, Q + i * n, 1, xs, 1, n);
+        v = lane_chain<false>(v, E + i, n, ms, 1, k);
         r3 = fmax(r3, fabs(v));
       }
     } else {
@@ -514,26 +531,26 @@ __global__ void __launch_bounds__(kBlock) k_kkt_residual(DevEngine p, Inputs in,
       const double* c = in.f[IN_c] + st.in[IN_c];
       for (int i = ECLQR_TID; i < np; i += ECLQR_NT) {
         double v = c[i] - x1[i];
-        for (int l = 0; l < n; ++l) v = fma(A[i * n + l], xs[l], v);
-        for (int l = 0; l < m; ++l) v = fma(B[i * m + l], us[l], v);
+        v = lane_chain<false>(v, A + i * n, 1, xs, 1, n);
+        v = lane_chain<false>(v, B + i * m, 1, us, 1, m);
         r1 = fmax(r1, fabs(v));
       }
       for (int i = ECLQR_TID; i < n; i += ECLQR_NT) {
         double v = q[i] - ls[i];
-        for (int l = 0; l < n; ++l) v = fma(Q[i * n + l], xs[l], v);
+        v = lane_chain<false>(v, Q + i * n, 1, xs, 1, n);
         if (M)
-          for (int l = 0; l < m; ++l) v = fma(M[i * m + l], us[l], v);
-        for (int l = 0; l < np; ++l) v = fma(A[l * n + i], l1[l], v);
-        for (int l = 0; l < k; ++l) v = fma(E[l * n + i], ms[l], v);
+          v = lane_chain<false>(v, M + i * m, 1, us, 1, m);
+        v = lane_chain<false>(v, A + i, n, l1, 1, np);
+        v = lane_chain<false>(v, E + i, n, ms, 1, k);
         r3 = fmax(r3, fabs(v));
       }
       for (int i = ECLQR_TID; i < m; i += ECLQR_NT) {
         double v = r[i];
-        for (int l = 0; l < m; ++l) v = fma(R[i * m + l], us[l], v);
+        v = lane_chain<false>(v, R + i * m, 1, us, 1, m);
         if (M)
-          for (int l = 0; l < n; ++l) v = fma(M[l * m + i], xs[l], v);
-        for (int l = 0; l < np; ++l) v = fma(B[l * m + i], l1[l], v);
-        for (int l = 0; l < k; ++l) v = fma(F[l * m + i], ms[l], v);
+          v = lane_chain<false>(v, M + i, m, xs, 1, n);
+        v = lane_chain<false>(v, B + i, m, l1, 1, np);
+        v = lane_chain<false>(v, F + i, m, ms, 1, k);
         r3 = fmax(r3, fabs(v));
       }
     }
@@ -675,8 +692,8 @@ void launch_flag_unconverged(const unsigned long long* omega, const int32_t* ste
                              int32_t bit, int32_t B, hipStream_t s) {
   hipLaunchKernelGGL(k_flag_unconverged, dim3(grid_for(B)), dim3(256), 0, s, omega, steps, tol, status, bit, B);
 }
-void launch_gate_advance(int32_t* gate, int32_t B, hipStream_t s) {
-  hipLaunchKernelGGL(k_gate_advance, dim3(grid_for(B)), dim3(256), 0, s, gate, B);
+void launch_gate_advance(int32_t* gate, int32_t* live, int32_t B, hipStream_t s) {
+  hipLaunchKernelGGL(k_gate_advance, dim3(1), dim3(256), 0, s, gate, live, B);
 }
 void launch_fill(double* y, double v, int64_t n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(256), 0, s, y, v, n);

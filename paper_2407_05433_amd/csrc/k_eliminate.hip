@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(kBlock) k_eliminate(DevEngine e, Inputs in, To
       wg_symmetrize(ric + rl.J, nb, nb);
       for (int i = ECLQR_TID; i < n; i += ECLQR_NT) {
         double a = qv[i];
-        for (int j = 0; j < n; ++j) a = fma(Q[i * n + j], tv[j], a);
+        a = lane_chain<false>(a, Q + i * n, 1, tv, 1, n);
         v[i] = a;
       }
       wg_sync();
@@ -73,7 +73,7 @@ __global__ void __launch_bounds__(kBlock) k_eliminate(DevEngine e, Inputs in, To
         double kap = 0.0;
         for (int i = 0; i < n; ++i) {
           double qi = 0.0;
-          for (int j = 0; j < n; ++j) qi = fma(Q[i * n + j], tv[j], qi);
+          qi = lane_chain<false>(qi, Q + i * n, 1, tv, 1, n);
           kap += tv[i] * (0.5 * qi + qv[i]);
         }
         base[ar.kap] = kap;
@@ -119,15 +119,15 @@ __global__ void __launch_bounds__(kBlock) k_eliminate(DevEngine e, Inputs in, To
     wg_gemm(Ps + (int64_t)k * n, n, H1, ldh, false, A, n, false, r1, n, np, 1.0, 0.0);
     for (int j = ECLQR_TID; j < r1; j += ECLQR_NT) {
       double a = H1[j * ldh + np];
-      for (int l = 0; l < np; ++l) a = fma(H1[j * ldh + l], cv[l], a);
+      a = lane_chain<false>(a, H1 + j * ldh, 1, cv, 1, np);
       gs[k + j] = a;
     }
     wg_sync();
     // row scaling by the norms of [Gamma, Psi]
     for (int j = ECLQR_TID; j < q; j += ECLQR_NT) {
       double a = 0.0;
-      for (int l = 0; l < m; ++l) a = fma(Gs[j * m + l], Gs[j * m + l], a);
-      for (int l = 0; l < n; ++l) a = fma(Ps[j * n + l], Ps[j * n + l], a);
+      a = lane_chain<false>(a, Gs + j * m, 1, Gs + j * m, 1, m);
+      a = lane_chain<false>(a, Ps + j * n, 1, Ps + j * n, 1, n);
       rsc[j] = (a > 0.0) ? 1.0 / sqrt(a) : 1.0;
     }
     wg_sync();
@@ -139,7 +139,7 @@ __global__ void __launch_bounds__(kBlock) k_eliminate(DevEngine e, Inputs in, To
     wg_gemm(Phi, nb, Ps, n, false, T, nb, false, q, nb, n, 1.0, 0.0);
     for (int j = ECLQR_TID; j < q; j += ECLQR_NT) {
       double a = gs[j];
-      for (int l = 0; l < n; ++l) a = fma(Ps[j * n + l], tv[l], a);
+      a = lane_chain<false>(a, Ps + j * n, 1, tv, 1, n);
       gam[j] = a;
     }
     // Gamma^T in LDS, pivoted QR
@@ -177,7 +177,7 @@ __global__ void __launch_bounds__(kBlock) k_eliminate(DevEngine e, Inputs in, To
     wg_gemm(Y, nb, Qg, m, false, X, nb + 1, false, m, nb, rho, -1.0, 0.0);
     for (int i = ECLQR_TID; i < m; i += ECLQR_NT) {
       double a = 0.0;
-      for (int j = 0; j < rho; ++j) a = fma(Qg[i * m + j], X[j * (nb + 1) + nb], a);
+      a = lane_chain<false>(a, Qg + i * m, 1, X + nb, (nb + 1), rho);
       y[i] = -a;
     }
     for (int idx = ECLQR_TID; idx < m * mb; idx += ECLQR_NT) {
@@ -219,8 +219,8 @@ __global__ void __launch_bounds__(kBlock) k_eliminate(DevEngine e, Inputs in, To
     wg_gemm(Bb, mb, T1, nb1, true, BZ, mb, false, nb1, mb, np, 1.0, 0.0);
     for (int i = ECLQR_TID; i < np; i += ECLQR_NT) {
       double a = cv[i] - t1[i];
-      for (int j = 0; j < n; ++j) a = fma(A[i * n + j], tv[j], a);
-      for (int j = 0; j < m; ++j) a = fma(B[i * m + j], y[j], a);
+      a = lane_chain<false>(a, A + i * n, 1, tv, 1, n);
+      a = lane_chain<false>(a, B + i * m, 1, y, 1, m);
       cvv[i] = a;
     }
     wg_sync();
@@ -250,13 +250,13 @@ __global__ void __launch_bounds__(kBlock) k_eliminate(DevEngine e, Inputs in, To
     for (int i = ECLQR_TID; i < m; i += ECLQR_NT) {
       double a = rv[i];
       if (Mm)
-        for (int j = 0; j < n; ++j) a = fma(Mm[j * m + i], tv[j], a);
+        a = lane_chain<false>(a, Mm + i, m, tv, 1, n);
       rz[i] = a;
     }
     wg_sync();
     for (int i = ECLQR_TID; i < m; i += ECLQR_NT) {
       double a = rz[i];
-      for (int j = 0; j < m; ++j) a = fma(R[i * m + j], y[j], a);
+      a = lane_chain<false>(a, R + i * m, 1, y, 1, m);
       w[i] = a;
     }
     wg_sync();
@@ -279,15 +279,15 @@ __global__ void __launch_bounds__(kBlock) k_eliminate(DevEngine e, Inputs in, To
     // q^z = T^T (Q t + q); q-bar = q^z + Mz y + Y^T w ; r-bar = Z^T w
     for (int i = ECLQR_TID; i < n; i += ECLQR_NT) {
       double a = qv[i];
-      for (int j = 0; j < n; ++j) a = fma(Q[i * n + j], tv[j], a);
+      a = lane_chain<false>(a, Q + i * n, 1, tv, 1, n);
       QT[i] = a;  // reuse as a vector
     }
     wg_sync();
     wg_gemv(qz, T, nb, true, QT, nb, n, 1.0, 0.0);
     for (int i = ECLQR_TID; i < nb; i += ECLQR_NT) {
       double a = qz[i];
-      for (int j = 0; j < m; ++j) a = fma(Mz[i * m + j], y[j], a);
-      for (int j = 0; j < m; ++j) a = fma(Y[j * nb + i], w[j], a);
+      a = lane_chain<false>(a, Mz + i * m, 1, y, 1, m);
+      a = lane_chain<false>(a, Y + i, nb, w, 1, m);
       qb[i] = a;
     }
     wg_gemv(rb, Z, mb, true, w, mb, m, 1.0, 0.0);
@@ -295,12 +295,12 @@ __global__ void __launch_bounds__(kBlock) k_eliminate(DevEngine e, Inputs in, To
       double kap = 0.0;
       for (int i = 0; i < n; ++i) {
         double a = 0.0;
-        for (int j = 0; j < n; ++j) a = fma(Q[i * n + j], tv[j], a);
+        a = lane_chain<false>(a, Q + i * n, 1, tv, 1, n);
         kap += tv[i] * (0.5 * a + qv[i]);
       }
       for (int i = 0; i < m; ++i) {
         double a = 0.0;
-        for (int j = 0; j < m; ++j) a = fma(R[i * m + j], y[j], a);
+        a = lane_chain<false>(a, R + i * m, 1, y, 1, m);
         kap += y[i] * (0.5 * a + rz[i]);
       }
       base[ar.kap] = kap;
@@ -335,7 +335,7 @@ __global__ void __launch_bounds__(kBlock) k_eliminate(DevEngine e, Inputs in, To
     wg_gemm(Ae, nb, Wt, nb1, true, V, nb, false, nb1, nb, mb, -1.0, 1.0);
     for (int i = ECLQR_TID; i < nb1; i += ECLQR_NT) {
       double a = cb[i];
-      for (int j = 0; j < mb; ++j) a = fma(-Wt[j * nb1 + i], w2[j], a);
+      a = lane_chain<true>(a, Wt + i, nb1, w2, 1, mb);
       be[i] = a;
     }
     wg_gemm(Ce, nb1, Wt, nb1, true, Wt, nb1, false, nb1, nb1, mb, 1.0, 0.0);
@@ -345,7 +345,7 @@ __global__ void __launch_bounds__(kBlock) k_eliminate(DevEngine e, Inputs in, To
     wg_symmetrize(Je, nb, nb);
     for (int i = ECLQR_TID; i < nb; i += ECLQR_NT) {
       double a = qb[i];
-      for (int j = 0; j < mb; ++j) a = fma(-V[j * nb + i], w2[j], a);
+      a = lane_chain<true>(a, V + i, nb, w2, 1, mb);
       ee[i] = -a;
     }
     wg_sync();

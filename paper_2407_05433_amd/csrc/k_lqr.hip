@@ -6,6 +6,7 @@
 #include "device_util.hpp"
 #include "eclqr.h"
 #include "scratch.hpp"
+#include "smallreg.hpp"
 
 namespace eclqr {
 
@@ -30,7 +31,36 @@ namespace eclqr {
 // LU form is used.
 namespace {
 
-__device__ void combine_lu(const double* A1, const double* b1, const double* C1, const double* et1, const double* J1,
+// Routines of the combine: register-resident when NMAX > 0 and the size fits
+// (operands in LDS), else the LDS/global ones; both give the same bits.
+template <bool kL, int NMAX>
+__device__ __forceinline__ int d_cholesky(double* S, int ld, int n, double* sh, double floor, double* buf) {
+  if constexpr (NMAX > 0)
+    if (n <= NMAX) return reg_cholesky<NMAX>(S, ld, n, floor, buf);
+  return wg_cholesky<kL>(S, ld, n, sh, floor);
+}
+template <bool kL, int NMAX>
+__device__ __forceinline__ void d_trsm_lower(const double* L, int ld, double* X, int ldx, int n, int nc) {
+  if constexpr (NMAX > 0)
+    if (n <= NMAX) return reg_trsm_lower<NMAX>(L, ld, X, ldx, n, nc);
+  wg_trsm_lower<kL>(L, ld, X, ldx, n, nc);
+}
+template <bool kL, int NMAX>
+__device__ __forceinline__ void d_trsm_lower_t(const double* L, int ld, double* X, int ldx, int n, int nc) {
+  if constexpr (NMAX > 0)
+    if (n <= NMAX) return reg_trsm_lower_t<NMAX>(L, ld, X, ldx, n, nc);
+  wg_trsm_lower_t<kL>(L, ld, X, ldx, n, nc);
+}
+template <bool kL, int NMAX>
+__device__ __forceinline__ int d_pchol(const double* S, int ld, int n, double tol, double* K, int ldk, double* rem, int* used,
+                              double* sh, double* buf) {
+  if constexpr (NMAX > 0)
+    if (n <= NMAX) return reg_pchol<NMAX>(S, ld, n, tol, K, ldk, buf);
+  return wg_pchol<kL>(S, ld, n, tol, K, ldk, rem, used, sh);
+}
+
+template <bool kL>
+__device__ __forceinline__ void combine_lu(const double* A1, const double* b1, const double* C1, const double* et1, const double* J1,
                            const double* A2, const double* b2, const double* C2, const double* et2, const double* J2,
                            double* Eo, const RicLayout& lo, int ds, int dm, int de, bool binary, double* pool,
                            int* piv, double* sh, double* rlog) {
@@ -40,10 +70,10 @@ __device__ void combine_lu(const double* A1, const double* b1, const double* C1,
   double* T1 = Yv + rup4((int64_t)dm * (dm + 1));         // de x dm
   double* T2 = T1 + rup4((int64_t)de * dm);               // ds x dm
   const int lx = ds + 1 + dm, ly = dm + 1;
-  wg_gemm(Mt, dm, C1, dm, false, J2, dm, false, dm, dm, dm, 1.0, 0.0);
+  wg_gemm<kL>(Mt, dm, C1, dm, false, J2, dm, false, dm, dm, dm, 1.0, 0.0);
   for (int i = ECLQR_TID; i < dm; i += ECLQR_NT) Mt[i * dm + i] += 1.0;
-  wg_sync();
-  wg_lu(Mt, dm, dm, piv, sh);
+  bsync<kL>();
+  wg_lu<kL>(Mt, dm, dm, piv, sh);
   // log for the vector-only pass: flag 2, LU factors, pivots
   for (int idx = ECLQR_TID; idx < dm * dm; idx += ECLQR_NT) rlog[4 + idx] = Mt[idx];
   for (int i = ECLQR_TID; i < dm; i += ECLQR_NT) rlog[4 + 2 * dm * dm + i] = (double)piv[i];
@@ -53,9 +83,7 @@ __device__ void combine_lu(const double* A1, const double* b1, const double* C1,
     if (j < dm) {
       Yv[idx] = J2[i * dm + j];
     } else {
-      double v = et2[i];
-      for (int l = 0; l < dm; ++l) v = fma(-J2[i * dm + l], b1[l], v);
-      Yv[idx] = v;
+      Yv[idx] = lane_chain<true>(et2[i], J2 + i * dm, 1, b1, 1, dm);
     }
   }
   if (binary) {
@@ -65,48 +93,40 @@ __device__ void combine_lu(const double* A1, const double* b1, const double* C1,
       if (j < ds) {
         v = A1[i * ds + j];
       } else if (j == ds) {
-        v = b1[i];
-        for (int l = 0; l < dm; ++l) v = fma(C1[i * dm + l], et2[l], v);
+        v = lane_chain<false>(b1[i], C1 + i * dm, 1, et2, 1, dm);
       } else {
         v = C1[i * dm + (j - ds - 1)];
       }
       X[idx] = v;
     }
   }
-  wg_sync();
-  wg_lu_solve_t(Mt, dm, dm, piv, Yv, ly, ly);
-  wg_gemm(T2, dm, A1, ds, true, Yv, ly, false, ds, dm, dm, 1.0, 0.0);
-  wg_gemm(Eo + lo.J, ds, T2, dm, false, A1, ds, false, ds, ds, dm, 1.0, 0.0);
+  bsync<kL>();
+  wg_lu_solve_t<kL>(Mt, dm, dm, piv, Yv, ly, ly);
+  wg_gemm<kL>(T2, dm, A1, ds, true, Yv, ly, false, ds, dm, dm, 1.0, 0.0);
+  wg_gemm<kL>(Eo + lo.J, ds, T2, dm, false, A1, ds, false, ds, ds, dm, 1.0, 0.0);
   for (int idx = ECLQR_TID; idx < ds * ds; idx += ECLQR_NT) Eo[lo.J + idx] += J1[idx];
-  for (int i = ECLQR_TID; i < ds; i += ECLQR_NT) {
-    double v = et1[i];
-    for (int l = 0; l < dm; ++l) v = fma(A1[l * ds + i], Yv[l * ly + dm], v);
-    Eo[lo.eta + i] = v;
-  }
-  wg_sync();
-  wg_symmetrize(Eo + lo.J, ds, ds);
+  for (int i = ECLQR_TID; i < ds; i += ECLQR_NT) Eo[lo.eta + i] = lane_chain<false>(et1[i], A1 + i, ds, Yv + dm, ly, dm);
+  bsync<kL>();
+  wg_symmetrize<kL>(Eo + lo.J, ds, ds);
   if (binary) {
-    wg_lu_solve(Mt, dm, dm, piv, X, lx, lx);
-    wg_gemm(Eo + lo.A, ds, A2, dm, false, X, lx, false, de, ds, dm, 1.0, 0.0);
-    for (int i = ECLQR_TID; i < de; i += ECLQR_NT) {
-      double v = b2[i];
-      for (int l = 0; l < dm; ++l) v = fma(A2[i * dm + l], X[l * lx + ds], v);
-      Eo[lo.b + i] = v;
-    }
-    wg_gemm(T1, dm, A2, dm, false, X + ds + 1, lx, false, de, dm, dm, 1.0, 0.0);
-    wg_gemm(Eo + lo.C, de, T1, dm, false, A2, dm, true, de, de, dm, 1.0, 0.0);
+    wg_lu_solve<kL>(Mt, dm, dm, piv, X, lx, lx);
+    wg_gemm<kL>(Eo + lo.A, ds, A2, dm, false, X, lx, false, de, ds, dm, 1.0, 0.0);
+    for (int i = ECLQR_TID; i < de; i += ECLQR_NT) Eo[lo.b + i] = lane_chain<false>(b2[i], A2 + i * dm, 1, X + ds, lx, dm);
+    wg_gemm<kL>(T1, dm, A2, dm, false, X + ds + 1, lx, false, de, dm, dm, 1.0, 0.0);
+    wg_gemm<kL>(Eo + lo.C, de, T1, dm, false, A2, dm, true, de, de, dm, 1.0, 0.0);
     for (int idx = ECLQR_TID; idx < de * de; idx += ECLQR_NT) Eo[lo.C + idx] += C2[idx];
-    wg_sync();
-    wg_symmetrize(Eo + lo.C, de, de);
+    bsync<kL>();
+    wg_symmetrize<kL>(Eo + lo.C, de, de);
   }
 }
 
 // Factored combine; returns false (having written nothing) when J2 or G is not
 // numerically positive definite.
-__device__ bool combine_factored(const double* A1, const double* b1, const double* C1, const double* et1,
+template <bool kL, int NMAX>
+__device__ __forceinline__ bool combine_factored(const double* A1, const double* b1, const double* C1, const double* et1,
                                  const double* J1, const double* A2, const double* b2, const double* C2,
                                  const double* et2, const double* J2, double* Eo, const RicLayout& lo, int ds, int dm,
-                                 int de, bool binary, double* pool, int* used, double* sh, double* rlog) {
+                                 int de, bool binary, double* pool, int* used, double* sh, double* rlog, double* buf) {
   const int64_t dd = rup4((int64_t)dm * dm);
   double* Lj = pool;                          // dm x dm   L (J2 = L L')
   double* Gm = Lj + dd;                       // dm x dm   G, then Rg
@@ -123,96 +143,137 @@ __device__ bool combine_factored(const double* A1, const double* b1, const doubl
   double mx = 0.0;
   for (int i = 0; i < dm; ++i) mx = fmax(mx, J2[i * dm + i]);
   if (!(mx > 0.0)) return false;
-  wg_copy(Lj, dm, J2, dm, dm, dm);
-  if (wg_cholesky(Lj, dm, dm, sh, 1e-15 * mx)) return false;
+  wg_copy<kL>(Lj, dm, J2, dm, dm, dm);
+  if (d_cholesky<kL, NMAX>(Lj, dm, dm, sh, 1e-15 * mx, buf)) return false;
   // G = I + L'(C1 L)
-  wg_gemm(Tm, dm, C1, dm, false, Lj, dm, false, dm, dm, dm, 1.0, 0.0);
-  wg_gemm(Gm, dm, Lj, dm, true, Tm, dm, false, dm, dm, dm, 1.0, 0.0);
+  wg_gemm<kL>(Tm, dm, C1, dm, false, Lj, dm, false, dm, dm, dm, 1.0, 0.0);
+  wg_gemm<kL>(Gm, dm, Lj, dm, true, Tm, dm, false, dm, dm, dm, 1.0, 0.0);
   for (int i = ECLQR_TID; i < dm; i += ECLQR_NT) Gm[i * dm + i] += 1.0;
-  wg_sync();
-  wg_symmetrize(Gm, dm, dm);
-  if (wg_cholesky(Gm, dm, dm, sh)) return false;
+  bsync<kL>();
+  wg_symmetrize<kL>(Gm, dm, dm);
+  if (d_cholesky<kL, NMAX>(Gm, dm, dm, sh, 0.0, buf)) return false;
   // log for the vector-only pass: flag 1, L, Rg
   for (int idx = ECLQR_TID; idx < dm * dm; idx += ECLQR_NT) {
     rlog[4 + idx] = Lj[idx];
     rlog[4 + dm * dm + idx] = Gm[idx];
   }
   if (ECLQR_TID == 0) rlog[0] = 1.0;
-  // xi = L^{-1} eta2 ; tv = d = G^{-1}(xi - L'b1) ; wv = L d
-  for (int i = ECLQR_TID; i < dm; i += ECLQR_NT) xi[i] = et2[i];
-  wg_sync();
-  wg_trsm_lower(Lj, dm, xi, 1, dm, 1);
-  for (int i = ECLQR_TID; i < dm; i += ECLQR_NT) {
-    double v = xi[i];
-    for (int l = i; l < dm; ++l) v = fma(-Lj[l * dm + i], b1[l], v);
-    tv[i] = v;
+  // xi = L^{-1} eta2 ; tv = d = G^{-1}(xi - L'b1) ; wv = L d  (entry i in lane i)
+  {
+    const int lane = ECLQR_TID;
+    double xv = (lane < dm) ? et2[lane] : 0.0;
+    xv = lane_trsv_lower(Lj, dm, xv, dm);
+    double dv = xv;
+    if (lane < dm) dv = lane_chain<true>(dv, Lj + lane * dm + lane, dm, b1 + lane, 1, dm - lane);
+    dv = lane_trsv_lower(Gm, dm, dv, dm);
+    dv = lane_trsv_lower_t(Gm, dm, dv, dm);
+    if (lane < dm) {
+      xi[lane] = xv;
+      tv[lane] = dv;
+    }
   }
-  wg_sync();
-  wg_trsm_lower(Gm, dm, tv, 1, dm, 1);
-  wg_trsm_lower_t(Gm, dm, tv, 1, dm, 1);
-  for (int i = ECLQR_TID; i < dm; i += ECLQR_NT) {
-    double v = 0.0;
-    for (int l = 0; l <= i; ++l) v = fma(Lj[i * dm + l], tv[l], v);
-    wv[i] = v;
-  }
-  wg_sync();
-  for (int i = ECLQR_TID; i < ds; i += ECLQR_NT) {
-    double v = et1[i];
-    for (int l = 0; l < dm; ++l) v = fma(A1[l * ds + i], wv[l], v);
-    Eo[lo.eta + i] = v;
-  }
+  bsync<kL>();
+  for (int i = ECLQR_TID; i < dm; i += ECLQR_NT) wv[i] = lane_chain<false>(0.0, Lj + i * dm, 1, tv, 1, i + 1);
+  bsync<kL>();
+  for (int i = ECLQR_TID; i < ds; i += ECLQR_NT) Eo[lo.eta + i] = lane_chain<false>(et1[i], A1 + i, ds, wv, 1, dm);
   // Mm = Rg^{-1} L' ; Yb[:, :ds] = Mm A1 ; J = J1 + Yb'Yb
-  wg_copy_t(Mm, dm, Lj, dm, dm, dm);
-  wg_trsm_lower(Gm, dm, Mm, dm, dm, dm);
+  wg_copy_t<kL>(Mm, dm, Lj, dm, dm, dm);
+  d_trsm_lower<kL, NMAX>(Gm, dm, Mm, dm, dm, dm);
   const int ly = ds + 1;
-  wg_gemm(Yb, ly, Mm, dm, false, A1, ds, false, dm, ds, dm, 1.0, 0.0);
-  wg_gemm(Eo + lo.J, ds, Yb, ly, true, Yb, ly, false, ds, ds, dm, 1.0, 0.0);
+  wg_gemm<kL>(Yb, ly, Mm, dm, false, A1, ds, false, dm, ds, dm, 1.0, 0.0);
+  wg_gemm<kL>(Eo + lo.J, ds, Yb, ly, true, Yb, ly, false, ds, ds, dm, 1.0, 0.0);
   for (int idx = ECLQR_TID; idx < ds * ds; idx += ECLQR_NT) Eo[lo.J + idx] += J1[idx];
-  wg_sync();
-  wg_symmetrize(Eo + lo.J, ds, ds);
+  bsync<kL>();
+  wg_symmetrize<kL>(Eo + lo.J, ds, ds);
   if (!binary) return true;
   // Yb = L^{-T} [Rg^{-T} Mm A1 | xi - d] ; A = A2 Yb[:, :ds] ; b = A2 Yb[:, ds] + b2
   for (int i = ECLQR_TID; i < dm; i += ECLQR_NT) Yb[i * ly + ds] = xi[i] - tv[i];
-  wg_sync();
-  wg_trsm_lower_t(Gm, dm, Yb, ly, dm, ds);
-  wg_trsm_lower_t(Lj, dm, Yb, ly, dm, ly);
-  wg_gemm(Eo + lo.A, ds, A2, dm, false, Yb, ly, false, de, ds, dm, 1.0, 0.0);
-  for (int i = ECLQR_TID; i < de; i += ECLQR_NT) {
-    double v = b2[i];
-    for (int l = 0; l < dm; ++l) v = fma(A2[i * dm + l], Yb[l * ly + ds], v);
-    Eo[lo.b + i] = v;
-  }
+  bsync<kL>();
+  d_trsm_lower_t<kL, NMAX>(Gm, dm, Yb, ly, dm, ds);
+  d_trsm_lower_t<kL, NMAX>(Lj, dm, Yb, ly, dm, ly);
+  wg_gemm<kL>(Eo + lo.A, ds, A2, dm, false, Yb, ly, false, de, ds, dm, 1.0, 0.0);
+  for (int i = ECLQR_TID; i < de; i += ECLQR_NT) Eo[lo.b + i] = lane_chain<false>(b2[i], A2 + i * dm, 1, Yb + ds, ly, dm);
   // C = C2 + (A2 K R2^{-T})(A2 K R2^{-T})'
-  const int r = wg_pchol(C1, dm, dm, 1e-15, Km, dm, rem, used, sh);
+  const int r = d_pchol<kL, NMAX>(C1, dm, dm, 1e-15, Km, dm, rem, used, sh, buf);
   if (r > 0) {
-    wg_gemm(Tm, r, J2, dm, false, Km, dm, false, dm, r, dm, 1.0, 0.0);
-    wg_gemm(G2, r, Km, dm, true, Tm, r, false, r, r, dm, 1.0, 0.0);
+    wg_gemm<kL>(Tm, r, J2, dm, false, Km, dm, false, dm, r, dm, 1.0, 0.0);
+    wg_gemm<kL>(G2, r, Km, dm, true, Tm, r, false, r, r, dm, 1.0, 0.0);
     for (int i = ECLQR_TID; i < r; i += ECLQR_NT) G2[i * r + i] += 1.0;
-    wg_sync();
-    wg_symmetrize(G2, r, r);
-    if (wg_cholesky(G2, r, r, sh)) return false;
-    wg_copy_t(Mm, dm, Km, dm, dm, r);           // K' (r x dm)
-    wg_trsm_lower(G2, r, Mm, dm, r, dm);
-    wg_gemm(AN, r, A2, dm, false, Mm, dm, true, de, r, dm, 1.0, 0.0);
-    wg_gemm(Eo + lo.C, de, AN, r, false, AN, r, true, de, de, r, 1.0, 0.0);
+    bsync<kL>();
+    wg_symmetrize<kL>(G2, r, r);
+    if (d_cholesky<kL, NMAX>(G2, r, r, sh, 0.0, buf)) return false;
+    wg_copy_t<kL>(Mm, dm, Km, dm, dm, r);           // K' (r x dm)
+    d_trsm_lower<kL, NMAX>(G2, r, Mm, dm, r, dm);
+    wg_gemm<kL>(AN, r, A2, dm, false, Mm, dm, true, de, r, dm, 1.0, 0.0);
+    wg_gemm<kL>(Eo + lo.C, de, AN, r, false, AN, r, true, de, de, r, 1.0, 0.0);
   } else {
-    wg_fill(Eo + lo.C, de, de, de, 0.0);
+    wg_fill<kL>(Eo + lo.C, de, de, de, 0.0);
   }
   for (int idx = ECLQR_TID; idx < de * de; idx += ECLQR_NT) Eo[lo.C + idx] += C2[idx];
-  wg_sync();
-  wg_symmetrize(Eo + lo.C, de, de);
+  bsync<kL>();
+  wg_symmetrize<kL>(Eo + lo.C, de, de);
   return true;
 }
 
 }  // namespace
 
-// LDS: [pool (when it fits) | piv/used ints | sh]
-__global__ void __launch_bounds__(kBlock) k_ric_combine(DevEngine e, int64_t first, int64_t ntasks, int32_t* status,
-                                                        int maxd, int pool_in_lds) {
+// Copy the used part of a value-function element with reduced dims (na, nb)
+// between two layouts (fields A, b, C, eta, J, each contiguous); all loads of
+// a round are issued before its stores.
+__device__ __forceinline__ void ric_move(double* dst, const RicLayout& ld, const double* src, const RicLayout& ls, int na,
+                                int nb) {
+  const int64_t n0 = (int64_t)nb * na, n1 = n0 + nb, n2 = n1 + (int64_t)nb * nb, n3 = n2 + na,
+                n4 = n3 + (int64_t)na * na;
+  for (int64_t f0 = ECLQR_TID; f0 < n4; f0 += 8 * ECLQR_NT) {
+    double v[8];
+    int64_t od[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int64_t f = f0 + (int64_t)t * ECLQR_NT;
+      int64_t os = 0, o = -1;
+      if (f < n0) {
+        os = ls.A + f;
+        o = ld.A + f;
+      } else if (f < n1) {
+        os = ls.b + (f - n0);
+        o = ld.b + (f - n0);
+      } else if (f < n2) {
+        os = ls.C + (f - n1);
+        o = ld.C + (f - n1);
+      } else if (f < n3) {
+        os = ls.eta + (f - n2);
+        o = ld.eta + (f - n2);
+      } else if (f < n4) {
+        os = ls.J + (f - n3);
+        o = ld.J + (f - n3);
+      }
+      od[t] = o;
+      v[t] = (o >= 0) ? src[os] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+      if (od[t] >= 0) dst[od[t]] = v[t];
+  }
+}
+
+// kMode 0: work pool in per-block global scratch; 1: pool in LDS; 2: both
+// operands, the result and the pool in LDS (operands staged in, result
+// written out in bulk), every barrier LDS-only.
+// LDS: [operand 1 | operand 2 | result (mode 2)] [pool (modes 1, 2)] | piv/used ints | sh
+// NMAX > 0 (mode 2 only): factorizations and solves of size <= NMAX run
+// register-resident.
+template <int kMode, int NMAX>
+__global__ void __launch_bounds__(kBlock, 1) k_ric_combine(DevEngine e, int64_t first, int64_t ntasks, int32_t* status,
+                                                        int maxd) {
   extern __shared__ double lds[];
-  const int64_t pool_sz = pool_in_lds ? ric_pool(maxd) : 0;
-  int* piv = (int*)(lds + pool_sz);
+  const int64_t esz = (kMode == 2) ? ric_layout(maxd, maxd).size : 0;
+  const int64_t pool_sz = (kMode >= 1) ? ric_pool(maxd) : 0;
+  double* S1 = lds;
+  double* S2 = S1 + esz;
+  double* So = S2 + esz;
+  int* piv = (int*)(lds + 3 * esz + pool_sz);
   double* sh = (double*)(piv + kMaxDim);
+  double* buf = sh + 16;
   for (int64_t ti = blockIdx.x; ti < ntasks; ti += gridDim.x) {
     const int a = e.tasks[3 * (first + ti)];
     const int bsl = e.tasks[3 * (first + ti) + 1];
@@ -225,13 +286,30 @@ __global__ void __launch_bounds__(kBlock) k_ric_combine(DevEngine e, int64_t fir
     const double* E1 = slot_ptr(e, SCAN_RIC, a);
     const double* E2 = slot_ptr(e, SCAN_RIC, bsl);
     double* Eo = slot_ptr(e, SCAN_RIC, o);
-    const double *A1 = E1 + l1.A, *b1 = E1 + l1.b, *C1 = E1 + l1.C, *et1 = E1 + l1.eta, *J1 = E1 + l1.J;
-    const double *A2 = E2 + l2.A, *b2 = E2 + l2.b, *C2 = E2 + l2.C, *et2 = E2 + l2.eta, *J2 = E2 + l2.J;
-    double* pool = pool_in_lds ? lds : block_scratch(e);
     const bool binary = se >= 0;
     double* rlog = e.ric_log + e.ric_log_off[o];
-    if (!combine_factored(A1, b1, C1, et1, J1, A2, b2, C2, et2, J2, Eo, lo, ds, dm, de, binary, pool, piv, sh, rlog))
-      combine_lu(A1, b1, C1, et1, J1, A2, b2, C2, et2, J2, Eo, lo, ds, dm, de, binary, pool, piv, sh, rlog);
+    if constexpr (kMode == 2) {
+      const RicLayout s1 = ric_layout(ds, dm), s2 = ric_layout(dm, de), so = ric_layout(ds, de);
+      ric_move(S1, s1, E1, l1, ds, dm);
+      ric_move(S2, s2, E2, l2, dm, de);
+      lds_sync();
+      const double *A1 = S1 + s1.A, *b1 = S1 + s1.b, *C1 = S1 + s1.C, *et1 = S1 + s1.eta, *J1 = S1 + s1.J;
+      const double *A2 = S2 + s2.A, *b2 = S2 + s2.b, *C2 = S2 + s2.C, *et2 = S2 + s2.eta, *J2 = S2 + s2.J;
+      double* pool = lds + 3 * esz;
+      if (!combine_factored<true, NMAX>(A1, b1, C1, et1, J1, A2, b2, C2, et2, J2, So, so, ds, dm, de, binary, pool,
+                                        piv, sh, rlog, buf))
+        combine_lu<true>(A1, b1, C1, et1, J1, A2, b2, C2, et2, J2, So, so, ds, dm, de, binary, pool, piv, sh, rlog);
+      lds_sync();
+      ric_move(Eo, lo, So, so, ds, de);
+      lds_sync();
+    } else {
+      const double *A1 = E1 + l1.A, *b1 = E1 + l1.b, *C1 = E1 + l1.C, *et1 = E1 + l1.eta, *J1 = E1 + l1.J;
+      const double *A2 = E2 + l2.A, *b2 = E2 + l2.b, *C2 = E2 + l2.C, *et2 = E2 + l2.eta, *J2 = E2 + l2.J;
+      double* pool = (kMode == 1) ? lds : block_scratch(e);
+      if (!combine_factored<false, 0>(A1, b1, C1, et1, J1, A2, b2, C2, et2, J2, Eo, lo, ds, dm, de, binary, pool,
+                                      piv, sh, rlog, buf))
+        combine_lu<false>(A1, b1, C1, et1, J1, A2, b2, C2, et2, J2, Eo, lo, ds, dm, de, binary, pool, piv, sh, rlog);
+    }
     (void)status;
   }
 }
@@ -271,7 +349,7 @@ __global__ void __launch_bounds__(kBlock) k_gains(DevEngine e, int32_t* status, 
     wg_gemm(PA, nb, P1, nb1, false, Ab, nb, false, nb1, nb, nb1, 1.0, 0.0);
     for (int i = ECLQR_TID; i < nb1; i += ECLQR_NT) {
       double v = -et1[i];
-      for (int l = 0; l < nb1; ++l) v = fma(P1[i * nb1 + l], cb[l], v);
+      v = lane_chain<false>(v, P1 + i * nb1, 1, cb, 1, nb1);
       pc[i] = v;
     }
     wg_copy(Huu, mb, Rb, mb, mb, mb);
@@ -281,7 +359,7 @@ __global__ void __launch_bounds__(kBlock) k_gains(DevEngine e, int32_t* status, 
     wg_gemm(Hux, nb, Bb, mb, true, PA, nb, false, mb, nb, nb1, 1.0, 1.0);
     for (int i = ECLQR_TID; i < mb; i += ECLQR_NT) {
       double v = rb[i];
-      for (int l = 0; l < nb1; ++l) v = fma(Bb[l * mb + i], pc[l], v);
+      v = lane_chain<false>(v, Bb + i, mb, pc, 1, nb1);
       hu[i] = v;
     }
     wg_sync();
@@ -306,7 +384,7 @@ __global__ void __launch_bounds__(kBlock) k_gains(DevEngine e, int32_t* status, 
     wg_gemm(Fs, nb, Bb, mb, false, K, nb, false, nb1, nb, mb, 1.0, 1.0);
     for (int i = ECLQR_TID; i < nb1; i += ECLQR_NT) {
       double v = cb[i];
-      for (int l = 0; l < mb; ++l) v = fma(Bb[i * mb + l], kk[l], v);
+      v = lane_chain<false>(v, Bb + i * mb, 1, kk, 1, mb);
       fs[i] = v;
     }
     wg_sync();
@@ -334,7 +412,7 @@ __global__ void __launch_bounds__(kBlock) k_fwd_combine(DevEngine e, int64_t fir
     if (sin_ >= 0) wg_gemm(Fo, din, F1, dmid, false, F2, din, false, dout, din, dmid, 1.0, 0.0);
     for (int i = ECLQR_TID; i < dout; i += ECLQR_NT) {
       double v = f1[i];
-      for (int l = 0; l < dmid; ++l) v = fma(F1[i * dmid + l], f2[l], v);
+      v = lane_chain<false>(v, F1 + i * dmid, 1, f2, 1, dmid);
       fo[i] = v;
     }
     wg_sync();
@@ -344,6 +422,7 @@ __global__ void __launch_bounds__(kBlock) k_fwd_combine(DevEngine e, int64_t fir
 // Recovery (eq. (recovery-maps)): v_i = K_i z_i + k_i, x_i = T_i z_i + t_i,
 // u_i = Y_i z_i + Z_i v_i + y_i.
 __global__ void __launch_bounds__(kBlock) k_recover(DevEngine e, double* x, double* u) {
+  if (none_live(e)) return;
   __shared__ double vsh[kMaxDim];
   for (int64_t s = blockIdx.x; s < e.S; s += gridDim.x) {
     const StageInfo st = e.st[s];
@@ -358,7 +437,7 @@ __global__ void __launch_bounds__(kBlock) k_recover(DevEngine e, double* x, doub
     const double* tv = base + ar.t;
     for (int i = ECLQR_TID; i < n; i += ECLQR_NT) {
       double v = tv[i];
-      for (int l = 0; l < nb; ++l) v = fma(T[i * nb + l], z[l], v);
+      v = lane_chain<false>(v, T + i * nb, 1, z, 1, nb);
       xo[i] = v;
     }
     if (!st.terminal) {
@@ -366,15 +445,15 @@ __global__ void __launch_bounds__(kBlock) k_recover(DevEngine e, double* x, doub
       const double *K = base + ar.K, *kk = base + ar.kk, *Y = base + ar.Y, *Z = base + ar.Z, *y = base + ar.y;
       for (int i = ECLQR_TID; i < mb; i += ECLQR_NT) {
         double v = kk[i];
-        for (int l = 0; l < nb; ++l) v = fma(K[i * nb + l], z[l], v);
+        v = lane_chain<false>(v, K + i * nb, 1, z, 1, nb);
         vsh[i] = v;
       }
       __syncthreads();
       double* uo = u + st.in[IN_r];
       for (int i = ECLQR_TID; i < m; i += ECLQR_NT) {
         double v = y[i];
-        for (int l = 0; l < nb; ++l) v = fma(Y[i * nb + l], z[l], v);
-        for (int l = 0; l < mb; ++l) v = fma(Z[i * mb + l], vsh[l], v);
+        v = lane_chain<false>(v, Y + i * nb, 1, z, 1, nb);
+        v = lane_chain<false>(v, Z + i * mb, 1, vsh, 1, mb);
         uo[i] = v;
       }
     }
@@ -386,26 +465,54 @@ static int g_lqr_max_lds = 65536;
 
 void lqr_set_max_lds(int bytes) {
   g_lqr_max_lds = bytes;
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_ric_combine), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            bytes);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_ric_combine<1, 0>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_ric_combine<2, 0>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_ric_combine<2, 16>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_ric_combine<2, 32>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_gains), hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
-static bool ric_pool_fits(int maxd) {
-  return sizeof(double) * ((size_t)ric_pool(maxd) + 16) + sizeof(int) * kMaxDim + 64 <= (size_t)g_lqr_max_lds;
+// LDS bytes of a value-function combine launch in mode m at middle dim bound d.
+static size_t ric_mode_bytes(int m, int d) {
+  const size_t esz = (m == 2) ? (size_t)ric_layout(d, d).size : 0;
+  const size_t pool = (m >= 1) ? (size_t)ric_pool(d) : 0;
+  return sizeof(double) * (3 * esz + pool + 16 + kMaxDim) + sizeof(int) * kMaxDim + 64;
 }
-size_t ric_lds_bytes(int maxd) {
-  return sizeof(double) * ((ric_pool_fits(maxd) ? (size_t)ric_pool(maxd) : 0) + 16) + sizeof(int) * kMaxDim + 64;
+// Mode actually used for a requested mode: the largest one <= requested whose
+// LDS fits.
+static int ric_mode(int want, int d) {
+  for (int m = want; m > 0; --m)
+    if (ric_mode_bytes(m, d) <= (size_t)g_lqr_max_lds) return m;
+  return 0;
 }
+size_t ric_lds_bytes(int maxd) { return ric_mode_bytes(ric_mode(2, maxd), maxd); }
 size_t gains_lds_bytes(int maxm) { return sizeof(double) * ((size_t)maxm * maxm + 16) + 64; }
 
 void launch_ric_combine(const DevEngine& e, int64_t first, int64_t ntasks, int32_t* status, int maxd,
                         hipStream_t s) {
   if (ntasks <= 0) return;
   const int grid = (int)(ntasks < e.nblocks ? ntasks : e.nblocks);
-  const int in_lds = (e.pool_lds && ric_pool_fits(maxd)) ? 1 : 0;
-  const size_t lds = in_lds ? ric_lds_bytes(maxd) : sizeof(double) * 16 + sizeof(int) * kMaxDim + 64;
-  hipLaunchKernelGGL(k_ric_combine, dim3(grid), dim3(kBlock), lds, s, e, first, ntasks, status, maxd, in_lds);
+  const int mode = ric_mode(e.pool_lds, maxd);
+  const size_t lds = ric_mode_bytes(mode, maxd);
+  if (mode == 2 && maxd <= 16)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ric_combine<2, 16>), dim3(grid), dim3(kBlock), lds, s, e, first, ntasks,
+                       status, maxd);
+  else if (mode == 2 && maxd <= 32)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ric_combine<2, 32>), dim3(grid), dim3(kBlock), lds, s, e, first, ntasks,
+                       status, maxd);
+  else if (mode == 2)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ric_combine<2, 0>), dim3(grid), dim3(kBlock), lds, s, e, first, ntasks,
+                       status, maxd);
+  else if (mode == 1)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ric_combine<1, 0>), dim3(grid), dim3(kBlock), lds, s, e, first, ntasks,
+                       status, maxd);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ric_combine<0, 0>), dim3(grid), dim3(kBlock), lds, s, e, first, ntasks,
+                       status, maxd);
 }
 
 void launch_gains(const DevEngine& e, int32_t* status, int maxm, hipStream_t s) {

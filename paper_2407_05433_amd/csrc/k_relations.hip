@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(kBlock) k_validate(DevEngine e, Inputs in, int
 __device__ inline double scale_rows(double* W, int ld, int p, int ncoef, double* sh, double* scales) {
   for (int r = ECLQR_TID; r < p; r += ECLQR_NT) {
     double s = 0.0;
-    for (int j = 0; j < ncoef; ++j) s = fma(W[r * ld + j], W[r * ld + j], s);
+    s = lane_chain<false>(s, W + r * ld, 1, W + r * ld, 1, ncoef);
     const double inv = (s > 0.0) ? 1.0 / sqrt(s) : 1.0;
     if (s > 0.0)
       for (int j = 0; j <= ncoef; ++j) W[r * ld + j] *= inv;
@@ -484,7 +484,7 @@ __global__ void __launch_bounds__(kBlock) k_domain(DevEngine e, Inputs in, Tols 
     for (int idx = ECLQR_TID; idx < n * nb; idx += ECLQR_NT) T[idx] = X[idx];
     for (int i = ECLQR_TID; i < n; i += ECLQR_NT) {
       double v = 0.0;
-      for (int j = 0; j < r; ++j) v = fma(H[j * (n + 1) + i], H[j * (n + 1) + n], v);
+      v = lane_chain<false>(v, H + i, (n + 1), H + n, (n + 1), r);
       tv[i] = -v;
     }
     if (ECLQR_TID == 0) e.nbar[s] = nb;
@@ -497,7 +497,7 @@ __global__ void __launch_bounds__(kBlock) k_domain(DevEngine e, Inputs in, Tols 
         for (int j = 0; j < r; ++j) {
           double v = H[j * (n + 1) + n];
           sc = fmax(sc, fabs(v));
-          for (int i = 0; i < n; ++i) v = fma(H[j * (n + 1) + i], x0[i], v);
+          v = lane_chain<false>(v, H + j * (n + 1), 1, x0, 1, n);
           res = fmax(res, fabs(v));
         }
         if (res > t.cons * sc) flag(status, st.inst, ECLQR_INFEASIBLE_INITIAL);

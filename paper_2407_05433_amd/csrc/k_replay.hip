@@ -25,63 +25,68 @@ namespace {
 
 constexpr int kMaxRows = 4 * kMaxDim;  // stacked rows of a composition (two relations of <= 2n rows)
 
-// Solve L y = x (L lower triangular, n x n, n <= 64) for a vector held one
-// entry per lane; returns the lane's entry of y.
-__device__ inline double lane_trsv_lower(const double* L, int ld, double v, int n) {
-  const int lane = ECLQR_TID;
-  for (int i = 0; i < n; ++i) {
-    const double xi = __shfl(v, i, 64) / L[i * ld + i];
-    if (lane > i && lane < n) v = fma(-L[lane * ld + i], xi, v);
-    if (lane == i) v = xi;
-  }
-  return v;
-}
-
-// Solve L' y = x (L lower triangular).
-__device__ inline double lane_trsv_lower_t(const double* L, int ld, double v, int n) {
-  const int lane = ECLQR_TID;
-  for (int i = n - 1; i >= 0; --i) {
-    const double yi = __shfl(v, i, 64) / L[i * ld + i];
-    if (lane < i) v = fma(-L[i * ld + lane], yi, v);
-    if (lane == i) v = yi;
-  }
-  return v;
-}
-
-// Solve U' y = x (U upper triangular).
-__device__ inline double lane_trsv_upper_t(const double* U, int ld, double v, int n) {
-  const int lane = ECLQR_TID;
-  for (int i = 0; i < n; ++i) {
-    const double xi = __shfl(v, i, 64) / U[i * ld + i];
-    if (lane > i && lane < n) v = fma(-U[i * ld + lane], xi, v);
-    if (lane == i) v = xi;
-  }
-  return v;
-}
-
-// Replay a relation log on the offset column o (LDS, p entries).  Returns the
-// rows eliminated (rho) and kept (rr); the new offsets are o[rho .. rho+rr).
-__device__ inline void rel_replay(double* o, const double* lg, const RelLog& L, int P, int R, int C, bool scaled,
-                                  int* rho_out, int* rr_out) {
+// Header of a relation log, clamped to the log's capacity: rows p, eliminated
+// columns rho, kept rows rr.
+struct RelHdr {
+  int p, rho, rr;
+};
+__device__ inline RelHdr rel_header(const double* lg, int P, int R, int C) {
   int p = (int)lg[0], rho = (int)lg[1], rr = (int)lg[2];
   p = (p < 0) ? 0 : ((p > P) ? P : p);
   rho = (rho < 0) ? 0 : ((rho > R) ? R : rho);
   rho = (rho > p) ? p : rho;
   rr = (rr < 0) ? 0 : ((rr > C) ? C : rr);
   rr = (rr > p - rho) ? p - rho : rr;
+  return RelHdr{p, rho, rr};
+}
+
+// dst[r * stride + k] = src[r * stride + k] for r < nr, k < len: eight
+// ranges' loads in flight per lane.
+__device__ inline void stage_ranges(double* dst, const double* src, int64_t stride, int nr, int len) {
+  for (int r0 = 0; r0 < nr; r0 += 8)
+    for (int k = ECLQR_TID; k < len; k += ECLQR_NT) {
+      double v[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) v[t] = (r0 + t < nr) ? src[(int64_t)(r0 + t) * stride + k] : 0.0;
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        if (r0 + t < nr) dst[(int64_t)(r0 + t) * stride + k] = v[t];
+    }
+}
+
+// Copy what a replay of the log reads into LDS at the log's own offsets:
+// header, row scales, tau and reflectors of the rho eliminated columns (rows
+// < p) and the rr Gram-Schmidt records (entries < 2 + C + p).
+__device__ inline void stage_rel_log(double* dst, const double* lg, const RelLog& L, int P, int C, const RelHdr& h,
+                                     bool scaled) {
+  stage_ranges(dst, lg, 0, 1, 4);
+  if (scaled) stage_ranges(dst + L.scale, lg + L.scale, 0, 1, h.p);
+  stage_ranges(dst + L.tau, lg + L.tau, 0, 1, h.rho);
+  stage_ranges(dst + L.V, lg + L.V, P, h.rho, h.p);
+  stage_ranges(dst + L.gs, lg + L.gs, L.step, h.rr, 2 + C + h.p);
+}
+
+// Replay a relation log on the offset column o (LDS, p entries).  Returns the
+// rows eliminated (rho) and kept (rr); the new offsets are o[rho .. rho+rr).
+// o lives in LDS and the log is read only, so LDS-only barriers order every
+// exchange.
+__device__ inline void rel_replay(double* o, const double* lg, const RelLog& L, int P, int R, int C, bool scaled,
+                                  int* rho_out, int* rr_out) {
+  const RelHdr h = rel_header(lg, P, R, C);
+  const int p = h.p, rho = h.rho, rr = h.rr;
   if (scaled) {
     for (int r = ECLQR_TID; r < p; r += ECLQR_NT) o[r] *= lg[L.scale + r];
-    wg_sync();
+    lds_sync();
   }
   for (int j = 0; j < rho; ++j) {
     const double* v = lg + L.V + (int64_t)j * P;
     double part = 0.0;
     for (int row = j + 1 + ECLQR_TID; row < p; row += ECLQR_NT) part = fma(v[row], o[row], part);
     const double w = (o[j] + wave_sum(part)) * lg[L.tau + j];
-    wg_sync();
+    lds_sync();
     if (ECLQR_TID == 0) o[j] -= w;
     for (int row = j + 1 + ECLQR_TID; row < p; row += ECLQR_NT) o[row] = fma(-w, v[row], o[row]);
-    wg_sync();
+    lds_sync();
   }
   for (int sel = 0; sel < rr; ++sel) {
     const double* rec = lg + L.gs + (int64_t)sel * L.step;
@@ -94,15 +99,15 @@ __device__ inline void rel_replay(double* o, const double* lg, const RelLog& L, 
         o[base] = o[best];
         o[best] = a;
       }
-      wg_sync();
+      lds_sync();
     }
     double part = 0.0;
     for (int l = ECLQR_TID; l < sel; l += ECLQR_NT) part = fma(rec[2 + l], o[rho + l], part);
     const double nbv = (o[base] - wave_sum(part)) * rec[1];
-    wg_sync();
+    lds_sync();
     if (ECLQR_TID == 0) o[base] = nbv;
     for (int row = base + 1 + ECLQR_TID; row < p; row += ECLQR_NT) o[row] = fma(-rec[2 + C + row], nbv, o[row]);
-    wg_sync();
+    lds_sync();
   }
   *rho_out = rho;
   *rr_out = rr;
@@ -114,13 +119,11 @@ __device__ inline void rel_replay(double* o, const double* lg, const RelLog& L, 
 __device__ inline void rel_replay_reg(double* o, const double* lg, const RelLog& L, int P, int R, int C, int* rho_out,
                                       int* rr_out) {
   const int lane = ECLQR_TID;
-  int p = (int)lg[0], rho = (int)lg[1], rr = (int)lg[2];
-  p = (p < 0) ? 0 : ((p > P) ? P : p);
-  rho = (rho < 0) ? 0 : ((rho > R) ? R : rho);
-  rho = (rho > p) ? p : rho;
+  const RelHdr h = rel_header(lg, P, R, C);
+  const int p = h.p, rho = h.rho;
   int q = p - rho;
   q = (q > 64) ? 64 : q;
-  rr = (rr < 0) ? 0 : ((rr > C) ? C : rr);
+  int rr = h.rr;
   rr = (rr > q) ? q : rr;
   rr = (rr > 64) ? 64 : rr;
   for (int j = 0; j < rho; ++j) {
@@ -128,10 +131,10 @@ __device__ inline void rel_replay_reg(double* o, const double* lg, const RelLog&
     double part = 0.0;
     for (int row = j + 1 + lane; row < p; row += ECLQR_NT) part = fma(v[row], o[row], part);
     const double w = (o[j] + wave_sum(part)) * lg[L.tau + j];
-    wg_sync();
+    lds_sync();
     if (lane == 0) o[j] -= w;
     for (int row = j + 1 + lane; row < p; row += ECLQR_NT) o[row] = fma(-w, v[row], o[row]);
-    wg_sync();
+    lds_sync();
   }
   double v = (lane < q) ? o[rho + lane] : 0.0;
   bool chosen = lane >= q;
@@ -140,16 +143,16 @@ __device__ inline void rel_replay_reg(double* o, const double* lg, const RelLog&
     const double* rec = lg + L.gs + (int64_t)sel * L.step;
     int piv = (int)rec[0];
     piv = (piv < 0 || piv >= q) ? 0 : piv;
-    const double vp = __shfl(v, piv, 64);
+    const double vp = wave_bcast(v, piv);
     const double part = (lane < sel) ? rec[2 + lane] * qoff : 0.0;
     const double nv = (vp - wave_sum(part)) * rec[1];
     if (lane == sel) qoff = nv;
     if (lane == piv) chosen = true;
     if (!chosen) v = fma(-rec[2 + C + lane], nv, v);
   }
-  wg_sync();
+  lds_sync();
   if (lane < rr) o[rho + lane] = qoff;
-  wg_sync();
+  lds_sync();
   *rho_out = rho;
   *rr_out = rr;
 }
@@ -157,8 +160,11 @@ __device__ inline void rel_replay_reg(double* o, const double* lg, const RelLog&
 }  // namespace
 
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) k_base_relation_vec(DevEngine e, Inputs in) {
+// Logs of at most logcap doubles are staged in LDS before the replay.
+__global__ void __launch_bounds__(kBlock) k_base_relation_vec(DevEngine e, Inputs in, int64_t logcap) {
+  if (none_live(e)) return;
   __shared__ double o[kMaxRows];
+  extern __shared__ double lgs[];
   for (int64_t s = blockIdx.x; s < e.S; s += gridDim.x) {
     const StageInfo st = e.st[s];
     if (gated(e, st.inst)) continue;
@@ -170,24 +176,30 @@ __global__ void __launch_bounds__(kBlock) k_base_relation_vec(DevEngine e, Input
     const int R = st.terminal ? 0 : ((m < P) ? m : P);
     const RelLog L = rel_log_layout(P, R, cap);
     const double* lg = e.rel_log + e.rel_log_off[slot];
+    if (L.size <= logcap) {
+      stage_rel_log(lgs, lg, L, P, cap, rel_header(lg, P, R, cap), true);
+      lg = lgs;
+    }
     if (st.terminal) {
       for (int r = ECLQR_TID; r < k; r += ECLQR_NT) o[r] = g[r];
     } else {
       const double* cv = in.f[IN_c] + st.in[IN_c];
       for (int r = ECLQR_TID; r < P; r += ECLQR_NT) o[r] = (r < np) ? cv[r] : g[r - np];
     }
-    wg_sync();
+    lds_sync();
     int rho = 0, rr = 0;
     rel_replay(o, lg, L, P, R, cap, true, &rho, &rr);
     const int lo = st.terminal ? n + 1 : n + np + 1;
     double* out = slot_ptr(e, SCAN_REL, slot);
     for (int r = ECLQR_TID; r < rr; r += ECLQR_NT) out[r * lo + lo - 1] = o[rho + r];
-    wg_sync();
+    lds_sync();
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_rel_compose_vec(DevEngine e, int64_t first, int64_t ntasks) {
+__global__ void __launch_bounds__(kBlock) k_rel_compose_vec(DevEngine e, int64_t first, int64_t ntasks, int64_t logcap) {
+  if (none_live(e)) return;
   __shared__ double o[kMaxRows];
+  extern __shared__ double lgs[];
   for (int64_t ti = blockIdx.x; ti < ntasks; ti += gridDim.x) {
     const int a = e.tasks[3 * (first + ti)];
     const int bsl = e.tasks[3 * (first + ti) + 1];
@@ -217,22 +229,29 @@ __global__ void __launch_bounds__(kBlock) k_rel_compose_vec(DevEngine e, int64_t
       wg_sync();
       continue;
     }
+    const bool regfmt = lg[3] == 2.0;
+    const int R = (nb < P) ? nb : P;
+    if (L.size <= logcap) {
+      stage_rel_log(lgs, lg, L, P, cap, rel_header(lg, P, R, cap), false);
+      lg = lgs;
+    }
     for (int r = ECLQR_TID; r < ra + rb; r += ECLQR_NT)
       o[r] = (r < ra) ? Ls[r * lda + na + nb] : Rs[(r - ra) * ldb + nb + nc];
-    wg_sync();
+    lds_sync();
     int rho = 0, rr = 0;
-    if (lg[3] == 2.0) rel_replay_reg(o, lg, L, P, (nb < P) ? nb : P, cap, &rho, &rr);
-    else rel_replay(o, lg, L, P, (nb < P) ? nb : P, cap, false, &rho, &rr);
+    if (regfmt) rel_replay_reg(o, lg, L, P, R, cap, &rho, &rr);
+    else rel_replay(o, lg, L, P, R, cap, false, &rho, &rr);
     if (rr > e.slot_rows[oo]) rr = e.slot_rows[oo];
     const int lo = na + nc + 1;
     double* out = slot_ptr(e, SCAN_REL, oo);
     for (int r = ECLQR_TID; r < rr; r += ECLQR_NT) out[r * lo + lo - 1] = o[rho + r];
-    wg_sync();
+    lds_sync();
   }
 }
 
 // t = -H' h; on stage 0, z_0 = T'(x0 - t).
 __global__ void __launch_bounds__(kBlock) k_domain_vec(DevEngine e, Inputs in) {
+  if (none_live(e)) return;
   for (int64_t s = blockIdx.x; s < e.S; s += gridDim.x) {
     const StageInfo st = e.st[s];
     if (gated(e, st.inst)) continue;
@@ -245,7 +264,7 @@ __global__ void __launch_bounds__(kBlock) k_domain_vec(DevEngine e, Inputs in) {
     double* tv = base + ar.t;
     for (int i = ECLQR_TID; i < n; i += ECLQR_NT) {
       double v = 0.0;
-      for (int j = 0; j < r; ++j) v = fma(H[j * (n + 1) + i], H[j * (n + 1) + n], v);
+      v = lane_chain<false>(v, H + i, (n + 1), H + n, (n + 1), r);
       tv[i] = -v;
     }
     wg_sync();
@@ -266,6 +285,7 @@ __global__ void __launch_bounds__(kBlock) k_domain_vec(DevEngine e, Inputs in) {
 
 // Vector part of the stage elimination and of the value-function element.
 __global__ void __launch_bounds__(kBlock) k_eliminate_vec(DevEngine e, Inputs in) {
+  if (none_live(e)) return;
   __shared__ double tvs[kMaxDim], gam[2 * kMaxDim], yv[kMaxDim], atc[kMaxDim], cvv[kMaxDim], wv[kMaxDim],
       qt[kMaxDim], rz[kMaxDim], sv[kMaxDim];
   for (int64_t s = blockIdx.x; s < e.S; s += gridDim.x) {
@@ -284,7 +304,7 @@ __global__ void __launch_bounds__(kBlock) k_eliminate_vec(DevEngine e, Inputs in
     // Q t + q
     for (int i = ECLQR_TID; i < n; i += ECLQR_NT) {
       double a = qv[i];
-      for (int j = 0; j < n; ++j) a = fma(Q[i * n + j], tvs[j], a);
+      a = lane_chain<false>(a, Q + i * n, 1, tvs, 1, n);
       qt[i] = a;
     }
     wg_sync();
@@ -295,7 +315,7 @@ __global__ void __launch_bounds__(kBlock) k_eliminate_vec(DevEngine e, Inputs in
       double* qb = base + ar.qb;
       for (int i = ECLQR_TID; i < nb; i += ECLQR_NT) {
         double a = 0.0;
-        for (int l = 0; l < n; ++l) a = fma(T[l * nb + i], qt[l], a);
+        a = lane_chain<false>(a, T + i, nb, qt, 1, n);
         qb[i] = a;
         ric[rl.eta + i] = -a;
       }
@@ -327,7 +347,7 @@ __global__ void __launch_bounds__(kBlock) k_eliminate_vec(DevEngine e, Inputs in
     // gamma = rows-scaled [E t + g; H'(A t + c) + h']
     for (int i = ECLQR_TID; i < np; i += ECLQR_NT) {
       double a = cv[i];
-      for (int j = 0; j < n; ++j) a = fma(A[i * n + j], tvs[j], a);
+      a = lane_chain<false>(a, A + i * n, 1, tvs, 1, n);
       atc[i] = a;
     }
     wg_sync();
@@ -335,11 +355,11 @@ __global__ void __launch_bounds__(kBlock) k_eliminate_vec(DevEngine e, Inputs in
       double a;
       if (j < k) {
         a = g[j];
-        for (int l = 0; l < n; ++l) a = fma(E[j * n + l], tvs[l], a);
+        a = lane_chain<false>(a, E + j * n, 1, tvs, 1, n);
       } else {
         const int jj = j - k;
         a = H1[jj * ldh + np];
-        for (int l = 0; l < np; ++l) a = fma(H1[jj * ldh + l], atc[l], a);
+        a = lane_chain<false>(a, H1 + jj * ldh, 1, atc, 1, np);
       }
       gam[j] = a * base[ar.rsc + j];
     }
@@ -357,7 +377,7 @@ __global__ void __launch_bounds__(kBlock) k_eliminate_vec(DevEngine e, Inputs in
     double* y = base + ar.y;
     for (int i = ECLQR_TID; i < m; i += ECLQR_NT) {
       double a = 0.0;
-      for (int j = 0; j < rho; ++j) a = fma(base[ar.Q1 + i * rho + j], sv[j], a);
+      a = lane_chain<false>(a, base + ar.Q1 + i * rho, 1, sv, 1, rho);
       y[i] = -a;
       yv[i] = -a;
     }
@@ -365,22 +385,22 @@ __global__ void __launch_bounds__(kBlock) k_eliminate_vec(DevEngine e, Inputs in
     // c-bar = T1'(A t + B y + c - t1)
     for (int i = ECLQR_TID; i < np; i += ECLQR_NT) {
       double a = atc[i] - t1[i];
-      for (int j = 0; j < m; ++j) a = fma(B[i * m + j], yv[j], a);
+      a = lane_chain<false>(a, B + i * m, 1, yv, 1, m);
       cvv[i] = a;
     }
     // rz = r + M' t ; w = rz + R y
     for (int i = ECLQR_TID; i < m; i += ECLQR_NT) {
       double a = rv[i];
       if (Mm)
-        for (int j = 0; j < n; ++j) a = fma(Mm[j * m + i], tvs[j], a);
+        a = lane_chain<false>(a, Mm + i, m, tvs, 1, n);
       rz[i] = a;
       double b = a;
-      for (int j = 0; j < m; ++j) b = fma(R[i * m + j], yv[j], b);
+      b = lane_chain<false>(b, R + i * m, 1, yv, 1, m);
       wv[i] = b;
     }
     for (int i = ECLQR_TID; i < m; i += ECLQR_NT) {
       double a = 0.0;
-      for (int j = 0; j < m; ++j) a = fma(R[i * m + j], yv[j], a);
+      a = lane_chain<false>(a, R + i * m, 1, yv, 1, m);
       kap += yv[i] * (0.5 * a + rz[i]);
     }
     kap = wave_sum(kap);
@@ -389,7 +409,7 @@ __global__ void __launch_bounds__(kBlock) k_eliminate_vec(DevEngine e, Inputs in
       wg_sync();
       for (int i = ECLQR_TID; i < n; i += ECLQR_NT) {
         double a = qt[i];
-        for (int j = 0; j < m; ++j) a = fma(Mm[i * m + j], yv[j], a);
+        a = lane_chain<false>(a, Mm + i * m, 1, yv, 1, m);
         qt[i] = a;
       }
     }
@@ -401,18 +421,18 @@ __global__ void __launch_bounds__(kBlock) k_eliminate_vec(DevEngine e, Inputs in
     const double* Z = base + ar.Z;
     for (int i = ECLQR_TID; i < nb1; i += ECLQR_NT) {
       double a = 0.0;
-      for (int l = 0; l < np; ++l) a = fma(T1[l * nb1 + i], cvv[l], a);
+      a = lane_chain<false>(a, T1 + i, nb1, cvv, 1, np);
       cb[i] = a;
     }
     for (int i = ECLQR_TID; i < nb; i += ECLQR_NT) {
       double a = 0.0;
-      for (int l = 0; l < n; ++l) a = fma(T[l * nb + i], qt[l], a);
-      for (int j = 0; j < m; ++j) a = fma(Y[j * nb + i], wv[j], a);
+      a = lane_chain<false>(a, T + i, nb, qt, 1, n);
+      a = lane_chain<false>(a, Y + i, nb, wv, 1, m);
       qb[i] = a;
     }
     double rbl = 0.0;
     if (ECLQR_TID < mb) {
-      for (int j = 0; j < m; ++j) rbl = fma(Z[j * mb + ECLQR_TID], wv[j], rbl);
+      rbl = lane_chain<false>(rbl, Z + ECLQR_TID, mb, wv, 1, m);
       rb[ECLQR_TID] = rbl;
     }
     if (ECLQR_TID == 0) base[ar.kap] = kap;
@@ -426,12 +446,12 @@ __global__ void __launch_bounds__(kBlock) k_eliminate_vec(DevEngine e, Inputs in
     const double* Mb = base + ar.Mb;
     for (int i = ECLQR_TID; i < nb1; i += ECLQR_NT) {
       double a = cb[i];
-      for (int j = 0; j < mb; ++j) a = fma(-Bb[i * mb + j], sv[j], a);
+      a = lane_chain<true>(a, Bb + i * mb, 1, sv, 1, mb);
       ric[rl.b + i] = a;
     }
     for (int i = ECLQR_TID; i < nb; i += ECLQR_NT) {
       double a = qb[i];
-      for (int j = 0; j < mb; ++j) a = fma(-Mb[i * mb + j], sv[j], a);
+      a = lane_chain<true>(a, Mb + i * mb, 1, sv, 1, mb);
       ric[rl.eta + i] = -a;
     }
     wg_sync();
@@ -439,9 +459,13 @@ __global__ void __launch_bounds__(kBlock) k_eliminate_vec(DevEngine e, Inputs in
 }
 
 // b, eta of a value-function combine from its logged factors.
-__global__ void __launch_bounds__(kBlock) k_ric_combine_vec(DevEngine e, int64_t first, int64_t ntasks) {
+// LDS (maxd): [log: 4 + 2 maxd^2 + maxd | A1: maxd^2 | A2: maxd^2]; the
+// factored form reads its factors and both A blocks from there.
+__global__ void __launch_bounds__(kBlock) k_ric_combine_vec(DevEngine e, int64_t first, int64_t ntasks, int maxd) {
+  if (none_live(e)) return;
   __shared__ double v1[kMaxDim], v2[kMaxDim], v3[kMaxDim];
   __shared__ int piv[kMaxDim];
+  extern __shared__ double rs[];
   for (int64_t ti = blockIdx.x; ti < ntasks; ti += gridDim.x) {
     const int a = e.tasks[3 * (first + ti)];
     const int bsl = e.tasks[3 * (first + ti) + 1];
@@ -459,6 +483,18 @@ __global__ void __launch_bounds__(kBlock) k_ric_combine_vec(DevEngine e, int64_t
     const double* rlog = e.ric_log + e.ric_log_off[o];
     const bool binary = se >= 0;
     const bool factored = (dm > 0) && (rlog[0] == 1.0);
+    if (factored && dm <= maxd && ds <= maxd && de <= maxd) {
+      const int64_t lsz = 4 + 2 * (int64_t)maxd * maxd + maxd;
+      double* A1s = rs + lsz;
+      double* A2s = A1s + (int64_t)maxd * maxd;
+      stage_ranges(rs, rlog, 0, 1, 4 + 2 * dm * dm);
+      stage_ranges(A1s, A1, 0, 1, dm * ds);
+      if (binary) stage_ranges(A2s, A2, 0, 1, de * dm);
+      lds_sync();
+      rlog = rs;
+      A1 = A1s;
+      A2 = A2s;
+    }
     if (factored) {
       const double* Lj = rlog + 4;
       const double* Rg = rlog + 4 + (int64_t)dm * dm;
@@ -471,29 +507,29 @@ __global__ void __launch_bounds__(kBlock) k_ric_combine_vec(DevEngine e, int64_t
       tvv = lane_trsv_lower(Rg, dm, tvv, dm);
       tvv = lane_trsv_lower_t(Rg, dm, tvv, dm);
       if (ECLQR_TID < dm) v1[ECLQR_TID] = tvv;
-      wg_sync();
+      lds_sync();
       if (ECLQR_TID < dm) {
         double w = 0.0;
         for (int l = 0; l <= ECLQR_TID; ++l) w = fma(Lj[ECLQR_TID * dm + l], v1[l], w);
         v2[ECLQR_TID] = w;
       }
-      wg_sync();
+      lds_sync();
       for (int i = ECLQR_TID; i < ds; i += ECLQR_NT) {
         double v = et1[i];
-        for (int l = 0; l < dm; ++l) v = fma(A1[l * ds + i], v2[l], v);
+        v = lane_chain<false>(v, A1 + i, ds, v2, 1, dm);
         Eo[lo.eta + i] = v;
       }
       if (binary) {
         double yl = lane_trsv_lower_t(Lj, dm, xi - tvv, dm);
         if (ECLQR_TID < dm) v3[ECLQR_TID] = yl;
-        wg_sync();
+        lds_sync();
         for (int i = ECLQR_TID; i < de; i += ECLQR_NT) {
           double v = b2[i];
-          for (int l = 0; l < dm; ++l) v = fma(A2[i * dm + l], v3[l], v);
+          v = lane_chain<false>(v, A2 + i * dm, 1, v3, 1, dm);
           Eo[lo.b + i] = v;
         }
       }
-      wg_sync();
+      lds_sync();
       continue;
     }
     // LU form: eta = A1' Minv'(eta2 - J2 b1) + eta1 ; b = A2 Minv (b1 + C1 eta2) + b2
@@ -501,35 +537,36 @@ __global__ void __launch_bounds__(kBlock) k_ric_combine_vec(DevEngine e, int64_t
     for (int i = ECLQR_TID; i < dm; i += ECLQR_NT) {
       piv[i] = (int)rlog[4 + 2 * (int64_t)dm * dm + i];
       double v = et2[i];
-      for (int l = 0; l < dm; ++l) v = fma(-J2[i * dm + l], b1[l], v);
+      v = lane_chain<true>(v, J2 + i * dm, 1, b1, 1, dm);
       v1[i] = v;
       double w = b1[i];
-      for (int l = 0; l < dm; ++l) w = fma(C1[i * dm + l], et2[l], w);
+      w = lane_chain<false>(w, C1 + i * dm, 1, et2, 1, dm);
       v3[i] = w;
     }
-    wg_sync();
+    lds_sync();
     for (int i = ECLQR_TID; i < dm; i += ECLQR_NT) piv[i] = (piv[i] < i || piv[i] >= dm) ? i : piv[i];
-    wg_sync();
+    lds_sync();
     wg_lu_solve_t(LU, dm, dm, piv, v1, 1, 1);
     for (int i = ECLQR_TID; i < ds; i += ECLQR_NT) {
       double v = et1[i];
-      for (int l = 0; l < dm; ++l) v = fma(A1[l * ds + i], v1[l], v);
+      v = lane_chain<false>(v, A1 + i, ds, v1, 1, dm);
       Eo[lo.eta + i] = v;
     }
     if (binary) {
       wg_lu_solve(LU, dm, dm, piv, v3, 1, 1);
       for (int i = ECLQR_TID; i < de; i += ECLQR_NT) {
         double v = b2[i];
-        for (int l = 0; l < dm; ++l) v = fma(A2[i * dm + l], v3[l], v);
+        v = lane_chain<false>(v, A2 + i * dm, 1, v3, 1, dm);
         Eo[lo.b + i] = v;
       }
     }
-    wg_sync();
+    lds_sync();
   }
 }
 
 // k = -H_uu^{-1} h_u from the logged Cholesky factor; forward leaf vector.
 __global__ void __launch_bounds__(kBlock) k_gains_vec(DevEngine e) {
+  if (none_live(e)) return;
   __shared__ double pc[kMaxDim], kv[kMaxDim];
   for (int64_t s = blockIdx.x; s < e.S; s += gridDim.x) {
     const StageInfo st = e.st[s];
@@ -545,14 +582,14 @@ __global__ void __launch_bounds__(kBlock) k_gains_vec(DevEngine e) {
     const double *Bb = base + ar.Bb, *cb = base + ar.cb, *rb = base + ar.rb;
     for (int i = ECLQR_TID; i < nb1; i += ECLQR_NT) {
       double v = -et1[i];
-      for (int l = 0; l < nb1; ++l) v = fma(P1[i * nb1 + l], cb[l], v);
+      v = lane_chain<false>(v, P1 + i * nb1, 1, cb, 1, nb1);
       pc[i] = v;
     }
-    wg_sync();
+    lds_sync();
     double hu = 0.0;
     if (ECLQR_TID < mb) {
       hu = rb[ECLQR_TID];
-      for (int l = 0; l < nb1; ++l) hu = fma(Bb[l * mb + ECLQR_TID], pc[l], hu);
+      hu = lane_chain<false>(hu, Bb + ECLQR_TID, mb, pc, 1, nb1);
     }
     hu = lane_trsv_lower(base + ar.Hc, mb, hu, mb);
     hu = lane_trsv_lower_t(base + ar.Hc, mb, hu, mb);
@@ -560,19 +597,20 @@ __global__ void __launch_bounds__(kBlock) k_gains_vec(DevEngine e) {
       kv[ECLQR_TID] = -hu;
       base[ar.kk + ECLQR_TID] = -hu;
     }
-    wg_sync();
+    lds_sync();
     double* fs = slot_ptr(e, SCAN_FWD, st.elem[SCAN_FWD]) + (int64_t)np * n;
     for (int i = ECLQR_TID; i < nb1; i += ECLQR_NT) {
       double v = cb[i];
-      for (int l = 0; l < mb; ++l) v = fma(Bb[i * mb + l], kv[l], v);
+      v = lane_chain<false>(v, Bb + i * mb, 1, kv, 1, mb);
       fs[i] = v;
     }
-    wg_sync();
+    lds_sync();
   }
 }
 
 // f = F1 f2 + f1 (F = F1 F2 is unchanged).
 __global__ void __launch_bounds__(kBlock) k_fwd_combine_vec(DevEngine e, int64_t first, int64_t ntasks) {
+  if (none_live(e)) return;
   for (int64_t ti = blockIdx.x; ti < ntasks; ti += gridDim.x) {
     const int a = e.tasks[3 * (first + ti)];
     const int bsl = e.tasks[3 * (first + ti) + 1];
@@ -589,7 +627,7 @@ __global__ void __launch_bounds__(kBlock) k_fwd_combine_vec(DevEngine e, int64_t
     double* fo = Fo + (int64_t)nout * nin;
     for (int i = ECLQR_TID; i < dout; i += ECLQR_NT) {
       double v = f1[i];
-      for (int l = 0; l < dmid; ++l) v = fma(F1[i * dmid + l], f2[l], v);
+      v = lane_chain<false>(v, F1 + i * dmid, 1, f2, 1, dmid);
       fo[i] = v;
     }
   }
@@ -600,11 +638,37 @@ static unsigned grid_of(const DevEngine& e, int64_t ntasks) {
   return (unsigned)((ntasks < e.nblocks) ? ntasks : e.nblocks);
 }
 
-void launch_base_relation_vec(const DevEngine& e, const Inputs& in, hipStream_t s) {
-  hipLaunchKernelGGL(k_base_relation_vec, dim3(e.nblocks), dim3(kBlock), 0, s, e, in);
+// Largest dynamic LDS (bytes) of each replay kernel: the device limit less the
+// kernel's static LDS (the attribute cannot exceed that difference).
+static int g_dyn_base = 65536 - 4096, g_dyn_compose = 65536 - 4096, g_dyn_ric = 65536 - 4096;
+static int set_dyn_limit(const void* fn, int device_bytes) {
+  hipFuncAttributes a{};
+  int stat = 4096;
+  if (hipFuncGetAttributes(&a, fn) == hipSuccess) stat = (int)a.sharedSizeBytes;
+  const int dyn = device_bytes - stat;
+  if (dyn > 0 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, dyn) == hipSuccess) return dyn;
+  (void)hipGetLastError();
+  return 65536 - stat > 0 ? 65536 - stat : 0;
 }
-void launch_rel_compose_vec(const DevEngine& e, int64_t first, int64_t ntasks, hipStream_t s) {
-  if (ntasks > 0) hipLaunchKernelGGL(k_rel_compose_vec, dim3(grid_of(e, ntasks)), dim3(kBlock), 0, s, e, first, ntasks);
+void replay_set_max_lds(int bytes) {
+  g_dyn_base = set_dyn_limit(reinterpret_cast<const void*>(k_base_relation_vec), bytes);
+  g_dyn_compose = set_dyn_limit(reinterpret_cast<const void*>(k_rel_compose_vec), bytes);
+  g_dyn_ric = set_dyn_limit(reinterpret_cast<const void*>(k_ric_combine_vec), bytes);
+}
+// doubles of dynamic LDS for a staged relation log, at most the kernel's limit
+static int64_t rel_logcap(int64_t want, int dyn_bytes) {
+  const int64_t room = (int64_t)dyn_bytes / (int64_t)sizeof(double);
+  return want < room ? want : (room > 0 ? room : 0);
+}
+void launch_base_relation_vec(const DevEngine& e, const Inputs& in, int64_t logmax, hipStream_t s) {
+  const int64_t cap = rel_logcap(logmax, g_dyn_base);
+  hipLaunchKernelGGL(k_base_relation_vec, dim3(e.nblocks), dim3(kBlock), sizeof(double) * cap, s, e, in, cap);
+}
+void launch_rel_compose_vec(const DevEngine& e, int64_t first, int64_t ntasks, int64_t logmax, hipStream_t s) {
+  const int64_t cap = rel_logcap(logmax, g_dyn_compose);
+  if (ntasks > 0)
+    hipLaunchKernelGGL(k_rel_compose_vec, dim3(grid_of(e, ntasks)), dim3(kBlock), sizeof(double) * cap, s, e, first,
+                       ntasks, cap);
 }
 void launch_domain_vec(const DevEngine& e, const Inputs& in, hipStream_t s) {
   hipLaunchKernelGGL(k_domain_vec, dim3(e.nblocks), dim3(kBlock), 0, s, e, in);
@@ -612,8 +676,13 @@ void launch_domain_vec(const DevEngine& e, const Inputs& in, hipStream_t s) {
 void launch_eliminate_vec(const DevEngine& e, const Inputs& in, hipStream_t s) {
   hipLaunchKernelGGL(k_eliminate_vec, dim3(e.nblocks), dim3(kBlock), 0, s, e, in);
 }
-void launch_ric_combine_vec(const DevEngine& e, int64_t first, int64_t ntasks, hipStream_t s) {
-  if (ntasks > 0) hipLaunchKernelGGL(k_ric_combine_vec, dim3(grid_of(e, ntasks)), dim3(kBlock), 0, s, e, first, ntasks);
+void launch_ric_combine_vec(const DevEngine& e, int64_t first, int64_t ntasks, int maxd, hipStream_t s) {
+  // staged factors need (4 + 2 d^2 + d) + 2 d^2 doubles; larger levels read them in place
+  int d = maxd;
+  while (d > 0 && (int64_t)sizeof(double) * (4 + 4 * (int64_t)d * d + d) > (int64_t)g_dyn_ric) --d;
+  const size_t lds = d > 0 ? sizeof(double) * (4 + 4 * (size_t)d * d + d) : 0;
+  if (ntasks > 0)
+    hipLaunchKernelGGL(k_ric_combine_vec, dim3(grid_of(e, ntasks)), dim3(kBlock), lds, s, e, first, ntasks, d);
 }
 void launch_gains_vec(const DevEngine& e, hipStream_t s) {
   hipLaunchKernelGGL(k_gains_vec, dim3(e.nblocks), dim3(kBlock), 0, s, e);

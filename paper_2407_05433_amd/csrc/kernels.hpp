@@ -27,13 +27,14 @@ struct DevEngine {
   double* rel_log;            // factor logs of the relation scan
   double* ric_log;            // factor logs of the value-function scan
   const int32_t* gate;        // per-instance refinement state, null = every instance runs
+  const int32_t* live;        // instances still refining; 0 makes the kernels of a refinement step return at once
   double* scratch;            // per-workgroup global scratch
   int64_t scratch_per_block;  // doubles
   int64_t S;
   int32_t B;
   int32_t nslots;
   int32_t nblocks;            // grid size of the stage-parallel kernels (grid-stride)
-  int32_t pool_lds;           // 1: value-function combines keep their pool in LDS when it fits
+  int32_t pool_lds;           // value-function combine LDS mode (0 global pool, 1 LDS pool, 2 all in LDS)
   int32_t reg_compose;        // 1: relation compositions that fit run register-resident
 };
 
@@ -53,6 +54,7 @@ void launch_validate(const DevEngine& e, const Inputs& in, int32_t* status, hipS
 void relations_set_max_lds(int bytes);
 void eliminate_set_max_lds(int bytes);
 void lqr_set_max_lds(int bytes);
+void replay_set_max_lds(int bytes);
 size_t rel_lds_bytes(int maxp, int ldw);
 size_t domain_lds_bytes(int maxn);
 size_t elim_lds_bytes(int maxm, int maxq);
@@ -73,11 +75,11 @@ void launch_fwd_combine(const DevEngine& e, int64_t first_task, int64_t ntasks, 
 void launch_recover(const DevEngine& e, double* x, double* u, hipStream_t s);
 
 // vector-only replays of the kernels above (factors logged by the full pass)
-void launch_base_relation_vec(const DevEngine& e, const Inputs& in, hipStream_t s);
-void launch_rel_compose_vec(const DevEngine& e, int64_t first, int64_t ntasks, hipStream_t s);
+void launch_base_relation_vec(const DevEngine& e, const Inputs& in, int64_t logmax, hipStream_t s);
+void launch_rel_compose_vec(const DevEngine& e, int64_t first, int64_t ntasks, int64_t logmax, hipStream_t s);
 void launch_domain_vec(const DevEngine& e, const Inputs& in, hipStream_t s);
 void launch_eliminate_vec(const DevEngine& e, const Inputs& in, hipStream_t s);
-void launch_ric_combine_vec(const DevEngine& e, int64_t first, int64_t ntasks, hipStream_t s);
+void launch_ric_combine_vec(const DevEngine& e, int64_t first, int64_t ntasks, int maxd, hipStream_t s);
 void launch_gains_vec(const DevEngine& e, hipStream_t s);
 void launch_fwd_combine_vec(const DevEngine& e, int64_t first, int64_t ntasks, hipStream_t s);
 
@@ -111,7 +113,7 @@ void launch_refine_update(const DevEngine& p, double* x, double* u, const double
                           double* norms, hipStream_t s);
 void launch_refine_decide(const DevEngine& p, const int64_t* sbase, const double* norms, double tol, int last,
                           int32_t* gate, int32_t* steps, hipStream_t s);
-void launch_gate_advance(int32_t* gate, int32_t B, hipStream_t s);
+void launch_gate_advance(int32_t* gate, int32_t* live, int32_t B, hipStream_t s);
 // per-instance componentwise backward error (as the bit pattern of a
 // non-negative double, max-accumulated: clear to 0 first)
 void launch_backward_error(const DevEngine& p, const Inputs& in, const double* x, const double* u, const double* lam,

@@ -228,6 +228,8 @@ std::string Engine::build(const eclqr_dims* d) {
   rel_log_off.assign(nslots, -1);
   ric_log_off.assign(nslots, -1);
   rel_log_total = ric_log_total = 0;
+  base_rel_log = 0;
+  lvl_rel_log.assign(2 * D, 0);
   for (int32_t q = 0; q < nslots; ++q) {
     const int b = slot_inst[q], s = slot_s[q], e = slot_e[q];
     if (e != s + 1) continue;
@@ -236,6 +238,7 @@ std::string Engine::build(const eclqr_dims* d) {
     const int R = x.terminal ? 0 : std::min(x.m, P);
     rel_log_off[q] = rel_log_total;
     rel_log_total += rel_log_layout(P, R, slot_cap[q]).size;
+    base_rel_log = std::max(base_rel_log, rel_log_layout(P, R, slot_cap[q]).size);
   }
   for (size_t t = 0; t < tasks.size() / 3; ++t) {
     const int a = tasks[3 * t], c = tasks[3 * t + 1], o = tasks[3 * t + 2];
@@ -244,6 +247,9 @@ std::string Engine::build(const eclqr_dims* d) {
     const int P = slot_cap[a] + slot_cap[c];
     rel_log_off[o] = rel_log_total;
     rel_log_total += rel_log_layout(P, std::min(nmid, P), slot_cap[o]).size;
+    for (int l = 0; l < 2 * D; ++l)
+      if ((int64_t)t >= lvl_begin[l] && (int64_t)t < lvl_begin[l] + lvl_count[l])
+        lvl_rel_log[l] = std::max(lvl_rel_log[l], rel_log_layout(P, std::min(nmid, P), slot_cap[o]).size);
     ric_log_off[o] = ric_log_total;
     ric_log_total += ric_log_size(nmid);
   }
@@ -426,6 +432,7 @@ std::string build_plan(Plan& p, const eclqr_dims* d, const eclqr_options* opt) {
   p.o_gate = o; o = align256(o + sizeof(int32_t) * std::max<int32_t>(1, P.B));
   p.o_rnorm = o; o = align256(o + sizeof(double) * 2 * std::max<int64_t>(1, P.S));
   p.o_rsteps = o; o = align256(o + sizeof(int32_t) * std::max<int32_t>(1, P.B));
+  p.o_live = o; o = align256(o + sizeof(int32_t));
   p.o_omega = o; o = align256(o + sizeof(double) * std::max<int32_t>(1, P.B));
   {
     const int64_t nz = std::max<int64_t>(1, std::max(P.total[ECLQR_F_c], std::max(P.total[ECLQR_F_g], P.total[ECLQR_F_x0])));

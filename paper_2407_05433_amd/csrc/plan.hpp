@@ -51,6 +51,8 @@ struct Engine {
   // factor logs replayed by the vector-only pass, per output slot
   std::vector<int64_t> rel_log_off, ric_log_off;
   int64_t rel_log_total = 0, ric_log_total = 0;
+  std::vector<int64_t> lvl_rel_log;  // largest relation log (doubles) of each level's outputs
+  int64_t base_rel_log = 0;          // largest relation log of the leaves
 
   int64_t arena_total = 0;  // stage arena doubles
   int32_t maxn = 0, maxm = 0, maxk = 0;
@@ -80,6 +82,7 @@ struct Plan {
   size_t o_gate = 0;   // per-instance refinement state (kGate*)
   size_t o_rnorm = 0;  // per-stage squared norms of correction and iterate
   size_t o_rsteps = 0; // per-instance count of refinement steps taken
+  size_t o_live = 0;   // instances still refining (one int)
   size_t o_omega = 0;  // per-instance backward error after the first solve (double bits)
   size_t bytes = 0;
   void* bound_ws = nullptr;
@@ -88,7 +91,7 @@ struct Plan {
   // pointers it was captured with
   // tuning (eclqr_plan_autotune / eclqr_plan_set_tuning)
   int32_t level_buckets = 1;  // relation levels launch in LDS-size buckets
-  int32_t pool_lds = 1;       // value-function combine pool in LDS when it fits
+  int32_t pool_lds = 2;       // value-function combine LDS mode (0 global pool, 1 LDS pool, 2 all in LDS)
   int32_t grid_divisor = 1;   // grid of the stage-parallel kernels = nblocks / divisor
   int32_t reg_compose = 1;    // register-resident relation compositions where they fit
   double tuned_ms = 0.0;

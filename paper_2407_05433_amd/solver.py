@@ -139,6 +139,17 @@ class Plan:
               "eclqr_plan_scan_rows")
         return np.frombuffer(rows, dtype=np.int32)[:n.value].copy()
 
+    def combine_forms(self, ws: torch.Tensor, dual: bool = False) -> np.ndarray:
+        """Form of the value-function combine of every scan slot in the last solve:
+        0 none, 1 Cholesky-factored, 2 LU (synchronises)."""
+        n = C.c_int32()
+        check(lib().eclqr_plan_combine_forms(self._h, None, int(dual), None, C.byref(n)), "eclqr_plan_combine_forms")
+        forms = (C.c_int32 * max(1, n.value))()
+        wptr, _ = _aligned_ws(ws)
+        check(lib().eclqr_plan_combine_forms(self._h, C.c_void_p(wptr), int(dual), forms, C.byref(n)),
+              "eclqr_plan_combine_forms")
+        return np.frombuffer(forms, dtype=np.int32)[:n.value].copy()
+
     def slot_info(self, dual: bool = False):
         """(instance, first leaf, end leaf) of every scan slot."""
         n = C.c_int32()
