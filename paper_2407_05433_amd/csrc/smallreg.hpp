@@ -1,9 +1,11 @@
 // Register-resident small dense routines (one wavefront, n <= NMAX <= 64):
-// a row (Cholesky) or a column (triangular solves) of the operand per lane,
-// every loop unrolled to NMAX with the runtime size as a uniform guard.  The
-// arithmetic of each routine is exactly that of its LDS counterpart in
-// dense.hpp (same operations in the same order), so the two give the same
-// bits and either may serve any task.
+// a row (Cholesky, pivoted Cholesky) or a column (triangular solves) of the
+// operand per lane, every loop unrolled to NMAX with the runtime size as a
+// uniform guard.  Loads are unconditional at clamped (in-bounds) indices and
+// issued together, and lane-dependent updates are selects, so no load waits
+// inside a divergent branch.  The arithmetic of each routine is exactly that
+// of its LDS counterpart in dense.hpp (same operations in the same order), so
+// the two give the same bits and either may serve any task.
 #pragma once
 
 #include "dense.hpp"
@@ -17,9 +19,13 @@ template <int NMAX>
 __device__ __forceinline__ int reg_cholesky(double* S, int ld, int n, double floor, double* colbuf) {
   const int lane = ECLQR_TID;
   const bool mine = lane < n;
+  const int rl = mine ? lane : 0;
   double r[NMAX];
 #pragma unroll
-  for (int k = 0; k < NMAX; ++k) r[k] = (mine && k < n) ? S[lane * ld + k] : 0.0;
+  for (int k = 0; k < NMAX; ++k) {
+    const double v = S[rl * ld + (k < n ? k : 0)];
+    r[k] = (mine && k < n) ? v : 0.0;
+  }
   int fail = 0;
 #pragma unroll
   for (int j = 0; j < NMAX; ++j) {
@@ -29,22 +35,22 @@ __device__ __forceinline__ int reg_cholesky(double* S, int ld, int n, double flo
         fail = 1;
       } else {
         const double dj = sqrt(d);
-        if (lane > j) r[j] = r[j] / dj;
-        if (lane == j) r[j] = dj;
-        if (mine) colbuf[lane] = r[j];
+        const double sc = r[j] / dj;
+        r[j] = (lane > j) ? sc : ((lane == j) ? dj : r[j]);
+        colbuf[lane] = r[j];
         lds_sync();
+        double lc[NMAX];
+#pragma unroll
+        for (int c = j + 1; c < NMAX; ++c) lc[c] = colbuf[c];
         const double al = -r[j];
 #pragma unroll
         for (int c = j + 1; c < NMAX; ++c) {
-          if (c < n) {
-            const double lc = colbuf[c];
-            if (lane >= c) r[c] = fma(al, lc, r[c]);
-          }
+          const double nv = fma(al, lc[c], r[c]);
+          r[c] = (c < n && lane >= c) ? nv : r[c];
         }
         lds_sync();
       }
     }
-    __builtin_amdgcn_sched_barrier(0);
   }
   if (!fail && mine) {
 #pragma unroll
@@ -58,23 +64,27 @@ __device__ __forceinline__ int reg_cholesky(double* S, int ld, int n, double flo
 // wg_trsm_lower: L X = B in place on X (n x nc), column per lane.
 template <int NMAX>
 __device__ __forceinline__ void reg_trsm_lower(const double* L, int ld, double* X, int ldx, int n, int nc) {
+  const int lane = ECLQR_TID;
+  const double rdl = 1.0 / L[(lane < n ? lane : 0) * (ld + 1)];  // 1 / L(i,i) in lane i
   for (int c0 = 0; c0 < nc; c0 += ECLQR_NT) {
-    const int col = c0 + ECLQR_TID;
+    const int col = c0 + lane;
     const bool mine = col < nc;
+    const int cl = mine ? col : c0;
     double x[NMAX];
 #pragma unroll
-    for (int k = 0; k < NMAX; ++k) x[k] = (mine && k < n) ? X[k * ldx + col] : 0.0;
-    const double rdl = (ECLQR_TID < n) ? 1.0 / L[ECLQR_TID * ld + ECLQR_TID] : 0.0;  // 1 / L(i,i) in lane i
+    for (int k = 0; k < NMAX; ++k) x[k] = X[(k < n ? k : 0) * ldx + cl];
 #pragma unroll
     for (int i = 0; i < NMAX; ++i) {
       if (i < n) {
         const double rd = wave_bcast(rdl, i);
+        double lr[NMAX];
+#pragma unroll
+        for (int k = 0; k < i; ++k) lr[k] = L[i * ld + k];
         double acc = x[i];
 #pragma unroll
-        for (int k = 0; k < i; ++k) acc = fma(-L[i * ld + k], x[k], acc);
+        for (int k = 0; k < i; ++k) acc = fma(-lr[k], x[k], acc);
         x[i] = acc * rd;
       }
-      __builtin_amdgcn_sched_barrier(0);
     }
     if (mine) {
 #pragma unroll
@@ -88,24 +98,30 @@ __device__ __forceinline__ void reg_trsm_lower(const double* L, int ld, double* 
 // wg_trsm_lower_t: L' X = B in place on X (n x nc), column per lane.
 template <int NMAX>
 __device__ __forceinline__ void reg_trsm_lower_t(const double* L, int ld, double* X, int ldx, int n, int nc) {
+  const int lane = ECLQR_TID;
+  const double rdl = 1.0 / L[(lane < n ? lane : 0) * (ld + 1)];
   for (int c0 = 0; c0 < nc; c0 += ECLQR_NT) {
-    const int col = c0 + ECLQR_TID;
+    const int col = c0 + lane;
     const bool mine = col < nc;
+    const int cl = mine ? col : c0;
     double x[NMAX];
 #pragma unroll
-    for (int k = 0; k < NMAX; ++k) x[k] = (mine && k < n) ? X[k * ldx + col] : 0.0;
-    const double rdl = (ECLQR_TID < n) ? 1.0 / L[ECLQR_TID * ld + ECLQR_TID] : 0.0;  // 1 / L(i,i) in lane i
+    for (int k = 0; k < NMAX; ++k) x[k] = X[(k < n ? k : 0) * ldx + cl];
 #pragma unroll
     for (int i = NMAX - 1; i >= 0; --i) {
       if (i < n) {
         const double rd = wave_bcast(rdl, i);
+        double lc[NMAX];
+#pragma unroll
+        for (int k = i + 1; k < NMAX; ++k) lc[k] = L[(k < n ? k : i) * ld + i];
         double acc = x[i];
 #pragma unroll
-        for (int k = i + 1; k < NMAX; ++k)
-          if (k < n) acc = fma(-L[k * ld + i], x[k], acc);
+        for (int k = i + 1; k < NMAX; ++k) {
+          const double nv = fma(-lc[k], x[k], acc);
+          acc = (k < n) ? nv : acc;
+        }
         x[i] = acc * rd;
       }
-      __builtin_amdgcn_sched_barrier(0);
     }
     if (mine) {
 #pragma unroll
@@ -119,13 +135,15 @@ __device__ __forceinline__ void reg_trsm_lower_t(const double* L, int ld, double
 // wg_pchol on S (LDS, read only): lane i holds row i of K; the pivot row is
 // handed to every lane through rowbuf (LDS, >= NMAX doubles).
 template <int NMAX>
-__device__ __forceinline__ int reg_pchol(const double* S, int ld, int n, double tol, double* K, int ldk, double* rowbuf) {
+__device__ __forceinline__ int reg_pchol(const double* S, int ld, int n, double tol, double* K, int ldk,
+                                         double* rowbuf) {
   const int lane = ECLQR_TID;
   const bool row = lane < n;
+  const int rl = row ? lane : 0;
   double kr[NMAX];
 #pragma unroll
   for (int k = 0; k < NMAX; ++k) kr[k] = 0.0;
-  double rm = row ? S[lane * ld + lane] : 0.0;
+  double rm = row ? S[rl * ld + rl] : 0.0;
   bool done = !row;
   const double ref = wave_max(row ? rm : 0.0);
   int r = 0;
@@ -146,25 +164,21 @@ __device__ __forceinline__ int reg_pchol(const double* S, int ld, int n, double 
           for (int l = 0; l < j; ++l) rowbuf[l] = kr[l];
         }
         lds_sync();
-        double v = 0.0;
-        if (row) {
-          if (lane == p) {
-            v = dp;
-          } else if (!done) {
-            double acc = S[lane * ld + p];
+        double kp[NMAX];
 #pragma unroll
-            for (int l = 0; l < j; ++l) acc = fma(-kr[l], rowbuf[l], acc);
-            v = acc / dp;
-          }
-        }
+        for (int l = 0; l < j; ++l) kp[l] = rowbuf[l];
+        double acc = S[rl * ld + p];
+#pragma unroll
+        for (int l = 0; l < j; ++l) acc = fma(-kr[l], kp[l], acc);
+        const double q = acc / dp;
+        const double v = !row ? 0.0 : ((lane == p) ? dp : (done ? 0.0 : q));
         kr[j] = v;
         if (lane == p) done = true;
-        if (!done) rm = fma(-v, v, rm);
+        rm = done ? rm : fma(-v, v, rm);
         r = j + 1;
         lds_sync();
       }
     }
-    __builtin_amdgcn_sched_barrier(0);
   }
   if (row) {
 #pragma unroll
