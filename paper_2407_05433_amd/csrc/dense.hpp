@@ -667,8 +667,9 @@ __device__ __forceinline__ void wg_trsm_lower_t(const double* L, int ldl, double
   for (int col = ECLQR_TID; col < nc; col += ECLQR_NT) {
     for (int i = n - 1; i >= 0; --i) {
       const double rd = 1.0 / L[i * ldl + i];
+      // updates in descending k (the order of the right-looking form)
       X[i * ldx + col] =
-          lane_chain<true>(X[i * ldx + col], L + (i + 1) * ldl + i, ldl, X + (i + 1) * ldx + col, ldx, n - i - 1) * rd;
+          lane_chain<true>(X[i * ldx + col], L + (n - 1) * ldl + i, -ldl, X + (n - 1) * ldx + col, -ldx, n - i - 1) * rd;
     }
   }
   bsync<kL>();

@@ -31,31 +31,32 @@ namespace eclqr {
 // LU form is used.
 namespace {
 
-// Routines of the combine: register-resident when NMAX > 0 and the size fits
-// (operands in LDS), else the LDS/global ones; both give the same bits.
+// Routines of the combine: on the 8 x 8 lane grid when NMAX > 0 and the sizes
+// fit (operands in LDS), else the LDS/global ones; both give the same bits.
 template <bool kL, int NMAX>
 __device__ __forceinline__ int d_cholesky(double* S, int ld, int n, double* sh, double floor, double* buf) {
   if constexpr (NMAX > 0)
-    if (n <= NMAX) return reg_cholesky<NMAX>(S, ld, n, floor, buf);
+    if (n <= NMAX) return reg_cholesky<NMAX / 8>(S, ld, n, floor, buf);
   return wg_cholesky<kL>(S, ld, n, sh, floor);
 }
 template <bool kL, int NMAX>
-__device__ __forceinline__ void d_trsm_lower(const double* L, int ld, double* X, int ldx, int n, int nc) {
+__device__ __forceinline__ void d_trsm_lower(const double* L, int ld, double* X, int ldx, int n, int nc,
+                                             double* buf) {
   if constexpr (NMAX > 0)
-    if (n <= NMAX) return reg_trsm_lower<NMAX>(L, ld, X, ldx, n, nc);
+    if (n <= NMAX && nc <= NMAX + 8) return reg_trsm_lower<NMAX / 8, NMAX / 8 + 1>(L, ld, X, ldx, n, nc, buf);
   wg_trsm_lower<kL>(L, ld, X, ldx, n, nc);
 }
 template <bool kL, int NMAX>
-__device__ __forceinline__ void d_trsm_lower_t(const double* L, int ld, double* X, int ldx, int n, int nc) {
+__device__ __forceinline__ void d_trsm_lower_t(const double* L, int ld, double* X, int ldx, int n, int nc,
+                                               double* buf) {
   if constexpr (NMAX > 0)
-    if (n <= NMAX) return reg_trsm_lower_t<NMAX>(L, ld, X, ldx, n, nc);
+    if (n <= NMAX && nc <= NMAX + 8) return reg_trsm_lower_t<NMAX / 8, NMAX / 8 + 1>(L, ld, X, ldx, n, nc, buf);
   wg_trsm_lower_t<kL>(L, ld, X, ldx, n, nc);
 }
 template <bool kL, int NMAX>
-__device__ __forceinline__ int d_pchol(const double* S, int ld, int n, double tol, double* K, int ldk, double* rem, int* used,
-                              double* sh, double* buf) {
-  if constexpr (NMAX > 0)
-    if (n <= NMAX) return reg_pchol<NMAX>(S, ld, n, tol, K, ldk, buf);
+__device__ __forceinline__ int d_pchol(const double* S, int ld, int n, double tol, double* K, int ldk, double* rem,
+                                       int* used, double* sh, double* buf) {
+  (void)buf;
   return wg_pchol<kL>(S, ld, n, tol, K, ldk, rem, used, sh);
 }
 
@@ -178,7 +179,7 @@ __device__ __forceinline__ bool combine_factored(const double* A1, const double*
   for (int i = ECLQR_TID; i < ds; i += ECLQR_NT) Eo[lo.eta + i] = lane_chain<false>(et1[i], A1 + i, ds, wv, 1, dm);
   // Mm = Rg^{-1} L' ; Yb[:, :ds] = Mm A1 ; J = J1 + Yb'Yb
   wg_copy_t<kL>(Mm, dm, Lj, dm, dm, dm);
-  d_trsm_lower<kL, NMAX>(Gm, dm, Mm, dm, dm, dm);
+  d_trsm_lower<kL, NMAX>(Gm, dm, Mm, dm, dm, dm, buf);
   const int ly = ds + 1;
   wg_gemm<kL>(Yb, ly, Mm, dm, false, A1, ds, false, dm, ds, dm, 1.0, 0.0);
   wg_gemm<kL>(Eo + lo.J, ds, Yb, ly, true, Yb, ly, false, ds, ds, dm, 1.0, 0.0);
@@ -189,8 +190,8 @@ __device__ __forceinline__ bool combine_factored(const double* A1, const double*
   // Yb = L^{-T} [Rg^{-T} Mm A1 | xi - d] ; A = A2 Yb[:, :ds] ; b = A2 Yb[:, ds] + b2
   for (int i = ECLQR_TID; i < dm; i += ECLQR_NT) Yb[i * ly + ds] = xi[i] - tv[i];
   bsync<kL>();
-  d_trsm_lower_t<kL, NMAX>(Gm, dm, Yb, ly, dm, ds);
-  d_trsm_lower_t<kL, NMAX>(Lj, dm, Yb, ly, dm, ly);
+  d_trsm_lower_t<kL, NMAX>(Gm, dm, Yb, ly, dm, ds, buf);
+  d_trsm_lower_t<kL, NMAX>(Lj, dm, Yb, ly, dm, ly, buf);
   wg_gemm<kL>(Eo + lo.A, ds, A2, dm, false, Yb, ly, false, de, ds, dm, 1.0, 0.0);
   for (int i = ECLQR_TID; i < de; i += ECLQR_NT) Eo[lo.b + i] = lane_chain<false>(b2[i], A2 + i * dm, 1, Yb + ds, ly, dm);
   // C = C2 + (A2 K R2^{-T})(A2 K R2^{-T})'
@@ -203,7 +204,7 @@ __device__ __forceinline__ bool combine_factored(const double* A1, const double*
     wg_symmetrize<kL>(G2, r, r);
     if (d_cholesky<kL, NMAX>(G2, r, r, sh, 0.0, buf)) return false;
     wg_copy_t<kL>(Mm, dm, Km, dm, dm, r);           // K' (r x dm)
-    d_trsm_lower<kL, NMAX>(G2, r, Mm, dm, r, dm);
+    d_trsm_lower<kL, NMAX>(G2, r, Mm, dm, r, dm, buf);
     wg_gemm<kL>(AN, r, A2, dm, false, Mm, dm, true, de, r, dm, 1.0, 0.0);
     wg_gemm<kL>(Eo + lo.C, de, AN, r, false, AN, r, true, de, de, r, 1.0, 0.0);
   } else {

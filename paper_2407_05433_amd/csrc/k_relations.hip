@@ -319,6 +319,7 @@ __global__ void __launch_bounds__(kBlock) k_rel_compose_reg(DevEngine e, int64_t
   constexpr int QROWS = (PR > KC) ? PR : KC;
   __shared__ double Qb[QROWS * (KC + 1)];
   __shared__ double vbuf[PR];
+  __shared__ double vs[PR];
   __shared__ double pb[KC + 1];
   __shared__ double dots[KC];
   const int lane = ECLQR_TID;
@@ -396,7 +397,7 @@ __global__ void __launch_bounds__(kBlock) k_rel_compose_reg(DevEngine e, int64_t
     }
     const double omax = fmax(1.0, wave_max(om));
     const int R = (nb < P) ? nb : P;
-    const int rho = rr_phase1<PR, NC>(col, p, c, nb, t.rank, vbuf, glog + lg.V, P, glog + lg.tau, R);
+    const int rho = rr_phase1<PR, NC>(col, p, c, nb, t.rank, vbuf, vs, glog + lg.V, P, glog + lg.tau, R);
     // rows rho.. of the (a | c | 1) columns, one row per lane
     const int q = p - rho;
 #pragma unroll
@@ -421,7 +422,7 @@ __global__ void __launch_bounds__(kBlock) k_rel_compose_reg(DevEngine e, int64_t
     if (lane < q) off = Qb[lane * (KC + 1) + KC];
     lds_sync();
     int bad = 0, over = 0;
-    const int rr = rr_phase2<KC>(row, off, q, t.rank, t.cons * omax, Qb, pb, dots, cap, glog + lg.gs, lg.step, &bad,
+    const int rr = rr_phase2<KC>(row, off, q, kc, t.rank, t.cons * omax, Qb, pb, dots, cap, glog + lg.gs, lg.step, &bad,
                                  &over);
     const int lo = kc + 1;
     if (!over)

@@ -22,9 +22,10 @@
 
 namespace eclqr {
 
+// vbuf, vs: LDS, PR doubles each.
 template <int PR, int NC>
-__device__ inline int rr_phase1(double (&col)[NC][PR], int p, int c, int nb, double thr, double* vbuf, double* Vlog,
-                                int P, double* taulog, int R) {
+__device__ __forceinline__ int rr_phase1(double (&col)[NC][PR], int p, int c, int nb, double thr, double* vbuf,
+                                         double* vs, double* Vlog, int P, double* taulog, int R) {
   const int lane = ECLQR_TID;
   bool used[NC];
 #pragma unroll
@@ -41,11 +42,16 @@ __device__ inline int rr_phase1(double (&col)[NC][PR], int p, int c, int nb, dou
       if (cl < nb && !used[t]) {
         double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-        for (int r = 0; r < PR; r += 2) {
-          const double a0 = (r >= j) ? col[t][r] : 0.0;
-          const double a1 = (r + 1 >= j) ? col[t][r + 1] : 0.0;
-          s0 = fma(a0, a0, s0);
-          s1 = fma(a1, a1, s1);
+        for (int r0 = 0; r0 < PR; r0 += 8) {
+          if (r0 + 8 > j) {  // uniform: blocks of rows above the pivot row add exact zeros
+#pragma unroll
+            for (int r = r0; r < r0 + 8; r += 2) {
+              const double a0 = (r >= j) ? col[t][r] : 0.0;
+              const double a1 = (r + 1 >= j) ? col[t][r + 1] : 0.0;
+              s0 = fma(a0, a0, s0);
+              s1 = fma(a1, a1, s1);
+            }
+          }
         }
         const double s = s0 + s1;
         if (best < 0 || s > bv) {
@@ -74,27 +80,39 @@ __device__ inline int rr_phase1(double (&col)[NC][PR], int p, int c, int nb, dou
     const double beta = -copysign(nrm, x0);
     const double tj = (beta - x0) / beta;
     const double scale = 1.0 / (x0 - beta);
-    if (j < R) {
-      for (int r = lane; r < p; r += 64) Vlog[(int64_t)j * P + r] = (r > j) ? vbuf[r] * scale : 0.0;
-      if (lane == 0) taulog[j] = tj;
+    // the scaled reflector, entry r in lane r (implicit 1 at row j), once
+    for (int r = lane; r < PR; r += 64) {
+      const double v = (r > j && r < p) ? vbuf[r] * scale : ((r == j) ? 1.0 : 0.0);
+      vs[r] = v;
+      if (j < R && r < p) Vlog[(int64_t)j * P + r] = (r > j) ? v : 0.0;
     }
+    if (j < R && lane == 0) taulog[j] = tj;
+    lds_sync();
+    double vr[PR];
+#pragma unroll
+    for (int r = 0; r < PR; ++r) vr[r] = vs[r];
 #pragma unroll
     for (int t = 0; t < NC; ++t) {
       const int cl = lane + 64 * t;
       if (cl < c && !used[t]) {
         double w0 = 0.0, w1 = 0.0;
 #pragma unroll
-        for (int r = 0; r < PR; r += 2) {
-          const double v0 = (r > j) ? vbuf[r] * scale : ((r == j) ? 1.0 : 0.0);
-          const double v1 = (r + 1 > j) ? vbuf[r + 1] * scale : ((r + 1 == j) ? 1.0 : 0.0);
-          w0 = fma(v0, col[t][r], w0);
-          w1 = fma(v1, col[t][r + 1], w1);
+        for (int r0 = 0; r0 < PR; r0 += 8) {
+          if (r0 + 8 > j) {
+#pragma unroll
+            for (int r = r0; r < r0 + 8; r += 2) {
+              w0 = fma(vr[r], col[t][r], w0);
+              w1 = fma(vr[r + 1], col[t][r + 1], w1);
+            }
+          }
         }
         const double w = (w0 + w1) * tj;
 #pragma unroll
-        for (int r = 0; r < PR; ++r) {
-          const double v = (r > j) ? vbuf[r] * scale : ((r == j) ? 1.0 : 0.0);
-          col[t][r] = fma(-w, v, col[t][r]);
+        for (int r0 = 0; r0 < PR; r0 += 8) {
+          if (r0 + 8 > j) {
+#pragma unroll
+            for (int r = r0; r < r0 + 8; ++r) col[t][r] = fma(-w, vr[r], col[t][r]);
+          }
         }
       }
     }
@@ -107,9 +125,11 @@ __device__ inline int rr_phase1(double (&col)[NC][PR], int p, int c, int nb, dou
 // Phase 2 on the rows held one per lane (lane < q).  Q: LDS, >= C x (KC + 1)
 // (chosen rows with their offsets), pb: LDS KC + 1, dots: LDS C.  Returns the
 // rows chosen; *over = 1 when more than C rows are independent.
+// Columns >= kc of every row are zero; the unrolled sweeps skip those blocks.
 template <int KC>
-__device__ inline int rr_phase2(double (&row)[KC], double& off, int q, double thr, double cons_thr, double* Q, double* pb,
-                                double* dots, int C, double* gslog, int64_t gstep, int* bad, int* over) {
+__device__ __forceinline__ int rr_phase2(double (&row)[KC], double& off, int q, int kc, double thr, double cons_thr,
+                                         double* Q, double* pb, double* dots, int C, double* gslog, int64_t gstep,
+                                         int* bad, int* over) {
   const int lane = ECLQR_TID;
   bool chosen = lane >= q;
   int sel = 0;
@@ -118,9 +138,14 @@ __device__ inline int rr_phase2(double (&row)[KC], double& off, int q, double th
   while (sel < q) {
     double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-    for (int k = 0; k < KC; k += 2) {
-      s0 = fma(row[k], row[k], s0);
-      s1 = fma(row[k + 1], row[k + 1], s1);
+    for (int k0 = 0; k0 < KC; k0 += 8) {
+      if (k0 < kc) {
+#pragma unroll
+        for (int k = k0; k < k0 + 8; k += 2) {
+          s0 = fma(row[k], row[k], s0);
+          s1 = fma(row[k + 1], row[k + 1], s1);
+        }
+      }
     }
     double bv = chosen ? 0.0 : s0 + s1;
     int best = chosen ? -1 : lane;
@@ -144,7 +169,7 @@ __device__ inline int rr_phase2(double (&row)[KC], double& off, int q, double th
     lds_sync();
     if (sel > 0) {
       for (int l = lane; l < sel; l += 64) {
-        const double d = lane_dot(Q + (int64_t)l * (KC + 1), 1, pb, 1, KC);
+        const double d = lane_dot(Q + (int64_t)l * (KC + 1), 1, pb, 1, kc);
         dots[l] = d;
         rec[2 + l] = d;
       }
@@ -159,16 +184,29 @@ __device__ inline int rr_phase2(double (&row)[KC], double& off, int q, double th
     double* qs = Q + (int64_t)sel * (KC + 1);
     for (int k = lane; k <= KC; k += 64) qs[k] = pb[k] * inv;
     lds_sync();
+    double qv[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) qv[k] = qs[k];
     if (!chosen) {
       double d0 = 0.0, d1 = 0.0;
 #pragma unroll
-      for (int k = 0; k < KC; k += 2) {
-        d0 = fma(row[k], qs[k], d0);
-        d1 = fma(row[k + 1], qs[k + 1], d1);
+      for (int k0 = 0; k0 < KC; k0 += 8) {
+        if (k0 < kc) {
+#pragma unroll
+          for (int k = k0; k < k0 + 8; k += 2) {
+            d0 = fma(row[k], qv[k], d0);
+            d1 = fma(row[k + 1], qv[k + 1], d1);
+          }
+        }
       }
       const double d = d0 + d1;
 #pragma unroll
-      for (int k = 0; k < KC; ++k) row[k] = fma(-d, qs[k], row[k]);
+      for (int k0 = 0; k0 < KC; k0 += 8) {
+        if (k0 < kc) {
+#pragma unroll
+          for (int k = k0; k < k0 + 8; ++k) row[k] = fma(-d, qv[k], row[k]);
+        }
+      }
       off = fma(-d, qs[KC], off);
       rec[2 + C + lane] = d;
     }
