@@ -169,6 +169,35 @@ def secondary_differentiable(ecl, torch, steps):
     return res
 
 
+def stored_traffic(kernel_class, workload):
+    """HBM bytes per launch of `kernel_class` on `workload` from a committed
+    rocprofv3 --pmc summary under profiles/ (FETCH_SIZE and WRITE_SIZE runs,
+    calibrated against a device copy), or None when there is none or when the
+    kernel sources it hashes have changed since the counters were taken."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.md"))):
+        kv = {}
+        with open(path) as fh:
+            for ln in fh:
+                if ":" in ln and ln[:1].isalpha():
+                    k, v = ln.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("traffic_kernel_class") != kernel_class or kv.get("traffic_workload") != workload:
+            continue
+        h = hashlib.sha256()
+        try:
+            for f in kv.get("sources", "").split():
+                with open(os.path.join(ROOT, f), "rb") as fh:
+                    h.update(fh.read())
+        except OSError:
+            return None
+        if h.hexdigest() != kv.get("sources_sha256"):
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    return None
+
+
 def cpu_baseline(problems, min_s=10.0, max_s=30.0):
     """The oracle (sequential method + minimum-norm multipliers + one
     refinement step) on a bounded sample of the workload: instances in order,
@@ -249,7 +278,8 @@ def main():
     dom_launches = prof[dom][1]
     achieved = work[dom] / (dom_ms * 1e-3) / 1e12
     roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+            "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+            "traffic": stored_traffic(dom, args.workload),
             "flops_per_solve": work[dom], "ms_per_solve": dom_ms, "launches_per_solve": dom_launches,
             "avg_launch_us": dom_ms * 1e3 / max(dom_launches, 1)}
     total_flops = sum(work.values())
