@@ -207,7 +207,9 @@ typedef struct {
   double ms_per_solve;    /* time of the configuration chosen by eclqr_plan_autotune (0 if never tuned) */
   int32_t register_compose; /* relation compositions that fit (<= 64 stacked rows, <= 128 columns) keep the
                              * stacked system in registers instead of LDS */
-  int32_t reserved[3];
+  int32_t stage_lds;      /* stage eliminations and feedback gains keep their working arrays in LDS when these
+                             need at most 32 KiB per workgroup (1, default), else in global scratch (0) */
+  int32_t reserved[2];
 } eclqr_tuning;
 
 /* Time the caller's problem under alternative launch configurations

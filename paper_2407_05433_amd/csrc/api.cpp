@@ -52,7 +52,7 @@ T* at(void* ws, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
 }
 
-int32_t g_pool_lds = 2, g_grid_div = 1, g_buckets = 1, g_reg = 1;  // tuning of the plan being launched
+int32_t g_pool_lds = 2, g_grid_div = 1, g_buckets = 1, g_reg = 1, g_stage_lds = 1;  // tuning of the plan being launched
 
 DevEngine dev_engine(const Engine& E, void* ws, size_t base) {
   DevEngine d{};
@@ -81,6 +81,7 @@ DevEngine dev_engine(const Engine& E, void* ws, size_t base) {
   d.nblocks = std::max<int32_t>(1, E.nblocks / std::max<int32_t>(1, g_grid_div));
   d.pool_lds = g_pool_lds;
   d.reg_compose = g_reg;
+  d.elim_lds = g_stage_lds;
   return d;
 }
 
@@ -211,13 +212,13 @@ eclqr_status run_engine(const Engine& E, const DevEngine& d, const Inputs& in, d
     }
   }
   { Timed tm(ECLQR_K_DOMAIN, s); launch_domain(d, in, t, status, std::max(1, E.maxn), s); }
-  { Timed tm(ECLQR_K_ELIMINATE, s); launch_eliminate(d, in, t, status, std::max(1, E.maxm), E.elim_maxq, s); }
+  { Timed tm(ECLQR_K_ELIMINATE, s); launch_eliminate(d, in, t, status, std::max(1, E.maxm), E.elim_maxq, std::max(1, E.maxn), E.maxk, s); }
   for (int l = 0; l < 2 * E.D; ++l) {
     if (E.lvl_count[l] == 0) continue;
     Timed tm(ECLQR_K_RIC_COMBINE, s);
     launch_ric_combine(d, E.lvl_begin[l], E.lvl_count[l], status, std::max(1, E.lvl_dim[l]), s);
   }
-  { Timed tm(ECLQR_K_GAINS, s); launch_gains(d, status, std::max(1, E.maxm), s); }
+  { Timed tm(ECLQR_K_GAINS, s); launch_gains(d, status, std::max(1, E.maxm), std::max(1, E.maxn), s); }
   for (int l = 0; l < 2 * E.D; ++l) {
     if (E.lvl_count[l] == 0) continue;
     Timed tm(ECLQR_K_FWD_COMBINE, s);
@@ -291,6 +292,7 @@ struct Views {
 
 Views views(Plan& p, void* ws) {
   g_pool_lds = p.pool_lds;
+  g_stage_lds = p.stage_lds;
   g_grid_div = p.grid_divisor;
   g_buckets = p.level_buckets;
   g_reg = p.reg_compose;
@@ -791,6 +793,7 @@ eclqr_status eclqr_plan_get_tuning(const eclqr_plan* plan, eclqr_tuning* out) {
   out->pool_in_lds = p.pool_lds;
   out->grid_divisor = p.grid_divisor;
   out->register_compose = p.reg_compose;
+  out->stage_lds = p.stage_lds;
   out->ms_per_solve = p.tuned_ms;
   return ECLQR_SUCCESS;
 }
@@ -805,6 +808,7 @@ eclqr_status eclqr_plan_set_tuning(eclqr_plan* plan, const eclqr_tuning* t) {
   p.pool_lds = t->pool_in_lds;
   p.grid_divisor = t->grid_divisor;
   p.reg_compose = t->register_compose != 0;
+  p.stage_lds = t->stage_lds != 0;
   release_graph(p);
   return ECLQR_SUCCESS;
 }
@@ -843,7 +847,7 @@ eclqr_status eclqr_plan_autotune(eclqr_plan* plan, const eclqr_problem* prob, ec
     int32_t alt;
   };
   int32_t graph = p.opt.use_graph;
-  Knob knobs[] = {{&p.reg_compose, p.reg_compose ? 0 : 1},
+  Knob knobs[] = {{&p.reg_compose, p.reg_compose ? 0 : 1}, {&p.stage_lds, p.stage_lds ? 0 : 1},
                   {&p.level_buckets, p.level_buckets ? 0 : 1}, {&p.pool_lds, p.pool_lds == 2 ? 1 : 2},
                   {&p.grid_divisor, p.grid_divisor == 1 ? 4 : 1}, {&graph, graph ? 0 : 1}};
   for (Knob& k : knobs) {

@@ -32,6 +32,10 @@ struct Bump {
 // Terminal stage: Q-bar_N = T^T Q_N T, q-bar_N = T^T (Q_N t + q_N)
 // (eq. (terminal-cost-data)), element J = Q-bar_N, eta = -q-bar_N.
 // LDS: W (maxm x maxq) | tau | qr scratch | perm | Lc (maxm x maxm) | sh | reduction buffer
+// [| the stage's working arrays, kLS: they live in LDS instead of the
+// workgroup's global scratch (every dependent access then waits on LDS, not
+// on L2)]
+template <bool kLS>
 __global__ void __launch_bounds__(kBlock) k_eliminate(DevEngine e, Inputs in, Tols t, int32_t* status, int maxm,
                                                       int maxq) {
   extern __shared__ double lds[];
@@ -42,6 +46,7 @@ __global__ void __launch_bounds__(kBlock) k_eliminate(DevEngine e, Inputs in, To
   double* Lc = (double*)(perm + 2 * kMaxDim);
   double* sh = Lc + (int64_t)maxm * maxm;
   double* red = sh + 16;
+  double* lscr = red + kBlock;
   for (int64_t s = blockIdx.x; s < e.S; s += gridDim.x) {
     const StageInfo st = e.st[s];
     if (gated(e, st.inst)) continue;
@@ -53,7 +58,7 @@ __global__ void __launch_bounds__(kBlock) k_eliminate(DevEngine e, Inputs in, To
     const double* tv = base + ar.t;
     const double* Q = in.f[IN_Q] + st.in[IN_Q];
     const double* qv = in.f[IN_q] + st.in[IN_q];
-    Bump bump{block_scratch(e)};
+    Bump bump{kLS ? lscr : block_scratch(e)};
     double* ric = slot_ptr(e, SCAN_RIC, st.elem[SCAN_RIC]);
     if (st.terminal) {
       const RicLayout rl = ric_layout(n, 0);
@@ -352,9 +357,13 @@ __global__ void __launch_bounds__(kBlock) k_eliminate(DevEngine e, Inputs in, To
   }
 }
 
+static int g_elim_max_lds = 65536;
 void eliminate_set_max_lds(int bytes) {
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_eliminate), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            bytes);
+  g_elim_max_lds = bytes;
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_eliminate<false>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_eliminate<true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 size_t elim_lds_bytes(int maxm, int maxq) {
@@ -362,10 +371,18 @@ size_t elim_lds_bytes(int maxm, int maxq) {
          sizeof(int) * 2 * kMaxDim + 64;
 }
 
-void launch_eliminate(const DevEngine& e, const Inputs& in, Tols t, int32_t* status, int maxm, int maxq,
-                      hipStream_t s) {
-  hipLaunchKernelGGL(k_eliminate, dim3(e.nblocks), dim3(kBlock), elim_lds_bytes(maxm, maxq), s, e, in, t, status,
-                     maxm, maxq);
+void launch_eliminate(const DevEngine& e, const Inputs& in, Tols t, int32_t* status, int maxm, int maxq, int maxn,
+                      int maxk, hipStream_t s) {
+  const size_t base = elim_lds_bytes(maxm, maxq);
+  const size_t with = base + sizeof(double) * (size_t)elim_scratch(maxn, maxn, maxm, maxk);
+  // LDS only while a workgroup needs at most 32 KiB: above that the lost
+  // occupancy costs more than the faster accesses gain
+  if (e.elim_lds && with <= 32768 && with <= (size_t)g_elim_max_lds)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_eliminate<true>), dim3(e.nblocks), dim3(kBlock), with, s, e, in, t, status,
+                       maxm, maxq);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_eliminate<false>), dim3(e.nblocks), dim3(kBlock), base, s, e, in, t, status,
+                       maxm, maxq);
 }
 
 }  // namespace eclqr

@@ -320,11 +320,14 @@ __global__ void __launch_bounds__(kBlock, 1) k_ric_combine(DevEngine e, int64_t 
 // H_ux = M-bar' + B-bar'P'A-bar, h_u = r-bar + B-bar'(P'c-bar + p'),
 // K = -H_uu^{-1} H_ux, k = -H_uu^{-1} h_u, and the closed-loop map
 // z' = (A-bar + B-bar K) z + (B-bar k + c-bar) as the forward-scan leaf.
-// LDS: Huu (maxm x maxm) | sh
+// LDS: Huu (maxm x maxm) | sh [| working arrays, kLS: in LDS instead of the
+// workgroup's global scratch]
+template <bool kLS>
 __global__ void __launch_bounds__(kBlock) k_gains(DevEngine e, int32_t* status, int maxm) {
   extern __shared__ double lds[];
   double* Huu = lds;
   double* sh = Huu + (int64_t)maxm * maxm;
+  double* lscr = sh + 16;
   for (int64_t s = blockIdx.x; s < e.S; s += gridDim.x) {
     const StageInfo st = e.st[s];
     if (st.terminal || gated(e, st.inst)) continue;
@@ -340,7 +343,7 @@ __global__ void __launch_bounds__(kBlock) k_gains(DevEngine e, int32_t* status, 
     const double *Mb = base + ar.Mb, *Rb = base + ar.Rb, *rb = base + ar.rb;
     double* K = base + ar.K;
     double* kk = base + ar.kk;
-    double* s0 = block_scratch(e);
+    double* s0 = kLS ? lscr : block_scratch(e);
     double* PB = s0;                                   // nb1 x mb
     double* PA = PB + rup4((int64_t)nb1 * mb);         // nb1 x nb
     double* Hux = PA + rup4((int64_t)nb1 * nb);        // mb x nb
@@ -474,7 +477,10 @@ void lqr_set_max_lds(int bytes) {
                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_ric_combine<2, 32>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_gains), hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_gains<false>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            bytes);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_gains<true>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            bytes);
 }
 
 // LDS bytes of a value-function combine launch in mode m at middle dim bound d.
@@ -516,8 +522,13 @@ void launch_ric_combine(const DevEngine& e, int64_t first, int64_t ntasks, int32
                        status, maxd);
 }
 
-void launch_gains(const DevEngine& e, int32_t* status, int maxm, hipStream_t s) {
-  hipLaunchKernelGGL(k_gains, dim3(e.nblocks), dim3(kBlock), gains_lds_bytes(maxm), s, e, status, maxm);
+void launch_gains(const DevEngine& e, int32_t* status, int maxm, int maxn, hipStream_t s) {
+  const size_t base = gains_lds_bytes(maxm);
+  const size_t with = base + sizeof(double) * (size_t)gains_scratch(maxn, maxn, maxm);
+  if (e.elim_lds && with <= 32768 && with <= (size_t)g_lqr_max_lds)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gains<true>), dim3(e.nblocks), dim3(kBlock), with, s, e, status, maxm);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gains<false>), dim3(e.nblocks), dim3(kBlock), base, s, e, status, maxm);
 }
 
 void launch_fwd_combine(const DevEngine& e, int64_t first, int64_t ntasks, hipStream_t s) {

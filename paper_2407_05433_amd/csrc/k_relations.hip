@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(kBlock) k_base_relation(DevEngine e, Inputs in
                                                           int ldw) {
   extern __shared__ double lds[];
   double* W = lds;
-  double* tau = W + (int64_t)maxp * ldw;
+  double* tau = W + (int64_t)maxp * (ldw | 1);
   double* qd = tau + kMaxDim;
   int* perm = (int*)(qd + kMaxDim + 8);
   double* rbs = (double*)(perm + kMaxDim);
@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(kBlock) k_base_relation(DevEngine e, Inputs in
     }
     const int p = np + k;
     const int c = m + n + np + 1;
-    const int ld = c;
+    const int ld = c | 1;  // odd: rows read one per lane hit distinct LDS banks
     const double* A = in.f[IN_A] + st.in[IN_A];
     const double* B = in.f[IN_B] + st.in[IN_B];
     const double* cv = in.f[IN_c] + st.in[IN_c];
@@ -200,7 +200,7 @@ __global__ void __launch_bounds__(kBlock) k_rel_compose(DevEngine e, int64_t fir
                                                         int32_t* status, int maxp, int ldw) {
   extern __shared__ double lds[];
   double* W = lds;
-  double* tau = W + (int64_t)maxp * ldw;
+  double* tau = W + (int64_t)maxp * (ldw | 1);
   double* qd = tau + kMaxDim;
   int* perm = (int*)(qd + kMaxDim + 8);
   double* rbs = (double*)(perm + kMaxDim);
@@ -252,7 +252,7 @@ __global__ void __launch_bounds__(kBlock) k_rel_compose(DevEngine e, int64_t fir
       continue;
     }
     const int c = nb + na + nc + 1;
-    const int ld = c;
+    const int ld = c | 1;  // odd: rows read one per lane hit distinct LDS banks
     const int lda = na + nb + 1, ldb = nb + nc + 1;
     for (int idx = ECLQR_TID; idx < p * c; idx += ECLQR_NT) {
       const int r = idx / c, j = idx % c;
@@ -525,7 +525,7 @@ void relations_set_max_lds(int bytes) {
 }
 
 size_t rel_lds_bytes(int maxp, int ldw) {
-  return sizeof(double) * ((size_t)maxp * ldw + kMaxDim + kMaxDim + 8 + 2 * maxp + 8 + 64 + 16) +
+  return sizeof(double) * ((size_t)maxp * (ldw | 1) + kMaxDim + kMaxDim + 8 + 2 * maxp + 8 + 64 + 16) +
          sizeof(int) * kMaxDim + 64;
 }
 

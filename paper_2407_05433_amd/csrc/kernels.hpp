@@ -36,6 +36,7 @@ struct DevEngine {
   int32_t nblocks;            // grid size of the stage-parallel kernels (grid-stride)
   int32_t pool_lds;           // value-function combine LDS mode (0 global pool, 1 LDS pool, 2 all in LDS)
   int32_t reg_compose;        // 1: relation compositions that fit run register-resident
+  int32_t elim_lds;           // 1: stage eliminations keep their working arrays in LDS when they fit
 };
 
 // Pointers to one problem's data (caller layout of the engine).
@@ -66,11 +67,11 @@ void launch_base_relation(const DevEngine& e, const Inputs& in, Tols t, int32_t*
 void launch_rel_compose(const DevEngine& e, int64_t first_task, int64_t ntasks, Tols t, int32_t* status, int maxp,
                         int ldw, int maxkc, hipStream_t s);
 void launch_domain(const DevEngine& e, const Inputs& in, Tols t, int32_t* status, int maxn, hipStream_t s);
-void launch_eliminate(const DevEngine& e, const Inputs& in, Tols t, int32_t* status, int maxm, int maxq,
-                      hipStream_t s);
+void launch_eliminate(const DevEngine& e, const Inputs& in, Tols t, int32_t* status, int maxm, int maxq, int maxn,
+                      int maxk, hipStream_t s);
 void launch_ric_combine(const DevEngine& e, int64_t first_task, int64_t ntasks, int32_t* status, int maxd,
                         hipStream_t s);
-void launch_gains(const DevEngine& e, int32_t* status, int maxm, hipStream_t s);
+void launch_gains(const DevEngine& e, int32_t* status, int maxm, int maxn, hipStream_t s);
 void launch_fwd_combine(const DevEngine& e, int64_t first_task, int64_t ntasks, hipStream_t s);
 void launch_recover(const DevEngine& e, double* x, double* u, hipStream_t s);
 

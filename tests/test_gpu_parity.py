@@ -294,7 +294,8 @@ def test_autotune_keeps_results():
     base = ecl.get_tuning(plan)
     tuned = ecl.autotune(plan, data, ws)
     assert tuned["ms_per_solve"] > 0
-    for cfg in ({"level_buckets": 0}, {"pool_in_lds": 0}, {"pool_in_lds": 1}, {"grid_divisor": 4}, {"use_graph": 1},
+    for cfg in ({"level_buckets": 0}, {"pool_in_lds": 0}, {"pool_in_lds": 1}, {"stage_lds": 0}, {"grid_divisor": 4},
+                {"use_graph": 1},
                 {"register_compose": 0}, tuned):
         full = dict(base)
         full.update(cfg)
