@@ -655,17 +655,24 @@ void replay_set_max_lds(int bytes) {
   g_dyn_compose = set_dyn_limit(reinterpret_cast<const void*>(k_rel_compose_vec), bytes);
   g_dyn_ric = set_dyn_limit(reinterpret_cast<const void*>(k_ric_combine_vec), bytes);
 }
-// doubles of dynamic LDS for a staged relation log, at most the kernel's limit
+// Staging a log pays off for latency-bound launches (at most kStageTasks
+// tasks: a few per compute unit) and up to 24 KiB per workgroup; on wider
+// launches, or beyond that size, the lost occupancy costs more than the
+// faster accesses save, so logs are read in place.
+constexpr int64_t kStageCapBytes = 24 * 1024;
+constexpr int64_t kStageTasks = 1024;
+// doubles of dynamic LDS for a staged relation log
 static int64_t rel_logcap(int64_t want, int dyn_bytes) {
-  const int64_t room = (int64_t)dyn_bytes / (int64_t)sizeof(double);
+  int64_t room = (int64_t)dyn_bytes / (int64_t)sizeof(double);
+  if (room > kStageCapBytes / (int64_t)sizeof(double)) room = kStageCapBytes / (int64_t)sizeof(double);
   return want < room ? want : (room > 0 ? room : 0);
 }
 void launch_base_relation_vec(const DevEngine& e, const Inputs& in, int64_t logmax, hipStream_t s) {
-  const int64_t cap = rel_logcap(logmax, g_dyn_base);
+  const int64_t cap = (e.S <= kStageTasks) ? rel_logcap(logmax, g_dyn_base) : 0;
   hipLaunchKernelGGL(k_base_relation_vec, dim3(e.nblocks), dim3(kBlock), sizeof(double) * cap, s, e, in, cap);
 }
 void launch_rel_compose_vec(const DevEngine& e, int64_t first, int64_t ntasks, int64_t logmax, hipStream_t s) {
-  const int64_t cap = rel_logcap(logmax, g_dyn_compose);
+  const int64_t cap = (ntasks <= kStageTasks) ? rel_logcap(logmax, g_dyn_compose) : 0;
   if (ntasks > 0)
     hipLaunchKernelGGL(k_rel_compose_vec, dim3(grid_of(e, ntasks)), dim3(kBlock), sizeof(double) * cap, s, e, first,
                        ntasks, cap);
@@ -678,8 +685,10 @@ void launch_eliminate_vec(const DevEngine& e, const Inputs& in, hipStream_t s) {
 }
 void launch_ric_combine_vec(const DevEngine& e, int64_t first, int64_t ntasks, int maxd, hipStream_t s) {
   // staged factors need (4 + 2 d^2 + d) + 2 d^2 doubles; larger levels read them in place
-  int d = maxd;
-  while (d > 0 && (int64_t)sizeof(double) * (4 + 4 * (int64_t)d * d + d) > (int64_t)g_dyn_ric) --d;
+  int d = (ntasks <= kStageTasks) ? maxd : 0;
+  while (d > 0 && ((int64_t)sizeof(double) * (4 + 4 * (int64_t)d * d + d) > (int64_t)g_dyn_ric ||
+                   (int64_t)sizeof(double) * (4 + 4 * (int64_t)d * d + d) > kStageCapBytes))
+    --d;
   const size_t lds = d > 0 ? sizeof(double) * (4 + 4 * (size_t)d * d + d) : 0;
   if (ntasks > 0)
     hipLaunchKernelGGL(k_ric_combine_vec, dim3(grid_of(e, ntasks)), dim3(kBlock), lds, s, e, first, ntasks, d);
