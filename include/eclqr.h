@@ -17,8 +17,8 @@
  * suffix scan over affine endpoint relations (Sections III-IV), the
  * stage-parallel elimination (Section V), an associative-scan Riccati solve of
  * the reduced LQR (Section VI), primal recovery (eq. (recovery-maps)) and the
- * multipliers of Section VII (the minimum-norm solution of the stationarity
- * equations).
+ * multipliers of Section VII (by default the minimum-norm solution of the
+ * stationarity equations; optionally the factor-reusing route).
  *
  * Conventions
  * - All floating-point data are FP64.  Integers are int32 unless stated.
@@ -103,7 +103,11 @@ typedef struct {
   double refine_tol;      /* an instance stops refining once ||correction|| <= refine_tol*||(x,u)||; 1e-8 */
   double accept_tol;      /* an instance whose componentwise KKT backward error after the first solve is
                            * <= accept_tol takes no refinement step; 1e-13 (0: always refine) */
-  int32_t multipliers;    /* 1: compute lam and mu; 0: primal only */
+  int32_t multipliers;    /* 0: primal only; 1: lam and mu as the minimum-norm solution of the stationarity
+                           * equations (the reversed-time problem of Section VII); 2: factor-reusing route
+                           * (Section IX implementation notes): one representative from the primal pass's
+                           * domains and scans -- equal to route 1 where the multipliers are unique (LICQ),
+                           * otherwise a valid multiplier vector that need not have minimum norm. 1 */
   int32_t refine;         /* most steps of iterative refinement per instance (0..4); 3.  A refined
                            * instance whose final KKT backward error exceeds dual_cons_tol reports
                            * ECLQR_DUAL_FAILED */
@@ -186,6 +190,7 @@ enum {
   ECLQR_K_RIC_COMBINE, ECLQR_K_GAINS, ECLQR_K_FWD_COMBINE, ECLQR_K_RECOVER, ECLQR_K_MULTIPLIER_IO,
   ECLQR_K_REFINE_IO, ECLQR_K_OTHER,
   ECLQR_K_REPLAY, /* every kernel of a vector-only pass (recovery included) */
+  ECLQR_K_MULT_FAST, /* the factor-reusing multiplier route (multipliers = 2) */
   ECLQR_NUM_KERNEL_CLASSES
 };
 

@@ -68,6 +68,7 @@ DevEngine dev_engine(const Engine& E, void* ws, size_t base) {
   d.mbar = reinterpret_cast<int32_t*>(b + E.o_mbar);
   d.arena = reinterpret_cast<double*>(b + E.o_arena);
   for (int k = 0; k < SCAN_COUNT; ++k) d.scan[k] = reinterpret_cast<double*>(b + E.o_scan[k]);
+  d.theta = reinterpret_cast<double*>(b + E.o_theta);
   d.resid = reinterpret_cast<double*>(b + E.o_resid);
   d.rel_log_off = reinterpret_cast<const int64_t*>(b + E.o_rel_log_off);
   d.ric_log_off = reinterpret_cast<const int64_t*>(b + E.o_ric_log_off);
@@ -171,6 +172,7 @@ eclqr_status bind(Plan& p, void* ws, hipStream_t s) {
     eliminate_set_max_lds(lds);
     lqr_set_max_lds(lds);
     replay_set_max_lds(lds);
+    fast_set_max_lds(lds);
   }
   eclqr_status st = upload_engine(p.primal, ws, p.o_primal, s);
   if (st != ECLQR_SUCCESS) return st;
@@ -361,6 +363,26 @@ eclqr_status multipliers(Plan& p, const Views& v, const Inputs& in, const double
   return ECLQR_SUCCESS;
 }
 
+// Factor-reusing multipliers of the problem `in` at its solution (x, u): the
+// per-stage local systems from the feasible domains and the value-function
+// and forward scans that the last primal pass on `in` (full or replayed) left
+// in the workspace, the forward scan of their theta maps, then lambda and mu
+// (added to lam, mu when acc).  Inconsistent local systems set
+// ECLQR_RANK_INCONSISTENT in `status` (null: not checked).
+eclqr_status fast_multipliers(Plan& p, const Views& v, const Inputs& in, const double* x, const double* u,
+                              double* lam, double* mu, int32_t* status, bool acc, hipStream_t s) {
+  const Engine& E = p.primal;
+  const Tols td{p.opt.rank_tol, p.opt.dual_cons_tol, 0};
+  Timed tm(ECLQR_K_MULT_FAST, s);
+  if (!launch_mult_local(v.P, in, x, u, td, status, E.fast_rows, E.fast_ldw, s))
+    return fail(ECLQR_UNSUPPORTED, "stage too large for the LDS tile of the factor-reusing multipliers");
+  for (int l = 0; l < 2 * E.D; ++l)
+    if (E.lvl_count[l] > 0) launch_theta_combine(v.P, E.lvl_begin[l], E.lvl_count[l], s);
+  launch_mult_final(v.P, lam, mu, acc ? 1 : 0, s);
+  HIP_OK(hipGetLastError());
+  return ECLQR_SUCCESS;
+}
+
 constexpr int32_t kDualStructural = ECLQR_CAPACITY | ECLQR_NOT_CONVEX | ECLQR_INVALID_INPUT;
 
 // Full solve of the problem `in`: primal, multipliers, refinement.  With
@@ -389,11 +411,13 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
                            : run_engine(p.primal, v.P, in, x, u, status, tp, s);
   if (st != ECLQR_SUCCESS) return st;
   if (!want_mult) return ECLQR_SUCCESS;
-  if (replay) {
+  const bool fast = p.opt.multipliers == 2;
+  if (replay || fast) {
     Timed tm(ECLQR_K_REFINE_IO, s);
     launch_fill_i32(v.dstatus, 0, B, s);
   }
-  st = multipliers(p, v, in, x, u, lam, mu, s, replay);
+  st = fast ? fast_multipliers(p, v, in, x, u, lam, mu, v.dstatus, false, s)
+            : multipliers(p, v, in, x, u, lam, mu, s, replay);
   if (st != ECLQR_SUCCESS) return st;
   const int nref = p.opt.refine;
   if (nref == 0) {
@@ -421,13 +445,19 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
     }
     st = run_engine_vec(p.primal, v.P, cin, v.cx, v.cu, s);
     if (st != ECLQR_SUCCESS) return st;
+    if (fast) {  // multipliers of the correction problem (the route is linear in the vectors)
+      st = fast_multipliers(p, v, cin, v.cx, v.cu, lam, mu, nullptr, true, s);
+      if (st != ECLQR_SUCCESS) return st;
+    }
     {
       Timed tm(ECLQR_K_REFINE_IO, s);
       launch_refine_update(v.P, x, u, v.cx, v.cu, v.rnorm, s);
       launch_refine_decide(v.P, v.psbase, v.rnorm, p.opt.refine_tol, it + 1 == nref, v.gate, v.rsteps, s);
     }
-    st = multipliers(p, v, in, x, u, lam, mu, s, true);
-    if (st != ECLQR_SUCCESS) return st;
+    if (!fast) {
+      st = multipliers(p, v, in, x, u, lam, mu, s, true);
+      if (st != ECLQR_SUCCESS) return st;
+    }
   }
   {
     Timed tm(ECLQR_K_REFINE_IO, s);
@@ -446,7 +476,7 @@ bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7) == 0; 
 eclqr_status solve_sequence(Plan& p, const Views& v, const Inputs& in, eclqr_solution* sol, bool want, hipStream_t s) {
   const Engine& E = p.primal;
   launch_fill_i32(sol->status, 0, E.B, s);
-  if (want) launch_dual_matrices(v.P, in, v.D, v.dp, s);
+  if (want && p.opt.multipliers == 1) launch_dual_matrices(v.P, in, v.D, v.dp, s);
   eclqr_status st = solve_all(p, v, in, sol->x, sol->u, sol->lam, sol->mu, sol->status, want, false, s);
   if (st != ECLQR_SUCCESS) return st;
   launch_finalize(v.P, sol->status, sol->x, sol->u, want ? sol->lam : nullptr, want ? sol->mu : nullptr, s);
@@ -498,7 +528,7 @@ eclqr_status eclqr_plan_create(eclqr_plan** out, const eclqr_dims* dims, const e
   if (opt) o = *opt;
   else eclqr_default_options(&o);
   if (!(o.rank_tol > 0) || !(o.cons_tol > 0) || !(o.dual_cons_tol > 0) || !(o.refine_tol >= 0) || !(o.accept_tol >= 0) || o.refine < 0 ||
-      o.refine > 4)
+      o.refine > 4 || o.multipliers < 0 || o.multipliers > 2)
     return fail(ECLQR_INVALID_ARGUMENT, "bad options");
   eclqr_plan* p = new (std::nothrow) eclqr_plan();
   if (!p) return fail(ECLQR_INVALID_ARGUMENT, "out of host memory");
@@ -578,6 +608,8 @@ eclqr_status eclqr_solve(eclqr_plan* plan, const eclqr_problem* prob, eclqr_solu
   eclqr_status st = bind(p, ws, s);
   if (st != ECLQR_SUCCESS) return st;
   g_prof = &p;
+  if (p.opt.multipliers == 2 && mult_local_lds_bytes(p.primal.fast_rows, p.primal.fast_ldw) > (size_t)g_max_lds)
+    return fail(ECLQR_UNSUPPORTED, "stage too large for the LDS tile of the factor-reusing multipliers");
   Views v = views(p, ws);
   Inputs in = inputs_of(prob);
   if (!p.opt.use_graph || p.profiling) return solve_sequence(p, v, in, sol, want, s);
@@ -701,7 +733,7 @@ eclqr_status eclqr_plan_profile(eclqr_plan* plan, double* ms, int64_t* launches,
 const char* eclqr_kernel_class_name(int32_t k) {
   static const char* names[ECLQR_NUM_KERNEL_CLASSES] = {
       "validate", "base_relation", "rel_compose", "domain", "eliminate", "ric_combine",
-      "gains", "fwd_combine", "recover", "multiplier_io", "refine_io", "other", "replay"};
+      "gains", "fwd_combine", "recover", "multiplier_io", "refine_io", "other", "replay", "multipliers_fast"};
   return (k >= 0 && k < ECLQR_NUM_KERNEL_CLASSES) ? names[k] : "unknown";
 }
 

@@ -41,7 +41,7 @@ struct StageInfo {
 // R-bar and of H_uu.
 struct Arena {
   int64_t T, t, Y, Z, y, Ab, Bb, cb, Qb, Mb, Rb, qb, rb, K, kk, v, kap;
-  int64_t rsc, prm, Q1, R11, Lc, Hc, size;
+  int64_t rsc, prm, Q1, R11, Lc, Hc, wl, Ym, ym, size;
 };
 
 ECLQR_HD inline Arena arena_layout(int n, int np, int m, int k) {
@@ -70,6 +70,9 @@ ECLQR_HD inline Arena arena_layout(int n, int np, int m, int k) {
   a.R11 = o; o += (int64_t)m * m;
   a.Lc = o; o += (int64_t)m * m;
   a.Hc = o; o += (int64_t)m * m;
+  a.wl = o; o += n;                // fast multipliers: T lambda-bar
+  a.Ym = o; o += (int64_t)k * n;   // mu = Ym theta + ym (k x r, ld n)
+  a.ym = o; o += k;
   a.size = (o + 3) & ~int64_t(3);  // 32-byte multiple
   return a;
 }

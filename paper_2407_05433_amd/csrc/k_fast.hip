@@ -1,0 +1,264 @@
+// Factor-reusing multiplier recovery (the fast route beside the contraction-
+// expansion of Section VII, which the paper's implementation notes describe as
+// algebraically equivalent).  It reuses what the primal pass already holds:
+// the domains X_i = {H_i x + h_i = 0} (orthonormal rows H_i, null basis T_i),
+// the value-function scan (suffix element of stage i: V_i(z) = 1/2 z'J_i z -
+// eta_i'z) and the forward scan (z_i).
+//
+// With the objective gradients of eq. (objective-gradients) and the stage
+// stationarity of eq. (stage-stationarity) (merged rows E_i x + F_i u + g_i = 0
+// with multiplier mu_i):
+//   * every multiplier has lambda_i = w_i + H_i' theta_i with w_i = T_i
+//     lambda-bar_i, lambda-bar_i = J_i z_i - eta_i the costate of the reduced
+//     problem (T_i' lambda_i is the gradient of the cost-to-go in z), and theta_i
+//     in R^{r_i}, r_i = rank H_i;
+//   * stage i's stationarity in the unknowns y = (mu_i, theta_{i+1}) reads
+//       [E_i'  (H_{i+1} A_i)'] y = H_i' theta_i - g^x_i - A_i' w_{i+1} + w_i
+//       [F_i'  (H_{i+1} B_i)'] y = - g^u_i - B_i' w_{i+1},
+//     consistent for every theta_i (the rows of H_i span the projected
+//     constraints of stage i).  A column-pivoted Householder QR of the
+//     coefficient matrix and back substitution (free coordinates zero) give one
+//     solution, affine in theta_i: theta_{i+1} = Pi_i theta_i + pi_i and
+//     mu_i = Ym_i theta_i + ym_i;
+//   * theta_0 = 0 (lambda_0 = -alpha then has no component normal to X_0);
+//     a forward scan of the affine maps gives every theta_i;
+//   * terminal stationarity (eq. (terminal-stationarity)):
+//       E_N' mu_N = H_N' theta_N + w_N - g^x_N.
+// Under LICQ the multipliers are unique and equal those of the minimum-norm
+// route; otherwise this is one valid representative.  The route is linear in
+// the vector data for fixed matrices, so refinement corrections add up.
+#include "dense.hpp"
+#include "device_util.hpp"
+#include "eclqr.h"
+#include "scratch.hpp"
+
+namespace eclqr {
+
+namespace {
+
+// Reduced dims of the domain normal: r_s = n_s - n-bar_s.
+__device__ __forceinline__ int rdim(const DevEngine& e, int s) { return e.st[s].n - e.nbar[s]; }
+
+// w = T (J z - eta) of stage s into out (LDS, n entries); tmp: LDS, >= n-bar.
+__device__ __forceinline__ void reduced_costate(const DevEngine& e, int64_t s, double* out, double* tmp) {
+  const StageInfo& st = e.st[s];
+  const int n = st.n, nb = e.nbar[s];
+  const RicLayout rl = ric_layout(n, 0);
+  const double* V = slot_ptr(e, SCAN_RIC, st.suf[SCAN_RIC]);
+  const double* J = V + rl.J;
+  const double* eta = V + rl.eta;
+  const double* z = slot_ptr(e, SCAN_FWD, st.suf[SCAN_FWD]);
+  for (int j = ECLQR_TID; j < nb; j += ECLQR_NT) tmp[j] = lane_chain<false>(-eta[j], J + j * nb, 1, z, 1, nb);
+  lds_sync();
+  const Arena ar = arena_layout(n, st.np, st.m, st.k);
+  const double* T = e.arena + st.ws + ar.T;
+  for (int a = ECLQR_TID; a < n; a += ECLQR_NT) out[a] = lane_chain<false>(0.0, T + a * nb, 1, tmp, 1, nb);
+  lds_sync();
+}
+
+}  // namespace
+
+// One wavefront per stage.  LDS: W (maxrow x ldw) | tau | qr scratch | perm |
+// w_i | w_{i+1} | gx | gu | tmp.
+__global__ void __launch_bounds__(kBlock) k_mult_local(DevEngine e, Inputs in, const double* x, const double* u,
+                                                       Tols t, int32_t* status, int maxrow, int ldw) {
+  extern __shared__ double lds[];
+  double* W = lds;
+  double* tau = W + (int64_t)maxrow * ldw;
+  double* qd = tau + 2 * kMaxDim;
+  int* perm = (int*)(qd + 2 * kMaxDim + 8);
+  double* wi = (double*)(perm + 2 * kMaxDim);
+  double* w1 = wi + kMaxDim;
+  double* gx = w1 + kMaxDim;
+  double* gu = gx + kMaxDim;
+  double* tmp = gu + kMaxDim;
+  if (none_live(e)) return;
+  for (int64_t s = blockIdx.x; s < e.S; s += gridDim.x) {
+    const StageInfo st = e.st[s];
+    if (gated(e, st.inst)) continue;
+    const int n = st.n, m = st.terminal ? 0 : st.m, k = st.k;
+    const Arena ar = arena_layout(n, st.np, st.m, st.k);
+    double* base = e.arena + st.ws;
+    const int ri = rdim(e, (int)s);
+    const double* Hi = slot_ptr(e, SCAN_REL, st.suf[SCAN_REL]);  // r_i x (n + 1)
+    reduced_costate(e, s, wi, tmp);
+    for (int a = ECLQR_TID; a < n; a += ECLQR_NT) base[ar.wl + a] = wi[a];
+    // objective gradients, eq. (objective-gradients)
+    const double* Q = in.f[IN_Q] + st.in[IN_Q];
+    const double* xs = x + st.in[IN_q];
+    const double* us = st.terminal ? nullptr : u + st.in[IN_r];
+    const double* Mm = (in.f[IN_M] && !st.terminal) ? in.f[IN_M] + st.in[IN_M] : nullptr;
+    for (int a = ECLQR_TID; a < n; a += ECLQR_NT) {
+      double v = lane_chain<false>(in.f[IN_q][st.in[IN_q] + a], Q + a * n, 1, xs, 1, n);
+      if (Mm) v = lane_chain<false>(v, Mm + a * m, 1, us, 1, m);
+      gx[a] = v;
+    }
+    if (!st.terminal) {
+      const double* R = in.f[IN_R] + st.in[IN_R];
+      for (int b = ECLQR_TID; b < m; b += ECLQR_NT) {
+        double v = lane_chain<false>(in.f[IN_r][st.in[IN_r] + b], R + b * m, 1, us, 1, m);
+        if (Mm) v = lane_chain<false>(v, Mm + b, m, xs, 1, n);
+        gu[b] = v;
+      }
+    }
+    lds_sync();
+    const double* E = in.f[IN_E] + st.in[IN_E];
+    int r1 = 0, n1 = 0;
+    const double* H1 = nullptr;
+    if (!st.terminal) {
+      reduced_costate(e, s + 1, w1, tmp);
+      r1 = rdim(e, (int)s + 1);
+      n1 = e.st[s + 1].n;
+      H1 = slot_ptr(e, SCAN_REL, e.st[s + 1].suf[SCAN_REL]);  // r1 x (n1 + 1)
+    }
+    // W = [coefficients (q columns) | H_i' (r_i columns) | constant], rows: x (n), u (m)
+    const int q = k + r1, rows = n + m, c = q + ri + 1, ld = c | 1;
+    const double* A = st.terminal ? nullptr : in.f[IN_A] + st.in[IN_A];
+    const double* B = st.terminal ? nullptr : in.f[IN_B] + st.in[IN_B];
+    const double* F = st.terminal ? nullptr : in.f[IN_F] + st.in[IN_F];
+    for (int idx = ECLQR_TID; idx < rows * c; idx += ECLQR_NT) {
+      const int row = idx / c, col = idx - (idx / c) * c;
+      const bool xr = row < n;
+      const int a = xr ? row : row - n;
+      double v = 0.0;
+      if (col < k) {
+        v = xr ? E[col * n + a] : F[col * m + a];
+      } else if (col < q) {  // (H_{i+1} A_i)' or (H_{i+1} B_i)'
+        const int l = col - k;
+        v = xr ? lane_chain<false>(0.0, H1 + l * (n1 + 1), 1, A + a, n, n1)
+               : lane_chain<false>(0.0, H1 + l * (n1 + 1), 1, B + a, m, n1);
+      } else if (col < q + ri) {
+        v = xr ? Hi[(col - q) * (n + 1) + a] : 0.0;
+      } else if (xr) {
+        v = wi[a] - gx[a];
+        if (!st.terminal) v = lane_chain<true>(v, A + a, n, w1, 1, n1);
+      } else {
+        v = lane_chain<true>(-gu[a], B + a, m, w1, 1, n1);
+      }
+      W[row * ld + col] = v;
+    }
+    wg_sync();
+    const int rho = wg_qr_colpiv(W, ld, rows, c, 0, q, t.rank, tau, QRScratch{qd, perm});
+    // Per right-hand side (one lane each): consistency -- the part outside
+    // the range of the coefficients, rows rho.. of Q'rhs, against the column
+    // norm (Q is orthogonal) -- then back substitution R11 y = (Q'rhs)[0:rho].
+    bool bad = false;
+    for (int col = q + ECLQR_TID; col < c; col += ECLQR_NT) {
+      double res = 0.0, tot = 0.0;
+      for (int row = 0; row < rows; ++row) {
+        const double v = W[row * ld + col];
+        tot = fma(v, v, tot);
+        if (row >= rho) res = fma(v, v, res);
+      }
+      if (!(sqrt(res) <= t.cons * fmax(1.0, sqrt(tot)))) bad = true;
+      for (int j = rho - 1; j >= 0; --j) {
+        double v = W[j * ld + col];
+        for (int l = j + 1; l < rho; ++l) v = fma(-W[j * ld + l], W[l * ld + col], v);
+        W[j * ld + col] = v / W[j * ld + j];
+      }
+    }
+    if (bad) flag(status, st.inst, ECLQR_RANK_INCONSISTENT);
+    wg_sync();
+    // y[perm[j]] = solution row j (j < rho), free coordinates 0
+    double* Ymu = base + ar.Ym;
+    double* ymu = base + ar.ym;
+    double* Fth = st.terminal ? nullptr : e.theta + e.slot_off[SCAN_FWD * e.nslots + st.elem[SCAN_FWD]];
+    for (int idx = ECLQR_TID; idx < q * (ri + 1); idx += ECLQR_NT) {
+      const int yr = idx / (ri + 1), cc = idx - (idx / (ri + 1)) * (ri + 1);
+      // position of unknown yr among the pivots
+      int pos = -1;
+      for (int j = 0; j < rho; ++j)
+        if (perm[j] == yr) pos = j;
+      const double v = (pos >= 0) ? W[pos * ld + q + cc] : 0.0;
+      if (yr < k) {
+        if (cc < ri) Ymu[yr * n + cc] = v;
+        else ymu[yr] = v;
+      } else {
+        const int l = yr - k;  // theta_{i+1} row: map (r1 x r_i, ld r_i), constant at np * n
+        if (cc < ri) Fth[l * ri + cc] = v;
+        else Fth[(int64_t)st.np * n + l] = v;
+      }
+    }
+    if (st.i == 0) {  // theta_0 = 0: the constant leaf of the scan
+      double* th0 = e.theta + e.slot_off[SCAN_FWD * e.nslots + st.suf[SCAN_FWD]];
+      for (int j = ECLQR_TID; j < ri; j += ECLQR_NT) th0[j] = 0.0;
+    }
+    wg_sync();
+  }
+}
+
+// Forward scan of the theta maps: k_fwd_combine on the theta arena with the
+// normal dims r_s.
+__global__ void __launch_bounds__(kBlock) k_theta_combine(DevEngine e, int64_t first, int64_t ntasks) {
+  if (none_live(e)) return;
+  for (int64_t ti = blockIdx.x; ti < ntasks; ti += gridDim.x) {
+    const int a = e.tasks[3 * (first + ti)];
+    const int bsl = e.tasks[3 * (first + ti) + 1];
+    const int o = e.tasks[3 * (first + ti) + 2];
+    const int so = slot_a(e, 1, a), smid = slot_b(e, 1, a), sin_ = slot_b(e, 1, bsl);
+    if (gated(e, e.st[so].inst)) continue;
+    const int dout = rdim(e, so), dmid = rdim(e, smid), din = (sin_ >= 0) ? rdim(e, sin_) : 0;
+    const int nout = e.st[so].n, nmid = e.st[smid].n, nin = (sin_ >= 0) ? e.st[sin_].n : 0;
+    const double* F1 = e.theta + e.slot_off[SCAN_FWD * e.nslots + a];
+    const double* f1 = F1 + (int64_t)nout * nmid;
+    const double* F2 = e.theta + e.slot_off[SCAN_FWD * e.nslots + bsl];
+    const double* f2 = F2 + (int64_t)nmid * nin;
+    double* Fo = e.theta + e.slot_off[SCAN_FWD * e.nslots + o];
+    double* fo = Fo + (int64_t)nout * nin;
+    if (sin_ >= 0) wg_gemm(Fo, din, F1, dmid, false, F2, din, false, dout, din, dmid, 1.0, 0.0);
+    for (int i = ECLQR_TID; i < dout; i += ECLQR_NT) fo[i] = lane_chain<false>(f1[i], F1 + i * dmid, 1, f2, 1, dmid);
+    wg_sync();
+  }
+}
+
+// lambda_i = w_i + H_i' theta_i, mu_i = Ym_i theta_i + ym_i; written, or added
+// to the values present (refinement corrections).
+__global__ void __launch_bounds__(kBlock) k_mult_final(DevEngine e, double* lam, double* mu, int accumulate) {
+  if (none_live(e)) return;
+  for (int64_t s = blockIdx.x; s < e.S; s += gridDim.x) {
+    const StageInfo st = e.st[s];
+    if (gated(e, st.inst)) continue;
+    const int n = st.n, k = st.k;
+    const Arena ar = arena_layout(n, st.np, st.m, st.k);
+    const double* base = e.arena + st.ws;
+    const int ri = rdim(e, (int)s);
+    const double* Hi = slot_ptr(e, SCAN_REL, st.suf[SCAN_REL]);
+    const double* th = e.theta + e.slot_off[SCAN_FWD * e.nslots + st.suf[SCAN_FWD]];
+    for (int a = ECLQR_TID; a < n; a += ECLQR_NT) {
+      const double v = lane_chain<false>(base[ar.wl + a], Hi + a, n + 1, th, 1, ri);
+      lam[st.in[IN_q] + a] = accumulate ? lam[st.in[IN_q] + a] + v : v;
+    }
+    for (int j = ECLQR_TID; j < k; j += ECLQR_NT) {
+      const double v = lane_chain<false>(base[ar.ym + j], base + ar.Ym + j * n, 1, th, 1, ri);
+      mu[st.in[IN_g] + j] = accumulate ? mu[st.in[IN_g] + j] + v : v;
+    }
+  }
+}
+
+static int g_fast_max_lds = 65536;
+void fast_set_max_lds(int bytes) {
+  g_fast_max_lds = bytes;
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_mult_local), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            bytes);
+}
+size_t mult_local_lds_bytes(int maxrow, int ldw) {
+  return sizeof(double) * ((size_t)maxrow * ldw + 2 * kMaxDim + 2 * kMaxDim + 8 + 5 * kMaxDim) +
+         sizeof(int) * 2 * kMaxDim + 64;
+}
+bool launch_mult_local(const DevEngine& e, const Inputs& in, const double* x, const double* u, Tols t,
+                       int32_t* status, int maxrow, int ldw, hipStream_t s) {
+  const size_t lds = mult_local_lds_bytes(maxrow, ldw);
+  if (lds > (size_t)g_fast_max_lds) return false;
+  hipLaunchKernelGGL(k_mult_local, dim3(e.nblocks), dim3(kBlock), lds, s, e, in, x, u, t, status, maxrow, ldw);
+  return true;
+}
+void launch_theta_combine(const DevEngine& e, int64_t first, int64_t ntasks, hipStream_t s) {
+  if (ntasks <= 0) return;
+  const int grid = (int)(ntasks < e.nblocks ? ntasks : e.nblocks);
+  hipLaunchKernelGGL(k_theta_combine, dim3(grid), dim3(kBlock), 0, s, e, first, ntasks);
+}
+void launch_mult_final(const DevEngine& e, double* lam, double* mu, int accumulate, hipStream_t s) {
+  hipLaunchKernelGGL(k_mult_final, dim3(e.nblocks), dim3(kBlock), 0, s, e, lam, mu, accumulate);
+}
+
+}  // namespace eclqr

@@ -21,6 +21,7 @@ struct DevEngine {
   int32_t* mbar;              // reduced input dim per stage
   double* arena;              // stage arenas
   double* scan[SCAN_COUNT];   // slot arenas
+  double* theta;              // fast multiplier route: theta maps, laid out like the forward scan
   double* resid;              // [4 * S]
   const int64_t* rel_log_off; // per slot, -1 = none
   const int64_t* ric_log_off;
@@ -137,6 +138,14 @@ void launch_finalize(const DevEngine& p, const int32_t* status, double* x, doubl
                      hipStream_t s);
 void launch_kkt_residual(const DevEngine& p, const Inputs& in, const double* x, const double* u, const double* lam,
                          const double* mu, const int64_t* sbase, double* out, hipStream_t s);
+// factor-reusing multipliers (reuse the primal pass's scans; run right after it)
+void fast_set_max_lds(int bytes);
+size_t mult_local_lds_bytes(int maxrow, int ldw);
+// false (nothing launched) when the tile exceeds the device's LDS
+bool launch_mult_local(const DevEngine& e, const Inputs& in, const double* x, const double* u, Tols t,
+                       int32_t* status, int maxrow, int ldw, hipStream_t s);
+void launch_theta_combine(const DevEngine& e, int64_t first, int64_t ntasks, hipStream_t s);
+void launch_mult_final(const DevEngine& e, double* lam, double* mu, int accumulate, hipStream_t s);
 void launch_grad_assemble(const DevEngine& p, const double* x, const double* u, const double* lam, const double* mu,
                           const double* ax, const double* au, const double* al, const double* am, const GradPtrs& g,
                           hipStream_t s);

@@ -340,6 +340,8 @@ std::string Engine::build(const eclqr_dims* d) {
   base_maxp = 1;
   base_ldw = 1;
   elim_maxq = 1;
+  fast_rows = 1;
+  fast_ldw = 1;
   scratch_per_block = 64;
   for (int64_t s = 0; s < S; ++s) {
     const StageInfo& x = st[s];
@@ -351,6 +353,9 @@ std::string Engine::build(const eclqr_dims* d) {
       base_ldw = std::max(base_ldw, x.m + x.n + x.np + 1);
       elim_maxq = std::max(elim_maxq, x.k + x.np);
     }
+    // factor-reusing multipliers: (x, u) rows; mu, theta', H' and constant columns
+    fast_rows = std::max(fast_rows, x.n + (x.terminal ? 0 : x.m));
+    fast_ldw = std::max(fast_ldw, (x.k + x.np + x.n + 1) | 1);
     scratch_per_block = std::max(scratch_per_block, elim_scratch(x.n, x.np, x.m, x.k));
     scratch_per_block = std::max(scratch_per_block, gains_scratch(x.n, x.np, x.m));
   }
@@ -381,6 +386,9 @@ std::string Engine::build(const eclqr_dims* d) {
     o_scan[k] = o;
     o = align256(o + sizeof(double) * scan_arena[k]);
   }
+  // affine maps of the fast multiplier route, laid out like the forward scan
+  o_theta = o;
+  o = align256(o + sizeof(double) * std::max<int64_t>(1, scan_arena[SCAN_FWD]));
   bytes = o;
   return "";
 }

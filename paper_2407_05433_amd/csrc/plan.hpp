@@ -57,13 +57,15 @@ struct Engine {
   int64_t arena_total = 0;  // stage arena doubles
   int32_t maxn = 0, maxm = 0, maxk = 0;
   int32_t base_maxp = 0, base_ldw = 0, elim_maxq = 0;
+  int32_t fast_rows = 0, fast_ldw = 0;  // LDS tile of the factor-reusing multiplier kernel
   int32_t nblocks = 0;             // grid of the stage-parallel kernels
   int64_t scratch_per_block = 0;   // doubles
 
   // workspace map (byte offsets from the engine's base)
   size_t o_stage = 0, o_slot_off = 0, o_slot_na = 0, o_slot_nb = 0, o_slot_cap = 0, o_slot_rows = 0,
          o_tasks = 0, o_nbar = 0, o_mbar = 0, o_arena = 0, o_scan[SCAN_COUNT] = {0, 0, 0}, o_resid = 0,
-         o_sbase = 0, o_scratch = 0, o_rel_log_off = 0, o_ric_log_off = 0, o_rel_log = 0, o_ric_log = 0;
+         o_sbase = 0, o_scratch = 0, o_rel_log_off = 0, o_ric_log_off = 0, o_rel_log = 0, o_ric_log = 0,
+         o_theta = 0;
   size_t bytes = 0;
 
   std::string build(const eclqr_dims* d);
