@@ -214,7 +214,11 @@ typedef struct {
                              * stacked system in registers instead of LDS */
   int32_t stage_lds;      /* stage eliminations and feedback gains keep their working arrays in LDS when these
                              need at most 32 KiB per workgroup (1, default), else in global scratch (0) */
-  int32_t reserved[2];
+  int32_t overlap_dual;   /* with the minimum-norm multipliers, the reversed-time problem is factored (matrix data
+                           * only) on a second stream while the primal pass runs, and its vector-only replay at
+                           * the primal solution gives the multipliers (1, default); 0: one stream, full pass after
+                           * the primal pass */
+  int32_t reserved[1];
 } eclqr_tuning;
 
 /* Time the caller's problem under alternative launch configurations

@@ -26,6 +26,9 @@ void release_graph(Plan& p) {
 Plan::~Plan() {
   release_graph(*this);
   if (capture_stream) (void)hipStreamDestroy(reinterpret_cast<hipStream_t>(capture_stream));
+  if (aux_stream) (void)hipStreamDestroy(reinterpret_cast<hipStream_t>(aux_stream));
+  if (ev_fork) (void)hipEventDestroy(reinterpret_cast<hipEvent_t>(ev_fork));
+  if (ev_join) (void)hipEventDestroy(reinterpret_cast<hipEvent_t>(ev_join));
   for (void* e : event_pool) (void)hipEventDestroy(reinterpret_cast<hipEvent_t>(e));
 }
 
@@ -173,6 +176,16 @@ eclqr_status bind(Plan& p, void* ws, hipStream_t s) {
     lqr_set_max_lds(lds);
     replay_set_max_lds(lds);
     fast_set_max_lds(lds);
+  }
+  if (!p.aux_stream) {
+    hipStream_t a = nullptr;
+    HIP_OK(hipStreamCreateWithFlags(&a, hipStreamNonBlocking));
+    p.aux_stream = reinterpret_cast<void*>(a);
+    hipEvent_t f = nullptr, j = nullptr;
+    HIP_OK(hipEventCreateWithFlags(&f, hipEventDisableTiming));
+    HIP_OK(hipEventCreateWithFlags(&j, hipEventDisableTiming));
+    p.ev_fork = reinterpret_cast<void*>(f);
+    p.ev_join = reinterpret_cast<void*>(j);
   }
   eclqr_status st = upload_engine(p.primal, ws, p.o_primal, s);
   if (st != ECLQR_SUCCESS) return st;
@@ -397,7 +410,7 @@ constexpr int32_t kDualStructural = ECLQR_CAPACITY | ECLQR_NOT_CONVEX | ECLQR_IN
 //   4. the backward error of the returned point is recomputed; a refined
 //      instance whose error exceeds dual_cons_tol reports a multiplier failure.
 eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, double* u, double* lam, double* mu,
-                       int32_t* status, bool want_mult, bool replay, hipStream_t s) {
+                       int32_t* status, bool want_mult, bool replay, hipStream_t s, hipEvent_t dual_join = nullptr) {
   const Tols tp{p.opt.rank_tol, p.opt.cons_tol, 1};
   const int32_t B = p.primal.B;
   {
@@ -412,12 +425,15 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
   if (st != ECLQR_SUCCESS) return st;
   if (!want_mult) return ECLQR_SUCCESS;
   const bool fast = p.opt.multipliers == 2;
-  if (replay || fast) {
+  if (dual_join) {
+    // the reversed-time problem was factored on the second stream
+    HIP_OK(hipStreamWaitEvent(s, dual_join, 0));
+  } else if (replay || fast) {
     Timed tm(ECLQR_K_REFINE_IO, s);
     launch_fill_i32(v.dstatus, 0, B, s);
   }
   st = fast ? fast_multipliers(p, v, in, x, u, lam, mu, v.dstatus, false, s)
-            : multipliers(p, v, in, x, u, lam, mu, s, replay);
+            : multipliers(p, v, in, x, u, lam, mu, s, replay || dual_join != nullptr);
   if (st != ECLQR_SUCCESS) return st;
   const int nref = p.opt.refine;
   if (nref == 0) {
@@ -472,12 +488,52 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
 
 bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7) == 0; }
 
+// Factorization of the reversed-time problem on its own (matrix data only,
+// zero vectors), on stream s2: every rank decision, factor log and
+// matrix-dependent outcome bit of its full pass, ready for the vector-only
+// replay at the primal solution.  Independent of the primal pass, so the two
+// run side by side.  Runs every instance (no refinement gate).
+eclqr_status dual_prefactor(Plan& p, const Views& v, const Inputs& in, hipStream_t s2) {
+  const Tols td{p.opt.rank_tol, p.opt.dual_cons_tol, 0};
+  {
+    Timed tm(ECLQR_K_MULTIPLIER_IO, s2);
+    launch_dual_matrices(v.P, in, v.D, v.dp, s2);
+    int64_t nz = 1;
+    for (int f : {ECLQR_F_q, ECLQR_F_r, ECLQR_F_c, ECLQR_F_g, ECLQR_F_x0}) nz = std::max(nz, p.dual.total[f]);
+    launch_fill(const_cast<double*>(v.zero), 0.0, nz, s2);
+    launch_fill_i32(v.dstatus, 0, p.primal.B, s2);
+  }
+  Inputs din = dual_inputs(v);
+  for (int f : {IN_q, IN_r, IN_c, IN_g}) din.f[f] = v.zero;
+  din.x0 = v.zero;
+  DevEngine d = v.D;
+  d.gate = nullptr;
+  d.live = nullptr;
+  return run_engine(p.dual, d, din, v.dx, v.du, v.dstatus, td, s2);
+}
+
 // The whole launch sequence of one solve.
 eclqr_status solve_sequence(Plan& p, const Views& v, const Inputs& in, eclqr_solution* sol, bool want, hipStream_t s) {
   const Engine& E = p.primal;
   launch_fill_i32(sol->status, 0, E.B, s);
-  if (want && p.opt.multipliers == 1) launch_dual_matrices(v.P, in, v.D, v.dp, s);
-  eclqr_status st = solve_all(p, v, in, sol->x, sol->u, sol->lam, sol->mu, sol->status, want, false, s);
+  hipEvent_t join = nullptr;
+  if (want && p.opt.multipliers == 1) {
+    if (p.overlap_dual) {
+      hipStream_t s2 = reinterpret_cast<hipStream_t>(p.aux_stream);
+      HIP_OK(hipEventRecord(reinterpret_cast<hipEvent_t>(p.ev_fork), s));
+      HIP_OK(hipStreamWaitEvent(s2, reinterpret_cast<hipEvent_t>(p.ev_fork), 0));
+      const eclqr_status pst = dual_prefactor(p, v, in, s2);
+      join = reinterpret_cast<hipEvent_t>(p.ev_join);
+      HIP_OK(hipEventRecord(join, s2));
+      if (pst != ECLQR_SUCCESS) {
+        HIP_OK(hipStreamWaitEvent(s, join, 0));
+        return pst;
+      }
+    } else {
+      launch_dual_matrices(v.P, in, v.D, v.dp, s);
+    }
+  }
+  eclqr_status st = solve_all(p, v, in, sol->x, sol->u, sol->lam, sol->mu, sol->status, want, false, s, join);
   if (st != ECLQR_SUCCESS) return st;
   launch_finalize(v.P, sol->status, sol->x, sol->u, want ? sol->lam : nullptr, want ? sol->mu : nullptr, s);
   HIP_OK(hipGetLastError());
@@ -826,6 +882,7 @@ eclqr_status eclqr_plan_get_tuning(const eclqr_plan* plan, eclqr_tuning* out) {
   out->grid_divisor = p.grid_divisor;
   out->register_compose = p.reg_compose;
   out->stage_lds = p.stage_lds;
+  out->overlap_dual = p.overlap_dual;
   out->ms_per_solve = p.tuned_ms;
   return ECLQR_SUCCESS;
 }
@@ -841,6 +898,7 @@ eclqr_status eclqr_plan_set_tuning(eclqr_plan* plan, const eclqr_tuning* t) {
   p.grid_divisor = t->grid_divisor;
   p.reg_compose = t->register_compose != 0;
   p.stage_lds = t->stage_lds != 0;
+  p.overlap_dual = t->overlap_dual != 0;
   release_graph(p);
   return ECLQR_SUCCESS;
 }
@@ -881,7 +939,8 @@ eclqr_status eclqr_plan_autotune(eclqr_plan* plan, const eclqr_problem* prob, ec
   int32_t graph = p.opt.use_graph;
   Knob knobs[] = {{&p.reg_compose, p.reg_compose ? 0 : 1}, {&p.stage_lds, p.stage_lds ? 0 : 1},
                   {&p.level_buckets, p.level_buckets ? 0 : 1}, {&p.pool_lds, p.pool_lds == 2 ? 1 : 2},
-                  {&p.grid_divisor, p.grid_divisor == 1 ? 4 : 1}, {&graph, graph ? 0 : 1}};
+                  {&p.grid_divisor, p.grid_divisor == 1 ? 4 : 1}, {&graph, graph ? 0 : 1},
+                  {&p.overlap_dual, p.overlap_dual ? 0 : 1}};
   for (Knob& k : knobs) {
     if (st != ECLQR_SUCCESS) break;
     const int32_t old = *k.v;

@@ -273,6 +273,29 @@ __global__ void __launch_bounds__(kBlock) k_refine_decide(DevEngine p, const int
   }
 }
 
+// v += sum_l a[l sa] b[l sb] and mag += sum_l |a[l sa] b[l sb]| in ascending l
+// (the same sums as a plain loop), with the loads of each batch of 8 issued
+// before its additions.
+__device__ __forceinline__ void acc_terms(const double* a, int sa, const double* b, int sb, int n, double& v,
+                                          double& mag) {
+  int l = 0;
+  for (; l + 8 <= n; l += 8) {
+    double t[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) t[j] = a[(l + j) * sa] * b[(l + j) * sb];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      v += t[j];
+      mag += fabs(t[j]);
+    }
+  }
+  for (; l < n; ++l) {
+    const double t = a[l * sa] * b[l * sb];
+    v += t;
+    mag += fabs(t);
+  }
+}
+
 // Componentwise backward error of the KKT system at (x, u, lambda, mu):
 // max over rows of |residual| / (sum of |terms|), over stationarity in x and
 // u, dynamics, equality rows and the initial condition.  One wavefront per
@@ -311,84 +334,33 @@ __global__ void __launch_bounds__(kBlock) k_backward_error(DevEngine p, Inputs i
     };
     for (int i = lane; i < n; i += 64) {  // stationarity in x_i
       double v = q[i] - ls[i], a = fabs(q[i]) + fabs(ls[i]);
-      for (int l = 0; l < n; ++l) {
-        const double t = Q[i * n + l] * xs[l];
-        v += t;
-        a += fabs(t);
-      }
-      for (int l = 0; l < k; ++l) {
-        const double t = E[l * n + i] * ms[l];
-        v += t;
-        a += fabs(t);
-      }
+      acc_terms(Q + i * n, 1, xs, 1, n, v, a);
+      acc_terms(E + i, n, ms, 1, k, v, a);
       if (!term) {
-        if (M)
-          for (int l = 0; l < m; ++l) {
-            const double t = M[i * m + l] * us[l];
-            v += t;
-            a += fabs(t);
-          }
-        for (int l = 0; l < np; ++l) {
-          const double t = A[l * n + i] * l1[l];
-          v += t;
-          a += fabs(t);
-        }
+        if (M) acc_terms(M + i * m, 1, us, 1, m, v, a);
+        acc_terms(A + i, n, l1, 1, np, v, a);
       }
       acc(v, a);
     }
     for (int i = lane; i < k; i += 64) {  // equality rows
       double v = g[i], a = fabs(g[i]);
-      for (int l = 0; l < n; ++l) {
-        const double t = E[i * n + l] * xs[l];
-        v += t;
-        a += fabs(t);
-      }
-      if (!term)
-        for (int l = 0; l < m; ++l) {
-          const double t = F[i * m + l] * us[l];
-          v += t;
-          a += fabs(t);
-        }
+      acc_terms(E + i * n, 1, xs, 1, n, v, a);
+      if (!term) acc_terms(F + i * m, 1, us, 1, m, v, a);
       acc(v, a);
     }
     if (!term) {
       for (int i = lane; i < m; i += 64) {  // stationarity in u_i
         double v = r[i], a = fabs(r[i]);
-        for (int l = 0; l < m; ++l) {
-          const double t = R[i * m + l] * us[l];
-          v += t;
-          a += fabs(t);
-        }
-        if (M)
-          for (int l = 0; l < n; ++l) {
-            const double t = M[l * m + i] * xs[l];
-            v += t;
-            a += fabs(t);
-          }
-        for (int l = 0; l < np; ++l) {
-          const double t = B[l * m + i] * l1[l];
-          v += t;
-          a += fabs(t);
-        }
-        for (int l = 0; l < k; ++l) {
-          const double t = F[l * m + i] * ms[l];
-          v += t;
-          a += fabs(t);
-        }
+        acc_terms(R + i * m, 1, us, 1, m, v, a);
+        if (M) acc_terms(M + i, m, xs, 1, n, v, a);
+        acc_terms(B + i, m, l1, 1, np, v, a);
+        acc_terms(F + i, m, ms, 1, k, v, a);
         acc(v, a);
       }
       for (int i = lane; i < np; i += 64) {  // dynamics
         double v = c[i] - x1[i], a = fabs(c[i]) + fabs(x1[i]);
-        for (int l = 0; l < n; ++l) {
-          const double t = A[i * n + l] * xs[l];
-          v += t;
-          a += fabs(t);
-        }
-        for (int l = 0; l < m; ++l) {
-          const double t = B[i * m + l] * us[l];
-          v += t;
-          a += fabs(t);
-        }
+        acc_terms(A + i * n, 1, xs, 1, n, v, a);
+        acc_terms(B + i * m, 1, us, 1, m, v, a);
         acc(v, a);
       }
     }
@@ -674,8 +646,7 @@ void launch_refine_decide(const DevEngine& p, const int64_t* sbase, const double
 }
 void launch_backward_error(const DevEngine& p, const Inputs& in, const double* x, const double* u, const double* lam,
                            const double* mu, unsigned long long* omega, hipStream_t s) {
-  const int64_t g = std::min<int64_t>(4096, std::max<int64_t>(1, (p.S + 3) / 4));
-  hipLaunchKernelGGL(k_backward_error, dim3((unsigned)g), dim3(kBlock), 0, s, p, in, x, u, lam, mu, omega);
+  hipLaunchKernelGGL(k_backward_error, dim3(p.nblocks), dim3(kBlock), 0, s, p, in, x, u, lam, mu, omega);
 }
 void launch_accept(const unsigned long long* omega, const int32_t* dstatus, double tol, int32_t* gate, int32_t B,
                    hipStream_t s) {

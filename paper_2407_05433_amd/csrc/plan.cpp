@@ -443,7 +443,9 @@ std::string build_plan(Plan& p, const eclqr_dims* d, const eclqr_options* opt) {
   p.o_live = o; o = align256(o + sizeof(int32_t));
   p.o_omega = o; o = align256(o + sizeof(double) * std::max<int32_t>(1, P.B));
   {
-    const int64_t nz = std::max<int64_t>(1, std::max(P.total[ECLQR_F_c], std::max(P.total[ECLQR_F_g], P.total[ECLQR_F_x0])));
+    int64_t nz = std::max<int64_t>(1, std::max(P.total[ECLQR_F_c], std::max(P.total[ECLQR_F_g], P.total[ECLQR_F_x0])));
+    // the overlapped reversed-time factorization reads zero vectors
+    for (int f : {ECLQR_F_q, ECLQR_F_r, ECLQR_F_c, ECLQR_F_g, ECLQR_F_x0}) nz = std::max(nz, p.dual.total[f]);
     p.o_zero = o; o = align256(o + sizeof(double) * nz);
   }
   p.bytes = o;

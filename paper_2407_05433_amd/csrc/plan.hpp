@@ -97,9 +97,13 @@ struct Plan {
   int32_t pool_lds = 2;       // value-function combine LDS mode (0 global pool, 1 LDS pool, 2 all in LDS)
   int32_t grid_divisor = 1;   // grid of the stage-parallel kernels = nblocks / divisor
   int32_t reg_compose = 1;    // register-resident relation compositions where they fit
+  int32_t overlap_dual = 1;   // factor the reversed-time problem on a second stream beside the primal pass
   double tuned_ms = 0.0;
   void* graph_exec = nullptr;
   void* capture_stream = nullptr;  // plan-owned stream the sequence is captured on
+  void* aux_stream = nullptr;      // plan-owned stream of the overlapped reversed-time factorization
+  void* ev_fork = nullptr;         // fork / join events between the two streams
+  void* ev_join = nullptr;
   std::vector<const void*> graph_key;
   ~Plan();
   // profiler: recorded (class, start, stop) event triples

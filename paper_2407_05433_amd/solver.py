@@ -329,7 +329,7 @@ def unpack(plan: Plan, flat: torch.Tensor, field: str, problems) -> List[List[np
 def _tuning_dict(t: _lib.Tuning) -> Dict[str, float]:
     return {"use_graph": int(t.use_graph), "level_buckets": int(t.level_buckets), "pool_in_lds": int(t.pool_in_lds),
             "grid_divisor": int(t.grid_divisor), "register_compose": int(t.register_compose),
-            "stage_lds": int(t.stage_lds), "ms_per_solve": float(t.ms_per_solve)}
+            "stage_lds": int(t.stage_lds), "overlap_dual": int(t.overlap_dual), "ms_per_solve": float(t.ms_per_solve)}
 
 
 def autotune(plan: Plan, data: Dict[str, torch.Tensor], ws: torch.Tensor, out: Optional[Solution] = None) -> Dict:

@@ -295,6 +295,7 @@ def test_autotune_keeps_results():
     tuned = ecl.autotune(plan, data, ws)
     assert tuned["ms_per_solve"] > 0
     for cfg in ({"level_buckets": 0}, {"pool_in_lds": 0}, {"pool_in_lds": 1}, {"stage_lds": 0}, {"grid_divisor": 4},
+                {"overlap_dual": 0},
                 {"use_graph": 1},
                 {"register_compose": 0}, tuned):
         full = dict(base)
@@ -303,10 +304,11 @@ def test_autotune_keeps_results():
         sol = ecl.solve(plan, data, ws)
         torch.cuda.synchronize()
         for f in ("x", "u", "lam", "mu", "status"):
-            if full["register_compose"] == base["register_compose"]:
+            if full["register_compose"] == base["register_compose"] and full["overlap_dual"] == base["overlap_dual"]:
                 assert torch.equal(getattr(sol, f), ref[f]), (cfg, f)
             else:
-                # the LDS and register compositions differ in rounding only
+                # the LDS and register compositions differ in rounding only,
+                # and so do the full and the replayed reversed-time passes
                 a, b = getattr(sol, f).double(), ref[f].double()
                 err = float((a - b).norm() / max(float(b.norm()), 1e-300))
                 assert err <= 1e-8, (cfg, f, err)
