@@ -191,6 +191,7 @@ enum {
   ECLQR_K_REFINE_IO, ECLQR_K_OTHER,
   ECLQR_K_REPLAY, /* every kernel of a vector-only pass (recovery included) */
   ECLQR_K_MULT_FAST, /* the factor-reusing multiplier route (multipliers = 2) */
+  ECLQR_K_MULT_THETA, /* local systems, initial state and read-out of the theta-LQR minimum-norm route */
   ECLQR_NUM_KERNEL_CLASSES
 };
 
@@ -218,7 +219,13 @@ typedef struct {
                            * only) on a second stream while the primal pass runs, and its vector-only replay at
                            * the primal solution gives the multipliers (1, default); 0: one stream, full pass after
                            * the primal pass */
-  int32_t reserved[1];
+  int32_t multiplier_route; /* how the minimum-norm multipliers (multipliers = 1) are computed: 1 (default where
+                           * the stage input capacity k_i + n_{i+1} <= 64): from the primal pass's domains and
+                           * scans, as an unconstrained LQR over the normal coordinates theta_i of the domains
+                           * (minimum-norm local systems, value-function scan, gains, forward scan); 0: the
+                           * reversed-time stationarity problem solved by the full engine.  Both give the
+                           * minimum-norm multipliers; they differ in rounding.  eclqr_backward needs the
+                           * workspace of a solve made with the same route. */
 } eclqr_tuning;
 
 /* Time the caller's problem under alternative launch configurations
@@ -244,7 +251,9 @@ const char* eclqr_kernel_class_name(int32_t k);
 /* Reduced dimensions n-bar_i, m-bar_i (Section V) computed by the last solve
  * in workspace ws, copied to host arrays of length sum_b (N_b + 1) (m-bar of a
  * terminal stage is 0).  which = 0: the problem; 1: the reversed-time
- * stationarity problem of the multipliers.  Synchronises the device. */
+ * stationarity problem of the multipliers; 2: the theta LQR of the
+ * minimum-norm route (normal dims r_i, free dims of the local systems; plans
+ * without it return ECLQR_INVALID_ARGUMENT).  Synchronises the device. */
 eclqr_status eclqr_plan_reduced_dims(const eclqr_plan* plan, const void* ws, int32_t which, int32_t* nbar,
                                      int32_t* mbar);
 

@@ -14,7 +14,7 @@ NUM_FIELDS = 12
 FIELDS = ("Q", "q", "R", "r", "M", "A", "B", "c", "E", "F", "g", "x0")
 FIELD_INDEX = {f: i for i, f in enumerate(FIELDS)}
 
-NUM_KERNEL_CLASSES = 14
+NUM_KERNEL_CLASSES = 15
 
 STATUS_BITS = {
     1: "infeasible_suffix",
@@ -41,7 +41,7 @@ class Options(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("use_graph", C.c_int32), ("level_buckets", C.c_int32), ("pool_in_lds", C.c_int32),
                 ("grid_divisor", C.c_int32), ("ms_per_solve", C.c_double), ("register_compose", C.c_int32),
-                ("stage_lds", C.c_int32), ("overlap_dual", C.c_int32), ("reserved", C.c_int32 * 1)]
+                ("stage_lds", C.c_int32), ("overlap_dual", C.c_int32), ("multiplier_route", C.c_int32)]
 
 
 class ProblemPtrs(C.Structure):

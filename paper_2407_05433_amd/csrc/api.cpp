@@ -176,6 +176,7 @@ eclqr_status bind(Plan& p, void* ws, hipStream_t s) {
     lqr_set_max_lds(lds);
     replay_set_max_lds(lds);
     fast_set_max_lds(lds);
+    theta_set_max_lds(lds);
   }
   if (!p.aux_stream) {
     hipStream_t a = nullptr;
@@ -191,6 +192,11 @@ eclqr_status bind(Plan& p, void* ws, hipStream_t s) {
   if (st != ECLQR_SUCCESS) return st;
   st = upload_engine(p.dual, ws, p.o_dual, s);
   if (st != ECLQR_SUCCESS) return st;
+  if (p.theta_ok) {
+    st = upload_engine(p.theta, ws, p.o_theta_eng, s);
+    if (st != ECLQR_SUCCESS) return st;
+  }
+  p.ws_route = -1;
   launch_fill_i32(reinterpret_cast<int32_t*>(static_cast<char*>(ws) + p.o_live), 1, 1, s);
   p.bound_ws = ws;
   p.bound_device = dev;
@@ -290,7 +296,7 @@ Inputs inputs_of(const eclqr_problem* p) {
 }
 
 struct Views {
-  DevEngine P, D;
+  DevEngine P, D, T;
   DualPtrs dp;
   CorrPtrs cp;
   double *dx, *du;
@@ -314,6 +320,7 @@ Views views(Plan& p, void* ws) {
   Views v{};
   v.P = dev_engine(p.primal, ws, p.o_primal);
   v.D = dev_engine(p.dual, ws, p.o_dual);
+  if (p.theta_ok) v.T = dev_engine(p.theta, ws, p.o_theta_eng);
   for (int f = 0; f < IN_COUNT; ++f) v.dp.f[f] = at<double>(ws, p.o_dprob[f]);
   v.dp.f[IN_M] = nullptr;
   v.dp.pbase = dev_sbase(p.primal, ws, p.o_primal);
@@ -341,6 +348,8 @@ Views views(Plan& p, void* ws) {
   v.live = at<int32_t>(ws, p.o_live);
   v.P.live = v.live;
   v.D.live = v.live;
+  v.T.gate = v.gate;
+  v.T.live = v.live;
   return v;
 }
 
@@ -396,6 +405,62 @@ eclqr_status fast_multipliers(Plan& p, const Views& v, const Inputs& in, const d
   return ECLQR_SUCCESS;
 }
 
+// Minimum-norm multipliers of the problem `in` at its solution (x, u) through
+// the theta LQR: local minimum-norm systems from the primal pass's domains and
+// scans, then the value-function scan, gains and forward scan of the theta
+// engine (full: factorizations logged; else replayed from the last full
+// pass), then lambda and mu (added to lam, mu when acc).  Outcome bits of the
+// local systems and gains go to `status` (null: not checked).
+eclqr_status theta_multipliers(Plan& p, const Views& v, const Inputs& in, const double* x, const double* u,
+                               double* lam, double* mu, int32_t* status, bool full, bool acc, hipStream_t s) {
+  const Engine& T = p.theta;
+  const Tols td{p.opt.rank_tol, p.opt.dual_cons_tol, 0};
+  {
+    Timed tm(ECLQR_K_MULT_THETA, s);
+    if (!launch_theta_local(v.P, v.T, in, x, u, td, status, p.th_q, p.th_ldw, p.th_r, s))
+      return fail(ECLQR_UNSUPPORTED, "stage too large for the LDS tile of the minimum-norm local systems");
+  }
+  for (int l = 0; l < 2 * T.D; ++l) {
+    if (T.lvl_count[l] == 0) continue;
+    if (full) {
+      Timed tm(ECLQR_K_RIC_COMBINE, s);
+      launch_ric_combine(v.T, T.lvl_begin[l], T.lvl_count[l], status, std::max(1, T.lvl_dim[l]), s);
+    } else {
+      Timed tm(ECLQR_K_REPLAY, s);
+      launch_ric_combine_vec(v.T, T.lvl_begin[l], T.lvl_count[l], std::max(1, T.lvl_dim[l]), s);
+    }
+  }
+  if (full) {
+    Timed tm(ECLQR_K_GAINS, s);
+    launch_gains(v.T, status, std::max(1, T.maxm), std::max(1, T.maxn), s);
+  } else {
+    Timed tm(ECLQR_K_REPLAY, s);
+    launch_gains_vec(v.T, s);
+  }
+  {
+    Timed tm(ECLQR_K_MULT_THETA, s);
+    launch_theta_init(v.T, s);
+  }
+  for (int l = 0; l < 2 * T.D; ++l) {
+    if (T.lvl_count[l] == 0) continue;
+    if (full) {
+      Timed tm(ECLQR_K_FWD_COMBINE, s);
+      launch_fwd_combine(v.T, T.lvl_begin[l], T.lvl_count[l], s);
+    } else {
+      Timed tm(ECLQR_K_REPLAY, s);
+      launch_fwd_combine_vec(v.T, T.lvl_begin[l], T.lvl_count[l], s);
+    }
+  }
+  {
+    Timed tm(ECLQR_K_MULT_THETA, s);
+    launch_theta_final(v.P, v.T, lam, mu, acc ? 1 : 0, s);
+  }
+  HIP_OK(hipGetLastError());
+  return ECLQR_SUCCESS;
+}
+
+bool theta_route(const Plan& p) { return p.opt.multipliers == 1 && p.theta_ok && p.mult_route == 1; }
+
 constexpr int32_t kDualStructural = ECLQR_CAPACITY | ECLQR_NOT_CONVEX | ECLQR_INVALID_INPUT;
 
 // Full solve of the problem `in`: primal, multipliers, refinement.  With
@@ -425,15 +490,20 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
   if (st != ECLQR_SUCCESS) return st;
   if (!want_mult) return ECLQR_SUCCESS;
   const bool fast = p.opt.multipliers == 2;
+  const bool theta = theta_route(p);
   if (dual_join) {
     // the reversed-time problem was factored on the second stream
     HIP_OK(hipStreamWaitEvent(s, dual_join, 0));
-  } else if (replay || fast) {
+  } else if (replay || fast || theta) {
     Timed tm(ECLQR_K_REFINE_IO, s);
     launch_fill_i32(v.dstatus, 0, B, s);
   }
-  st = fast ? fast_multipliers(p, v, in, x, u, lam, mu, v.dstatus, false, s)
-            : multipliers(p, v, in, x, u, lam, mu, s, replay || dual_join != nullptr);
+  if (fast)
+    st = fast_multipliers(p, v, in, x, u, lam, mu, v.dstatus, false, s);
+  else if (theta)
+    st = theta_multipliers(p, v, in, x, u, lam, mu, v.dstatus, !replay, false, s);
+  else
+    st = multipliers(p, v, in, x, u, lam, mu, s, replay || dual_join != nullptr);
   if (st != ECLQR_SUCCESS) return st;
   const int nref = p.opt.refine;
   if (nref == 0) {
@@ -464,13 +534,16 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
     if (fast) {  // multipliers of the correction problem (the route is linear in the vectors)
       st = fast_multipliers(p, v, cin, v.cx, v.cu, lam, mu, nullptr, true, s);
       if (st != ECLQR_SUCCESS) return st;
+    } else if (theta) {  // minimum-norm multipliers of the correction problem (linear in the vectors)
+      st = theta_multipliers(p, v, cin, v.cx, v.cu, lam, mu, nullptr, false, true, s);
+      if (st != ECLQR_SUCCESS) return st;
     }
     {
       Timed tm(ECLQR_K_REFINE_IO, s);
       launch_refine_update(v.P, x, u, v.cx, v.cu, v.rnorm, s);
       launch_refine_decide(v.P, v.psbase, v.rnorm, p.opt.refine_tol, it + 1 == nref, v.gate, v.rsteps, s);
     }
-    if (!fast) {
+    if (!fast && !theta) {
       st = multipliers(p, v, in, x, u, lam, mu, s, true);
       if (st != ECLQR_SUCCESS) return st;
     }
@@ -517,7 +590,7 @@ eclqr_status solve_sequence(Plan& p, const Views& v, const Inputs& in, eclqr_sol
   const Engine& E = p.primal;
   launch_fill_i32(sol->status, 0, E.B, s);
   hipEvent_t join = nullptr;
-  if (want && p.opt.multipliers == 1) {
+  if (want && p.opt.multipliers == 1 && !theta_route(p)) {
     if (p.overlap_dual) {
       hipStream_t s2 = reinterpret_cast<hipStream_t>(p.aux_stream);
       HIP_OK(hipEventRecord(reinterpret_cast<hipEvent_t>(p.ev_fork), s));
@@ -666,6 +739,8 @@ eclqr_status eclqr_solve(eclqr_plan* plan, const eclqr_problem* prob, eclqr_solu
   g_prof = &p;
   if (p.opt.multipliers == 2 && mult_local_lds_bytes(p.primal.fast_rows, p.primal.fast_ldw) > (size_t)g_max_lds)
     return fail(ECLQR_UNSUPPORTED, "stage too large for the LDS tile of the factor-reusing multipliers");
+  if (theta_route(p) && theta_local_lds_bytes(p.th_q, p.th_ldw, p.th_r) > (size_t)g_max_lds) p.mult_route = 0;
+  p.ws_route = want ? (p.opt.multipliers == 2 ? 2 : (theta_route(p) ? 1 : 0)) : -1;
   Views v = views(p, ws);
   Inputs in = inputs_of(prob);
   if (!p.opt.use_graph || p.profiling) return solve_sequence(p, v, in, sol, want, s);
@@ -713,6 +788,10 @@ eclqr_status eclqr_backward(eclqr_plan* plan, const eclqr_problem* prob, const e
   hipStream_t s = static_cast<hipStream_t>(stream);
   eclqr_status st = bind(p, ws, s);
   if (st != ECLQR_SUCCESS) return st;
+  const int route = p.opt.multipliers == 2 ? 2 : (theta_route(p) ? 1 : 0);
+  if (p.ws_route != route)
+    return fail(ECLQR_INVALID_ARGUMENT,
+                "the workspace does not hold the factorizations of a solve with this plan's multiplier route");
   g_prof = &p;
   Views v = views(p, ws);
   const Engine& E = p.primal;
@@ -789,7 +868,8 @@ eclqr_status eclqr_plan_profile(eclqr_plan* plan, double* ms, int64_t* launches,
 const char* eclqr_kernel_class_name(int32_t k) {
   static const char* names[ECLQR_NUM_KERNEL_CLASSES] = {
       "validate", "base_relation", "rel_compose", "domain", "eliminate", "ric_combine",
-      "gains", "fwd_combine", "recover", "multiplier_io", "refine_io", "other", "replay", "multipliers_fast"};
+      "gains", "fwd_combine", "recover", "multiplier_io", "refine_io", "other", "replay", "multipliers_fast",
+      "multipliers_theta"};
   return (k >= 0 && k < ECLQR_NUM_KERNEL_CLASSES) ? names[k] : "unknown";
 }
 
@@ -797,8 +877,10 @@ eclqr_status eclqr_plan_reduced_dims(const eclqr_plan* plan, const void* ws, int
                                      int32_t* mbar) {
   if (!plan || !ws) return fail(ECLQR_INVALID_ARGUMENT, "NULL argument");
   const Plan& p = plan->p;
-  const Engine& E = which ? p.dual : p.primal;
-  const size_t base = which ? p.o_dual : p.o_primal;
+  if (which < 0 || which > 2 || (which == 2 && !p.theta_ok))
+    return fail(ECLQR_INVALID_ARGUMENT, "which: 0 problem, 1 reversed-time problem, 2 theta LQR (if the plan has it)");
+  const Engine& E = which == 2 ? p.theta : (which ? p.dual : p.primal);
+  const size_t base = which == 2 ? p.o_theta_eng : (which ? p.o_dual : p.o_primal);
   const char* b = static_cast<const char*>(ws) + base;
   HIP_OK(hipDeviceSynchronize());
   if (nbar) HIP_OK(hipMemcpy(nbar, b + E.o_nbar, sizeof(int32_t) * E.S, hipMemcpyDeviceToHost));
@@ -883,6 +965,7 @@ eclqr_status eclqr_plan_get_tuning(const eclqr_plan* plan, eclqr_tuning* out) {
   out->register_compose = p.reg_compose;
   out->stage_lds = p.stage_lds;
   out->overlap_dual = p.overlap_dual;
+  out->multiplier_route = p.theta_ok ? p.mult_route : 0;
   out->ms_per_solve = p.tuned_ms;
   return ECLQR_SUCCESS;
 }
@@ -899,6 +982,7 @@ eclqr_status eclqr_plan_set_tuning(eclqr_plan* plan, const eclqr_tuning* t) {
   p.reg_compose = t->register_compose != 0;
   p.stage_lds = t->stage_lds != 0;
   p.overlap_dual = t->overlap_dual != 0;
+  p.mult_route = (p.theta_ok && t->multiplier_route != 0) ? 1 : 0;
   release_graph(p);
   return ECLQR_SUCCESS;
 }
@@ -940,9 +1024,10 @@ eclqr_status eclqr_plan_autotune(eclqr_plan* plan, const eclqr_problem* prob, ec
   Knob knobs[] = {{&p.reg_compose, p.reg_compose ? 0 : 1}, {&p.stage_lds, p.stage_lds ? 0 : 1},
                   {&p.level_buckets, p.level_buckets ? 0 : 1}, {&p.pool_lds, p.pool_lds == 2 ? 1 : 2},
                   {&p.grid_divisor, p.grid_divisor == 1 ? 4 : 1}, {&graph, graph ? 0 : 1},
-                  {&p.overlap_dual, p.overlap_dual ? 0 : 1}};
+                  {&p.overlap_dual, p.overlap_dual ? 0 : 1}, {&p.mult_route, p.mult_route ? 0 : 1}};
   for (Knob& k : knobs) {
     if (st != ECLQR_SUCCESS) break;
+    if (k.v == &p.mult_route && !p.theta_ok) continue;
     const int32_t old = *k.v;
     *k.v = k.alt;
     p.opt.use_graph = graph;

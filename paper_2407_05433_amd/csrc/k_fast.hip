@@ -261,4 +261,299 @@ void launch_mult_final(const DevEngine& e, double* lam, double* mu, int accumula
   hipLaunchKernelGGL(k_mult_final, dim3(e.nblocks), dim3(kBlock), 0, s, e, lam, mu, accumulate);
 }
 
+
+// ---------------------------------------------------------------------------
+// Minimum-norm multipliers from the same domains and scans.
+//
+// Every valid multiplier vector is lambda_i = w_i + H_i' theta_i with
+// (mu_i, theta_{i+1}) solving stage i's local system M_i y = [H_i'; 0] theta_i
+// + c_i (see above).  With the minimum-norm solution of that system and an
+// orthonormal basis N_i of null(M_i),
+//   (mu_i, theta_{i+1}) = Y_i theta_i + y_i + N_i omega_i,   N_i'Y_i = 0, N_i'y_i = 0,
+// and ||lambda_i||^2 = ||w_i||^2 + ||theta_i||^2 (w_i = T_i lambda-bar_i is
+// orthogonal to the rows of H_i).  So the minimum-norm multiplier minimises
+//   1/2 ||theta_0||^2 + sum_{i<N} [1/2 ||Y_i theta_i + y_i||^2 + 1/2 ||omega_i||^2]
+//   + 1/2 ||Y_N theta_N + y_N||^2
+// over theta_0 and omega subject to theta_{i+1} = Y_i^theta theta_i + N_i^theta
+// omega_i + y_i^theta (the theta rows of the maps; each stage's term carries
+// 1/2 ||theta_{i+1}||^2), a reduced LQR in the form the value-function scan
+// solves: stage cost Q = Y'Y, q = Y'y, R = I, no cross term; dynamics
+// A = Y^theta, B = N^theta, c = y^theta; terminal Q = Y_N'Y_N, q = Y_N'y_N;
+// element A_e = A, b_e = c, C_e = B B', J_e = Q, eta_e = -q.  The free initial
+// state is theta_0 = (I + J_0)^{-1} eta_0 from the scan's value function at
+// stage 0.  The minimum-norm local solution comes from a Householder QR of
+// M_i' with column pivoting (rows of M_i), as in Lemma 2 with the
+// Moore-Penrose inverse: M_i' P = Q [R11 R12], y = Q1 R11^{-T} (P'b)_{1:rho},
+// N_i = Q[:, rho:].
+//
+// The theta engine shares the primal schedule; its stage arena (input
+// capacity k_i + n_{i+1}) holds: Y (q x r, ld r), y (q), Z = N (q x f, ld f)
+// (the terminal stage: Ym, ym), the reduced LQR data Ab Bb cb Qb Mb Rb qb rb,
+// the gains, and wl = w_i.
+
+// LDS: W (maxq x ldw) | Qg (maxq x maxq) | X (maxq x (maxr+1)) | Yl (maxq x (maxr+1)) |
+// tau (maxq) | qd (ldw + 8) | cr (ldw) | perm (ldw ints) | wi w1 gx gu tmp (kMaxDim each)
+size_t theta_local_lds_bytes(int maxq, int ldw, int maxr) {
+  return sizeof(double) * ((size_t)maxq * ldw + (size_t)maxq * maxq + 2 * (size_t)maxq * (maxr + 1) + maxq +
+                           2 * (size_t)ldw + 8 + 5 * kMaxDim) +
+         sizeof(int) * (size_t)(ldw + 1) + 64;
+}
+
+__global__ void __launch_bounds__(kBlock) k_theta_local(DevEngine p, DevEngine th, Inputs in, const double* x,
+                                                        const double* u, Tols t, int32_t* status, int maxq, int ldw,
+                                                        int maxr) {
+  extern __shared__ double lds[];
+  double* W = lds;
+  double* Qg = W + (int64_t)maxq * ldw;
+  double* X = Qg + (int64_t)maxq * maxq;
+  double* Yl = X + (int64_t)maxq * (maxr + 1);
+  double* tau = Yl + (int64_t)maxq * (maxr + 1);
+  double* qd = tau + maxq;
+  double* cr = qd + ldw + 8;
+  double* wi = cr + ldw;
+  double* w1 = wi + kMaxDim;
+  double* gx = w1 + kMaxDim;
+  double* gu = gx + kMaxDim;
+  double* tmp = gu + kMaxDim;
+  int* perm = (int*)(tmp + kMaxDim);
+  if (none_live(p)) return;
+  for (int64_t s = blockIdx.x; s < p.S; s += gridDim.x) {
+    const StageInfo st = p.st[s];
+    if (gated(p, st.inst)) continue;
+    const StageInfo ts = th.st[s];
+    const bool term = st.terminal;
+    const int n = st.n, m = term ? 0 : st.m, k = st.k;
+    const int ri = rdim(p, (int)s);
+    const double* Hi = slot_ptr(p, SCAN_REL, st.suf[SCAN_REL]);  // r_i x (n + 1)
+    reduced_costate(p, s, wi, tmp);
+    const double* Q = in.f[IN_Q] + st.in[IN_Q];
+    const double* xs = x + st.in[IN_q];
+    const double* us = term ? nullptr : u + st.in[IN_r];
+    const double* Mm = (in.f[IN_M] && !term) ? in.f[IN_M] + st.in[IN_M] : nullptr;
+    for (int a = ECLQR_TID; a < n; a += ECLQR_NT) {
+      double v = lane_chain<false>(in.f[IN_q][st.in[IN_q] + a], Q + a * n, 1, xs, 1, n);
+      if (Mm) v = lane_chain<false>(v, Mm + a * m, 1, us, 1, m);
+      gx[a] = v;
+    }
+    if (!term) {
+      const double* R = in.f[IN_R] + st.in[IN_R];
+      for (int b = ECLQR_TID; b < m; b += ECLQR_NT) {
+        double v = lane_chain<false>(in.f[IN_r][st.in[IN_r] + b], R + b * m, 1, us, 1, m);
+        if (Mm) v = lane_chain<false>(v, Mm + b, m, xs, 1, n);
+        gu[b] = v;
+      }
+    }
+    lds_sync();
+    int r1 = 0, n1 = 0;
+    const double* H1 = nullptr;
+    if (!term) {
+      reduced_costate(p, s + 1, w1, tmp);
+      r1 = rdim(p, (int)s + 1);
+      n1 = p.st[s + 1].n;
+      H1 = slot_ptr(p, SCAN_REL, p.st[s + 1].suf[SCAN_REL]);  // r1 x (n1 + 1)
+    }
+    const double* E = in.f[IN_E] + st.in[IN_E];
+    const double* A = term ? nullptr : in.f[IN_A] + st.in[IN_A];
+    const double* B = term ? nullptr : in.f[IN_B] + st.in[IN_B];
+    const double* F = term ? nullptr : in.f[IN_F] + st.in[IN_F];
+    const int q = k + r1, Rr = n + m;
+    // W = M' (q x Rr): row col of W is column col of M (a multiplier unknown)
+    for (int idx = ECLQR_TID; idx < q * Rr; idx += ECLQR_NT) {
+      const int col = idx / Rr, row = idx - (idx / Rr) * Rr;
+      const bool xr = row < n;
+      const int a = xr ? row : row - n;
+      double v;
+      if (col < k) {
+        v = xr ? E[col * n + a] : F[col * m + a];
+      } else {
+        const int l = col - k;
+        v = xr ? lane_chain<false>(0.0, H1 + l * (n1 + 1), 1, A + a, n, n1)
+               : lane_chain<false>(0.0, H1 + l * (n1 + 1), 1, B + a, m, n1);
+      }
+      W[col * ldw + row] = v;
+    }
+    // constant right-hand side: [w_i - g^x - A'w_{i+1}; -g^u - B'w_{i+1}]
+    for (int row = ECLQR_TID; row < Rr; row += ECLQR_NT) {
+      double v;
+      if (row < n) {
+        v = wi[row] - gx[row];
+        if (!term) v = lane_chain<true>(v, A + row, n, w1, 1, n1);
+      } else {
+        v = lane_chain<true>(-gu[row - n], B + (row - n), m, w1, 1, n1);
+      }
+      cr[row] = v;
+    }
+    wg_sync();
+    const int rho = wg_qr_colpiv(W, ldw, q, Rr, 0, Rr, t.rank, tau, QRScratch{qd, perm});
+    const int f = q - rho;
+    const int nc = ri + 1;
+    wg_identity(Qg, q, q);
+    wg_apply_q(W, ldw, q, 0, rho, tau, Qg, q, q);
+    // X = (P' [H_i' | c])_{1:rho}, then X <- R11^{-T} X
+    for (int idx = ECLQR_TID; idx < rho * nc; idx += ECLQR_NT) {
+      const int j = idx / nc, c = idx - (idx / nc) * nc;
+      const int row = perm[j];
+      X[idx] = (c < ri) ? ((row < n) ? Hi[c * (n + 1) + row] : 0.0) : cr[row];
+    }
+    wg_sync();
+    wg_trsm_upper_t(W, ldw, 0, X, nc, rho, nc);
+    // consistency: rows rho.. of P'b against R12' X (one lane per (row, column))
+    {
+      bool bad = false;
+      for (int idx = ECLQR_TID; idx < (Rr - rho) * nc; idx += ECLQR_NT) {
+        const int jj = rho + idx / nc, c = idx - (idx / nc) * nc;
+        const int row = perm[jj];
+        const double bv = (c < ri) ? ((row < n) ? Hi[c * (n + 1) + row] : 0.0) : cr[row];
+        double e = -bv, mag = fabs(bv);
+        for (int l = 0; l < rho; ++l) {
+          const double tl = W[l * ldw + jj] * X[l * nc + c];
+          e += tl;
+          mag += fabs(tl);
+        }
+        if (!(fabs(e) <= t.cons * fmax(1.0, mag))) bad = true;
+      }
+      if (bad) flag(status, st.inst, ECLQR_RANK_INCONSISTENT);
+    }
+    // Yl = Q1 X (q x (r_i + 1)): [Y | y]
+    wg_gemm(Yl, nc, Qg, q, false, X, nc, false, q, nc, rho, 1.0, 0.0);
+    // theta engine arena
+    // [Y | y] in the fields Y, y (capacity k + n') of a stage, Ym, ym (k x n) at the terminal
+    const Arena at = arena_layout(ts.n, ts.np, ts.m, ts.k);
+    double* tb = th.arena + ts.ws;
+    double* Ya = tb + (term ? at.Ym : at.Y);
+    double* ya = tb + (term ? at.ym : at.y);
+    for (int idx = ECLQR_TID; idx < q * ri; idx += ECLQR_NT) Ya[idx] = Yl[(idx / ri) * nc + idx % ri];
+    for (int j = ECLQR_TID; j < q; j += ECLQR_NT) ya[j] = Yl[j * nc + ri];
+    if (!term) {
+      double* Na = tb + at.Z;
+      for (int idx = ECLQR_TID; idx < q * f; idx += ECLQR_NT) Na[idx] = Qg[(idx / f) * q + rho + idx % f];
+    }
+    for (int a = ECLQR_TID; a < n; a += ECLQR_NT) tb[at.wl + a] = wi[a];
+    // reduced LQR data and the value-function element
+    double* Qb = tb + at.Qb;
+    double* qb = tb + at.qb;
+    wg_gemm(Qb, ri, Yl, nc, true, Yl, nc, false, ri, ri, q, 1.0, 0.0);
+    for (int c = ECLQR_TID; c < ri; c += ECLQR_NT) qb[c] = lane_chain<false>(0.0, Yl + c, nc, Yl + ri, nc, q);
+    wg_sync();
+    wg_symmetrize(Qb, ri, ri);
+    double* ric = slot_ptr(th, SCAN_RIC, ts.elem[SCAN_RIC]);
+    if (term) {
+      const RicLayout rl = ric_layout(ts.n, 0);
+      wg_copy(ric + rl.J, ri, Qb, ri, ri, ri);
+      for (int c = ECLQR_TID; c < ri; c += ECLQR_NT) ric[rl.eta + c] = -qb[c];
+      if (ECLQR_TID == 0) {
+        th.nbar[s] = ri;
+        th.mbar[s] = 0;
+      }
+      wg_sync();
+      continue;
+    }
+    double* Ab = tb + at.Ab;
+    double* Bb = tb + at.Bb;
+    double* cb = tb + at.cb;
+    for (int idx = ECLQR_TID; idx < r1 * ri; idx += ECLQR_NT) Ab[idx] = Yl[(k + idx / ri) * nc + idx % ri];
+    for (int idx = ECLQR_TID; idx < r1 * f; idx += ECLQR_NT) Bb[idx] = Qg[(k + idx / f) * q + rho + idx % f];
+    for (int l = ECLQR_TID; l < r1; l += ECLQR_NT) cb[l] = Yl[(k + l) * nc + ri];
+    wg_fill(tb + at.Mb, f, ri, f, 0.0);
+    wg_identity(tb + at.Rb, f, f);
+    for (int j = ECLQR_TID; j < f; j += ECLQR_NT) tb[at.rb + j] = 0.0;
+    wg_sync();
+    const RicLayout rl = ric_layout(ts.n, ts.np);
+    wg_copy(ric + rl.A, ri, Ab, ri, r1, ri);
+    for (int l = ECLQR_TID; l < r1; l += ECLQR_NT) ric[rl.b + l] = cb[l];
+    wg_gemm(ric + rl.C, r1, Bb, f, false, Bb, f, true, r1, r1, f, 1.0, 0.0);
+    wg_symmetrize(ric + rl.C, r1, r1);
+    wg_copy(ric + rl.J, ri, Qb, ri, ri, ri);
+    for (int c = ECLQR_TID; c < ri; c += ECLQR_NT) ric[rl.eta + c] = -qb[c];
+    if (ECLQR_TID == 0) {
+      th.nbar[s] = ri;
+      th.mbar[s] = f;
+    }
+    wg_sync();
+  }
+}
+
+// theta_0 = (I + J_0)^{-1} eta_0: the free initial state of the theta LQR,
+// written as the constant leaf of its forward scan.
+__global__ void __launch_bounds__(kBlock) k_theta_init(DevEngine th) {
+  __shared__ double S0[kMaxDim * kMaxDim];
+  __shared__ double sh[16];
+  if (none_live(th)) return;
+  for (int64_t s = blockIdx.x; s < th.S; s += gridDim.x) {
+    const StageInfo ts = th.st[s];
+    if (ts.i != 0 || gated(th, ts.inst)) continue;
+    const int r0 = th.nbar[s];
+    const RicLayout rl = ric_layout(ts.n, 0);
+    const double* V = slot_ptr(th, SCAN_RIC, ts.suf[SCAN_RIC]);
+    for (int idx = ECLQR_TID; idx < r0 * r0; idx += ECLQR_NT) {
+      const int i = idx / r0, j = idx - (idx / r0) * r0;
+      S0[idx] = V[rl.J + idx] + ((i == j) ? 1.0 : 0.0);
+    }
+    lds_sync();
+    wg_cholesky<true>(S0, r0, r0, sh, 0.0);
+    const int lane = ECLQR_TID;
+    double v = (lane < r0) ? V[rl.eta + lane] : 0.0;
+    v = lane_trsv_lower(S0, r0, v, r0);
+    v = lane_trsv_lower_t(S0, r0, v, r0);
+    double* th0 = slot_ptr(th, SCAN_FWD, ts.suf[SCAN_FWD]);
+    if (lane < r0) th0[lane] = v;
+    lds_sync();
+  }
+}
+
+// lambda_i = w_i + H_i' theta_i; omega_i = K_i theta_i + k_i;
+// mu_i = (Y_i theta_i + y_i + N_i omega_i)_{1:k_i} (terminal: Y_N theta_N + y_N);
+// written, or added to the values present (refinement corrections).
+__global__ void __launch_bounds__(kBlock) k_theta_final(DevEngine p, DevEngine th, double* lam, double* mu,
+                                                        int accumulate) {
+  __shared__ double om[kMaxDim];
+  if (none_live(p)) return;
+  for (int64_t s = blockIdx.x; s < p.S; s += gridDim.x) {
+    const StageInfo st = p.st[s];
+    if (gated(p, st.inst)) continue;
+    const StageInfo ts = th.st[s];
+    const int n = st.n, k = st.k;
+    const int ri = th.nbar[s], f = st.terminal ? 0 : th.mbar[s];
+    const Arena at = arena_layout(ts.n, ts.np, ts.m, ts.k);
+    const double* tb = th.arena + ts.ws;
+    const double* Hi = slot_ptr(p, SCAN_REL, st.suf[SCAN_REL]);
+    const double* tv = slot_ptr(th, SCAN_FWD, ts.suf[SCAN_FWD]);
+    for (int a = ECLQR_TID; a < n; a += ECLQR_NT) {
+      const double v = lane_chain<false>(tb[at.wl + a], Hi + a, n + 1, tv, 1, ri);
+      lam[st.in[IN_q] + a] = accumulate ? lam[st.in[IN_q] + a] + v : v;
+    }
+    for (int j = ECLQR_TID; j < f; j += ECLQR_NT) om[j] = lane_chain<false>(tb[at.kk + j], tb + at.K + j * ri, 1, tv, 1, ri);
+    lds_sync();
+    const int64_t oY = st.terminal ? at.Ym : at.Y, oy = st.terminal ? at.ym : at.y;
+    for (int j = ECLQR_TID; j < k; j += ECLQR_NT) {
+      double v = lane_chain<false>(tb[oy + j], tb + oY + j * ri, 1, tv, 1, ri);
+      if (f > 0) v = lane_chain<false>(v, tb + at.Z + j * f, 1, om, 1, f);
+      mu[st.in[IN_g] + j] = accumulate ? mu[st.in[IN_g] + j] + v : v;
+    }
+    lds_sync();
+  }
+}
+
+static int g_theta_max_lds = 65536;
+void theta_set_max_lds(int bytes) {
+  g_theta_max_lds = bytes;
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_theta_local), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            bytes);
+}
+bool launch_theta_local(const DevEngine& p, const DevEngine& th, const Inputs& in, const double* x, const double* u,
+                        Tols t, int32_t* status, int maxq, int ldw, int maxr, hipStream_t s) {
+  const size_t lds = theta_local_lds_bytes(maxq, ldw, maxr);
+  if (lds > (size_t)g_theta_max_lds) return false;
+  hipLaunchKernelGGL(k_theta_local, dim3(p.nblocks), dim3(kBlock), lds, s, p, th, in, x, u, t, status, maxq, ldw,
+                     maxr);
+  return true;
+}
+void launch_theta_init(const DevEngine& th, hipStream_t s) {
+  hipLaunchKernelGGL(k_theta_init, dim3(th.nblocks), dim3(kBlock), 0, s, th);
+}
+void launch_theta_final(const DevEngine& p, const DevEngine& th, double* lam, double* mu, int accumulate,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_theta_final, dim3(p.nblocks), dim3(kBlock), 0, s, p, th, lam, mu, accumulate);
+}
+
 }  // namespace eclqr

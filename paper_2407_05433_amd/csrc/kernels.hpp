@@ -146,6 +146,15 @@ bool launch_mult_local(const DevEngine& e, const Inputs& in, const double* x, co
                        int32_t* status, int maxrow, int ldw, hipStream_t s);
 void launch_theta_combine(const DevEngine& e, int64_t first, int64_t ntasks, hipStream_t s);
 void launch_mult_final(const DevEngine& e, double* lam, double* mu, int accumulate, hipStream_t s);
+// minimum-norm multipliers through the theta LQR (p: the primal engine, th:
+// the theta engine over the same schedule)
+void theta_set_max_lds(int bytes);
+size_t theta_local_lds_bytes(int maxq, int ldw, int maxr);
+bool launch_theta_local(const DevEngine& p, const DevEngine& th, const Inputs& in, const double* x, const double* u,
+                        Tols t, int32_t* status, int maxq, int ldw, int maxr, hipStream_t s);
+void launch_theta_init(const DevEngine& th, hipStream_t s);
+void launch_theta_final(const DevEngine& p, const DevEngine& th, double* lam, double* mu, int accumulate,
+                        hipStream_t s);
 void launch_grad_assemble(const DevEngine& p, const double* x, const double* u, const double* lam, const double* mu,
                           const double* ax, const double* au, const double* al, const double* am, const GradPtrs& g,
                           hipStream_t s);

@@ -218,7 +218,7 @@ std::string Engine::build(const eclqr_dims* d) {
     slot_na[SCAN_FWD][q] = fa;
     slot_nb[SCAN_FWD][q] = fb;
     slot_off[SCAN_REL][q] = scan_arena[SCAN_REL];
-    scan_arena[SCAN_REL] += rel_slot_size(slot_cap[q], na, nb);
+    if (need_rel) scan_arena[SCAN_REL] += rel_slot_size(slot_cap[q], na, nb);
     slot_off[SCAN_RIC][q] = scan_arena[SCAN_RIC];
     scan_arena[SCAN_RIC] += ric_layout(na, nb).size;
     slot_off[SCAN_FWD][q] = scan_arena[SCAN_FWD];
@@ -232,7 +232,7 @@ std::string Engine::build(const eclqr_dims* d) {
   lvl_rel_log.assign(2 * D, 0);
   for (int32_t q = 0; q < nslots; ++q) {
     const int b = slot_inst[q], s = slot_s[q], e = slot_e[q];
-    if (e != s + 1) continue;
+    if (e != s + 1 || !need_rel) continue;
     const StageInfo& x = st[sbase[b] + s];
     const int P = x.terminal ? x.k : x.np + x.k;
     const int R = x.terminal ? 0 : std::min(x.m, P);
@@ -245,11 +245,13 @@ std::string Engine::build(const eclqr_dims* d) {
     const int b = slot_inst[a];
     const int nmid = st[sbase[b] + slot_e[a]].n;
     const int P = slot_cap[a] + slot_cap[c];
-    rel_log_off[o] = rel_log_total;
-    rel_log_total += rel_log_layout(P, std::min(nmid, P), slot_cap[o]).size;
-    for (int l = 0; l < 2 * D; ++l)
-      if ((int64_t)t >= lvl_begin[l] && (int64_t)t < lvl_begin[l] + lvl_count[l])
-        lvl_rel_log[l] = std::max(lvl_rel_log[l], rel_log_layout(P, std::min(nmid, P), slot_cap[o]).size);
+    if (need_rel) {
+      rel_log_off[o] = rel_log_total;
+      rel_log_total += rel_log_layout(P, std::min(nmid, P), slot_cap[o]).size;
+      for (int l = 0; l < 2 * D; ++l)
+        if ((int64_t)t >= lvl_begin[l] && (int64_t)t < lvl_begin[l] + lvl_count[l])
+          lvl_rel_log[l] = std::max(lvl_rel_log[l], rel_log_layout(P, std::min(nmid, P), slot_cap[o]).size);
+    }
     ric_log_off[o] = ric_log_total;
     ric_log_total += ric_log_size(nmid);
   }
@@ -356,7 +358,7 @@ std::string Engine::build(const eclqr_dims* d) {
     // factor-reusing multipliers: (x, u) rows; mu, theta', H' and constant columns
     fast_rows = std::max(fast_rows, x.n + (x.terminal ? 0 : x.m));
     fast_ldw = std::max(fast_ldw, (x.k + x.np + x.n + 1) | 1);
-    scratch_per_block = std::max(scratch_per_block, elim_scratch(x.n, x.np, x.m, x.k));
+    if (need_rel) scratch_per_block = std::max(scratch_per_block, elim_scratch(x.n, x.np, x.m, x.k));
     scratch_per_block = std::max(scratch_per_block, gains_scratch(x.n, x.np, x.m));
   }
   scratch_per_block = std::max(scratch_per_block, ric_pool(maxn));
@@ -418,9 +420,45 @@ std::string build_plan(Plan& p, const eclqr_dims* d, const eclqr_options* opt) {
   err = p.dual.build(&dd);
   if (!err.empty()) return "dual: " + err;
 
+  // theta engine: the primal's stages with input capacity k_i + n_{i+1}
+  {
+    std::vector<int32_t> tu;
+    bool ok = true;
+    for (int64_t s = 0; s < P.S; ++s) {
+      const StageInfo& x = P.st[s];
+      if (x.terminal) continue;
+      tu.push_back(x.k + x.np);
+      if (x.k + x.np > kMaxDim) ok = false;
+    }
+    if (ok) {
+      std::vector<int32_t> hor(P.N.begin(), P.N.end()), nx(P.S), nc(P.S);
+      for (int64_t s = 0; s < P.S; ++s) {
+        nx[s] = P.st[s].n;
+        nc[s] = P.st[s].k;
+      }
+      eclqr_dims td{P.B, hor.data(), nx.data(), tu.data(), nc.data()};
+      p.theta.need_rel = false;
+      ok = p.theta.build(&td).empty();
+    }
+    p.theta_ok = ok;
+    p.mult_route = ok ? 1 : 0;
+    p.th_q = p.th_ldw = p.th_r = 1;
+    for (int64_t s = 0; s < P.S; ++s) {
+      const StageInfo& x = P.st[s];
+      const int q = x.terminal ? x.k : x.k + x.np, R = x.terminal ? x.n : x.n + x.m;
+      p.th_q = std::max(p.th_q, q);
+      p.th_ldw = std::max(p.th_ldw, R | 1);
+      p.th_r = std::max(p.th_r, x.n);
+    }
+  }
+
   size_t o = 0;
   p.o_primal = o; o = align256(o + p.primal.bytes);
   p.o_dual = o; o = align256(o + p.dual.bytes);
+  if (p.theta_ok) {
+    p.o_theta_eng = o;
+    o = align256(o + p.theta.bytes);
+  }
   for (int f = 0; f < ECLQR_NUM_FIELDS; ++f) {
     p.o_dprob[f] = o;
     o = align256(o + sizeof(double) * std::max<int64_t>(1, p.dual.total[f]));

@@ -58,6 +58,7 @@ struct Engine {
   int32_t maxn = 0, maxm = 0, maxk = 0;
   int32_t base_maxp = 0, base_ldw = 0, elim_maxq = 0;
   int32_t fast_rows = 0, fast_ldw = 0;  // LDS tile of the factor-reusing multiplier kernel
+  bool need_rel = true;            // false: no relation-scan arenas or logs (an engine that only runs the LQR scans)
   int32_t nblocks = 0;             // grid of the stage-parallel kernels
   int64_t scratch_per_block = 0;   // doubles
 
@@ -74,6 +75,17 @@ struct Engine {
 struct Plan {
   eclqr_options opt;
   Engine primal, dual;
+  // Minimum-norm multipliers from the primal pass's domains and scans: the
+  // LQR over the normal coordinates theta_i of the domains (same schedule as
+  // the primal; stage input capacity k_i + n_{i+1}).  theta_ok is false when
+  // that capacity exceeds the kernels' limit; the reversed-time problem is
+  // used then.
+  Engine theta;
+  bool theta_ok = false;
+  size_t o_theta_eng = 0;
+  int32_t th_q = 1, th_ldw = 1, th_r = 1;  // LDS tile of the local minimum-norm systems
+  int32_t mult_route = 1;     // 1: theta LQR (when theta_ok), 0: reversed-time problem
+  int32_t ws_route = -1;      // route whose factors the bound workspace holds (-1: none yet)
   // workspace regions (bytes from the workspace base)
   size_t o_primal = 0, o_dual = 0;
   size_t o_dprob[ECLQR_NUM_FIELDS] = {0};  // reversed-time stationarity problem data

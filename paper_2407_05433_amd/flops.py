@@ -6,10 +6,12 @@ combines.  Reduced dimensions and relation row counts are read back from the
 workspace after a solve.  Householder QR of a p x c matrix with r reflections
 counts sum_{j<r} 4 (p - j)(c - j); row-pivoted Gram-Schmidt of p rows over kc
 columns choosing r rows counts sum_{j<r} (4 j kc + 4 (p - j - 1)(kc + 1)).
-A solve with multipliers runs each engine (the problem and the reversed-time
-stationarity problem) once in full; refinement steps and the adjoint replay
-the logged factors on new vectors (kernel class "replay", whose matrix-vector
-work is not counted here).
+A solve with multipliers runs the problem's engine and, by the multiplier
+route of the plan, either the reversed-time stationarity problem's engine or
+the theta LQR (local minimum-norm systems, value-function scan, gains and
+forward scan over the normal coordinates of the domains) once in full;
+refinement steps and the adjoint replay the logged factors on new vectors
+(kernel class "replay", whose matrix-vector work is not counted here).
 """
 
 from __future__ import annotations
@@ -126,13 +128,68 @@ def engine_flops(plan, ws, dual: bool, weight=None) -> Dict[str, float]:
     return dict(F)
 
 
+def theta_flops(plan, ws) -> Dict[str, float]:
+    """Flops of the theta LQR route: per stage the minimum-norm local system
+    (QR of the q x R transposed system with rho reflections, Q formed, the
+    triangular solve and Q1 X for r + 1 right-hand sides, Y'Y), the gains; per
+    task the value-function and forward combines at dims r."""
+    dims = plan.stage_dims(False)
+    nb_p, _ = plan.reduced_dims(ws)
+    r, f = plan.reduced_dims(ws, which=2)
+    F = defaultdict(float)
+    horizons = list(plan.horizons)
+    stage_inst = np.repeat(np.arange(len(horizons)), [h + 1 for h in horizons])
+    sbase = np.concatenate([[0], np.cumsum([h + 1 for h in horizons])[:-1]]).astype(np.int64)
+    for s, (n, np_, m, k) in enumerate(dims):
+        b = int(stage_inst[s])
+        term = (s - int(sbase[b])) == horizons[b]
+        ri = int(r[s])
+        r1 = 0 if term else int(r[s + 1])
+        q = k + r1
+        R = n + (0 if term else m)
+        rho = q - (0 if term else int(f[s]))
+        nc = ri + 1
+        t = 2.0 * r1 * np_ * (n + m) + _qr(q, R, rho) + sum(4.0 * (q - j) * q for j in range(rho))
+        t += rho * rho * nc + 2.0 * q * rho * nc + 2.0 * ri * ri * q + 2.0 * ri * q
+        t += 2.0 * n * (n + m) + 2.0 * int(nb_p[s]) * (n + 1)  # gradients, costate
+        F["multipliers_theta"] += t
+        if not term:
+            mb, nb, nb1 = int(f[s]), ri, r1
+            g = 2.0 * nb1 * nb1 * (mb + nb) + 2.0 * mb * mb * nb1 + 2.0 * mb * nb * nb1 + mb ** 3 / 3.0
+            g += 2.0 * mb * mb * (nb + 1) + 2.0 * nb1 * mb * nb + 2.0 * nb1 * (nb1 + mb)
+            F["gains"] += g
+    inst, first, last = plan.slot_info(False)
+    for lv in plan.schedule(False):
+        for a, bb, o in lv:
+            b = int(inst[a])
+            L = horizons[b] + 1
+            s0, mid, e0 = int(first[a]), int(last[a]), int(last[bb])
+            ds, dm = int(r[sbase[b] + s0]), int(r[sbase[b] + mid])
+            de = int(r[sbase[b] + e0]) if e0 < L else 0
+            fl = 2.0 * dm ** 3 + 2.0 / 3.0 * dm ** 3 + 2.0 * dm * dm * (dm + 1) + 2.0 * dm * dm
+            fl += 2.0 * ds * dm * dm + 2.0 * ds * ds * dm + 2.0 * ds * dm
+            if e0 < L:
+                fl += 2.0 * dm * dm * (ds + 1 + dm) + 2.0 * dm * dm + 2.0 * de * ds * dm + 2.0 * de * dm
+                fl += 2.0 * de * dm * dm + 2.0 * de * de * dm
+            F["ric_combine"] += fl
+            N = horizons[b]
+            do, dmid = int(r[sbase[b] + N - s0]), int(r[sbase[b] + N - mid])
+            din = int(r[sbase[b] + N - e0]) if e0 < L else 0
+            F["fwd_combine"] += 2.0 * do * dmid * (din + 1)
+    return dict(F)
+
+
 def solve_flops(plan, problems, ws, multipliers: bool = True, steps=None) -> Dict[str, float]:
-    """Flops per kernel class of the full passes of one solve (the problem and,
-    with multipliers, the reversed-time problem, each once)."""
+    """Flops per kernel class of the full passes of one solve: the problem and,
+    with multipliers, the route the plan takes (the reversed-time problem or
+    the theta LQR), each once."""
+    from .solver import get_tuning
     out = defaultdict(float)
     for k, v in engine_flops(plan, ws, False).items():
         out[k] += v
     if multipliers:
-        for k, v in engine_flops(plan, ws, True).items():
+        theta = int(plan.options.multipliers) == 1 and get_tuning(plan).get("multiplier_route", 0) == 1
+        extra = theta_flops(plan, ws) if theta else engine_flops(plan, ws, True)
+        for k, v in extra.items():
             out[k] += v
     return dict(out)

@@ -106,13 +106,15 @@ class Plan:
         check(lib().eclqr_plan_profile(self._h, ms, cnt, int(reset)), "eclqr_plan_profile")
         return {lib().eclqr_kernel_class_name(k).decode(): (ms[k], cnt[k]) for k in range(n)}
 
-    def reduced_dims(self, ws: torch.Tensor, dual: bool = False):
-        """(n-bar, m-bar) per stage from the last solve in ``ws`` (synchronises)."""
-        S = len(self._nx) if not dual else int(sum(h + 2 for h in self.horizons))
+    def reduced_dims(self, ws: torch.Tensor, dual: bool = False, which: Optional[int] = None):
+        """(n-bar, m-bar) per stage from the last solve in ``ws`` (synchronises);
+        which = 2: (r, f) of the theta LQR of the minimum-norm route."""
+        w = int(dual) if which is None else int(which)
+        S = int(sum(h + 2 for h in self.horizons)) if w == 1 else len(self._nx)
         nb = (C.c_int32 * S)()
         mb = (C.c_int32 * S)()
         wptr, _ = _aligned_ws(ws)
-        check(lib().eclqr_plan_reduced_dims(self._h, C.c_void_p(wptr), int(dual), nb, mb), "eclqr_plan_reduced_dims")
+        check(lib().eclqr_plan_reduced_dims(self._h, C.c_void_p(wptr), w, nb, mb), "eclqr_plan_reduced_dims")
         return np.frombuffer(nb, dtype=np.int32).copy(), np.frombuffer(mb, dtype=np.int32).copy()
 
     def refine_steps(self, ws: torch.Tensor) -> np.ndarray:
@@ -329,7 +331,8 @@ def unpack(plan: Plan, flat: torch.Tensor, field: str, problems) -> List[List[np
 def _tuning_dict(t: _lib.Tuning) -> Dict[str, float]:
     return {"use_graph": int(t.use_graph), "level_buckets": int(t.level_buckets), "pool_in_lds": int(t.pool_in_lds),
             "grid_divisor": int(t.grid_divisor), "register_compose": int(t.register_compose),
-            "stage_lds": int(t.stage_lds), "overlap_dual": int(t.overlap_dual), "ms_per_solve": float(t.ms_per_solve)}
+            "stage_lds": int(t.stage_lds), "overlap_dual": int(t.overlap_dual), "multiplier_route": int(t.multiplier_route),
+            "ms_per_solve": float(t.ms_per_solve)}
 
 
 def autotune(plan: Plan, data: Dict[str, torch.Tensor], ws: torch.Tensor, out: Optional[Solution] = None) -> Dict:

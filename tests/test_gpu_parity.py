@@ -25,9 +25,11 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-def gpu_solve(probs, **opts):
+def gpu_solve(probs, tuning=None, **opts):
     import paper_2407_05433_amd as ecl
     plan = ecl.Plan.for_problems(probs, **opts)
+    if tuning:
+        ecl.set_tuning(plan, **tuning)
     data = ecl.pack(plan, probs)
     ws = plan.workspace()
     sol = ecl.solve(plan, data, ws)
@@ -78,6 +80,22 @@ def test_c0_tiny():
     from workloads import config_c0
     probs = config_c0()
     check_parity(probs, gpu_solve(probs))
+
+
+def test_reversed_time_multiplier_route():
+    """The minimum-norm multipliers through the reversed-time stationarity
+    problem (multiplier_route = 0), with and without the overlapped
+    factorization, on the small case, the structural family and a batch."""
+    _need_gpu()
+    from tests._util import problem_family
+    from workloads import config_c0, config_c3
+    fam = [p for _, p in problem_family()]
+    for tun in ({"multiplier_route": 0}, {"multiplier_route": 0, "overlap_dual": 0}):
+        probs = config_c0()
+        check_parity(probs, gpu_solve(probs, tuning=tun))
+        check_parity(fam, gpu_solve(fam, tuning=tun))
+    probs = config_c3(B=8, N_range=(32, 90))
+    check_parity(probs, gpu_solve(probs, tuning={"multiplier_route": 0}))
 
 
 def test_structural_family_single_and_batched():
@@ -295,7 +313,7 @@ def test_autotune_keeps_results():
     tuned = ecl.autotune(plan, data, ws)
     assert tuned["ms_per_solve"] > 0
     for cfg in ({"level_buckets": 0}, {"pool_in_lds": 0}, {"pool_in_lds": 1}, {"stage_lds": 0}, {"grid_divisor": 4},
-                {"overlap_dual": 0},
+                {"overlap_dual": 0}, {"multiplier_route": 1 - base["multiplier_route"]},
                 {"use_graph": 1},
                 {"register_compose": 0}, tuned):
         full = dict(base)
@@ -304,11 +322,14 @@ def test_autotune_keeps_results():
         sol = ecl.solve(plan, data, ws)
         torch.cuda.synchronize()
         for f in ("x", "u", "lam", "mu", "status"):
-            if full["register_compose"] == base["register_compose"] and full["overlap_dual"] == base["overlap_dual"]:
+            same = all(full[k] == base[k] for k in ("register_compose", "overlap_dual", "multiplier_route"))
+            if same or (full["multiplier_route"] == 1 and base["multiplier_route"] == 1 and
+                        full["register_compose"] == base["register_compose"]):
                 assert torch.equal(getattr(sol, f), ref[f]), (cfg, f)
             else:
                 # the LDS and register compositions differ in rounding only,
-                # and so do the full and the replayed reversed-time passes
+                # and so do the multiplier routes (the theta LQR, the full and
+                # the replayed reversed-time passes)
                 a, b = getattr(sol, f).double(), ref[f].double()
                 err = float((a - b).norm() / max(float(b.norm()), 1e-300))
                 assert err <= 1e-8, (cfg, f, err)
