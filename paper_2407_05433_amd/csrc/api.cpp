@@ -424,7 +424,13 @@ eclqr_status theta_multipliers(Plan& p, const Views& v, const Inputs& in, const 
     if (T.lvl_count[l] == 0) continue;
     if (full) {
       Timed tm(ECLQR_K_RIC_COMBINE, s);
-      launch_ric_combine(v.T, T.lvl_begin[l], T.lvl_count[l], status, std::max(1, T.lvl_dim[l]), s);
+      // theta dims are mostly <= 4: one lane per combine on levels whose
+      // tasks fit in a few waves per CU (latency-bound); wide levels keep one
+      // wavefront per combine (more waves in flight)
+      if (T.lvl_count[l] <= 4096)
+        launch_ric_combine_lane(v.T, T.lvl_begin[l], T.lvl_count[l], s);
+      else
+        launch_ric_combine(v.T, T.lvl_begin[l], T.lvl_count[l], status, std::max(1, T.lvl_dim[l]), s);
     } else {
       Timed tm(ECLQR_K_REPLAY, s);
       launch_ric_combine_vec(v.T, T.lvl_begin[l], T.lvl_count[l], std::max(1, T.lvl_dim[l]), s);

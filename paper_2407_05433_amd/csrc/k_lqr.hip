@@ -216,6 +216,379 @@ __device__ __forceinline__ bool combine_factored(const double* A1, const double*
   return true;
 }
 
+
+// ---- one lane per combine: reduced dims <= 4 ---------------------------------
+// The factored combine above, with every matrix held in the registers of one
+// lane (4 x 4 arrays; a block beyond the task's dims is identity on the
+// diagonal of the factored matrices and zero elsewhere, which leaves the
+// leading blocks exactly as at their own size).  64 small combines run side by
+// side in one wavefront instead of one after another.  Same factorizations,
+// same failure tests, same log (flag 1, L, Rg); a combine that fails a test is
+// redone by the whole wavefront with the routines above (factored, else LU).
+constexpr int kLD = 4;
+
+// In-place Cholesky of the leading n x n block (identity beyond it); false
+// when a leading pivot is not above floor.
+__device__ __forceinline__ bool lc_chol(double (&S)[kLD][kLD], int n, double floor) {
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < kLD; ++j) {
+    double d = S[j][j];
+#pragma unroll
+    for (int p = 0; p < j; ++p) d = fma(-S[j][p], S[j][p], d);
+    ok = ok && (j >= n || d > floor);
+    const double lj = (j < n) ? sqrt(d) : 1.0;
+    const double rl = 1.0 / lj;
+    S[j][j] = lj;
+#pragma unroll
+    for (int i = j + 1; i < kLD; ++i) {
+      double v = S[i][j];
+#pragma unroll
+      for (int p = 0; p < j; ++p) v = fma(-S[i][p], S[j][p], v);
+      S[i][j] = v * rl;
+    }
+#pragma unroll
+    for (int i = 0; i < j; ++i) S[i][j] = 0.0;
+  }
+  return ok;
+}
+// x <- L^{-1} x, x <- L^{-T} x
+__device__ __forceinline__ void lc_fwd(const double (&L)[kLD][kLD], double (&x)[kLD]) {
+#pragma unroll
+  for (int i = 0; i < kLD; ++i) {
+    double v = x[i];
+#pragma unroll
+    for (int p = 0; p < i; ++p) v = fma(-L[i][p], x[p], v);
+    x[i] = v / L[i][i];
+  }
+}
+__device__ __forceinline__ void lc_bwd(const double (&L)[kLD][kLD], double (&x)[kLD]) {
+#pragma unroll
+  for (int i = kLD - 1; i >= 0; --i) {
+    double v = x[i];
+#pragma unroll
+    for (int p = i + 1; p < kLD; ++p) v = fma(-L[p][i], x[p], v);
+    x[i] = v / L[i][i];
+  }
+}
+__device__ __forceinline__ void lc_sym(double (&S)[kLD][kLD]) {
+#pragma unroll
+  for (int i = 0; i < kLD; ++i)
+#pragma unroll
+    for (int j = i + 1; j < kLD; ++j) {
+      const double v = 0.5 * (S[i][j] + S[j][i]);
+      S[i][j] = v;
+      S[j][i] = v;
+    }
+}
+// r x c block of a row-major (ld) array, zero beyond (pad_id: identity diagonal)
+__device__ __forceinline__ void lc_load(double (&M)[kLD][kLD], const double* src, int r, int c, int ld, bool pad_id) {
+#pragma unroll
+  for (int i = 0; i < kLD; ++i)
+#pragma unroll
+    for (int j = 0; j < kLD; ++j) {
+      double v = (pad_id && i == j) ? 1.0 : 0.0;
+      if (i < r && j < c) v = src[i * ld + j];
+      M[i][j] = v;
+    }
+}
+__device__ __forceinline__ void lc_store(double* dst, const double (&M)[kLD][kLD], int r, int c, int ld) {
+#pragma unroll
+  for (int i = 0; i < kLD; ++i)
+#pragma unroll
+    for (int j = 0; j < kLD; ++j)
+      if (i < r && j < c) dst[i * ld + j] = M[i][j];
+}
+
+// Returns false when a factorization test fails (outputs then incomplete).
+__device__ __forceinline__ bool lane_combine(const double* E1, const RicLayout& l1, const double* E2,
+                                             const RicLayout& l2, double* Eo, const RicLayout& lo, int ds, int dm,
+                                             int de, bool binary, double* rlog) {
+  if (dm == 0) {  // empty middle: J = J1, eta = eta1, A = 0, b = b2, C = C2 (the LU form's result)
+    double M[kLD][kLD];
+    lc_load(M, E1 + l1.J, ds, ds, ds, false);
+    lc_store(Eo + lo.J, M, ds, ds, ds);
+#pragma unroll
+    for (int i = 0; i < kLD; ++i)
+      if (i < ds) Eo[lo.eta + i] = E1[l1.eta + i];
+    if (binary) {
+#pragma unroll
+      for (int i = 0; i < kLD; ++i) {
+        if (i < de) Eo[lo.b + i] = E2[l2.b + i];
+#pragma unroll
+        for (int j = 0; j < kLD; ++j)
+          if (i < de && j < ds) Eo[lo.A + i * ds + j] = 0.0;
+      }
+      lc_load(M, E2 + l2.C, de, de, de, false);
+      lc_store(Eo + lo.C, M, de, de, de);
+    }
+    rlog[0] = 2.0;
+    return true;
+  }
+  double J2[kLD][kLD], L[kLD][kLD], Rg[kLD][kLD];
+  lc_load(J2, E2 + l2.J, dm, dm, dm, true);
+  double mx = 0.0;
+#pragma unroll
+  for (int i = 0; i < kLD; ++i)
+    if (i < dm) mx = fmax(mx, J2[i][i]);
+  if (!(mx > 0.0)) return false;
+#pragma unroll
+  for (int i = 0; i < kLD; ++i)
+#pragma unroll
+    for (int j = 0; j < kLD; ++j) L[i][j] = J2[i][j];
+  if (!lc_chol(L, dm, 1e-15 * mx)) return false;
+  {
+    // G = I + L'(C1 L)
+    double C1[kLD][kLD], T[kLD][kLD];
+    lc_load(C1, E1 + l1.C, dm, dm, dm, false);
+#pragma unroll
+    for (int i = 0; i < kLD; ++i)
+#pragma unroll
+      for (int j = 0; j < kLD; ++j) {
+        double v = 0.0;
+#pragma unroll
+        for (int p = 0; p < kLD; ++p) v = fma(C1[i][p], L[p][j], v);
+        T[i][j] = v;
+      }
+#pragma unroll
+    for (int i = 0; i < kLD; ++i)
+#pragma unroll
+      for (int j = 0; j < kLD; ++j) {
+        double v = 0.0;
+#pragma unroll
+        for (int p = 0; p < kLD; ++p) v = fma(L[p][i], T[p][j], v);
+        Rg[i][j] = v + ((i == j) ? 1.0 : 0.0);
+      }
+  }
+  lc_sym(Rg);
+  if (!lc_chol(Rg, dm, 0.0)) return false;
+  lc_store(rlog + 4, L, dm, dm, dm);
+  lc_store(rlog + 4 + dm * dm, Rg, dm, dm, dm);
+  rlog[0] = 1.0;
+  // xi = L^{-1} eta2 ; d = G^{-1}(xi - L'b1) ; w = L d
+  double xi[kLD], dv[kLD], wv[kLD];
+#pragma unroll
+  for (int i = 0; i < kLD; ++i) xi[i] = (i < dm) ? E2[l2.eta + i] : 0.0;
+  lc_fwd(L, xi);
+  {
+    double b1[kLD];
+#pragma unroll
+    for (int i = 0; i < kLD; ++i) b1[i] = (i < dm) ? E1[l1.b + i] : 0.0;
+#pragma unroll
+    for (int i = 0; i < kLD; ++i) {
+      double v = xi[i];
+#pragma unroll
+      for (int j = i; j < kLD; ++j) v = fma(-L[j][i], b1[j], v);
+      dv[i] = v;
+    }
+  }
+  lc_fwd(Rg, dv);
+  lc_bwd(Rg, dv);
+#pragma unroll
+  for (int i = 0; i < kLD; ++i) {
+    double v = 0.0;
+#pragma unroll
+    for (int p = 0; p <= i; ++p) v = fma(L[i][p], dv[p], v);
+    wv[i] = v;
+  }
+  double A1[kLD][kLD], Yb[kLD][kLD];
+  lc_load(A1, E1 + l1.A, dm, ds, ds, false);
+#pragma unroll
+  for (int c = 0; c < kLD; ++c) {
+    double v = 0.0;
+#pragma unroll
+    for (int j = 0; j < kLD; ++j) v = fma(A1[j][c], wv[j], v);
+    if (c < ds) Eo[lo.eta + c] = E1[l1.eta + c] + v;
+  }
+  // Yb = Rg^{-1} L' A1 ; J = J1 + Yb'Yb
+  {
+    double Mm[kLD][kLD];
+#pragma unroll
+    for (int c = 0; c < kLD; ++c) {
+      double col[kLD];
+#pragma unroll
+      for (int r = 0; r < kLD; ++r) col[r] = L[c][r];
+      lc_fwd(Rg, col);
+#pragma unroll
+      for (int r = 0; r < kLD; ++r) Mm[r][c] = col[r];
+    }
+#pragma unroll
+    for (int i = 0; i < kLD; ++i)
+#pragma unroll
+      for (int c = 0; c < kLD; ++c) {
+        double v = 0.0;
+#pragma unroll
+        for (int j = 0; j < kLD; ++j) v = fma(Mm[i][j], A1[j][c], v);
+        Yb[i][c] = v;
+      }
+  }
+  {
+    double Jo[kLD][kLD];
+    lc_load(Jo, E1 + l1.J, ds, ds, ds, false);
+#pragma unroll
+    for (int a = 0; a < kLD; ++a)
+#pragma unroll
+      for (int b = 0; b < kLD; ++b) {
+        double v = 0.0;
+#pragma unroll
+        for (int i = 0; i < kLD; ++i) v = fma(Yb[i][a], Yb[i][b], v);
+        Jo[a][b] += v;
+      }
+    lc_sym(Jo);
+    lc_store(Eo + lo.J, Jo, ds, ds, ds);
+  }
+  if (!binary) return true;
+  // [Yb | xi - d] <- L^{-T} [Rg^{-T} Yb | xi - d] ; A = A2 Yb ; b = b2 + A2 (.)
+  double yv[kLD];
+#pragma unroll
+  for (int i = 0; i < kLD; ++i) yv[i] = xi[i] - dv[i];
+#pragma unroll
+  for (int c = 0; c < kLD; ++c) {
+    double col[kLD];
+#pragma unroll
+    for (int r = 0; r < kLD; ++r) col[r] = Yb[r][c];
+    lc_bwd(Rg, col);
+    lc_bwd(L, col);
+#pragma unroll
+    for (int r = 0; r < kLD; ++r) Yb[r][c] = col[r];
+  }
+  lc_bwd(L, yv);
+  double A2[kLD][kLD];
+  lc_load(A2, E2 + l2.A, de, dm, dm, false);
+#pragma unroll
+  for (int r = 0; r < kLD; ++r) {
+#pragma unroll
+    for (int c = 0; c < kLD; ++c) {
+      double v = 0.0;
+#pragma unroll
+      for (int i = 0; i < kLD; ++i) v = fma(A2[r][i], Yb[i][c], v);
+      if (r < de && c < ds) Eo[lo.A + r * ds + c] = v;
+    }
+    double v = 0.0;
+#pragma unroll
+    for (int i = 0; i < kLD; ++i) v = fma(A2[r][i], yv[i], v);
+    if (r < de) Eo[lo.b + r] = E2[l2.b + r] + v;
+  }
+  // C = C2 + (A2 K R2^{-T})(A2 K R2^{-T})' with C1 = K K' (pivoted Cholesky, tol 1e-15)
+  double K[kLD][kLD];
+  int rk = 0;
+  {
+    double C1[kLD][kLD], rm[kLD];
+    bool done[kLD];
+    lc_load(C1, E1 + l1.C, dm, dm, dm, false);
+    double ref = 0.0;
+#pragma unroll
+    for (int i = 0; i < kLD; ++i) {
+      rm[i] = C1[i][i];
+      done[i] = i >= dm;
+      if (i < dm) ref = fmax(ref, rm[i]);
+#pragma unroll
+      for (int j = 0; j < kLD; ++j) K[i][j] = 0.0;
+    }
+    bool go = true;
+#pragma unroll
+    for (int j = 0; j < kLD; ++j) {
+      double bv = 0.0;
+      int best = -1;
+#pragma unroll
+      for (int i = 0; i < kLD; ++i)
+        if (!done[i] && (best < 0 || rm[i] > bv)) {
+          bv = rm[i];
+          best = i;
+        }
+      go = go && best >= 0 && bv > 1e-15 * ref && bv > 0.0;
+      if (go) {
+        const double dp = sqrt(bv);
+        double kp[kLD];  // row `best` of K (columns < j)
+#pragma unroll
+        for (int l = 0; l < kLD; ++l) {
+          double v = 0.0;
+#pragma unroll
+          for (int i = 0; i < kLD; ++i) v = (i == best) ? K[i][l] : v;
+          kp[l] = v;
+        }
+#pragma unroll
+        for (int i = 0; i < kLD; ++i) {
+          double cib = 0.0;
+#pragma unroll
+          for (int q = 0; q < kLD; ++q) cib = (q == best) ? C1[i][q] : cib;
+          double v = 0.0;
+          if (i == best) {
+            v = dp;
+          } else if (!done[i]) {
+            v = cib;
+#pragma unroll
+            for (int l = 0; l < j; ++l) v = fma(-K[i][l], kp[l], v);
+            v = v / dp;
+          }
+          K[i][j] = v;
+          done[i] = done[i] || (i == best);
+          if (!done[i]) rm[i] = fma(-v, v, rm[i]);
+        }
+        rk = j + 1;
+      }
+    }
+  }
+  double Co[kLD][kLD];
+  lc_load(Co, E2 + l2.C, de, de, de, false);
+  if (rk > 0) {
+    // G2 = I + K' J2 K = R2 R2'
+    double G2[kLD][kLD];
+    {
+      double T[kLD][kLD];
+#pragma unroll
+      for (int i = 0; i < kLD; ++i)
+#pragma unroll
+        for (int j = 0; j < kLD; ++j) {
+          double v = 0.0;
+#pragma unroll
+          for (int p = 0; p < kLD; ++p)
+            if (p < dm) v = fma(J2[i][p], K[p][j], v);
+          T[i][j] = (i < dm) ? v : 0.0;
+        }
+#pragma unroll
+      for (int i = 0; i < kLD; ++i)
+#pragma unroll
+        for (int j = 0; j < kLD; ++j) {
+          double v = 0.0;
+#pragma unroll
+          for (int p = 0; p < kLD; ++p) v = fma(K[p][i], T[p][j], v);
+          G2[i][j] = v + ((i == j) ? 1.0 : 0.0);
+        }
+    }
+    lc_sym(G2);
+    if (!lc_chol(G2, rk, 0.0)) return false;
+    // AN = A2 K R2^{-T} (rows of (R2^{-1} K')' ), C += AN AN'
+    double AN[kLD][kLD];
+#pragma unroll
+    for (int r = 0; r < kLD; ++r) {
+      double v[kLD];
+#pragma unroll
+      for (int j = 0; j < kLD; ++j) {
+        double a = 0.0;
+#pragma unroll
+        for (int i = 0; i < kLD; ++i) a = fma(A2[r][i], K[i][j], a);
+        v[j] = a;
+      }
+      lc_fwd(G2, v);  // row r of A2 K times R2^{-T}: solve R2 y = (A2 K)_r'
+#pragma unroll
+      for (int j = 0; j < kLD; ++j) AN[r][j] = v[j];
+    }
+#pragma unroll
+    for (int a = 0; a < kLD; ++a)
+#pragma unroll
+      for (int b = 0; b < kLD; ++b) {
+        double v = 0.0;
+#pragma unroll
+        for (int j = 0; j < kLD; ++j) v = fma(AN[a][j], AN[b][j], v);
+        Co[a][b] += v;
+      }
+  }
+  lc_sym(Co);
+  lc_store(Eo + lo.C, Co, de, de, de);
+  return true;
+}
+
 }  // namespace
 
 // Copy the used part of a value-function element with reduced dims (na, nb)
@@ -312,6 +685,63 @@ __global__ void __launch_bounds__(kBlock, 1) k_ric_combine(DevEngine e, int64_t 
         combine_lu<false>(A1, b1, C1, et1, J1, A2, b2, C2, et2, J2, Eo, lo, ds, dm, de, binary, pool, piv, sh, rlog);
     }
     (void)status;
+  }
+}
+
+// Value-function combines of a level, one lane per task where every reduced
+// dim is <= 4 (lane_combine); the tasks of a tile of 64 that do not qualify,
+// or fail a factorization test there, are combined by the whole wavefront
+// (global work pool).
+__global__ void __launch_bounds__(kBlock) k_ric_combine_lane(DevEngine e, int64_t first, int64_t ntasks) {
+  __shared__ int piv[kMaxDim];
+  __shared__ double sh[16];
+  __shared__ double buf[kMaxDim];
+  const int lane = ECLQR_TID;
+  for (int64_t t0 = (int64_t)blockIdx.x * kBlock; t0 < ntasks; t0 += (int64_t)gridDim.x * kBlock) {
+    const int64_t ti = t0 + lane;
+    bool need = false;
+    if (ti < ntasks) {
+      const int a = e.tasks[3 * (first + ti)];
+      const int bsl = e.tasks[3 * (first + ti) + 1];
+      const int o = e.tasks[3 * (first + ti) + 2];
+      const int sa = slot_a(e, 0, a), sm = slot_b(e, 0, a), se = slot_b(e, 0, bsl);
+      if (!gated(e, e.st[sa].inst)) {
+        const int ds = e.nbar[sa], dm = e.nbar[sm], de = (se >= 0) ? e.nbar[se] : 0;
+        need = true;
+        if (ds <= kLD && dm <= kLD && de <= kLD) {
+          const int ns = e.st[sa].n, nm = e.st[sm].n, ne = (se >= 0) ? e.st[se].n : 0;
+          const RicLayout l1 = ric_layout(ns, nm), l2 = ric_layout(nm, ne), lo = ric_layout(ns, ne);
+          need = !lane_combine(slot_ptr(e, SCAN_RIC, a), l1, slot_ptr(e, SCAN_RIC, bsl), l2, slot_ptr(e, SCAN_RIC, o),
+                               lo, ds, dm, de, se >= 0, e.ric_log + e.ric_log_off[o]);
+        }
+      }
+    }
+    // the rest, one task at a time by the whole wavefront
+    unsigned long long rest = __ballot(need);
+    while (rest) {
+      const int l = __ffsll((long long)rest) - 1;
+      rest &= rest - 1;
+      const int64_t tj = t0 + l;
+      const int a = e.tasks[3 * (first + tj)];
+      const int bsl = e.tasks[3 * (first + tj) + 1];
+      const int o = e.tasks[3 * (first + tj) + 2];
+      const int sa = slot_a(e, 0, a), sm = slot_b(e, 0, a), se = slot_b(e, 0, bsl);
+      const int ds = e.nbar[sa], dm = e.nbar[sm], de = (se >= 0) ? e.nbar[se] : 0;
+      const int ns = e.st[sa].n, nm = e.st[sm].n, ne = (se >= 0) ? e.st[se].n : 0;
+      const RicLayout l1 = ric_layout(ns, nm), l2 = ric_layout(nm, ne), lo = ric_layout(ns, ne);
+      const double* E1 = slot_ptr(e, SCAN_RIC, a);
+      const double* E2 = slot_ptr(e, SCAN_RIC, bsl);
+      double* Eo = slot_ptr(e, SCAN_RIC, o);
+      const double *A1 = E1 + l1.A, *b1 = E1 + l1.b, *C1 = E1 + l1.C, *et1 = E1 + l1.eta, *J1 = E1 + l1.J;
+      const double *A2 = E2 + l2.A, *b2 = E2 + l2.b, *C2 = E2 + l2.C, *et2 = E2 + l2.eta, *J2 = E2 + l2.J;
+      double* rlog = e.ric_log + e.ric_log_off[o];
+      double* pool = block_scratch(e);
+      wg_sync();
+      if (!combine_factored<false, 0>(A1, b1, C1, et1, J1, A2, b2, C2, et2, J2, Eo, lo, ds, dm, de, se >= 0, pool, piv,
+                                      sh, rlog, buf))
+        combine_lu<false>(A1, b1, C1, et1, J1, A2, b2, C2, et2, J2, Eo, lo, ds, dm, de, se >= 0, pool, piv, sh, rlog);
+      wg_sync();
+    }
   }
 }
 
@@ -520,6 +950,13 @@ void launch_ric_combine(const DevEngine& e, int64_t first, int64_t ntasks, int32
   else
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ric_combine<0, 0>), dim3(grid), dim3(kBlock), lds, s, e, first, ntasks,
                        status, maxd);
+}
+
+void launch_ric_combine_lane(const DevEngine& e, int64_t first, int64_t ntasks, hipStream_t s) {
+  if (ntasks <= 0) return;
+  const int64_t tiles = (ntasks + kBlock - 1) / kBlock;
+  const int grid = (int)(tiles < e.nblocks ? tiles : e.nblocks);
+  hipLaunchKernelGGL(k_ric_combine_lane, dim3(grid), dim3(kBlock), 0, s, e, first, ntasks);
 }
 
 void launch_gains(const DevEngine& e, int32_t* status, int maxm, int maxn, hipStream_t s) {
