@@ -417,7 +417,7 @@ eclqr_status theta_multipliers(Plan& p, const Views& v, const Inputs& in, const 
   const Tols td{p.opt.rank_tol, p.opt.dual_cons_tol, 0};
   {
     Timed tm(ECLQR_K_MULT_THETA, s);
-    if (!launch_theta_local(v.P, v.T, in, x, u, td, status, p.th_q, p.th_ldw, p.th_r, s))
+    if (!launch_theta_local(v.P, v.T, in, x, u, td, status, p.th_q, p.th_ldw, p.th_r, !full, s))
       return fail(ECLQR_UNSUPPORTED, "stage too large for the LDS tile of the minimum-norm local systems");
   }
   for (int l = 0; l < 2 * T.D; ++l) {

@@ -299,6 +299,11 @@ size_t theta_local_lds_bytes(int maxq, int ldw, int maxr) {
          sizeof(int) * (size_t)(ldw + 1) + 64;
 }
 
+// kVec: vector-only pass for new vectors with the same matrices (refinement
+// corrections, the adjoint): a stage other than the terminal one reuses the
+// factors the full pass kept (pivots, R11, Q1) and recomputes only y and the
+// vector parts of its element.
+template <bool kVec>
 __global__ void __launch_bounds__(kBlock) k_theta_local(DevEngine p, DevEngine th, Inputs in, const double* x,
                                                         const double* u, Tols t, int32_t* status, int maxq, int ldw,
                                                         int maxr) {
@@ -357,6 +362,46 @@ __global__ void __launch_bounds__(kBlock) k_theta_local(DevEngine p, DevEngine t
     const double* B = term ? nullptr : in.f[IN_B] + st.in[IN_B];
     const double* F = term ? nullptr : in.f[IN_F] + st.in[IN_F];
     const int q = k + r1, Rr = n + m;
+    // constant right-hand side: [w_i - g^x - A'w_{i+1}; -g^u - B'w_{i+1}]
+    for (int row = ECLQR_TID; row < Rr; row += ECLQR_NT) {
+      double v;
+      if (row < n) {
+        v = wi[row] - gx[row];
+        if (!term) v = lane_chain<true>(v, A + row, n, w1, 1, n1);
+      } else {
+        v = lane_chain<true>(-gu[row - n], B + (row - n), m, w1, 1, n1);
+      }
+      cr[row] = v;
+    }
+    if (kVec && !term) {
+      const Arena at = arena_layout(ts.n, ts.np, ts.m, ts.k);
+      double* tb = th.arena + ts.ws;
+      const int f = th.mbar[s], rho = q - f;
+      lds_sync();
+      // z = R11^{-T} (P'c)_{1:rho}, y = Q1 z
+      const int lane = ECLQR_TID;
+      double zv = (lane < rho) ? cr[(int)tb[at.prm + lane]] : 0.0;
+      zv = lane_trsv_upper_t(tb + at.R11, rho, zv, rho);
+      if (lane < rho) tmp[lane] = zv;
+      lds_sync();
+      for (int i = lane; i < q; i += ECLQR_NT) Yl[i] = lane_chain<false>(0.0, tb + at.Q1 + i * rho, 1, tmp, 1, rho);
+      lds_sync();
+      for (int i = lane; i < q; i += ECLQR_NT) tb[at.y + i] = Yl[i];
+      for (int a = lane; a < n; a += ECLQR_NT) tb[at.wl + a] = wi[a];
+      const RicLayout rl = ric_layout(ts.n, ts.np);
+      double* ric = slot_ptr(th, SCAN_RIC, ts.elem[SCAN_RIC]);
+      for (int l = lane; l < r1; l += ECLQR_NT) {
+        tb[at.cb + l] = Yl[k + l];
+        ric[rl.b + l] = Yl[k + l];
+      }
+      for (int c = lane; c < ri; c += ECLQR_NT) {
+        const double v = lane_chain<false>(0.0, tb + at.Y + c, ri, Yl, 1, q);
+        tb[at.qb + c] = v;
+        ric[rl.eta + c] = -v;
+      }
+      wg_sync();
+      continue;
+    }
     // W = M' (q x Rr): row col of W is column col of M (a multiplier unknown)
     for (int idx = ECLQR_TID; idx < q * Rr; idx += ECLQR_NT) {
       const int col = idx / Rr, row = idx - (idx / Rr) * Rr;
@@ -371,17 +416,6 @@ __global__ void __launch_bounds__(kBlock) k_theta_local(DevEngine p, DevEngine t
                : lane_chain<false>(0.0, H1 + l * (n1 + 1), 1, B + a, m, n1);
       }
       W[col * ldw + row] = v;
-    }
-    // constant right-hand side: [w_i - g^x - A'w_{i+1}; -g^u - B'w_{i+1}]
-    for (int row = ECLQR_TID; row < Rr; row += ECLQR_NT) {
-      double v;
-      if (row < n) {
-        v = wi[row] - gx[row];
-        if (!term) v = lane_chain<true>(v, A + row, n, w1, 1, n1);
-      } else {
-        v = lane_chain<true>(-gu[row - n], B + (row - n), m, w1, 1, n1);
-      }
-      cr[row] = v;
     }
     wg_sync();
     const int rho = wg_qr_colpiv(W, ldw, q, Rr, 0, Rr, t.rank, tau, QRScratch{qd, perm});
@@ -427,6 +461,13 @@ __global__ void __launch_bounds__(kBlock) k_theta_local(DevEngine p, DevEngine t
     if (!term) {
       double* Na = tb + at.Z;
       for (int idx = ECLQR_TID; idx < q * f; idx += ECLQR_NT) Na[idx] = Qg[(idx / f) * q + rho + idx % f];
+      // factors of the minimum-norm solve, for the vector-only passes
+      for (int j = ECLQR_TID; j < rho; j += ECLQR_NT) tb[at.prm + j] = (double)perm[j];
+      for (int idx = ECLQR_TID; idx < rho * rho; idx += ECLQR_NT) {
+        const int i = idx / rho, j = idx - (idx / rho) * rho;
+        tb[at.R11 + idx] = (j >= i) ? W[i * ldw + j] : 0.0;
+      }
+      for (int idx = ECLQR_TID; idx < q * rho; idx += ECLQR_NT) tb[at.Q1 + idx] = Qg[(idx / rho) * q + idx % rho];
     }
     for (int a = ECLQR_TID; a < n; a += ECLQR_NT) tb[at.wl + a] = wi[a];
     // reduced LQR data and the value-function element
@@ -537,15 +578,21 @@ __global__ void __launch_bounds__(kBlock) k_theta_final(DevEngine p, DevEngine t
 static int g_theta_max_lds = 65536;
 void theta_set_max_lds(int bytes) {
   g_theta_max_lds = bytes;
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_theta_local), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            bytes);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_theta_local<false>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_theta_local<true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 bool launch_theta_local(const DevEngine& p, const DevEngine& th, const Inputs& in, const double* x, const double* u,
-                        Tols t, int32_t* status, int maxq, int ldw, int maxr, hipStream_t s) {
+                        Tols t, int32_t* status, int maxq, int ldw, int maxr, bool vec, hipStream_t s) {
   const size_t lds = theta_local_lds_bytes(maxq, ldw, maxr);
   if (lds > (size_t)g_theta_max_lds) return false;
-  hipLaunchKernelGGL(k_theta_local, dim3(p.nblocks), dim3(kBlock), lds, s, p, th, in, x, u, t, status, maxq, ldw,
-                     maxr);
+  if (vec)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_theta_local<true>), dim3(p.nblocks), dim3(kBlock), lds, s, p, th, in, x, u,
+                       t, status, maxq, ldw, maxr);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_theta_local<false>), dim3(p.nblocks), dim3(kBlock), lds, s, p, th, in, x,
+                       u, t, status, maxq, ldw, maxr);
   return true;
 }
 void launch_theta_init(const DevEngine& th, hipStream_t s) {

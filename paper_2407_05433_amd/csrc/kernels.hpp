@@ -153,8 +153,9 @@ void launch_mult_final(const DevEngine& e, double* lam, double* mu, int accumula
 // the theta engine over the same schedule)
 void theta_set_max_lds(int bytes);
 size_t theta_local_lds_bytes(int maxq, int ldw, int maxr);
+// vec: reuse the local factors of the last full pass (new vectors, same matrices)
 bool launch_theta_local(const DevEngine& p, const DevEngine& th, const Inputs& in, const double* x, const double* u,
-                        Tols t, int32_t* status, int maxq, int ldw, int maxr, hipStream_t s);
+                        Tols t, int32_t* status, int maxq, int ldw, int maxr, bool vec, hipStream_t s);
 void launch_theta_init(const DevEngine& th, hipStream_t s);
 void launch_theta_final(const DevEngine& p, const DevEngine& th, double* lam, double* mu, int accumulate,
                         hipStream_t s);
