@@ -113,7 +113,11 @@ typedef struct {
                            * ECLQR_DUAL_FAILED */
   int32_t use_graph;      /* 1: capture the launch sequence of eclqr_solve once per set of pointers and
                            * replay it as a hipGraph; 0 */
-  int32_t reserved[5];
+  int32_t scan_schedule;  /* parenthesization of the associative scans (Proposition 1 allows any): 1 balanced
+                           * up/down sweep (about 2 L tasks in 2 log2 L levels per instance of L = N + 1
+                           * leaves); 2 recursive doubling (about L log2 L tasks in log2 L levels); 0 (default)
+                           * doubling while the batch has at most 2048 leaves, else balanced */
+  int32_t reserved[4];
 } eclqr_options;
 
 /* Device pointers to the problem data (layout from eclqr_plan_layout).  M may

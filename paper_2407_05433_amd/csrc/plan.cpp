@@ -7,6 +7,13 @@
 // scan": an up-sweep composing interval aggregates, a down-sweep handing each
 // interval the aggregate to its right) serves all three; only the slot sizes
 // differ.  Tasks of every instance at the same level form one launch.
+//
+// Recursive doubling is the depth-optimal alternative: at level l every leaf
+// j with j + 2^l < L combines its interval [j, j + 2^l) with [j + 2^l,
+// min(j + 2^(l+1), L)); after ceil(log2 L) levels leaf j holds [j, L).  It has
+// half the levels of the balanced sweep (no down-sweep) and about L log2 L
+// tasks instead of 2L, so it wins while one level's tasks fit on the device
+// at once (small problems, latency-bound) and loses on large batches.
 #include "plan.hpp"
 #include "scratch.hpp"
 
@@ -120,6 +127,43 @@ std::string Engine::build(const eclqr_dims* d) {
       const StageInfo& x = st[s0 + j];
       int cap = (j < N[b]) ? std::min(x.np + x.k, x.n + x.np) : std::min(x.k, x.n);
       lv[0].push_back({j, j + 1, new_slot(b, j, j + 1, cap)});
+    }
+    if (doubling) {
+      std::vector<int32_t> cur(L), cend(L);
+      for (int j = 0; j < L; ++j) {
+        cur[j] = lv[0][j].slot;
+        cend[j] = j + 1;
+      }
+      int lev = 0;
+      for (int span = 1; span < L; span *= 2, ++lev) {
+        if ((int)up_lv.size() <= lev) up_lv.emplace_back();
+        std::vector<int32_t> nxt(cur), nend(cend);
+        for (int j = 0; j + span < L; ++j) {
+          const int mid = cend[j], e = cend[mid];
+          int na, nb;
+          rel_dims(j, e, na, nb);
+          const int cap = std::min(slot_cap[cur[j]] + slot_cap[cur[mid]], na + nb);
+          const int slot = new_slot(b, j, e, cap);
+          up_lv[lev].insert(up_lv[lev].end(), {cur[j], cur[mid], slot});
+          nxt[j] = slot;
+          nend[j] = e;
+        }
+        cur.swap(nxt);
+        cend.swap(nend);
+      }
+      D = std::max(D, lev);
+      for (int j = 0; j < L; ++j) {
+        if (cend[j] != L) return "internal error: doubling left an interval short of the end";
+        StageInfo& x = st[s0 + j];
+        x.elem[SCAN_REL] = x.elem[SCAN_RIC] = lv[0][j].slot;
+        x.suf[SCAN_REL] = x.suf[SCAN_RIC] = cur[j];
+      }
+      for (int j = 0; j < L; ++j) {
+        StageInfo& x = st[s0 + j];
+        x.elem[SCAN_FWD] = (j < N[b]) ? lv[0][N[b] - 1 - j].slot : -1;
+        x.suf[SCAN_FWD] = cur[N[b] - j];
+      }
+      continue;
     }
     int lev = 0;
     while (lv[lev].size() > 1) {
@@ -397,6 +441,15 @@ std::string Engine::build(const eclqr_dims* d) {
 
 std::string build_plan(Plan& p, const eclqr_dims* d, const eclqr_options* opt) {
   p.opt = *opt;
+  if (opt->scan_schedule < 0 || opt->scan_schedule > 2) return "scan_schedule must be 0, 1 or 2";
+  {
+    // automatic: recursive doubling while the leaves of the whole batch fit
+    // the device in one level (each task is one wavefront)
+    int64_t leaves = 0;
+    for (int b = 0; b < d->batch; ++b) leaves += (int64_t)d->horizon[b] + 1;
+    const bool dbl = opt->scan_schedule == 2 || (opt->scan_schedule == 0 && leaves <= 2048);
+    p.primal.doubling = p.dual.doubling = p.theta.doubling = dbl;
+  }
   std::string err = p.primal.build(d);
   if (!err.empty()) return err;
   const Engine& P = p.primal;

@@ -91,20 +91,41 @@ def _replay_schedule(plan, problem):
     return rel, levels, D
 
 
+@pytest.mark.parametrize("schedule", [1, 2])
 @pytest.mark.parametrize("N", [1, 2, 3, 5, 8, 13, 16])
-def test_schedule_reproduces_sequential_suffixes(N):
+def test_schedule_reproduces_sequential_suffixes(N, schedule):
+    """Both parenthesizations (balanced up/down sweep, recursive doubling)
+    compose the oracle's base relations into the sequential suffixes
+    (Proposition 1)."""
     from oracle import solve_sequential
     from oracle.relations import same_set
     p = tiny_problem(800 + N, N=N, n=3, m=1, kinds=[["state"]] * N, terminal_rows=2)
-    plan = ecl.Plan.for_problems([p])
+    plan = ecl.Plan.for_problems([p], scan_schedule=schedule)
     rel, levels, D = _replay_schedule(plan, p)
     assert D == max(1, int(np.ceil(np.log2(N + 1))))
     seq = solve_sequential(p, keep_relations=True)
     # every leaf's suffix slot must hold S_i; locate it through the stage table
     # (slots are leaves 0..N, then internal / suffix slots in allocation order)
-    leaf_suffix = _leaf_suffix_slots(plan, N)
+    leaf_suffix = _leaf_suffix_slots(plan, N) if schedule == 1 else _doubling_suffix_slots(plan, N)
     for i in range(N + 1):
         assert same_set(rel[leaf_suffix[i]], seq.suffix[i], tol=1e-9), i
+    if schedule == 2:
+        L = N + 1
+        assert all(len(lv) == 0 for lv in levels[D:])  # no down-sweep
+        assert [len(lv) for lv in levels[:D]] == [L - 2 ** l for l in range(D)]
+
+
+def _doubling_suffix_slots(plan, N):
+    """Recursive doubling: the last output whose left operand starts at leaf
+    i covers [i, L); the terminal leaf is its own suffix."""
+    levels = plan.schedule()
+    start = {i: i for i in range(N + 1)}
+    suf = {i: i for i in range(N + 1)}
+    for lv in levels:
+        for a, b, o in lv:
+            start[int(o)] = start[int(a)]
+            suf[start[int(a)]] = int(o)
+    return suf
 
 
 def _leaf_suffix_slots(plan, N):
@@ -137,7 +158,7 @@ def _leaf_suffix_slots(plan, N):
 def test_batched_schedule_levels_merge_instances():
     probs = [tiny_problem(900 + s, N=N, n=2, m=1, kinds=[[]] * N, terminal_rows=0) for s, N in
              enumerate([3, 17, 1, 64])]
-    plan = ecl.Plan.for_problems(probs)
+    plan = ecl.Plan.for_problems(probs, scan_schedule=1)
     levels = plan.schedule()
     D = len(levels) // 2
     assert D == 7  # ceil(log2(65))

@@ -98,6 +98,21 @@ def test_reversed_time_multiplier_route():
     check_parity(probs, gpu_solve(probs, tuning={"multiplier_route": 0}))
 
 
+def test_both_scan_schedules():
+    """Small problems default to recursive doubling; the balanced up/down
+    sweep (scan_schedule = 1) on the same cases, and doubling forced on a
+    batch that would default to the balanced sweep."""
+    _need_gpu()
+    from tests._util import problem_family
+    from workloads import config_c0, config_c3
+    fam = [p for _, p in problem_family()]
+    probs = config_c0()
+    check_parity(probs, gpu_solve(probs, scan_schedule=1))
+    check_parity(fam, gpu_solve(fam, scan_schedule=1))
+    probs = config_c3(B=12, N_range=(150, 250))
+    check_parity(probs, gpu_solve(probs, scan_schedule=2), idx=range(0, 12, 3))
+
+
 def test_structural_family_single_and_batched():
     _need_gpu()
     from tests._util import problem_family
