@@ -247,6 +247,8 @@ def main():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--graph", type=int, default=1, help="replay the solve as a captured hipGraph (1) or launch eagerly (0)")
     ap.add_argument("--autotune", type=int, default=1, help="choose the launch configuration by timing first (untimed)")
+    ap.add_argument("--scan-schedule", type=int, default=0, choices=(0, 1, 2),
+                    help="scan parenthesization: 0 automatic, 1 balanced up/down sweep, 2 recursive doubling")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device once (reference for hardware byte counters) and exit")
     args = ap.parse_args()
@@ -270,7 +272,7 @@ def main():
 
     log(f"[bench] generating {args.workload}")
     problems = make(args.workload)
-    plan = ecl.Plan.for_problems(problems, use_graph=args.graph)
+    plan = ecl.Plan.for_problems(problems, use_graph=args.graph, scan_schedule=args.scan_schedule)
     data = ecl.pack(plan, problems)
     ws = plan.workspace()
     sol = ecl.allocate_solution(plan)
@@ -318,6 +320,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "instances": len(problems),
                    "stages": stages, "multipliers": True, "launch": tuning,
+                   "scan_schedule": "doubling" if all(len(lv) == 0 for lv in plan.schedule()[len(plan.schedule()) // 2:])
+                   else "balanced",
                    "refine": {"max_steps": int(plan.options.refine), "tol": float(plan.options.refine_tol),
                               "steps_taken": {str(int(k)): int(v) for k, v in zip(*np.unique(rsteps, return_counts=True))}}},
         "roofline": roof,

@@ -116,7 +116,9 @@ typedef struct {
   int32_t scan_schedule;  /* parenthesization of the associative scans (Proposition 1 allows any): 1 balanced
                            * up/down sweep (about 2 L tasks in 2 log2 L levels per instance of L = N + 1
                            * leaves); 2 recursive doubling (about L log2 L tasks in log2 L levels); 0 (default)
-                           * doubling while the batch has at most 2048 leaves, else balanced */
+                           * hybrid: the fewest balanced up-sweep levels after which the batch has at most 2048
+                           * interval nodes (512 when a state dim exceeds 16), doubling over those nodes, then
+                           * the balanced down-sweep (pure doubling for up to 2048 leaves) */
   int32_t reserved[4];
 } eclqr_options;
 

@@ -8,12 +8,14 @@
 // interval the aggregate to its right) serves all three; only the slot sizes
 // differ.  Tasks of every instance at the same level form one launch.
 //
-// Recursive doubling is the depth-optimal alternative: at level l every leaf
-// j with j + 2^l < L combines its interval [j, j + 2^l) with [j + 2^l,
-// min(j + 2^(l+1), L)); after ceil(log2 L) levels leaf j holds [j, L).  It has
-// half the levels of the balanced sweep (no down-sweep) and about L log2 L
-// tasks instead of 2L, so it wins while one level's tasks fit on the device
-// at once (small problems, latency-bound) and loses on large batches.
+// Recursive doubling is the depth-optimal alternative: at level l every node
+// j with j + 2^l < K combines its interval with the one 2^l nodes to its
+// right; after ceil(log2 K) levels node j covers [start_j, L).  It has no
+// down-sweep and about K log2 K tasks instead of 2K, so it wins while a
+// level's tasks fit on the device at once and loses on wide levels.  The
+// schedule built here is the hybrid: b balanced up-sweep levels (K = the
+// nodes left), doubling over those K nodes, then the b balanced down-sweep
+// levels.  b = 0 is pure doubling, b >= depth the plain balanced sweep.
 #include "plan.hpp"
 #include "scratch.hpp"
 
@@ -114,6 +116,11 @@ std::string Engine::build(const eclqr_dims* d) {
     slot_cap.push_back(cap);
     return nslots++;
   };
+  // balanced levels before the doubling phase (every instance the same, so
+  // levels stay aligned across the batch): all of them for the balanced
+  // schedule, none for pure doubling
+  const int bal_levels = bal_levels_;
+  std::vector<int32_t> top_suffix;
   for (int b = 0; b < B; ++b) {
     const int L = N[b] + 1;
     const int64_t s0 = sbase[b];
@@ -128,45 +135,8 @@ std::string Engine::build(const eclqr_dims* d) {
       int cap = (j < N[b]) ? std::min(x.np + x.k, x.n + x.np) : std::min(x.k, x.n);
       lv[0].push_back({j, j + 1, new_slot(b, j, j + 1, cap)});
     }
-    if (doubling) {
-      std::vector<int32_t> cur(L), cend(L);
-      for (int j = 0; j < L; ++j) {
-        cur[j] = lv[0][j].slot;
-        cend[j] = j + 1;
-      }
-      int lev = 0;
-      for (int span = 1; span < L; span *= 2, ++lev) {
-        if ((int)up_lv.size() <= lev) up_lv.emplace_back();
-        std::vector<int32_t> nxt(cur), nend(cend);
-        for (int j = 0; j + span < L; ++j) {
-          const int mid = cend[j], e = cend[mid];
-          int na, nb;
-          rel_dims(j, e, na, nb);
-          const int cap = std::min(slot_cap[cur[j]] + slot_cap[cur[mid]], na + nb);
-          const int slot = new_slot(b, j, e, cap);
-          up_lv[lev].insert(up_lv[lev].end(), {cur[j], cur[mid], slot});
-          nxt[j] = slot;
-          nend[j] = e;
-        }
-        cur.swap(nxt);
-        cend.swap(nend);
-      }
-      D = std::max(D, lev);
-      for (int j = 0; j < L; ++j) {
-        if (cend[j] != L) return "internal error: doubling left an interval short of the end";
-        StageInfo& x = st[s0 + j];
-        x.elem[SCAN_REL] = x.elem[SCAN_RIC] = lv[0][j].slot;
-        x.suf[SCAN_REL] = x.suf[SCAN_RIC] = cur[j];
-      }
-      for (int j = 0; j < L; ++j) {
-        StageInfo& x = st[s0 + j];
-        x.elem[SCAN_FWD] = (j < N[b]) ? lv[0][N[b] - 1 - j].slot : -1;
-        x.suf[SCAN_FWD] = cur[N[b] - j];
-      }
-      continue;
-    }
     int lev = 0;
-    while (lv[lev].size() > 1) {
+    while (lv[lev].size() > 1 && lev < bal_levels) {
       const auto& cur = lv[lev];
       std::vector<Node> nxt;
       if ((int)up_lv.size() <= lev) up_lv.emplace_back();
@@ -187,11 +157,44 @@ std::string Engine::build(const eclqr_dims* d) {
       lv.push_back(nxt);
       ++lev;
     }
+    // recursive doubling over the nodes of the top balanced level: node j
+    // covers [top[j].s, end_j); after ceil(log2 K) levels every node reaches L
+    {
+      const std::vector<Node>& top = lv[lev];
+      const int K = (int)top.size();
+      std::vector<int32_t> cur(K), cend(K);
+      for (int j = 0; j < K; ++j) {
+        cur[j] = top[j].slot;
+        cend[j] = j + 1;  // end as a node index (K = the terminal end L)
+      }
+      int dl = lev;
+      for (int span = 1; span < K; span *= 2, ++dl) {
+        if ((int)up_lv.size() <= dl) up_lv.emplace_back();
+        std::vector<int32_t> nxt(cur), nend(cend);
+        for (int j = 0; j + span < K; ++j) {
+          const int mid = cend[j], e = cend[mid];
+          const int ee = (e == K) ? L : top[e].s;
+          int na, nb;
+          rel_dims(top[j].s, ee, na, nb);
+          const int cap = std::min(slot_cap[cur[j]] + slot_cap[cur[mid]], na + nb);
+          const int slot = new_slot(b, top[j].s, ee, cap);
+          up_lv[dl].insert(up_lv[dl].end(), {cur[j], cur[mid], slot});
+          nxt[j] = slot;
+          nend[j] = e;
+        }
+        cur.swap(nxt);
+        cend.swap(nend);
+      }
+      D = std::max(D, dl);
+      top_suffix.assign(L + 1, -1);
+      for (int j = 0; j < K; ++j) {
+        if (cend[j] != K) return "internal error: doubling left a node short of the end";
+        top_suffix[top[j].s] = cur[j];
+      }
+    }
     const int Db = lev;
-    D = std::max(D, Db);
-    // down-sweep: suffix slot of every leaf
-    std::vector<int32_t> suf(L + 1, -1);
-    suf[0] = lv[Db][0].slot;
+    // down-sweep over the balanced levels: suffix slot of every leaf
+    std::vector<int32_t> suf(top_suffix);
     for (int l = Db; l >= 1; --l) {
       const auto& par = lv[l];
       const auto& ch = lv[l - 1];
@@ -443,12 +446,24 @@ std::string build_plan(Plan& p, const eclqr_dims* d, const eclqr_options* opt) {
   p.opt = *opt;
   if (opt->scan_schedule < 0 || opt->scan_schedule > 2) return "scan_schedule must be 0, 1 or 2";
   {
-    // automatic: recursive doubling while the leaves of the whole batch fit
-    // the device in one level (each task is one wavefront)
+    // automatic: the smallest number of balanced levels after which the
+    // batch has at most as many interval nodes as the device runs combines at
+    // once (one wavefront each): 2048 up to state dim 16; 512 above, where a
+    // combine's LDS tile leaves room for one workgroup per CU
     int64_t leaves = 0;
-    for (int b = 0; b < d->batch; ++b) leaves += (int64_t)d->horizon[b] + 1;
-    const bool dbl = opt->scan_schedule == 2 || (opt->scan_schedule == 0 && leaves <= 2048);
-    p.primal.doubling = p.dual.doubling = p.theta.doubling = dbl;
+    for (int b = 0; b < d->batch; ++b) leaves += (d->horizon[b] >= 1) ? (int64_t)d->horizon[b] + 1 : 0;
+    int maxn = 0;
+    for (int64_t s = 0; s < leaves; ++s) maxn = std::max(maxn, d->nx[s]);
+    const int64_t cap_nodes = maxn <= 16 ? 2048 : 512;
+    int bl = 0;
+    for (;; ++bl) {
+      int64_t nodes = 0;
+      for (int b = 0; b < d->batch; ++b)
+        if (d->horizon[b] >= 1) nodes += (((int64_t)d->horizon[b] + 1) + (int64_t(1) << bl) - 1) >> bl;
+      if (nodes <= cap_nodes || bl >= 30) break;
+    }
+    const int lv = opt->scan_schedule == 1 ? (1 << 30) : (opt->scan_schedule == 2 ? 0 : bl);
+    p.primal.bal_levels_ = p.dual.bal_levels_ = p.theta.bal_levels_ = lv;
   }
   std::string err = p.primal.build(d);
   if (!err.empty()) return err;

@@ -59,7 +59,7 @@ struct Engine {
   int32_t base_maxp = 0, base_ldw = 0, elim_maxq = 0;
   int32_t fast_rows = 0, fast_ldw = 0;  // LDS tile of the factor-reusing multiplier kernel
   bool need_rel = true;            // false: no relation-scan arenas or logs (an engine that only runs the LQR scans)
-  bool doubling = false;           // scan schedule: false balanced up/down sweep, true recursive doubling
+  int32_t bal_levels_ = 1 << 30;   // balanced levels before recursive doubling (0: pure doubling)
   int32_t nblocks = 0;             // grid of the stage-parallel kernels
   int64_t scratch_per_block = 0;   // doubles
 

@@ -176,3 +176,38 @@ def test_c3_plan_builds_quickly():
     plan = ecl.Plan.for_problems(probs)
     assert time.time() - t < 5.0
     assert plan.batch == 64
+
+
+def test_hybrid_schedule_reproduces_sequential_suffixes():
+    """The automatic schedule on a batch of 2440 leaves: one balanced level,
+    recursive doubling over the 1240 nodes left, one balanced down level; every
+    leaf's suffix slot (the one slot covering [i, L) of its instance) holds the
+    oracle's sequential suffix S_i."""
+    from oracle import solve_sequential
+    from oracle.relations import base_relation, compose, same_set, terminal_relation
+    probs = [tiny_problem(1500 + s, N=60, n=3, m=1, kinds=[["state"]] * 60, terminal_rows=2) for s in range(40)]
+    plan = ecl.Plan.for_problems(probs)
+    inst, first, last = plan.slot_info()
+    levels = plan.schedule()
+    D = len(levels) // 2
+    # one balanced level (1200 tasks), ceil(log2 31) = 5 doubling levels over the
+    # 31 nodes per instance, one balanced down level
+    assert [len(lv) for lv in levels] == [1200, 1200, 1160, 1080, 920, 600, 0, 0, 0, 0, 0, 1200]
+    rel = {}
+    leaf0 = {}
+    for q in range(len(inst)):
+        b, i, e = int(inst[q]), int(first[q]), int(last[q])
+        if e == i + 1:
+            p = probs[b]
+            rel[q] = (base_relation(p.A[i], p.B[i], p.c[i], p.E[i], p.F[i], p.g[i]) if i < p.N
+                      else terminal_relation(p.E[p.N], p.g[p.N]))
+    for lv in levels:
+        for a, bb, o in lv:
+            rel[int(o)] = compose(rel[int(a)], rel[int(bb)])
+    for b in (0, 17, 39):
+        p = probs[b]
+        seq = solve_sequential(p, keep_relations=True)
+        for i in range(p.N + 1):
+            q = [q for q in range(len(inst)) if inst[q] == b and first[q] == i and last[q] == p.N + 1]
+            assert len(q) == 1, (b, i, q)
+            assert same_set(rel[q[0]], seq.suffix[i], tol=1e-9), (b, i)
