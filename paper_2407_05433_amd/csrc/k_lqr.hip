@@ -281,16 +281,34 @@ __device__ __forceinline__ void lc_sym(double (&S)[kLD][kLD]) {
       S[j][i] = v;
     }
 }
-// r x c block of a row-major (ld) array, zero beyond (pad_id: identity diagonal)
-__device__ __forceinline__ void lc_load(double (&M)[kLD][kLD], const double* src, int r, int c, int ld, bool pad_id) {
+// r x c block of a row-major (ld) array, zero beyond (pad_id: identity
+// diagonal).  Every lane issues all 16 loads unconditionally (indices clamped
+// into the block, or to `safe` when the block is empty) and selects
+// afterwards: a load under a lane-dependent branch would wait on its own.
+__device__ __forceinline__ void lc_load(double (&M)[kLD][kLD], const double* src, int r, int c, int ld, bool pad_id,
+                                        const double* safe) {
+  const double* base = (r > 0 && c > 0) ? src : safe;
+  double v[kLD][kLD];
 #pragma unroll
   for (int i = 0; i < kLD; ++i)
 #pragma unroll
     for (int j = 0; j < kLD; ++j) {
-      double v = (pad_id && i == j) ? 1.0 : 0.0;
-      if (i < r && j < c) v = src[i * ld + j];
-      M[i][j] = v;
+      const int ii = (i < r) ? i : 0, jj = (j < c) ? j : 0;
+      v[i][j] = base[ii * ld + jj];
     }
+#pragma unroll
+  for (int i = 0; i < kLD; ++i)
+#pragma unroll
+    for (int j = 0; j < kLD; ++j) M[i][j] = (i < r && j < c) ? v[i][j] : ((pad_id && i == j) ? 1.0 : 0.0);
+}
+// first n entries of a vector, zero beyond (same load discipline)
+__device__ __forceinline__ void lc_loadv(double (&x)[kLD], const double* src, int n, const double* safe) {
+  const double* base = (n > 0) ? src : safe;
+  double v[kLD];
+#pragma unroll
+  for (int i = 0; i < kLD; ++i) v[i] = base[(i < n) ? i : 0];
+#pragma unroll
+  for (int i = 0; i < kLD; ++i) x[i] = (i < n) ? v[i] : 0.0;
 }
 __device__ __forceinline__ void lc_store(double* dst, const double (&M)[kLD][kLD], int r, int c, int ld) {
 #pragma unroll
@@ -303,30 +321,33 @@ __device__ __forceinline__ void lc_store(double* dst, const double (&M)[kLD][kLD
 // Returns false when a factorization test fails (outputs then incomplete).
 __device__ __forceinline__ bool lane_combine(const double* E1, const RicLayout& l1, const double* E2,
                                              const RicLayout& l2, double* Eo, const RicLayout& lo, int ds, int dm,
-                                             int de, bool binary, double* rlog) {
+                                             int de, bool binary, double* rlog, const double* safe) {
   if (dm == 0) {  // empty middle: J = J1, eta = eta1, A = 0, b = b2, C = C2 (the LU form's result)
     double M[kLD][kLD];
-    lc_load(M, E1 + l1.J, ds, ds, ds, false);
+    lc_load(M, E1 + l1.J, ds, ds, ds, false, safe);
     lc_store(Eo + lo.J, M, ds, ds, ds);
+    double ev[kLD], bv[kLD];
+    lc_loadv(ev, E1 + l1.eta, ds, safe);
+    lc_loadv(bv, E2 + l2.b, de, safe);
 #pragma unroll
     for (int i = 0; i < kLD; ++i)
-      if (i < ds) Eo[lo.eta + i] = E1[l1.eta + i];
+      if (i < ds) Eo[lo.eta + i] = ev[i];
     if (binary) {
 #pragma unroll
       for (int i = 0; i < kLD; ++i) {
-        if (i < de) Eo[lo.b + i] = E2[l2.b + i];
+        if (i < de) Eo[lo.b + i] = bv[i];
 #pragma unroll
         for (int j = 0; j < kLD; ++j)
           if (i < de && j < ds) Eo[lo.A + i * ds + j] = 0.0;
       }
-      lc_load(M, E2 + l2.C, de, de, de, false);
+      lc_load(M, E2 + l2.C, de, de, de, false, safe);
       lc_store(Eo + lo.C, M, de, de, de);
     }
     rlog[0] = 2.0;
     return true;
   }
   double J2[kLD][kLD], L[kLD][kLD], Rg[kLD][kLD];
-  lc_load(J2, E2 + l2.J, dm, dm, dm, true);
+  lc_load(J2, E2 + l2.J, dm, dm, dm, true, safe);
   double mx = 0.0;
 #pragma unroll
   for (int i = 0; i < kLD; ++i)
@@ -340,7 +361,7 @@ __device__ __forceinline__ bool lane_combine(const double* E1, const RicLayout& 
   {
     // G = I + L'(C1 L)
     double C1[kLD][kLD], T[kLD][kLD];
-    lc_load(C1, E1 + l1.C, dm, dm, dm, false);
+    lc_load(C1, E1 + l1.C, dm, dm, dm, false, safe);
 #pragma unroll
     for (int i = 0; i < kLD; ++i)
 #pragma unroll
@@ -367,13 +388,11 @@ __device__ __forceinline__ bool lane_combine(const double* E1, const RicLayout& 
   rlog[0] = 1.0;
   // xi = L^{-1} eta2 ; d = G^{-1}(xi - L'b1) ; w = L d
   double xi[kLD], dv[kLD], wv[kLD];
-#pragma unroll
-  for (int i = 0; i < kLD; ++i) xi[i] = (i < dm) ? E2[l2.eta + i] : 0.0;
+  lc_loadv(xi, E2 + l2.eta, dm, safe);
   lc_fwd(L, xi);
   {
     double b1[kLD];
-#pragma unroll
-    for (int i = 0; i < kLD; ++i) b1[i] = (i < dm) ? E1[l1.b + i] : 0.0;
+    lc_loadv(b1, E1 + l1.b, dm, safe);
 #pragma unroll
     for (int i = 0; i < kLD; ++i) {
       double v = xi[i];
@@ -392,13 +411,17 @@ __device__ __forceinline__ bool lane_combine(const double* E1, const RicLayout& 
     wv[i] = v;
   }
   double A1[kLD][kLD], Yb[kLD][kLD];
-  lc_load(A1, E1 + l1.A, dm, ds, ds, false);
+  lc_load(A1, E1 + l1.A, dm, ds, ds, false, safe);
+  {
+    double e1[kLD];
+    lc_loadv(e1, E1 + l1.eta, ds, safe);
 #pragma unroll
-  for (int c = 0; c < kLD; ++c) {
-    double v = 0.0;
+    for (int c = 0; c < kLD; ++c) {
+      double v = 0.0;
 #pragma unroll
-    for (int j = 0; j < kLD; ++j) v = fma(A1[j][c], wv[j], v);
-    if (c < ds) Eo[lo.eta + c] = E1[l1.eta + c] + v;
+      for (int j = 0; j < kLD; ++j) v = fma(A1[j][c], wv[j], v);
+      if (c < ds) Eo[lo.eta + c] = e1[c] + v;
+    }
   }
   // Yb = Rg^{-1} L' A1 ; J = J1 + Yb'Yb
   {
@@ -424,7 +447,7 @@ __device__ __forceinline__ bool lane_combine(const double* E1, const RicLayout& 
   }
   {
     double Jo[kLD][kLD];
-    lc_load(Jo, E1 + l1.J, ds, ds, ds, false);
+    lc_load(Jo, E1 + l1.J, ds, ds, ds, false, safe);
 #pragma unroll
     for (int a = 0; a < kLD; ++a)
 #pragma unroll
@@ -453,8 +476,9 @@ __device__ __forceinline__ bool lane_combine(const double* E1, const RicLayout& 
     for (int r = 0; r < kLD; ++r) Yb[r][c] = col[r];
   }
   lc_bwd(L, yv);
-  double A2[kLD][kLD];
-  lc_load(A2, E2 + l2.A, de, dm, dm, false);
+  double A2[kLD][kLD], b2[kLD];
+  lc_load(A2, E2 + l2.A, de, dm, dm, false, safe);
+  lc_loadv(b2, E2 + l2.b, de, safe);
 #pragma unroll
   for (int r = 0; r < kLD; ++r) {
 #pragma unroll
@@ -467,7 +491,7 @@ __device__ __forceinline__ bool lane_combine(const double* E1, const RicLayout& 
     double v = 0.0;
 #pragma unroll
     for (int i = 0; i < kLD; ++i) v = fma(A2[r][i], yv[i], v);
-    if (r < de) Eo[lo.b + r] = E2[l2.b + r] + v;
+    if (r < de) Eo[lo.b + r] = b2[r] + v;
   }
   // C = C2 + (A2 K R2^{-T})(A2 K R2^{-T})' with C1 = K K' (pivoted Cholesky, tol 1e-15)
   double K[kLD][kLD];
@@ -475,7 +499,7 @@ __device__ __forceinline__ bool lane_combine(const double* E1, const RicLayout& 
   {
     double C1[kLD][kLD], rm[kLD];
     bool done[kLD];
-    lc_load(C1, E1 + l1.C, dm, dm, dm, false);
+    lc_load(C1, E1 + l1.C, dm, dm, dm, false, safe);
     double ref = 0.0;
 #pragma unroll
     for (int i = 0; i < kLD; ++i) {
@@ -530,7 +554,7 @@ __device__ __forceinline__ bool lane_combine(const double* E1, const RicLayout& 
     }
   }
   double Co[kLD][kLD];
-  lc_load(Co, E2 + l2.C, de, de, de, false);
+  lc_load(Co, E2 + l2.C, de, de, de, false, safe);
   if (rk > 0) {
     // G2 = I + K' J2 K = R2 R2'
     double G2[kLD][kLD];
@@ -712,7 +736,7 @@ __global__ void __launch_bounds__(kBlock) k_ric_combine_lane(DevEngine e, int64_
           const int ns = e.st[sa].n, nm = e.st[sm].n, ne = (se >= 0) ? e.st[se].n : 0;
           const RicLayout l1 = ric_layout(ns, nm), l2 = ric_layout(nm, ne), lo = ric_layout(ns, ne);
           need = !lane_combine(slot_ptr(e, SCAN_RIC, a), l1, slot_ptr(e, SCAN_RIC, bsl), l2, slot_ptr(e, SCAN_RIC, o),
-                               lo, ds, dm, de, se >= 0, e.ric_log + e.ric_log_off[o]);
+                               lo, ds, dm, de, se >= 0, e.ric_log + e.ric_log_off[o], e.arena);
         }
       }
     }
