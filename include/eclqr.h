@@ -232,6 +232,9 @@ typedef struct {
                            * reversed-time stationarity problem solved by the full engine.  Both give the
                            * minimum-norm multipliers; they differ in rounding.  eclqr_backward needs the
                            * workspace of a solve made with the same route. */
+  int32_t split_combine;  /* value-function combines of a level whose tasks all fit the device at once run on two
+                           * wavefronts (J, eta, A, b on one, the C update on the other; same bits) (1, default) or
+                           * one (0) */
 } eclqr_tuning;
 
 /* Time the caller's problem under alternative launch configurations

@@ -55,7 +55,8 @@ T* at(void* ws, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
 }
 
-int32_t g_pool_lds = 2, g_grid_div = 1, g_buckets = 1, g_reg = 1, g_stage_lds = 1;  // tuning of the plan being launched
+int32_t g_pool_lds = 2, g_grid_div = 1, g_buckets = 1, g_reg = 1, g_stage_lds = 1,
+        g_split = 1;  // tuning of the plan being launched
 
 DevEngine dev_engine(const Engine& E, void* ws, size_t base) {
   DevEngine d{};
@@ -86,6 +87,7 @@ DevEngine dev_engine(const Engine& E, void* ws, size_t base) {
   d.pool_lds = g_pool_lds;
   d.reg_compose = g_reg;
   d.elim_lds = g_stage_lds;
+  d.split_combine = g_split;
   return d;
 }
 
@@ -177,6 +179,13 @@ eclqr_status bind(Plan& p, void* ws, hipStream_t s) {
     replay_set_max_lds(lds);
     fast_set_max_lds(lds);
     theta_set_max_lds(lds);
+  }
+  {
+    int lds_cu = 0, ncu = 0;
+    if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess) lds_cu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) ncu = 0;
+    (void)hipGetLastError();
+    lqr_set_device(lds_cu, ncu);
   }
   if (!p.aux_stream) {
     hipStream_t a = nullptr;
@@ -314,6 +323,7 @@ struct Views {
 Views views(Plan& p, void* ws) {
   g_pool_lds = p.pool_lds;
   g_stage_lds = p.stage_lds;
+  g_split = p.split_combine;
   g_grid_div = p.grid_divisor;
   g_buckets = p.level_buckets;
   g_reg = p.reg_compose;
@@ -972,6 +982,7 @@ eclqr_status eclqr_plan_get_tuning(const eclqr_plan* plan, eclqr_tuning* out) {
   out->stage_lds = p.stage_lds;
   out->overlap_dual = p.overlap_dual;
   out->multiplier_route = p.theta_ok ? p.mult_route : 0;
+  out->split_combine = p.split_combine;
   out->ms_per_solve = p.tuned_ms;
   return ECLQR_SUCCESS;
 }
@@ -989,6 +1000,7 @@ eclqr_status eclqr_plan_set_tuning(eclqr_plan* plan, const eclqr_tuning* t) {
   p.stage_lds = t->stage_lds != 0;
   p.overlap_dual = t->overlap_dual != 0;
   p.mult_route = (p.theta_ok && t->multiplier_route != 0) ? 1 : 0;
+  p.split_combine = t->split_combine != 0;
   release_graph(p);
   return ECLQR_SUCCESS;
 }
@@ -1030,7 +1042,8 @@ eclqr_status eclqr_plan_autotune(eclqr_plan* plan, const eclqr_problem* prob, ec
   Knob knobs[] = {{&p.reg_compose, p.reg_compose ? 0 : 1}, {&p.stage_lds, p.stage_lds ? 0 : 1},
                   {&p.level_buckets, p.level_buckets ? 0 : 1}, {&p.pool_lds, p.pool_lds == 2 ? 1 : 2},
                   {&p.grid_divisor, p.grid_divisor == 1 ? 4 : 1}, {&graph, graph ? 0 : 1},
-                  {&p.overlap_dual, p.overlap_dual ? 0 : 1}, {&p.mult_route, p.mult_route ? 0 : 1}};
+                  {&p.overlap_dual, p.overlap_dual ? 0 : 1}, {&p.mult_route, p.mult_route ? 0 : 1},
+                  {&p.split_combine, p.split_combine ? 0 : 1}};
   for (Knob& k : knobs) {
     if (st != ECLQR_SUCCESS) break;
     if (k.v == &p.mult_route && !p.theta_ok) continue;

@@ -16,8 +16,15 @@
 
 namespace eclqr {
 
+// Lane id and lane count of the routines; a file whose workgroups hold
+// several wavefronts that each run routines on their own data defines them
+// per wavefront before including this header.
+#ifndef ECLQR_TID
 #define ECLQR_TID ((int)threadIdx.x)
+#endif
+#ifndef ECLQR_NT
 #define ECLQR_NT ((int)blockDim.x)
+#endif
 
 __device__ __forceinline__ void wg_sync() { __syncthreads(); }
 

@@ -2,6 +2,11 @@
 // logarithmic-depth associative scan over conditional value functions),
 // feedback gains, the forward affine scan and the recovery maps
 // (eq. (recovery-maps)).
+// Every kernel here runs one wavefront per workgroup except the split
+// value-function combine (two wavefronts, each running its own part of one
+// combine): the dense routines count lanes within the wavefront.
+#define ECLQR_TID ((int)(threadIdx.x & 63))
+#define ECLQR_NT 64
 #include "dense.hpp"
 #include "device_util.hpp"
 #include "eclqr.h"
@@ -121,9 +126,12 @@ __device__ __forceinline__ void combine_lu(const double* A1, const double* b1, c
   }
 }
 
-// Factored combine; returns false (having written nothing) when J2 or G is not
-// numerically positive definite.
-template <bool kL, int NMAX>
+// Factored combine; returns false when J2, G or G2 is not numerically
+// positive definite (outputs then incomplete: the caller redoes the combine in
+// LU form).  kPart 0: everything; 1: all but C (J, eta, A, b and the log);
+// 2: only C (binary combines) -- the two parts share no output or work array
+// other than the read-only operands, so two wavefronts can run them at once.
+template <bool kL, int NMAX, int kPart = 0>
 __device__ __forceinline__ bool combine_factored(const double* A1, const double* b1, const double* C1, const double* et1,
                                  const double* J1, const double* A2, const double* b2, const double* C2,
                                  const double* et2, const double* J2, double* Eo, const RicLayout& lo, int ds, int dm,
@@ -141,6 +149,7 @@ __device__ __forceinline__ bool combine_factored(const double* A1, const double*
   double* tv = xi + rup4(dm);                 // dm
   double* wv = tv + rup4(dm);                 // dm
   double* rem = wv + rup4(dm);                // dm
+  if constexpr (kPart != 2) {
   double mx = 0.0;
   for (int i = 0; i < dm; ++i) mx = fmax(mx, J2[i * dm + i]);
   if (!(mx > 0.0)) return false;
@@ -194,6 +203,8 @@ __device__ __forceinline__ bool combine_factored(const double* A1, const double*
   d_trsm_lower_t<kL, NMAX>(Lj, dm, Yb, ly, dm, ly, buf);
   wg_gemm<kL>(Eo + lo.A, ds, A2, dm, false, Yb, ly, false, de, ds, dm, 1.0, 0.0);
   for (int i = ECLQR_TID; i < de; i += ECLQR_NT) Eo[lo.b + i] = lane_chain<false>(b2[i], A2 + i * dm, 1, Yb + ds, ly, dm);
+  }
+  if constexpr (kPart == 1) return true;
   // C = C2 + (A2 K R2^{-T})(A2 K R2^{-T})'
   const int r = d_pchol<kL, NMAX>(C1, dm, dm, 1e-15, Km, dm, rem, used, sh, buf);
   if (r > 0) {
@@ -712,6 +723,67 @@ __global__ void __launch_bounds__(kBlock, 1) k_ric_combine(DevEngine e, int64_t 
   }
 }
 
+// Value-function combines of a level with two wavefronts per task: wavefront
+// 0 computes J, eta, A, b (and the log), wavefront 1 the C update -- the two
+// chains of the factored combine depend only on the operands.  Operands and
+// result in LDS as in mode 2, one work pool per wavefront; the LU form, when a
+// factorization fails, by wavefront 0.  Same operations in the same order as
+// the one-wavefront kernel, so the same bits.
+// LDS: S1 | S2 | So | pool 0 | pool 1 | piv 0, 1 | flags | sh, buf (x2)
+template <int NMAX>
+__global__ void __launch_bounds__(2 * kBlock, 1) k_ric_combine_split(DevEngine e, int64_t first, int64_t ntasks,
+                                                                     int maxd) {
+  extern __shared__ double lds[];
+  const int64_t esz = ric_layout(maxd, maxd).size;
+  const int64_t pool_sz = ric_pool(maxd);
+  const int wave = threadIdx.x >> 6;
+  double* S1 = lds;
+  double* S2 = S1 + esz;
+  double* So = S2 + esz;
+  double* pool = So + esz + wave * pool_sz;
+  int* pivs = (int*)(So + esz + 2 * pool_sz);
+  int* piv = pivs + wave * kMaxDim;
+  int* okf = pivs + 2 * kMaxDim;
+  double* sh = (double*)(okf + 4) + wave * (16 + kMaxDim);
+  double* buf = sh + 16;
+  for (int64_t ti = blockIdx.x; ti < ntasks; ti += gridDim.x) {
+    const int a = e.tasks[3 * (first + ti)];
+    const int bsl = e.tasks[3 * (first + ti) + 1];
+    const int o = e.tasks[3 * (first + ti) + 2];
+    const int sa = slot_a(e, 0, a), sm = slot_b(e, 0, a), se = slot_b(e, 0, bsl);
+    if (gated(e, e.st[sa].inst)) continue;  // the same for both wavefronts
+    const int ds = e.nbar[sa], dm = e.nbar[sm], de = (se >= 0) ? e.nbar[se] : 0;
+    const int ns = e.st[sa].n, nm = e.st[sm].n, ne = (se >= 0) ? e.st[se].n : 0;
+    const RicLayout l1 = ric_layout(ns, nm), l2 = ric_layout(nm, ne), lo = ric_layout(ns, ne);
+    const RicLayout s1 = ric_layout(ds, dm), s2 = ric_layout(dm, de), so = ric_layout(ds, de);
+    const bool binary = se >= 0;
+    double* rlog = e.ric_log + e.ric_log_off[o];
+    if (wave == 0)
+      ric_move(S1, s1, slot_ptr(e, SCAN_RIC, a), l1, ds, dm);
+    else
+      ric_move(S2, s2, slot_ptr(e, SCAN_RIC, bsl), l2, dm, de);
+    __syncthreads();
+    const double *A1 = S1 + s1.A, *b1 = S1 + s1.b, *C1 = S1 + s1.C, *et1 = S1 + s1.eta, *J1 = S1 + s1.J;
+    const double *A2 = S2 + s2.A, *b2 = S2 + s2.b, *C2 = S2 + s2.C, *et2 = S2 + s2.eta, *J2 = S2 + s2.J;
+    bool ok = true;
+    if (wave == 0)
+      ok = combine_factored<true, NMAX, 1>(A1, b1, C1, et1, J1, A2, b2, C2, et2, J2, So, so, ds, dm, de, binary,
+                                           pool, piv, sh, rlog, buf);
+    else if (binary)
+      ok = combine_factored<true, NMAX, 2>(A1, b1, C1, et1, J1, A2, b2, C2, et2, J2, So, so, ds, dm, de, binary,
+                                           pool, piv, sh, rlog, buf);
+    if ((threadIdx.x & 63) == 0) okf[wave] = ok ? 1 : 0;
+    __syncthreads();
+    if (!(okf[0] && okf[1])) {  // read by both wavefronts after the barrier: uniform
+      if (wave == 0) combine_lu<true>(A1, b1, C1, et1, J1, A2, b2, C2, et2, J2, So, so, ds, dm, de, binary, pool, piv,
+                                      sh, rlog);
+      __syncthreads();
+    }
+    if (wave == 0) ric_move(slot_ptr(e, SCAN_RIC, o), lo, So, so, ds, de);
+    __syncthreads();
+  }
+}
+
 // Value-function combines of a level, one lane per task where every reduced
 // dim is <= 4 (lane_combine); the tasks of a tile of 64 that do not qualify,
 // or fail a factorization test there, are combined by the whole wavefront
@@ -931,6 +1003,10 @@ void lqr_set_max_lds(int bytes) {
                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_ric_combine<2, 32>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_ric_combine_split<16>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_ric_combine_split<32>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_gains<false>), hipFuncAttributeMaxDynamicSharedMemorySize,
                             bytes);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_gains<true>), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -953,11 +1029,35 @@ static int ric_mode(int want, int d) {
 size_t ric_lds_bytes(int maxd) { return ric_mode_bytes(ric_mode(2, maxd), maxd); }
 size_t gains_lds_bytes(int maxm) { return sizeof(double) * ((size_t)maxm * maxm + 16) + 64; }
 
+static int g_lds_per_cu = 160 * 1024, g_num_cu = 256;
+void lqr_set_device(int lds_per_cu, int num_cu) {
+  if (lds_per_cu > 0) g_lds_per_cu = lds_per_cu;
+  if (num_cu > 0) g_num_cu = num_cu;
+}
+static size_t ric_split_bytes(int d) {
+  return sizeof(double) * (3 * (size_t)ric_layout(d, d).size + 2 * (size_t)ric_pool(d) + 2 * (16 + kMaxDim)) +
+         sizeof(int) * (2 * kMaxDim + 4) + 64;
+}
+
 void launch_ric_combine(const DevEngine& e, int64_t first, int64_t ntasks, int32_t* status, int maxd,
                         hipStream_t s) {
   if (ntasks <= 0) return;
   const int grid = (int)(ntasks < e.nblocks ? ntasks : e.nblocks);
   const int mode = ric_mode(e.pool_lds, maxd);
+  // two wavefronts per combine while the level still fits the device at once
+  if (e.split_combine && mode == 2 && maxd <= 32) {
+    const size_t lds = ric_split_bytes(maxd);
+    const int64_t per_cu = (int64_t)g_lds_per_cu / (int64_t)lds;
+    if (lds <= (size_t)g_lqr_max_lds && ntasks <= per_cu * g_num_cu) {
+      if (maxd <= 16)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ric_combine_split<16>), dim3(grid), dim3(2 * kBlock), lds, s, e, first,
+                           ntasks, maxd);
+      else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ric_combine_split<32>), dim3(grid), dim3(2 * kBlock), lds, s, e, first,
+                           ntasks, maxd);
+      return;
+    }
+  }
   const size_t lds = ric_mode_bytes(mode, maxd);
   if (mode == 2 && maxd <= 16)
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ric_combine<2, 16>), dim3(grid), dim3(kBlock), lds, s, e, first, ntasks,

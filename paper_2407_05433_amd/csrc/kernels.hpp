@@ -38,6 +38,7 @@ struct DevEngine {
   int32_t pool_lds;           // value-function combine LDS mode (0 global pool, 1 LDS pool, 2 all in LDS)
   int32_t reg_compose;        // 1: relation compositions that fit run register-resident
   int32_t elim_lds;           // 1: stage eliminations keep their working arrays in LDS when they fit
+  int32_t split_combine;      // 1: value-function combines of a level that fits the device run on two wavefronts
 };
 
 // Pointers to one problem's data (caller layout of the engine).
@@ -56,6 +57,7 @@ void launch_validate(const DevEngine& e, const Inputs& in, int32_t* status, hipS
 void relations_set_max_lds(int bytes);
 void eliminate_set_max_lds(int bytes);
 void lqr_set_max_lds(int bytes);
+void lqr_set_device(int lds_per_cu, int num_cu);
 void replay_set_max_lds(int bytes);
 size_t rel_lds_bytes(int maxp, int ldw);
 size_t domain_lds_bytes(int maxn);

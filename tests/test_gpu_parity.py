@@ -328,7 +328,7 @@ def test_autotune_keeps_results():
     tuned = ecl.autotune(plan, data, ws)
     assert tuned["ms_per_solve"] > 0
     for cfg in ({"level_buckets": 0}, {"pool_in_lds": 0}, {"pool_in_lds": 1}, {"stage_lds": 0}, {"grid_divisor": 4},
-                {"overlap_dual": 0}, {"multiplier_route": 1 - base["multiplier_route"]},
+                {"overlap_dual": 0}, {"multiplier_route": 1 - base["multiplier_route"]}, {"split_combine": 0},
                 {"use_graph": 1},
                 {"register_compose": 0}, tuned):
         full = dict(base)
