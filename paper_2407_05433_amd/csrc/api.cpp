@@ -305,6 +305,7 @@ Inputs inputs_of(const eclqr_problem* p) {
 }
 
 struct Views {
+  void* ws;
   DevEngine P, D, T;
   DualPtrs dp;
   CorrPtrs cp;
@@ -328,6 +329,7 @@ Views views(Plan& p, void* ws) {
   g_buckets = p.level_buckets;
   g_reg = p.reg_compose;
   Views v{};
+  v.ws = ws;
   v.P = dev_engine(p.primal, ws, p.o_primal);
   v.D = dev_engine(p.dual, ws, p.o_dual);
   if (p.theta_ok) v.T = dev_engine(p.theta, ws, p.o_theta_eng);
@@ -430,17 +432,21 @@ eclqr_status theta_multipliers(Plan& p, const Views& v, const Inputs& in, const 
     if (!launch_theta_local(v.P, v.T, in, x, u, td, status, p.th_q, p.th_ldw, p.th_r, !full, s))
       return fail(ECLQR_UNSUPPORTED, "stage too large for the LDS tile of the minimum-norm local systems");
   }
+  int32_t* defer = at<int32_t>(v.ws, p.o_defer);
+  if (full) {
+    Timed tm(ECLQR_K_MULT_THETA, s);
+    launch_fill_i32(defer, 0, 2 * T.D, s);
+  }
   for (int l = 0; l < 2 * T.D; ++l) {
     if (T.lvl_count[l] == 0) continue;
     if (full) {
       Timed tm(ECLQR_K_RIC_COMBINE, s);
-      // theta dims are mostly <= 4: one lane per combine on levels whose
-      // tasks fit in a few waves per CU (latency-bound); wide levels keep one
-      // wavefront per combine (more waves in flight)
-      if (T.lvl_count[l] <= 4096)
-        launch_ric_combine_lane(v.T, T.lvl_begin[l], T.lvl_count[l], s);
-      else
-        launch_ric_combine(v.T, T.lvl_begin[l], T.lvl_count[l], status, std::max(1, T.lvl_dim[l]), s);
+      // theta dims are mostly <= 4: one lane per combine.  On a wide level
+      // the larger combines go to a second launch, one per wavefront, instead
+      // of being run one after another by the wavefront that found them.
+      const bool wide = T.lvl_count[l] > 4096;
+      launch_ric_combine_lane(v.T, T.lvl_begin[l], T.lvl_count[l], wide ? defer + l : nullptr,
+                              wide ? defer + 2 * T.D + 4 : nullptr, s);
     } else {
       Timed tm(ECLQR_K_REPLAY, s);
       launch_ric_combine_vec(v.T, T.lvl_begin[l], T.lvl_count[l], std::max(1, T.lvl_dim[l]), s);

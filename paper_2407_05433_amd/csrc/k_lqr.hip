@@ -784,11 +784,39 @@ __global__ void __launch_bounds__(2 * kBlock, 1) k_ric_combine_split(DevEngine e
   }
 }
 
+// One combine of a level by the whole wavefront, global work pool (factored,
+// else LU): the tasks the lane kernel does not finish.
+__device__ __forceinline__ void ric_combine_wave(const DevEngine& e, int64_t first, int64_t tj, int* piv, double* sh,
+                                                 double* buf) {
+  const int a = e.tasks[3 * (first + tj)];
+  const int bsl = e.tasks[3 * (first + tj) + 1];
+  const int o = e.tasks[3 * (first + tj) + 2];
+  const int sa = slot_a(e, 0, a), sm = slot_b(e, 0, a), se = slot_b(e, 0, bsl);
+  const int ds = e.nbar[sa], dm = e.nbar[sm], de = (se >= 0) ? e.nbar[se] : 0;
+  const int ns = e.st[sa].n, nm = e.st[sm].n, ne = (se >= 0) ? e.st[se].n : 0;
+  const RicLayout l1 = ric_layout(ns, nm), l2 = ric_layout(nm, ne), lo = ric_layout(ns, ne);
+  const double* E1 = slot_ptr(e, SCAN_RIC, a);
+  const double* E2 = slot_ptr(e, SCAN_RIC, bsl);
+  double* Eo = slot_ptr(e, SCAN_RIC, o);
+  const double *A1 = E1 + l1.A, *b1 = E1 + l1.b, *C1 = E1 + l1.C, *et1 = E1 + l1.eta, *J1 = E1 + l1.J;
+  const double *A2 = E2 + l2.A, *b2 = E2 + l2.b, *C2 = E2 + l2.C, *et2 = E2 + l2.eta, *J2 = E2 + l2.J;
+  double* rlog = e.ric_log + e.ric_log_off[o];
+  double* pool = block_scratch(e);
+  wg_sync();
+  if (!combine_factored<false, 0>(A1, b1, C1, et1, J1, A2, b2, C2, et2, J2, Eo, lo, ds, dm, de, se >= 0, pool, piv, sh,
+                                  rlog, buf))
+    combine_lu<false>(A1, b1, C1, et1, J1, A2, b2, C2, et2, J2, Eo, lo, ds, dm, de, se >= 0, pool, piv, sh, rlog);
+  wg_sync();
+}
+
 // Value-function combines of a level, one lane per task where every reduced
-// dim is <= 4 (lane_combine); the tasks of a tile of 64 that do not qualify,
+// dim is <= 4 (lane_combine).  The tasks of a tile of 64 that do not qualify,
 // or fail a factorization test there, are combined by the whole wavefront
-// (global work pool).
-__global__ void __launch_bounds__(kBlock) k_ric_combine_lane(DevEngine e, int64_t first, int64_t ntasks) {
+// (global work pool) -- right away, or (defer_count non-null) appended to
+// defer_list for k_ric_combine_deferred, so that a wide level's large tasks
+// run one per wavefront instead of one after another.
+__global__ void __launch_bounds__(kBlock) k_ric_combine_lane(DevEngine e, int64_t first, int64_t ntasks,
+                                                             int32_t* defer_count, int32_t* defer_list) {
   __shared__ int piv[kMaxDim];
   __shared__ double sh[16];
   __shared__ double buf[kMaxDim];
@@ -812,33 +840,34 @@ __global__ void __launch_bounds__(kBlock) k_ric_combine_lane(DevEngine e, int64_
         }
       }
     }
-    // the rest, one task at a time by the whole wavefront
     unsigned long long rest = __ballot(need);
+    if (defer_count) {  // append the rest to the deferred list
+      if (rest) {
+        int base = 0;
+        if (lane == 0) base = atomicAdd(defer_count, __popcll(rest));
+        base = wave_bcast_i(base, 0);
+        if (need) defer_list[base + __popcll(rest & ((1ull << lane) - 1ull))] = (int32_t)ti;
+      }
+      continue;
+    }
+    // the rest, one task at a time by the whole wavefront
     while (rest) {
       const int l = __ffsll((long long)rest) - 1;
       rest &= rest - 1;
-      const int64_t tj = t0 + l;
-      const int a = e.tasks[3 * (first + tj)];
-      const int bsl = e.tasks[3 * (first + tj) + 1];
-      const int o = e.tasks[3 * (first + tj) + 2];
-      const int sa = slot_a(e, 0, a), sm = slot_b(e, 0, a), se = slot_b(e, 0, bsl);
-      const int ds = e.nbar[sa], dm = e.nbar[sm], de = (se >= 0) ? e.nbar[se] : 0;
-      const int ns = e.st[sa].n, nm = e.st[sm].n, ne = (se >= 0) ? e.st[se].n : 0;
-      const RicLayout l1 = ric_layout(ns, nm), l2 = ric_layout(nm, ne), lo = ric_layout(ns, ne);
-      const double* E1 = slot_ptr(e, SCAN_RIC, a);
-      const double* E2 = slot_ptr(e, SCAN_RIC, bsl);
-      double* Eo = slot_ptr(e, SCAN_RIC, o);
-      const double *A1 = E1 + l1.A, *b1 = E1 + l1.b, *C1 = E1 + l1.C, *et1 = E1 + l1.eta, *J1 = E1 + l1.J;
-      const double *A2 = E2 + l2.A, *b2 = E2 + l2.b, *C2 = E2 + l2.C, *et2 = E2 + l2.eta, *J2 = E2 + l2.J;
-      double* rlog = e.ric_log + e.ric_log_off[o];
-      double* pool = block_scratch(e);
-      wg_sync();
-      if (!combine_factored<false, 0>(A1, b1, C1, et1, J1, A2, b2, C2, et2, J2, Eo, lo, ds, dm, de, se >= 0, pool, piv,
-                                      sh, rlog, buf))
-        combine_lu<false>(A1, b1, C1, et1, J1, A2, b2, C2, et2, J2, Eo, lo, ds, dm, de, se >= 0, pool, piv, sh, rlog);
-      wg_sync();
+      ric_combine_wave(e, first, t0 + l, piv, sh, buf);
     }
   }
+}
+
+// The deferred tasks of a level (count and task indices from the lane
+// kernel), one per wavefront.
+__global__ void __launch_bounds__(kBlock) k_ric_combine_deferred(DevEngine e, int64_t first, const int32_t* count,
+                                                                 const int32_t* list) {
+  __shared__ int piv[kMaxDim];
+  __shared__ double sh[16];
+  __shared__ double buf[kMaxDim];
+  const int n = *count;
+  for (int i = blockIdx.x; i < n; i += gridDim.x) ric_combine_wave(e, first, list[i], piv, sh, buf);
 }
 
 // Feedback of stage i from the value function of stage i+1 (P', p' = J, -eta
@@ -1076,11 +1105,16 @@ void launch_ric_combine(const DevEngine& e, int64_t first, int64_t ntasks, int32
                        status, maxd);
 }
 
-void launch_ric_combine_lane(const DevEngine& e, int64_t first, int64_t ntasks, hipStream_t s) {
+void launch_ric_combine_lane(const DevEngine& e, int64_t first, int64_t ntasks, int32_t* defer_count,
+                             int32_t* defer_list, hipStream_t s) {
   if (ntasks <= 0) return;
   const int64_t tiles = (ntasks + kBlock - 1) / kBlock;
   const int grid = (int)(tiles < e.nblocks ? tiles : e.nblocks);
-  hipLaunchKernelGGL(k_ric_combine_lane, dim3(grid), dim3(kBlock), 0, s, e, first, ntasks);
+  hipLaunchKernelGGL(k_ric_combine_lane, dim3(grid), dim3(kBlock), 0, s, e, first, ntasks, defer_count, defer_list);
+  if (defer_count) {
+    const int g2 = (int)(ntasks < e.nblocks ? ntasks : e.nblocks);
+    hipLaunchKernelGGL(k_ric_combine_deferred, dim3(g2), dim3(kBlock), 0, s, e, first, defer_count, defer_list);
+  }
 }
 
 void launch_gains(const DevEngine& e, int32_t* status, int maxm, int maxn, hipStream_t s) {

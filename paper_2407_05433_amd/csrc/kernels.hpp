@@ -75,8 +75,11 @@ void launch_eliminate(const DevEngine& e, const Inputs& in, Tols t, int32_t* sta
 void launch_ric_combine(const DevEngine& e, int64_t first_task, int64_t ntasks, int32_t* status, int maxd,
                         hipStream_t s);
 // the same combines, one lane per task where every reduced dim is <= 4 (the
-// rest by the wavefront); for engines whose reduced dims are mostly tiny
-void launch_ric_combine_lane(const DevEngine& e, int64_t first, int64_t ntasks, hipStream_t s);
+// rest by the wavefront: inline, or with defer_count non-null (zero on entry)
+// through defer_list (ntasks entries) and a second launch, one per
+// wavefront); for engines whose reduced dims are mostly tiny
+void launch_ric_combine_lane(const DevEngine& e, int64_t first, int64_t ntasks, int32_t* defer_count,
+                             int32_t* defer_list, hipStream_t s);
 void launch_gains(const DevEngine& e, int32_t* status, int maxm, int maxn, hipStream_t s);
 void launch_fwd_combine(const DevEngine& e, int64_t first_task, int64_t ntasks, hipStream_t s);
 void launch_recover(const DevEngine& e, double* x, double* u, hipStream_t s);

@@ -526,6 +526,10 @@ std::string build_plan(Plan& p, const eclqr_dims* d, const eclqr_options* opt) {
   if (p.theta_ok) {
     p.o_theta_eng = o;
     o = align256(o + p.theta.bytes);
+    int64_t widest = 1;
+    for (int64_t c : p.theta.lvl_count) widest = std::max(widest, c);
+    p.o_defer = o;
+    o = align256(o + sizeof(int32_t) * (2 * (int64_t)p.theta.D + 4 + widest));
   }
   for (int f = 0; f < ECLQR_NUM_FIELDS; ++f) {
     p.o_dprob[f] = o;

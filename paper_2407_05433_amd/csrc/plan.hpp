@@ -84,6 +84,7 @@ struct Plan {
   Engine theta;
   bool theta_ok = false;
   size_t o_theta_eng = 0;
+  size_t o_defer = 0;         // per level: count of deferred combines (2 D ints), then one task list
   int32_t th_q = 1, th_ldw = 1, th_r = 1;  // LDS tile of the local minimum-norm systems
   int32_t mult_route = 1;     // 1: theta LQR (when theta_ok), 0: reversed-time problem
   int32_t ws_route = -1;      // route whose factors the bound workspace holds (-1: none yet)
