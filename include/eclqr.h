@@ -119,7 +119,10 @@ typedef struct {
                            * hybrid: the fewest balanced up-sweep levels after which the batch has at most 2048
                            * interval nodes (512 when a state dim exceeds 16), doubling over those nodes, then
                            * the balanced down-sweep (pure doubling for up to 2048 leaves) */
-  int32_t reserved[4];
+  int32_t reversed_time;  /* with multipliers = 1: 1 also lays out the reversed-time stationarity problem in the
+                           * workspace, so the tuning field multiplier_route can select it; 0 (default) only when
+                           * the theta route is unavailable (a stage with k_i + n_{i+1} > 64) */
+  int32_t reserved[3];
 } eclqr_options;
 
 /* Device pointers to the problem data (layout from eclqr_plan_layout).  M may
@@ -230,7 +233,8 @@ typedef struct {
                            * scans, as an unconstrained LQR over the normal coordinates theta_i of the domains
                            * (minimum-norm local systems, value-function scan, gains, forward scan); 0: the
                            * reversed-time stationarity problem solved by the full engine.  Both give the
-                           * minimum-norm multipliers; they differ in rounding.  eclqr_backward needs the
+                           * minimum-norm multipliers; they differ in rounding.  Route 0 needs a plan made with
+                           * the option reversed_time = 1 (else the field stays 1).  eclqr_backward needs the
                            * workspace of a solve made with the same route. */
   int32_t split_combine;  /* value-function combines of a level whose tasks all fit the device at once run on two
                            * wavefronts (J, eta, A, b on one, the C update on the other; same bits) (1, default) or

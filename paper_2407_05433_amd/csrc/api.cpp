@@ -199,8 +199,10 @@ eclqr_status bind(Plan& p, void* ws, hipStream_t s) {
   }
   eclqr_status st = upload_engine(p.primal, ws, p.o_primal, s);
   if (st != ECLQR_SUCCESS) return st;
-  st = upload_engine(p.dual, ws, p.o_dual, s);
-  if (st != ECLQR_SUCCESS) return st;
+  if (p.has_dual) {
+    st = upload_engine(p.dual, ws, p.o_dual, s);
+    if (st != ECLQR_SUCCESS) return st;
+  }
   if (p.theta_ok) {
     st = upload_engine(p.theta, ws, p.o_theta_eng, s);
     if (st != ECLQR_SUCCESS) return st;
@@ -331,12 +333,12 @@ Views views(Plan& p, void* ws) {
   Views v{};
   v.ws = ws;
   v.P = dev_engine(p.primal, ws, p.o_primal);
-  v.D = dev_engine(p.dual, ws, p.o_dual);
+  if (p.has_dual) v.D = dev_engine(p.dual, ws, p.o_dual);
   if (p.theta_ok) v.T = dev_engine(p.theta, ws, p.o_theta_eng);
   for (int f = 0; f < IN_COUNT; ++f) v.dp.f[f] = at<double>(ws, p.o_dprob[f]);
   v.dp.f[IN_M] = nullptr;
   v.dp.pbase = dev_sbase(p.primal, ws, p.o_primal);
-  v.dp.dbase = dev_sbase(p.dual, ws, p.o_dual);
+  v.dp.dbase = p.has_dual ? dev_sbase(p.dual, ws, p.o_dual) : nullptr;
   v.cp.q = at<double>(ws, p.o_corr[ECLQR_F_q]);
   v.cp.r = at<double>(ws, p.o_corr[ECLQR_F_r]);
   v.cp.c = at<double>(ws, p.o_corr[ECLQR_F_c]);
@@ -725,6 +727,7 @@ eclqr_status eclqr_plan_workspace_size(const eclqr_plan* plan, size_t* bytes) {
 eclqr_status eclqr_plan_schedule(const eclqr_plan* plan, int32_t dual, int32_t* levels, int32_t level,
                                  const int32_t** tasks, int32_t* ntasks) {
   if (!plan) return fail(ECLQR_INVALID_ARGUMENT, "NULL plan");
+  if (dual && !plan->p.has_dual) return fail(ECLQR_INVALID_ARGUMENT, "the plan has no reversed-time engine");
   const Engine& E = dual ? plan->p.dual : plan->p.primal;
   if (levels) *levels = 2 * E.D;
   if (level >= 0) {
@@ -899,7 +902,7 @@ eclqr_status eclqr_plan_reduced_dims(const eclqr_plan* plan, const void* ws, int
                                      int32_t* mbar) {
   if (!plan || !ws) return fail(ECLQR_INVALID_ARGUMENT, "NULL argument");
   const Plan& p = plan->p;
-  if (which < 0 || which > 2 || (which == 2 && !p.theta_ok))
+  if (which < 0 || which > 2 || (which == 2 && !p.theta_ok) || (which == 1 && !p.has_dual))
     return fail(ECLQR_INVALID_ARGUMENT, "which: 0 problem, 1 reversed-time problem, 2 theta LQR (if the plan has it)");
   const Engine& E = which == 2 ? p.theta : (which ? p.dual : p.primal);
   const size_t base = which == 2 ? p.o_theta_eng : (which ? p.o_dual : p.o_primal);
@@ -932,6 +935,7 @@ eclqr_status eclqr_plan_scan_rows(const eclqr_plan* plan, const void* ws, int32_
                                   int32_t* nslots) {
   if (!plan) return fail(ECLQR_INVALID_ARGUMENT, "NULL plan");
   const Plan& p = plan->p;
+  if (which && !p.has_dual) return fail(ECLQR_INVALID_ARGUMENT, "the plan has no reversed-time engine");
   const Engine& E = which ? p.dual : p.primal;
   if (nslots) *nslots = E.nslots;
   if (rows) {
@@ -947,6 +951,7 @@ eclqr_status eclqr_plan_combine_forms(const eclqr_plan* plan, const void* ws, in
                                       int32_t* nslots) {
   if (!plan) return fail(ECLQR_INVALID_ARGUMENT, "NULL plan");
   const Plan& p = plan->p;
+  if (which && !p.has_dual) return fail(ECLQR_INVALID_ARGUMENT, "the plan has no reversed-time engine");
   const Engine& E = which ? p.dual : p.primal;
   if (nslots) *nslots = E.nslots;
   if (!forms) return ECLQR_SUCCESS;
@@ -966,6 +971,7 @@ eclqr_status eclqr_plan_combine_forms(const eclqr_plan* plan, const void* ws, in
 eclqr_status eclqr_plan_slot_info(const eclqr_plan* plan, int32_t which, int32_t* inst, int32_t* first,
                                   int32_t* last, int32_t* nslots) {
   if (!plan) return fail(ECLQR_INVALID_ARGUMENT, "NULL plan");
+  if (which && !plan->p.has_dual) return fail(ECLQR_INVALID_ARGUMENT, "the plan has no reversed-time engine");
   const Engine& E = which ? plan->p.dual : plan->p.primal;
   if (nslots) *nslots = E.nslots;
   for (int32_t q = 0; q < E.nslots; ++q) {
@@ -1005,7 +1011,7 @@ eclqr_status eclqr_plan_set_tuning(eclqr_plan* plan, const eclqr_tuning* t) {
   p.reg_compose = t->register_compose != 0;
   p.stage_lds = t->stage_lds != 0;
   p.overlap_dual = t->overlap_dual != 0;
-  p.mult_route = (p.theta_ok && t->multiplier_route != 0) ? 1 : 0;
+  p.mult_route = (p.theta_ok && (t->multiplier_route != 0 || !p.has_dual)) ? 1 : 0;
   p.split_combine = t->split_combine != 0;
   release_graph(p);
   return ECLQR_SUCCESS;
@@ -1052,7 +1058,8 @@ eclqr_status eclqr_plan_autotune(eclqr_plan* plan, const eclqr_problem* prob, ec
                   {&p.split_combine, p.split_combine ? 0 : 1}};
   for (Knob& k : knobs) {
     if (st != ECLQR_SUCCESS) break;
-    if (k.v == &p.mult_route && !p.theta_ok) continue;
+    if (k.v == &p.mult_route && !(p.theta_ok && p.has_dual)) continue;
+    if (k.v == &p.overlap_dual && !p.has_dual) continue;
     const int32_t old = *k.v;
     *k.v = k.alt;
     p.opt.use_graph = graph;

@@ -468,26 +468,6 @@ std::string build_plan(Plan& p, const eclqr_dims* d, const eclqr_options* opt) {
   std::string err = p.primal.build(d);
   if (!err.empty()) return err;
   const Engine& P = p.primal;
-  // Reversed-time stationarity problem (Section VII): stage 0 has an empty
-  // state and input mu_N; stage j = 1..N is primal stage i = N - j with state
-  // lambda_{i+1}, input mu_i and m_i mixed rows; the terminal state is lambda_0.
-  std::vector<int32_t> hor(P.B), nx, nu, nc;
-  for (int b = 0; b < P.B; ++b) {
-    const int Nb = P.N[b];
-    const int64_t s0 = P.sbase[b];
-    hor[b] = Nb + 1;
-    nx.push_back(0);
-    for (int j = 1; j <= Nb + 1; ++j) nx.push_back(P.st[s0 + Nb - j + 1].n);
-    nu.push_back(P.st[s0 + Nb].k);
-    for (int j = 1; j <= Nb; ++j) nu.push_back(P.st[s0 + Nb - j].k);
-    nc.push_back(0);
-    for (int j = 1; j <= Nb; ++j) nc.push_back(P.st[s0 + Nb - j].m);
-    nc.push_back(0);
-  }
-  eclqr_dims dd{P.B, hor.data(), nx.data(), nu.data(), nc.data()};
-  err = p.dual.build(&dd);
-  if (!err.empty()) return "dual: " + err;
-
   // theta engine: the primal's stages with input capacity k_i + n_{i+1}
   {
     std::vector<int32_t> tu;
@@ -518,6 +498,32 @@ std::string build_plan(Plan& p, const eclqr_dims* d, const eclqr_options* opt) {
       p.th_ldw = std::max(p.th_ldw, R | 1);
       p.th_r = std::max(p.th_r, x.n);
     }
+  }
+
+  // the reversed-time engine: needed when the minimum-norm multipliers have
+  // no theta engine, or when the caller asks for both routes
+  p.has_dual = opt->multipliers == 1 && (!p.theta_ok || opt->reversed_time != 0);
+  if (!p.has_dual) p.mult_route = 1;
+  // Reversed-time stationarity problem (Section VII): stage 0 has an empty
+  // state and input mu_N; stage j = 1..N is primal stage i = N - j with state
+  // lambda_{i+1}, input mu_i and m_i mixed rows; the terminal state is lambda_0.
+  std::vector<int32_t> hor(P.B), nx, nu, nc;
+  for (int b = 0; b < P.B; ++b) {
+    const int Nb = P.N[b];
+    const int64_t s0 = P.sbase[b];
+    hor[b] = Nb + 1;
+    nx.push_back(0);
+    for (int j = 1; j <= Nb + 1; ++j) nx.push_back(P.st[s0 + Nb - j + 1].n);
+    nu.push_back(P.st[s0 + Nb].k);
+    for (int j = 1; j <= Nb; ++j) nu.push_back(P.st[s0 + Nb - j].k);
+    nc.push_back(0);
+    for (int j = 1; j <= Nb; ++j) nc.push_back(P.st[s0 + Nb - j].m);
+    nc.push_back(0);
+  }
+  eclqr_dims dd{P.B, hor.data(), nx.data(), nu.data(), nc.data()};
+  if (p.has_dual) {
+    err = p.dual.build(&dd);
+    if (!err.empty()) return "dual: " + err;
   }
 
   size_t o = 0;

@@ -83,6 +83,7 @@ struct Plan {
   // used then.
   Engine theta;
   bool theta_ok = false;
+  bool has_dual = false;      // the reversed-time engine is in the workspace
   size_t o_theta_eng = 0;
   size_t o_defer = 0;         // per level: count of deferred combines (2 D ints), then one task list
   int32_t th_q = 1, th_ldw = 1, th_r = 1;  // LDS tile of the local minimum-norm systems

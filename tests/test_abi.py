@@ -158,7 +158,7 @@ def _leaf_suffix_slots(plan, N):
 def test_batched_schedule_levels_merge_instances():
     probs = [tiny_problem(900 + s, N=N, n=2, m=1, kinds=[[]] * N, terminal_rows=0) for s, N in
              enumerate([3, 17, 1, 64])]
-    plan = ecl.Plan.for_problems(probs, scan_schedule=1)
+    plan = ecl.Plan.for_problems(probs, scan_schedule=1, reversed_time=1)
     levels = plan.schedule()
     D = len(levels) // 2
     assert D == 7  # ceil(log2(65))

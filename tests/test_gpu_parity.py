@@ -92,10 +92,17 @@ def test_reversed_time_multiplier_route():
     fam = [p for _, p in problem_family()]
     for tun in ({"multiplier_route": 0}, {"multiplier_route": 0, "overlap_dual": 0}):
         probs = config_c0()
-        check_parity(probs, gpu_solve(probs, tuning=tun))
-        check_parity(fam, gpu_solve(fam, tuning=tun))
+        res = gpu_solve(probs, tuning=tun, reversed_time=1)
+        assert ecl_tuning(res)["multiplier_route"] == 0
+        check_parity(probs, res)
+        check_parity(fam, gpu_solve(fam, tuning=tun, reversed_time=1))
     probs = config_c3(B=8, N_range=(32, 90))
-    check_parity(probs, gpu_solve(probs, tuning={"multiplier_route": 0}))
+    check_parity(probs, gpu_solve(probs, tuning={"multiplier_route": 0}, reversed_time=1))
+
+
+def ecl_tuning(res):
+    import paper_2407_05433_amd as ecl
+    return ecl.get_tuning(res["_plan"])
 
 
 def test_both_scan_schedules():
@@ -318,7 +325,7 @@ def test_autotune_keeps_results():
     import paper_2407_05433_amd as ecl
     from workloads import config_c3
     probs = config_c3(B=8, N_range=(32, 90))
-    plan = ecl.Plan.for_problems(probs)
+    plan = ecl.Plan.for_problems(probs, reversed_time=1)
     data = ecl.pack(plan, probs)
     ws = plan.workspace()
     ref = ecl.solve(plan, data, ws)
