@@ -53,6 +53,18 @@ def make(workload):
     return make_config(workload)
 
 
+def scan_schedule_name(plan):
+    """The scan parenthesization a plan runs: the option, with the default
+    hybrid named "doubling" where it reduces to pure doubling (no down-sweep)."""
+    opt = int(plan.options.scan_schedule)
+    if opt == 1:
+        return "balanced"
+    sched = plan.schedule()
+    if opt == 2 or all(len(lv) == 0 for lv in sched[len(sched) // 2:]):
+        return "doubling"
+    return "hybrid"
+
+
 def time_solves(ecl, torch, plan, data, ws, sol, steps, warmup):
     for _ in range(warmup):
         ecl.solve(plan, data, ws, sol)
@@ -320,8 +332,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "instances": len(problems),
                    "stages": stages, "multipliers": True, "launch": tuning,
-                   "scan_schedule": "doubling" if all(len(lv) == 0 for lv in plan.schedule()[len(plan.schedule()) // 2:])
-                   else "balanced",
+                   "scan_schedule": scan_schedule_name(plan),
                    "refine": {"max_steps": int(plan.options.refine), "tol": float(plan.options.refine_tol),
                               "steps_taken": {str(int(k)): int(v) for k, v in zip(*np.unique(rsteps, return_counts=True))}}},
         "roofline": roof,
