@@ -122,7 +122,10 @@ typedef struct {
   int32_t reversed_time;  /* with multipliers = 1: 1 also lays out the reversed-time stationarity problem in the
                            * workspace, so the tuning field multiplier_route can select it; 0 (default) only when
                            * the theta route is unavailable (a stage with k_i + n_{i+1} > 64) */
-  int32_t reserved[3];
+  int32_t domain_shortcut; /* 1 (default): an instance with no terminal rows whose every F_i has full row rank
+                           * (Section VI: every domain is the whole space) skips the relation scan; 0: every
+                           * instance runs it.  Both give the same solution */
+  int32_t reserved[2];
 } eclqr_options;
 
 /* Device pointers to the problem data (layout from eclqr_plan_layout).  M may
@@ -224,10 +227,11 @@ typedef struct {
                              * stacked system in registers instead of LDS */
   int32_t stage_lds;      /* stage eliminations and feedback gains keep their working arrays in LDS when these
                              need at most 32 KiB per workgroup (1, default), else in global scratch (0) */
-  int32_t overlap_dual;   /* with the minimum-norm multipliers, the reversed-time problem is factored (matrix data
-                           * only) on a second stream while the primal pass runs, and its vector-only replay at
-                           * the primal solution gives the multipliers (1, default); 0: one stream, full pass after
-                           * the primal pass */
+  int32_t overlap_dual;   /* with the minimum-norm multipliers, the multiplier route's problem is factored (matrix
+                           * data only) on a second stream while the primal pass runs, and its vector-only replay
+                           * at the primal solution gives the multipliers (1, default); 0: one stream, full pass
+                           * after the primal pass.  Route 0 forks at the start of the solve (the reversed-time
+                           * problem needs no primal data), route 1 once the primal pass has the domains */
   int32_t multiplier_route; /* how the minimum-norm multipliers (multipliers = 1) are computed: 1 (default where
                            * the stage input capacity k_i + n_{i+1} <= 64): from the primal pass's domains and
                            * scans, as an unconstrained LQR over the normal coordinates theta_i of the domains

@@ -35,7 +35,8 @@ class Dims(C.Structure):
 class Options(C.Structure):
     _fields_ = [("rank_tol", C.c_double), ("cons_tol", C.c_double), ("dual_cons_tol", C.c_double),
                 ("refine_tol", C.c_double), ("accept_tol", C.c_double), ("multipliers", C.c_int32), ("refine", C.c_int32), ("use_graph", C.c_int32),
-                ("scan_schedule", C.c_int32), ("reversed_time", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("scan_schedule", C.c_int32), ("reversed_time", C.c_int32), ("domain_shortcut", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 class Tuning(C.Structure):

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <string>
 #include <vector>
@@ -77,6 +78,7 @@ DevEngine dev_engine(const Engine& E, void* ws, size_t base) {
   d.rel_log_off = reinterpret_cast<const int64_t*>(b + E.o_rel_log_off);
   d.ric_log_off = reinterpret_cast<const int64_t*>(b + E.o_ric_log_off);
   d.rel_log = reinterpret_cast<double*>(b + E.o_rel_log);
+  d.vac = E.shortcut ? reinterpret_cast<const int32_t*>(b + E.o_vac) : nullptr;
   d.ric_log = reinterpret_cast<double*>(b + E.o_ric_log);
   d.scratch = reinterpret_cast<double*>(b + E.o_scratch);
   d.scratch_per_block = E.scratch_per_block;
@@ -214,10 +216,24 @@ eclqr_status bind(Plan& p, void* ws, hipStream_t s) {
   return ECLQR_SUCCESS;
 }
 
+// Launches for a second stream, made by a primal pass at fixed points of its
+// own launch sequence, so that the host feeds both streams in turn: step 0
+// after the domains, 1 after value-function level `level`, 2 after the gains,
+// 3 after forward level `level`.
+using SideLaunch = std::function<eclqr_status(int step, int level)>;
+
 // One pass of the primal method of Algorithm 1 on the data `in`, writing x, u.
 eclqr_status run_engine(const Engine& E, const DevEngine& d, const Inputs& in, double* x, double* u,
-                        int32_t* status, Tols t, hipStream_t s) {
+                        int32_t* status, Tols t, hipStream_t s, const SideLaunch& side = {}) {
+  auto at_step = [&](int step, int level) -> eclqr_status { return side ? side(step, level) : ECLQR_SUCCESS; };
+  eclqr_status sst = ECLQR_SUCCESS;
   { Timed tm(ECLQR_K_VALIDATE, s); launch_validate(d, in, status, s); }
+  if (E.shortcut) {  // which instances have whole-space domains (Section VI)
+    Timed tm(ECLQR_K_BASE_RELATION, s);
+    int32_t* vac = const_cast<int32_t*>(d.vac);
+    launch_fill_i32(vac, 1, E.B, s);
+    launch_vacuous(d, in, t, vac, std::max(1, E.maxk), std::max(1, E.maxm), s);
+  }
   { Timed tm(ECLQR_K_BASE_RELATION, s); launch_base_relation(d, in, t, status, E.base_maxp, E.base_ldw, s); }
   for (int l = 0; l < 2 * E.D; ++l) {
     // one launch per bucket, or (without buckets) per run of buckets of the
@@ -244,17 +260,25 @@ eclqr_status run_engine(const Engine& E, const DevEngine& d, const Inputs& in, d
     }
   }
   { Timed tm(ECLQR_K_DOMAIN, s); launch_domain(d, in, t, status, std::max(1, E.maxn), s); }
+  if ((sst = at_step(0, 0)) != ECLQR_SUCCESS) return sst;
   { Timed tm(ECLQR_K_ELIMINATE, s); launch_eliminate(d, in, t, status, std::max(1, E.maxm), E.elim_maxq, std::max(1, E.maxn), E.maxk, s); }
   for (int l = 0; l < 2 * E.D; ++l) {
     if (E.lvl_count[l] == 0) continue;
-    Timed tm(ECLQR_K_RIC_COMBINE, s);
-    launch_ric_combine(d, E.lvl_begin[l], E.lvl_count[l], status, std::max(1, E.lvl_dim[l]), s);
+    {
+      Timed tm(ECLQR_K_RIC_COMBINE, s);
+      launch_ric_combine(d, E.lvl_begin[l], E.lvl_count[l], status, std::max(1, E.lvl_dim[l]), s);
+    }
+    if ((sst = at_step(1, l)) != ECLQR_SUCCESS) return sst;
   }
   { Timed tm(ECLQR_K_GAINS, s); launch_gains(d, status, std::max(1, E.maxm), std::max(1, E.maxn), s); }
+  if ((sst = at_step(2, 0)) != ECLQR_SUCCESS) return sst;
   for (int l = 0; l < 2 * E.D; ++l) {
     if (E.lvl_count[l] == 0) continue;
-    Timed tm(ECLQR_K_FWD_COMBINE, s);
-    launch_fwd_combine(d, E.lvl_begin[l], E.lvl_count[l], s);
+    {
+      Timed tm(ECLQR_K_FWD_COMBINE, s);
+      launch_fwd_combine(d, E.lvl_begin[l], E.lvl_count[l], s);
+    }
+    if ((sst = at_step(3, l)) != ECLQR_SUCCESS) return sst;
   }
   { Timed tm(ECLQR_K_RECOVER, s); launch_recover(d, x, u, s); }
   HIP_OK(hipGetLastError());
@@ -431,7 +455,7 @@ eclqr_status theta_multipliers(Plan& p, const Views& v, const Inputs& in, const 
   const Tols td{p.opt.rank_tol, p.opt.dual_cons_tol, 0};
   {
     Timed tm(ECLQR_K_MULT_THETA, s);
-    if (!launch_theta_local(v.P, v.T, in, x, u, td, status, p.th_q, p.th_ldw, p.th_r, !full, s))
+    if (!launch_theta_local(v.P, v.T, in, x, u, td, status, p.th_q, p.th_ldw, p.th_r, full ? 0 : 1, s))
       return fail(ECLQR_UNSUPPORTED, "stage too large for the LDS tile of the minimum-norm local systems");
   }
   int32_t* defer = at<int32_t>(v.ws, p.o_defer);
@@ -485,6 +509,46 @@ eclqr_status theta_multipliers(Plan& p, const Views& v, const Inputs& in, const 
 
 bool theta_route(const Plan& p) { return p.opt.multipliers == 1 && p.theta_ok && p.mult_route == 1; }
 
+// The theta LQR's factorizations on their own (matrix pass of the local
+// systems, value-function scan, gains, forward scan, all with zero vectors),
+// on stream s2: every rank decision, factor log and matrix-dependent outcome
+// bit of its full pass, ready for the vector-only pass at the primal solution.
+// Needs only the primal pass's domains, so it runs beside the rest of that
+// pass, one step at each SideLaunch point (the theta engine runs the primal
+// schedule: the same levels).  Runs every instance (no refinement gate).
+eclqr_status theta_prefactor_step(Plan& p, const Views& v, const Inputs& in, hipStream_t s2, int step, int l) {
+  const Engine& T = p.theta;
+  DevEngine P = v.P, Th = v.T;
+  P.gate = Th.gate = nullptr;
+  P.live = Th.live = nullptr;
+  int32_t* defer = at<int32_t>(v.ws, p.o_defer);
+  if (step == 0) {
+    const Tols td{p.opt.rank_tol, p.opt.dual_cons_tol, 0};
+    Timed tm(ECLQR_K_MULT_THETA, s2);
+    launch_fill_i32(v.dstatus, 0, p.primal.B, s2);
+    if (!launch_theta_local(P, Th, in, nullptr, nullptr, td, v.dstatus, p.th_q, p.th_ldw, p.th_r, 2, s2))
+      return fail(ECLQR_UNSUPPORTED, "stage too large for the LDS tile of the minimum-norm local systems");
+    launch_fill_i32(defer, 0, 2 * T.D, s2);
+  } else if (step == 1 && T.lvl_count[l] > 0) {
+    Timed tm(ECLQR_K_RIC_COMBINE, s2);
+    const bool wide = T.lvl_count[l] > 4096;
+    launch_ric_combine_lane(Th, T.lvl_begin[l], T.lvl_count[l], wide ? defer + l : nullptr,
+                            wide ? defer + 2 * T.D + 4 : nullptr, s2);
+  } else if (step == 2) {
+    {
+      Timed tm(ECLQR_K_GAINS, s2);
+      launch_gains(Th, v.dstatus, std::max(1, T.maxm), std::max(1, T.maxn), s2);
+    }
+    Timed tm(ECLQR_K_MULT_THETA, s2);
+    launch_theta_init(Th, s2);
+  } else if (step == 3 && T.lvl_count[l] > 0) {
+    Timed tm(ECLQR_K_FWD_COMBINE, s2);
+    launch_fwd_combine(Th, T.lvl_begin[l], T.lvl_count[l], s2);
+  }
+  HIP_OK(hipGetLastError());
+  return ECLQR_SUCCESS;
+}
+
 constexpr int32_t kDualStructural = ECLQR_CAPACITY | ECLQR_NOT_CONVEX | ECLQR_INVALID_INPUT;
 
 // Full solve of the problem `in`: primal, multipliers, refinement.  With
@@ -509,15 +573,35 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
     launch_fill_i32(v.rsteps, 0, B, s);
     launch_fill_u64(v.omega, 0ull, B, s);
   }
-  eclqr_status st = replay ? run_engine_vec(p.primal, v.P, in, x, u, s)
-                           : run_engine(p.primal, v.P, in, x, u, status, tp, s);
-  if (st != ECLQR_SUCCESS) return st;
-  if (!want_mult) return ECLQR_SUCCESS;
   const bool fast = p.opt.multipliers == 2;
   const bool theta = theta_route(p);
+  // theta route: its factorizations run on the second stream once the
+  // primal pass has the domains, beside the rest of that pass
+  hipEvent_t theta_join = nullptr;
+  SideLaunch side;
+  if (want_mult && theta && !replay && p.overlap_dual)
+    side = [&](int step, int level) -> eclqr_status {
+      hipStream_t s2 = reinterpret_cast<hipStream_t>(p.aux_stream);
+      if (step == 0) {
+        HIP_OK(hipEventRecord(reinterpret_cast<hipEvent_t>(p.ev_fork), s));
+        HIP_OK(hipStreamWaitEvent(s2, reinterpret_cast<hipEvent_t>(p.ev_fork), 0));
+        theta_join = reinterpret_cast<hipEvent_t>(p.ev_join);
+      }
+      return theta_prefactor_step(p, v, in, s2, step, level);
+    };
+  eclqr_status st = replay ? run_engine_vec(p.primal, v.P, in, x, u, s)
+                           : run_engine(p.primal, v.P, in, x, u, status, tp, s, side);
+  if (theta_join) {  // also after a failed pass: the second stream is joined before anything returns
+    HIP_OK(hipEventRecord(theta_join, reinterpret_cast<hipStream_t>(p.aux_stream)));
+    HIP_OK(hipStreamWaitEvent(s, theta_join, 0));
+  }
+  if (st != ECLQR_SUCCESS) return st;
+  if (!want_mult) return ECLQR_SUCCESS;
   if (dual_join) {
     // the reversed-time problem was factored on the second stream
     HIP_OK(hipStreamWaitEvent(s, dual_join, 0));
+  } else if (theta_join) {
+    // the theta LQR was factored on the second stream (outcome bits in v.dstatus)
   } else if (replay || fast || theta) {
     Timed tm(ECLQR_K_REFINE_IO, s);
     launch_fill_i32(v.dstatus, 0, B, s);
@@ -525,7 +609,7 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
   if (fast)
     st = fast_multipliers(p, v, in, x, u, lam, mu, v.dstatus, false, s);
   else if (theta)
-    st = theta_multipliers(p, v, in, x, u, lam, mu, v.dstatus, !replay, false, s);
+    st = theta_multipliers(p, v, in, x, u, lam, mu, v.dstatus, !replay && !theta_join, false, s);
   else
     st = multipliers(p, v, in, x, u, lam, mu, s, replay || dual_join != nullptr);
   if (st != ECLQR_SUCCESS) return st;
@@ -654,6 +738,7 @@ void eclqr_default_options(eclqr_options* opt) {
   opt->multipliers = 1;
   opt->refine = 3;
   opt->use_graph = 0;
+  opt->domain_shortcut = 1;
 }
 
 const char* eclqr_status_string(int32_t status) {
@@ -681,7 +766,7 @@ eclqr_status eclqr_plan_create(eclqr_plan** out, const eclqr_dims* dims, const e
   if (opt) o = *opt;
   else eclqr_default_options(&o);
   if (!(o.rank_tol > 0) || !(o.cons_tol > 0) || !(o.dual_cons_tol > 0) || !(o.refine_tol >= 0) || !(o.accept_tol >= 0) || o.refine < 0 ||
-      o.refine > 4 || o.multipliers < 0 || o.multipliers > 2)
+      o.refine > 4 || o.multipliers < 0 || o.multipliers > 2 || o.domain_shortcut < 0 || o.domain_shortcut > 1)
     return fail(ECLQR_INVALID_ARGUMENT, "bad options");
   eclqr_plan* p = new (std::nothrow) eclqr_plan();
   if (!p) return fail(ECLQR_INVALID_ARGUMENT, "out of host memory");
@@ -1059,7 +1144,7 @@ eclqr_status eclqr_plan_autotune(eclqr_plan* plan, const eclqr_problem* prob, ec
   for (Knob& k : knobs) {
     if (st != ECLQR_SUCCESS) break;
     if (k.v == &p.mult_route && !(p.theta_ok && p.has_dual)) continue;
-    if (k.v == &p.overlap_dual && !p.has_dual) continue;
+    if (k.v == &p.overlap_dual && !p.has_dual && !theta_route(p)) continue;
     const int32_t old = *k.v;
     *k.v = k.alt;
     p.opt.use_graph = graph;

@@ -299,14 +299,22 @@ size_t theta_local_lds_bytes(int maxq, int ldw, int maxr) {
          sizeof(int) * (size_t)(ldw + 1) + 64;
 }
 
-// kVec: vector-only pass for new vectors with the same matrices (refinement
-// corrections, the adjoint): a stage other than the terminal one reuses the
-// factors the full pass kept (pivots, R11, Q1) and recomputes only y and the
-// vector parts of its element.
-template <bool kVec>
+// kMode 0: full pass.  kMode 1: vector-only pass for new vectors with the
+// same matrices (refinement corrections, the adjoint, the solution after a
+// matrix pass): a stage other than the terminal one reuses the factors the
+// last full or matrix pass kept (pivots, R11, Q1) and recomputes only y and
+// the vector parts of its element; with `status` it also checks the vector
+// column of the local system, M_i y_i = c_i at the minimum-norm y_i (the part
+// of the full pass's consistency test that depends on the vectors).
+// kMode 2: matrix pass: the full pass with every vector zero (no read of the
+// primal solution or of its value-function and forward scans, so it can run
+// beside them once the domains are known); the vector pass completes it.
+template <int kMode>
 __global__ void __launch_bounds__(kBlock) k_theta_local(DevEngine p, DevEngine th, Inputs in, const double* x,
                                                         const double* u, Tols t, int32_t* status, int maxq, int ldw,
                                                         int maxr) {
+  constexpr bool kVec = kMode == 1;
+  constexpr bool kMat = kMode == 2;
   extern __shared__ double lds[];
   double* W = lds;
   double* Qg = W + (int64_t)maxq * ldw;
@@ -330,32 +338,45 @@ __global__ void __launch_bounds__(kBlock) k_theta_local(DevEngine p, DevEngine t
     const int n = st.n, m = term ? 0 : st.m, k = st.k;
     const int ri = rdim(p, (int)s);
     const double* Hi = slot_ptr(p, SCAN_REL, st.suf[SCAN_REL]);  // r_i x (n + 1)
-    reduced_costate(p, s, wi, tmp);
-    const double* Q = in.f[IN_Q] + st.in[IN_Q];
-    const double* xs = x + st.in[IN_q];
-    const double* us = term ? nullptr : u + st.in[IN_r];
-    const double* Mm = (in.f[IN_M] && !term) ? in.f[IN_M] + st.in[IN_M] : nullptr;
-    for (int a = ECLQR_TID; a < n; a += ECLQR_NT) {
-      double v = lane_chain<false>(in.f[IN_q][st.in[IN_q] + a], Q + a * n, 1, xs, 1, n);
-      if (Mm) v = lane_chain<false>(v, Mm + a * m, 1, us, 1, m);
-      gx[a] = v;
-    }
-    if (!term) {
-      const double* R = in.f[IN_R] + st.in[IN_R];
-      for (int b = ECLQR_TID; b < m; b += ECLQR_NT) {
-        double v = lane_chain<false>(in.f[IN_r][st.in[IN_r] + b], R + b * m, 1, us, 1, m);
-        if (Mm) v = lane_chain<false>(v, Mm + b, m, xs, 1, n);
-        gu[b] = v;
+    if constexpr (kMat) {
+      for (int a = ECLQR_TID; a < n; a += ECLQR_NT) {
+        wi[a] = 0.0;
+        gx[a] = 0.0;
+      }
+      for (int b = ECLQR_TID; b < m; b += ECLQR_NT) gu[b] = 0.0;
+    } else {
+      reduced_costate(p, s, wi, tmp);
+      const double* Q = in.f[IN_Q] + st.in[IN_Q];
+      const double* xs = x + st.in[IN_q];
+      const double* us = term ? nullptr : u + st.in[IN_r];
+      const double* Mm = (in.f[IN_M] && !term) ? in.f[IN_M] + st.in[IN_M] : nullptr;
+      for (int a = ECLQR_TID; a < n; a += ECLQR_NT) {
+        double v = lane_chain<false>(in.f[IN_q][st.in[IN_q] + a], Q + a * n, 1, xs, 1, n);
+        if (Mm) v = lane_chain<false>(v, Mm + a * m, 1, us, 1, m);
+        gx[a] = v;
+      }
+      if (!term) {
+        const double* R = in.f[IN_R] + st.in[IN_R];
+        for (int b = ECLQR_TID; b < m; b += ECLQR_NT) {
+          double v = lane_chain<false>(in.f[IN_r][st.in[IN_r] + b], R + b * m, 1, us, 1, m);
+          if (Mm) v = lane_chain<false>(v, Mm + b, m, xs, 1, n);
+          gu[b] = v;
+        }
       }
     }
     lds_sync();
     int r1 = 0, n1 = 0;
     const double* H1 = nullptr;
     if (!term) {
-      reduced_costate(p, s + 1, w1, tmp);
       r1 = rdim(p, (int)s + 1);
       n1 = p.st[s + 1].n;
       H1 = slot_ptr(p, SCAN_REL, p.st[s + 1].suf[SCAN_REL]);  // r1 x (n1 + 1)
+      if constexpr (kMat) {
+        for (int a = ECLQR_TID; a < n1; a += ECLQR_NT) w1[a] = 0.0;
+        lds_sync();
+      } else {
+        reduced_costate(p, s + 1, w1, tmp);
+      }
     }
     const double* E = in.f[IN_E] + st.in[IN_E];
     const double* A = term ? nullptr : in.f[IN_A] + st.in[IN_A];
@@ -398,6 +419,33 @@ __global__ void __launch_bounds__(kBlock) k_theta_local(DevEngine p, DevEngine t
         const double v = lane_chain<false>(0.0, tb + at.Y + c, ri, Yl, 1, q);
         tb[at.qb + c] = v;
         ric[rl.eta + c] = -v;
+      }
+      if (status) {
+        // M_i y = c_i: [E' y_mu + A'(H_{i+1}' y_theta); F' y_mu + B'(H_{i+1}' y_theta)] = c,
+        // each row against its own terms' magnitudes
+        for (int j = lane; j < n1; j += ECLQR_NT) tmp[j] = lane_chain<false>(0.0, H1 + j, n1 + 1, Yl + k, 1, r1);
+        lds_sync();
+        bool bad = false;
+        for (int row = lane; row < Rr; row += ECLQR_NT) {
+          const bool xr = row < n;
+          const int a = xr ? row : row - n;
+          const double* G = xr ? E + a : F + a;
+          const double* D = xr ? A + a : B + a;
+          const int ldg = xr ? n : m;
+          double e = -cr[row], mag = fabs(cr[row]);
+          for (int c = 0; c < k; ++c) {
+            const double tl = G[c * ldg] * Yl[c];
+            e += tl;
+            mag += fabs(tl);
+          }
+          for (int j = 0; j < n1; ++j) {
+            const double tl = D[j * ldg] * tmp[j];
+            e += tl;
+            mag += fabs(tl);
+          }
+          if (!(fabs(e) <= t.cons * fmax(1.0, mag))) bad = true;
+        }
+        if (bad) flag(status, st.inst, ECLQR_RANK_INCONSISTENT);
       }
       wg_sync();
       continue;
@@ -578,21 +626,26 @@ __global__ void __launch_bounds__(kBlock) k_theta_final(DevEngine p, DevEngine t
 static int g_theta_max_lds = 65536;
 void theta_set_max_lds(int bytes) {
   g_theta_max_lds = bytes;
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_theta_local<false>),
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_theta_local<0>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_theta_local<true>),
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_theta_local<1>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_theta_local<2>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 bool launch_theta_local(const DevEngine& p, const DevEngine& th, const Inputs& in, const double* x, const double* u,
-                        Tols t, int32_t* status, int maxq, int ldw, int maxr, bool vec, hipStream_t s) {
+                        Tols t, int32_t* status, int maxq, int ldw, int maxr, int mode, hipStream_t s) {
   const size_t lds = theta_local_lds_bytes(maxq, ldw, maxr);
   if (lds > (size_t)g_theta_max_lds) return false;
-  if (vec)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_theta_local<true>), dim3(p.nblocks), dim3(kBlock), lds, s, p, th, in, x, u,
-                       t, status, maxq, ldw, maxr);
+  if (mode == 1)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_theta_local<1>), dim3(p.nblocks), dim3(kBlock), lds, s, p, th, in, x, u, t,
+                       status, maxq, ldw, maxr);
+  else if (mode == 2)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_theta_local<2>), dim3(p.nblocks), dim3(kBlock), lds, s, p, th, in, x, u, t,
+                       status, maxq, ldw, maxr);
   else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_theta_local<false>), dim3(p.nblocks), dim3(kBlock), lds, s, p, th, in, x,
-                       u, t, status, maxq, ldw, maxr);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_theta_local<0>), dim3(p.nblocks), dim3(kBlock), lds, s, p, th, in, x, u, t,
+                       status, maxq, ldw, maxr);
   return true;
 }
 void launch_theta_init(const DevEngine& th, hipStream_t s) {

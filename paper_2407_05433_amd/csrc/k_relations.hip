@@ -55,6 +55,56 @@ __device__ inline double scale_rows(double* W, int ld, int p, int ncoef, double*
   return wave_max(mx);
 }
 
+// The domain shortcut of Section VI.  X_i = R^{n_i} for every stage of an
+// instance when it has no terminal rows and every F_i has full row rank: by
+// induction from the terminal stage, if X_{i+1} is the whole space, stage i's
+// rows E_i x + F_i u + g_i = 0 can be met by some u_i for every x_i, so the
+// suffix relation of stage i has no rows.  Such an instance skips the
+// relation scan (every relation of it is left empty: the suffixes, the only
+// relations read after the scan, are exactly empty) and its domains are the
+// whole spaces.  vac[b] starts at 1; a stage that fails the test stores 0.
+// The test is stricter than the scan's rank decisions (pivots of the rows of
+// F_i, each scaled by the norm of its whole row [F_i E_i g_i], above
+// sqrt(rank_tol)), so an instance it accepts has no borderline row.
+// LDS: W (maxk x (maxm | 1)) | tau | qr scratch | perm
+__global__ void __launch_bounds__(kBlock) k_vacuous(DevEngine e, Inputs in, Tols t, int32_t* vac, int maxk,
+                                                    int maxm) {
+  extern __shared__ double lds[];
+  const int ld = maxm | 1;
+  double* W = lds;
+  double* tau = W + (int64_t)maxk * ld;
+  double* qd = tau + kMaxDim;
+  int* perm = (int*)(qd + kMaxDim + 8);
+  for (int64_t s = blockIdx.x; s < e.S; s += gridDim.x) {
+    const StageInfo st = e.st[s];
+    const int n = st.n, m = st.terminal ? 0 : st.m, k = st.k;
+    if (k == 0) continue;
+    if (st.terminal || k > m) {
+      if (ECLQR_TID == 0) vac[st.inst] = 0;
+      continue;
+    }
+    const double* E = in.f[IN_E] + st.in[IN_E];
+    const double* F = in.f[IN_F] + st.in[IN_F];
+    const double* g = in.f[IN_g] + st.in[IN_g];
+    for (int r = ECLQR_TID; r < k; r += ECLQR_NT) {
+      double ss = g[r] * g[r];
+      for (int j = 0; j < m; ++j) ss = fma(F[r * m + j], F[r * m + j], ss);
+      for (int j = 0; j < n; ++j) ss = fma(E[r * n + j], E[r * n + j], ss);
+      tau[r] = (ss > 0.0) ? 1.0 / sqrt(ss) : 0.0;
+    }
+    lds_sync();
+    for (int idx = ECLQR_TID; idx < k * m; idx += ECLQR_NT) {
+      const int r = idx / m, j = idx - (idx / m) * m;
+      W[r * ld + j] = F[idx] * tau[r];
+    }
+    lds_sync();
+    const int rho = wg_qr_colpiv(W, ld, k, m, 0, m, sqrt(t.rank), tau, QRScratch{qd, perm});
+    if (rho < k && ECLQR_TID == 0) vac[st.inst] = 0;
+    lds_sync();
+  }
+}
+
+
 // ---------------------------------------------------------------------------
 // Base relation of stage i (eq. (base-system), (base-relation)):
 //   [B; F] u + [[A, -I], [E, 0]] (x_i, x_{i+1}) + [c; g] = 0,
@@ -77,6 +127,14 @@ __global__ void __launch_bounds__(kBlock) k_base_relation(DevEngine e, Inputs in
     const int n = st.n, np = st.np, m = st.m, k = st.k;
     const int slot = st.elem[SCAN_REL];
     double* out = slot_ptr(e, SCAN_REL, slot);
+    if (e.vac && e.vac[st.inst]) {  // whole-space domains: every relation of the instance is empty
+      if (ECLQR_TID == 0) {
+        double* glog = e.rel_log + e.rel_log_off[slot];
+        glog[0] = glog[1] = glog[2] = glog[3] = 0.0;
+        e.slot_rows[slot] = 0;
+      }
+      continue;
+    }
     if (st.terminal) {
       const int p = k, ld = n + 1;
       const double* E = in.f[IN_E] + st.in[IN_E];
@@ -220,6 +278,13 @@ __global__ void __launch_bounds__(kBlock) k_rel_compose(DevEngine e, int64_t fir
     const int cap = e.slot_cap[o];
     const RelLog lg = rel_log_layout(P, (nb < P) ? nb : P, cap);
     double* glog = e.rel_log + e.rel_log_off[o];
+    if (p == 0) {  // no rows on either side: no rows in the composition
+      if (ECLQR_TID == 0) {
+        glog[0] = glog[1] = glog[2] = glog[3] = 0.0;
+        e.slot_rows[o] = 0;
+      }
+      continue;
+    }
     if (p > maxp || p > 2 * kMaxDim * 2) {
       if (ECLQR_TID == 0) {
         glog[0] = 0;
@@ -341,6 +406,13 @@ __global__ void __launch_bounds__(kBlock) k_rel_compose_reg(DevEngine e, int64_t
     const double* Rr = slot_ptr(e, SCAN_REL, bsl);
     double* out = slot_ptr(e, SCAN_REL, o);
     const int c = nb + na + nc + 1, kc = na + nc;
+    if (p == 0) {  // no rows on either side: no rows in the composition
+      if (lane == 0) {
+        glog[0] = glog[1] = glog[2] = glog[3] = 0.0;
+        e.slot_rows[o] = 0;
+      }
+      continue;
+    }
     if (ra == na + nb && rb == nb + nc && kc <= cap) {
       int bad_full = 0;
       point_compose(L, na + nb, ra, Rr, nb + nc, rb, na, nb, nc, Qb, t.cons, out, &bad_full);
@@ -535,6 +607,11 @@ size_t domain_lds_bytes(int maxn) {
 
 void launch_validate(const DevEngine& e, const Inputs& in, int32_t* status, hipStream_t s) {
   hipLaunchKernelGGL(k_validate, dim3(e.nblocks), dim3(kBlock), 0, s, e, in, status);
+}
+
+void launch_vacuous(const DevEngine& e, const Inputs& in, Tols t, int32_t* vac, int maxk, int maxm, hipStream_t s) {
+  const size_t lds = sizeof(double) * ((size_t)maxk * (maxm | 1) + 2 * kMaxDim + 8) + sizeof(int) * kMaxDim;
+  hipLaunchKernelGGL(k_vacuous, dim3(e.nblocks), dim3(kBlock), lds, s, e, in, t, vac, maxk, maxm);
 }
 
 void launch_base_relation(const DevEngine& e, const Inputs& in, Tols t, int32_t* status, int maxp, int ldw,

@@ -27,6 +27,7 @@ struct DevEngine {
   const int64_t* ric_log_off;
   double* rel_log;            // factor logs of the relation scan
   double* ric_log;            // factor logs of the value-function scan
+  const int32_t* vac;         // per-instance whole-space domains (relation scan skipped), null = none
   const int32_t* gate;        // per-instance refinement state, null = every instance runs
   const int32_t* live;        // instances still refining; 0 makes the kernels of a refinement step return at once
   double* scratch;            // per-workgroup global scratch
@@ -64,6 +65,8 @@ size_t domain_lds_bytes(int maxn);
 size_t elim_lds_bytes(int maxm, int maxq);
 size_t ric_lds_bytes(int maxd);
 size_t gains_lds_bytes(int maxm);
+// per-instance test of the domain shortcut (vac preset to 1; failing instances get 0)
+void launch_vacuous(const DevEngine& e, const Inputs& in, Tols t, int32_t* vac, int maxk, int maxm, hipStream_t s);
 void launch_base_relation(const DevEngine& e, const Inputs& in, Tols t, int32_t* status, int maxp, int ldw,
                           hipStream_t s);
 // maxkc: most coefficient columns (n_a + n_c) of a result in the launch
@@ -158,9 +161,12 @@ void launch_mult_final(const DevEngine& e, double* lam, double* mu, int accumula
 // the theta engine over the same schedule)
 void theta_set_max_lds(int bytes);
 size_t theta_local_lds_bytes(int maxq, int ldw, int maxr);
-// vec: reuse the local factors of the last full pass (new vectors, same matrices)
+// mode 0: full pass; 1: vector pass reusing the local factors of the last
+// full or matrix pass (new vectors, same matrices; with status, the vector
+// column's consistency is checked); 2: matrix pass (every vector zero; reads
+// neither x, u nor the primal's value-function and forward scans)
 bool launch_theta_local(const DevEngine& p, const DevEngine& th, const Inputs& in, const double* x, const double* u,
-                        Tols t, int32_t* status, int maxq, int ldw, int maxr, bool vec, hipStream_t s);
+                        Tols t, int32_t* status, int maxq, int ldw, int maxr, int mode, hipStream_t s);
 void launch_theta_init(const DevEngine& th, hipStream_t s);
 void launch_theta_final(const DevEngine& p, const DevEngine& th, double* lam, double* mu, int accumulate,
                         hipStream_t s);

@@ -425,6 +425,7 @@ std::string Engine::build(const eclqr_dims* d) {
   o_mbar = o; o = align256(o + sizeof(int32_t) * S);
   o_resid = o; o = align256(o + sizeof(double) * 4 * S);
   o_sbase = o; o = align256(o + sizeof(int64_t) * B);
+  o_vac = o; o = align256(o + sizeof(int32_t) * B);
   o_scratch = o; o = align256(o + sizeof(double) * scratch_per_block * nblocks);
   o_arena = o; o = align256(o + sizeof(double) * arena_total);
   o_rel_log_off = o; o = align256(o + sizeof(int64_t) * std::max<int32_t>(1, nslots));
@@ -467,6 +468,17 @@ std::string build_plan(Plan& p, const eclqr_dims* d, const eclqr_options* opt) {
   }
   std::string err = p.primal.build(d);
   if (!err.empty()) return err;
+  // domain shortcut (Section VI): possible for an instance with no terminal
+  // rows and k_i <= m_i at every stage; the device tests the ranks
+  if (opt->domain_shortcut) {
+    Engine& E = p.primal;
+    for (int b = 0; b < E.B && !E.shortcut; ++b) {
+      bool ok = true;
+      for (int64_t s = E.sbase[b]; s <= E.sbase[b] + E.N[b] && ok; ++s)
+        ok = E.st[s].terminal ? E.st[s].k == 0 : E.st[s].k <= E.st[s].m;
+      E.shortcut = ok;
+    }
+  }
   const Engine& P = p.primal;
   // theta engine: the primal's stages with input capacity k_i + n_{i+1}
   {

@@ -59,6 +59,7 @@ struct Engine {
   int32_t base_maxp = 0, base_ldw = 0, elim_maxq = 0;
   int32_t fast_rows = 0, fast_ldw = 0;  // LDS tile of the factor-reusing multiplier kernel
   bool need_rel = true;            // false: no relation-scan arenas or logs (an engine that only runs the LQR scans)
+  bool shortcut = false;           // some instance may have whole-space domains (no terminal rows, k_i <= m_i)
   int32_t bal_levels_ = 1 << 30;   // balanced levels before recursive doubling (0: pure doubling)
   int32_t nblocks = 0;             // grid of the stage-parallel kernels
   int64_t scratch_per_block = 0;   // doubles
@@ -67,7 +68,7 @@ struct Engine {
   size_t o_stage = 0, o_slot_off = 0, o_slot_na = 0, o_slot_nb = 0, o_slot_cap = 0, o_slot_rows = 0,
          o_tasks = 0, o_nbar = 0, o_mbar = 0, o_arena = 0, o_scan[SCAN_COUNT] = {0, 0, 0}, o_resid = 0,
          o_sbase = 0, o_scratch = 0, o_rel_log_off = 0, o_ric_log_off = 0, o_rel_log = 0, o_ric_log = 0,
-         o_theta = 0;
+         o_theta = 0, o_vac = 0;
   size_t bytes = 0;
 
   std::string build(const eclqr_dims* d);
@@ -112,7 +113,7 @@ struct Plan {
   int32_t pool_lds = 2;       // value-function combine LDS mode (0 global pool, 1 LDS pool, 2 all in LDS)
   int32_t grid_divisor = 1;   // grid of the stage-parallel kernels = nblocks / divisor
   int32_t reg_compose = 1;    // register-resident relation compositions where they fit
-  int32_t overlap_dual = 1;   // factor the reversed-time problem on a second stream beside the primal pass
+  int32_t overlap_dual = 1;   // factor the multiplier route's problem on a second stream beside the primal pass
   int32_t split_combine = 1;  // two wavefronts per value-function combine on levels that fit the device
   double tuned_ms = 0.0;
   void* graph_exec = nullptr;

@@ -345,13 +345,49 @@ def test_autotune_keeps_results():
         torch.cuda.synchronize()
         for f in ("x", "u", "lam", "mu", "status"):
             same = all(full[k] == base[k] for k in ("register_compose", "overlap_dual", "multiplier_route"))
-            if same or (full["multiplier_route"] == 1 and base["multiplier_route"] == 1 and
-                        full["register_compose"] == base["register_compose"]):
+            if same:
                 assert torch.equal(getattr(sol, f), ref[f]), (cfg, f)
             else:
                 # the LDS and register compositions differ in rounding only,
-                # and so do the multiplier routes (the theta LQR, the full and
-                # the replayed reversed-time passes)
+                # and so do the multiplier routes and their full and
+                # factor-then-replay passes (overlap_dual)
                 a, b = getattr(sol, f).double(), ref[f].double()
                 err = float((a - b).norm() / max(float(b.norm()), 1e-300))
                 assert err <= 1e-8, (cfg, f, err)
+
+
+def test_domain_shortcut():
+    """The domain shortcut of Section VI: instances with no terminal rows whose
+    every F_i has full row rank skip the relation scan (every relation slot of
+    theirs is left empty); the other instances of the same batch (a state-only
+    row, a terminal row, more mixed rows than inputs, a redundant row) run it.
+    With the shortcut on and off: oracle parity, and the two agree."""
+    _need_gpu()
+    from tests._util import rel_err, tiny_problem
+    from workloads import config_c4
+    probs = config_c4(B=3, N=24) + [
+        tiny_problem(1201, N=6, n=4, m=3, kinds=[["mixed", "state"]] * 6, terminal_rows=0),
+        tiny_problem(1202, N=6, n=4, m=3, kinds=[["mixed"]] * 6, terminal_rows=1),
+        tiny_problem(1203, N=5, n=3, m=2, kinds=[["mixed"] * 3] + [["mixed"]] * 4, terminal_rows=0),
+        tiny_problem(1204, N=7, n=3, m=2, kinds=[[]] * 7, terminal_rows=0),
+        tiny_problem(1205, N=6, n=4, m=3, kinds=[["mixed", "mixed"]] * 6, terminal_rows=0, redundant=(2,)),
+        tiny_problem(1206, N=6, n=4, m=3, kinds=[["mixed", "mixed"]] * 6, terminal_rows=0),
+    ]
+    vacuous = [True, True, True, False, False, False, True, False, True]
+    res = {}
+    for sc in (1, 0):
+        r = gpu_solve(probs, domain_shortcut=sc)
+        check_parity(probs, r)
+        plan = r["_plan"]
+        rows = plan.scan_rows(r["_ws"])
+        inst = plan.slot_info()[0]
+        for b, v in enumerate(vacuous):
+            sel = inst == b
+            if sc and v:
+                assert np.all(rows[sel] == 0), (b, rows[sel])
+            else:
+                assert np.any(rows[sel] > 0), (sc, b)
+        res[sc] = r
+    for b in range(len(probs)):
+        for key in ("x", "u", "lam", "mu"):
+            assert rel_err(res[1][key][b], res[0][key][b]) <= 1e-11, (b, key)

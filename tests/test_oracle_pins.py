@@ -352,3 +352,33 @@ def test_degenerate_batched_instance_uses_lsqr_route():
     ns = solve_nullspace(p)
     assert rel_err(s["lam"], ns["lam"]) < 1e-10 and rel_err(s["mu"], ns["mu"]) < 1e-10
     assert rel_err(s["x"], ns["x"]) < 1e-10
+
+
+def _f_full_row_rank(p) -> bool:
+    return all(p.F[i].shape[0] == 0 or np.linalg.matrix_rank(p.F[i]) == p.F[i].shape[0] for i in range(p.N))
+
+
+def test_whole_space_domains_condition():
+    """Section VI: with no terminal rows and every F_i of full row rank, every
+    suffix relation of the oracle's scan is empty (X_i is the whole space);
+    a state-only row, a terminal row, or more mixed rows than inputs at a
+    stage leaves rows in some suffix.  This is the condition the domain
+    shortcut tests per instance on the device."""
+    from workloads import config_c4
+    vac = config_c4(B=2, N=12) + [tiny_problem(1204, N=7, n=3, m=2, kinds=[[]] * 7, terminal_rows=0),
+                                  tiny_problem(1206, N=6, n=4, m=3, kinds=[["mixed", "mixed"]] * 6,
+                                               terminal_rows=0)]
+    for p in vac:
+        assert p.E[p.N].shape[0] == 0 and _f_full_row_rank(p)
+        r = solve_sequential(p, keep_relations=True)
+        assert r.status == "ok"
+        assert all(S.L.shape[0] == 0 for S in r.suffix)
+        # the base relations themselves are not empty: the dynamics live there
+        assert all(R.L.shape[0] > 0 for R in r.relations[:p.N])
+    nonvac = [tiny_problem(1201, N=6, n=4, m=3, kinds=[["mixed", "state"]] * 6, terminal_rows=0),
+              tiny_problem(1202, N=6, n=4, m=3, kinds=[["mixed"]] * 6, terminal_rows=1),
+              tiny_problem(1203, N=5, n=3, m=2, kinds=[["mixed"] * 3] + [["mixed"]] * 4, terminal_rows=0)]
+    for p in nonvac:
+        r = solve_sequential(p, keep_relations=True)
+        assert r.status == "ok"
+        assert any(S.L.shape[0] > 0 for S in r.suffix)
