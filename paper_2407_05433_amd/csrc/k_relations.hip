@@ -83,14 +83,23 @@ __global__ void __launch_bounds__(kBlock) k_vacuous(DevEngine e, Inputs in, Tols
       if (ECLQR_TID == 0) vac[st.inst] = 0;
       continue;
     }
+    if (vac[st.inst] == 0) continue;  // another stage already failed the test
     const double* E = in.f[IN_E] + st.in[IN_E];
     const double* F = in.f[IN_F] + st.in[IN_F];
     const double* g = in.f[IN_g] + st.in[IN_g];
+    bool zero_row = false;  // a row with F = 0 (a state-only row) fails without a factorization
     for (int r = ECLQR_TID; r < k; r += ECLQR_NT) {
-      double ss = g[r] * g[r];
-      for (int j = 0; j < m; ++j) ss = fma(F[r * m + j], F[r * m + j], ss);
+      double sf = 0.0, ss = g[r] * g[r];
+      for (int j = 0; j < m; ++j) sf = fma(F[r * m + j], F[r * m + j], sf);
       for (int j = 0; j < n; ++j) ss = fma(E[r * n + j], E[r * n + j], ss);
+      ss += sf;
+      zero_row = zero_row || !(sf > 0.0);
       tau[r] = (ss > 0.0) ? 1.0 / sqrt(ss) : 0.0;
+    }
+    if (__ballot(zero_row) != 0) {
+      if (ECLQR_TID == 0) vac[st.inst] = 0;
+      lds_sync();
+      continue;
     }
     lds_sync();
     for (int idx = ECLQR_TID; idx < k * m; idx += ECLQR_NT) {
