@@ -227,11 +227,12 @@ typedef struct {
                              * stacked system in registers instead of LDS */
   int32_t stage_lds;      /* stage eliminations and feedback gains keep their working arrays in LDS when these
                              need at most 32 KiB per workgroup (1, default), else in global scratch (0) */
-  int32_t overlap_dual;   /* with the minimum-norm multipliers, the multiplier route's problem is factored (matrix
-                           * data only) on a second stream while the primal pass runs, and its vector-only replay
-                           * at the primal solution gives the multipliers (1, default); 0: one stream, full pass
-                           * after the primal pass.  Route 0 forks at the start of the solve (the reversed-time
-                           * problem needs no primal data), route 1 once the primal pass has the domains */
+  int32_t overlap_dual;   /* with the minimum-norm multipliers, 1: the multiplier route's problem is factored
+                           * (matrix data only) on a second stream while the primal pass runs, and its vector-only
+                           * replay at the primal solution gives the multipliers; 0: one stream, full pass after
+                           * the primal pass.  Route 0 forks at the start of the solve (the reversed-time problem
+                           * needs no primal data), route 1 once the primal pass has the domains.  Default 0 on
+                           * plans whose default route is 1 (it pays only on large batches), else 1 */
   int32_t multiplier_route; /* how the minimum-norm multipliers (multipliers = 1) are computed: 1 (default where
                            * the stage input capacity k_i + n_{i+1} <= 64): from the primal pass's domains and
                            * scans, as an unconstrained LQR over the normal coordinates theta_i of the domains

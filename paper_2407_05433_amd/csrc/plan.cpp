@@ -502,6 +502,9 @@ std::string build_plan(Plan& p, const eclqr_dims* d, const eclqr_options* opt) {
     }
     p.theta_ok = ok;
     p.mult_route = ok ? 1 : 0;
+    // the theta factorization beside the primal pass pays only on large
+    // batches (the autotuner tries it); the reversed-time one pays everywhere
+    p.overlap_dual = ok ? 0 : 1;
     p.th_q = p.th_ldw = p.th_r = 1;
     for (int64_t s = 0; s < P.S; ++s) {
       const StageInfo& x = P.st[s];

@@ -114,6 +114,7 @@ struct Plan {
   int32_t grid_divisor = 1;   // grid of the stage-parallel kernels = nblocks / divisor
   int32_t reg_compose = 1;    // register-resident relation compositions where they fit
   int32_t overlap_dual = 1;   // factor the multiplier route's problem on a second stream beside the primal pass
+                              // (plan default: 0 with the theta route, 1 without)
   int32_t split_combine = 1;  // two wavefronts per value-function combine on levels that fit the device
   double tuned_ms = 0.0;
   void* graph_exec = nullptr;

@@ -90,7 +90,7 @@ def test_reversed_time_multiplier_route():
     from tests._util import problem_family
     from workloads import config_c0, config_c3
     fam = [p for _, p in problem_family()]
-    for tun in ({"multiplier_route": 0}, {"multiplier_route": 0, "overlap_dual": 0}):
+    for tun in ({"multiplier_route": 0, "overlap_dual": 1}, {"multiplier_route": 0, "overlap_dual": 0}):
         probs = config_c0()
         res = gpu_solve(probs, tuning=tun, reversed_time=1)
         assert ecl_tuning(res)["multiplier_route"] == 0
@@ -335,7 +335,9 @@ def test_autotune_keeps_results():
     tuned = ecl.autotune(plan, data, ws)
     assert tuned["ms_per_solve"] > 0
     for cfg in ({"level_buckets": 0}, {"pool_in_lds": 0}, {"pool_in_lds": 1}, {"stage_lds": 0}, {"grid_divisor": 4},
-                {"overlap_dual": 0}, {"multiplier_route": 1 - base["multiplier_route"]}, {"split_combine": 0},
+                {"overlap_dual": 1 - base["overlap_dual"]}, {"multiplier_route": 1 - base["multiplier_route"]},
+                {"multiplier_route": 1 - base["multiplier_route"], "overlap_dual": 1 - base["overlap_dual"]},
+                {"split_combine": 0},
                 {"use_graph": 1},
                 {"register_compose": 0}, tuned):
         full = dict(base)
@@ -391,3 +393,38 @@ def test_domain_shortcut():
     for b in range(len(probs)):
         for key in ("x", "u", "lam", "mu"):
             assert rel_err(res[1][key][b], res[0][key][b]) <= 1e-11, (b, key)
+
+
+def test_theta_route_overlapped_factorization():
+    """The theta LQR factored on the second stream once the domains are known
+    (matrix pass, then a vector pass at the primal solution): oracle parity on
+    the small case, the structural family and a batch; graph replays equal
+    the eager solve."""
+    _need_gpu()
+    import paper_2407_05433_amd as ecl
+    from tests._util import problem_family
+    from workloads import config_c0, config_c3
+    tun = {"overlap_dual": 1, "multiplier_route": 1}
+    probs = config_c0()
+    res = gpu_solve(probs, tuning=tun)
+    assert ecl_tuning(res)["overlap_dual"] == 1
+    check_parity(probs, res)
+    fam = [p for _, p in problem_family()]
+    check_parity(fam, gpu_solve(fam, tuning=tun))
+    probs = config_c3(B=8, N_range=(32, 90))
+    check_parity(probs, gpu_solve(probs, tuning=tun))
+    eager = ecl.Plan.for_problems(probs)
+    graph = ecl.Plan.for_problems(probs, use_graph=1)
+    for pl in (eager, graph):
+        ecl.set_tuning(pl, **tun)
+    data = ecl.pack(eager, probs)
+    ref = ecl.solve(eager, data, eager.workspace())
+    ws_g = graph.workspace()
+    sol = ecl.allocate_solution(graph)
+    for rep in range(3):
+        ecl.solve(graph, data, ws_g, sol)
+        torch.cuda.synchronize()
+        for f in ("x", "u", "lam", "mu", "status"):
+            assert torch.equal(getattr(sol, f), getattr(ref, f)), (rep, f)
+        (data["q"] * 2.0).sum().item()
+        torch.cuda.synchronize()
