@@ -42,6 +42,17 @@ def test_status_strings_and_defaults():
     assert L.eclqr_status_string(2) == b"infeasible_initial"
     o = ecl.default_options()
     assert o.rank_tol == 1e-10 and o.cons_tol == 1e-8 and o.multipliers == 1 and o.refine == 3 and o.refine_tol == 1e-8
+    assert o.domain_shortcut == 1 and o.reversed_time == 0 and o.scan_schedule == 0
+
+
+def test_plan_rejects_bad_options():
+    dims = [([3, 3, 3], [2, 2], [1, 1, 0])]
+    for bad in ({"domain_shortcut": 2}, {"domain_shortcut": -1}, {"multipliers": 3}, {"refine": 5},
+                {"scan_schedule": 3}):
+        with pytest.raises(ecl.EclqrError):
+            ecl.Plan(dims, **bad)
+    for ok in ({"domain_shortcut": 0}, {"domain_shortcut": 1}):
+        ecl.Plan(dims, **ok)
 
 
 def test_plan_rejects_bad_dims():
