@@ -58,3 +58,22 @@ def problem_family():
     # one input and a state row per stage: long-interval relations keep rows
     out.append(("state-heavy", tiny_problem(309, N=8, n=4, m=1, kinds=[["state"]] * 8, terminal_rows=2)))
     return out
+
+
+def indefinite_cost_problems():
+    """Instances whose costs are indefinite only along directions the
+    constraints fix, so the reduced problem is strictly convex: R_i with
+    eigenvalue -2 along the u-direction of a mixed row, and Q_i with
+    eigenvalue -2 along the normal of a state row (stages 1..N, terminal row
+    included).  A third instance leaves the negative direction of R_1 free."""
+    p1 = tiny_problem(1301, N=5, n=3, m=2, kinds=[["mixed"]] * 5, terminal_rows=0)
+    for i in range(p1.N):
+        d = p1.F[i][0] / np.linalg.norm(p1.F[i][0])
+        p1.R[i] = np.eye(2) - 3.0 * np.outer(d, d)
+    p2 = tiny_problem(1302, N=5, n=3, m=2, kinds=[["state"]] * 5, terminal_rows=1)
+    for i in range(1, p2.N + 1):
+        e = p2.E[i][0] / np.linalg.norm(p2.E[i][0])
+        p2.Q[i] = np.eye(3) - 3.0 * np.outer(e, e)
+    p3 = tiny_problem(1303, N=4, n=3, m=2, kinds=[[]] * 4, terminal_rows=0)
+    p3.R[1] = np.diag([1.0, -1.0])
+    return p1, p2, p3

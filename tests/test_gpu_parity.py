@@ -428,3 +428,19 @@ def test_theta_route_overlapped_factorization():
             assert torch.equal(getattr(sol, f), getattr(ref, f)), (rep, f)
         (data["q"] * 2.0).sum().item()
         torch.cuda.synchronize()
+
+
+def test_indefinite_costs_with_convex_reduction():
+    """Convexity is needed only on the feasible set: R_i or Q_i indefinite
+    along directions the constraints fix reduce to a strictly convex problem
+    and match the oracle (both multiplier routes); a negative direction left
+    free is reported as not convex (status bit 8) without touching the other
+    instances of the batch."""
+    _need_gpu()
+    from tests._util import indefinite_cost_problems
+    p1, p2, p3 = indefinite_cost_problems()
+    check_parity([p1, p2], gpu_solve([p1, p2]))
+    check_parity([p1, p2], gpu_solve([p1, p2], tuning={"multiplier_route": 0}, reversed_time=1))
+    res = gpu_solve([p1, p3, p2])
+    assert res["status"][1] & 8, res["status"]
+    check_parity([p1, p2], {k: [v[0], v[2]] for k, v in res.items() if not k.startswith("_")})

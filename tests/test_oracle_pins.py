@@ -382,3 +382,19 @@ def test_whole_space_domains_condition():
         r = solve_sequential(p, keep_relations=True)
         assert r.status == "ok"
         assert any(S.L.shape[0] > 0 for S in r.suffix)
+
+
+def test_indefinite_costs_with_convex_reduction():
+    """Costs indefinite only along directions the constraints fix: the
+    oracle's reduction (Algorithm 1) equals the dense KKT solve, and the
+    reduced input and state Hessians it forms are positive definite."""
+    from tests._util import indefinite_cost_problems
+    p1, p2, _ = indefinite_cost_problems()
+    for p in (p1, p2):
+        assert min(np.linalg.eigvalsh(R).min() for R in p.R) < 0 or min(np.linalg.eigvalsh(Q).min() for Q in p.Q) < 0
+        r = solve_sequential(p)
+        assert r.status == "ok"
+        d = solve_dense(p)
+        for key in ("x", "u"):
+            assert rel_err(getattr(r, key), d[key]) <= 1e-10, key
+        assert all(np.linalg.eigvalsh(Rb).min() > 0 for Rb in r.Rbar if Rb.size)
