@@ -188,7 +188,7 @@ def test_c3_full_batch_sampled():
     import paper_2407_05433_amd as ecl
     from workloads import config_c3
     probs = config_c3()
-    res = gpu_solve(probs)
+    res = bench_config_solve(probs)
     assert np.all(np.array(res["status"]) == 0), np.nonzero(res["status"])
     check_parity(probs, res, idx=range(3, 512, 37))
     r = ecl.kkt_residual(res["_plan"], res["_data"], res["_sol"], res["_ws"]).cpu().numpy()
@@ -444,3 +444,49 @@ def test_indefinite_costs_with_convex_reduction():
     res = gpu_solve([p1, p3, p2])
     assert res["status"][1] & 8, res["status"]
     check_parity([p1, p2], {k: [v[0], v[2]] for k, v in res.items() if not k.startswith("_")})
+
+
+def bench_config_solve(probs):
+    """A solve in the launch configuration bench.py times: hipGraph replay of
+    an autotuned plan (the replay after the capturing solve is returned)."""
+    import paper_2407_05433_amd as ecl
+    plan = ecl.Plan.for_problems(probs, use_graph=1)
+    data = ecl.pack(plan, probs)
+    ws = plan.workspace()
+    ecl.autotune(plan, data, ws)
+    sol = ecl.allocate_solution(plan)
+    for _ in range(2):
+        ecl.solve(plan, data, ws, sol)
+    torch.cuda.synchronize()
+    return {
+        "status": sol.status.cpu().tolist(),
+        "x": ecl.unpack(plan, sol.x, "q", probs), "u": ecl.unpack(plan, sol.u, "r", probs),
+        "lam": ecl.unpack(plan, sol.lam, "q", probs), "mu": ecl.unpack(plan, sol.mu, "g", probs),
+        "_plan": plan, "_data": data, "_sol": sol, "_ws": ws,
+    }
+
+
+@pytest.mark.parametrize("workload", ["c1", "c2", "c4", "paper"])
+def test_full_size_bench_configuration(workload):
+    """The full-size workloads in the launch configuration bench.py times
+    (autotuned plan, graph replay): every instance through the oracle's KKT
+    residual computed on the host from the returned x, u, lambda, mu (initial
+    condition, dynamics and normalised equality rows absolute, stationarity
+    relative to the largest multiplier), and sampled instances of the batch
+    against the oracle's solution."""
+    _need_gpu()
+    from oracle.residual import kkt_residual
+    from workloads import config_c1, config_c2, config_c4, config_paper
+    probs = {"c1": config_c1, "c2": config_c2, "c4": config_c4, "paper": lambda: config_paper(8192)}[workload]()
+    res = bench_config_solve(probs)
+    assert np.all(np.array(res["status"]) == 0), np.nonzero(res["status"])
+    for b, p in enumerate(probs):
+        r = kkt_residual(p, res["x"][b], res["u"][b], res["lam"][b], res["mu"][b])
+        scale = max(1.0, max(np.abs(v).max(initial=0.0) for v in res["lam"][b]),
+                    max(np.abs(v).max(initial=0.0) for v in res["mu"][b]))
+        assert max(r["initial"], r["dynamics"], r["equality"]) < 1e-8, (b, r)
+        assert r["stationarity"] <= 1e-7 * scale, (b, r, scale)
+    if workload == "c4":
+        check_parity(probs, res, idx=range(5, 256, 50))
+    if workload == "c1":
+        check_parity(probs, res)
