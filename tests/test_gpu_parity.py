@@ -490,3 +490,38 @@ def test_full_size_bench_configuration(workload):
         check_parity(probs, res, idx=range(5, 256, 50))
     if workload == "c1":
         check_parity(probs, res)
+
+
+def test_maximum_dims():
+    """Stage dims at the kernels' limit (64): state dim 64 with few inputs,
+    input dim 64, and both.  Each instance is either solved (oracle parity)
+    or reported as out of on-chip capacity, never a silent wrong answer:
+    ECLQR_CAPACITY (bit 32: a relation composition whose stacked rows outgrow
+    the device's LDS; bits that follow from the truncated relation may be set
+    too), or ECLQR_DUAL_FAILED with the capacity bit repeated in bits 8..15
+    (the reversed-time problem, used when k_i + n_{i+1} > 64, outgrew the
+    tile).  A reported instance's outputs are NaN, as the ABI states.  In a
+    batch the other instances are unaffected."""
+    _need_gpu()
+    from tests._util import tiny_problem
+    probs = [
+        tiny_problem(1472, N=3, n=64, m=8, kinds=[["mixed", "state", "mixed", "state"]] * 3, terminal_rows=2),
+        tiny_problem(1480, N=3, n=16, m=64, kinds=[["mixed"] * 8] * 3, terminal_rows=1),
+        tiny_problem(1528, N=2, n=64, m=64, kinds=[["mixed"] * 6 + ["state"] * 2] * 2, terminal_rows=3),
+        tiny_problem(1529, N=6, n=4, m=2, terminal_rows=1),
+    ]
+
+    def check(res, b, p, i):
+        st = res["status"][i]
+        if st == 0:
+            check_parity([p], {k: [v[i]] for k, v in res.items() if not k.startswith("_")})
+        else:
+            assert (st & 32) or (st & 64 and (st >> 8) & 32), (b, st)
+            for key in ("x", "u", "lam", "mu"):
+                assert np.all(np.isnan(np.concatenate([v.ravel() for v in res[key][i]]))), (b, key)
+        return st
+
+    outcomes = [check(gpu_solve([p]), b, p, 0) for b, p in enumerate(probs)]
+    assert outcomes[1] == 0 and outcomes[3] == 0, outcomes
+    res = gpu_solve(probs)
+    assert [check(res, b, p, b) for b, p in enumerate(probs)] == outcomes
