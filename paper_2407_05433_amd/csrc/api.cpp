@@ -79,6 +79,9 @@ DevEngine dev_engine(const Engine& E, void* ws, size_t base) {
   d.ric_log_off = reinterpret_cast<const int64_t*>(b + E.o_ric_log_off);
   d.rel_log = reinterpret_cast<double*>(b + E.o_rel_log);
   d.vac = E.shortcut ? reinterpret_cast<const int32_t*>(b + E.o_vac) : nullptr;
+  d.gw = E.gw_blocks > 0 ? reinterpret_cast<double*>(b + E.o_gw) : nullptr;
+  d.gw_stride = E.gw_stride;
+  d.gw_blocks = E.gw_blocks;
   d.ric_log = reinterpret_cast<double*>(b + E.o_ric_log);
   d.scratch = reinterpret_cast<double*>(b + E.o_scratch);
   d.scratch_per_block = E.scratch_per_block;
@@ -251,9 +254,10 @@ eclqr_status run_engine(const Engine& E, const DevEngine& d, const Inputs& in, d
       }
       const int64_t first = E.bkt_begin[k];
       const int64_t count = E.bkt_begin[k1 - 1] + E.bkt_count[k1 - 1] - first;
-      // rows of the stacked system that fit the device's LDS (larger tasks are flagged ECLQR_CAPACITY)
+      // rows of the stacked system that fit the device's LDS or a global
+      // tile of the plan (larger tasks are flagged ECLQR_CAPACITY)
       if (!E.bkt_fit[k])
-        while (rows > 1 && rel_lds_bytes(rows, ldw) > (size_t)g_max_lds) --rows;
+        while (rows > 1 && !rel_fits(d, rows, ldw)) --rows;
       Timed tm(ECLQR_K_REL_COMPOSE, s);
       launch_rel_compose(d, first, count, t, status, rows, ldw, kc, s);
       k = k1;

@@ -121,11 +121,15 @@ __global__ void __launch_bounds__(kBlock) k_vacuous(DevEngine e, Inputs in, Tols
 // input columns; the remaining equations are replaced by an orthonormal row
 // basis.  The terminal relation (eq. (terminal-relation)) is E_N x_N + g_N = 0.
 // LDS: W (maxp x ldw) | tau (64) | qr scratch (64+8) | perm (64 ints) | rb scratch
+// kGW: the stacked system in the workgroup's tile of global memory (e.gw)
+// instead of LDS, for systems that outgrow the device's LDS; the small work
+// arrays stay in LDS.
+template <bool kGW>
 __global__ void __launch_bounds__(kBlock) k_base_relation(DevEngine e, Inputs in, Tols t, int32_t* status, int maxp,
                                                           int ldw) {
   extern __shared__ double lds[];
-  double* W = lds;
-  double* tau = W + (int64_t)maxp * (ldw | 1);
+  double* W = kGW ? e.gw + (int64_t)blockIdx.x * e.gw_stride : lds;
+  double* tau = kGW ? lds : W + (int64_t)maxp * (ldw | 1);
   double* qd = tau + kMaxDim;
   int* perm = (int*)(qd + kMaxDim + 8);
   double* rbs = (double*)(perm + kMaxDim);
@@ -263,11 +267,12 @@ __device__ inline void point_compose(const double* L, int lda, int ra, const dou
 // over the columns (b | a | c | 1), eliminate b with Lemma 1 (pivoted
 // Householder on the b columns) and keep an orthonormal row basis of the rest.
 // A unary right operand (n_c = 0) gives a unary result.
+template <bool kGW>
 __global__ void __launch_bounds__(kBlock) k_rel_compose(DevEngine e, int64_t first, int64_t ntasks, Tols t,
                                                         int32_t* status, int maxp, int ldw) {
   extern __shared__ double lds[];
-  double* W = lds;
-  double* tau = W + (int64_t)maxp * (ldw | 1);
+  double* W = kGW ? e.gw + (int64_t)blockIdx.x * e.gw_stride : lds;
+  double* tau = kGW ? lds : W + (int64_t)maxp * (ldw | 1);
   double* qd = tau + kMaxDim;
   int* perm = (int*)(qd + kMaxDim + 8);
   double* rbs = (double*)(perm + kMaxDim);
@@ -597,11 +602,14 @@ __global__ void __launch_bounds__(kBlock) k_domain(DevEngine e, Inputs in, Tols 
 }
 
 // ---------------------------------------------------------------------------
+static int g_rel_max_lds = 65536;
 void relations_set_max_lds(int bytes) {
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_base_relation), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            bytes);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_rel_compose), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            bytes);
+  g_rel_max_lds = bytes;
+  for (const void* f : {reinterpret_cast<const void*>(k_base_relation<false>),
+                        reinterpret_cast<const void*>(k_base_relation<true>),
+                        reinterpret_cast<const void*>(k_rel_compose<false>),
+                        reinterpret_cast<const void*>(k_rel_compose<true>)})
+    (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_domain), hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
@@ -623,10 +631,27 @@ void launch_vacuous(const DevEngine& e, const Inputs& in, Tols t, int32_t* vac, 
   hipLaunchKernelGGL(k_vacuous, dim3(e.nblocks), dim3(kBlock), lds, s, e, in, t, vac, maxk, maxm);
 }
 
+// The stacked system of maxp x ldw doubles goes to a global tile when it
+// does not fit the device's LDS and the plan laid tiles out.
+static bool rel_global(const DevEngine& e, int maxp, int ldw) {
+  return rel_lds_bytes(maxp, ldw) > (size_t)g_rel_max_lds && e.gw && (int64_t)maxp * (ldw | 1) <= e.gw_stride;
+}
+static size_t rel_tile_bytes(int maxp, int ldw) { return sizeof(double) * (size_t)maxp * (ldw | 1); }
+
 void launch_base_relation(const DevEngine& e, const Inputs& in, Tols t, int32_t* status, int maxp, int ldw,
                           hipStream_t s) {
-  hipLaunchKernelGGL(k_base_relation, dim3(e.nblocks), dim3(kBlock), rel_lds_bytes(maxp, ldw), s, e, in, t, status,
-                     maxp, ldw);
+  if (rel_global(e, maxp, ldw)) {
+    const int grid = e.nblocks < e.gw_blocks ? e.nblocks : e.gw_blocks;
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_base_relation<true>), dim3(grid), dim3(kBlock),
+                       rel_lds_bytes(maxp, ldw) - rel_tile_bytes(maxp, ldw), s, e, in, t, status, maxp, ldw);
+    return;
+  }
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_base_relation<false>), dim3(e.nblocks), dim3(kBlock), rel_lds_bytes(maxp, ldw),
+                     s, e, in, t, status, maxp, ldw);
+}
+
+bool rel_fits(const DevEngine& e, int maxp, int ldw) {
+  return rel_lds_bytes(maxp, ldw) <= (size_t)g_rel_max_lds || rel_global(e, maxp, ldw);
 }
 
 void launch_rel_compose(const DevEngine& e, int64_t first, int64_t ntasks, Tols t, int32_t* status, int maxp, int ldw,
@@ -651,8 +676,14 @@ void launch_rel_compose(const DevEngine& e, int64_t first, int64_t ntasks, Tols 
 #undef ECLQR_REG
     return;
   }
-  hipLaunchKernelGGL(k_rel_compose, dim3(grid), dim3(kBlock), rel_lds_bytes(maxp, ldw), s, e, first, ntasks, t,
-                     status, maxp, ldw);
+  if (rel_global(e, maxp, ldw)) {
+    const int g2 = grid < e.gw_blocks ? grid : e.gw_blocks;
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rel_compose<true>), dim3(g2), dim3(kBlock),
+                       rel_lds_bytes(maxp, ldw) - rel_tile_bytes(maxp, ldw), s, e, first, ntasks, t, status, maxp, ldw);
+    return;
+  }
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rel_compose<false>), dim3(grid), dim3(kBlock), rel_lds_bytes(maxp, ldw), s, e,
+                     first, ntasks, t, status, maxp, ldw);
 }
 
 void launch_domain(const DevEngine& e, const Inputs& in, Tols t, int32_t* status, int maxn, hipStream_t s) {

@@ -30,6 +30,9 @@ struct DevEngine {
   const int32_t* vac;         // per-instance whole-space domains (relation scan skipped), null = none
   const int32_t* gate;        // per-instance refinement state, null = every instance runs
   const int32_t* live;        // instances still refining; 0 makes the kernels of a refinement step return at once
+  double* gw;                 // per-workgroup global tiles for stacked relation systems beyond LDS, null = none
+  int64_t gw_stride;          // doubles per tile
+  int32_t gw_blocks;          // tiles (workgroups of a launch that uses them)
   double* scratch;            // per-workgroup global scratch
   int64_t scratch_per_block;  // doubles
   int64_t S;
@@ -67,6 +70,8 @@ size_t ric_lds_bytes(int maxd);
 size_t gains_lds_bytes(int maxm);
 // per-instance test of the domain shortcut (vac preset to 1; failing instances get 0)
 void launch_vacuous(const DevEngine& e, const Inputs& in, Tols t, int32_t* vac, int maxk, int maxm, hipStream_t s);
+// a stacked relation system of maxp x ldw fits LDS or a global tile of the plan
+bool rel_fits(const DevEngine& e, int maxp, int ldw);
 void launch_base_relation(const DevEngine& e, const Inputs& in, Tols t, int32_t* status, int maxp, int ldw,
                           hipStream_t s);
 // maxkc: most coefficient columns (n_a + n_c) of a result in the launch

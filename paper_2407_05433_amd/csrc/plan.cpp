@@ -412,6 +412,22 @@ std::string Engine::build(const eclqr_dims* d) {
   scratch_per_block = rup4(scratch_per_block);
   nblocks = (int32_t)std::min<int64_t>(std::max<int64_t>(S, 1), 8192);
 
+  // global tiles for stacked relation systems that may outgrow LDS (48 KiB
+  // and more: the device's LDS also holds the small work arrays)
+  gw_stride = 0;
+  gw_blocks = 0;
+  if (need_rel) {
+    int64_t tile = (int64_t)base_maxp * (base_ldw | 1), widest = S;
+    for (size_t l = 0; l < lvl_rows.size(); ++l) {
+      tile = std::max(tile, (int64_t)lvl_rows[l] * (lvl_ldw[l] | 1));
+      widest = std::max(widest, lvl_count[l]);
+    }
+    if ((int64_t)sizeof(double) * tile > 48 * 1024) {
+      gw_stride = rup4(tile);
+      gw_blocks = (int32_t)std::min<int64_t>(256, std::max<int64_t>(1, widest));
+    }
+  }
+
   // ---- workspace map -------------------------------------------------------
   size_t o = 0;
   o_stage = o; o = align256(o + sizeof(StageInfo) * S);
@@ -426,6 +442,7 @@ std::string Engine::build(const eclqr_dims* d) {
   o_resid = o; o = align256(o + sizeof(double) * 4 * S);
   o_sbase = o; o = align256(o + sizeof(int64_t) * B);
   o_vac = o; o = align256(o + sizeof(int32_t) * B);
+  o_gw = o; o = align256(o + sizeof(double) * (size_t)gw_stride * gw_blocks);
   o_scratch = o; o = align256(o + sizeof(double) * scratch_per_block * nblocks);
   o_arena = o; o = align256(o + sizeof(double) * arena_total);
   o_rel_log_off = o; o = align256(o + sizeof(int64_t) * std::max<int32_t>(1, nslots));

@@ -60,6 +60,8 @@ struct Engine {
   int32_t fast_rows = 0, fast_ldw = 0;  // LDS tile of the factor-reusing multiplier kernel
   bool need_rel = true;            // false: no relation-scan arenas or logs (an engine that only runs the LQR scans)
   bool shortcut = false;           // some instance may have whole-space domains (no terminal rows, k_i <= m_i)
+  int64_t gw_stride = 0;           // doubles per global tile for stacked relation systems beyond LDS (0: none)
+  int32_t gw_blocks = 0;           // tiles
   int32_t bal_levels_ = 1 << 30;   // balanced levels before recursive doubling (0: pure doubling)
   int32_t nblocks = 0;             // grid of the stage-parallel kernels
   int64_t scratch_per_block = 0;   // doubles
@@ -68,7 +70,7 @@ struct Engine {
   size_t o_stage = 0, o_slot_off = 0, o_slot_na = 0, o_slot_nb = 0, o_slot_cap = 0, o_slot_rows = 0,
          o_tasks = 0, o_nbar = 0, o_mbar = 0, o_arena = 0, o_scan[SCAN_COUNT] = {0, 0, 0}, o_resid = 0,
          o_sbase = 0, o_scratch = 0, o_rel_log_off = 0, o_ric_log_off = 0, o_rel_log = 0, o_ric_log = 0,
-         o_theta = 0, o_vac = 0;
+         o_theta = 0, o_vac = 0, o_gw = 0;
   size_t bytes = 0;
 
   std::string build(const eclqr_dims* d);
