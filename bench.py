@@ -265,8 +265,9 @@ def main():
                     help="only copy MIB MiB device-to-device once (reference for hardware byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the solver has no multi-GPU path (batches and horizons shard "
-              "across GPUs without communication, see DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the solver has no multi-GPU path (a batch would split across GPUs "
+              "by instances; a long horizon by stage chunks with one small all-gather per scan); "
+              "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
