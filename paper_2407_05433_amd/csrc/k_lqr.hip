@@ -239,8 +239,10 @@ __device__ __forceinline__ bool combine_factored(const double* A1, const double*
 constexpr int kLD = 4;
 
 // In-place Cholesky of the leading n x n block (identity beyond it); false
-// when a leading pivot is not above floor.
-__device__ __forceinline__ bool lc_chol(double (&S)[kLD][kLD], int n, double floor) {
+// when a leading pivot is not above floor.  rd: reciprocals of the diagonal
+// of the factor, for the triangular solves below (a multiply per entry
+// instead of a divide).
+__device__ __forceinline__ bool lc_chol(double (&S)[kLD][kLD], int n, double floor, double (&rd)[kLD]) {
   bool ok = true;
 #pragma unroll
   for (int j = 0; j < kLD; ++j) {
@@ -251,6 +253,7 @@ __device__ __forceinline__ bool lc_chol(double (&S)[kLD][kLD], int n, double flo
     const double lj = (j < n) ? sqrt(d) : 1.0;
     const double rl = 1.0 / lj;
     S[j][j] = lj;
+    rd[j] = rl;
 #pragma unroll
     for (int i = j + 1; i < kLD; ++i) {
       double v = S[i][j];
@@ -263,23 +266,23 @@ __device__ __forceinline__ bool lc_chol(double (&S)[kLD][kLD], int n, double flo
   }
   return ok;
 }
-// x <- L^{-1} x, x <- L^{-T} x
-__device__ __forceinline__ void lc_fwd(const double (&L)[kLD][kLD], double (&x)[kLD]) {
+// x <- L^{-1} x, x <- L^{-T} x (rd: reciprocals of L's diagonal)
+__device__ __forceinline__ void lc_fwd(const double (&L)[kLD][kLD], const double (&rd)[kLD], double (&x)[kLD]) {
 #pragma unroll
   for (int i = 0; i < kLD; ++i) {
     double v = x[i];
 #pragma unroll
     for (int p = 0; p < i; ++p) v = fma(-L[i][p], x[p], v);
-    x[i] = v / L[i][i];
+    x[i] = v * rd[i];
   }
 }
-__device__ __forceinline__ void lc_bwd(const double (&L)[kLD][kLD], double (&x)[kLD]) {
+__device__ __forceinline__ void lc_bwd(const double (&L)[kLD][kLD], const double (&rd)[kLD], double (&x)[kLD]) {
 #pragma unroll
   for (int i = kLD - 1; i >= 0; --i) {
     double v = x[i];
 #pragma unroll
     for (int p = i + 1; p < kLD; ++p) v = fma(-L[p][i], x[p], v);
-    x[i] = v / L[i][i];
+    x[i] = v * rd[i];
   }
 }
 __device__ __forceinline__ void lc_sym(double (&S)[kLD][kLD]) {
@@ -368,7 +371,8 @@ __device__ __forceinline__ bool lane_combine(const double* E1, const RicLayout& 
   for (int i = 0; i < kLD; ++i)
 #pragma unroll
     for (int j = 0; j < kLD; ++j) L[i][j] = J2[i][j];
-  if (!lc_chol(L, dm, 1e-15 * mx)) return false;
+  double rL[kLD], rR[kLD];
+  if (!lc_chol(L, dm, 1e-15 * mx, rL)) return false;
   {
     // G = I + L'(C1 L)
     double C1[kLD][kLD], T[kLD][kLD];
@@ -393,14 +397,14 @@ __device__ __forceinline__ bool lane_combine(const double* E1, const RicLayout& 
       }
   }
   lc_sym(Rg);
-  if (!lc_chol(Rg, dm, 0.0)) return false;
+  if (!lc_chol(Rg, dm, 0.0, rR)) return false;
   lc_store(rlog + 4, L, dm, dm, dm);
   lc_store(rlog + 4 + dm * dm, Rg, dm, dm, dm);
   rlog[0] = 1.0;
   // xi = L^{-1} eta2 ; d = G^{-1}(xi - L'b1) ; w = L d
   double xi[kLD], dv[kLD], wv[kLD];
   lc_loadv(xi, E2 + l2.eta, dm, safe);
-  lc_fwd(L, xi);
+  lc_fwd(L, rL, xi);
   {
     double b1[kLD];
     lc_loadv(b1, E1 + l1.b, dm, safe);
@@ -412,8 +416,8 @@ __device__ __forceinline__ bool lane_combine(const double* E1, const RicLayout& 
       dv[i] = v;
     }
   }
-  lc_fwd(Rg, dv);
-  lc_bwd(Rg, dv);
+  lc_fwd(Rg, rR, dv);
+  lc_bwd(Rg, rR, dv);
 #pragma unroll
   for (int i = 0; i < kLD; ++i) {
     double v = 0.0;
@@ -442,7 +446,7 @@ __device__ __forceinline__ bool lane_combine(const double* E1, const RicLayout& 
       double col[kLD];
 #pragma unroll
       for (int r = 0; r < kLD; ++r) col[r] = L[c][r];
-      lc_fwd(Rg, col);
+      lc_fwd(Rg, rR, col);
 #pragma unroll
       for (int r = 0; r < kLD; ++r) Mm[r][c] = col[r];
     }
@@ -481,12 +485,12 @@ __device__ __forceinline__ bool lane_combine(const double* E1, const RicLayout& 
     double col[kLD];
 #pragma unroll
     for (int r = 0; r < kLD; ++r) col[r] = Yb[r][c];
-    lc_bwd(Rg, col);
-    lc_bwd(L, col);
+    lc_bwd(Rg, rR, col);
+    lc_bwd(L, rL, col);
 #pragma unroll
     for (int r = 0; r < kLD; ++r) Yb[r][c] = col[r];
   }
-  lc_bwd(L, yv);
+  lc_bwd(L, rL, yv);
   double A2[kLD][kLD], b2[kLD];
   lc_load(A2, E2 + l2.A, de, dm, dm, false, safe);
   lc_loadv(b2, E2 + l2.b, de, safe);
@@ -592,7 +596,8 @@ __device__ __forceinline__ bool lane_combine(const double* E1, const RicLayout& 
         }
     }
     lc_sym(G2);
-    if (!lc_chol(G2, rk, 0.0)) return false;
+    double r2[kLD];
+    if (!lc_chol(G2, rk, 0.0, r2)) return false;
     // AN = A2 K R2^{-T} (rows of (R2^{-1} K')' ), C += AN AN'
     double AN[kLD][kLD];
 #pragma unroll
@@ -605,7 +610,7 @@ __device__ __forceinline__ bool lane_combine(const double* E1, const RicLayout& 
         for (int i = 0; i < kLD; ++i) a = fma(A2[r][i], K[i][j], a);
         v[j] = a;
       }
-      lc_fwd(G2, v);  // row r of A2 K times R2^{-T}: solve R2 y = (A2 K)_r'
+      lc_fwd(G2, r2, v);  // row r of A2 K times R2^{-T}: solve R2 y = (A2 K)_r'
 #pragma unroll
       for (int j = 0; j < kLD; ++j) AN[r][j] = v[j];
     }
