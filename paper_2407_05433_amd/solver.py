@@ -125,7 +125,8 @@ class Plan:
         return np.frombuffer(out, dtype=np.int32)[:self.batch].copy()
 
     def backward_error(self, ws: torch.Tensor) -> np.ndarray:
-        """Componentwise KKT backward error of each instance after the first solve (synchronises)."""
+        """Componentwise KKT backward error of each instance at the point the last solve returned (0 with
+        refine = 0; synchronises)."""
         out = (C.c_double * max(1, self.batch))()
         wptr, _ = _aligned_ws(ws)
         check(lib().eclqr_plan_backward_error(self._h, C.c_void_p(wptr), out), "eclqr_plan_backward_error")
