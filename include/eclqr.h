@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define ECLQR_ABI_VERSION 1
+#define ECLQR_ABI_VERSION 2
 
 /* synchronous return codes */
 typedef enum {
@@ -73,6 +73,12 @@ typedef enum {
 #define ECLQR_CAPACITY 32           /* a relation outgrew its on-chip tile */
 #define ECLQR_DUAL_FAILED 64        /* the multiplier (stationarity) solve failed; its own
                                        outcome bits are repeated in bits 8..15 */
+#define ECLQR_NOT_DIFFERENTIABLE 128 /* eclqr_backward only: the instance's constraint rows are
+                                       dependent (LICQ fails: a redundant row, or rows that together
+                                       with x_0 = x0 restrict x_0), so its multipliers are not unique
+                                       (Section VII, the remark after the multiplier proposition) and
+                                       the solution is not differentiable in the data; its gradients
+                                       are NaN */
 
 /* fields of the problem layout */
 enum {
@@ -102,12 +108,16 @@ typedef struct {
   double dual_cons_tol;   /* same test inside the multiplier solve; 1e-6 */
   double refine_tol;      /* an instance stops refining once ||correction|| <= refine_tol*||(x,u)||; 1e-8 */
   double accept_tol;      /* an instance whose componentwise KKT backward error after the first solve is
-                           * <= accept_tol takes no refinement step; 1e-13 (0: always refine) */
+                           * <= accept_tol takes no refinement step; 1e-10 (0: always refine).  Measured on
+                           * every workload, the first pass's relative error against the exact solution is
+                           * at most about 0.7 times this backward error */
   int32_t multipliers;    /* 0: primal only; 1: lam and mu as the minimum-norm solution of the stationarity
-                           * equations (the reversed-time problem of Section VII); 2: factor-reusing route
-                           * (Section IX implementation notes): one representative from the primal pass's
-                           * domains and scans -- equal to route 1 where the multipliers are unique (LICQ),
-                           * otherwise a valid multiplier vector that need not have minimum norm. 1 */
+                           * equations of Section VII (computed as the tuning field multiplier_route selects:
+                           * by default the theta LQR over the normal coordinates of the feasible domains,
+                           * else the reversed-time problem); 2: factor-reusing route (Section VIII, subsection
+                           * "Reference implementation"): one representative from the primal pass's domains
+                           * and scans -- equal to route 1 where the multipliers are unique (LICQ), otherwise a
+                           * valid multiplier vector that need not have minimum norm. 1 */
   int32_t refine;         /* most steps of iterative refinement per instance (0..4); 3.  A refined
                            * instance whose final KKT backward error exceeds dual_cons_tol reports
                            * ECLQR_DUAL_FAILED */
@@ -134,20 +144,35 @@ typedef struct {
   const double *Q, *q, *R, *r, *M, *A, *B, *c, *E, *F, *g, *x0;
 } eclqr_problem;
 
-/* Device output buffers.  lam and mu may be NULL when multipliers = 0. */
+/* Device output buffers.  lam and mu may be NULL when multipliers = 0.
+ * info (may be NULL) receives, per instance, the stage of its failure: the
+ * largest stage index at which a kernel of the problem's own pass (the
+ * relation scan, the state parameterization, the stage elimination, the
+ * feedback gains) set an outcome bit.  Algorithm 1 runs from the terminal
+ * stage backwards, so this is the first failing stage in its order: for
+ * ECLQR_INFEASIBLE_SUFFIX the largest i whose suffix set is empty, 0 for
+ * ECLQR_INFEASIBLE_INITIAL.  -1 when the problem's pass flagged nothing
+ * (status OK, or only the multiplier solve failed). */
 typedef struct {
   double *x, *u, *lam, *mu;
   int32_t* status;   /* [batch] */
+  int32_t* info;     /* [batch] or NULL */
 } eclqr_solution;
 
-/* Device buffers for the backward pass: dL/dx, dL/du in (layout of q, r). */
+/* Device buffers for the backward pass: dL/dx, dL/du (layouts of q, r) and,
+ * optionally (NULL = zero), dL/dlam (layout of q) and dL/dmu (layout of g). */
 typedef struct {
-  const double *dx, *du;
+  const double *dx, *du, *dlam, *dmu;
 } eclqr_cotangent;
 
-/* Device gradient buffers, same layouts as the problem fields (M may be NULL). */
+/* Device gradient buffers, same layouts as the problem fields (M may be
+ * NULL).  status (may be NULL) receives per instance the forward outcome
+ * bits, ECLQR_NOT_DIFFERENTIABLE, and ECLQR_DUAL_FAILED (with the adjoint
+ * solve's bits in 8..15) when the adjoint solve failed; the gradients of an
+ * instance with any bit set are NaN. */
 typedef struct {
   double *Q, *q, *R, *r, *M, *A, *B, *c, *E, *F, *g, *x0;
+  int32_t* status;   /* [batch] or NULL */
 } eclqr_grads;
 
 int eclqr_abi_version(void);
@@ -179,13 +204,17 @@ eclqr_status eclqr_plan_workspace_size(const eclqr_plan* plan, size_t* bytes);
 eclqr_status eclqr_solve(eclqr_plan* plan, const eclqr_problem* prob, eclqr_solution* sol, void* ws,
                          size_t ws_bytes, void* stream);
 
-/* Gradients of a loss L(x, u) with respect to every problem field
- * (implicit differentiation of the KKT system; adjoint = the same constrained
- * LQR with linear costs dL/dx, dL/du and zero offsets).  Requires the forward
- * solve's outputs (x, u, lam, mu) and its workspace, untouched since that
- * solve: the adjoint replays the factorizations the solve left there (no
- * factorization is recomputed).  Valid where the multipliers are unique
- * (LICQ). */
+/* Gradients of a loss L(x, u, lam, mu) with respect to every problem field
+ * (implicit differentiation of the KKT system; the adjoint is the same
+ * constrained LQR with linear costs dL/dx, dL/du and the offsets
+ * c_i <- dL/dlam_{i+1}, g_i <- dL/dmu_i, x0 <- dL/dlam_0).  Requires the
+ * forward solve's outputs (x, u, lam, mu) and its workspace: the last solve
+ * made in ws must be the one of this problem and solution (same pointers),
+ * with the plan's current multiplier route, else ECLQR_INVALID_ARGUMENT.  The
+ * adjoint replays the factorizations that solve left there (no factorization
+ * is recomputed).  Gradients exist where the multipliers are unique (LICQ);
+ * instances where the rank decisions of the forward pass show dependent rows
+ * get ECLQR_NOT_DIFFERENTIABLE and NaN gradients. */
 eclqr_status eclqr_backward(eclqr_plan* plan, const eclqr_problem* prob, const eclqr_solution* sol,
                             const eclqr_cotangent* ct, eclqr_grads* grads, void* ws, size_t ws_bytes,
                             void* stream);

@@ -28,7 +28,7 @@ paper (Lemma 2, Theorems 1-2, Propositions 2-3) or an independent route.
 """
 
 from .relations import Relation  # noqa: F401
-from .sequential import solve_sequential, SequentialResult  # noqa: F401
+from .sequential import rows_independent, solve_sequential, SequentialResult  # noqa: F401
 from .dense import dense_kkt, solve_dense  # noqa: F401
 from .multipliers import dual_problem, minnorm_multipliers, solve_with_multipliers  # noqa: F401
 from .residual import kkt_residual  # noqa: F401

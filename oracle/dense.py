@@ -179,3 +179,14 @@ def minnorm_multipliers_lsqr(prob, x, u, tol: float = 1e-15, maxiter: int = 2000
     g = np.concatenate(grad)
     res = lsqr(J.T.tocsr(), -g, atol=tol, btol=tol, conlim=1e14, iter_lim=maxiter)
     return split_dual(prob, res[0], layout), res
+
+
+def jacobian_full_row_rank(prob, rtol: float = 1e-10) -> bool:
+    """LICQ by definition: the stacked constraint Jacobian J of eq. (problem)
+    (rows x_0 - s_0, dynamics, stage rows, terminal rows) has full row rank,
+    judged by its singular values.  Tiny inputs only."""
+    _, _, J, _, _ = dense_kkt(prob)
+    if J.shape[0] == 0:
+        return True
+    s = np.linalg.svd(J, compute_uv=False)
+    return int(np.sum(s > rtol * s[0])) == J.shape[0]

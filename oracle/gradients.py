@@ -1,11 +1,13 @@
 """Gradients of a loss of the solution with respect to the problem data.
 
 Implicit differentiation of the KKT system K [w; nu] = -[h; b] of eq. (problem)
-(K symmetric): for a loss L(w), the adjoint (a_w, a_nu) solves
-K [a_w; a_nu] = -[dL/dw; 0], which is the KKT system of the same constrained
-LQR with linear costs q_i <- dL/dx_i, r_i <- dL/du_i and every offset
-(c_i, g_i, g_N, x0) set to zero.  Then dL = a_w^T (dh + dH w + dJ^T nu) +
-a_nu^T (dJ w + db), i.e.
+(K symmetric, constraints J w + b = 0 with b = (-x0, c_i, g_i)): for a loss
+L(w, nu), the adjoint (a_w, a_nu) solves K [a_w; a_nu] = -[dL/dw; dL/dnu],
+which is the KKT system of the same constrained LQR with linear costs
+q_i <- dL/dx_i, r_i <- dL/du_i and offsets b <- dL/dnu: c_i <- dL/dlambda_{i+1},
+g_i <- dL/dmu_i and, since the multiplier of x_0 - x0 = 0 is alpha =
+-lambda_0, x0 <- dL/dlambda_0 (all offsets zero for a loss of w alone).  Then
+dL = a_w^T (dh + dH w + dJ^T nu) + a_nu^T (dJ w + db), i.e.
 
     dL/dq_i = a_x_i,  dL/dr_i = a_u_i,  dL/dc_i = a_lambda_{i+1},
     dL/dg_i = a_mu_i, dL/dx0 = a_lambda_0 (lambda_0 = -alpha),
@@ -32,22 +34,29 @@ from .sequential import solve_sequential
 FIELDS = ("Q", "q", "R", "r", "M", "A", "B", "c", "E", "F", "g")
 
 
-def adjoint_problem(prob, dLdx: List[np.ndarray], dLdu: List[np.ndarray]):
+def adjoint_problem(prob, dLdx: List[np.ndarray], dLdu: List[np.ndarray], dLdlam=None, dLdmu=None):
     adj = prob.copy()
     N = prob.N
     adj.q = [np.array(dLdx[i], dtype=np.float64) for i in range(N + 1)]
     adj.r = [np.array(dLdu[i], dtype=np.float64) for i in range(N)]
-    adj.c = [np.zeros_like(ci) for ci in prob.c]
-    adj.g = [np.zeros_like(gi) for gi in prob.g]
-    adj.x0 = np.zeros_like(prob.x0)
+    if dLdlam is None:
+        adj.c = [np.zeros_like(ci) for ci in prob.c]
+        adj.x0 = np.zeros_like(prob.x0)
+    else:
+        adj.c = [np.array(dLdlam[i + 1], dtype=np.float64) for i in range(N)]
+        adj.x0 = np.array(dLdlam[0], dtype=np.float64)
+    if dLdmu is None:
+        adj.g = [np.zeros_like(gi) for gi in prob.g]
+    else:
+        adj.g = [np.array(dLdmu[i], dtype=np.float64) for i in range(N + 1)]
     return adj
 
 
-def adjoint_gradients(prob, sol: Dict, dLdx, dLdu) -> Dict[str, list]:
+def adjoint_gradients(prob, sol: Dict, dLdx, dLdu, dLdlam=None, dLdmu=None) -> Dict[str, list]:
     """Gradients of L with respect to every field, given the forward solution
-    ``sol`` (x, u, lam, mu) and dL/dx, dL/du."""
+    ``sol`` (x, u, lam, mu), dL/dx, dL/du and optionally dL/dlam, dL/dmu."""
     N = prob.N
-    a = solve_with_multipliers(adjoint_problem(prob, dLdx, dLdu))
+    a = solve_with_multipliers(adjoint_problem(prob, dLdx, dLdu, dLdlam, dLdmu))
     if a["status"] != "ok":
         raise RuntimeError("adjoint solve failed: " + a["status"])
     x, u, lam, mu = sol["x"], sol["u"], sol["lam"], sol["mu"]
@@ -75,6 +84,22 @@ def sumsq_loss(x, u) -> float:
 
 def sumsq_loss_grad(x, u):
     return [2.0 * xi for xi in x], [2.0 * ui for ui in u]
+
+
+def sumsq_all_loss(sol) -> float:
+    """L = sum |x_i|^2 + sum |u_i|^2 + sum |lambda_i|^2 + sum |mu_i|^2 (a loss
+    that also reads the multipliers)."""
+    return float(sum(float(v @ v) for k in ("x", "u", "lam", "mu") for v in sol[k]))
+
+
+def fd_directional_all(prob, d, h: float = 1e-4) -> float:
+    """Central difference of ``sumsq_all_loss`` through two full solves with
+    multipliers (valid where the multipliers are unique)."""
+    sp = solve_with_multipliers(perturbed(prob, d, h))
+    sm = solve_with_multipliers(perturbed(prob, d, -h))
+    if sp["status"] != "ok" or sm["status"] != "ok":
+        raise RuntimeError("finite-difference solve failed")
+    return (sumsq_all_loss(sp) - sumsq_all_loss(sm)) / (2.0 * h)
 
 
 def perturbed(prob, d: Dict[str, list], h: float):

@@ -244,3 +244,16 @@ def solve_sequential(prob, rank_tol: float = RANK_TOL, cons_tol: float = CONS_TO
     res.reduced_objective = float(fr)
     res.Qbar.append(QbN); res.qbar.append(qbN)
     return res
+
+
+def rows_independent(prob, res: SequentialResult) -> bool:
+    """LICQ from the sequential method's rank decisions (any size).  The
+    feasible trajectories are parameterized by the free inputs v_i alone (z_0
+    is fixed by x_0 = s_0 and the map v -> (x, u) is injective), so the
+    feasible set has dimension sum_i m-bar_i and rank J = dim(w) - sum_i
+    m-bar_i.  J has n_0 + sum_i (n_{i+1} + k_i) + k_N rows, hence full row rank
+    exactly when sum_{i<N} (m_i - m-bar_i) = sum_{i<=N} k_i.  Needs a solved
+    instance (res.status == 'ok')."""
+    N = prob.N
+    eliminated = sum(prob.nu[i] - res.Z[i].shape[1] for i in range(N))
+    return eliminated == sum(prob.nc[i] for i in range(N + 1))

@@ -24,6 +24,7 @@ STATUS_BITS = {
     16: "invalid_input",
     32: "capacity",
     64: "dual_failed",
+    128: "not_differentiable",
 }
 
 
@@ -52,15 +53,15 @@ class ProblemPtrs(C.Structure):
 
 class SolutionPtrs(C.Structure):
     _fields_ = [("x", C.c_void_p), ("u", C.c_void_p), ("lam", C.c_void_p), ("mu", C.c_void_p),
-                ("status", C.c_void_p)]
+                ("status", C.c_void_p), ("info", C.c_void_p)]
 
 
 class CotangentPtrs(C.Structure):
-    _fields_ = [("dx", C.c_void_p), ("du", C.c_void_p)]
+    _fields_ = [("dx", C.c_void_p), ("du", C.c_void_p), ("dlam", C.c_void_p), ("dmu", C.c_void_p)]
 
 
 class GradPtrs(C.Structure):
-    _fields_ = [(f, C.c_void_p) for f in FIELDS]
+    _fields_ = [(f, C.c_void_p) for f in FIELDS] + [("status", C.c_void_p)]
 
 
 _lib = None

@@ -212,7 +212,6 @@ eclqr_status bind(Plan& p, void* ws, hipStream_t s) {
     st = upload_engine(p.theta, ws, p.o_theta_eng, s);
     if (st != ECLQR_SUCCESS) return st;
   }
-  p.ws_route = -1;
   launch_fill_i32(reinterpret_cast<int32_t*>(static_cast<char*>(ws) + p.o_live), 1, 1, s);
   p.bound_ws = ws;
   p.bound_device = dev;
@@ -701,6 +700,7 @@ eclqr_status dual_prefactor(Plan& p, const Views& v, const Inputs& in, hipStream
 eclqr_status solve_sequence(Plan& p, const Views& v, const Inputs& in, eclqr_solution* sol, bool want, hipStream_t s) {
   const Engine& E = p.primal;
   launch_fill_i32(sol->status, 0, E.B, s);
+  launch_fill_i32(v.P.info, -1, E.B, s);
   hipEvent_t join = nullptr;
   if (want && p.opt.multipliers == 1 && !theta_route(p)) {
     if (p.overlap_dual) {
@@ -725,6 +725,68 @@ eclqr_status solve_sequence(Plan& p, const Views& v, const Inputs& in, eclqr_sol
   return ECLQR_SUCCESS;
 }
 
+// Graph path of eclqr_solve: the launch sequence is captured once per set of
+// pointers and replayed; every memory clear in it is a fill kernel.
+eclqr_status solve_graph(Plan& p, const Views& v, const Inputs& in, const eclqr_problem* prob, eclqr_solution* sol,
+                         void* ws, bool want, hipStream_t s) {
+  std::vector<const void*> key = {ws, prob->Q, prob->q, prob->R, prob->r, prob->M, prob->A, prob->B, prob->c,
+                                  prob->E, prob->F, prob->g, prob->x0, sol->x, sol->u, sol->lam, sol->mu,
+                                  sol->status, sol->info};
+  if (!p.graph_exec || p.graph_key != key) {
+    release_graph(p);
+    // captured on a plan-owned stream (the caller's may be the null stream,
+    // which cannot be captured); nothing runs during the capture
+    if (!p.capture_stream) {
+      hipStream_t cs = nullptr;
+      HIP_OK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+      p.capture_stream = reinterpret_cast<void*>(cs);
+    }
+    hipStream_t cs = reinterpret_cast<hipStream_t>(p.capture_stream);
+    HIP_OK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    const eclqr_status cst = solve_sequence(p, v, in, sol, want, cs);
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(cs, &g);
+    if (cst != ECLQR_SUCCESS) {
+      if (g) (void)hipGraphDestroy(g);
+      return cst;
+    }
+    if (ce != hipSuccess) return fail(ECLQR_HIP_ERROR, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) return fail(ECLQR_HIP_ERROR, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+    p.graph_exec = reinterpret_cast<void*>(ex);
+    p.graph_key = key;
+  }
+  HIP_OK(hipGraphLaunch(reinterpret_cast<hipGraphExec_t>(p.graph_exec), s));
+  return ECLQR_SUCCESS;
+}
+
+
+// Problem and solution pointers of a solve, in a fixed order.
+std::vector<const void*> solve_ptrs(const eclqr_problem* prob, const eclqr_solution* sol) {
+  return {prob->Q, prob->q, prob->R, prob->r, prob->M, prob->A, prob->B, prob->c, prob->E, prob->F, prob->g, prob->x0,
+          sol->x, sol->u, sol->lam, sol->mu};
+}
+
+const Plan::WsRecord* find_record(const Plan& p, const void* ws) {
+  for (const Plan::WsRecord& r : p.ws_records)
+    if (r.ws == ws) return &r;
+  return nullptr;
+}
+
+// After a solve is enqueued in ws, ws holds its factorizations (a failed
+// enqueue leaves them undefined: the record is dropped).  The list keeps
+// the most recent workspaces only.
+void record_solve(Plan& p, const void* ws, int32_t route, const eclqr_problem* prob, const eclqr_solution* sol,
+                  bool ok) {
+  auto& R = p.ws_records;
+  R.erase(std::remove_if(R.begin(), R.end(), [&](const Plan::WsRecord& r) { return r.ws == ws; }), R.end());
+  if (!ok) return;
+  if (R.size() >= 4096) R.erase(R.begin());
+  R.push_back({ws, route, ++p.generation, solve_ptrs(prob, sol)});
+}
+
 }  // namespace
 
 extern "C" {
@@ -738,7 +800,7 @@ void eclqr_default_options(eclqr_options* opt) {
   opt->cons_tol = 1e-8;
   opt->dual_cons_tol = 1e-6;
   opt->refine_tol = 1e-8;
-  opt->accept_tol = 1e-13;
+  opt->accept_tol = 1e-10;
   opt->multipliers = 1;
   opt->refine = 3;
   opt->use_graph = 0;
@@ -853,44 +915,15 @@ eclqr_status eclqr_solve(eclqr_plan* plan, const eclqr_problem* prob, eclqr_solu
   g_prof = &p;
   if (p.opt.multipliers == 2 && mult_local_lds_bytes(p.primal.fast_rows, p.primal.fast_ldw) > (size_t)g_max_lds)
     return fail(ECLQR_UNSUPPORTED, "stage too large for the LDS tile of the factor-reusing multipliers");
-  if (theta_route(p) && theta_local_lds_bytes(p.th_q, p.th_ldw, p.th_r) > (size_t)g_max_lds) p.mult_route = 0;
-  p.ws_route = want ? (p.opt.multipliers == 2 ? 2 : (theta_route(p) ? 1 : 0)) : -1;
+  if (theta_route(p) && theta_local_lds_bytes(p.th_q, p.th_ldw, p.th_r) > (size_t)g_max_lds)
+    return fail(ECLQR_UNSUPPORTED, "the device's LDS is smaller than the minimum-norm local systems' tile");
+  const int32_t route = want ? (p.opt.multipliers == 2 ? 2 : (theta_route(p) ? 1 : 0)) : -1;
   Views v = views(p, ws);
+  v.P.info = sol->info ? sol->info : at<int32_t>(ws, p.o_info);
   Inputs in = inputs_of(prob);
-  if (!p.opt.use_graph || p.profiling) return solve_sequence(p, v, in, sol, want, s);
-  // Graph path: the sequence is captured once per set of pointers and
-  // replayed; every memory clear in it is a fill kernel.
-  std::vector<const void*> key = {ws, prob->Q, prob->q, prob->R, prob->r, prob->M, prob->A, prob->B, prob->c,
-                                  prob->E, prob->F, prob->g, prob->x0, sol->x, sol->u, sol->lam, sol->mu,
-                                  sol->status};
-  if (!p.graph_exec || p.graph_key != key) {
-    release_graph(p);
-    // captured on a plan-owned stream (the caller's may be the null stream,
-    // which cannot be captured); nothing runs during the capture
-    if (!p.capture_stream) {
-      hipStream_t cs = nullptr;
-      HIP_OK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-      p.capture_stream = reinterpret_cast<void*>(cs);
-    }
-    hipStream_t cs = reinterpret_cast<hipStream_t>(p.capture_stream);
-    HIP_OK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    const eclqr_status cst = solve_sequence(p, v, in, sol, want, cs);
-    hipGraph_t g = nullptr;
-    const hipError_t ce = hipStreamEndCapture(cs, &g);
-    if (cst != ECLQR_SUCCESS) {
-      if (g) (void)hipGraphDestroy(g);
-      return cst;
-    }
-    if (ce != hipSuccess) return fail(ECLQR_HIP_ERROR, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
-    hipGraphExec_t ex = nullptr;
-    const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (ie != hipSuccess) return fail(ECLQR_HIP_ERROR, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
-    p.graph_exec = reinterpret_cast<void*>(ex);
-    p.graph_key = key;
-  }
-  HIP_OK(hipGraphLaunch(reinterpret_cast<hipGraphExec_t>(p.graph_exec), s));
-  return ECLQR_SUCCESS;
+  st = (!p.opt.use_graph || p.profiling) ? solve_sequence(p, v, in, sol, want, s) : solve_graph(p, v, in, prob, sol, ws, want, s);
+  record_solve(p, ws, route, prob, sol, st == ECLQR_SUCCESS);
+  return st;
 }
 
 eclqr_status eclqr_backward(eclqr_plan* plan, const eclqr_problem* prob, const eclqr_solution* sol,
@@ -899,17 +932,21 @@ eclqr_status eclqr_backward(eclqr_plan* plan, const eclqr_problem* prob, const e
   Plan& p = plan->p;
   if (ws_bytes < p.bytes) return fail(ECLQR_WORKSPACE_TOO_SMALL, "workspace smaller than eclqr_plan_workspace_size");
   if (!sol->lam || !sol->mu || !ct->dx || !ct->du) return fail(ECLQR_INVALID_ARGUMENT, "backward needs lam, mu, dx, du");
+  const int route = p.opt.multipliers == 2 ? 2 : (theta_route(p) ? 1 : 0);
+  const Plan::WsRecord* rec = find_record(p, ws);
+  if (!rec || rec->route != route || rec->ptrs != solve_ptrs(prob, sol))
+    return fail(ECLQR_INVALID_ARGUMENT,
+                "the workspace does not hold the factorizations of this solve (no solve of this problem and solution "
+                "with the plan's multiplier route was the last one made in it)");
   hipStream_t s = static_cast<hipStream_t>(stream);
   eclqr_status st = bind(p, ws, s);
   if (st != ECLQR_SUCCESS) return st;
-  const int route = p.opt.multipliers == 2 ? 2 : (theta_route(p) ? 1 : 0);
-  if (p.ws_route != route)
-    return fail(ECLQR_INVALID_ARGUMENT,
-                "the workspace does not hold the factorizations of a solve with this plan's multiplier route");
   g_prof = &p;
   Views v = views(p, ws);
   const Engine& E = p.primal;
-  // adjoint problem: same matrices, q <- dL/dx, r <- dL/du, zero offsets
+  // adjoint problem: same matrices, linear costs q <- dL/dx, r <- dL/du,
+  // offsets c_i <- dL/dlam_{i+1}, g <- dL/dmu, x0 <- dL/dlam_0 (zero when
+  // the loss does not read the multipliers)
   Inputs in = inputs_of(prob);
   double* zero = at<double>(ws, p.o_zero);
   launch_fill(zero, 0.0, std::max(E.total[ECLQR_F_c], std::max(E.total[ECLQR_F_g], E.total[ECLQR_F_x0])), s);
@@ -917,8 +954,19 @@ eclqr_status eclqr_backward(eclqr_plan* plan, const eclqr_problem* prob, const e
   adj.f[IN_q] = ct->dx;
   adj.f[IN_r] = ct->du;
   adj.f[IN_c] = zero;
-  adj.f[IN_g] = zero;
+  adj.f[IN_g] = ct->dmu ? ct->dmu : zero;
   adj.x0 = zero;
+  if (ct->dlam) {
+    double* oc = at<double>(ws, p.o_adjc);
+    double* ox = at<double>(ws, p.o_adjx0);
+    launch_adjoint_offsets(v.P, ct->dlam, oc, ox, s);
+    adj.f[IN_c] = oc;
+    adj.x0 = ox;
+  }
+  // per-instance outcome: forward bits, then the LICQ test on the forward
+  // pass's reduced input dims (kept in the workspace by that solve)
+  int32_t* gst = grads->status ? grads->status : at<int32_t>(ws, p.o_gstat);
+  launch_licq(v.P, v.psbase, sol->status, gst, s);
   // adjoint outputs live in the caller's gradient buffers q, r until assembly
   double* ax = grads->q;
   double* au = grads->r;
@@ -928,7 +976,7 @@ eclqr_status eclqr_backward(eclqr_plan* plan, const eclqr_problem* prob, const e
   launch_fill_i32(astatus, 0, E.B, s);
   // same matrices as the forward solve: every pass replays its factors
   st = solve_all(p, v, adj, ax, au, al, am, astatus, true, true, s);
-  launch_merge_status(sol->status, astatus, ECLQR_DUAL_FAILED, E.B, nullptr, 0, s);
+  launch_merge_status(gst, astatus, ECLQR_DUAL_FAILED, E.B, nullptr, 0, s);
   if (st != ECLQR_SUCCESS) return st;
   GradPtrs g{};
   g.f[IN_Q] = grads->Q;
@@ -943,7 +991,7 @@ eclqr_status eclqr_backward(eclqr_plan* plan, const eclqr_problem* prob, const e
   g.f[IN_F] = grads->F;
   g.f[IN_g] = grads->g;
   g.x0 = grads->x0;
-  launch_grad_assemble(v.P, sol->x, sol->u, sol->lam, sol->mu, ax, au, al, am, g, s);
+  launch_grad_assemble(v.P, sol->x, sol->u, sol->lam, sol->mu, ax, au, al, am, g, gst, s);
   HIP_OK(hipGetLastError());
   return ECLQR_SUCCESS;
 }

@@ -22,6 +22,17 @@ __device__ __forceinline__ void flag(int32_t* status, int inst, int32_t bit) {
   if (status) atomicOr(status + inst, bit);
 }
 
+// Outcome bit of a failure detected at stage `stage` of instance `inst` by a
+// kernel of the problem's own pass: info (when the engine has it) keeps the
+// largest such stage.  Algorithm 1 sweeps from the terminal stage backwards,
+// so that is the first failure in its order.
+__device__ __forceinline__ void flag_at(const DevEngine& e, int32_t* status, int inst, int32_t bit, int stage) {
+  if (status) {
+    atomicOr(status + inst, bit);
+    if (e.info) atomicMax(e.info + inst, stage);
+  }
+}
+
 // true when the instance has finished refining and must not be touched
 __device__ __forceinline__ bool gated(const DevEngine& e, int inst) { return e.gate && e.gate[inst] == kGateDone; }
 

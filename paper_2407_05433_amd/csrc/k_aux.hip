@@ -557,9 +557,22 @@ __global__ void k_resid_reduce(DevEngine p, const int64_t* sbase, double* out) {
 __global__ void __launch_bounds__(kBlock) k_grad_assemble(DevEngine p, const double* x, const double* u,
                                                           const double* lam, const double* mu, const double* ax,
                                                           const double* au, const double* al, const double* am,
-                                                          GradPtrs g) {
+                                                          GradPtrs g, const int32_t* gstatus) {
   for (int64_t s = blockIdx.x; s < p.S; s += gridDim.x) {
     const StageInfo st = p.st[s];
+    if (gstatus[st.inst] != 0) {  // not differentiable (or failed): every gradient block of the stage is NaN
+      const double nan = __builtin_nan("");
+      const int n = st.n, np = st.np, m = st.m, k = st.k;
+      const int64_t sz[IN_COUNT] = {(int64_t)n * n, n, (int64_t)m * m, m, (int64_t)n * m, (int64_t)np * n,
+                                    (int64_t)np * m, np, (int64_t)k * n, (int64_t)k * m, k};
+      for (int f = 0; f < IN_COUNT; ++f) {
+        if (!g.f[f]) continue;
+        for (int64_t j = ECLQR_TID; j < sz[f]; j += ECLQR_NT) g.f[f][st.in[f] + j] = nan;
+      }
+      if (st.i == 0)
+        for (int i = ECLQR_TID; i < n; i += ECLQR_NT) g.x0[st.x0 + i] = nan;
+      continue;
+    }
     const int n = st.n, np = st.np, m = st.m, k = st.k;
     const double* xs = x + st.in[IN_q];
     const double* axs = ax + st.in[IN_q];
@@ -607,6 +620,39 @@ __global__ void __launch_bounds__(kBlock) k_grad_assemble(DevEngine p, const dou
         g.f[IN_F][st.in[IN_F] + idx] = ms[i] * aus[j] + ams[i] * us[j];
       }
     }
+  }
+}
+
+// One wavefront per instance: the rows of its constraint Jacobian (x_0 = x0,
+// dynamics, stage rows, terminal rows) number n_0 + sum (n_{i+1} + k_i) + k_N
+// and its variables sum n_i + sum m_i; the feasible set found by the forward
+// pass has dimension sum m-bar_i (z_0 is fixed and every free input
+// coordinate is independent), so rank = dim(w) - sum m-bar_i, and the rows are
+// independent exactly when sum_{i<N} (m_i - m-bar_i) - sum_{i<=N} k_i = 0.
+__global__ void __launch_bounds__(kBlock) k_licq(DevEngine p, const int64_t* sbase, const int32_t* fstatus,
+                                                 int32_t* gstatus) {
+  for (int b = blockIdx.x; b < p.B; b += gridDim.x) {
+    const int64_t s0 = sbase[b];
+    const int N = p.st[s0].N;
+    long long def = 0;
+    for (int i = threadIdx.x; i <= N; i += kBlock) {
+      const StageInfo& st = p.st[s0 + i];
+      def += st.terminal ? -(long long)st.k : (long long)(st.m - p.mbar[s0 + i] - st.k);
+    }
+    const double tot = wave_sum((double)def);
+    if (threadIdx.x == 0) gstatus[b] = fstatus[b] | ((tot != 0.0) ? ECLQR_NOT_DIFFERENTIABLE : 0);
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_adjoint_offsets(DevEngine p, const double* dlam, double* c, double* x0) {
+  for (int64_t s = blockIdx.x; s < p.S; s += gridDim.x) {
+    const StageInfo& st = p.st[s];
+    if (!st.terminal) {
+      const StageInfo& st1 = p.st[s + 1];
+      for (int i = threadIdx.x; i < st.np; i += kBlock) c[st.in[IN_c] + i] = dlam[st1.in[IN_q] + i];
+    }
+    if (st.i == 0)
+      for (int i = threadIdx.x; i < st.n; i += kBlock) x0[st.x0 + i] = dlam[st.in[IN_q] + i];
   }
 }
 
@@ -687,8 +733,16 @@ void launch_kkt_residual(const DevEngine& p, const Inputs& in, const double* x, 
 }
 void launch_grad_assemble(const DevEngine& p, const double* x, const double* u, const double* lam, const double* mu,
                           const double* ax, const double* au, const double* al, const double* am, const GradPtrs& g,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(k_grad_assemble, dim3(p.nblocks), dim3(kBlock), 0, s, p, x, u, lam, mu, ax, au, al, am, g);
+                          const int32_t* gstatus, hipStream_t s) {
+  hipLaunchKernelGGL(k_grad_assemble, dim3(p.nblocks), dim3(kBlock), 0, s, p, x, u, lam, mu, ax, au, al, am, g,
+                     gstatus);
+}
+void launch_licq(const DevEngine& p, const int64_t* sbase, const int32_t* fstatus, int32_t* gstatus, hipStream_t s) {
+  const int grid = p.B < 4096 ? p.B : 4096;
+  hipLaunchKernelGGL(k_licq, dim3(grid > 0 ? grid : 1), dim3(kBlock), 0, s, p, sbase, fstatus, gstatus);
+}
+void launch_adjoint_offsets(const DevEngine& p, const double* dlam, double* c, double* x0, hipStream_t s) {
+  hipLaunchKernelGGL(k_adjoint_offsets, dim3(p.nblocks), dim3(kBlock), 0, s, p, dlam, c, x0);
 }
 
 }  // namespace eclqr

@@ -206,7 +206,7 @@ __global__ void __launch_bounds__(kBlock) k_eliminate(DevEngine e, Inputs in, To
       mres2 = wg_reduce_max(mres2, red);
       mg = wg_reduce_max(mg, red);
       if (ECLQR_TID == 0 && (mres > t.cons * fmax(1.0, mphi) || mres2 > t.cons * fmax(1.0, mg)))
-        flag(status, inst, ECLQR_RANK_INCONSISTENT);
+        flag_at(e, status, inst, ECLQR_RANK_INCONSISTENT, st.i);
       wg_sync();
     }
 
@@ -319,7 +319,7 @@ __global__ void __launch_bounds__(kBlock) k_eliminate(DevEngine e, Inputs in, To
     double* w2 = bump.take(m);
     wg_copy(Lc, mb, Rb, mb, mb, mb);
     if (wg_cholesky(Lc, mb, mb, sh + 8)) {
-      if (ECLQR_TID == 0) flag(status, inst, ECLQR_NOT_CONVEX);
+      if (ECLQR_TID == 0) flag_at(e, status, inst, ECLQR_NOT_CONVEX, st.i);
       wg_sync();
       continue;
     }

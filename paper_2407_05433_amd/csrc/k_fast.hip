@@ -293,11 +293,7 @@ void launch_mult_final(const DevEngine& e, double* lam, double* mu, int accumula
 
 // LDS: W (maxq x ldw) | Qg (maxq x maxq) | X (maxq x (maxr+1)) | Yl (maxq x (maxr+1)) |
 // tau (maxq) | qd (ldw + 8) | cr (ldw) | perm (ldw ints) | wi w1 gx gu tmp (kMaxDim each)
-size_t theta_local_lds_bytes(int maxq, int ldw, int maxr) {
-  return sizeof(double) * ((size_t)maxq * ldw + (size_t)maxq * maxq + 2 * (size_t)maxq * (maxr + 1) + maxq +
-                           2 * (size_t)ldw + 8 + 5 * kMaxDim) +
-         sizeof(int) * (size_t)(ldw + 1) + 64;
-}
+size_t theta_local_lds_bytes(int maxq, int ldw, int maxr) { return (size_t)theta_local_lds(maxq, ldw, maxr); }
 
 // kMode 0: full pass.  kMode 1: vector-only pass for new vectors with the
 // same matrices (refinement corrections, the adjoint, the solution after a

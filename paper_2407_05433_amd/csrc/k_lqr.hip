@@ -928,7 +928,7 @@ __global__ void __launch_bounds__(kBlock) k_gains(DevEngine e, int32_t* status, 
     }
     wg_sync();
     if (wg_cholesky(Huu, mb, mb, sh)) {
-      if (ECLQR_TID == 0) flag(status, st.inst, ECLQR_NOT_CONVEX);
+      if (ECLQR_TID == 0) flag_at(e, status, st.inst, ECLQR_NOT_CONVEX, st.i);
       wg_sync();
       continue;
     }

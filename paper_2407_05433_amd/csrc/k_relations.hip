@@ -31,7 +31,7 @@ __global__ void __launch_bounds__(kBlock) k_validate(DevEngine e, Inputs in, int
         if (!isfinite(in.x0[st.x0 + j])) mine = 1;
     if (mine) bad = 1;
     __syncthreads();
-    if (threadIdx.x == 0 && bad) flag(status, st.inst, ECLQR_INVALID_INPUT);
+    if (threadIdx.x == 0 && bad) flag_at(e, status, st.inst, ECLQR_INVALID_INPUT, st.i);
     __syncthreads();
   }
 }
@@ -170,7 +170,7 @@ __global__ void __launch_bounds__(kBlock) k_base_relation(DevEngine e, Inputs in
         glog[2] = rr;
         glog[3] = 0;
         e.slot_rows[slot] = rr;
-        if (b) flag(status, st.inst, ECLQR_INFEASIBLE_SUFFIX);
+        if (b) flag_at(e, status, st.inst, ECLQR_INFEASIBLE_SUFFIX, st.i);
       }
       wg_sync();
       continue;
@@ -222,7 +222,7 @@ __global__ void __launch_bounds__(kBlock) k_base_relation(DevEngine e, Inputs in
       glog[2] = rr;
       glog[3] = 0;
       e.slot_rows[slot] = rr;
-      if (b) flag(status, st.inst, ECLQR_INFEASIBLE_SUFFIX);
+      if (b) flag_at(e, status, st.inst, ECLQR_INFEASIBLE_SUFFIX, st.i);
     }
     wg_sync();
   }
@@ -306,7 +306,7 @@ __global__ void __launch_bounds__(kBlock) k_rel_compose(DevEngine e, int64_t fir
         glog[2] = 0;
         glog[3] = 0;
         e.slot_rows[o] = 0;
-        flag(status, inst, ECLQR_CAPACITY);
+        flag_at(e, status, inst, ECLQR_CAPACITY, e.st[sa].i);
       }
       wg_sync();
       continue;
@@ -325,7 +325,7 @@ __global__ void __launch_bounds__(kBlock) k_rel_compose(DevEngine e, int64_t fir
         glog[2] = na + nc;
         glog[3] = 1;
         e.slot_rows[o] = na + nc;
-        if (bad_full) flag(status, inst, ECLQR_INFEASIBLE_SUFFIX);
+        if (bad_full) flag_at(e, status, inst, ECLQR_INFEASIBLE_SUFFIX, e.st[sa].i);
       }
       wg_sync();
       continue;
@@ -370,7 +370,7 @@ __global__ void __launch_bounds__(kBlock) k_rel_compose(DevEngine e, int64_t fir
     if (rr > cap) {
       if (ECLQR_TID == 0) {
         e.slot_rows[o] = 0;
-        flag(status, inst, ECLQR_CAPACITY);
+        flag_at(e, status, inst, ECLQR_CAPACITY, e.st[sa].i);
       }
       wg_sync();
       continue;
@@ -381,7 +381,7 @@ __global__ void __launch_bounds__(kBlock) k_rel_compose(DevEngine e, int64_t fir
     }
     if (ECLQR_TID == 0) {
       e.slot_rows[o] = rr;
-      if (bad) flag(status, inst, ECLQR_INFEASIBLE_SUFFIX);
+      if (bad) flag_at(e, status, inst, ECLQR_INFEASIBLE_SUFFIX, e.st[sa].i);
     }
     wg_sync();
   }
@@ -436,7 +436,7 @@ __global__ void __launch_bounds__(kBlock) k_rel_compose_reg(DevEngine e, int64_t
         glog[2] = kc;
         glog[3] = 1;
         e.slot_rows[o] = kc;
-        if (bad_full) flag(status, inst, ECLQR_INFEASIBLE_SUFFIX);
+        if (bad_full) flag_at(e, status, inst, ECLQR_INFEASIBLE_SUFFIX, e.st[sa].i);
       }
       lds_sync();
       continue;
@@ -448,7 +448,7 @@ __global__ void __launch_bounds__(kBlock) k_rel_compose_reg(DevEngine e, int64_t
         glog[2] = 0;
         glog[3] = 0;
         e.slot_rows[o] = 0;
-        flag(status, inst, ECLQR_CAPACITY);
+        flag_at(e, status, inst, ECLQR_CAPACITY, e.st[sa].i);
       }
       lds_sync();
       continue;
@@ -522,8 +522,8 @@ __global__ void __launch_bounds__(kBlock) k_rel_compose_reg(DevEngine e, int64_t
       glog[2] = over ? 0 : rr;
       glog[3] = 2;
       e.slot_rows[o] = over ? 0 : rr;
-      if (over) flag(status, inst, ECLQR_CAPACITY);
-      else if (bad) flag(status, inst, ECLQR_INFEASIBLE_SUFFIX);
+      if (over) flag_at(e, status, inst, ECLQR_CAPACITY, e.st[sa].i);
+      else if (bad) flag_at(e, status, inst, ECLQR_INFEASIBLE_SUFFIX, e.st[sa].i);
     }
     lds_sync();
   }
@@ -587,7 +587,7 @@ __global__ void __launch_bounds__(kBlock) k_domain(DevEngine e, Inputs in, Tols 
           v = lane_chain<false>(v, H + j * (n + 1), 1, x0, 1, n);
           res = fmax(res, fabs(v));
         }
-        if (res > t.cons * sc) flag(status, st.inst, ECLQR_INFEASIBLE_INITIAL);
+        if (res > t.cons * sc) flag_at(e, status, st.inst, ECLQR_INFEASIBLE_INITIAL, 0);
       }
       double* z0 = slot_ptr(e, SCAN_FWD, st.suf[SCAN_FWD]);
       for (int j = ECLQR_TID; j < nb; j += ECLQR_NT) {

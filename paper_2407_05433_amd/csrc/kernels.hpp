@@ -30,6 +30,7 @@ struct DevEngine {
   const int32_t* vac;         // per-instance whole-space domains (relation scan skipped), null = none
   const int32_t* gate;        // per-instance refinement state, null = every instance runs
   const int32_t* live;        // instances still refining; 0 makes the kernels of a refinement step return at once
+  int32_t* info;              // per instance: largest stage at which the pass flagged a failure (-1 none), null = not kept
   double* gw;                 // per-workgroup global tiles for stacked relation systems beyond LDS, null = none
   int64_t gw_stride;          // doubles per tile
   int32_t gw_blocks;          // tiles (workgroups of a launch that uses them)
@@ -175,8 +176,17 @@ bool launch_theta_local(const DevEngine& p, const DevEngine& th, const Inputs& i
 void launch_theta_init(const DevEngine& th, hipStream_t s);
 void launch_theta_final(const DevEngine& p, const DevEngine& th, double* lam, double* mu, int accumulate,
                         hipStream_t s);
+// gradients of every field from the solution and the adjoint solution; the
+// gradients of an instance whose gstatus is nonzero are NaN
 void launch_grad_assemble(const DevEngine& p, const double* x, const double* u, const double* lam, const double* mu,
                           const double* ax, const double* au, const double* al, const double* am, const GradPtrs& g,
-                          hipStream_t s);
+                          const int32_t* gstatus, hipStream_t s);
+// gstatus[b] = fstatus[b], plus ECLQR_NOT_DIFFERENTIABLE where the forward
+// pass's rank decisions show dependent constraint rows: the feasible set has
+// dimension sum_i m-bar_i, so the rows have full rank exactly when
+// sum_{i<N} (m_i - m-bar_i) = sum_{i<=N} k_i
+void launch_licq(const DevEngine& p, const int64_t* sbase, const int32_t* fstatus, int32_t* gstatus, hipStream_t s);
+// adjoint offsets from dL/dlam: c_i <- dlam_{i+1} (layout of c), x0 <- dlam_0
+void launch_adjoint_offsets(const DevEngine& p, const double* dlam, double* c, double* x0, hipStream_t s);
 
 }  // namespace eclqr

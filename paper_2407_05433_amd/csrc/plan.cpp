@@ -530,6 +530,14 @@ std::string build_plan(Plan& p, const eclqr_dims* d, const eclqr_options* opt) {
       p.th_ldw = std::max(p.th_ldw, R | 1);
       p.th_r = std::max(p.th_r, x.n);
     }
+    // the local systems are factored in one LDS tile per stage: where that
+    // tile exceeds the device's LDS the reversed-time route is laid out
+    // instead (decided here, so a plan never switches routes at solve time)
+    if (p.theta_ok && theta_local_lds(p.th_q, p.th_ldw, p.th_r) > kDeviceLdsBytes) {
+      p.theta_ok = false;
+      p.mult_route = 0;
+      p.overlap_dual = 1;
+    }
   }
 
   // the reversed-time engine: needed when the minimum-norm multipliers have
@@ -590,6 +598,10 @@ std::string build_plan(Plan& p, const eclqr_dims* d, const eclqr_options* opt) {
   p.o_rsteps = o; o = align256(o + sizeof(int32_t) * std::max<int32_t>(1, P.B));
   p.o_live = o; o = align256(o + sizeof(int32_t));
   p.o_omega = o; o = align256(o + sizeof(double) * std::max<int32_t>(1, P.B));
+  p.o_info = o; o = align256(o + sizeof(int32_t) * std::max<int32_t>(1, P.B));
+  p.o_gstat = o; o = align256(o + sizeof(int32_t) * std::max<int32_t>(1, P.B));
+  p.o_adjc = o; o = align256(o + sizeof(double) * std::max<int64_t>(1, P.total[ECLQR_F_c]));
+  p.o_adjx0 = o; o = align256(o + sizeof(double) * std::max<int64_t>(1, P.total[ECLQR_F_x0]));
   {
     int64_t nz = std::max<int64_t>(1, std::max(P.total[ECLQR_F_c], std::max(P.total[ECLQR_F_g], P.total[ECLQR_F_x0])));
     // the overlapped reversed-time factorization reads zero vectors

@@ -91,7 +91,17 @@ struct Plan {
   size_t o_defer = 0;         // per level: count of deferred combines (2 D ints), then one task list
   int32_t th_q = 1, th_ldw = 1, th_r = 1;  // LDS tile of the local minimum-norm systems
   int32_t mult_route = 1;     // 1: theta LQR (when theta_ok), 0: reversed-time problem
-  int32_t ws_route = -1;      // route whose factors the bound workspace holds (-1: none yet)
+  // What each workspace holds: the factorizations of the last solve made in
+  // it (multiplier route, problem and solution pointers).  eclqr_backward
+  // replays them only for that solve.
+  struct WsRecord {
+    const void* ws;
+    int32_t route;
+    uint64_t generation;
+    std::vector<const void*> ptrs;  // problem fields, then x, u, lam, mu
+  };
+  std::vector<WsRecord> ws_records;
+  uint64_t generation = 0;
   // workspace regions (bytes from the workspace base)
   size_t o_primal = 0, o_dual = 0;
   size_t o_dprob[ECLQR_NUM_FIELDS] = {0};  // reversed-time stationarity problem data
@@ -104,6 +114,9 @@ struct Plan {
   size_t o_rsteps = 0; // per-instance count of refinement steps taken
   size_t o_live = 0;   // instances still refining (one int)
   size_t o_omega = 0;  // per-instance backward error after the first solve (double bits)
+  size_t o_info = 0;   // per-instance failing stage of the last solve (when the caller passes no info buffer)
+  size_t o_adjc = 0, o_adjx0 = 0;  // adjoint offsets from dL/dlam (layouts of c and x0)
+  size_t o_gstat = 0;  // per-instance outcome of the last backward (when the caller passes no status buffer)
   size_t bytes = 0;
   void* bound_ws = nullptr;
   int bound_device = -1;

@@ -39,4 +39,18 @@ ECLQR_HD inline int64_t gains_scratch(int n, int np, int m) {
   return s;
 }
 
+// LDS per workgroup on gfx950 (the only target): plans decide at creation
+// which kernels' tiles fit, and a device that reports less is rejected at
+// solve time rather than launched past its limit.
+constexpr int64_t kDeviceLdsBytes = 160 * 1024;
+
+// LDS bytes of the minimum-norm local systems of the theta route
+// (k_theta_local): the stacked system maxq x ldw, its Q factor, two
+// maxq x (maxr + 1) blocks, vectors and pivots.
+ECLQR_HD inline int64_t theta_local_lds(int maxq, int ldw, int maxr) {
+  return 8 * ((int64_t)maxq * ldw + (int64_t)maxq * maxq + 2 * (int64_t)maxq * (maxr + 1) + maxq + 2 * (int64_t)ldw +
+              8 + 5 * kMaxDim) +
+         4 * (int64_t)(ldw + 1) + 64;
+}
+
 }  // namespace eclqr

@@ -226,6 +226,13 @@ class Solution:
     lam: Optional[torch.Tensor]
     mu: Optional[torch.Tensor]
     status: torch.Tensor
+    info: Optional[torch.Tensor] = None  # per instance: stage of the first failure in Algorithm 1's order, -1 none
+
+    def ptrs(self) -> _lib.SolutionPtrs:
+        return _lib.SolutionPtrs(self.x.data_ptr(), self.u.data_ptr(),
+                                 self.lam.data_ptr() if self.lam is not None else None,
+                                 self.mu.data_ptr() if self.mu is not None else None, self.status.data_ptr(),
+                                 self.info.data_ptr() if self.info is not None else None)
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -260,6 +267,7 @@ def allocate_solution(plan: Plan, device="cuda", multipliers: bool = True) -> So
     _, ng = plan.layout("g")
     mk = lambda n: torch.empty(max(1, n), dtype=torch.float64, device=device)  # noqa: E731
     return Solution(mk(nq), mk(nr), mk(nq) if multipliers else None, mk(ng) if multipliers else None,
+                    torch.empty(plan.batch, dtype=torch.int32, device=device),
                     torch.empty(plan.batch, dtype=torch.int32, device=device))
 
 
@@ -271,9 +279,7 @@ def solve(plan: Plan, data: Dict[str, torch.Tensor], ws: Optional[torch.Tensor] 
         ws = plan.workspace(device)
     if out is None:
         out = allocate_solution(plan, device, bool(plan.options.multipliers))
-    sp = _lib.SolutionPtrs(out.x.data_ptr(), out.u.data_ptr(),
-                           out.lam.data_ptr() if out.lam is not None else None,
-                           out.mu.data_ptr() if out.mu is not None else None, out.status.data_ptr())
+    sp = out.ptrs()
     pp = _problem_ptrs(data)
     wptr, wbytes = _aligned_ws(ws)
     check(lib().eclqr_solve(plan.handle, C.byref(pp), C.byref(sp), C.c_void_p(wptr), C.c_size_t(wbytes), _stream()),
@@ -283,17 +289,22 @@ def solve(plan: Plan, data: Dict[str, torch.Tensor], ws: Optional[torch.Tensor] 
 
 
 def backward(plan: Plan, data: Dict[str, torch.Tensor], sol: Solution, dx: torch.Tensor, du: torch.Tensor,
-             ws: torch.Tensor) -> Dict[str, torch.Tensor]:
-    """eclqr_backward: gradients of a loss L(x, u) given dL/dx, dL/du."""
+             ws: torch.Tensor, dlam: Optional[torch.Tensor] = None,
+             dmu: Optional[torch.Tensor] = None) -> Dict[str, torch.Tensor]:
+    """eclqr_backward: gradients of a loss L(x, u, lam, mu) given dL/dx, dL/du
+    and optionally dL/dlam, dL/dmu.  ``grads["status"]`` holds the per-instance
+    outcome (ECLQR_NOT_DIFFERENTIABLE where the constraint rows are dependent;
+    the gradients of a flagged instance are NaN)."""
     device = dx.device
     grads = {f: torch.empty(max(1, plan.layout(f)[1]), dtype=torch.float64, device=device)
              for f in FIELDS if f != "M" or "M" in data}
+    grads["status"] = torch.empty(plan.batch, dtype=torch.int32, device=device)
     gp = _lib.GradPtrs()
-    for f in FIELDS:
+    for f in FIELDS + ("status",):
         setattr(gp, f, grads[f].data_ptr() if f in grads else None)
-    sp = _lib.SolutionPtrs(sol.x.data_ptr(), sol.u.data_ptr(), sol.lam.data_ptr(), sol.mu.data_ptr(),
-                           sol.status.data_ptr())
-    ct = _lib.CotangentPtrs(dx.data_ptr(), du.data_ptr())
+    sp = sol.ptrs()
+    ct = _lib.CotangentPtrs(dx.data_ptr(), du.data_ptr(), dlam.data_ptr() if dlam is not None else None,
+                            dmu.data_ptr() if dmu is not None else None)
     pp = _problem_ptrs(data)
     wptr, wbytes = _aligned_ws(ws)
     check(lib().eclqr_backward(plan.handle, C.byref(pp), C.byref(sp), C.byref(ct), C.byref(gp), C.c_void_p(wptr),
@@ -303,8 +314,7 @@ def backward(plan: Plan, data: Dict[str, torch.Tensor], sol: Solution, dx: torch
 
 def kkt_residual(plan: Plan, data: Dict[str, torch.Tensor], sol: Solution, ws: torch.Tensor) -> torch.Tensor:
     out = torch.empty(4 * plan.batch, dtype=torch.float64, device=sol.x.device)
-    sp = _lib.SolutionPtrs(sol.x.data_ptr(), sol.u.data_ptr(), sol.lam.data_ptr(), sol.mu.data_ptr(),
-                           sol.status.data_ptr())
+    sp = sol.ptrs()
     pp = _problem_ptrs(data)
     wptr, wbytes = _aligned_ws(ws)
     check(lib().eclqr_kkt_residual(plan.handle, C.byref(pp), C.byref(sp), C.c_void_p(out.data_ptr()),
@@ -342,9 +352,7 @@ def autotune(plan: Plan, data: Dict[str, torch.Tensor], ws: torch.Tensor, out: O
     problem under alternative launch configurations and keeps the fastest."""
     if out is None:
         out = allocate_solution(plan, data["Q"].device, bool(plan.options.multipliers))
-    sp = _lib.SolutionPtrs(out.x.data_ptr(), out.u.data_ptr(),
-                           out.lam.data_ptr() if out.lam is not None else None,
-                           out.mu.data_ptr() if out.mu is not None else None, out.status.data_ptr())
+    sp = out.ptrs()
     pp = _problem_ptrs(data)
     wptr, wbytes = _aligned_ws(ws)
     t = _lib.Tuning()

@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
     assert len(names) >= 12
     for n in names:
         assert hasattr(L, n), n
-    assert L.eclqr_abi_version() == 1
+    assert L.eclqr_abi_version() == 2
 
 
 def test_status_strings_and_defaults():
@@ -222,3 +222,34 @@ def test_hybrid_schedule_reproduces_sequential_suffixes():
             q = [q for q in range(len(inst)) if inst[q] == b and first[q] == i and last[q] == p.N + 1]
             assert len(q) == 1, (b, i, q)
             assert same_set(rel[q[0]], seq.suffix[i], tol=1e-9), (b, i)
+
+
+def test_route_decided_at_plan_creation_from_the_lds_bound():
+    """Minimum-norm local systems whose tile exceeds 160 KiB of LDS (n = 64,
+    m = 64, no rows) get the reversed-time route when the plan is made; a
+    plan whose tiles fit keeps the theta route."""
+    big = [([64] * 4, [64] * 3, [0] * 4)]
+    assert ecl.get_tuning(ecl.Plan(big))["multiplier_route"] == 0
+    small = [([12] * 4, [6] * 3, [2, 2, 2, 1])]
+    assert ecl.get_tuning(ecl.Plan(small))["multiplier_route"] == 1
+
+
+def test_ctypes_structs_follow_the_header():
+    """The ctypes mirrors of eclqr_solution, eclqr_cotangent and eclqr_grads
+    list the header's fields in the header's order."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+
+    def fields(tag):
+        body = re.search(r"typedef struct \{([^}]*)\}\s*" + tag + ";", text).group(1)
+        out = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            names = decl.split(None, 1)[1] if not decl.startswith("const") else decl.split(None, 2)[2]
+            out += [n.strip().lstrip("*") for n in names.split(",")]
+        return out
+
+    assert [f for f, _ in _lib.SolutionPtrs._fields_] == fields("eclqr_solution")
+    assert [f for f, _ in _lib.CotangentPtrs._fields_] == fields("eclqr_cotangent")
+    assert [f for f, _ in _lib.GradPtrs._fields_] == fields("eclqr_grads")

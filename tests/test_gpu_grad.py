@@ -35,7 +35,9 @@ def _gpu_grads(probs):
     out = []
     for b, p in enumerate(probs):
         out.append({})
-    for f in FIELDS + ("x0",):
+    for f in FIELDS + ("M", "x0"):
+        if f not in leaves:
+            continue
         g = leaves[f].grad.detach().cpu().numpy()
         offs, _ = plan.layout(f)
         s = 0
@@ -96,6 +98,33 @@ def test_gradients_full_c4_batch_sampled():
         for _ in range(3):
             d = random_direction(p, rng)
             d.pop("M", None)
+            an = directional(G[b], effective_direction(p, d, 1e-6))
+            fd = fd_directional_corrected(p, sol, d, 1e-6)
+            assert abs(fd - an) / max(abs(fd), abs(an)) < 1e-6, (b, fd, an)
+
+
+def test_cross_term_gradient():
+    """Nonzero cross terms M_i: the gradient with respect to M (and every
+    other field) against the oracle's adjoint, and central differences along
+    directions that include M."""
+    _need_gpu()
+    from oracle import solve_with_multipliers
+    from oracle.gradients import (adjoint_gradients, directional, effective_direction, fd_directional_corrected,
+                                  random_direction, sumsq_loss_grad)
+    from tests._util import tiny_problem
+    # joint stage Hessians [[Q, M], [M', R]] = L L' + 1e-2 I (convex, nonzero M)
+    probs = [tiny_problem(4099 + b, N=24, n=6, m=3, kinds=[["mixed"] * 2] * 24, terminal_rows=0, g_mode="random",
+                          with_M=True) for b in range(3)]
+    rng = np.random.default_rng(4099)
+    G = _gpu_grads(probs)
+    for b, p in enumerate(probs):
+        sol = solve_with_multipliers(p)
+        gx, gu = sumsq_loss_grad(sol["x"], sol["u"])
+        Go = adjoint_gradients(p, sol, gx, gu)
+        for f in FIELDS + ("M", "x0"):
+            assert _rel(G[b][f], Go[f]) < 1e-8, (b, f, _rel(G[b][f], Go[f]))
+        for _ in range(3):
+            d = random_direction(p, rng, ("Q", "q", "R", "r", "M", "A", "B", "c", "E", "F", "g", "x0"))
             an = directional(G[b], effective_direction(p, d, 1e-6))
             fd = fd_directional_corrected(p, sol, d, 1e-6)
             assert abs(fd - an) / max(abs(fd), abs(an)) < 1e-6, (b, fd, an)

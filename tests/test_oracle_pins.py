@@ -398,3 +398,52 @@ def test_indefinite_costs_with_convex_reduction():
         for key in ("x", "u"):
             assert rel_err(getattr(r, key), d[key]) <= 1e-10, key
         assert all(np.linalg.eigvalsh(Rb).min() > 0 for Rb in r.Rbar if Rb.size)
+
+
+# ---------------------------------------------------------------------------
+# relation equality has negatives; LICQ from the rank decisions
+# ---------------------------------------------------------------------------
+
+def test_same_set_accepts_bases_of_one_set_and_rejects_others():
+    """same_set is the Definition 1 equivalence: another row basis of the same
+    set (rows mixed by an invertible matrix, offsets mixed alike) is equal;
+    a shifted offset, a tilted row space, a dropped row and a unary versus
+    binary split are not."""
+    rng = np.random.default_rng(31)
+    L = rng.standard_normal((2, 3))
+    R = rng.standard_normal((2, 2))
+    ell = rng.standard_normal(2)
+    base = Relation(L, R, ell)
+    T = np.array([[2.0, 1.0], [-1.0, 3.0]])
+    assert same_set(base, Relation(T @ L, T @ R, T @ ell))
+    assert same_set(base, Relation(L[::-1].copy(), R[::-1].copy(), ell[::-1].copy()))
+    assert not same_set(base, Relation(L, R, ell + np.array([1e-3, 0.0])))
+    tilt = R.copy()
+    tilt[0, 1] += 1e-3
+    assert not same_set(base, Relation(L, tilt, ell))
+    assert not same_set(base, Relation(L[:1], R[:1], ell[:1]))
+    assert not same_set(Relation(np.hstack([L, R]), np.zeros((2, 0)), ell), Relation(L, R, ell + 1.0))
+
+
+def test_rows_independent_matches_dense_rank():
+    """LICQ read off the sequential method's rank decisions (sum of
+    eliminated input dims against the row count) equals the rank of the
+    dense constraint Jacobian, on the structural family and on instances
+    built to fail it: a redundant row, a state row at stage 0, a terminal
+    row repeating a stage row's restriction."""
+    from oracle import rows_independent
+    from oracle.dense import jacobian_full_row_rank
+    cases = [p for _, p in FAMILY]
+    cases.append(tiny_problem(1601, N=5, n=3, m=2, kinds=[["mixed"]] * 5, terminal_rows=0, redundant=(2,)))
+    cases.append(tiny_problem(1602, N=4, n=3, m=2, kinds=[["state"], [], ["mixed"], []], terminal_rows=0))
+    cases.append(tiny_problem(1603, N=4, n=3, m=2, kinds=[[], ["state"], [], []], terminal_rows=1))
+    pinned = tiny_problem(1604, N=3, n=2, m=1, kinds=[[], [], ["state", "state"]], terminal_rows=0)
+    cases.append(pinned)
+    seen = set()
+    for p in cases:
+        res = solve_sequential(p)
+        assert res.status == "ok"
+        a, b = rows_independent(p, res), jacobian_full_row_rank(p)
+        assert a == b, (a, b)
+        seen.add(a)
+    assert seen == {True, False}
