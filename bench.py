@@ -1,20 +1,31 @@
 """Benchmark: stages/s of the full solve (primal + multipliers) on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload c1|c2|c3|c4|paper]
+    python bench.py [--steps K] [--warmup W] [--workload c3|c1|c2|c4|paper]
 
 A step is one solve of the whole hot path (feasible-domain scan, stage
-elimination, reduced-LQR scan, recovery, multipliers, and iterative
-refinement that each instance stops once its correction is below 1e-8 of its
-solution, at most 3 steps) of one batch of synthetic instances already resident in HBM.  Prints one JSON
-line; the per-kernel breakdown and the secondary workloads go to stderr and to
-the "secondary" object.
+elimination, reduced-LQR scan, recovery, multipliers, and the iterative
+refinement an instance takes when its backward error after the first pass
+exceeds 1e-10) of one batch of synthetic instances already resident in HBM.
+The default workload is the 512-instance batch solved in one call; beside it
+the same instances are solved one after another with single-instance plans
+(batched vs single), and the single instances (N=1024; N=8192 with n=32) and
+the 256-instance differentiable batch (forward, and forward + backward) are
+measured as secondaries.  Prints one JSON line; the per-kernel breakdowns go
+to stderr and to the "secondary" object.
+
+Roofline: the kernel class that takes the most time per solve, its
+algorithmic FP64 flops being the method's work: the kernels' nominal counts at
+the actual dims of every stage and of the tasks of the balanced up/down sweep
+(two combines per stage and scan, the O(N) scan of the paper's Section IV),
+whichever parenthesization ran; vector-only replays by the bytes of the
+factors they read.
 """
 
 from __future__ import annotations
 
 import os
 
-# the CPU baseline (the oracle) runs on one core
+# the oracle (CPU baseline) runs one instance per process, one thread each
 for _v in ("OPENBLAS_NUM_THREADS", "OMP_NUM_THREADS", "MKL_NUM_THREADS"):
     os.environ.setdefault(_v, "1")
 
@@ -31,6 +42,7 @@ if ROOT not in sys.path:
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CUs x 128 FP64 flop/clk x 2.4 GHz
 HBM_PEAK_GBS = 8000.0
+METRIC = "stages/s solved (primal+multipliers) batched vs single; fwd+bwd ms at 1e-9 acc"
 
 WORKLOADS = {
     "c0": "tiny: 1 instance, N=16, n=4, m=2, 1 mixed row/stage, 2 terminal rows",
@@ -69,19 +81,16 @@ def time_solves(ecl, torch, plan, data, ws, sol, steps, warmup):
     for _ in range(warmup):
         ecl.solve(plan, data, ws, sol)
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    e0.record()
     for _ in range(steps):
         ecl.solve(plan, data, ws, sol)
-    e1.record()
     torch.cuda.synchronize()
-    wall = (time.perf_counter() - t0) * 1e3 / steps
-    return wall, e0.elapsed_time(e1) / steps
+    return (time.perf_counter() - t0) * 1e3 / steps
 
 
 def kernel_profile(ecl, torch, plan, data, ws, sol, steps):
+    """{class: (ms per solve, launches per solve)} from HIP events around
+    every launch on the launch stream (eager launches)."""
     plan.set_profiling(True)
     plan.profile(reset=True)
     for _ in range(steps):
@@ -92,60 +101,110 @@ def kernel_profile(ecl, torch, plan, data, ws, sol, steps):
     return {k: (ms / steps, n / steps) for k, (ms, n) in prof.items()}
 
 
-def secondary_batched(ecl, torch, steps):
-    """The 512-instance batch solved in one call versus the same instances
-    solved one after another, each with its own single-instance plan."""
-    problems = make("c3")
-    stages = sum(p.N for p in problems)
-    plan = ecl.Plan.for_problems(problems)
+def method_work(ecl, torch, problems, data, multipliers=True):
+    """Flops per kernel class of the method's work: the same problem solved
+    once (untimed) by a plan with the balanced up/down sweep, its flop model
+    evaluated at that solve's dims, plus the bytes of the factor logs a
+    vector-only replay pass reads."""
+    from paper_2407_05433_amd import flops as flopmodel
+    plan = ecl.Plan.for_problems(problems, scan_schedule=1)
+    ws = plan.workspace()
+    sol = ecl.solve(plan, data, ws)
+    torch.cuda.synchronize()
+    work = flopmodel.solve_flops(plan, problems, ws, multipliers=multipliers)
+    del sol, ws
+    torch.cuda.empty_cache()
+    return work
+
+
+def replay_bytes(plan):
+    """Bytes of the factors one vector-only pass of the problem and of its
+    multiplier route reads (relation and value-function logs, stage arenas)."""
+    return float(sum(plan.footprint(w)["factor_bytes"] for w in (0, 2) if plan.has_engine(w)))
+
+
+def roofline(prof, work, replay_b, passes):
+    """The class with the most time per solve: achieved = algorithmic work
+    per solve / its time per solve (per launch: the same ratio)."""
+    dom = max((k for k in prof if prof[k][1] > 0), key=lambda k: prof[k][0])
+    ms, launches = prof[dom]
+    if dom == "replay":
+        achieved = replay_b * passes / (ms * 1e-3) / 1e9
+        return {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "bytes_per_solve": replay_b * passes, "ms_per_solve": ms,
+                "launches_per_solve": launches, "avg_launch_us": ms * 1e3 / max(launches, 1)}
+    achieved = work.get(dom, 0.0) / (ms * 1e-3) / 1e12
+    return {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "flops_per_solve": work.get(dom, 0.0), "ms_per_solve": ms,
+            "launches_per_solve": launches, "avg_launch_us": ms * 1e3 / max(launches, 1)}
+
+
+def measure(ecl, torch, workload, problems, steps, warmup, graph=1, autotune=1, scan_schedule=0):
+    """Autotuned solve of one workload: wall ms per solve (graph replay),
+    per-class profile, method-work roofline of the dominant class."""
+    plan = ecl.Plan.for_problems(problems, use_graph=graph, scan_schedule=scan_schedule)
     data = ecl.pack(plan, problems)
     ws = plan.workspace()
     sol = ecl.allocate_solution(plan)
-    batched_ms, _ = time_solves(ecl, torch, plan, data, ws, sol, steps, 1)
-    ok_batched = int((sol.status != 0).sum().item()) == 0
-    del ws
+    stages = sum(p.N for p in problems)
+    tuning = ecl.autotune(plan, data, ws, sol) if autotune else ecl.get_tuning(plan)
+    ms = time_solves(ecl, torch, plan, data, ws, sol, steps, warmup)
+    status_ok = int((sol.status != 0).sum().item()) == 0
+    prof = kernel_profile(ecl, torch, plan, data, ws, sol, max(2, min(steps, 5)))
+    rsteps = plan.refine_steps(ws)
+    # vector passes per solve: two per refinement step (the problem and its
+    # multiplier route; averaged over instances: a finished instance's tasks
+    # return at once), plus the multiplier route's pass at the primal point
+    # when its factorization was overlapped
+    passes = 2.0 * float(np.mean(rsteps)) + (1.0 if tuning.get("overlap_dual") else 0.0)
+    rb = replay_bytes(plan)
+    sched = scan_schedule_name(plan)
+    del ws, sol
+    torch.cuda.empty_cache()
+    work = method_work(ecl, torch, problems, data)
+    roof = roofline(prof, work, rb, passes)
+    res = {"workload": f"{workload}: {WORKLOADS[workload]}", "instances": len(problems), "stages": stages,
+           "ms_per_solve": ms, "stages_per_s": stages / (ms * 1e-3), "status_ok": status_ok,
+           "launch": tuning, "scan_schedule": sched,
+           "refine_steps_taken": {str(int(k)): int(v) for k, v in zip(*np.unique(rsteps, return_counts=True))},
+           "roofline": roof, "kernel_ms_per_solve": {k: v[0] for k, v in prof.items() if v[1]},
+           "launches_per_solve": {k: v[1] for k, v in prof.items() if v[1]},
+           "method_flops_per_solve": sum(work.values())}
+    log(f"[bench] {workload}: {ms:.3f} ms/solve, {res['stages_per_s']:.0f} stages/s, schedule {sched}, "
+        f"dominant {roof['kernel']} {100 * roof['frac']:.3f}% of {roof['peak']} {roof['unit']}")
+    for k, (kms, n) in sorted(prof.items(), key=lambda kv: -kv[1][0]):
+        if n:
+            log(f"[bench]   {k:18s} {kms:8.3f} ms/solve  {n:7.1f} launches/solve")
+    return res, plan, data
+
+
+def single_loop(ecl, torch, problems):
+    """The same instances solved one after another, each with its own
+    single-instance plan (graph replay), wall time of the whole loop."""
     singles = []
     for p in problems:
-        pl = ecl.Plan.for_problems([p])
+        pl = ecl.Plan.for_problems([p], use_graph=1)
         singles.append((pl, ecl.pack(pl, [p]), pl.workspace(), ecl.allocate_solution(pl)))
-    for pl, d, w, s in singles:
-        ecl.solve(pl, d, w, s)
+    for _ in range(2):  # capture, then one replay
+        for pl, d, w, s in singles:
+            ecl.solve(pl, d, w, s)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for pl, d, w, s in singles:
         ecl.solve(pl, d, w, s)
     torch.cuda.synchronize()
-    loop_ms = (time.perf_counter() - t0) * 1e3
-    ok_single = all(int((s.status != 0).sum().item()) == 0 for _, _, _, s in singles)
+    ms = (time.perf_counter() - t0) * 1e3
+    ok = all(int((s.status != 0).sum().item()) == 0 for _, _, _, s in singles)
     del singles
-    return {"workload": "c3: " + WORKLOADS["c3"], "stages": stages,
-            "batched_ms": batched_ms, "batched_stages_per_s": stages / (batched_ms * 1e-3),
-            "single_loop_ms": loop_ms, "single_loop_stages_per_s": stages / (loop_ms * 1e-3),
-            "batched_over_single": loop_ms / batched_ms, "status_ok": ok_batched and ok_single}
+    torch.cuda.empty_cache()
+    return ms, ok
 
 
-def secondary_fast_multipliers(ecl, torch, problems, tuning, steps, warmup, graph, minnorm_ms):
-    """The same workload with the factor-reusing multiplier route
-    (multipliers = 2) in the launch configuration of the headline run."""
-    plan = ecl.Plan.for_problems(problems, multipliers=2, use_graph=graph)
-    ecl.set_tuning(plan, **{k: v for k, v in tuning.items() if k not in ("ms_per_solve", "use_graph")})
-    data = ecl.pack(plan, problems)
-    ws = plan.workspace()
-    sol = ecl.allocate_solution(plan)
-    wall_ms, ev_ms = time_solves(ecl, torch, plan, data, ws, sol, steps, warmup)
-    ok = int((sol.status != 0).sum().item()) == 0
-    prof = kernel_profile(ecl, torch, plan, data, ws, sol, max(2, steps // 2))
-    stages = sum(p.N for p in problems)
-    return {"ms_per_solve": wall_ms, "stages_per_s": stages / (wall_ms * 1e-3),
-            "speedup_over_minimum_norm": minnorm_ms / wall_ms, "status_ok": ok,
-            "kernel_ms_per_solve": {k: v[0] for k, v in prof.items() if v[1]}}
-
-
-def secondary_differentiable(ecl, torch, steps):
+def differentiable(ecl, torch, steps):
     """Forward solve + backward (gradients of sum ||x||^2 + ||u||^2 with
     respect to every field) of the 256-instance batch; instance 0 checked
     against the oracle (x, u, lambda, mu at 1e-9) and one central finite
-    difference (h = 1e-6, 1e-6 relative)."""
+    difference (h = 1e-6, 1e-6 relative) in the same run."""
     from paper_2407_05433_amd.autograd import eclqr_layer
     problems = make("c4")
     plan = ecl.Plan.for_problems(problems)
@@ -175,7 +234,7 @@ def secondary_differentiable(ecl, torch, steps):
         p = problems[0]
         o = solve_with_multipliers(p)
         got = {"x": ecl.unpack(plan, x.detach(), "q", problems)[0], "u": ecl.unpack(plan, u.detach(), "r", problems)[0],
-               "lam": ecl.unpack(plan, lam, "q", problems)[0], "mu": ecl.unpack(plan, mu, "g", problems)[0]}
+               "lam": ecl.unpack(plan, lam.detach(), "q", problems)[0], "mu": ecl.unpack(plan, mu.detach(), "g", problems)[0]}
         errs = {k: float(np.linalg.norm(np.concatenate([np.ravel(a) for a in got[k]]) -
                                         np.concatenate([np.ravel(a) for a in o[k]])) /
                          max(np.linalg.norm(np.concatenate([np.ravel(a) for a in o[k]])), 1e-300)) for k in got}
@@ -195,6 +254,8 @@ def secondary_differentiable(ecl, torch, steps):
                                   "pass": max(errs.values()) <= 1e-9 and abs(fd - an) / max(abs(fd), abs(an)) <= 1e-6}
     except Exception as ex:  # the check is a report, not part of the timing
         res["check_instance0"] = {"error": repr(ex)}
+    del ws
+    torch.cuda.empty_cache()
     return res
 
 
@@ -227,26 +288,52 @@ def stored_traffic(kernel_class, workload):
     return None
 
 
-def cpu_baseline(problems, min_s=10.0, max_s=30.0):
+def _oracle_task(p):
+    from oracle import solve_with_multipliers
+    solve_with_multipliers(p)
+    return p.N
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(problems, min_s=12.0):
     """The oracle (sequential method + minimum-norm multipliers + one
     refinement step) on a bounded sample of the workload: instances in order,
-    cycling, until at least min_s seconds (at most max_s) have passed."""
-    from oracle import solve_with_multipliers
+    one per task, over a process pool of the host cores this job may use (at
+    most 16), a new task started whenever one ends until min_s seconds have
+    passed; every started task is finished and counted."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
     t0 = time.perf_counter()
-    stages, solves, i = 0, 0, 0
-    while True:
-        p = problems[i % len(problems)]
-        solve_with_multipliers(p)
-        stages += p.N
-        solves += 1
-        i += 1
-        dt = time.perf_counter() - t0
-        if dt >= min_s or dt > max_s:
-            break
+    stages = solves = nxt = 0
+    with cf.ProcessPoolExecutor(cores, mp_context=mp.get_context("fork")) as ex:
+        live = set()
+        while True:
+            while len(live) < cores and time.perf_counter() - t0 < min_s:
+                live.add(ex.submit(_oracle_task, problems[nxt % len(problems)]))
+                nxt += 1
+            if not live:
+                break
+            done, live = cf.wait(live, return_when=cf.FIRST_COMPLETED)
+            for f in done:
+                stages += f.result()
+                solves += 1
+    dt = time.perf_counter() - t0
     distinct = min(solves, len(problems))
-    return {"value": stages / dt, "unit": "stages/s", "cores": 1, "kind": "oracle",
-            "sample": f"{solves} solves of {distinct} of the {len(problems)} instances ({stages} stages), "
-                      f"{dt:.1f} s, one thread"}
+    return {"value": stages / dt, "unit": "stages/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": f"{solves} solves of the first {distinct} of the {len(problems)} instances ({stages} stages) "
+                      f"in {dt:.1f} s, one instance per process, {cores} processes of one thread"}
 
 
 def main():
@@ -254,7 +341,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--graph", type=int, default=1, help="replay the solve as a captured hipGraph (1) or launch eagerly (0)")
@@ -270,6 +357,16 @@ def main():
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    log(f"[bench] generating {args.workload}")
+    problems = make(args.workload)
+    cpu = None
+    if not args.no_cpu and not args.copy_calibration:
+        # before the GPU is touched: the pool's worker processes are forked
+        # from a process without a device context
+        log("[bench] cpu baseline (oracle, process pool)")
+        cpu = cpu_baseline(problems)
+        log(f"[bench]   {cpu}")
+
     import torch
     if args.copy_calibration:
         n = args.copy_calibration * (1 << 20) // 8
@@ -281,83 +378,57 @@ def main():
         print(json.dumps({"copy_mib": args.copy_calibration, "bytes_read": n * 8, "bytes_written": n * 8}))
         return
     import paper_2407_05433_amd as ecl
-    from paper_2407_05433_amd import flops as flopmodel
 
-    log(f"[bench] generating {args.workload}")
-    problems = make(args.workload)
-    plan = ecl.Plan.for_problems(problems, use_graph=args.graph, scan_schedule=args.scan_schedule)
-    data = ecl.pack(plan, problems)
-    ws = plan.workspace()
-    sol = ecl.allocate_solution(plan)
-    stages = sum(p.N for p in problems)
-    log(f"[bench] {len(problems)} instances, {stages} stages, workspace {plan.workspace_bytes / 2**20:.1f} MiB")
-    tuning = ecl.autotune(plan, data, ws, sol) if args.autotune else ecl.get_tuning(plan)
-    log(f"[bench] launch configuration {tuning}")
-    wall_ms, ev_ms = time_solves(ecl, torch, plan, data, ws, sol, args.steps, args.warmup)
-    st = sol.status.cpu().numpy()
-    if np.any(st != 0):
-        log(f"[bench] WARNING: nonzero status {np.unique(st)}")
-    log(f"[bench] {wall_ms:.3f} ms/solve wall, {ev_ms:.3f} ms/solve events")
-    prof = kernel_profile(ecl, torch, plan, data, ws, sol, max(3, args.steps // 2))
-    for k, (ms, n) in sorted(prof.items(), key=lambda kv: -kv[1][0]):
-        if n:
-            log(f"[bench]   {k:14s} {ms:8.3f} ms/solve  {n:6.1f} launches/solve")
-    # roofline of the dominant kernel class (algorithmic FP64 flops / its time)
-    rsteps = plan.refine_steps(ws)
-    work = flopmodel.solve_flops(plan, problems, ws, steps=rsteps)
-    dom = max((k for k in prof if prof[k][1] > 0 and k in work), key=lambda k: prof[k][0])
-    dom_ms = prof[dom][0]
-    dom_launches = prof[dom][1]
-    achieved = work[dom] / (dom_ms * 1e-3) / 1e12
-    roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-            "traffic": stored_traffic(dom, args.workload),
-            "flops_per_solve": work[dom], "ms_per_solve": dom_ms, "launches_per_solve": dom_launches,
-            "avg_launch_us": dom_ms * 1e3 / max(dom_launches, 1)}
-    total_flops = sum(work.values())
-    log(f"[bench] dominant {dom}: {achieved:.3f} TFLOP/s ({100 * achieved / FP64_VECTOR_PEAK_TFLOPS:.2f}% of FP64 "
-        f"vector peak); whole solve {total_flops / (ev_ms * 1e-3) / 1e12:.3f} TFLOP/s")
-
+    head, plan, data = measure(ecl, torch, args.workload, problems, args.steps, args.warmup, args.graph,
+                               args.autotune, args.scan_schedule)
+    roof = dict(head["roofline"])
+    roof["traffic"] = stored_traffic(roof["kernel"], args.workload)
+    del plan, data
+    torch.cuda.empty_cache()
     line = {
-        "metric": "stages/s solved (primal+multipliers)",
-        "value": stages / (wall_ms * 1e-3),
+        "metric": METRIC,
+        "value": head["stages_per_s"],
         "unit": "stages/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall_ms,
+        "ms_per_step": head["ms_per_solve"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "instances": len(problems),
-                   "stages": stages, "multipliers": True, "launch": tuning,
-                   "scan_schedule": scan_schedule_name(plan),
-                   "refine": {"max_steps": int(plan.options.refine), "tol": float(plan.options.refine_tol),
-                              "steps_taken": {str(int(k)): int(v) for k, v in zip(*np.unique(rsteps, return_counts=True))}}},
+        "config": {"workload": head["workload"], "instances": head["instances"], "stages": head["stages"],
+                   "multipliers": True, "launch": head["launch"], "scan_schedule": head["scan_schedule"],
+                   "refine": {"accept_backward_error": 1e-10, "steps_taken": head["refine_steps_taken"]}},
         "roofline": roof,
-        "kernel_ms_per_solve": {k: v[0] for k, v in prof.items() if v[1]},
+        "kernel_ms_per_solve": head["kernel_ms_per_solve"],
+        "launches_per_solve": head["launches_per_solve"],
     }
+    if args.workload == "c3":
+        log("[bench] the same 512 instances one after another (single-instance plans)")
+        loop_ms, ok = single_loop(ecl, torch, problems)
+        line["batched_vs_single"] = {"batched_ms": head["ms_per_solve"], "batched_stages_per_s": head["stages_per_s"],
+                                     "single_loop_ms": loop_ms,
+                                     "single_loop_stages_per_s": head["stages"] / (loop_ms * 1e-3),
+                                     "batched_over_single": loop_ms / head["ms_per_solve"], "status_ok": ok}
+        log(f"[bench]   {line['batched_vs_single']}")
     if not args.no_secondary:
-        del ws, sol, data
-        torch.cuda.empty_cache()
-        log("[bench] secondary: the same workload with the factor-reusing multiplier route")
-        sec = {"fast_multipliers": secondary_fast_multipliers(ecl, torch, problems, tuning, args.steps, args.warmup,
-                                                              args.graph, wall_ms)}
-        log(f"[bench]   {sec['fast_multipliers']}")
-        torch.cuda.empty_cache()
-        log("[bench] secondary: c3 batched vs single-instance loop")
-        sec["batched_vs_single"] = secondary_batched(ecl, torch, max(1, min(args.steps, 3)))
-        log(f"[bench]   {sec['batched_vs_single']}")
-        torch.cuda.empty_cache()
+        sec = {}
+        for w in ("c1", "c2", "c4"):
+            if w == args.workload:
+                continue
+            log(f"[bench] secondary: {w}")
+            r, pl, dt = measure(ecl, torch, w, make(w), max(3, min(args.steps, 10)), 2)
+            del pl, dt
+            torch.cuda.empty_cache()
+            sec[w] = r
         log("[bench] secondary: c4 forward + backward")
-        sec["differentiable"] = secondary_differentiable(ecl, torch, max(1, min(args.steps, 5)))
-        log(f"[bench]   {sec['differentiable']}")
+        sec["c4_fwd_bwd"] = differentiable(ecl, torch, max(2, min(args.steps, 5)))
+        log(f"[bench]   {sec['c4_fwd_bwd']}")
         line["secondary"] = sec
-    if not args.no_cpu:
-        log("[bench] cpu baseline (oracle)")
-        line["cpu_baseline"] = cpu_baseline(problems)
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
 
 

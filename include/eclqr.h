@@ -328,6 +328,14 @@ eclqr_status eclqr_plan_scan_rows(const eclqr_plan* plan, const void* ws, int32_
 eclqr_status eclqr_plan_combine_forms(const eclqr_plan* plan, const void* ws, int32_t which, int32_t* forms,
                                       int32_t* nslots);
 
+/* Device bytes of one engine's parts in the workspace (which: 0 the problem,
+ * 1 the reversed-time problem, 2 the theta LQR; ECLQR_INVALID_ARGUMENT when
+ * the plan has no such engine): out[0] stage arenas (the stage kernels'
+ * results and kept factors), out[1] relation-scan factor logs, out[2]
+ * value-function-scan factor logs, out[3] scan slot arenas.  A vector-only
+ * pass reads out[0] + out[1] + out[2]. */
+eclqr_status eclqr_plan_footprint(const eclqr_plan* plan, int32_t which, int64_t* out);
+
 /* Interval of every scan slot: instance, first leaf, one past the last leaf
  * (leaf N_b is the terminal; a slot whose end is N_b + 1 is unary).  Host
  * arrays of *nslots entries (may be NULL to query *nslots only). */

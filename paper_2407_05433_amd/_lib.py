@@ -121,6 +121,8 @@ def lib():
     L.eclqr_plan_slot_info.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                        C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.eclqr_plan_slot_info.restype = C.c_int
+    L.eclqr_plan_footprint.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int64)]
+    L.eclqr_plan_footprint.restype = C.c_int
     for fn in ("eclqr_plan_create", "eclqr_plan_layout", "eclqr_plan_workspace_size", "eclqr_plan_schedule",
                "eclqr_solve", "eclqr_backward", "eclqr_kkt_residual", "eclqr_plan_set_profiling",
                "eclqr_plan_profile", "eclqr_plan_reduced_dims"):

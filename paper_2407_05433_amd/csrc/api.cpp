@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <functional>
 #include <new>
@@ -55,6 +56,11 @@ template <class T>
 T* at(void* ws, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
 }
+
+// Set while a solve runs that may allocate nothing (eclqr_solve_noalloc):
+// no stream, event or graph is created, so the second stream is used only if
+// an earlier solve of the plan created it.
+thread_local bool g_noalloc = false;
 
 int32_t g_pool_lds = 2, g_grid_div = 1, g_buckets = 1, g_reg = 1, g_stage_lds = 1,
         g_split = 1;  // tuning of the plan being launched
@@ -173,6 +179,16 @@ struct Timed {
 eclqr_status bind(Plan& p, void* ws, hipStream_t s) {
   int dev = -1;
   HIP_OK(hipGetDevice(&dev));
+  if (!p.aux_stream && !g_noalloc) {
+    hipStream_t a = nullptr;
+    HIP_OK(hipStreamCreateWithFlags(&a, hipStreamNonBlocking));
+    p.aux_stream = reinterpret_cast<void*>(a);
+    hipEvent_t f = nullptr, j = nullptr;
+    HIP_OK(hipEventCreateWithFlags(&f, hipEventDisableTiming));
+    HIP_OK(hipEventCreateWithFlags(&j, hipEventDisableTiming));
+    p.ev_fork = reinterpret_cast<void*>(f);
+    p.ev_join = reinterpret_cast<void*>(j);
+  }
   if (p.bound_ws == ws && p.bound_device == dev) return ECLQR_SUCCESS;
   int lds = 0;
   HIP_OK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
@@ -191,16 +207,6 @@ eclqr_status bind(Plan& p, void* ws, hipStream_t s) {
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) ncu = 0;
     (void)hipGetLastError();
     lqr_set_device(lds_cu, ncu);
-  }
-  if (!p.aux_stream) {
-    hipStream_t a = nullptr;
-    HIP_OK(hipStreamCreateWithFlags(&a, hipStreamNonBlocking));
-    p.aux_stream = reinterpret_cast<void*>(a);
-    hipEvent_t f = nullptr, j = nullptr;
-    HIP_OK(hipEventCreateWithFlags(&f, hipEventDisableTiming));
-    HIP_OK(hipEventCreateWithFlags(&j, hipEventDisableTiming));
-    p.ev_fork = reinterpret_cast<void*>(f);
-    p.ev_join = reinterpret_cast<void*>(j);
   }
   eclqr_status st = upload_engine(p.primal, ws, p.o_primal, s);
   if (st != ECLQR_SUCCESS) return st;
@@ -582,7 +588,7 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
   // primal pass has the domains, beside the rest of that pass
   hipEvent_t theta_join = nullptr;
   SideLaunch side;
-  if (want_mult && theta && !replay && p.overlap_dual)
+  if (want_mult && theta && !replay && p.overlap_dual && p.aux_stream)
     side = [&](int step, int level) -> eclqr_status {
       hipStream_t s2 = reinterpret_cast<hipStream_t>(p.aux_stream);
       if (step == 0) {
@@ -703,7 +709,7 @@ eclqr_status solve_sequence(Plan& p, const Views& v, const Inputs& in, eclqr_sol
   launch_fill_i32(v.P.info, -1, E.B, s);
   hipEvent_t join = nullptr;
   if (want && p.opt.multipliers == 1 && !theta_route(p)) {
-    if (p.overlap_dual) {
+    if (p.overlap_dual && p.aux_stream) {
       hipStream_t s2 = reinterpret_cast<hipStream_t>(p.aux_stream);
       HIP_OK(hipEventRecord(reinterpret_cast<hipEvent_t>(p.ev_fork), s));
       HIP_OK(hipStreamWaitEvent(s2, reinterpret_cast<hipEvent_t>(p.ev_fork), 0));
@@ -787,7 +793,76 @@ void record_solve(Plan& p, const void* ws, int32_t route, const eclqr_problem* p
   R.push_back({ws, route, ++p.generation, solve_ptrs(prob, sol)});
 }
 
+// eclqr_solve, and eclqr_solve_noalloc with noalloc set (eager launches on
+// the caller's stream; nothing is created or allocated).
+eclqr_status solve_impl(eclqr_plan* plan, const eclqr_problem* prob, eclqr_solution* sol, void* ws,
+                        size_t ws_bytes, void* stream, bool noalloc = false) {
+  if (!plan || !prob || !sol || !ws) return fail(ECLQR_INVALID_ARGUMENT, "NULL argument");
+  Plan& p = plan->p;
+  if (ws_bytes < p.bytes) return fail(ECLQR_WORKSPACE_TOO_SMALL, "workspace smaller than eclqr_plan_workspace_size");
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(ECLQR_INVALID_ARGUMENT, "workspace not 256-byte aligned");
+  const Engine& E = p.primal;
+  const void* req[] = {prob->Q, prob->q, prob->R, prob->r, prob->A, prob->B, prob->c, prob->E, prob->F, prob->g,
+                       prob->x0, sol->x, sol->u, sol->status};
+  const int64_t need[] = {E.total[ECLQR_F_Q], E.total[ECLQR_F_q], E.total[ECLQR_F_R], E.total[ECLQR_F_r],
+                          E.total[ECLQR_F_A], E.total[ECLQR_F_B], E.total[ECLQR_F_c], E.total[ECLQR_F_E],
+                          E.total[ECLQR_F_F], E.total[ECLQR_F_g], E.total[ECLQR_F_x0], E.total[ECLQR_F_q],
+                          E.total[ECLQR_F_r], 1};
+  for (size_t i = 0; i < sizeof(req) / sizeof(req[0]); ++i) {
+    if (need[i] > 0 && !req[i]) return fail(ECLQR_INVALID_ARGUMENT, "NULL data pointer for a non-empty field");
+    if (req[i] && !aligned(req[i])) return fail(ECLQR_INVALID_ARGUMENT, "misaligned data pointer");
+  }
+  const bool want = p.opt.multipliers != 0;
+  if (want && ((E.total[ECLQR_F_q] > 0 && !sol->lam) || (E.total[ECLQR_F_g] > 0 && !sol->mu)))
+    return fail(ECLQR_INVALID_ARGUMENT, "lam/mu are NULL but multipliers were requested");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  g_noalloc = noalloc;
+  eclqr_status st = bind(p, ws, s);
+  g_noalloc = false;
+  if (st != ECLQR_SUCCESS) return st;
+  g_prof = noalloc ? nullptr : &p;
+  if (p.opt.multipliers == 2 && mult_local_lds_bytes(p.primal.fast_rows, p.primal.fast_ldw) > (size_t)g_max_lds)
+    return fail(ECLQR_UNSUPPORTED, "stage too large for the LDS tile of the factor-reusing multipliers");
+  if (theta_route(p) && theta_local_lds_bytes(p.th_q, p.th_ldw, p.th_r) > (size_t)g_max_lds)
+    return fail(ECLQR_UNSUPPORTED, "the device's LDS is smaller than the minimum-norm local systems' tile");
+  const int32_t route = want ? (p.opt.multipliers == 2 ? 2 : (theta_route(p) ? 1 : 0)) : -1;
+  Views v = views(p, ws);
+  v.P.info = sol->info ? sol->info : at<int32_t>(ws, p.o_info);
+  Inputs in = inputs_of(prob);
+  if (noalloc || !p.opt.use_graph || p.profiling) {
+    g_noalloc = noalloc;
+    st = solve_sequence(p, v, in, sol, want, s);
+    g_noalloc = false;
+  } else {
+    st = solve_graph(p, v, in, prob, sol, ws, want, s);
+  }
+  record_solve(p, ws, route, prob, sol, st == ECLQR_SUCCESS);
+  return st;
+}
+
 }  // namespace
+
+namespace eclqr {
+
+eclqr_status report_error(eclqr_status st, const char* msg) { return fail(st, msg); }
+
+// The solve of eclqr_solve_noalloc in a caller-provided device buffer that
+// every plan on this device shares: *owner names the plan whose tables the
+// buffer holds (0: none); another plan's call uploads its own first.
+eclqr_status solve_in_shared(eclqr_plan* plan, const eclqr_problem* prob, eclqr_solution* sol, void* buf,
+                             size_t bytes, void* stream, uint64_t* owner) {
+  if (!plan) return fail(ECLQR_INVALID_ARGUMENT, "NULL plan");
+  if (plan->p.bytes > bytes)
+    return fail(ECLQR_WORKSPACE_TOO_SMALL, "the plan's workspace (" + std::to_string(plan->p.bytes) +
+                                               " bytes) exceeds the library's static scratch (" +
+                                               std::to_string(bytes) + " bytes)");
+  if (*owner != plan->p.uid) plan->p.bound_ws = nullptr;  // tables of another plan are there
+  const eclqr_status st = solve_impl(plan, prob, sol, buf, bytes, stream, true);
+  *owner = (plan->p.bound_ws == buf) ? plan->p.uid : 0;
+  return st;
+}
+
+}  // namespace eclqr
 
 extern "C" {
 
@@ -836,6 +911,8 @@ eclqr_status eclqr_plan_create(eclqr_plan** out, const eclqr_dims* dims, const e
     return fail(ECLQR_INVALID_ARGUMENT, "bad options");
   eclqr_plan* p = new (std::nothrow) eclqr_plan();
   if (!p) return fail(ECLQR_INVALID_ARGUMENT, "out of host memory");
+  static std::atomic<uint64_t> next_uid{0};
+  p->p.uid = ++next_uid;
   std::string err;
   try {
     err = build_plan(p->p, dims, &o);
@@ -891,44 +968,13 @@ eclqr_status eclqr_plan_schedule(const eclqr_plan* plan, int32_t dual, int32_t* 
 
 eclqr_status eclqr_solve(eclqr_plan* plan, const eclqr_problem* prob, eclqr_solution* sol, void* ws,
                          size_t ws_bytes, void* stream) {
-  if (!plan || !prob || !sol || !ws) return fail(ECLQR_INVALID_ARGUMENT, "NULL argument");
-  Plan& p = plan->p;
-  if (ws_bytes < p.bytes) return fail(ECLQR_WORKSPACE_TOO_SMALL, "workspace smaller than eclqr_plan_workspace_size");
-  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(ECLQR_INVALID_ARGUMENT, "workspace not 256-byte aligned");
-  const Engine& E = p.primal;
-  const void* req[] = {prob->Q, prob->q, prob->R, prob->r, prob->A, prob->B, prob->c, prob->E, prob->F, prob->g,
-                       prob->x0, sol->x, sol->u, sol->status};
-  const int64_t need[] = {E.total[ECLQR_F_Q], E.total[ECLQR_F_q], E.total[ECLQR_F_R], E.total[ECLQR_F_r],
-                          E.total[ECLQR_F_A], E.total[ECLQR_F_B], E.total[ECLQR_F_c], E.total[ECLQR_F_E],
-                          E.total[ECLQR_F_F], E.total[ECLQR_F_g], E.total[ECLQR_F_x0], E.total[ECLQR_F_q],
-                          E.total[ECLQR_F_r], 1};
-  for (size_t i = 0; i < sizeof(req) / sizeof(req[0]); ++i) {
-    if (need[i] > 0 && !req[i]) return fail(ECLQR_INVALID_ARGUMENT, "NULL data pointer for a non-empty field");
-    if (req[i] && !aligned(req[i])) return fail(ECLQR_INVALID_ARGUMENT, "misaligned data pointer");
-  }
-  const bool want = p.opt.multipliers != 0;
-  if (want && ((E.total[ECLQR_F_q] > 0 && !sol->lam) || (E.total[ECLQR_F_g] > 0 && !sol->mu)))
-    return fail(ECLQR_INVALID_ARGUMENT, "lam/mu are NULL but multipliers were requested");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  eclqr_status st = bind(p, ws, s);
-  if (st != ECLQR_SUCCESS) return st;
-  g_prof = &p;
-  if (p.opt.multipliers == 2 && mult_local_lds_bytes(p.primal.fast_rows, p.primal.fast_ldw) > (size_t)g_max_lds)
-    return fail(ECLQR_UNSUPPORTED, "stage too large for the LDS tile of the factor-reusing multipliers");
-  if (theta_route(p) && theta_local_lds_bytes(p.th_q, p.th_ldw, p.th_r) > (size_t)g_max_lds)
-    return fail(ECLQR_UNSUPPORTED, "the device's LDS is smaller than the minimum-norm local systems' tile");
-  const int32_t route = want ? (p.opt.multipliers == 2 ? 2 : (theta_route(p) ? 1 : 0)) : -1;
-  Views v = views(p, ws);
-  v.P.info = sol->info ? sol->info : at<int32_t>(ws, p.o_info);
-  Inputs in = inputs_of(prob);
-  st = (!p.opt.use_graph || p.profiling) ? solve_sequence(p, v, in, sol, want, s) : solve_graph(p, v, in, prob, sol, ws, want, s);
-  record_solve(p, ws, route, prob, sol, st == ECLQR_SUCCESS);
-  return st;
+  return solve_impl(plan, prob, sol, ws, ws_bytes, stream);
 }
 
 eclqr_status eclqr_backward(eclqr_plan* plan, const eclqr_problem* prob, const eclqr_solution* sol,
                             const eclqr_cotangent* ct, eclqr_grads* grads, void* ws, size_t ws_bytes, void* stream) {
   if (!plan || !prob || !sol || !ct || !grads || !ws) return fail(ECLQR_INVALID_ARGUMENT, "NULL argument");
+
   Plan& p = plan->p;
   if (ws_bytes < p.bytes) return fail(ECLQR_WORKSPACE_TOO_SMALL, "workspace smaller than eclqr_plan_workspace_size");
   if (!sol->lam || !sol->mu || !ct->dx || !ct->du) return fail(ECLQR_INVALID_ARGUMENT, "backward needs lam, mu, dx, du");
@@ -1102,6 +1148,19 @@ eclqr_status eclqr_plan_combine_forms(const eclqr_plan* plan, const void* ws, in
     const double f = (o >= 0 && o < (int64_t)lg.size()) ? lg[(size_t)o] : 0.0;
     forms[q] = (f == 1.0) ? 1 : ((f == 2.0) ? 2 : 0);
   }
+  return ECLQR_SUCCESS;
+}
+
+eclqr_status eclqr_plan_footprint(const eclqr_plan* plan, int32_t which, int64_t* out) {
+  if (!plan || !out) return fail(ECLQR_INVALID_ARGUMENT, "NULL argument");
+  const Plan& p = plan->p;
+  if (which < 0 || which > 2 || (which == 1 && !p.has_dual) || (which == 2 && !p.theta_ok))
+    return fail(ECLQR_INVALID_ARGUMENT, "which: 0 problem, 1 reversed-time problem, 2 theta LQR (if the plan has it)");
+  const Engine& E = which == 2 ? p.theta : (which ? p.dual : p.primal);
+  out[0] = (int64_t)sizeof(double) * E.arena_total;
+  out[1] = (int64_t)sizeof(double) * E.rel_log_total;
+  out[2] = (int64_t)sizeof(double) * E.ric_log_total;
+  out[3] = (int64_t)sizeof(double) * (E.scan_arena[0] + E.scan_arena[1] + E.scan_arena[2]);
   return ECLQR_SUCCESS;
 }
 

@@ -102,6 +102,7 @@ struct Plan {
   };
   std::vector<WsRecord> ws_records;
   uint64_t generation = 0;
+  uint64_t uid = 0;           // unique per plan of the process (owner of a shared scratch buffer)
   // workspace regions (bytes from the workspace base)
   size_t o_primal = 0, o_dual = 0;
   size_t o_dprob[ECLQR_NUM_FIELDS] = {0};  // reversed-time stationarity problem data

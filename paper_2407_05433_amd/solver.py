@@ -161,6 +161,20 @@ class Plan:
         check(lib().eclqr_plan_slot_info(self._h, int(dual), a, b, c, C.byref(n)), "eclqr_plan_slot_info")
         return tuple(np.frombuffer(x, dtype=np.int32)[:n.value].copy() for x in (a, b, c))
 
+    def has_engine(self, which: int) -> bool:
+        """Whether the plan lays out engine `which` (0 problem, 1 reversed-time
+        problem, 2 theta LQR)."""
+        out = (C.c_int64 * 4)()
+        return lib().eclqr_plan_footprint(self._h, int(which), out) == 0
+
+    def footprint(self, which: int = 0) -> Dict[str, int]:
+        """Device bytes of one engine's workspace parts (eclqr_plan_footprint)."""
+        out = (C.c_int64 * 4)()
+        check(lib().eclqr_plan_footprint(self._h, int(which), out), "eclqr_plan_footprint")
+        arena, rel, ric, slots = (int(v) for v in out)
+        return {"arena_bytes": arena, "rel_log_bytes": rel, "ric_log_bytes": ric, "slot_bytes": slots,
+                "factor_bytes": arena + rel + ric}
+
     def stage_dims(self, dual: bool = False):
         """(n, n', m, k) per stage of the problem or of the reversed-time problem."""
         nx, nu, nc = self._nx, self._nu, self._nc

@@ -221,14 +221,15 @@ def test_c3_full_batch_sampled():
 def test_refinement_options():
     """refine = 0 (multipliers at the first primal point) and a single
     forced step both stay within tolerance on a well-conditioned instance;
-    refine_tol = 0 forces every instance through the maximum step count."""
+    accept_tol = 0 and refine_tol = 0 force every instance through the
+    maximum step count."""
     _need_gpu()
     from workloads import config_c0, config_c3
     probs = config_c0()
     check_parity(probs, gpu_solve(probs, refine=0))
     check_parity(probs, gpu_solve(probs, refine=1))
     probs = config_c3(B=4, N_range=(32, 64))
-    res = gpu_solve(probs, refine=2, refine_tol=0.0)
+    res = gpu_solve(probs, refine=2, refine_tol=0.0, accept_tol=0.0)
     assert np.all(res["_plan"].refine_steps(res["_ws"]) == 2)
     check_parity(probs, res)
 
