@@ -204,6 +204,22 @@ eclqr_status eclqr_plan_workspace_size(const eclqr_plan* plan, size_t* bytes);
 eclqr_status eclqr_solve(eclqr_plan* plan, const eclqr_problem* prob, eclqr_solution* sol, void* ws,
                          size_t ws_bytes, void* stream);
 
+/* eclqr_solve for callers that cannot allocate device memory (code under
+ * stream capture, serving loops that forbid allocation): the same solve, with
+ * the workspace in a static device array of the library (64 MiB, one per GPU,
+ * held until the process ends) instead of a caller buffer.  The caller still
+ * passes the problem and the solution buffers.  Calls no allocating routine:
+ * no hipMalloc/hipFree, no stream, event or graph creation (launches are
+ * eager on `stream`; the plan's overlapped second stream is used only if an
+ * earlier eclqr_solve of the plan created it).  Errors:
+ * ECLQR_WORKSPACE_TOO_SMALL when eclqr_plan_workspace_size exceeds 64 MiB,
+ * the other errors of eclqr_solve.  Every call on one GPU shares that GPU's
+ * array, which keeps the last call's contents (the solve initialises what it
+ * reads): calls that overlap on one GPU (two host threads, or unsynchronised
+ * streams) race and give undefined results.  eclqr_backward cannot follow a
+ * call of this entry point. */
+eclqr_status eclqr_solve_noalloc(eclqr_plan* plan, const eclqr_problem* prob, eclqr_solution* sol, void* stream);
+
 /* Gradients of a loss L(x, u, lam, mu) with respect to every problem field
  * (implicit differentiation of the KKT system; the adjoint is the same
  * constrained LQR with linear costs dL/dx, dL/du and the offsets

@@ -10,7 +10,7 @@ used by ``ECLQRFunction``.  This package is its Python binding.
 
 from ._lib import EclqrError, STATUS_BITS, status_names  # noqa: F401
 from .solver import (Plan, Solution, allocate_solution, autotune, backward, default_options, get_tuning,  # noqa: F401
-                     kkt_residual, pack, set_tuning, solve, unpack)
+                     kkt_residual, pack, set_tuning, solve, solve_noalloc, unpack)
 
 
 def __getattr__(name):

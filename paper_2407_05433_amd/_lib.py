@@ -90,6 +90,8 @@ def lib():
                                       C.POINTER(C.POINTER(C.c_int32)), C.POINTER(C.c_int32)]
     L.eclqr_solve.argtypes = [C.c_void_p, C.POINTER(ProblemPtrs), C.POINTER(SolutionPtrs), C.c_void_p, C.c_size_t,
                               C.c_void_p]
+    L.eclqr_solve_noalloc.argtypes = [C.c_void_p, C.POINTER(ProblemPtrs), C.POINTER(SolutionPtrs), C.c_void_p]
+    L.eclqr_solve_noalloc.restype = C.c_int
     L.eclqr_backward.argtypes = [C.c_void_p, C.POINTER(ProblemPtrs), C.POINTER(SolutionPtrs),
                                  C.POINTER(CotangentPtrs), C.POINTER(GradPtrs), C.c_void_p, C.c_size_t, C.c_void_p]
     L.eclqr_kkt_residual.argtypes = [C.c_void_p, C.POINTER(ProblemPtrs), C.POINTER(SolutionPtrs), C.c_void_p,

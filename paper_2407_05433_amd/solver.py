@@ -302,6 +302,16 @@ def solve(plan: Plan, data: Dict[str, torch.Tensor], ws: Optional[torch.Tensor] 
     return out
 
 
+def solve_noalloc(plan: Plan, data: Dict[str, torch.Tensor], out: Solution) -> Solution:
+    """eclqr_solve_noalloc on the current stream: the solve with the library's
+    static per-GPU scratch as its workspace (no allocation by the library;
+    the caller provides the solution buffers)."""
+    pp = _problem_ptrs(data)
+    sp = out.ptrs()
+    check(lib().eclqr_solve_noalloc(plan.handle, C.byref(pp), C.byref(sp), _stream()), "eclqr_solve_noalloc")
+    return out
+
+
 def backward(plan: Plan, data: Dict[str, torch.Tensor], sol: Solution, dx: torch.Tensor, du: torch.Tensor,
              ws: torch.Tensor, dlam: Optional[torch.Tensor] = None,
              dmu: Optional[torch.Tensor] = None) -> Dict[str, torch.Tensor]:
