@@ -25,9 +25,11 @@ from __future__ import annotations
 
 import os
 
-# the oracle (CPU baseline) runs one instance per process, one thread each
+# the oracle (CPU baseline) runs one instance per process, one BLAS thread
+# each; set before NumPy loads, so no BLAS thread pool exists when the pool's
+# workers are forked
 for _v in ("OPENBLAS_NUM_THREADS", "OMP_NUM_THREADS", "MKL_NUM_THREADS"):
-    os.environ.setdefault(_v, "1")
+    os.environ[_v] = "1"
 
 import argparse  # noqa: E402
 import json  # noqa: E402
@@ -328,6 +330,8 @@ def cpu_baseline(problems, min_s=12.0):
             for f in done:
                 stages += f.result()
                 solves += 1
+                if solves % 16 == 0:
+                    log(f"[bench]   oracle: {solves} solves, {stages} stages, {time.perf_counter() - t0:.1f} s")
     dt = time.perf_counter() - t0
     distinct = min(solves, len(problems))
     return {"value": stages / dt, "unit": "stages/s", "cores": cores, "kind": "oracle",
