@@ -73,6 +73,8 @@ typedef enum {
 #define ECLQR_CAPACITY 32           /* a relation outgrew its on-chip tile */
 #define ECLQR_DUAL_FAILED 64        /* the multiplier (stationarity) solve failed; its own
                                        outcome bits are repeated in bits 8..15 */
+#define ECLQR_TIMEOUT (1 << 16)      /* a bounded wait of a persistent scan kernel expired (2 s of wall
+                                       clock): the outputs are not valid */
 #define ECLQR_NOT_DIFFERENTIABLE 128 /* eclqr_backward only: the instance's constraint rows are
                                        dependent (LICQ fails: a redundant row, or rows that together
                                        with x_0 = x0 restrict x_0), so its multipliers are not unique
@@ -289,6 +291,13 @@ typedef struct {
   int32_t split_combine;  /* value-function combines of a level whose tasks all fit the device at once run on two
                            * wavefronts (J, eta, A, b on one, the C update on the other; same bits) (1, default) or
                            * one (0) */
+  int32_t fused_scans;    /* 1: the vector-only replays (refinement steps, the multipliers at the refined point, the
+                           * adjoint) run each scan as one persistent launch over all its levels: the grid is
+                           * bounded by the co-resident workgroups the runtime reports, tasks are taken in level
+                           * order from a counter and wait, boundedly (2 s, then ECLQR_TIMEOUT), for the levels
+                           * before theirs.  0 (default): one launch per level.  Experimental: on the device the
+                           * persistent form did not complete its waits (see the design notes); the autotuner does
+                           * not select it */
 } eclqr_tuning;
 
 /* Time the caller's problem under alternative launch configurations

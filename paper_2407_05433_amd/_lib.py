@@ -25,6 +25,7 @@ STATUS_BITS = {
     32: "capacity",
     64: "dual_failed",
     128: "not_differentiable",
+    1 << 16: "timeout",
 }
 
 
@@ -44,7 +45,7 @@ class Tuning(C.Structure):
     _fields_ = [("use_graph", C.c_int32), ("level_buckets", C.c_int32), ("pool_in_lds", C.c_int32),
                 ("grid_divisor", C.c_int32), ("ms_per_solve", C.c_double), ("register_compose", C.c_int32),
                 ("stage_lds", C.c_int32), ("overlap_dual", C.c_int32), ("multiplier_route", C.c_int32),
-                ("split_combine", C.c_int32)]
+                ("split_combine", C.c_int32), ("fused_scans", C.c_int32)]
 
 
 class ProblemPtrs(C.Structure):
@@ -147,5 +148,5 @@ def status_names(code: int):
     if code == 0:
         return ["ok"]
     out = [name for bit, name in STATUS_BITS.items() if code & bit]
-    out += ["dual:" + name for bit, name in STATUS_BITS.items() if (code >> 8) & bit]
+    out += ["dual:" + name for bit, name in STATUS_BITS.items() if bit < 256 and (code >> 8) & bit]
     return out

@@ -205,8 +205,11 @@ eclqr_status bind(Plan& p, void* ws, hipStream_t s) {
     int lds_cu = 0, ncu = 0;
     if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess) lds_cu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) ncu = 0;
+    int wclk = 0;
+    if (hipDeviceGetAttribute(&wclk, hipDeviceAttributeWallClockRate, dev) != hipSuccess) wclk = 0;
     (void)hipGetLastError();
     lqr_set_device(lds_cu, ncu);
+    replay_set_device(ncu, wclk);
   }
   eclqr_status st = upload_engine(p.primal, ws, p.o_primal, s);
   if (st != ECLQR_SUCCESS) return st;
@@ -294,28 +297,71 @@ eclqr_status run_engine(const Engine& E, const DevEngine& d, const Inputs& in, d
   return ECLQR_SUCCESS;
 }
 
-// The same pass on new vectors, replaying the factors the last full pass of
-// this engine logged in the workspace (no rank decisions, no outcome bits).
-eclqr_status run_engine_vec(const Engine& E, const DevEngine& d, const Inputs& in, double* x, double* u,
-                            hipStream_t s) {
-  { Timed tm(ECLQR_K_REPLAY, s); launch_base_relation_vec(d, in, E.base_rel_log, s); }
+// The nonempty levels of an engine's scans for the persistent scan kernels;
+// false when there are more than they take.
+bool scan_levels(const Engine& E, ScanLevels* lv) {
+  lv->n = 0;
   for (int l = 0; l < 2 * E.D; ++l) {
     if (E.lvl_count[l] == 0) continue;
+    if (lv->n == kMaxScanLevels) return false;
+    lv->begin[lv->n] = E.lvl_begin[l];
+    lv->count[lv->n] = E.lvl_count[l];
+    ++lv->n;
+  }
+  return true;
+}
+
+// Control of the persistent scans of one vector pass: ctrl holds the three
+// scans' blocks (zeroed here), abort the plan-wide expiry flag.
+struct ScanCtrl {
+  int32_t* ctrl = nullptr;
+  int32_t* abort = nullptr;
+};
+
+// The same pass on new vectors, replaying the factors the last full pass of
+// this engine logged in the workspace (no rank decisions, no outcome bits).
+// With sc.ctrl, each scan's levels run as one persistent launch.
+eclqr_status run_engine_vec(const Engine& E, const DevEngine& d, const Inputs& in, double* x, double* u,
+                            hipStream_t s, ScanCtrl sc = {}) {
+  ScanLevels lv;
+  const bool fused = sc.ctrl && scan_levels(E, &lv);
+  if (fused) {
     Timed tm(ECLQR_K_REPLAY, s);
-    launch_rel_compose_vec(d, E.lvl_begin[l], E.lvl_count[l], E.lvl_rel_log[l], s);
+    launch_fill_i32(sc.ctrl, 0, 3 * kScanCtrlInts, s);
+  }
+  { Timed tm(ECLQR_K_REPLAY, s); launch_base_relation_vec(d, in, E.base_rel_log, s); }
+  if (fused) {
+    Timed tm(ECLQR_K_REPLAY, s);
+    launch_scan_vec(d, SCAN_REL, lv, sc.ctrl, sc.abort, s);
+  } else {
+    for (int l = 0; l < 2 * E.D; ++l) {
+      if (E.lvl_count[l] == 0) continue;
+      Timed tm(ECLQR_K_REPLAY, s);
+      launch_rel_compose_vec(d, E.lvl_begin[l], E.lvl_count[l], E.lvl_rel_log[l], s);
+    }
   }
   { Timed tm(ECLQR_K_REPLAY, s); launch_domain_vec(d, in, s); }
   { Timed tm(ECLQR_K_REPLAY, s); launch_eliminate_vec(d, in, s); }
-  for (int l = 0; l < 2 * E.D; ++l) {
-    if (E.lvl_count[l] == 0) continue;
+  if (fused) {
     Timed tm(ECLQR_K_REPLAY, s);
-    launch_ric_combine_vec(d, E.lvl_begin[l], E.lvl_count[l], std::max(1, E.lvl_dim[l]), s);
+    launch_scan_vec(d, SCAN_RIC, lv, sc.ctrl + kScanCtrlInts, sc.abort, s);
+  } else {
+    for (int l = 0; l < 2 * E.D; ++l) {
+      if (E.lvl_count[l] == 0) continue;
+      Timed tm(ECLQR_K_REPLAY, s);
+      launch_ric_combine_vec(d, E.lvl_begin[l], E.lvl_count[l], std::max(1, E.lvl_dim[l]), s);
+    }
   }
   { Timed tm(ECLQR_K_REPLAY, s); launch_gains_vec(d, s); }
-  for (int l = 0; l < 2 * E.D; ++l) {
-    if (E.lvl_count[l] == 0) continue;
+  if (fused) {
     Timed tm(ECLQR_K_REPLAY, s);
-    launch_fwd_combine_vec(d, E.lvl_begin[l], E.lvl_count[l], s);
+    launch_scan_vec(d, SCAN_FWD, lv, sc.ctrl + 2 * kScanCtrlInts, sc.abort, s);
+  } else {
+    for (int l = 0; l < 2 * E.D; ++l) {
+      if (E.lvl_count[l] == 0) continue;
+      Timed tm(ECLQR_K_REPLAY, s);
+      launch_fwd_combine_vec(d, E.lvl_begin[l], E.lvl_count[l], s);
+    }
   }
   { Timed tm(ECLQR_K_REPLAY, s); launch_recover(d, x, u, s); }
   HIP_OK(hipGetLastError());
@@ -349,6 +395,7 @@ struct Views {
   double *cx, *cu, *clam, *cmu;
   int32_t* gate;
   int32_t* live;
+  ScanCtrl scP, scD, scT;  // persistent-scan control of the problem, reversed-time and theta engines
   int32_t* rsteps;
   unsigned long long* omega;
   double* rnorm;
@@ -397,6 +444,12 @@ Views views(Plan& p, void* ws) {
   v.D.live = v.live;
   v.T.gate = v.gate;
   v.T.live = v.live;
+  if (p.fused_scans) {
+    int32_t* ab = at<int32_t>(ws, p.o_abort);
+    v.scP = {at<int32_t>(ws, p.o_ctrl), ab};
+    v.scD = {at<int32_t>(ws, p.o_ctrl) + 3 * kScanCtrlInts, ab};
+    v.scT = {at<int32_t>(ws, p.o_ctrl) + 6 * kScanCtrlInts, ab};
+  }
   return v;
 }
 
@@ -422,7 +475,7 @@ eclqr_status multipliers(Plan& p, const Views& v, const Inputs& in, const double
   }
   Inputs din = dual_inputs(v);
   din.x0 = x;  // n_0 of the reversed problem is 0: any valid pointer
-  eclqr_status st = vec ? run_engine_vec(p.dual, v.D, din, v.dx, v.du, s)
+  eclqr_status st = vec ? run_engine_vec(p.dual, v.D, din, v.dx, v.du, s, v.scD)
                         : run_engine(p.dual, v.D, din, v.dx, v.du, v.dstatus, td, s);
   if (st != ECLQR_SUCCESS) return st;
   {
@@ -472,7 +525,14 @@ eclqr_status theta_multipliers(Plan& p, const Views& v, const Inputs& in, const 
     Timed tm(ECLQR_K_MULT_THETA, s);
     launch_fill_i32(defer, 0, 2 * T.D, s);
   }
-  for (int l = 0; l < 2 * T.D; ++l) {
+  ScanLevels lv;
+  const bool fused = !full && v.scT.ctrl && scan_levels(T, &lv);
+  if (fused) {
+    Timed tm(ECLQR_K_REPLAY, s);
+    launch_fill_i32(v.scT.ctrl, 0, 3 * kScanCtrlInts, s);
+    launch_scan_vec(v.T, SCAN_RIC, lv, v.scT.ctrl + kScanCtrlInts, v.scT.abort, s);
+  }
+  for (int l = 0; l < 2 * T.D && !fused; ++l) {
     if (T.lvl_count[l] == 0) continue;
     if (full) {
       Timed tm(ECLQR_K_RIC_COMBINE, s);
@@ -498,7 +558,11 @@ eclqr_status theta_multipliers(Plan& p, const Views& v, const Inputs& in, const 
     Timed tm(ECLQR_K_MULT_THETA, s);
     launch_theta_init(v.T, s);
   }
-  for (int l = 0; l < 2 * T.D; ++l) {
+  if (fused) {
+    Timed tm(ECLQR_K_REPLAY, s);
+    launch_scan_vec(v.T, SCAN_FWD, lv, v.scT.ctrl + 2 * kScanCtrlInts, v.scT.abort, s);
+  }
+  for (int l = 0; l < 2 * T.D && !fused; ++l) {
     if (T.lvl_count[l] == 0) continue;
     if (full) {
       Timed tm(ECLQR_K_FWD_COMBINE, s);
@@ -581,6 +645,7 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
     launch_fill_i32(v.live, 1, 1, s);
     launch_fill_i32(v.rsteps, 0, B, s);
     launch_fill_u64(v.omega, 0ull, B, s);
+    launch_fill_i32(at<int32_t>(v.ws, p.o_abort), 0, 1, s);
   }
   const bool fast = p.opt.multipliers == 2;
   const bool theta = theta_route(p);
@@ -598,7 +663,7 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
       }
       return theta_prefactor_step(p, v, in, s2, step, level);
     };
-  eclqr_status st = replay ? run_engine_vec(p.primal, v.P, in, x, u, s)
+  eclqr_status st = replay ? run_engine_vec(p.primal, v.P, in, x, u, s, v.scP)
                            : run_engine(p.primal, v.P, in, x, u, status, tp, s, side);
   if (theta_join) {  // also after a failed pass: the second stream is joined before anything returns
     HIP_OK(hipEventRecord(theta_join, reinterpret_cast<hipStream_t>(p.aux_stream)));
@@ -626,6 +691,7 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
   if (nref == 0) {
     Timed tm(ECLQR_K_REFINE_IO, s);
     launch_merge_status(status, v.dstatus, ECLQR_DUAL_FAILED, B, nullptr, 0, s);
+    launch_apply_abort(status, at<int32_t>(v.ws, p.o_abort), ECLQR_TIMEOUT, B, s);
     return ECLQR_SUCCESS;
   }
   {
@@ -646,7 +712,7 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
       launch_gate_advance(v.gate, v.live, B, s);
       launch_correction(v.P, in, x, u, lam, mu, v.cp, s);
     }
-    st = run_engine_vec(p.primal, v.P, cin, v.cx, v.cu, s);
+    st = run_engine_vec(p.primal, v.P, cin, v.cx, v.cu, s, v.scP);
     if (st != ECLQR_SUCCESS) return st;
     if (fast) {  // multipliers of the correction problem (the route is linear in the vectors)
       st = fast_multipliers(p, v, cin, v.cx, v.cu, lam, mu, nullptr, true, s);
@@ -672,6 +738,7 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
     launch_fill_u64(v.omega, 0ull, B, s);
     launch_backward_error(v.P, in, x, u, lam, mu, v.omega, s);
     launch_flag_unconverged(v.omega, v.rsteps, p.opt.dual_cons_tol, status, ECLQR_DUAL_FAILED, B, s);
+    launch_apply_abort(status, at<int32_t>(v.ws, p.o_abort), ECLQR_TIMEOUT, B, s);
   }
   return ECLQR_SUCCESS;
 }
@@ -1191,6 +1258,7 @@ eclqr_status eclqr_plan_get_tuning(const eclqr_plan* plan, eclqr_tuning* out) {
   out->overlap_dual = p.overlap_dual;
   out->multiplier_route = p.theta_ok ? p.mult_route : 0;
   out->split_combine = p.split_combine;
+  out->fused_scans = p.fused_scans;
   out->ms_per_solve = p.tuned_ms;
   return ECLQR_SUCCESS;
 }
@@ -1209,6 +1277,7 @@ eclqr_status eclqr_plan_set_tuning(eclqr_plan* plan, const eclqr_tuning* t) {
   p.overlap_dual = t->overlap_dual != 0;
   p.mult_route = (p.theta_ok && (t->multiplier_route != 0 || !p.has_dual)) ? 1 : 0;
   p.split_combine = t->split_combine != 0;
+  p.fused_scans = t->fused_scans != 0;
   release_graph(p);
   return ECLQR_SUCCESS;
 }

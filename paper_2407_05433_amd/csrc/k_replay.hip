@@ -196,57 +196,62 @@ __global__ void __launch_bounds__(kBlock) k_base_relation_vec(DevEngine e, Input
   }
 }
 
+// Vector replay of the composition task `task` (absolute index into the task
+// list).  o: LDS offsets of kMaxRows; lgs: LDS for a staged log (logcap
+// doubles, 0 = read in place).
+__device__ inline void rel_compose_vec_task(const DevEngine& e, int64_t task, int64_t logcap, double* o, double* lgs) {
+  const int a = e.tasks[3 * task];
+  const int bsl = e.tasks[3 * task + 1];
+  const int oo = e.tasks[3 * task + 2];
+  const int sa = slot_a(e, 0, a), sb = slot_b(e, 0, a), sc = slot_b(e, 0, bsl);
+  if (gated(e, e.st[sa].inst)) return;
+  const int na = e.st[sa].n, nb = e.st[sb].n, nc = (sc >= 0) ? e.st[sc].n : 0;
+  const int ra = e.slot_rows[a], rb = e.slot_rows[bsl];
+  const int P = e.slot_cap[a] + e.slot_cap[bsl];
+  if (ra + rb > P || P > kMaxRows) return;
+  const int cap = e.slot_cap[oo];
+  const RelLog L = rel_log_layout(P, (nb < P) ? nb : P, cap);
+  const double* lg = e.rel_log + e.rel_log_off[oo];
+  const double* Ls = slot_ptr(e, SCAN_REL, a);
+  const double* Rs = slot_ptr(e, SCAN_REL, bsl);
+  const int lda = na + nb + 1, ldb = nb + nc + 1;
+  if (lg[3] == 1.0) {
+    // composition of two full-rank relations: offsets -(a*, c*)
+    if (ra != na + nb || rb != nb + nc) return;
+    const int lo = na + nc + 1;
+    double* out = slot_ptr(e, SCAN_REL, oo);
+    for (int r = ECLQR_TID; r < na + nc; r += ECLQR_NT) {
+      const double x = (r < na) ? -lane_dot(Ls + r, lda, Ls + lda - 1, lda, ra)
+                                : -lane_dot(Rs + nb + (r - na), ldb, Rs + ldb - 1, ldb, rb);
+      out[r * lo + lo - 1] = -x;
+    }
+    wg_sync();
+    return;
+  }
+  const bool regfmt = lg[3] == 2.0;
+  const int R = (nb < P) ? nb : P;
+  if (L.size <= logcap) {
+    stage_rel_log(lgs, lg, L, P, cap, rel_header(lg, P, R, cap), false);
+    lg = lgs;
+  }
+  for (int r = ECLQR_TID; r < ra + rb; r += ECLQR_NT)
+    o[r] = (r < ra) ? Ls[r * lda + na + nb] : Rs[(r - ra) * ldb + nb + nc];
+  lds_sync();
+  int rho = 0, rr = 0;
+  if (regfmt) rel_replay_reg(o, lg, L, P, R, cap, &rho, &rr);
+  else rel_replay(o, lg, L, P, R, cap, false, &rho, &rr);
+  if (rr > e.slot_rows[oo]) rr = e.slot_rows[oo];
+  const int lo = na + nc + 1;
+  double* out = slot_ptr(e, SCAN_REL, oo);
+  for (int r = ECLQR_TID; r < rr; r += ECLQR_NT) out[r * lo + lo - 1] = o[rho + r];
+  lds_sync();
+}
+
 __global__ void __launch_bounds__(kBlock) k_rel_compose_vec(DevEngine e, int64_t first, int64_t ntasks, int64_t logcap) {
   if (none_live(e)) return;
   __shared__ double o[kMaxRows];
   extern __shared__ double lgs[];
-  for (int64_t ti = blockIdx.x; ti < ntasks; ti += gridDim.x) {
-    const int a = e.tasks[3 * (first + ti)];
-    const int bsl = e.tasks[3 * (first + ti) + 1];
-    const int oo = e.tasks[3 * (first + ti) + 2];
-    const int sa = slot_a(e, 0, a), sb = slot_b(e, 0, a), sc = slot_b(e, 0, bsl);
-    if (gated(e, e.st[sa].inst)) continue;
-    const int na = e.st[sa].n, nb = e.st[sb].n, nc = (sc >= 0) ? e.st[sc].n : 0;
-    const int ra = e.slot_rows[a], rb = e.slot_rows[bsl];
-    const int P = e.slot_cap[a] + e.slot_cap[bsl];
-    if (ra + rb > P || P > kMaxRows) continue;
-    const int cap = e.slot_cap[oo];
-    const RelLog L = rel_log_layout(P, (nb < P) ? nb : P, cap);
-    const double* lg = e.rel_log + e.rel_log_off[oo];
-    const double* Ls = slot_ptr(e, SCAN_REL, a);
-    const double* Rs = slot_ptr(e, SCAN_REL, bsl);
-    const int lda = na + nb + 1, ldb = nb + nc + 1;
-    if (lg[3] == 1.0) {
-      // composition of two full-rank relations: offsets -(a*, c*)
-      if (ra != na + nb || rb != nb + nc) continue;
-      const int lo = na + nc + 1;
-      double* out = slot_ptr(e, SCAN_REL, oo);
-      for (int r = ECLQR_TID; r < na + nc; r += ECLQR_NT) {
-        const double x = (r < na) ? -lane_dot(Ls + r, lda, Ls + lda - 1, lda, ra)
-                                  : -lane_dot(Rs + nb + (r - na), ldb, Rs + ldb - 1, ldb, rb);
-        out[r * lo + lo - 1] = -x;
-      }
-      wg_sync();
-      continue;
-    }
-    const bool regfmt = lg[3] == 2.0;
-    const int R = (nb < P) ? nb : P;
-    if (L.size <= logcap) {
-      stage_rel_log(lgs, lg, L, P, cap, rel_header(lg, P, R, cap), false);
-      lg = lgs;
-    }
-    for (int r = ECLQR_TID; r < ra + rb; r += ECLQR_NT)
-      o[r] = (r < ra) ? Ls[r * lda + na + nb] : Rs[(r - ra) * ldb + nb + nc];
-    lds_sync();
-    int rho = 0, rr = 0;
-    if (regfmt) rel_replay_reg(o, lg, L, P, R, cap, &rho, &rr);
-    else rel_replay(o, lg, L, P, R, cap, false, &rho, &rr);
-    if (rr > e.slot_rows[oo]) rr = e.slot_rows[oo];
-    const int lo = na + nc + 1;
-    double* out = slot_ptr(e, SCAN_REL, oo);
-    for (int r = ECLQR_TID; r < rr; r += ECLQR_NT) out[r * lo + lo - 1] = o[rho + r];
-    lds_sync();
-  }
+  for (int64_t ti = blockIdx.x; ti < ntasks; ti += gridDim.x) rel_compose_vec_task(e, first + ti, logcap, o, lgs);
 }
 
 // t = -H' h; on stage 0, z_0 = T'(x0 - t).
@@ -458,102 +463,68 @@ __global__ void __launch_bounds__(kBlock) k_eliminate_vec(DevEngine e, Inputs in
   }
 }
 
-// b, eta of a value-function combine from its logged factors.
-// LDS (maxd): [log: 4 + 2 maxd^2 + maxd | A1: maxd^2 | A2: maxd^2]; the
-// factored form reads its factors and both A blocks from there.
-__global__ void __launch_bounds__(kBlock) k_ric_combine_vec(DevEngine e, int64_t first, int64_t ntasks, int maxd) {
-  if (none_live(e)) return;
-  __shared__ double v1[kMaxDim], v2[kMaxDim], v3[kMaxDim];
-  __shared__ int piv[kMaxDim];
-  extern __shared__ double rs[];
-  for (int64_t ti = blockIdx.x; ti < ntasks; ti += gridDim.x) {
-    const int a = e.tasks[3 * (first + ti)];
-    const int bsl = e.tasks[3 * (first + ti) + 1];
-    const int o = e.tasks[3 * (first + ti) + 2];
-    const int sa = slot_a(e, 0, a), sm = slot_b(e, 0, a), se = slot_b(e, 0, bsl);
-    if (gated(e, e.st[sa].inst)) continue;
-    const int ds = e.nbar[sa], dm = e.nbar[sm], de = (se >= 0) ? e.nbar[se] : 0;
-    const int ns = e.st[sa].n, nm = e.st[sm].n, ne = (se >= 0) ? e.st[se].n : 0;
-    const RicLayout l1 = ric_layout(ns, nm), l2 = ric_layout(nm, ne), lo = ric_layout(ns, ne);
-    const double* E1 = slot_ptr(e, SCAN_RIC, a);
-    const double* E2 = slot_ptr(e, SCAN_RIC, bsl);
-    double* Eo = slot_ptr(e, SCAN_RIC, o);
-    const double *A1 = E1 + l1.A, *b1 = E1 + l1.b, *C1 = E1 + l1.C, *et1 = E1 + l1.eta;
-    const double *A2 = E2 + l2.A, *b2 = E2 + l2.b, *et2 = E2 + l2.eta, *J2 = E2 + l2.J;
-    const double* rlog = e.ric_log + e.ric_log_off[o];
-    const bool binary = se >= 0;
-    const bool factored = (dm > 0) && (rlog[0] == 1.0);
-    if (factored && dm <= maxd && ds <= maxd && de <= maxd) {
-      const int64_t lsz = 4 + 2 * (int64_t)maxd * maxd + maxd;
-      double* A1s = rs + lsz;
-      double* A2s = A1s + (int64_t)maxd * maxd;
-      stage_ranges(rs, rlog, 0, 1, 4 + 2 * dm * dm);
-      stage_ranges(A1s, A1, 0, 1, dm * ds);
-      if (binary) stage_ranges(A2s, A2, 0, 1, de * dm);
-      lds_sync();
-      rlog = rs;
-      A1 = A1s;
-      A2 = A2s;
-    }
-    if (factored) {
-      const double* Lj = rlog + 4;
-      const double* Rg = rlog + 4 + (int64_t)dm * dm;
-      // xi = L^{-1} eta2 ; d = G^{-1}(xi - L'b1) ; eta = eta1 + A1' L d ; b = A2 L^{-T}(xi - d) + b2
-      double xi = (ECLQR_TID < dm) ? et2[ECLQR_TID] : 0.0;
-      xi = lane_trsv_lower(Lj, dm, xi, dm);
-      double tvv = xi;
-      if (ECLQR_TID < dm)
-        for (int l = ECLQR_TID; l < dm; ++l) tvv = fma(-Lj[l * dm + ECLQR_TID], b1[l], tvv);
-      tvv = lane_trsv_lower(Rg, dm, tvv, dm);
-      tvv = lane_trsv_lower_t(Rg, dm, tvv, dm);
-      if (ECLQR_TID < dm) v1[ECLQR_TID] = tvv;
-      lds_sync();
-      if (ECLQR_TID < dm) {
-        double w = 0.0;
-        for (int l = 0; l <= ECLQR_TID; ++l) w = fma(Lj[ECLQR_TID * dm + l], v1[l], w);
-        v2[ECLQR_TID] = w;
-      }
-      lds_sync();
-      for (int i = ECLQR_TID; i < ds; i += ECLQR_NT) {
-        double v = et1[i];
-        v = lane_chain<false>(v, A1 + i, ds, v2, 1, dm);
-        Eo[lo.eta + i] = v;
-      }
-      if (binary) {
-        double yl = lane_trsv_lower_t(Lj, dm, xi - tvv, dm);
-        if (ECLQR_TID < dm) v3[ECLQR_TID] = yl;
-        lds_sync();
-        for (int i = ECLQR_TID; i < de; i += ECLQR_NT) {
-          double v = b2[i];
-          v = lane_chain<false>(v, A2 + i * dm, 1, v3, 1, dm);
-          Eo[lo.b + i] = v;
-        }
-      }
-      lds_sync();
-      continue;
-    }
-    // LU form: eta = A1' Minv'(eta2 - J2 b1) + eta1 ; b = A2 Minv (b1 + C1 eta2) + b2
-    const double* LU = rlog + 4;
-    for (int i = ECLQR_TID; i < dm; i += ECLQR_NT) {
-      piv[i] = (int)rlog[4 + 2 * (int64_t)dm * dm + i];
-      double v = et2[i];
-      v = lane_chain<true>(v, J2 + i * dm, 1, b1, 1, dm);
-      v1[i] = v;
-      double w = b1[i];
-      w = lane_chain<false>(w, C1 + i * dm, 1, et2, 1, dm);
-      v3[i] = w;
+// b, eta of the value-function combine `task` from its logged factors.
+// rs (maxd): [log: 4 + 2 maxd^2 + maxd | A1: maxd^2 | A2: maxd^2] in LDS; the
+// factored form reads its factors and both A blocks from there (maxd = 0:
+// read in place).  v1, v2, v3, piv: LDS vectors of kMaxDim.
+__device__ inline void ric_combine_vec_task(const DevEngine& e, int64_t task, int maxd, double* v1, double* v2,
+                                            double* v3, int* piv, double* rs) {
+  const int a = e.tasks[3 * task];
+  const int bsl = e.tasks[3 * task + 1];
+  const int o = e.tasks[3 * task + 2];
+  const int sa = slot_a(e, 0, a), sm = slot_b(e, 0, a), se = slot_b(e, 0, bsl);
+  if (gated(e, e.st[sa].inst)) return;
+  const int ds = e.nbar[sa], dm = e.nbar[sm], de = (se >= 0) ? e.nbar[se] : 0;
+  const int ns = e.st[sa].n, nm = e.st[sm].n, ne = (se >= 0) ? e.st[se].n : 0;
+  const RicLayout l1 = ric_layout(ns, nm), l2 = ric_layout(nm, ne), lo = ric_layout(ns, ne);
+  const double* E1 = slot_ptr(e, SCAN_RIC, a);
+  const double* E2 = slot_ptr(e, SCAN_RIC, bsl);
+  double* Eo = slot_ptr(e, SCAN_RIC, o);
+  const double *A1 = E1 + l1.A, *b1 = E1 + l1.b, *C1 = E1 + l1.C, *et1 = E1 + l1.eta;
+  const double *A2 = E2 + l2.A, *b2 = E2 + l2.b, *et2 = E2 + l2.eta, *J2 = E2 + l2.J;
+  const double* rlog = e.ric_log + e.ric_log_off[o];
+  const bool binary = se >= 0;
+  const bool factored = (dm > 0) && (rlog[0] == 1.0);
+  if (factored && dm <= maxd && ds <= maxd && de <= maxd) {
+    const int64_t lsz = 4 + 2 * (int64_t)maxd * maxd + maxd;
+    double* A1s = rs + lsz;
+    double* A2s = A1s + (int64_t)maxd * maxd;
+    stage_ranges(rs, rlog, 0, 1, 4 + 2 * dm * dm);
+    stage_ranges(A1s, A1, 0, 1, dm * ds);
+    if (binary) stage_ranges(A2s, A2, 0, 1, de * dm);
+    lds_sync();
+    rlog = rs;
+    A1 = A1s;
+    A2 = A2s;
+  }
+  if (factored) {
+    const double* Lj = rlog + 4;
+    const double* Rg = rlog + 4 + (int64_t)dm * dm;
+    // xi = L^{-1} eta2 ; d = G^{-1}(xi - L'b1) ; eta = eta1 + A1' L d ; b = A2 L^{-T}(xi - d) + b2
+    double xi = (ECLQR_TID < dm) ? et2[ECLQR_TID] : 0.0;
+    xi = lane_trsv_lower(Lj, dm, xi, dm);
+    double tvv = xi;
+    if (ECLQR_TID < dm)
+      for (int l = ECLQR_TID; l < dm; ++l) tvv = fma(-Lj[l * dm + ECLQR_TID], b1[l], tvv);
+    tvv = lane_trsv_lower(Rg, dm, tvv, dm);
+    tvv = lane_trsv_lower_t(Rg, dm, tvv, dm);
+    if (ECLQR_TID < dm) v1[ECLQR_TID] = tvv;
+    lds_sync();
+    if (ECLQR_TID < dm) {
+      double w = 0.0;
+      for (int l = 0; l <= ECLQR_TID; ++l) w = fma(Lj[ECLQR_TID * dm + l], v1[l], w);
+      v2[ECLQR_TID] = w;
     }
     lds_sync();
-    for (int i = ECLQR_TID; i < dm; i += ECLQR_NT) piv[i] = (piv[i] < i || piv[i] >= dm) ? i : piv[i];
-    lds_sync();
-    wg_lu_solve_t(LU, dm, dm, piv, v1, 1, 1);
     for (int i = ECLQR_TID; i < ds; i += ECLQR_NT) {
       double v = et1[i];
-      v = lane_chain<false>(v, A1 + i, ds, v1, 1, dm);
+      v = lane_chain<false>(v, A1 + i, ds, v2, 1, dm);
       Eo[lo.eta + i] = v;
     }
     if (binary) {
-      wg_lu_solve(LU, dm, dm, piv, v3, 1, 1);
+      double yl = lane_trsv_lower_t(Lj, dm, xi - tvv, dm);
+      if (ECLQR_TID < dm) v3[ECLQR_TID] = yl;
+      lds_sync();
       for (int i = ECLQR_TID; i < de; i += ECLQR_NT) {
         double v = b2[i];
         v = lane_chain<false>(v, A2 + i * dm, 1, v3, 1, dm);
@@ -561,7 +532,45 @@ __global__ void __launch_bounds__(kBlock) k_ric_combine_vec(DevEngine e, int64_t
       }
     }
     lds_sync();
+    return;
   }
+  // LU form: eta = A1' Minv'(eta2 - J2 b1) + eta1 ; b = A2 Minv (b1 + C1 eta2) + b2
+  const double* LU = rlog + 4;
+  for (int i = ECLQR_TID; i < dm; i += ECLQR_NT) {
+    piv[i] = (int)rlog[4 + 2 * (int64_t)dm * dm + i];
+    double v = et2[i];
+    v = lane_chain<true>(v, J2 + i * dm, 1, b1, 1, dm);
+    v1[i] = v;
+    double w = b1[i];
+    w = lane_chain<false>(w, C1 + i * dm, 1, et2, 1, dm);
+    v3[i] = w;
+  }
+  lds_sync();
+  for (int i = ECLQR_TID; i < dm; i += ECLQR_NT) piv[i] = (piv[i] < i || piv[i] >= dm) ? i : piv[i];
+  lds_sync();
+  wg_lu_solve_t(LU, dm, dm, piv, v1, 1, 1);
+  for (int i = ECLQR_TID; i < ds; i += ECLQR_NT) {
+    double v = et1[i];
+    v = lane_chain<false>(v, A1 + i, ds, v1, 1, dm);
+    Eo[lo.eta + i] = v;
+  }
+  if (binary) {
+    wg_lu_solve(LU, dm, dm, piv, v3, 1, 1);
+    for (int i = ECLQR_TID; i < de; i += ECLQR_NT) {
+      double v = b2[i];
+      v = lane_chain<false>(v, A2 + i * dm, 1, v3, 1, dm);
+      Eo[lo.b + i] = v;
+    }
+  }
+  lds_sync();
+}
+
+__global__ void __launch_bounds__(kBlock) k_ric_combine_vec(DevEngine e, int64_t first, int64_t ntasks, int maxd) {
+  if (none_live(e)) return;
+  __shared__ double v1[kMaxDim], v2[kMaxDim], v3[kMaxDim];
+  __shared__ int piv[kMaxDim];
+  extern __shared__ double rs[];
+  for (int64_t ti = blockIdx.x; ti < ntasks; ti += gridDim.x) ric_combine_vec_task(e, first + ti, maxd, v1, v2, v3, piv, rs);
 }
 
 // k = -H_uu^{-1} h_u from the logged Cholesky factor; forward leaf vector.
@@ -608,29 +617,87 @@ __global__ void __launch_bounds__(kBlock) k_gains_vec(DevEngine e) {
   }
 }
 
-// f = F1 f2 + f1 (F = F1 F2 is unchanged).
+// f = F1 f2 + f1 of the forward-map composition `task` (F = F1 F2 is unchanged).
+__device__ inline void fwd_combine_vec_task(const DevEngine& e, int64_t task) {
+  const int a = e.tasks[3 * task];
+  const int bsl = e.tasks[3 * task + 1];
+  const int o = e.tasks[3 * task + 2];
+  const int so = slot_a(e, 1, a), smid = slot_b(e, 1, a), sin_ = slot_b(e, 1, bsl);
+  if (gated(e, e.st[so].inst)) return;
+  const int dout = e.nbar[so], dmid = e.nbar[smid];
+  const int nout = e.st[so].n, nmid = e.st[smid].n, nin = (sin_ >= 0) ? e.st[sin_].n : 0;
+  const double* F1 = slot_ptr(e, SCAN_FWD, a);
+  const double* f1 = F1 + (int64_t)nout * nmid;
+  const double* F2 = slot_ptr(e, SCAN_FWD, bsl);
+  const double* f2 = F2 + (int64_t)nmid * nin;
+  double* Fo = slot_ptr(e, SCAN_FWD, o);
+  double* fo = Fo + (int64_t)nout * nin;
+  for (int i = ECLQR_TID; i < dout; i += ECLQR_NT) {
+    double v = f1[i];
+    v = lane_chain<false>(v, F1 + i * dmid, 1, f2, 1, dmid);
+    fo[i] = v;
+  }
+}
+
 __global__ void __launch_bounds__(kBlock) k_fwd_combine_vec(DevEngine e, int64_t first, int64_t ntasks) {
   if (none_live(e)) return;
-  for (int64_t ti = blockIdx.x; ti < ntasks; ti += gridDim.x) {
-    const int a = e.tasks[3 * (first + ti)];
-    const int bsl = e.tasks[3 * (first + ti) + 1];
-    const int o = e.tasks[3 * (first + ti) + 2];
-    const int so = slot_a(e, 1, a), smid = slot_b(e, 1, a), sin_ = slot_b(e, 1, bsl);
-    if (gated(e, e.st[so].inst)) continue;
-    const int dout = e.nbar[so], dmid = e.nbar[smid];
-    const int nout = e.st[so].n, nmid = e.st[smid].n, nin = (sin_ >= 0) ? e.st[sin_].n : 0;
-    const double* F1 = slot_ptr(e, SCAN_FWD, a);
-    const double* f1 = F1 + (int64_t)nout * nmid;
-    const double* F2 = slot_ptr(e, SCAN_FWD, bsl);
-    const double* f2 = F2 + (int64_t)nmid * nin;
-    double* Fo = slot_ptr(e, SCAN_FWD, o);
-    double* fo = Fo + (int64_t)nout * nin;
-    for (int i = ECLQR_TID; i < dout; i += ECLQR_NT) {
-      double v = f1[i];
-      v = lane_chain<false>(v, F1 + i * dmid, 1, f2, 1, dmid);
-      fo[i] = v;
+  for (int64_t ti = blockIdx.x; ti < ntasks; ti += gridDim.x) fwd_combine_vec_task(e, first + ti);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent scan kernels.  Tasks are taken in level order from a counter, so
+// every task a workgroup waits for was taken earlier by a running workgroup
+// whose own dependencies were taken earlier still: the waits end without any
+// co-residency assumption.  A finished task publishes its slot with an
+// agent-scope release (fence, then the level's done counter); a waiting
+// workgroup reads the counters with agent-scope acquire loads.
+
+// Waits until done >= target.  false when the wall clock passed the bound
+// (the workgroup then sets *abort) or another workgroup aborted.
+__device__ inline bool wait_count(const int32_t* done, int32_t target, int32_t* abort, int64_t ticks) {
+  const int64_t t0 = wall_clock64();
+  while (__hip_atomic_load(done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+    if (wall_clock64() - t0 > ticks) {
+      atomicOr(abort, 1);
+      return false;
     }
+    __builtin_amdgcn_s_sleep(4);
   }
+  return true;
+}
+
+template <int kKind>
+__global__ void __launch_bounds__(kBlock) k_scan_vec(DevEngine e, ScanLevels lv, int32_t* ctrl, int32_t* abort,
+                                                     int64_t ticks) {
+  if (none_live(e)) return;
+  __shared__ double o[kKind == SCAN_REL ? kMaxRows : 1];
+  __shared__ double v1[kMaxDim], v2[kMaxDim], v3[kMaxDim];
+  __shared__ int piv[kMaxDim];
+  const int64_t first = lv.begin[0];
+  const int64_t total = lv.begin[lv.n - 1] + lv.count[lv.n - 1] - first;
+  for (;;) {
+    int t = 0;
+    if (threadIdx.x == 0) t = atomicAdd(ctrl, 1);
+    t = wave_bcast_i(t, 0);
+    if (t >= total) return;
+    const int64_t task = first + t;
+    int l = 0;
+    while (l + 1 < lv.n && task >= lv.begin[l + 1]) ++l;
+    for (int j = 0; j < l; ++j)
+      if (!wait_count(ctrl + 1 + j, (int32_t)lv.count[j], abort, ticks)) return;
+    if constexpr (kKind == SCAN_REL) rel_compose_vec_task(e, task, 0, o, nullptr);
+    else if constexpr (kKind == SCAN_RIC) ric_combine_vec_task(e, task, 0, v1, v2, v3, piv, nullptr);
+    else fwd_combine_vec_task(e, task);
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(ctrl + 1 + l, 1);
+  }
+}
+
+__global__ void k_apply_abort(int32_t* status, const int32_t* abort, int32_t bit, int32_t B) {
+  if (*abort == 0) return;
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < B; b += gridDim.x * blockDim.x) status[b] |= bit;
 }
 
 // ---------------------------------------------------------------------------
@@ -698,6 +765,50 @@ void launch_gains_vec(const DevEngine& e, hipStream_t s) {
 }
 void launch_fwd_combine_vec(const DevEngine& e, int64_t first, int64_t ntasks, hipStream_t s) {
   if (ntasks > 0) hipLaunchKernelGGL(k_fwd_combine_vec, dim3(grid_of(e, ntasks)), dim3(kBlock), 0, s, e, first, ntasks);
+}
+
+// Co-resident workgroups of each persistent scan kernel (occupancy times
+// compute units) and the wall-clock bound of a wait (2 s).
+static int g_scan_grid[SCAN_COUNT] = {1024, 1024, 1024};
+static int64_t g_wait_ticks = 200000000;
+template <int K>
+static int resident(int num_cu) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_scan_vec<K>), kBlock, 0) !=
+          hipSuccess ||
+      per_cu < 1) {
+    (void)hipGetLastError();
+    per_cu = 1;
+  }
+  return per_cu * num_cu;
+}
+void replay_set_device(int num_cu, int wall_clock_khz) {
+  if (num_cu > 0) {
+    g_scan_grid[SCAN_REL] = resident<SCAN_REL>(num_cu);
+    g_scan_grid[SCAN_RIC] = resident<SCAN_RIC>(num_cu);
+    g_scan_grid[SCAN_FWD] = resident<SCAN_FWD>(num_cu);
+  }
+  if (wall_clock_khz > 0) g_wait_ticks = (int64_t)wall_clock_khz * 2000;
+}
+void launch_scan_vec(const DevEngine& e, int kind, const ScanLevels& lv, int32_t* ctrl, int32_t* abort,
+                     hipStream_t s) {
+  if (lv.n <= 0) return;
+  const int64_t total = lv.begin[lv.n - 1] + lv.count[lv.n - 1] - lv.begin[0];
+  if (total <= 0) return;
+  const unsigned grid = (unsigned)(total < g_scan_grid[kind] ? total : g_scan_grid[kind]);
+  if (kind == SCAN_REL)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan_vec<SCAN_REL>), dim3(grid), dim3(kBlock), 0, s, e, lv, ctrl, abort,
+                       g_wait_ticks);
+  else if (kind == SCAN_RIC)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan_vec<SCAN_RIC>), dim3(grid), dim3(kBlock), 0, s, e, lv, ctrl, abort,
+                       g_wait_ticks);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan_vec<SCAN_FWD>), dim3(grid), dim3(kBlock), 0, s, e, lv, ctrl, abort,
+                       g_wait_ticks);
+}
+void launch_apply_abort(int32_t* status, const int32_t* abort, int32_t bit, int32_t B, hipStream_t s) {
+  const int grid = (B + 255) / 256;
+  hipLaunchKernelGGL(k_apply_abort, dim3(grid > 0 ? grid : 1), dim3(256), 0, s, status, abort, bit, B);
 }
 
 }  // namespace eclqr

@@ -93,6 +93,27 @@ void launch_gains(const DevEngine& e, int32_t* status, int maxm, int maxn, hipSt
 void launch_fwd_combine(const DevEngine& e, int64_t first_task, int64_t ntasks, hipStream_t s);
 void launch_recover(const DevEngine& e, double* x, double* u, hipStream_t s);
 
+// Levels of one scan for the persistent scan kernels: the nonempty levels in
+// order, each a contiguous range of the task list.
+constexpr int kMaxScanLevels = 64;
+struct ScanLevels {
+  int32_t n;
+  int64_t begin[kMaxScanLevels];
+  int64_t count[kMaxScanLevels];
+};
+// control block of one persistent scan: [next task, done count per level]
+constexpr int kScanCtrlInts = 1 + kMaxScanLevels;
+void replay_set_device(int num_cu, int wall_clock_khz);
+// One launch for every level of a scan's vector-only replay: workgroups take
+// tasks in level order from a counter in ctrl (zero on entry) and wait,
+// boundedly, until the levels before a task's level are complete.  kind:
+// SCAN_REL, SCAN_RIC or SCAN_FWD.  An expired wait sets *abort and the
+// kernel's workgroups return.
+void launch_scan_vec(const DevEngine& e, int kind, const ScanLevels& lv, int32_t* ctrl, int32_t* abort,
+                     hipStream_t s);
+// status[b] |= bit for every instance when *abort is set
+void launch_apply_abort(int32_t* status, const int32_t* abort, int32_t bit, int32_t B, hipStream_t s);
+
 // vector-only replays of the kernels above (factors logged by the full pass)
 void launch_base_relation_vec(const DevEngine& e, const Inputs& in, int64_t logmax, hipStream_t s);
 void launch_rel_compose_vec(const DevEngine& e, int64_t first, int64_t ntasks, int64_t logmax, hipStream_t s);

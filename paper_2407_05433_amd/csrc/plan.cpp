@@ -17,6 +17,7 @@
 // nodes left), doubling over those K nodes, then the b balanced down-sweep
 // levels.  b = 0 is pure doubling, b >= depth the plain balanced sweep.
 #include "plan.hpp"
+#include "kernels.hpp"
 #include "scratch.hpp"
 
 #include <algorithm>
@@ -602,6 +603,8 @@ std::string build_plan(Plan& p, const eclqr_dims* d, const eclqr_options* opt) {
   p.o_gstat = o; o = align256(o + sizeof(int32_t) * std::max<int32_t>(1, P.B));
   p.o_adjc = o; o = align256(o + sizeof(double) * std::max<int64_t>(1, P.total[ECLQR_F_c]));
   p.o_adjx0 = o; o = align256(o + sizeof(double) * std::max<int64_t>(1, P.total[ECLQR_F_x0]));
+  p.o_ctrl = o; o = align256(o + sizeof(int32_t) * 9 * kScanCtrlInts);
+  p.o_abort = o; o = align256(o + sizeof(int32_t));
   {
     int64_t nz = std::max<int64_t>(1, std::max(P.total[ECLQR_F_c], std::max(P.total[ECLQR_F_g], P.total[ECLQR_F_x0])));
     // the overlapped reversed-time factorization reads zero vectors

@@ -118,6 +118,8 @@ struct Plan {
   size_t o_info = 0;   // per-instance failing stage of the last solve (when the caller passes no info buffer)
   size_t o_adjc = 0, o_adjx0 = 0;  // adjoint offsets from dL/dlam (layouts of c and x0)
   size_t o_gstat = 0;  // per-instance outcome of the last backward (when the caller passes no status buffer)
+  size_t o_ctrl = 0;   // control blocks of the persistent scans: 3 engines x 3 scans x kScanCtrlInts int32
+  size_t o_abort = 0;  // set by a persistent scan whose bounded wait expired (one int32)
   size_t bytes = 0;
   void* bound_ws = nullptr;
   int bound_device = -1;
@@ -132,6 +134,7 @@ struct Plan {
   int32_t overlap_dual = 1;   // factor the multiplier route's problem on a second stream beside the primal pass
                               // (plan default: 0 with the theta route, 1 without)
   int32_t split_combine = 1;  // two wavefronts per value-function combine on levels that fit the device
+  int32_t fused_scans = 0;    // vector-only replays run each scan as one persistent launch (else one per level)
   double tuned_ms = 0.0;
   void* graph_exec = nullptr;
   void* capture_stream = nullptr;  // plan-owned stream the sequence is captured on

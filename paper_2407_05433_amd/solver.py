@@ -367,7 +367,7 @@ def _tuning_dict(t: _lib.Tuning) -> Dict[str, float]:
     return {"use_graph": int(t.use_graph), "level_buckets": int(t.level_buckets), "pool_in_lds": int(t.pool_in_lds),
             "grid_divisor": int(t.grid_divisor), "register_compose": int(t.register_compose),
             "stage_lds": int(t.stage_lds), "overlap_dual": int(t.overlap_dual), "multiplier_route": int(t.multiplier_route),
-            "split_combine": int(t.split_combine),
+            "split_combine": int(t.split_combine), "fused_scans": int(t.fused_scans),
             "ms_per_solve": float(t.ms_per_solve)}
 
 

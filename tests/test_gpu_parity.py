@@ -361,7 +361,7 @@ def test_autotune_keeps_results():
     for cfg in ({"level_buckets": 0}, {"pool_in_lds": 0}, {"pool_in_lds": 1}, {"stage_lds": 0}, {"grid_divisor": 4},
                 {"overlap_dual": 1 - base["overlap_dual"]}, {"multiplier_route": 1 - base["multiplier_route"]},
                 {"multiplier_route": 1 - base["multiplier_route"], "overlap_dual": 1 - base["overlap_dual"]},
-                {"split_combine": 0},
+                {"split_combine": 0}, {"fused_scans": 0},
                 {"use_graph": 1},
                 {"register_compose": 0}, tuned):
         full = dict(base)
@@ -551,3 +551,42 @@ def test_maximum_dims():
     assert outcomes == [0, 0, 0, 0], outcomes
     res = gpu_solve(probs)
     assert [check(res, b, p, b) for b, p in enumerate(probs)] == outcomes
+
+
+@pytest.mark.skip(reason="the persistent scan kernels (fused_scans = 1) did not finish on the MI355X: the run "
+                         "went silent in the autotune test while they replayed refinement steps; the cause is not "
+                         "established (the dependency order is checked on the CPU in test_scan_schedule.py), so "
+                         "the path is off by default and stays off the GPU")
+def test_persistent_scans_equal_per_level_launches():
+    """Refinement steps forced on every instance (accept_tol = 0): the
+    vector-only replays with one persistent launch per scan give the same
+    bits as one launch per level, on a batch of the 512-instance law and on
+    the N=1024 instance, eager and as a replayed graph; no instance reports
+    an expired wait (bit 65536)."""
+    _need_gpu()
+    import paper_2407_05433_amd as ecl
+    from workloads import config_c1, config_c3
+    for probs in (config_c3(B=16, N_range=(32, 200)), config_c1(N=1024)):
+        ref = None
+        for fused, graph in ((0, 0), (1, 0), (1, 1)):
+            plan = ecl.Plan.for_problems(probs, accept_tol=0.0, use_graph=graph)
+            ecl.set_tuning(plan, fused_scans=fused)
+            data = ecl.pack(plan, probs)
+            ws = plan.workspace()
+            sol = ecl.allocate_solution(plan)
+            for _ in range(2 if graph else 1):
+                ecl.solve(plan, data, ws, sol)
+            torch.cuda.synchronize()
+            assert int(sol.status.abs().sum()) == 0, sol.status
+            assert plan.refine_steps(ws).min() >= 1
+            got = {f: getattr(sol, f).clone() for f in ("x", "u", "lam", "mu")}
+            if ref is None:
+                ref = got
+                check_parity(probs, {"status": sol.status.cpu().tolist(),
+                                     "x": ecl.unpack(plan, sol.x, "q", probs), "u": ecl.unpack(plan, sol.u, "r", probs),
+                                     "lam": ecl.unpack(plan, sol.lam, "q", probs),
+                                     "mu": ecl.unpack(plan, sol.mu, "g", probs)},
+                             idx=range(0, len(probs), 5), block_tol=C3_BLOCK_TOL)
+            else:
+                for f in got:
+                    assert torch.equal(got[f], ref[f]), (fused, graph, f)
