@@ -119,7 +119,14 @@ typedef struct {
                            * else the reversed-time problem); 2: factor-reusing route (Section VIII, subsection
                            * "Reference implementation"): one representative from the primal pass's domains
                            * and scans -- equal to route 1 where the multipliers are unique (LICQ), otherwise a
-                           * valid multiplier vector that need not have minimum norm. 1 */
+                           * valid multiplier vector that need not have minimum norm; 3: the contraction-expansion
+                           * route of Section VII: the dual base relations (eq. (dual-base-system)) composed by a
+                           * balanced up-sweep, the minimum-norm lambda_0 of the root relation, the tree expanded
+                           * from the root with each shared costate the minimum-norm solution of its two operand
+                           * relations (eq. (middle-dual-map) with rho_j = 0), then the minimum-norm mu_i of each
+                           * stage's stationarity rows; computed at the refined primal point (the refinement
+                           * itself uses route 1).  Equal to route 1 under LICQ, otherwise another valid
+                           * representative. 1 */
   int32_t refine;         /* most steps of iterative refinement per instance (0..4); 3.  A refined
                            * instance whose final KKT backward error exceeds dual_cons_tol reports
                            * ECLQR_DUAL_FAILED */
@@ -251,6 +258,7 @@ enum {
   ECLQR_K_REPLAY, /* every kernel of a vector-only pass (recovery included) */
   ECLQR_K_MULT_FAST, /* the factor-reusing multiplier route (multipliers = 2) */
   ECLQR_K_MULT_THETA, /* local systems, initial state and read-out of the theta-LQR minimum-norm route */
+  ECLQR_K_MULT_CX,    /* the contraction-expansion multiplier route (multipliers = 3) */
   ECLQR_NUM_KERNEL_CLASSES
 };
 

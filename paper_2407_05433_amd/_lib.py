@@ -14,7 +14,7 @@ NUM_FIELDS = 12
 FIELDS = ("Q", "q", "R", "r", "M", "A", "B", "c", "E", "F", "g", "x0")
 FIELD_INDEX = {f: i for i, f in enumerate(FIELDS)}
 
-NUM_KERNEL_CLASSES = 15
+NUM_KERNEL_CLASSES = 16
 
 STATUS_BITS = {
     1: "infeasible_suffix",

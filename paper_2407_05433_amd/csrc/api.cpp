@@ -200,6 +200,7 @@ eclqr_status bind(Plan& p, void* ws, hipStream_t s) {
     replay_set_max_lds(lds);
     fast_set_max_lds(lds);
     theta_set_max_lds(lds);
+    cx_set_max_lds(lds);
   }
   {
     int lds_cu = 0, ncu = 0;
@@ -219,6 +220,10 @@ eclqr_status bind(Plan& p, void* ws, hipStream_t s) {
   }
   if (p.theta_ok) {
     st = upload_engine(p.theta, ws, p.o_theta_eng, s);
+    if (st != ECLQR_SUCCESS) return st;
+  }
+  if (p.cx_ok) {
+    st = upload_engine(p.cx, ws, p.o_cx_eng, s);
     if (st != ECLQR_SUCCESS) return st;
   }
   launch_fill_i32(reinterpret_cast<int32_t*>(static_cast<char*>(ws) + p.o_live), 1, 1, s);
@@ -387,7 +392,7 @@ Inputs inputs_of(const eclqr_problem* p) {
 
 struct Views {
   void* ws;
-  DevEngine P, D, T;
+  DevEngine P, D, T, C;
   DualPtrs dp;
   CorrPtrs cp;
   double *dx, *du;
@@ -415,6 +420,7 @@ Views views(Plan& p, void* ws) {
   v.P = dev_engine(p.primal, ws, p.o_primal);
   if (p.has_dual) v.D = dev_engine(p.dual, ws, p.o_dual);
   if (p.theta_ok) v.T = dev_engine(p.theta, ws, p.o_theta_eng);
+  if (p.cx_ok) v.C = dev_engine(p.cx, ws, p.o_cx_eng);
   for (int f = 0; f < IN_COUNT; ++f) v.dp.f[f] = at<double>(ws, p.o_dprob[f]);
   v.dp.f[IN_M] = nullptr;
   v.dp.pbase = dev_sbase(p.primal, ws, p.o_primal);
@@ -580,7 +586,9 @@ eclqr_status theta_multipliers(Plan& p, const Views& v, const Inputs& in, const 
   return ECLQR_SUCCESS;
 }
 
-bool theta_route(const Plan& p) { return p.opt.multipliers == 1 && p.theta_ok && p.mult_route == 1; }
+// minimum-norm multipliers (route 1, and route 3 while it refines)
+bool minnorm_route(const Plan& p) { return p.opt.multipliers == 1 || p.opt.multipliers == 3; }
+bool theta_route(const Plan& p) { return minnorm_route(p) && p.theta_ok && p.mult_route == 1; }
 
 // The theta LQR's factorizations on their own (matrix pass of the local
 // systems, value-function scan, gains, forward scan, all with zero vectors),
@@ -769,13 +777,60 @@ eclqr_status dual_prefactor(Plan& p, const Views& v, const Inputs& in, hipStream
   return run_engine(p.dual, d, din, v.dx, v.du, v.dstatus, td, s2);
 }
 
+// Relation-scan launches of levels [l0, l1) of engine E (per bucket, as in
+// the full pass).
+void launch_rel_levels(const Engine& E, const DevEngine& d, Tols t, int32_t* status, int l0, int l1, hipStream_t s) {
+  for (int l = l0; l < l1; ++l) {
+    const int b0 = E.lvl_bkt_first[l], b1 = b0 + E.lvl_bkt_n[l];
+    for (int k = b0; k < b1;) {
+      int k1 = k + 1;
+      if (!g_buckets)
+        while (k1 < b1 && E.bkt_fit[k1] == E.bkt_fit[k]) ++k1;
+      int rows = 1, ldw = 1, kc = 0;
+      for (int q = k; q < k1; ++q) {
+        rows = std::max(rows, E.bkt_rows[q]);
+        ldw = std::max(ldw, E.bkt_ldw[q]);
+        kc = std::max(kc, E.bkt_kc[q]);
+      }
+      const int64_t first = E.bkt_begin[k];
+      const int64_t count = E.bkt_begin[k1 - 1] + E.bkt_count[k1 - 1] - first;
+      if (!E.bkt_fit[k])
+        while (rows > 1 && !rel_fits(d, rows, ldw)) --rows;
+      launch_rel_compose(d, first, count, t, status, rows, ldw, kc, s);
+      k = k1;
+    }
+  }
+}
+
+// Multipliers by the contraction-expansion route at the solution (x, u):
+// dual base relations, balanced up-sweep, root, expansion from the top level
+// down, leaf solves; outcome bits of the route set ECLQR_DUAL_FAILED.
+eclqr_status cx_multipliers(Plan& p, const Views& v, const Inputs& in, const double* x, const double* u, double* lam,
+                            double* mu, int32_t* status, hipStream_t s) {
+  const Engine& C = p.cx;
+  const Tols td{p.opt.rank_tol, p.opt.dual_cons_tol, 0};
+  Timed tm(ECLQR_K_MULT_CX, s);
+  launch_fill_i32(v.dstatus, 0, p.primal.B, s);
+  launch_cx_base(v.C, v.P, v.psbase, in, x, u, td, v.dstatus, p.cx_base_p, p.cx_base_ld, s);
+  launch_rel_levels(C, v.C, td, v.dstatus, 0, C.D, s);
+  launch_cx_root(v.C, v.P, dev_sbase(C, v.ws, p.o_cx_eng), v.psbase, lam, td, std::max(1, C.maxn),
+                 std::max(1, C.maxn), s);
+  for (int l = C.D - 1; l >= 0; --l)
+    launch_cx_expand(v.C, v.P, v.psbase, C.lvl_begin[l], C.lvl_count[l], lam, td, v.dstatus, p.cx_exp_n, p.cx_exp_p,
+                     s);
+  launch_cx_leaf(v.P, in, x, u, lam, mu, td, v.dstatus, p.cx_leaf_q, p.cx_leaf_r, s);
+  launch_merge_status(status, v.dstatus, ECLQR_DUAL_FAILED, p.primal.B, nullptr, 0, s);
+  HIP_OK(hipGetLastError());
+  return ECLQR_SUCCESS;
+}
+
 // The whole launch sequence of one solve.
 eclqr_status solve_sequence(Plan& p, const Views& v, const Inputs& in, eclqr_solution* sol, bool want, hipStream_t s) {
   const Engine& E = p.primal;
   launch_fill_i32(sol->status, 0, E.B, s);
   launch_fill_i32(v.P.info, -1, E.B, s);
   hipEvent_t join = nullptr;
-  if (want && p.opt.multipliers == 1 && !theta_route(p)) {
+  if (want && minnorm_route(p) && !theta_route(p)) {
     if (p.overlap_dual && p.aux_stream) {
       hipStream_t s2 = reinterpret_cast<hipStream_t>(p.aux_stream);
       HIP_OK(hipEventRecord(reinterpret_cast<hipEvent_t>(p.ev_fork), s));
@@ -793,6 +848,10 @@ eclqr_status solve_sequence(Plan& p, const Views& v, const Inputs& in, eclqr_sol
   }
   eclqr_status st = solve_all(p, v, in, sol->x, sol->u, sol->lam, sol->mu, sol->status, want, false, s, join);
   if (st != ECLQR_SUCCESS) return st;
+  if (want && p.opt.multipliers == 3) {
+    st = cx_multipliers(p, v, in, sol->x, sol->u, sol->lam, sol->mu, sol->status, s);
+    if (st != ECLQR_SUCCESS) return st;
+  }
   launch_finalize(v.P, sol->status, sol->x, sol->u, want ? sol->lam : nullptr, want ? sol->mu : nullptr, s);
   HIP_OK(hipGetLastError());
   return ECLQR_SUCCESS;
@@ -890,6 +949,9 @@ eclqr_status solve_impl(eclqr_plan* plan, const eclqr_problem* prob, eclqr_solut
   g_prof = noalloc ? nullptr : &p;
   if (p.opt.multipliers == 2 && mult_local_lds_bytes(p.primal.fast_rows, p.primal.fast_ldw) > (size_t)g_max_lds)
     return fail(ECLQR_UNSUPPORTED, "stage too large for the LDS tile of the factor-reusing multipliers");
+  if (p.opt.multipliers == 3 &&
+      (!p.cx_ok || !cx_fits(p.cx_base_p, p.cx_base_ld, p.cx_exp_n, p.cx_exp_p, p.cx_leaf_q, p.cx_leaf_r)))
+    return fail(ECLQR_UNSUPPORTED, "dims beyond the contraction-expansion route's tiles");
   if (theta_route(p) && theta_local_lds_bytes(p.th_q, p.th_ldw, p.th_r) > (size_t)g_max_lds)
     return fail(ECLQR_UNSUPPORTED, "the device's LDS is smaller than the minimum-norm local systems' tile");
   const int32_t route = want ? (p.opt.multipliers == 2 ? 2 : (theta_route(p) ? 1 : 0)) : -1;
@@ -974,7 +1036,7 @@ eclqr_status eclqr_plan_create(eclqr_plan** out, const eclqr_dims* dims, const e
   if (opt) o = *opt;
   else eclqr_default_options(&o);
   if (!(o.rank_tol > 0) || !(o.cons_tol > 0) || !(o.dual_cons_tol > 0) || !(o.refine_tol >= 0) || !(o.accept_tol >= 0) || o.refine < 0 ||
-      o.refine > 4 || o.multipliers < 0 || o.multipliers > 2 || o.domain_shortcut < 0 || o.domain_shortcut > 1)
+      o.refine > 4 || o.multipliers < 0 || o.multipliers > 3 || o.domain_shortcut < 0 || o.domain_shortcut > 1)
     return fail(ECLQR_INVALID_ARGUMENT, "bad options");
   eclqr_plan* p = new (std::nothrow) eclqr_plan();
   if (!p) return fail(ECLQR_INVALID_ARGUMENT, "out of host memory");
@@ -1144,7 +1206,7 @@ const char* eclqr_kernel_class_name(int32_t k) {
   static const char* names[ECLQR_NUM_KERNEL_CLASSES] = {
       "validate", "base_relation", "rel_compose", "domain", "eliminate", "ric_combine",
       "gains", "fwd_combine", "recover", "multiplier_io", "refine_io", "other", "replay", "multipliers_fast",
-      "multipliers_theta"};
+      "multipliers_theta", "multipliers_cx"};
   return (k >= 0 && k < ECLQR_NUM_KERNEL_CLASSES) ? names[k] : "unknown";
 }
 

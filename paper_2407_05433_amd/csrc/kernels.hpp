@@ -199,6 +199,18 @@ void launch_theta_final(const DevEngine& p, const DevEngine& th, double* lam, do
                         hipStream_t s);
 // gradients of every field from the solution and the adjoint solution; the
 // gradients of an instance whose gstatus is nonzero are NaN
+// contraction-expansion multipliers (c: the engine of the dual relations, p:
+// the problem's engine)
+void cx_set_max_lds(int bytes);
+bool cx_fits(int base_p, int base_ld, int exp_n, int exp_p, int leaf_k, int leaf_r);
+void launch_cx_base(const DevEngine& c, const DevEngine& p, const int64_t* psbase, const Inputs& in, const double* x,
+                    const double* u, Tols t, int32_t* status, int maxp, int ldw, hipStream_t s);
+void launch_cx_root(const DevEngine& c, const DevEngine& p, const int64_t* csbase, const int64_t* psbase, double* lam,
+                    Tols t, int maxn, int maxp, hipStream_t s);
+void launch_cx_expand(const DevEngine& c, const DevEngine& p, const int64_t* psbase, int64_t first, int64_t ntasks,
+                      double* lam, Tols t, int32_t* status, int maxn, int maxp, hipStream_t s);
+void launch_cx_leaf(const DevEngine& p, const Inputs& in, const double* x, const double* u, const double* lam,
+                    double* mu, Tols t, int32_t* status, int maxk, int maxr, hipStream_t s);
 void launch_grad_assemble(const DevEngine& p, const double* x, const double* u, const double* lam, const double* mu,
                           const double* ax, const double* au, const double* al, const double* am, const GradPtrs& g,
                           const int32_t* gstatus, hipStream_t s);

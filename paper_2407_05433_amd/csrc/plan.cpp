@@ -543,7 +543,7 @@ std::string build_plan(Plan& p, const eclqr_dims* d, const eclqr_options* opt) {
 
   // the reversed-time engine: needed when the minimum-norm multipliers have
   // no theta engine, or when the caller asks for both routes
-  p.has_dual = opt->multipliers == 1 && (!p.theta_ok || opt->reversed_time != 0);
+  p.has_dual = (opt->multipliers == 1 || opt->multipliers == 3) && (!p.theta_ok || opt->reversed_time != 0);
   if (!p.has_dual) p.mult_route = 1;
   // Reversed-time stationarity problem (Section VII): stage 0 has an empty
   // state and input mu_N; stage j = 1..N is primal stage i = N - j with state
@@ -567,6 +567,50 @@ std::string build_plan(Plan& p, const eclqr_dims* d, const eclqr_options* opt) {
     if (!err.empty()) return "dual: " + err;
   }
 
+  // contraction-expansion route: engine over (lambda_i) with inputs mu_i
+  p.cx_ok = false;
+  if (opt->multipliers == 3) {
+    std::vector<int32_t> chor(P.B), cnx, cnu, cnc;
+    bool ok = true;
+    for (int b = 0; b < P.B; ++b) {
+      const int Nb = P.N[b];
+      const int64_t s0 = P.sbase[b];
+      chor[b] = Nb + 1;
+      for (int i = 0; i <= Nb; ++i) {
+        const StageInfo& x = P.st[s0 + i];
+        cnx.push_back(x.n);
+        cnu.push_back(x.k);
+        // stacked stationarity rows n_i + m_i, held as n_{i+1} + c_i rows
+        const int rows = x.n + (x.terminal ? 0 : x.m);
+        const int np = x.terminal ? 0 : x.np;
+        cnc.push_back(std::max(0, rows - np));
+        p.cx_base_p = std::max(p.cx_base_p, rows);
+        p.cx_base_ld = std::max(p.cx_base_ld, (x.k + x.n + np + 1) | 1);
+        p.cx_leaf_q = std::max(p.cx_leaf_q, x.k);
+        p.cx_leaf_r = std::max(p.cx_leaf_r, rows);
+        if (std::max(0, rows - np) > kMaxDim) ok = false;
+      }
+      cnx.push_back(0);
+      cnc.push_back(0);
+    }
+    if (ok) {
+      eclqr_dims cd{P.B, chor.data(), cnx.data(), cnu.data(), cnc.data()};
+      p.cx.bal_levels_ = 1 << 30;
+      ok = p.cx.build(&cd).empty();
+    }
+    if (ok) {
+      const Engine& C = p.cx;
+      for (int l = 0; l < C.D; ++l)
+        for (int64_t t = C.lvl_begin[l]; t < C.lvl_begin[l] + C.lvl_count[l]; ++t) {
+          const int a = C.tasks[3 * t], c = C.tasks[3 * t + 1];
+          const int b = C.slot_inst[a];
+          p.cx_exp_p = std::max(p.cx_exp_p, C.slot_cap[a] + C.slot_cap[c]);
+          p.cx_exp_n = std::max(p.cx_exp_n, C.st[C.sbase[b] + C.slot_e[a]].n);
+        }
+    }
+    p.cx_ok = ok;
+  }
+
   size_t o = 0;
   p.o_primal = o; o = align256(o + p.primal.bytes);
   p.o_dual = o; o = align256(o + p.dual.bytes);
@@ -577,6 +621,10 @@ std::string build_plan(Plan& p, const eclqr_dims* d, const eclqr_options* opt) {
     for (int64_t c : p.theta.lvl_count) widest = std::max(widest, c);
     p.o_defer = o;
     o = align256(o + sizeof(int32_t) * (2 * (int64_t)p.theta.D + 4 + widest));
+  }
+  if (p.cx_ok) {
+    p.o_cx_eng = o;
+    o = align256(o + p.cx.bytes);
   }
   for (int f = 0; f < ECLQR_NUM_FIELDS; ++f) {
     p.o_dprob[f] = o;

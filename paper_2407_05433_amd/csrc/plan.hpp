@@ -86,6 +86,17 @@ struct Plan {
   // used then.
   Engine theta;
   bool theta_ok = false;
+  // The contraction-expansion multiplier route (multipliers = 3): the dual
+  // base relations over (lambda_i, lambda_{i+1}) composed by a balanced
+  // up-sweep, then expanded from the root.  Its engine has the problem's
+  // state dims, input dims k_i (the eliminated mu_i), and one more stage of
+  // dimension zero so that the terminal relation has a right endpoint.
+  Engine cx;
+  bool cx_ok = false;
+  size_t o_cx_eng = 0;
+  int32_t cx_base_p = 1, cx_base_ld = 1;  // LDS tile of the dual base relations
+  int32_t cx_exp_p = 1, cx_exp_n = 1;     // stacked operand rows and middle dim of an expansion step
+  int32_t cx_leaf_q = 1, cx_leaf_r = 1;   // leaf systems: mu dims x stationarity rows
   bool has_dual = false;      // the reversed-time engine is in the workspace
   size_t o_theta_eng = 0;
   size_t o_defer = 0;         // per level: count of deferred combines (2 D ints), then one task list

@@ -47,7 +47,7 @@ def test_status_strings_and_defaults():
 
 def test_plan_rejects_bad_options():
     dims = [([3, 3, 3], [2, 2], [1, 1, 0])]
-    for bad in ({"domain_shortcut": 2}, {"domain_shortcut": -1}, {"multipliers": 3}, {"refine": 5},
+    for bad in ({"domain_shortcut": 2}, {"domain_shortcut": -1}, {"multipliers": 4}, {"refine": 5},
                 {"scan_schedule": 3}):
         with pytest.raises(ecl.EclqrError):
             ecl.Plan(dims, **bad)
@@ -253,3 +253,14 @@ def test_ctypes_structs_follow_the_header():
     assert [f for f, _ in _lib.SolutionPtrs._fields_] == fields("eclqr_solution")
     assert [f for f, _ in _lib.CotangentPtrs._fields_] == fields("eclqr_cotangent")
     assert [f for f, _ in _lib.GradPtrs._fields_] == fields("eclqr_grads")
+
+
+def test_contraction_expansion_option():
+    """multipliers = 3 (the contraction-expansion route) is accepted and
+    lays out its engine; 4 is refused."""
+    dims = [([3, 3, 3, 3], [2, 2, 2], [1, 0, 1, 1])]
+    p3 = ecl.Plan(dims, multipliers=3)
+    p1 = ecl.Plan(dims, multipliers=1)
+    assert p3.workspace_bytes > p1.workspace_bytes
+    with pytest.raises(ecl.EclqrError):
+        ecl.Plan(dims, multipliers=4)
