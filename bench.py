@@ -54,6 +54,9 @@ WORKLOADS = {
     "c4": "differentiable: 256 instances, N=128, n=16, m=8, 3 mixed rows/stage",
     "paper": "paper Table I shape: 1 instance, N=8192, n=8, m=4, 2 state rows/stage",
 }
+MPC_WORKLOAD = ("bounded: 256 instances, N=128, n=16, m=8, 3 mixed rows/stage, inputs boxed at +-0.5 around a "
+                "feasible trajectory; Mehrotra predictor-corrector, 25 iterations")
+IPM_ITER = 25
 
 
 def log(*a):
@@ -261,6 +264,58 @@ def differentiable(ecl, torch, steps):
     return res
 
 
+def interior_point(ecl, torch, steps):
+    """The interior-point driver on the bounded batch: one step is a whole
+    bound-constrained solve (start solve + IPM_ITER predictor-corrector
+    iterations, each a full solve and a factor-replaying solve of the
+    256-instance Newton problem), one captured graph per iteration.  Reports
+    the converged fraction and the optimality conditions of instance 0
+    (evaluated by the oracle's residual function on the device result)."""
+    from workloads import config_mpc
+    problems = config_mpc()
+    bounds = [p.meta["bounds"] for p in problems]
+    plan = ecl.Plan.for_problems(problems)
+    plan.set_graph(True)
+    data = ecl.pack(plan, problems)
+    bd = ecl.pack_bounds(plan, problems, bounds)
+    ws = ecl.ipm_workspace(plan)
+    sol = ecl.ipm_solve(plan, data, bd, ws, iterations=IPM_ITER)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ecl.ipm_solve(plan, data, bd, ws, sol, iterations=IPM_ITER)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    stages = sum(p.N + 1 for p in problems)
+    st, it, comp = sol.status.cpu().numpy(), sol.steps.cpu().numpy(), sol.comp.cpu().numpy()
+    res = {"workload": "mpc: " + MPC_WORKLOAD, "ms_per_solve": ms, "ms_per_iteration": ms / IPM_ITER,
+           "newton_stage_solves_per_s": 2 * IPM_ITER * stages / (ms * 1e-3),
+           "converged_fraction": float(np.mean((st == 0) & (comp < 1e-8))),
+           "iterations_taken": [int(it.min()), int(it.max())], "status_ok": bool((st == 0).all())}
+    plan.set_graph(False)
+    plan.set_profiling(True)
+    plan.profile(reset=True)
+    ecl.ipm_solve(plan, data, bd, ws, sol, iterations=IPM_ITER)
+    torch.cuda.synchronize()
+    prof = plan.profile(reset=True)
+    plan.set_profiling(False)
+    res["kernel_ms_per_solve"] = {k: round(v[0], 4) for k, v in prof.items() if v[1] > 0}
+    try:
+        from oracle.ipm import bound_kkt_residual
+        p = problems[0]
+        got = {f: ecl.unpack(plan, getattr(sol, f), fl, [p])[0]
+               for f, fl in (("x", "q"), ("u", "r"), ("lam", "q"), ("mu", "g"), ("z_ulo", "r"), ("z_uhi", "r"),
+                             ("z_xlo", "q"), ("z_xhi", "q"))}
+        got["z_u"] = list(zip(got["z_ulo"], got["z_uhi"]))
+        got["z_x"] = list(zip(got["z_xlo"], got["z_xhi"]))
+        res["kkt_instance0"] = bound_kkt_residual(p, bounds[0], got)
+    except Exception as ex:  # a report, not part of the timing
+        res["kkt_instance0"] = {"error": repr(ex)}
+    del ws, sol
+    torch.cuda.empty_cache()
+    return res
+
+
 def stored_traffic(kernel_class, workload):
     """HBM bytes per launch of `kernel_class` on `workload` from a committed
     rocprofv3 --pmc summary under profiles/ (FETCH_SIZE and WRITE_SIZE runs,
@@ -430,6 +485,9 @@ def main():
         log("[bench] secondary: c4 forward + backward")
         sec["c4_fwd_bwd"] = differentiable(ecl, torch, max(2, min(args.steps, 5)))
         log(f"[bench]   {sec['c4_fwd_bwd']}")
+        log("[bench] secondary: bounded batch, interior-point driver")
+        sec["mpc_ipm"] = interior_point(ecl, torch, max(2, min(args.steps, 5)))
+        log(f"[bench]   {sec['mpc_ipm']}")
         line["secondary"] = sec
     if cpu is not None:
         line["cpu_baseline"] = cpu

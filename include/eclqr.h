@@ -109,10 +109,10 @@ typedef struct {
   double cons_tol;        /* 0 = gamma accepted if |gamma| <= cons_tol*max(1,|offsets|); 1e-8 */
   double dual_cons_tol;   /* same test inside the multiplier solve; 1e-6 */
   double refine_tol;      /* an instance stops refining once ||correction|| <= refine_tol*||(x,u)||; 1e-8 */
-  double accept_tol;      /* an instance whose componentwise KKT backward error after the first solve is
-                           * <= accept_tol takes no refinement step; 1e-10 (0: always refine).  Measured on
-                           * every workload, the first pass's relative error against the exact solution is
-                           * at most about 0.7 times this backward error */
+  double accept_tol;      /* an instance whose KKT backward error (see eclqr_plan_backward_error) after the
+                           * first solve is <= accept_tol takes no refinement step; 1e-10 (0: always refine).
+                           * Measured on every workload, the first pass's relative error against the exact
+                           * solution is at most about 0.7 times this backward error */
   int32_t multipliers;    /* 0: primal only; 1: lam and mu as the minimum-norm solution of the stationarity
                            * equations of Section VII (computed as the tuning field multiplier_route selects:
                            * by default the theta LQR over the normal coordinates of the feasible domains,
@@ -250,6 +250,93 @@ eclqr_status eclqr_backward(eclqr_plan* plan, const eclqr_problem* prob, const e
 eclqr_status eclqr_kkt_residual(eclqr_plan* plan, const eclqr_problem* prob, const eclqr_solution* sol,
                                 double* out, void* ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Interior-point driver for bound-constrained problems.  Section I motivates
+ * the method by interior-point and SQP solvers, which solve a sequence of
+ * equality-constrained LQR problems of fixed structure whose cost weights
+ * change; this driver is that use, on the GPU: the problem above plus bounds
+ *   lo <= u_i <= hi (i < N),   lo <= x_i <= hi (1 <= i <= N),
+ * solved by Mehrotra's predictor-corrector primal-dual method (SIAM J. Optim.
+ * 2(4), 1992).  With bound multipliers z_lo, z_hi >= 0, distances
+ * d_lo = v - lo, d_hi = hi - v and complementarity targets t_lo, t_hi, each
+ * linear system of the method is the equality-constrained LQR problem with
+ *   Q_i + diag(z_lo/d_lo + z_hi/d_hi),  R_i likewise,
+ *   q_i = grad_x f - t_lo/d_lo + t_hi/d_hi,  r_i likewise,
+ *   c_i = A_i x_i + B_i u_i + c_i - x_{i+1},  g_i = E_i x_i + F_i u_i + g_i,
+ *   x0 = x0 - x_0
+ * at the current iterate (M, A, B, E, F unchanged); its solution is the step
+ * and its multipliers the new equality multipliers.  Per iteration and
+ * instance, with mu the mean complementarity product: the predictor (targets
+ * 0) is a full solve; sigma = min(1, (mu_aff/mu)^3) from the complementarity
+ * after its largest feasible step; the corrector (targets sigma mu minus the
+ * predictor's second-order term) has the same matrices and replays the
+ * predictor's factorizations; the step is the largest <= 1 that keeps the
+ * iterate strictly inside the bounds and z positive (fraction tau to the
+ * boundary).  An instance stops once its mu is below mu_stop.  The start
+ * point is the equality-constrained solution moved inside the bounds.
+ * --------------------------------------------------------------------------- */
+
+/* Device bound arrays (NULL = no bound on that side; an infinite entry is an
+ * absent bound).  u_lo, u_hi: layout of r; x_lo, x_hi: layout of q (the block
+ * of x_0 is ignored: x_0 = x0 is fixed).  Where both sides are finite lo < hi
+ * is required (a fixed variable belongs in the equality rows); an instance
+ * with lo >= hi or a NaN bound gets ECLQR_INVALID_INPUT. */
+typedef struct {
+  const double *u_lo, *u_hi, *x_lo, *x_hi;
+} eclqr_bounds;
+
+/* Method parameters (eclqr_ipm_default_params: 30, 1e-8, 0.995, 100, 0.25, 1). */
+typedef struct {
+  int32_t iterations; /* predictor-corrector iterations at most (every instance is solved in each; >= 0) */
+  double mu_stop;     /* an instance stops once its mean complementarity is below this (the Newton
+                       * matrices' diagonal grows like z^2 / mu: much below 1e-8 their factorizations lose
+                       * the accuracy the refinement needs) */
+  double tau;         /* fraction to the boundary, in (0, 1) */
+  double mu0;         /* initial z = mu0 / (distance to the bound), > 0 */
+  double interior;    /* start point: at least this fraction of a two-sided gap (one-sided: of
+                       * max(1, |bound|)) inside each finite bound, in (0, 0.5) */
+  int32_t corrector_replay; /* 1: the corrector replays the predictor's factorizations (its matrices are
+                             * the same); 0: the corrector is a full solve */
+} eclqr_ipm_params;
+
+/* Device outputs: the last iterate of each instance. */
+typedef struct {
+  double *x, *u, *lam, *mu;   /* layouts of q, r, q, g (lam, mu: equality multipliers, as eclqr_solution) */
+  double *z_ulo, *z_uhi;      /* bound multipliers of the inputs, layout of r */
+  double *z_xlo, *z_xhi;      /* bound multipliers of the states, layout of q (zero on the block of x_0) */
+  double* comp;               /* [batch] mean complementarity at the returned iterate, or NULL */
+  int32_t* steps;             /* [batch] iterations the instance took, or NULL */
+  int32_t* status;            /* [batch]: the start solve's outcome bits, ECLQR_INVALID_INPUT for bad bounds,
+                               * or the bits of the first predictor or corrector solve that failed (the
+                               * instance stops there and keeps its last iterate).  A Newton solve whose
+                               * refinement stops above dual_cons_tol is not a failure: its inexact step is
+                               * taken */
+} eclqr_ipm_solution;
+
+void eclqr_ipm_default_params(eclqr_ipm_params* prm);
+
+/* Bytes of device workspace eclqr_ipm_solve needs (the plan's solve
+ * workspace plus the Newton problem's data, the predictor's and corrector's
+ * solutions and the driver's per-instance state); 256-byte aligned by the
+ * caller. */
+eclqr_status eclqr_ipm_workspace_size(const eclqr_plan* plan, size_t* bytes);
+
+/* Runs the start solve and up to prm->iterations predictor-corrector
+ * iterations, all enqueued on `stream` (no synchronisation; every iteration
+ * solves the whole batch, the stopped instances' results unused).  The
+ * Newton problems live at fixed addresses in ws, so with use_graph one
+ * iteration is captured once (per set of pointers and parameters) and
+ * replayed.  Requires a plan with multipliers 1, 2 or 3 (the Newton
+ * multipliers are the equality multipliers' update; with 3 the corrector's
+ * multipliers come from the minimum-norm route, equal where they are
+ * unique).  Errors: INVALID_ARGUMENT for NULL pointers, a plan without
+ * multipliers or bad parameters, WORKSPACE_TOO_SMALL, and the errors of
+ * eclqr_solve.  After this call ws holds Newton factorizations, not a solve
+ * of prob: eclqr_backward cannot follow it. */
+eclqr_status eclqr_ipm_solve(eclqr_plan* plan, const eclqr_problem* prob, const eclqr_bounds* bounds,
+                             const eclqr_ipm_params* prm, eclqr_ipm_solution* sol, void* ws, size_t ws_bytes,
+                             void* stream);
+
 /* Kernel classes timed by the optional profiler. */
 enum {
   ECLQR_K_VALIDATE = 0, ECLQR_K_BASE_RELATION, ECLQR_K_REL_COMPOSE, ECLQR_K_DOMAIN, ECLQR_K_ELIMINATE,
@@ -259,6 +346,7 @@ enum {
   ECLQR_K_MULT_FAST, /* the factor-reusing multiplier route (multipliers = 2) */
   ECLQR_K_MULT_THETA, /* local systems, initial state and read-out of the theta-LQR minimum-norm route */
   ECLQR_K_MULT_CX,    /* the contraction-expansion multiplier route (multipliers = 3) */
+  ECLQR_K_IPM,        /* the interior-point driver's own kernels (Newton data, step, complementarity) */
   ECLQR_NUM_KERNEL_CLASSES
 };
 
@@ -341,10 +429,15 @@ eclqr_status eclqr_plan_reduced_dims(const eclqr_plan* plan, const void* ws, int
  * batch entries).  Synchronises the device. */
 eclqr_status eclqr_plan_refine_steps(const eclqr_plan* plan, const void* ws, int32_t* steps);
 
-/* Componentwise KKT backward error of each instance at the point returned by
- * the last eclqr_solve (or eclqr_backward, for the adjoint) in ws: max over
- * rows of |residual| / sum |terms| (host array of batch entries; 0 when
- * refine = 0).  Synchronises. */
+/* KKT backward error of each instance at the point returned by the last
+ * eclqr_solve (or eclqr_backward, for the adjoint) in ws: the max over rows
+ * of |residual| / sum |terms| (componentwise), except on rows where that sum
+ * is below 1000 * (terms) * eps times the row's normwise scale
+ * ||coefficients||_1 * max|unknowns| + |offset|, which take the normwise scale
+ * as denominator (Arioli, Demmel and Duff's two-category backward error; a
+ * row whose data and solution are of rounding size would otherwise count as
+ * inaccurate).  Host array of batch entries; 0 when refine = 0.
+ * Synchronises. */
 eclqr_status eclqr_plan_backward_error(const eclqr_plan* plan, const void* ws, double* omega);
 
 /* Row counts of every slot of the feasible-domain scan after the last solve

@@ -5,27 +5,38 @@ The paper's motivation (Section I) is that interior-point and SQP methods
 solve a sequence of equality-constrained LQR problems with the same
 structure and new diagonal weights.  This module states that use plainly:
 eq. (problem) plus bounds lo <= u_i <= hi on the inputs and lo <= x_i <= hi
-on the states after x_0 (an infinite bound is absent), solved by a
-primal-dual path-following method whose Newton step is one such LQR,
-solved by the oracle's sequential method with minimum-norm multipliers.
+on the states after x_0 (an infinite bound is absent), solved by Mehrotra's
+predictor-corrector primal-dual method (S. Mehrotra, "On the implementation
+of a primal-dual interior point method", SIAM J. Optim. 2(4), 1992), whose
+two linear systems per iteration are each one such LQR, solved by the
+oracle's sequential method with minimum-norm multipliers.
 
-With bound multipliers z_lo, z_hi >= 0 and barrier target sigma * mu,
-eliminating dz from the linearised optimality conditions
+With bound multipliers z_lo, z_hi >= 0, d_lo = w - lo, d_hi = hi - w and
+per-bound complementarity targets t_lo, t_hi, eliminating dz from the
+linearised optimality conditions
     grad f(w) + J' nu - z_lo + z_hi = 0,  c(w) = 0,
-    z_lo (w - lo) = sigma mu,  z_hi (hi - w) = sigma mu
+    z_lo d_lo = t_lo,  z_hi d_hi = t_hi
 gives, for the step dw and the new equality multipliers nu+, the
 equality-constrained quadratic problem
     min 1/2 dw' (H + S) dw + g' dw   s.t.  J dw + c(w) = 0,
-    S = diag(z_lo / (w - lo) + z_hi / (hi - w)),
-    g = grad f(w) - sigma mu / (w - lo) + sigma mu / (hi - w),
+    S = diag(z_lo / d_lo + z_hi / d_hi),
+    g = grad f(w) - t_lo / d_lo + t_hi / d_hi,
 whose multipliers are nu+; then
-    dz_lo = sigma mu / (w - lo) - z_lo - (z_lo / (w - lo)) dw,
-    dz_hi = sigma mu / (hi - w) - z_hi + (z_hi / (hi - w)) dw.
-Every instance takes the largest step alpha <= 1 that keeps w strictly
-inside the bounds and z positive (fraction to the boundary tau); mu is the
-mean complementarity product of the instance.  At most a fixed number of
-iterations is taken (the device driver runs the same count); an instance
-stops once its mean complementarity is below MU_STOP.
+    dz_lo = t_lo / d_lo - z_lo - (z_lo / d_lo) dw,
+    dz_hi = t_hi / d_hi - z_hi + (z_hi / d_hi) dw.
+One iteration, with mu the instance's mean complementarity product:
+  1. predictor: targets 0; its largest step a_aff <= 1 keeping d and z
+     non-negative, and mu_aff, the mean complementarity after that step;
+  2. sigma = min(1, (mu_aff / mu)^3);
+  3. corrector: the same matrices with targets
+         t_lo = sigma mu - dz_lo_aff dw_aff,  t_hi = sigma mu + dz_hi_aff dw_aff
+     (the second-order term of the complementarity products);
+  4. step a = min(1, tau * largest step keeping d and z non-negative) for
+     (w, z), and nu <- nu + a (nu+ - nu).
+The start point is the equality-constrained solution moved inside the
+bounds with z = MU0 / distance.  At most a fixed number of iterations is
+taken (the device driver runs the same count); an instance stops once its
+mean complementarity is below MU_STOP.
 """
 
 from __future__ import annotations
@@ -36,11 +47,10 @@ import numpy as np
 
 from .multipliers import objective_gradients, solve_with_multipliers
 
-SIGMA = 0.1
 TAU = 0.995
-MU0 = 1.0
-MU_STOP = 1e-10  # an instance stops once its mean complementarity is below this
-INTERIOR = 0.05  # initial point: at least this fraction of the bound gap inside
+MU0 = 100.0
+MU_STOP = 1e-8  # an instance stops once its mean complementarity is below this
+INTERIOR = 0.25  # initial point: at least this fraction of the bound gap inside
 
 
 def _blocks(prob, bounds):
@@ -55,113 +65,145 @@ def _blocks(prob, bounds):
     return [np.asarray(v, float) for v in ulo], [np.asarray(v, float) for v in uhi], xlo, xhi
 
 
-def _interior(v, lo, hi):
-    """Move v inside [lo, hi]: at least INTERIOR of the gap (two-sided) or
-    INTERIOR * max(1, |bound|) (one-sided) from each finite bound."""
+def _interior(v, lo, hi, frac=INTERIOR):
+    """Move v inside [lo, hi]: at least frac of the gap (two-sided) or
+    frac * max(1, |bound|) (one-sided) from each finite bound."""
     v = np.array(v, float)
     two = np.isfinite(lo) & np.isfinite(hi)
     gap = np.where(two, hi - lo, 0.0)
-    off_lo = np.where(two, INTERIOR * gap, INTERIOR * np.maximum(1.0, np.abs(np.where(np.isfinite(lo), lo, 0.0))))
-    off_hi = np.where(two, INTERIOR * gap, INTERIOR * np.maximum(1.0, np.abs(np.where(np.isfinite(hi), hi, 0.0))))
+    off_lo = np.where(two, frac * gap, frac * np.maximum(1.0, np.abs(np.where(np.isfinite(lo), lo, 0.0))))
+    off_hi = np.where(two, frac * gap, frac * np.maximum(1.0, np.abs(np.where(np.isfinite(hi), hi, 0.0))))
     v = np.where(np.isfinite(lo), np.maximum(v, lo + off_lo), v)
     v = np.where(np.isfinite(hi), np.minimum(v, hi - off_hi), v)
     return v
 
 
-def ipm_solve(prob, bounds: Dict[str, Optional[List[np.ndarray]]], iterations: int = 30) -> Dict:
-    """Returns x, u, lam, mu (equality multipliers), z (bound multipliers per
-    block: u_lo, u_hi, x_lo, x_hi), mu_history (mean complementarity per
-    iteration) and the Newton LQR status of each iteration."""
+class _Var:
+    """One block of bounded variables (u_i or x_i) with its bounds and bound
+    multipliers; absent bounds are masked out of every product."""
+
+    def __init__(self, v, lo, hi):
+        self.v, self.lo, self.hi = v, lo, hi
+        self.fl, self.fh = np.isfinite(lo), np.isfinite(hi)
+        self.zl = np.zeros_like(v)
+        self.zh = np.zeros_like(v)
+
+    def gaps(self, v=None):
+        v = self.v if v is None else v
+        return np.where(self.fl, v - np.where(self.fl, self.lo, 0.0), 1.0), \
+            np.where(self.fh, np.where(self.fh, self.hi, 0.0) - v, 1.0)
+
+    def products(self):
+        dl, dh = self.gaps()
+        return float(np.sum((self.zl * dl)[self.fl]) + np.sum((self.zh * dh)[self.fh])), \
+            int(self.fl.sum() + self.fh.sum())
+
+    def newton_terms(self, tl, th):
+        """Diagonal S and the barrier part of the linear term for targets tl, th."""
+        dl, dh = self.gaps()
+        S = np.where(self.fl, self.zl / dl, 0.0) + np.where(self.fh, self.zh / dh, 0.0)
+        gb = np.where(self.fl, -tl / dl, 0.0) + np.where(self.fh, th / dh, 0.0)
+        return S, gb
+
+    def dz(self, dv, tl, th):
+        dl, dh = self.gaps()
+        return (np.where(self.fl, tl / dl - self.zl - self.zl / dl * dv, 0.0),
+                np.where(self.fh, th / dh - self.zh + self.zh / dh * dv, 0.0))
+
+    def max_step(self, dv, dzl, dzh):
+        """Largest a with v + a dv inside the bounds and z + a dz >= 0 (inf if none binds)."""
+        dl, dh = self.gaps()
+        a = np.inf
+        for ok, num, den in ((self.fl & (dv < 0), dl, -dv), (self.fh & (dv > 0), dh, dv),
+                             (self.fl & (dzl < 0), self.zl, -dzl), (self.fh & (dzh < 0), self.zh, -dzh)):
+            if np.any(ok):
+                a = min(a, float(np.min(num[ok] / den[ok])))
+        return a
+
+    def products_after(self, a, dv, dzl, dzh):
+        dl, dh = self.gaps(self.v + a * dv)
+        return float(np.sum(((self.zl + a * dzl) * dl)[self.fl]) + np.sum(((self.zh + a * dzh) * dh)[self.fh]))
+
+
+def ipm_solve(prob, bounds: Dict[str, Optional[List[np.ndarray]]], iterations: int = 30, mu_stop: float = MU_STOP,
+              tau: float = TAU, mu0: float = MU0, interior: float = INTERIOR) -> Dict:
+    """Returns x, u, lam, mu (equality multipliers), z_u, z_x (bound
+    multipliers per block: (lower, upper)), mu_history (mean complementarity
+    at the start of each iteration) and steps (Newton iterations taken)."""
     N = prob.N
     ulo, uhi, xlo, xhi = _blocks(prob, bounds)
     start = solve_with_multipliers(prob)
     if start["status"] != "ok":
         return {"status": "start_" + start["status"]}
-    x = [v.copy() for v in start["x"]]
-    u = [_interior(start["u"][i], ulo[i], uhi[i]) for i in range(N)]
-    x = [x[0]] + [_interior(x[i], xlo[i], xhi[i]) for i in range(1, N + 1)]
+    U = [_Var(_interior(start["u"][i], ulo[i], uhi[i], interior), ulo[i], uhi[i]) for i in range(N)]
+    X = [_Var(np.array(start["x"][0], float), xlo[0], xhi[0])] + \
+        [_Var(_interior(start["x"][i], xlo[i], xhi[i], interior), xlo[i], xhi[i]) for i in range(1, N + 1)]
+    blocks = U + X  # u_0..u_{N-1}, x_0..x_N
+    for b in blocks:
+        dl, dh = b.gaps()
+        b.zl = np.where(b.fl, mu0 / dl, 0.0)
+        b.zh = np.where(b.fh, mu0 / dh, 0.0)
     lam = [v.copy() for v in start["lam"]]
     mu = [v.copy() for v in start["mu"]]
+    hist: List[float] = []
+    steps = 0
 
-    def zinit(v, lo, hi):
-        zl = np.where(np.isfinite(lo), MU0 / np.where(np.isfinite(lo), v - lo, 1.0), 0.0)
-        zh = np.where(np.isfinite(hi), MU0 / np.where(np.isfinite(hi), hi - v, 1.0), 0.0)
-        return zl, zh
-
-    zu = [zinit(u[i], ulo[i], uhi[i]) for i in range(N)]
-    zx = [zinit(x[i], xlo[i], xhi[i]) for i in range(N + 1)]
-    hist = []
-    for _ in range(iterations):
-        # mean complementarity over the finite bounds
-        prods, count = 0.0, 0
-        for v, lo, hi, (zl, zh) in [(u[i], ulo[i], uhi[i], zu[i]) for i in range(N)] + \
-                                   [(x[i], xlo[i], xhi[i], zx[i]) for i in range(N + 1)]:
-            fl, fh = np.isfinite(lo), np.isfinite(hi)
-            prods += float(np.sum(zl[fl] * (v - lo)[fl]) + np.sum(zh[fh] * (hi - v)[fh]))
-            count += int(fl.sum() + fh.sum())
-        mu_b = prods / max(count, 1)
-        hist.append(mu_b)
-        if mu_b < MU_STOP:
-            break
-        target = SIGMA * mu_b
+    def newton(targets):
+        x = [b.v for b in X]
+        u = [b.v for b in U]
         gx, gu = objective_gradients(prob, x, u)
-
-        def weights(v, lo, hi, zl, zh):
-            fl, fh = np.isfinite(lo), np.isfinite(hi)
-            dl = np.where(fl, v - lo, 1.0)
-            dh = np.where(fh, hi - v, 1.0)
-            S = np.where(fl, zl / dl, 0.0) + np.where(fh, zh / dh, 0.0)
-            gb = np.where(fl, -target / dl, 0.0) + np.where(fh, target / dh, 0.0)
-            return S, gb
-
-        newton = prob.copy()
+        nw = prob.copy()
         for i in range(N):
-            S, gb = weights(u[i], ulo[i], uhi[i], *zu[i])
-            newton.R[i] = prob.R[i] + np.diag(S)
-            newton.r[i] = gu[i] + gb
-            newton.c[i] = prob.A[i] @ x[i] + prob.B[i] @ u[i] + prob.c[i] - x[i + 1]
-            newton.g[i] = prob.E[i] @ x[i] + prob.F[i] @ u[i] + prob.g[i]
+            S, gb = U[i].newton_terms(*targets[i])
+            nw.R[i] = prob.R[i] + np.diag(S)
+            nw.r[i] = gu[i] + gb
+            nw.c[i] = prob.A[i] @ x[i] + prob.B[i] @ u[i] + prob.c[i] - x[i + 1]
+            nw.g[i] = prob.E[i] @ x[i] + prob.F[i] @ u[i] + prob.g[i]
         for i in range(N + 1):
-            S, gb = weights(x[i], xlo[i], xhi[i], *zx[i])
-            newton.Q[i] = prob.Q[i] + np.diag(S)
-            newton.q[i] = gx[i] + gb
-        newton.g[N] = prob.E[N] @ x[N] + prob.g[N]
-        newton.x0 = prob.x0 - x[0]
-        st = solve_with_multipliers(newton)
-        if st["status"] != "ok":
-            return {"status": "newton_" + st["status"], "mu_history": hist}
-        dx, du = st["x"], st["u"]
+            S, gb = X[i].newton_terms(*targets[N + i])
+            nw.Q[i] = prob.Q[i] + np.diag(S)
+            nw.q[i] = gx[i] + gb
+        nw.g[N] = prob.E[N] @ x[N] + prob.g[N]
+        nw.x0 = prob.x0 - x[0]
+        return solve_with_multipliers(nw)
 
-        def dz(v, lo, hi, zl, zh, dv):
-            fl, fh = np.isfinite(lo), np.isfinite(hi)
-            dl = np.where(fl, v - lo, 1.0)
-            dh = np.where(fh, hi - v, 1.0)
-            dzl = np.where(fl, target / dl - zl - zl / dl * dv, 0.0)
-            dzh = np.where(fh, target / dh - zh + zh / dh * dv, 0.0)
-            return dzl, dzh
-
-        alpha = 1.0
-        steps = []
-        for v, lo, hi, (zl, zh), dv in [(u[i], ulo[i], uhi[i], zu[i], du[i]) for i in range(N)] + \
-                                       [(x[i], xlo[i], xhi[i], zx[i], dx[i]) for i in range(N + 1)]:
-            dzl, dzh = dz(v, lo, hi, zl, zh, dv)
-            steps.append((dzl, dzh))
-            fl, fh = np.isfinite(lo), np.isfinite(hi)
-            for ok, num, den in ((fl & (dv < 0), v - lo, -dv), (fh & (dv > 0), hi - v, dv),
-                                 (fl & (dzl < 0), zl, -dzl), (fh & (dzh < 0), zh, -dzh)):
-                if np.any(ok):
-                    alpha = min(alpha, TAU * float(np.min(num[ok] / den[ok])))
-        for i in range(N):
-            u[i] = u[i] + alpha * du[i]
-            zu[i] = (zu[i][0] + alpha * steps[i][0], zu[i][1] + alpha * steps[i][1])
-        for i in range(N + 1):
-            x[i] = x[i] + alpha * dx[i]
-            zx[i] = (zx[i][0] + alpha * steps[N + i][0], zx[i][1] + alpha * steps[N + i][1])
-        lam = [a + alpha * (b - a) for a, b in zip(lam, st["lam"])]
-        mu = [a + alpha * (b - a) for a, b in zip(mu, st["mu"])]
-    return {"status": "ok", "x": x, "u": u, "lam": lam, "mu": mu, "z_u": zu, "z_x": zx, "mu_history": hist}
-
-
+    for _ in range(iterations):
+        prods = [b.products() for b in blocks]
+        count = sum(c for _, c in prods)
+        mu_b = sum(p for p, _ in prods) / max(count, 1)
+        hist.append(mu_b)
+        if mu_b < mu_stop:
+            break
+        # 1. predictor (affine scaling direction)
+        zero = [(np.zeros_like(b.v), np.zeros_like(b.v)) for b in blocks]
+        aff = newton(zero)
+        if aff["status"] != "ok":
+            return {"status": "newton_" + aff["status"], "mu_history": hist}
+        dv_aff = list(aff["u"]) + list(aff["x"])
+        dz_aff = [b.dz(dv, 0.0, 0.0) for b, dv in zip(blocks, dv_aff)]
+        a_aff = min(1.0, min(b.max_step(dv, *dz) for b, dv, dz in zip(blocks, dv_aff, dz_aff)))
+        mu_aff = sum(b.products_after(a_aff, dv, *dz) for b, dv, dz in zip(blocks, dv_aff, dz_aff)) / max(count, 1)
+        # 2. centering
+        sigma = min(1.0, (mu_aff / mu_b) ** 3)
+        # 3. corrector: same matrices, second-order targets
+        targets = [(sigma * mu_b - dzl * dv, sigma * mu_b + dzh * dv) for dv, (dzl, dzh) in zip(dv_aff, dz_aff)]
+        cor = newton(targets)
+        if cor["status"] != "ok":
+            return {"status": "newton_" + cor["status"], "mu_history": hist}
+        dv = list(cor["u"]) + list(cor["x"])
+        dz = [b.dz(d, *t) for b, d, t in zip(blocks, dv, targets)]
+        # 4. step
+        a = min(1.0, tau * min(b.max_step(d, *z) for b, d, z in zip(blocks, dv, dz)))
+        for b, d, (dzl, dzh) in zip(blocks, dv, dz):
+            b.v = b.v + a * d
+            b.zl = b.zl + a * dzl
+            b.zh = b.zh + a * dzh
+        lam = [p + a * (q - p) for p, q in zip(lam, cor["lam"])]
+        mu = [p + a * (q - p) for p, q in zip(mu, cor["mu"])]
+        steps += 1
+    return {"status": "ok", "x": [b.v for b in X], "u": [b.v for b in U], "lam": lam, "mu": mu,
+            "z_u": [(b.zl, b.zh) for b in U], "z_x": [(b.zl, b.zh) for b in X], "mu_history": hist,
+            "steps": steps}
 def bound_kkt_residual(prob, bounds, sol) -> Dict[str, float]:
     """Residuals of the optimality conditions of the bound-constrained
     problem at sol: stationarity grad f + J' nu - z_lo + z_hi (inf norm),

@@ -9,8 +9,9 @@ used by ``ECLQRFunction``.  This package is its Python binding.
 """
 
 from ._lib import EclqrError, STATUS_BITS, status_names  # noqa: F401
-from .solver import (Plan, Solution, allocate_solution, autotune, backward, default_options, get_tuning,  # noqa: F401
-                     kkt_residual, pack, set_tuning, solve, solve_noalloc, unpack)
+from .solver import (IpmSolution, Plan, Solution, allocate_solution, autotune, backward, default_options,  # noqa: F401
+                     get_tuning, ipm_default_params, ipm_solve, ipm_workspace, kkt_residual, pack, pack_bounds, set_tuning,
+                     solve, solve_noalloc, unpack)
 
 
 def __getattr__(name):

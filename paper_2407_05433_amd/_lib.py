@@ -14,7 +14,7 @@ NUM_FIELDS = 12
 FIELDS = ("Q", "q", "R", "r", "M", "A", "B", "c", "E", "F", "g", "x0")
 FIELD_INDEX = {f: i for i, f in enumerate(FIELDS)}
 
-NUM_KERNEL_CLASSES = 16
+NUM_KERNEL_CLASSES = 17
 
 STATUS_BITS = {
     1: "infeasible_suffix",
@@ -63,6 +63,21 @@ class CotangentPtrs(C.Structure):
 
 class GradPtrs(C.Structure):
     _fields_ = [(f, C.c_void_p) for f in FIELDS] + [("status", C.c_void_p)]
+
+
+class BoundPtrs(C.Structure):
+    _fields_ = [("u_lo", C.c_void_p), ("u_hi", C.c_void_p), ("x_lo", C.c_void_p), ("x_hi", C.c_void_p)]
+
+
+class IpmParams(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("mu_stop", C.c_double), ("tau", C.c_double), ("mu0", C.c_double),
+                ("interior", C.c_double), ("corrector_replay", C.c_int32)]
+
+
+class IpmSolutionPtrs(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("u", C.c_void_p), ("lam", C.c_void_p), ("mu", C.c_void_p),
+                ("z_ulo", C.c_void_p), ("z_uhi", C.c_void_p), ("z_xlo", C.c_void_p), ("z_xhi", C.c_void_p),
+                ("comp", C.c_void_p), ("steps", C.c_void_p), ("status", C.c_void_p)]
 
 
 _lib = None
@@ -126,6 +141,13 @@ def lib():
     L.eclqr_plan_slot_info.restype = C.c_int
     L.eclqr_plan_footprint.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int64)]
     L.eclqr_plan_footprint.restype = C.c_int
+    L.eclqr_ipm_default_params.argtypes = [C.POINTER(IpmParams)]
+    L.eclqr_ipm_default_params.restype = None
+    L.eclqr_ipm_workspace_size.argtypes = [C.c_void_p, C.POINTER(C.c_size_t)]
+    L.eclqr_ipm_workspace_size.restype = C.c_int
+    L.eclqr_ipm_solve.argtypes = [C.c_void_p, C.POINTER(ProblemPtrs), C.POINTER(BoundPtrs), C.POINTER(IpmParams),
+                                  C.POINTER(IpmSolutionPtrs), C.c_void_p, C.c_size_t, C.c_void_p]
+    L.eclqr_ipm_solve.restype = C.c_int
     for fn in ("eclqr_plan_create", "eclqr_plan_layout", "eclqr_plan_workspace_size", "eclqr_plan_schedule",
                "eclqr_solve", "eclqr_backward", "eclqr_kkt_residual", "eclqr_plan_set_profiling",
                "eclqr_plan_profile", "eclqr_plan_reduced_dims"):

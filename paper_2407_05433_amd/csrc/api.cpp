@@ -25,8 +25,16 @@ void release_graph(Plan& p) {
   p.graph_key.clear();
 }
 
+// every captured graph of the plan (after a tuning change, or at the end)
+void release_graphs(Plan& p) {
+  release_graph(p);
+  if (p.ipm_graph_exec) (void)hipGraphExecDestroy(reinterpret_cast<hipGraphExec_t>(p.ipm_graph_exec));
+  p.ipm_graph_exec = nullptr;
+  p.ipm_graph_key.clear();
+}
+
 Plan::~Plan() {
-  release_graph(*this);
+  release_graphs(*this);
   if (capture_stream) (void)hipStreamDestroy(reinterpret_cast<hipStream_t>(capture_stream));
   if (aux_stream) (void)hipStreamDestroy(reinterpret_cast<hipStream_t>(aux_stream));
   if (ev_fork) (void)hipEventDestroy(reinterpret_cast<hipEvent_t>(ev_fork));
@@ -705,7 +713,7 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
   {
     Timed tm(ECLQR_K_REFINE_IO, s);
     launch_merge_dual_bits(status, v.dstatus, ECLQR_DUAL_FAILED, kDualStructural, B, s);
-    launch_backward_error(v.P, in, x, u, lam, mu, v.omega, s);
+    launch_backward_error(v.P, in, x, u, lam, mu, at<unsigned long long>(v.ws, p.o_wmax), v.omega, s);
     launch_accept(v.omega, v.dstatus, p.opt.accept_tol, v.gate, B, s);
   }
   Inputs cin = in;
@@ -744,8 +752,9 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
     launch_fill_i32(v.gate, kGateActive, B, s);  // later launches on this workspace run every instance
     launch_fill_i32(v.live, 1, 1, s);
     launch_fill_u64(v.omega, 0ull, B, s);
-    launch_backward_error(v.P, in, x, u, lam, mu, v.omega, s);
-    launch_flag_unconverged(v.omega, v.rsteps, p.opt.dual_cons_tol, status, ECLQR_DUAL_FAILED, B, s);
+    launch_backward_error(v.P, in, x, u, lam, mu, at<unsigned long long>(v.ws, p.o_wmax), v.omega, s);
+    if (!p.inexact_newton)
+      launch_flag_unconverged(v.omega, v.rsteps, p.opt.dual_cons_tol, status, ECLQR_DUAL_FAILED, B, s);
     launch_apply_abort(status, at<int32_t>(v.ws, p.o_abort), ECLQR_TIMEOUT, B, s);
   }
   return ECLQR_SUCCESS;
@@ -993,6 +1002,146 @@ eclqr_status solve_in_shared(eclqr_plan* plan, const eclqr_problem* prob, eclqr_
 
 }  // namespace eclqr
 
+namespace {
+
+// Interior-point workspace: the plan's solve workspace, then the Newton
+// problem's own fields, its solution, and the driver's per-instance state.
+struct IpmLayout {
+  size_t nQ, nq, nR, nr, nc, ng, nx0, dx, du, dlam, dmu, cx, cu, clam, cmu, nstat, cstat, part, comp, smu, alpha, act,
+      steps, bytes;
+};
+
+IpmLayout ipm_layout(const Plan& p) {
+  const Engine& E = p.primal;
+  IpmLayout L{};
+  size_t o = (p.bytes + 255) & ~size_t(255);
+  auto take = [&](size_t& off, size_t n) {
+    off = o;
+    o = (o + n + 255) & ~size_t(255);
+  };
+  const auto d = [&](int f) { return sizeof(double) * (size_t)E.total[f]; };
+  take(L.nQ, d(ECLQR_F_Q));
+  take(L.nq, d(ECLQR_F_q));
+  take(L.nR, d(ECLQR_F_R));
+  take(L.nr, d(ECLQR_F_r));
+  take(L.nc, d(ECLQR_F_c));
+  take(L.ng, d(ECLQR_F_g));
+  take(L.nx0, d(ECLQR_F_x0));
+  take(L.dx, d(ECLQR_F_q));
+  take(L.du, d(ECLQR_F_r));
+  take(L.dlam, d(ECLQR_F_q));
+  take(L.dmu, d(ECLQR_F_g));
+  take(L.cx, d(ECLQR_F_q));
+  take(L.cu, d(ECLQR_F_r));
+  take(L.clam, d(ECLQR_F_q));
+  take(L.cmu, d(ECLQR_F_g));
+  take(L.nstat, sizeof(int32_t) * (size_t)E.B);
+  take(L.cstat, sizeof(int32_t) * (size_t)E.B);
+  take(L.part, sizeof(double) * 2 * (size_t)E.S);
+  take(L.comp, sizeof(double) * (size_t)E.B);
+  take(L.smu, sizeof(double) * (size_t)E.B);
+  take(L.alpha, sizeof(unsigned long long) * (size_t)E.B);
+  take(L.act, sizeof(int32_t) * (size_t)E.B);
+  take(L.steps, sizeof(int32_t) * (size_t)E.B);
+  L.bytes = o;
+  return L;
+}
+
+// Device state of one interior-point call.
+struct IpmCtx {
+  Inputs in;         // the caller's problem
+  Inputs newton;     // the Newton problem: its own Q q R r c g x0, the caller's M A B E F
+  IpmBounds bd;
+  IpmDuals z;
+  IpmNewton nw;
+  eclqr_solution pred;              // predictor solution (status: nstat)
+  double *cx, *cu, *clam, *cmu;     // corrector solution
+  double *x, *u, *lam, *mu;         // the iterate (caller's buffers)
+  int32_t *status, *nstat, *cstat, *act, *steps;
+  double *part, *comp, *smu;
+  unsigned long long* alpha;
+  double tau, mu_stop;
+  bool replay;       // corrector by replaying the predictor's factorizations
+};
+
+// One predictor-corrector iteration: complementarity and stop test, the
+// predictor's Newton data and full solve, the centering parameter, the
+// corrector's linear terms and its solve by replaying the predictor's
+// factorizations (same matrices), then the step.
+eclqr_status ipm_iteration(Plan& p, const Views& v, const IpmCtx& c, hipStream_t s) {
+  const DevEngine& P = v.P;
+  {
+    Timed tm(ECLQR_K_IPM, s);
+    launch_ipm_mu(P, v.psbase, c.bd, c.x, c.u, c.z, c.part, c.mu_stop, c.comp, c.act, s);
+    launch_ipm_newton(P, c.in, c.bd, c.x, c.u, c.z, nullptr, nullptr, nullptr, 0, c.nw, s);
+  }
+  eclqr_solution pred = c.pred;
+  eclqr_status st = solve_sequence(p, v, c.newton, &pred, true, s);
+  if (st != ECLQR_SUCCESS) return st;
+  {
+    Timed tm(ECLQR_K_IPM, s);
+    launch_ipm_centering(P, v.psbase, c.bd, c.x, c.u, c.z, pred.x, pred.u, c.alpha, c.part, c.comp, c.smu, c.act, s);
+    launch_ipm_newton(P, c.in, c.bd, c.x, c.u, c.z, pred.x, pred.u, c.smu, 1, c.nw, s);
+  }
+  if (c.replay) {
+    st = solve_all(p, v, c.newton, c.cx, c.cu, c.clam, c.cmu, c.nstat, true, true, s);
+  } else {
+    eclqr_solution cor{c.cx, c.cu, c.clam, c.cmu, c.cstat, nullptr};
+    st = solve_sequence(p, v, c.newton, &cor, true, s);
+  }
+  if (st != ECLQR_SUCCESS) return st;
+  {
+    Timed tm(ECLQR_K_IPM, s);
+    launch_ipm_step(P, c.bd, c.x, c.u, c.lam, c.mu, c.z, c.cx, c.cu, c.clam, c.cmu, pred.x, pred.u, c.smu, c.nstat,
+                    c.replay ? nullptr : c.cstat, c.status, c.tau, c.alpha, c.act, c.steps, s);
+  }
+  HIP_OK(hipGetLastError());
+  return ECLQR_SUCCESS;
+}
+
+// The iteration captured once per set of pointers and parameters, replayed
+// once per iteration.
+eclqr_status ipm_iteration_graph(Plan& p, const Views& v, const IpmCtx& c, const std::vector<const void*>& key,
+                                 hipStream_t s) {
+  if (!p.ipm_graph_exec || p.ipm_graph_key != key) {
+    if (p.ipm_graph_exec) (void)hipGraphExecDestroy(reinterpret_cast<hipGraphExec_t>(p.ipm_graph_exec));
+    p.ipm_graph_exec = nullptr;
+    p.ipm_graph_key.clear();
+    if (!p.capture_stream) {
+      hipStream_t cs = nullptr;
+      HIP_OK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+      p.capture_stream = reinterpret_cast<void*>(cs);
+    }
+    hipStream_t cs = reinterpret_cast<hipStream_t>(p.capture_stream);
+    HIP_OK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    const eclqr_status cst = ipm_iteration(p, v, c, cs);
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(cs, &g);
+    if (cst != ECLQR_SUCCESS) {
+      if (g) (void)hipGraphDestroy(g);
+      return cst;
+    }
+    if (ce != hipSuccess) return fail(ECLQR_HIP_ERROR, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) return fail(ECLQR_HIP_ERROR, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+    p.ipm_graph_exec = reinterpret_cast<void*>(ex);
+    p.ipm_graph_key = key;
+  }
+  HIP_OK(hipGraphLaunch(reinterpret_cast<hipGraphExec_t>(p.ipm_graph_exec), s));
+  return ECLQR_SUCCESS;
+}
+
+const void* bits_key(double d) {
+  uintptr_t b = 0;
+  static_assert(sizeof(uintptr_t) == sizeof(double), "64-bit host");
+  std::memcpy(&b, &d, sizeof(d));
+  return reinterpret_cast<const void*>(b);
+}
+
+}  // namespace
+
 extern "C" {
 
 int eclqr_abi_version(void) { return ECLQR_ABI_VERSION; }
@@ -1061,7 +1210,7 @@ void eclqr_plan_destroy(eclqr_plan* plan) { delete plan; }
 eclqr_status eclqr_plan_set_graph(eclqr_plan* plan, int32_t on) {
   if (!plan) return fail(ECLQR_INVALID_ARGUMENT, "NULL plan");
   plan->p.opt.use_graph = (on != 0);
-  if (!on) release_graph(plan->p);
+  if (!on) release_graphs(plan->p);
   return ECLQR_SUCCESS;
 }
 
@@ -1206,7 +1355,7 @@ const char* eclqr_kernel_class_name(int32_t k) {
   static const char* names[ECLQR_NUM_KERNEL_CLASSES] = {
       "validate", "base_relation", "rel_compose", "domain", "eliminate", "ric_combine",
       "gains", "fwd_combine", "recover", "multiplier_io", "refine_io", "other", "replay", "multipliers_fast",
-      "multipliers_theta", "multipliers_cx"};
+      "multipliers_theta", "multipliers_cx", "ipm"};
   return (k >= 0 && k < ECLQR_NUM_KERNEL_CLASSES) ? names[k] : "unknown";
 }
 
@@ -1340,7 +1489,7 @@ eclqr_status eclqr_plan_set_tuning(eclqr_plan* plan, const eclqr_tuning* t) {
   p.mult_route = (p.theta_ok && (t->multiplier_route != 0 || !p.has_dual)) ? 1 : 0;
   p.split_combine = t->split_combine != 0;
   p.fused_scans = t->fused_scans != 0;
-  release_graph(p);
+  release_graphs(p);
   return ECLQR_SUCCESS;
 }
 
@@ -1390,7 +1539,7 @@ eclqr_status eclqr_plan_autotune(eclqr_plan* plan, const eclqr_problem* prob, ec
     const int32_t old = *k.v;
     *k.v = k.alt;
     p.opt.use_graph = graph;
-    release_graph(p);
+    release_graphs(p);
     double ms = 0.0;
     st = measure(&ms);
     if (st == ECLQR_SUCCESS && ms < 0.98 * best) {
@@ -1398,7 +1547,7 @@ eclqr_status eclqr_plan_autotune(eclqr_plan* plan, const eclqr_problem* prob, ec
     } else {
       *k.v = old;
       p.opt.use_graph = graph;
-      release_graph(p);
+      release_graphs(p);
     }
   }
   (void)hipEventDestroy(ea);
@@ -1421,6 +1570,150 @@ eclqr_status eclqr_kkt_residual(eclqr_plan* plan, const eclqr_problem* prob, con
   Views v = views(p, ws);
   launch_kkt_residual(v.P, inputs_of(prob), sol->x, sol->u, sol->lam, sol->mu, dev_sbase(p.primal, ws, p.o_primal),
                       out, s);
+  HIP_OK(hipGetLastError());
+  return ECLQR_SUCCESS;
+}
+
+void eclqr_ipm_default_params(eclqr_ipm_params* prm) {
+  if (!prm) return;
+  prm->iterations = 30;
+  prm->mu_stop = 1e-8;
+  prm->tau = 0.995;
+  prm->mu0 = 100.0;
+  prm->interior = 0.25;
+  prm->corrector_replay = 1;
+}
+
+eclqr_status eclqr_ipm_workspace_size(const eclqr_plan* plan, size_t* bytes) {
+  if (!plan || !bytes) return fail(ECLQR_INVALID_ARGUMENT, "NULL argument");
+  *bytes = ipm_layout(plan->p).bytes;
+  return ECLQR_SUCCESS;
+}
+
+eclqr_status eclqr_ipm_solve(eclqr_plan* plan, const eclqr_problem* prob, const eclqr_bounds* bounds,
+                             const eclqr_ipm_params* prm, eclqr_ipm_solution* sol, void* ws, size_t ws_bytes,
+                             void* stream) {
+  if (!plan || !prob || !bounds || !prm || !sol || !ws) return fail(ECLQR_INVALID_ARGUMENT, "NULL argument");
+  Plan& p = plan->p;
+  const Engine& E = p.primal;
+  const IpmLayout L = ipm_layout(p);
+  if (ws_bytes < L.bytes) return fail(ECLQR_WORKSPACE_TOO_SMALL, "workspace smaller than eclqr_ipm_workspace_size");
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(ECLQR_INVALID_ARGUMENT, "workspace not 256-byte aligned");
+  if (p.opt.multipliers == 0)
+    return fail(ECLQR_INVALID_ARGUMENT, "the interior-point driver needs a plan with multipliers (1, 2 or 3)");
+  if (prm->iterations < 0 || !(prm->tau > 0.0 && prm->tau < 1.0) || !(prm->mu0 > 0.0) ||
+      !(prm->interior > 0.0 && prm->interior < 0.5) || !(prm->mu_stop >= 0.0))
+    return fail(ECLQR_INVALID_ARGUMENT, "parameters: iterations >= 0, 0 < tau < 1, mu0 > 0, 0 < interior < 0.5, "
+                                        "mu_stop >= 0");
+  const int64_t nq = E.total[ECLQR_F_q], nr = E.total[ECLQR_F_r], ng = E.total[ECLQR_F_g];
+  const void* req[] = {sol->x, sol->u, sol->lam, sol->mu, sol->z_ulo, sol->z_uhi, sol->z_xlo, sol->z_xhi, sol->status};
+  const int64_t need[] = {nq, nr, nq, ng, nr, nr, nq, nq, 1};
+  for (size_t i = 0; i < sizeof(req) / sizeof(req[0]); ++i) {
+    if (need[i] > 0 && !req[i]) return fail(ECLQR_INVALID_ARGUMENT, "NULL output pointer for a non-empty field");
+    if (req[i] && !aligned(req[i])) return fail(ECLQR_INVALID_ARGUMENT, "misaligned output pointer");
+  }
+  const void* opt_ptrs[] = {bounds->u_lo, bounds->u_hi, bounds->x_lo, bounds->x_hi, sol->comp, sol->steps};
+  for (const void* q : opt_ptrs)
+    if (q && !aligned(q)) return fail(ECLQR_INVALID_ARGUMENT, "misaligned bound or output pointer");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  IpmCtx c{};
+  c.nw = {at<double>(ws, L.nQ), at<double>(ws, L.nq), at<double>(ws, L.nR), at<double>(ws, L.nr),
+          at<double>(ws, L.nc), at<double>(ws, L.ng), at<double>(ws, L.nx0)};
+  eclqr_problem np = *prob;  // the Newton problem at fixed addresses in ws
+  np.Q = c.nw.Q;
+  np.q = c.nw.q;
+  np.R = c.nw.R;
+  np.r = c.nw.r;
+  np.c = c.nw.c;
+  np.g = c.nw.g;
+  np.x0 = c.nw.x0;
+  c.in = inputs_of(prob);
+  c.newton = inputs_of(&np);
+  c.bd = {bounds->u_lo, bounds->u_hi, bounds->x_lo, bounds->x_hi};
+  c.z = {sol->z_ulo, sol->z_uhi, sol->z_xlo, sol->z_xhi};
+  c.nstat = at<int32_t>(ws, L.nstat);
+  c.pred = {at<double>(ws, L.dx), at<double>(ws, L.du), at<double>(ws, L.dlam), at<double>(ws, L.dmu), c.nstat,
+            nullptr};
+  c.cx = at<double>(ws, L.cx);
+  c.cu = at<double>(ws, L.cu);
+  c.clam = at<double>(ws, L.clam);
+  c.cmu = at<double>(ws, L.cmu);
+  c.x = sol->x;
+  c.u = sol->u;
+  c.lam = sol->lam;
+  c.mu = sol->mu;
+  c.status = sol->status;
+  c.act = at<int32_t>(ws, L.act);
+  c.steps = sol->steps ? sol->steps : at<int32_t>(ws, L.steps);
+  c.part = at<double>(ws, L.part);
+  c.comp = sol->comp ? sol->comp : at<double>(ws, L.comp);
+  c.smu = at<double>(ws, L.smu);
+  c.alpha = at<unsigned long long>(ws, L.alpha);
+  c.tau = prm->tau;
+  c.mu_stop = prm->mu_stop;
+  c.replay = prm->corrector_replay != 0;
+  c.cstat = at<int32_t>(ws, L.cstat);
+
+  // start: the equality-constrained problem itself, solved at the Newton
+  // problem's addresses (its captured graph, if any, serves the next call)
+  const std::pair<const double*, double*> start[] = {{prob->Q, c.nw.Q}, {prob->q, c.nw.q}, {prob->R, c.nw.R},
+                                                     {prob->r, c.nw.r}, {prob->c, c.nw.c}, {prob->g, c.nw.g},
+                                                     {prob->x0, c.nw.x0}};
+  const int fields[] = {ECLQR_F_Q, ECLQR_F_q, ECLQR_F_R, ECLQR_F_r, ECLQR_F_c, ECLQR_F_g, ECLQR_F_x0};
+  for (int f = 0; f < 7; ++f) {
+    const size_t n = sizeof(double) * (size_t)E.total[fields[f]];
+    if (n == 0) continue;
+    if (!start[f].first) return fail(ECLQR_INVALID_ARGUMENT, "NULL data pointer for a non-empty field");
+    HIP_OK(hipMemcpyAsync(start[f].second, start[f].first, n, hipMemcpyDeviceToDevice, s));
+  }
+  eclqr_solution pred = c.pred;
+  eclqr_status st = solve_impl(plan, &np, &pred, ws, ws_bytes, stream);
+  // ws will hold Newton factorizations, not a solve of prob
+  record_solve(p, ws, -1, &np, &pred, false);
+  if (st != ECLQR_SUCCESS) return st;
+  const auto copy = [&](double* dst, const double* src, int64_t n) -> eclqr_status {
+    if (n > 0) HIP_OK(hipMemcpyAsync(dst, src, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s));
+    return ECLQR_SUCCESS;
+  };
+  if ((st = copy(c.x, pred.x, nq)) != ECLQR_SUCCESS || (st = copy(c.u, pred.u, nr)) != ECLQR_SUCCESS ||
+      (st = copy(c.lam, pred.lam, nq)) != ECLQR_SUCCESS || (st = copy(c.mu, pred.mu, ng)) != ECLQR_SUCCESS)
+    return st;
+
+  Views v = views(p, ws);
+  v.P.info = at<int32_t>(ws, p.o_info);
+  g_prof = &p;
+  {
+    Timed tm(ECLQR_K_IPM, s);
+    launch_ipm_start(c.nstat, c.status, c.act, c.steps, E.B, s);
+    launch_ipm_init(v.P, c.bd, c.x, c.u, c.z, prm->mu0, prm->interior, c.status, c.act, s);
+  }
+  HIP_OK(hipGetLastError());
+  // Newton steps need not be exact: near the solution their matrices carry
+  // diagonal entries of order z^2 / mu, and an instance whose refinement
+  // stops short of dual_cons_tol still takes its step
+  struct Inexact {
+    Plan& p;
+    explicit Inexact(Plan& q) : p(q) { p.inexact_newton = true; }
+    ~Inexact() { p.inexact_newton = false; }
+  } inexact(p);
+  if (p.opt.use_graph && !p.profiling && prm->iterations > 0) {
+    std::vector<const void*> key = {ws, prob->Q, prob->q, prob->R, prob->r, prob->M, prob->A, prob->B, prob->c,
+                                    prob->E, prob->F, prob->g, prob->x0, bounds->u_lo, bounds->u_hi, bounds->x_lo,
+                                    bounds->x_hi, c.x, c.u, c.lam, c.mu, c.z.ul, c.z.uh, c.z.xl, c.z.xh, c.status,
+                                    c.steps, c.comp, bits_key(c.tau), bits_key(c.mu_stop),
+                                    reinterpret_cast<const void*>(static_cast<uintptr_t>(c.replay))};
+    for (int it = 0; it < prm->iterations; ++it)
+      if ((st = ipm_iteration_graph(p, v, c, key, s)) != ECLQR_SUCCESS) return st;
+  } else {
+    for (int it = 0; it < prm->iterations; ++it)
+      if ((st = ipm_iteration(p, v, c, s)) != ECLQR_SUCCESS) return st;
+  }
+  {
+    // complementarity at the returned iterate (stops no instance)
+    Timed tm(ECLQR_K_IPM, s);
+    launch_ipm_mu(v.P, v.psbase, c.bd, c.x, c.u, c.z, c.part, 0.0, c.comp, c.act, s);
+  }
   HIP_OK(hipGetLastError());
   return ECLQR_SUCCESS;
 }

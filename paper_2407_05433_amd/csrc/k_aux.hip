@@ -273,42 +273,77 @@ __global__ void __launch_bounds__(kBlock) k_refine_decide(DevEngine p, const int
   }
 }
 
-// v += sum_l a[l sa] b[l sb] and mag += sum_l |a[l sa] b[l sb]| in ascending l
-// (the same sums as a plain loop), with the loads of each batch of 8 issued
-// before its additions.
+// v += sum_l a[l sa] b[l sb], mag += sum_l |a[l sa] b[l sb]| and
+// an += sum_l |a[l sa]| in ascending l (the same sums as a plain loop), with
+// the loads of each batch of 8 issued before its additions.
 __device__ __forceinline__ void acc_terms(const double* a, int sa, const double* b, int sb, int n, double& v,
-                                          double& mag) {
+                                          double& mag, double& an) {
   int l = 0;
   for (; l + 8 <= n; l += 8) {
-    double t[8];
+    double av[8], t[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) t[j] = a[(l + j) * sa] * b[(l + j) * sb];
+    for (int j = 0; j < 8; ++j) {
+      av[j] = a[(l + j) * sa];
+      t[j] = av[j] * b[(l + j) * sb];
+    }
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       v += t[j];
       mag += fabs(t[j]);
+      an += fabs(av[j]);
     }
   }
   for (; l < n; ++l) {
-    const double t = a[l * sa] * b[l * sb];
+    const double av = a[l * sa];
+    const double t = av * b[l * sb];
     v += t;
     mag += fabs(t);
+    an += fabs(av);
   }
 }
 
-// Componentwise backward error of the KKT system at (x, u, lambda, mu):
-// max over rows of |residual| / (sum of |terms|), over stationarity in x and
-// u, dynamics, equality rows and the initial condition.  One wavefront per
-// stage; the per-instance maximum is accumulated with an integer atomic max
-// on the bit pattern (order independent, so deterministic).
+// Largest |entry| of x, u, lambda, mu per instance (the scale of the
+// unknowns), max-accumulated on the bit patterns of non-negative doubles.
+__global__ void __launch_bounds__(kBlock) k_unknown_scale(DevEngine p, const double* x, const double* u,
+                                                          const double* lam, const double* mu,
+                                                          unsigned long long* wmax) {
+  for (int64_t s = blockIdx.x; s < p.S; s += gridDim.x) {
+    const StageInfo st = p.st[s];
+    if (gated(p, st.inst)) continue;
+    double w = 0.0;
+    for (int i = ECLQR_TID; i < st.n; i += ECLQR_NT)
+      w = fmax(w, fmax(fabs(x[st.in[IN_q] + i]), fabs(lam[st.in[IN_q] + i])));
+    if (!st.terminal)
+      for (int i = ECLQR_TID; i < st.m; i += ECLQR_NT) w = fmax(w, fabs(u[st.in[IN_r] + i]));
+    for (int i = ECLQR_TID; i < st.k; i += ECLQR_NT) w = fmax(w, fabs(mu[st.in[IN_g] + i]));
+    w = wave_max(w);
+    if (ECLQR_TID == 0) atomicMax(wmax + st.inst, (unsigned long long)__double_as_longlong(w));
+  }
+}
+
+// Backward error of the KKT system at (x, u, lambda, mu), over stationarity
+// in x and u, dynamics, equality rows and the initial condition: per row
+// |residual| / (sum of |terms|), the componentwise measure, except on rows
+// whose componentwise scale is negligible next to their normwise scale
+// ||row||_1 ||unknowns||_inf + |offset| (below 1000 (terms) eps times it),
+// which take the normwise measure instead -- the two-category backward error
+// of Arioli, Demmel and Duff (SIAM J. Matrix Anal. Appl. 10(2), 1989).  Rows
+// whose data and solution are near zero (an offset of rounding size, as in a
+// Newton step at a feasible point) would otherwise demand a relative accuracy
+// no solver reaches.  The maximum over rows; one wavefront per stage; the
+// per-instance maximum is accumulated with an integer atomic max on the bit
+// pattern (order independent, so deterministic).
 __global__ void __launch_bounds__(kBlock) k_backward_error(DevEngine p, Inputs in, const double* x, const double* u,
                                                            const double* lam, const double* mu,
+                                                           const unsigned long long* wmax,
                                                            unsigned long long* omega) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
+  constexpr double kEps = 2.220446049250313e-16;
   for (int64_t s = (int64_t)blockIdx.x * waves + wave; s < p.S; s += (int64_t)gridDim.x * waves) {
     const StageInfo st = p.st[s];
     if (gated(p, st.inst)) continue;
     const int n = st.n, np = st.np, m = st.m, k = st.k;
+    const double W = __longlong_as_double((long long)wmax[st.inst]);
     const double* xs = x + st.in[IN_q];
     const double* ls = lam + st.in[IN_q];
     const double* ms = mu + st.in[IN_g];
@@ -328,44 +363,51 @@ __global__ void __launch_bounds__(kBlock) k_backward_error(DevEngine p, Inputs i
     const double* x1 = term ? nullptr : x + p.st[s + 1].in[IN_q];
     const double* l1 = term ? nullptr : lam + p.st[s + 1].in[IN_q];
     double w = 0.0;
-    auto acc = [&](double res, double mag) {
-      const double e = (mag > 0.0) ? fabs(res) / mag : (res == 0.0 ? 0.0 : HUGE_VAL);
+    // res: residual, mag: sum of |terms|, an: sum of |coefficients|, b: the
+    // row's offset, len: its number of terms
+    auto acc = [&](double res, double mag, double an, double b, int len) {
+      const double nrm = an * W + fabs(b);
+      const double den = (mag > 1000.0 * len * kEps * nrm) ? mag : nrm;
+      const double e = (den > 0.0) ? fabs(res) / den : (res == 0.0 ? 0.0 : HUGE_VAL);
       w = (e > w || e != e) ? e : w;
     };
     for (int i = lane; i < n; i += 64) {  // stationarity in x_i
-      double v = q[i] - ls[i], a = fabs(q[i]) + fabs(ls[i]);
-      acc_terms(Q + i * n, 1, xs, 1, n, v, a);
-      acc_terms(E + i, n, ms, 1, k, v, a);
+      double v = q[i] - ls[i], a = fabs(q[i]) + fabs(ls[i]), an = 1.0;
+      acc_terms(Q + i * n, 1, xs, 1, n, v, a, an);
+      acc_terms(E + i, n, ms, 1, k, v, a, an);
+      int len = 2 + n + k;
       if (!term) {
-        if (M) acc_terms(M + i * m, 1, us, 1, m, v, a);
-        acc_terms(A + i, n, l1, 1, np, v, a);
+        if (M) acc_terms(M + i * m, 1, us, 1, m, v, a, an);
+        acc_terms(A + i, n, l1, 1, np, v, a, an);
+        len += (M ? m : 0) + np;
       }
-      acc(v, a);
+      acc(v, a, an, q[i], len);
     }
     for (int i = lane; i < k; i += 64) {  // equality rows
-      double v = g[i], a = fabs(g[i]);
-      acc_terms(E + i * n, 1, xs, 1, n, v, a);
-      if (!term) acc_terms(F + i * m, 1, us, 1, m, v, a);
-      acc(v, a);
+      double v = g[i], a = fabs(g[i]), an = 0.0;
+      acc_terms(E + i * n, 1, xs, 1, n, v, a, an);
+      if (!term) acc_terms(F + i * m, 1, us, 1, m, v, a, an);
+      acc(v, a, an, g[i], 1 + n + (term ? 0 : m));
     }
     if (!term) {
       for (int i = lane; i < m; i += 64) {  // stationarity in u_i
-        double v = r[i], a = fabs(r[i]);
-        acc_terms(R + i * m, 1, us, 1, m, v, a);
-        if (M) acc_terms(M + i, m, xs, 1, n, v, a);
-        acc_terms(B + i, m, l1, 1, np, v, a);
-        acc_terms(F + i, m, ms, 1, k, v, a);
-        acc(v, a);
+        double v = r[i], a = fabs(r[i]), an = 0.0;
+        acc_terms(R + i * m, 1, us, 1, m, v, a, an);
+        if (M) acc_terms(M + i, m, xs, 1, n, v, a, an);
+        acc_terms(B + i, m, l1, 1, np, v, a, an);
+        acc_terms(F + i, m, ms, 1, k, v, a, an);
+        acc(v, a, an, r[i], 1 + m + (M ? n : 0) + np + k);
       }
       for (int i = lane; i < np; i += 64) {  // dynamics
-        double v = c[i] - x1[i], a = fabs(c[i]) + fabs(x1[i]);
-        acc_terms(A + i * n, 1, xs, 1, n, v, a);
-        acc_terms(B + i * m, 1, us, 1, m, v, a);
-        acc(v, a);
+        double v = c[i] - x1[i], a = fabs(c[i]) + fabs(x1[i]), an = 1.0;
+        acc_terms(A + i * n, 1, xs, 1, n, v, a, an);
+        acc_terms(B + i * m, 1, us, 1, m, v, a, an);
+        acc(v, a, an, c[i], 2 + n + m);
       }
     }
     if (st.i == 0)
-      for (int i = lane; i < n; i += 64) acc(xs[i] - in.x0[st.x0 + i], fabs(xs[i]) + fabs(in.x0[st.x0 + i]));
+      for (int i = lane; i < n; i += 64)
+        acc(xs[i] - in.x0[st.x0 + i], fabs(xs[i]) + fabs(in.x0[st.x0 + i]), 1.0, in.x0[st.x0 + i], 2);
     for (int off = 32; off > 0; off >>= 1) {
       const double o = __shfl_xor(w, off, 64);
       w = (o > w || o != o) ? o : w;
@@ -691,8 +733,10 @@ void launch_refine_decide(const DevEngine& p, const int64_t* sbase, const double
   hipLaunchKernelGGL(k_refine_decide, dim3(g), dim3(kBlock), 0, s, p, sbase, norms, tol, last, gate, steps);
 }
 void launch_backward_error(const DevEngine& p, const Inputs& in, const double* x, const double* u, const double* lam,
-                           const double* mu, unsigned long long* omega, hipStream_t s) {
-  hipLaunchKernelGGL(k_backward_error, dim3(p.nblocks), dim3(kBlock), 0, s, p, in, x, u, lam, mu, omega);
+                           const double* mu, unsigned long long* wmax, unsigned long long* omega, hipStream_t s) {
+  launch_fill_u64(wmax, 0ull, p.B, s);
+  hipLaunchKernelGGL(k_unknown_scale, dim3(p.nblocks), dim3(kBlock), 0, s, p, x, u, lam, mu, wmax);
+  hipLaunchKernelGGL(k_backward_error, dim3(p.nblocks), dim3(kBlock), 0, s, p, in, x, u, lam, mu, wmax, omega);
 }
 void launch_accept(const unsigned long long* omega, const int32_t* dstatus, double tol, int32_t* gate, int32_t B,
                    hipStream_t s) {

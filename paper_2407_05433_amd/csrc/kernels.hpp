@@ -114,6 +114,45 @@ void launch_scan_vec(const DevEngine& e, int kind, const ScanLevels& lv, int32_t
 // status[b] |= bit for every instance when *abort is set
 void launch_apply_abort(int32_t* status, const int32_t* abort, int32_t bit, int32_t B, hipStream_t s);
 
+// Interior-point driver (bounds on u_i and on x_i, i >= 1): bound arrays
+// (null = no bound on that side), bound multipliers and the Newton
+// problem's own fields (layouts of the problem's fields).
+struct IpmBounds {
+  const double *u_lo, *u_hi, *x_lo, *x_hi;
+};
+struct IpmDuals {
+  double *ul, *uh, *xl, *xh;
+};
+struct IpmNewton {
+  double *Q, *q, *R, *r, *c, *g, *x0;
+};
+// status[b] = nstatus[b], act[b] = (status == 0), steps[b] = 0
+void launch_ipm_start(const int32_t* nstatus, int32_t* status, int32_t* act, int32_t* steps, int32_t B,
+                      hipStream_t s);
+// iterate moved inside the bounds, z = mu0 / distance; bad bounds flag the instance
+void launch_ipm_init(const DevEngine& p, const IpmBounds& bd, double* x, double* u, const IpmDuals& z, double mu0,
+                     double interior, int32_t* status, int32_t* act, hipStream_t s);
+// mean complementarity per instance (part: 2 S doubles); instances below mu_stop stop
+void launch_ipm_mu(const DevEngine& p, const int64_t* sbase, const IpmBounds& bd, const double* x, const double* u,
+                   const IpmDuals& z, double* part, double mu_stop, double* mu, int32_t* act, hipStream_t s);
+// Newton data at the iterate: predictor (ax null: zero targets, every field)
+// or corrector (targets from the predictor step ax, au and smu; with
+// vectors_only only q and r are written)
+void launch_ipm_newton(const DevEngine& p, const Inputs& in, const IpmBounds& bd, const double* x, const double* u,
+                       const IpmDuals& z, const double* ax, const double* au, const double* smu, int vectors_only,
+                       const IpmNewton& nw, hipStream_t s);
+// predictor step length (alpha), complementarity after it and smu = sigma mu
+void launch_ipm_centering(const DevEngine& p, const int64_t* sbase, const IpmBounds& bd, const double* x,
+                          const double* u, const IpmDuals& z, const double* ax, const double* au,
+                          unsigned long long* alpha, double* part, double* mu, double* smu, const int32_t* act,
+                          hipStream_t s);
+// Newton outcome, corrector step length and update of the active instances
+void launch_ipm_step(const DevEngine& p, const IpmBounds& bd, double* x, double* u, double* lam, double* mu_eq,
+                     const IpmDuals& z, const double* dx, const double* du, const double* lam_new,
+                     const double* mu_new, const double* ax, const double* au, const double* smu,
+                     const int32_t* nstatus, const int32_t* cstatus, int32_t* status, double tau,
+                     unsigned long long* alpha, int32_t* act, int32_t* steps, hipStream_t s);
+
 // vector-only replays of the kernels above (factors logged by the full pass)
 void launch_base_relation_vec(const DevEngine& e, const Inputs& in, int64_t logmax, hipStream_t s);
 void launch_rel_compose_vec(const DevEngine& e, int64_t first, int64_t ntasks, int64_t logmax, hipStream_t s);
@@ -156,8 +195,10 @@ void launch_refine_decide(const DevEngine& p, const int64_t* sbase, const double
 void launch_gate_advance(int32_t* gate, int32_t* live, int32_t B, hipStream_t s);
 // per-instance componentwise backward error (as the bit pattern of a
 // non-negative double, max-accumulated: clear to 0 first)
+// max-accumulates the backward error per instance into omega (wmax: B
+// entries of scratch for the scale of the unknowns)
 void launch_backward_error(const DevEngine& p, const Inputs& in, const double* x, const double* u, const double* lam,
-                           const double* mu, unsigned long long* omega, hipStream_t s);
+                           const double* mu, unsigned long long* wmax, unsigned long long* omega, hipStream_t s);
 void launch_accept(const unsigned long long* omega, const int32_t* dstatus, double tol, int32_t* gate, int32_t B,
                    hipStream_t s);
 void launch_fill_u64(unsigned long long* y, unsigned long long v, int64_t n, hipStream_t s);

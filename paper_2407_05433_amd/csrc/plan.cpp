@@ -647,6 +647,7 @@ std::string build_plan(Plan& p, const eclqr_dims* d, const eclqr_options* opt) {
   p.o_rsteps = o; o = align256(o + sizeof(int32_t) * std::max<int32_t>(1, P.B));
   p.o_live = o; o = align256(o + sizeof(int32_t));
   p.o_omega = o; o = align256(o + sizeof(double) * std::max<int32_t>(1, P.B));
+  p.o_wmax = o; o = align256(o + sizeof(double) * std::max<int32_t>(1, P.B));
   p.o_info = o; o = align256(o + sizeof(int32_t) * std::max<int32_t>(1, P.B));
   p.o_gstat = o; o = align256(o + sizeof(int32_t) * std::max<int32_t>(1, P.B));
   p.o_adjc = o; o = align256(o + sizeof(double) * std::max<int64_t>(1, P.total[ECLQR_F_c]));

@@ -126,6 +126,7 @@ struct Plan {
   size_t o_rsteps = 0; // per-instance count of refinement steps taken
   size_t o_live = 0;   // instances still refining (one int)
   size_t o_omega = 0;  // per-instance backward error after the first solve (double bits)
+  size_t o_wmax = 0;   // per-instance scale of the unknowns of the backward error (double bits)
   size_t o_info = 0;   // per-instance failing stage of the last solve (when the caller passes no info buffer)
   size_t o_adjc = 0, o_adjx0 = 0;  // adjoint offsets from dL/dlam (layouts of c and x0)
   size_t o_gstat = 0;  // per-instance outcome of the last backward (when the caller passes no status buffer)
@@ -153,9 +154,14 @@ struct Plan {
   void* ev_fork = nullptr;         // fork / join events between the two streams
   void* ev_join = nullptr;
   std::vector<const void*> graph_key;
+  void* ipm_graph_exec = nullptr;          // one interior-point iteration, captured (eclqr_ipm_solve)
+  std::vector<const void*> ipm_graph_key;
   ~Plan();
   // profiler: recorded (class, start, stop) event triples
   bool profiling = false;
+  bool inexact_newton = false;  // set while the interior-point driver enqueues its Newton solves: an
+                                // instance whose refinement stops above dual_cons_tol keeps its (inexact)
+                                // step instead of reporting ECLQR_DUAL_FAILED
   std::vector<std::pair<int, std::pair<void*, void*>>> events;
   std::vector<void*> event_pool;
   size_t pool_next = 0;

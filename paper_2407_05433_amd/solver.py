@@ -312,6 +312,103 @@ def solve_noalloc(plan: Plan, data: Dict[str, torch.Tensor], out: Solution) -> S
     return out
 
 
+@dataclass
+class IpmSolution:
+    """Last iterate of the interior-point driver (layouts of q, r, q, g; bound
+    multipliers of the inputs in the layout of r, of the states in that of q)."""
+    x: torch.Tensor
+    u: torch.Tensor
+    lam: torch.Tensor
+    mu: torch.Tensor
+    z_ulo: torch.Tensor
+    z_uhi: torch.Tensor
+    z_xlo: torch.Tensor
+    z_xhi: torch.Tensor
+    comp: torch.Tensor
+    steps: torch.Tensor
+    status: torch.Tensor
+
+    def ptrs(self) -> _lib.IpmSolutionPtrs:
+        return _lib.IpmSolutionPtrs(*(getattr(self, f).data_ptr() for f, _ in _lib.IpmSolutionPtrs._fields_))
+
+
+def pack_bounds(plan: Plan, problems, bounds, device="cuda") -> Dict[str, Optional[torch.Tensor]]:
+    """Device arrays of box bounds in the plan's layouts: bounds[b] is a dict
+    with any of u_lo, u_hi (one array per stage i < N), x_lo, x_hi (one per
+    stage i <= N; the block of x_0 is ignored).  A key no instance has is None
+    (no bound); a missing block is infinite."""
+    out: Dict[str, Optional[torch.Tensor]] = {}
+    for key, field in (("u_lo", "r"), ("u_hi", "r"), ("x_lo", "q"), ("x_hi", "q")):
+        if all(b.get(key) is None for b in bounds):
+            out[key] = None
+            continue
+        inf = -np.inf if key.endswith("lo") else np.inf
+        parts = []
+        for p, b in zip(problems, bounds):
+            dims = p.nu if field == "r" else p.nx
+            blocks = b.get(key)
+            if blocks is None:
+                blocks = [np.full(d, inf) for d in dims]
+            if len(blocks) != len(dims):
+                raise ValueError(f"bound {key}: {len(blocks)} blocks, the instance has {len(dims)}")
+            parts += [np.asarray(v, dtype=np.float64).ravel() for v in blocks]
+        flat = np.concatenate(parts) if parts else np.zeros(0)
+        if flat.size != plan.layout(field)[1]:
+            raise ValueError(f"bound {key}: {flat.size} elements, layout of {field} expects {plan.layout(field)[1]}")
+        out[key] = torch.from_numpy(np.ascontiguousarray(flat)).to(device)
+    return out
+
+
+def ipm_default_params() -> Dict[str, float]:
+    prm = _lib.IpmParams()
+    lib().eclqr_ipm_default_params(C.byref(prm))
+    return {f: getattr(prm, f) for f, _ in _lib.IpmParams._fields_}
+
+
+def ipm_workspace(plan: Plan, device="cuda") -> torch.Tensor:
+    n = C.c_size_t()
+    check(lib().eclqr_ipm_workspace_size(plan.handle, C.byref(n)), "eclqr_ipm_workspace_size")
+    return torch.empty(n.value + 256, dtype=torch.uint8, device=device)
+
+
+def ipm_solve(plan: Plan, data: Dict[str, torch.Tensor], bounds: Dict[str, Optional[torch.Tensor]],
+              ws: Optional[torch.Tensor] = None, out: Optional[IpmSolution] = None, **params) -> IpmSolution:
+    """eclqr_ipm_solve on the current stream (asynchronous).  bounds: device
+    tensors u_lo, u_hi (layout of r), x_lo, x_hi (layout of q), any of them
+    absent or None; params override eclqr_ipm_default_params."""
+    device = data["Q"].device
+    if ws is None:
+        ws = ipm_workspace(plan, device)
+    prm = _lib.IpmParams()
+    lib().eclqr_ipm_default_params(C.byref(prm))
+    for k, v in params.items():
+        if k not in dict(_lib.IpmParams._fields_):
+            raise TypeError(f"unknown interior-point parameter {k}")
+        setattr(prm, k, v)
+    if out is None:
+        _, nq = plan.layout("q")
+        _, nr = plan.layout("r")
+        _, ng = plan.layout("g")
+        mk = lambda n: torch.empty(max(1, n), dtype=torch.float64, device=device)  # noqa: E731
+        out = IpmSolution(mk(nq), mk(nr), mk(nq), mk(ng), mk(nr), mk(nr), mk(nq), mk(nq),
+                          torch.empty(plan.batch, dtype=torch.float64, device=device),
+                          torch.empty(plan.batch, dtype=torch.int32, device=device),
+                          torch.empty(plan.batch, dtype=torch.int32, device=device))
+    bp = _lib.BoundPtrs()
+    for f in ("u_lo", "u_hi", "x_lo", "x_hi"):
+        t = bounds.get(f)
+        if t is not None and t.dtype != torch.float64:
+            raise TypeError(f"bound {f} must be float64")
+        setattr(bp, f, t.data_ptr() if t is not None else None)
+    pp = _problem_ptrs(data)
+    sp = out.ptrs()
+    wptr, wbytes = _aligned_ws(ws)
+    check(lib().eclqr_ipm_solve(plan.handle, C.byref(pp), C.byref(bp), C.byref(prm), C.byref(sp), C.c_void_p(wptr),
+                                C.c_size_t(wbytes), _stream()), "eclqr_ipm_solve")
+    out._ws = ws
+    return out
+
+
 def backward(plan: Plan, data: Dict[str, torch.Tensor], sol: Solution, dx: torch.Tensor, du: torch.Tensor,
              ws: torch.Tensor, dlam: Optional[torch.Tensor] = None,
              dmu: Optional[torch.Tensor] = None) -> Dict[str, torch.Tensor]:

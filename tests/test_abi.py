@@ -264,3 +264,79 @@ def test_contraction_expansion_option():
     assert p3.workspace_bytes > p1.workspace_bytes
     with pytest.raises(ecl.EclqrError):
         ecl.Plan(dims, multipliers=4)
+
+
+def test_ipm_structs_defaults_and_argument_errors():
+    """The interior-point entry points: ctypes mirrors in the header's order,
+    the documented defaults, a workspace larger than the solve's, and the
+    argument errors that are decided before any device work (a plan without
+    multipliers, parameters out of range, missing outputs)."""
+    import ctypes as C
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+
+    def fields(tag):
+        body = re.search(r"typedef struct \{([^}]*)\}\s*" + tag + ";", text).group(1)
+        out = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if decl:
+                names = decl.split(None, 1)[1] if not decl.startswith("const") else decl.split(None, 2)[2]
+                out += [n.strip().lstrip("*") for n in names.split(",")]
+        return out
+
+    assert [f for f, _ in _lib.BoundPtrs._fields_] == fields("eclqr_bounds")
+    assert [f for f, _ in _lib.IpmParams._fields_] == fields("eclqr_ipm_params")
+    assert [f for f, _ in _lib.IpmSolutionPtrs._fields_] == fields("eclqr_ipm_solution")
+    d = ecl.ipm_default_params()
+    assert d == {"iterations": 30, "mu_stop": 1e-8, "tau": 0.995, "mu0": 100.0, "interior": 0.25, "corrector_replay": 1}
+    L = _lib.lib()
+    dims = [([3, 3, 3, 3], [2, 2, 2], [1, 0, 1, 0])]
+    plan = ecl.Plan(dims)
+    n = C.c_size_t()
+    assert L.eclqr_ipm_workspace_size(plan.handle, C.byref(n)) == 0
+    assert n.value > plan.workspace_bytes
+    fake_ws, big = C.c_void_p(1 << 20), C.c_size_t(1 << 40)  # never dereferenced: every case fails first
+    pp, bp, sp = _lib.ProblemPtrs(), _lib.BoundPtrs(), _lib.IpmSolutionPtrs()
+
+    def call(pl, **kw):
+        prm = _lib.IpmParams()
+        L.eclqr_ipm_default_params(C.byref(prm))
+        for k, v in kw.items():
+            setattr(prm, k, v)
+        return L.eclqr_ipm_solve(pl.handle, C.byref(pp), C.byref(bp), C.byref(prm), C.byref(sp), fake_ws, big, None)
+
+    assert call(ecl.Plan(dims, multipliers=0)) == 1
+    assert b"multipliers" in L.eclqr_last_error()
+    for bad in ({"tau": 1.0}, {"tau": 0.0}, {"mu0": 0.0}, {"interior": 0.5}, {"iterations": -1}, {"mu_stop": -1.0}):
+        assert call(plan, **bad) == 1, bad
+    assert call(plan) == 1 and b"NULL output" in L.eclqr_last_error()
+    assert L.eclqr_ipm_solve(plan.handle, C.byref(pp), C.byref(bp), None, C.byref(sp), fake_ws, big, None) == 1
+    assert L.eclqr_ipm_solve(plan.handle, C.byref(pp), C.byref(bp), C.byref(_lib.IpmParams()), C.byref(sp), fake_ws,
+                             C.c_size_t(16), None) == 2
+
+
+def test_pack_bounds_layout():
+    """Bounds land in the plan's layouts of r (inputs) and q (states), missing
+    blocks and instances are infinite with the right sign, and a key no
+    instance has is absent (None)."""
+    import numpy as np
+    from tests._util import tiny_problem
+    probs = [tiny_problem(5, N=3, n=3, m=2, kinds=[["mixed"]] * 3, terminal_rows=0),
+             tiny_problem(6, N=2, n=2, m=1, kinds=[[]] * 2, terminal_rows=1)]
+    plan = ecl.Plan.for_problems(probs)
+    b0 = {"u_lo": [np.full(2, -1.0 - i) for i in range(3)], "x_hi": [np.full(3, 10.0 + i) for i in range(4)]}
+    out = ecl.pack_bounds(plan, probs, [b0, {}], device="cpu")
+    assert out["u_hi"] is None and out["x_lo"] is None
+    ulo, xhi = out["u_lo"].numpy(), out["x_hi"].numpy()
+    offs, tot = plan.layout("r")
+    assert ulo.size == tot
+    for i in range(3):
+        assert np.all(ulo[offs[i]:offs[i] + 2] == -1.0 - i)
+    assert np.all(np.isneginf(ulo[offs[4]:offs[4] + 1])) and np.all(np.isneginf(ulo[offs[5]:offs[5] + 1]))
+    offs, tot = plan.layout("q")
+    assert xhi.size == tot
+    for i in range(4):
+        assert np.all(xhi[offs[i]:offs[i] + 3] == 10.0 + i)
+    assert np.all(np.isposinf(xhi[offs[4]:]))
+    with pytest.raises(ValueError):
+        ecl.pack_bounds(plan, probs, [{"u_lo": [np.zeros(2)] * 2}, {}], device="cpu")

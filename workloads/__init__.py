@@ -12,6 +12,7 @@ from .generate import (  # noqa: F401
     config_c2,
     config_c3,
     config_c4,
+    config_mpc,
     config_paper,
     random_problem,
     make_config,

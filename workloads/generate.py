@@ -26,7 +26,7 @@ from typing import List, Optional, Sequence
 
 import numpy as np
 
-CONFIG_SEEDS = {"c0": 1000, "c1": 1001, "c2": 1002, "c3": 1003, "c4": 1004, "paper": 1005}
+CONFIG_SEEDS = {"c0": 1000, "c1": 1001, "c2": 1002, "c3": 1003, "c4": 1004, "paper": 1005, "mpc": 1006}
 
 
 @dataclass
@@ -192,8 +192,10 @@ def random_problem(
     E.append(rng.standard_normal((terminal_rows, nx[N])))
     x0 = rng.standard_normal(nx[0])
 
+    traj = None
     if g_mode == "trajectory":
         xs, us = feasible_trajectory(rng, A, B, c, x0)
+        traj = (xs, us)
         g = [-(E[i] @ xs[i] + F[i] @ us[i]) for i in range(N)]
         g.append(-(E[N] @ xs[N]))
     elif g_mode == "random":
@@ -210,7 +212,10 @@ def random_problem(
         F[i] = np.vstack([F[i], a @ F[i]])
         g[i] = np.concatenate([g[i], [a @ g[i]]])
 
-    return Problem(Q, q, R, r, M, A, B, c, E, F, g, x0)
+    p = Problem(Q, q, R, r, M, A, B, c, E, F, g, x0)
+    if traj is not None:
+        p.meta["trajectory"] = traj  # a feasible (x, u), for workloads that need an interior point
+    return p
 
 
 # ----------------------------------------------------------------------------
@@ -310,6 +315,23 @@ def config_paper(N: int, seed: int = CONFIG_SEEDS["paper"]) -> List[Problem]:
     return [p]
 
 
+def config_mpc(seed: int = CONFIG_SEEDS["mpc"], B: int = 256, N: int = 128, width: float = 0.5) -> List[Problem]:
+    """Bound-constrained batch for the interior-point driver: the differentiable
+    batch's shape (256 instances, N=128, n=16, m=8, 3 mixed rows per stage),
+    offsets from a bounded random feasible trajectory, and box bounds on every
+    input at +-width around that trajectory's inputs, so the bounded problem is
+    feasible with the trajectory strictly inside (p.meta["bounds"]: u_lo, u_hi
+    per stage)."""
+    out = []
+    for rng in _stream(seed, B):
+        p = random_problem(rng, [16] * (N + 1), [8] * N, [["mixed"] * 3] * N, terminal_rows=0,
+                           g_mode="trajectory")
+        us = p.meta.pop("trajectory")[1]
+        p.meta = {"config": "mpc", "bounds": {"u_lo": [v - width for v in us], "u_hi": [v + width for v in us]}}
+        out.append(p)
+    return out
+
+
 def make_config(name: str, **kw) -> List[Problem]:
     return {"c0": config_c0, "c1": config_c1, "c2": config_c2, "c3": config_c3,
-            "c4": config_c4, "paper": config_paper}[name](**kw)
+            "c4": config_c4, "paper": config_paper, "mpc": config_mpc}[name](**kw)
