@@ -129,29 +129,45 @@ def replay_bytes(plan):
 
 
 def roofline(prof, work, replay_b, passes):
-    """The class with the most time per solve: achieved = algorithmic work
-    per solve / its time per solve (per launch: the same ratio)."""
-    dom = max((k for k in prof if prof[k][1] > 0), key=lambda k: prof[k][0])
+    """The class with the most time per solve among those that do work in it
+    (achieved = algorithmic work per solve / its time per solve, which per
+    launch is the same ratio).  A class whose launches do no work in this
+    solve (replay when no instance refines: its workgroups exit at once) is
+    listed under "skipped" with its time and launch count instead."""
+    def work_of(k):
+        return replay_b * passes if k == "replay" else work.get(k, 0.0)
+    live = [k for k in prof if prof[k][1] > 0 and work_of(k) > 0]
+    skipped = [{"kernel": k, "ms_per_solve": prof[k][0], "launches_per_solve": prof[k][1],
+                "reason": "no modeled work in this solve (launches whose workgroups return at once)"}
+               for k in prof if prof[k][1] > 0 and work_of(k) <= 0 and prof[k][0] >= max(v[0] for v in prof.values()) * 0.25]
+    dom = max(live, key=lambda k: prof[k][0])
     ms, launches = prof[dom]
     if dom == "replay":
         achieved = replay_b * passes / (ms * 1e-3) / 1e9
-        return {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "bytes_per_solve": replay_b * passes, "ms_per_solve": ms,
-                "launches_per_solve": launches, "avg_launch_us": ms * 1e3 / max(launches, 1)}
-    achieved = work.get(dom, 0.0) / (ms * 1e-3) / 1e12
-    return {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "flops_per_solve": work.get(dom, 0.0), "ms_per_solve": ms,
-            "launches_per_solve": launches, "avg_launch_us": ms * 1e3 / max(launches, 1)}
+        out = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": achieved / HBM_PEAK_GBS, "bytes_per_solve": replay_b * passes, "ms_per_solve": ms,
+               "launches_per_solve": launches, "avg_launch_us": ms * 1e3 / max(launches, 1)}
+    else:
+        achieved = work.get(dom, 0.0) / (ms * 1e-3) / 1e12
+        out = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+               "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "flops_per_solve": work.get(dom, 0.0), "ms_per_solve": ms,
+               "launches_per_solve": launches, "avg_launch_us": ms * 1e3 / max(launches, 1)}
+    if skipped:
+        out["skipped"] = skipped
+    return out
 
 
-def measure(ecl, torch, workload, problems, steps, warmup, graph=1, autotune=1, scan_schedule=0):
+def measure(ecl, torch, workload, problems, steps, warmup, graph=1, autotune=1, scan_schedule=0, tuning=None):
     """Autotuned solve of one workload: wall ms per solve (graph replay),
-    per-class profile, method-work roofline of the dominant class."""
+    per-class profile, method-work roofline of the dominant class.  With
+    autotune = 0, `tuning` (a dict of eclqr_tuning fields) is applied instead."""
     plan = ecl.Plan.for_problems(problems, use_graph=graph, scan_schedule=scan_schedule)
     data = ecl.pack(plan, problems)
     ws = plan.workspace()
     sol = ecl.allocate_solution(plan)
     stages = sum(p.N for p in problems)
+    if not autotune and tuning:
+        ecl.set_tuning(plan, **tuning)
     tuning = ecl.autotune(plan, data, ws, sol) if autotune else ecl.get_tuning(plan)
     ms = time_solves(ecl, torch, plan, data, ws, sol, steps, warmup)
     status_ok = int((sol.status != 0).sum().item()) == 0
@@ -405,6 +421,8 @@ def main():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--graph", type=int, default=1, help="replay the solve as a captured hipGraph (1) or launch eagerly (0)")
     ap.add_argument("--autotune", type=int, default=1, help="choose the launch configuration by timing first (untimed)")
+    ap.add_argument("--tuning", default=None, metavar="JSON",
+                    help="with --autotune 0: eclqr_tuning fields to set, e.g. the configuration an autotuned run chose")
     ap.add_argument("--scan-schedule", type=int, default=0, choices=(0, 1, 2),
                     help="scan parenthesization: 0 automatic, 1 balanced up/down sweep, 2 recursive doubling")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -439,7 +457,7 @@ def main():
     import paper_2407_05433_amd as ecl
 
     head, plan, data = measure(ecl, torch, args.workload, problems, args.steps, args.warmup, args.graph,
-                               args.autotune, args.scan_schedule)
+                               args.autotune, args.scan_schedule, json.loads(args.tuning) if args.tuning else None)
     roof = dict(head["roofline"])
     roof["traffic"] = stored_traffic(roof["kernel"], args.workload)
     del plan, data

@@ -127,9 +127,10 @@ typedef struct {
                            * stage's stationarity rows; computed at the refined primal point (the refinement
                            * itself uses route 1).  Equal to route 1 under LICQ, otherwise another valid
                            * representative. 1 */
-  int32_t refine;         /* most steps of iterative refinement per instance (0..4); 3.  A refined
-                           * instance whose final KKT backward error exceeds dual_cons_tol reports
-                           * ECLQR_DUAL_FAILED */
+  int32_t refine;         /* most steps of iterative refinement per instance (0..4); 2 (no instance of the
+                           * benchmark workloads takes more; every step is one vector-only pass whose
+                           * launches run even when no instance refines).  A refined instance whose final
+                           * KKT backward error exceeds dual_cons_tol reports ECLQR_DUAL_FAILED */
   int32_t use_graph;      /* 1: capture the launch sequence of eclqr_solve once per set of pointers and
                            * replay it as a hipGraph; 0 */
   int32_t scan_schedule;  /* parenthesization of the associative scans (Proposition 1 allows any): 1 balanced

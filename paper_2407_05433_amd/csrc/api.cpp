@@ -83,6 +83,7 @@ DevEngine dev_engine(const Engine& E, void* ws, size_t base) {
   d.slot_cap = reinterpret_cast<const int32_t*>(b + E.o_slot_cap);
   d.slot_rows = reinterpret_cast<int32_t*>(b + E.o_slot_rows);
   d.tasks = reinterpret_cast<const int32_t*>(b + E.o_tasks);
+  d.ric_perm = E.ric_perm.empty() ? nullptr : reinterpret_cast<const int32_t*>(b + E.o_ric_perm);
   d.nbar = reinterpret_cast<int32_t*>(b + E.o_nbar);
   d.mbar = reinterpret_cast<int32_t*>(b + E.o_mbar);
   d.arena = reinterpret_cast<double*>(b + E.o_arena);
@@ -136,6 +137,9 @@ eclqr_status upload_engine(const Engine& E, void* ws, size_t base, hipStream_t s
   HIP_OK(hipMemcpyAsync(b + E.o_slot_cap, E.slot_cap.data(), sizeof(int32_t) * E.nslots, hipMemcpyHostToDevice, s));
   if (!E.tasks.empty())
     HIP_OK(hipMemcpyAsync(b + E.o_tasks, E.tasks.data(), sizeof(int32_t) * E.tasks.size(), hipMemcpyHostToDevice, s));
+  if (!E.ric_perm.empty())
+    HIP_OK(hipMemcpyAsync(b + E.o_ric_perm, E.ric_perm.data(), sizeof(int32_t) * E.ric_perm.size(),
+                          hipMemcpyHostToDevice, s));
   HIP_OK(hipMemcpyAsync(b + E.o_sbase, E.sbase.data(), sizeof(int64_t) * E.B, hipMemcpyHostToDevice, s));
   if (E.nslots > 0) {
     HIP_OK(hipMemcpyAsync(b + E.o_rel_log_off, E.rel_log_off.data(), sizeof(int64_t) * E.nslots,
@@ -290,8 +294,14 @@ eclqr_status run_engine(const Engine& E, const DevEngine& d, const Inputs& in, d
   for (int l = 0; l < 2 * E.D; ++l) {
     if (E.lvl_count[l] == 0) continue;
     {
+      // one launch per dim bucket (tasks in ric_perm order), or the whole level
       Timed tm(ECLQR_K_RIC_COMBINE, s);
-      launch_ric_combine(d, E.lvl_begin[l], E.lvl_count[l], status, std::max(1, E.lvl_dim[l]), s);
+      if (g_buckets) {
+        for (int k = E.lvl_rbk_first[l]; k < E.lvl_rbk_first[l] + E.lvl_rbk_n[l]; ++k)
+          launch_ric_combine(d, E.rbk_begin[k], E.rbk_count[k], status, std::max(1, E.rbk_dim[k]), s);
+      } else {
+        launch_ric_combine(d, E.lvl_begin[l], E.lvl_count[l], status, std::max(1, E.lvl_dim[l]), s);
+      }
     }
     if ((sst = at_step(1, l)) != ECLQR_SUCCESS) return sst;
   }
@@ -1155,7 +1165,7 @@ void eclqr_default_options(eclqr_options* opt) {
   opt->refine_tol = 1e-8;
   opt->accept_tol = 1e-10;
   opt->multipliers = 1;
-  opt->refine = 3;
+  opt->refine = 2;
   opt->use_graph = 0;
   opt->domain_shortcut = 1;
 }

@@ -670,6 +670,10 @@ __device__ __forceinline__ void ric_move(double* dst, const RicLayout& ld, const
   }
 }
 
+// Task of position t of a value-function combine launch (the plan's dim-bucket
+// order, else the level's own order).
+__device__ __forceinline__ int64_t ric_task(const DevEngine& e, int64_t t) { return e.ric_perm ? e.ric_perm[t] : t; }
+
 // kMode 0: work pool in per-block global scratch; 1: pool in LDS; 2: both
 // operands, the result and the pool in LDS (operands staged in, result
 // written out in bulk), every barrier LDS-only.
@@ -689,9 +693,9 @@ __global__ void __launch_bounds__(kBlock, 1) k_ric_combine(DevEngine e, int64_t 
   double* sh = (double*)(piv + kMaxDim);
   double* buf = sh + 16;
   for (int64_t ti = blockIdx.x; ti < ntasks; ti += gridDim.x) {
-    const int a = e.tasks[3 * (first + ti)];
-    const int bsl = e.tasks[3 * (first + ti) + 1];
-    const int o = e.tasks[3 * (first + ti) + 2];
+    const int a = e.tasks[3 * ric_task(e, first + ti)];
+    const int bsl = e.tasks[3 * ric_task(e, first + ti) + 1];
+    const int o = e.tasks[3 * ric_task(e, first + ti) + 2];
     const int sa = slot_a(e, 0, a), sm = slot_b(e, 0, a), se = slot_b(e, 0, bsl);
     if (gated(e, e.st[sa].inst)) continue;
     const int ds = e.nbar[sa], dm = e.nbar[sm], de = (se >= 0) ? e.nbar[se] : 0;
@@ -752,9 +756,9 @@ __global__ void __launch_bounds__(2 * kBlock, 1) k_ric_combine_split(DevEngine e
   double* sh = (double*)(okf + 4) + wave * (16 + kMaxDim);
   double* buf = sh + 16;
   for (int64_t ti = blockIdx.x; ti < ntasks; ti += gridDim.x) {
-    const int a = e.tasks[3 * (first + ti)];
-    const int bsl = e.tasks[3 * (first + ti) + 1];
-    const int o = e.tasks[3 * (first + ti) + 2];
+    const int a = e.tasks[3 * ric_task(e, first + ti)];
+    const int bsl = e.tasks[3 * ric_task(e, first + ti) + 1];
+    const int o = e.tasks[3 * ric_task(e, first + ti) + 2];
     const int sa = slot_a(e, 0, a), sm = slot_b(e, 0, a), se = slot_b(e, 0, bsl);
     if (gated(e, e.st[sa].inst)) continue;  // the same for both wavefronts
     const int ds = e.nbar[sa], dm = e.nbar[sm], de = (se >= 0) ? e.nbar[se] : 0;

@@ -17,6 +17,7 @@ struct DevEngine {
   const int32_t* slot_cap;    // REL row capacity
   int32_t* slot_rows;         // REL rows written by the kernels
   const int32_t* tasks;       // (left, right, out) triples
+  const int32_t* ric_perm;    // launch order of the value-function combines (absolute task indices), null = identity
   int32_t* nbar;              // reduced state dim per stage
   int32_t* mbar;              // reduced input dim per stage
   double* arena;              // stage arenas

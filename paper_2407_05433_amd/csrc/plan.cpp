@@ -386,6 +386,49 @@ std::string Engine::build(const eclqr_dims* d) {
     }
     lvl_bkt_n[l] = (int32_t)bkt_begin.size() - lvl_bkt_first[l];
   }
+  // Value-function combine buckets.  Its LDS grows with the square of the
+  // largest endpoint dim of a launch, and LDS bounds how many workgroups a
+  // compute unit holds; a wide level (>= 2048 tasks) is launched in ranges of
+  // one dim class each (<= 8, 12, 16, 24, 32, 48, 64; ranges of fewer than
+  // 512 tasks join the next class) over its tasks ordered by that dim.
+  ric_perm.resize(tasks.size() / 3);
+  rbk_begin.clear();
+  rbk_count.clear();
+  rbk_dim.clear();
+  lvl_rbk_first.assign(2 * D, 0);
+  lvl_rbk_n.assign(2 * D, 0);
+  auto dim_class = [](int d) {
+    const int bounds[] = {8, 12, 16, 24, 32, 48, 64};
+    for (int b : bounds)
+      if (d <= b) return b;
+    return d;
+  };
+  for (int l = 0; l < 2 * D; ++l) {
+    const int64_t b0 = lvl_begin[l], nt = lvl_count[l];
+    std::vector<std::pair<int32_t, int32_t>> dv((size_t)nt);  // (dim, absolute task)
+    for (int64_t t = 0; t < nt; ++t)
+      dv[t] = {task_dim(tasks[3 * (b0 + t)], tasks[3 * (b0 + t) + 1]), (int32_t)(b0 + t)};
+    if (nt >= 2048) std::stable_sort(dv.begin(), dv.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+    for (int64_t t = 0; t < nt; ++t) ric_perm[b0 + t] = dv[t].second;
+    lvl_rbk_first[l] = (int32_t)rbk_begin.size();
+    int64_t t = 0;
+    while (t < nt) {
+      int64_t u = nt;
+      if (nt >= 2048) {
+        u = t + 1;
+        while (u < nt && dim_class(dv[u].first) == dim_class(dv[t].first)) ++u;
+        while (u < nt && u - t < 512) ++u;
+        if (nt - u < 512) u = nt;
+      }
+      int dim = 0;
+      for (int64_t v = t; v < u; ++v) dim = std::max(dim, dv[v].first);
+      rbk_begin.push_back(b0 + t);
+      rbk_count.push_back(u - t);
+      rbk_dim.push_back(dim);
+      t = u;
+    }
+    lvl_rbk_n[l] = (int32_t)rbk_begin.size() - lvl_rbk_first[l];
+  }
   // per-stage kernel sizes
   base_maxp = 1;
   base_ldw = 1;
@@ -438,6 +481,7 @@ std::string Engine::build(const eclqr_dims* d) {
   o_slot_cap = o; o = align256(o + sizeof(int32_t) * nslots);
   o_slot_rows = o; o = align256(o + sizeof(int32_t) * nslots);
   o_tasks = o; o = align256(o + sizeof(int32_t) * tasks.size() + 16);
+  o_ric_perm = o; o = align256(o + sizeof(int32_t) * ric_perm.size() + 16);
   o_nbar = o; o = align256(o + sizeof(int32_t) * S);
   o_mbar = o; o = align256(o + sizeof(int32_t) * S);
   o_resid = o; o = align256(o + sizeof(double) * 4 * S);

@@ -47,6 +47,13 @@ struct Engine {
   std::vector<int32_t> bkt_fit;     // every task of the bucket fits the register-resident composition
   std::vector<int32_t> lvl_kc;      // REL: max (n_a + n_c) over the level
   std::vector<int32_t> lvl_bkt_first, lvl_bkt_n;
+  // value-function combine buckets: the tasks of each level reordered by their
+  // endpoint dims (ric_perm: absolute task indices, in launch order) and cut
+  // into ranges with their own LDS sizing (rbk_dim)
+  std::vector<int32_t> ric_perm;
+  std::vector<int64_t> rbk_begin, rbk_count;
+  std::vector<int32_t> rbk_dim;
+  std::vector<int32_t> lvl_rbk_first, lvl_rbk_n;
 
   // factor logs replayed by the vector-only pass, per output slot
   std::vector<int64_t> rel_log_off, ric_log_off;
@@ -70,7 +77,7 @@ struct Engine {
   size_t o_stage = 0, o_slot_off = 0, o_slot_na = 0, o_slot_nb = 0, o_slot_cap = 0, o_slot_rows = 0,
          o_tasks = 0, o_nbar = 0, o_mbar = 0, o_arena = 0, o_scan[SCAN_COUNT] = {0, 0, 0}, o_resid = 0,
          o_sbase = 0, o_scratch = 0, o_rel_log_off = 0, o_ric_log_off = 0, o_rel_log = 0, o_ric_log = 0,
-         o_theta = 0, o_vac = 0, o_gw = 0;
+         o_theta = 0, o_vac = 0, o_gw = 0, o_ric_perm = 0;
   size_t bytes = 0;
 
   std::string build(const eclqr_dims* d);

@@ -41,7 +41,7 @@ def test_status_strings_and_defaults():
     assert L.eclqr_status_string(0) == b"ok"
     assert L.eclqr_status_string(2) == b"infeasible_initial"
     o = ecl.default_options()
-    assert o.rank_tol == 1e-10 and o.cons_tol == 1e-8 and o.multipliers == 1 and o.refine == 3 and o.refine_tol == 1e-8
+    assert o.rank_tol == 1e-10 and o.cons_tol == 1e-8 and o.multipliers == 1 and o.refine == 2 and o.refine_tol == 1e-8
     assert o.domain_shortcut == 1 and o.reversed_time == 0 and o.scan_schedule == 0
 
 
