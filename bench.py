@@ -419,6 +419,8 @@ def main():
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--no-single-loop", action="store_true",
+                    help="skip the one-by-one solves of the batch (counter runs of the batched solve)")
     ap.add_argument("--graph", type=int, default=1, help="replay the solve as a captured hipGraph (1) or launch eagerly (0)")
     ap.add_argument("--autotune", type=int, default=1, help="choose the launch configuration by timing first (untimed)")
     ap.add_argument("--tuning", default=None, metavar="JSON",
@@ -482,7 +484,7 @@ def main():
         "kernel_ms_per_solve": head["kernel_ms_per_solve"],
         "launches_per_solve": head["launches_per_solve"],
     }
-    if args.workload == "c3":
+    if args.workload == "c3" and not args.no_single_loop:
         log("[bench] the same 512 instances one after another (single-instance plans)")
         loop_ms, ok = single_loop(ecl, torch, problems)
         line["batched_vs_single"] = {"batched_ms": head["ms_per_solve"], "batched_stages_per_s": head["stages_per_s"],

@@ -293,15 +293,15 @@ eclqr_status run_engine(const Engine& E, const DevEngine& d, const Inputs& in, d
   { Timed tm(ECLQR_K_ELIMINATE, s); launch_eliminate(d, in, t, status, std::max(1, E.maxm), E.elim_maxq, std::max(1, E.maxn), E.maxk, s); }
   for (int l = 0; l < 2 * E.D; ++l) {
     if (E.lvl_count[l] == 0) continue;
-    {
-      // one launch per dim bucket (tasks in ric_perm order), or the whole level
-      Timed tm(ECLQR_K_RIC_COMBINE, s);
-      if (g_buckets) {
-        for (int k = E.lvl_rbk_first[l]; k < E.lvl_rbk_first[l] + E.lvl_rbk_n[l]; ++k)
-          launch_ric_combine(d, E.rbk_begin[k], E.rbk_count[k], status, std::max(1, E.rbk_dim[k]), s);
-      } else {
-        launch_ric_combine(d, E.lvl_begin[l], E.lvl_count[l], status, std::max(1, E.lvl_dim[l]), s);
+    // one launch per dim bucket (tasks in ric_perm order), or the whole level
+    if (g_buckets) {
+      for (int k = E.lvl_rbk_first[l]; k < E.lvl_rbk_first[l] + E.lvl_rbk_n[l]; ++k) {
+        Timed tm(ECLQR_K_RIC_COMBINE, s);
+        launch_ric_combine(d, E.rbk_begin[k], E.rbk_count[k], status, std::max(1, E.rbk_dim[k]), s);
       }
+    } else {
+      Timed tm(ECLQR_K_RIC_COMBINE, s);
+      launch_ric_combine(d, E.lvl_begin[l], E.lvl_count[l], status, std::max(1, E.lvl_dim[l]), s);
     }
     if ((sst = at_step(1, l)) != ECLQR_SUCCESS) return sst;
   }
