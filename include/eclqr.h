@@ -68,13 +68,25 @@ typedef enum {
 #define ECLQR_INFEASIBLE_SUFFIX 1   /* some suffix relation reads 0 = gamma (Algorithm 1) */
 #define ECLQR_INFEASIBLE_INITIAL 2  /* x0 outside X_0 (eq. (initial-feasibility)) */
 #define ECLQR_RANK_INCONSISTENT 4   /* nonzero residual after Lemma 2 (rank decisions) */
-#define ECLQR_NOT_CONVEX 8          /* a reduced input Hessian is not positive definite */
+#define ECLQR_NOT_CONVEX 8          /* the costs are not positive definite on the feasible set: the scan
+                                       route's reduced input Hessians are not, and the sequential
+                                       fallback (which solves every instance whose minimiser is unique)
+                                       found no unique minimiser either; ECLQR_NO_MINIMIZER when it shows
+                                       that none exists, neither bit added when it cannot decide (a
+                                       singular stage Hessian whose null space meets the state feedback) */
 #define ECLQR_INVALID_INPUT 16      /* NaN or Inf in the data */
 #define ECLQR_CAPACITY 32           /* a relation outgrew its on-chip tile */
 #define ECLQR_DUAL_FAILED 64        /* the multiplier (stationarity) solve failed; its own
                                        outcome bits are repeated in bits 8..15 */
 #define ECLQR_TIMEOUT (1 << 16)      /* a bounded wait of a persistent scan kernel expired (2 s of wall
                                        clock): the outputs are not valid */
+#define ECLQR_NO_MINIMIZER (1 << 17)  /* with ECLQR_NOT_CONVEX: the problem has no minimiser (the cost falls
+                                        without bound on the feasible set; Section II, the paragraph after
+                                        eq. (convexity)) */
+#define ECLQR_NOT_UNIQUE (1 << 18)    /* informational, outputs valid: the costs are not positive definite on the
+                                        feasible set; a minimiser exists but is not unique and the one
+                                        returned has no component along the flat input directions.  Test
+                                        (status & ~ECLQR_NOT_UNIQUE) == 0 for usable outputs */
 #define ECLQR_NOT_DIFFERENTIABLE 128 /* eclqr_backward only: the instance's constraint rows are
                                        dependent (LICQ fails: a redundant row, or rows that together
                                        with x_0 = x0 restrict x_0), so its multipliers are not unique

@@ -26,6 +26,8 @@ STATUS_BITS = {
     64: "dual_failed",
     128: "not_differentiable",
     1 << 16: "timeout",
+    1 << 17: "no_minimizer",
+    1 << 18: "not_unique",
 }
 
 

@@ -21,7 +21,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libeclqr.so")
 
 HIP_SOURCES = ["k_relations.hip", "k_eliminate.hip", "k_lqr.hip", "k_aux.hip", "k_replay.hip", "k_fast.hip",
-               "k_expand.hip", "noalloc.hip", "k_ipm.hip"]
+               "k_expand.hip", "noalloc.hip", "k_ipm.hip", "k_dp.hip"]
 CPP_SOURCES = ["plan.cpp", "api.cpp"]
 ARCH = "gfx950"
 

@@ -696,6 +696,20 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
     HIP_OK(hipStreamWaitEvent(s, theta_join, 0));
   }
   if (st != ECLQR_SUCCESS) return st;
+  int32_t* dpflag = at<int32_t>(v.ws, p.o_dpflag);
+  if (!replay) {
+    // Instances the scan rejected as not convex (reduced input Hessians not
+    // positive definite stage by stage) go through the sequential fallback
+    // while the stage arenas still hold this problem's data: a unique
+    // minimiser is solved (with the value functions and reduced states the
+    // multiplier routes read), the other cases are classified.  Solved
+    // instances take no refinement step (their factorizations are not the
+    // scan's) and the factor-reusing route cannot serve them.
+    Timed tm(ECLQR_K_OTHER, s);
+    launch_dp_fallback(v.P, in, v.psbase, x, u, status, v.P.info, dpflag, at<double>(v.ws, p.o_dp), p.dp_stride,
+                       p.dp_blocks, std::max(1, p.primal.maxn), std::max(1, p.primal.maxm), s);
+    if (want_mult && fast) launch_flag_where(dpflag, status, ECLQR_DUAL_FAILED, B, s);
+  }
   if (!want_mult) return ECLQR_SUCCESS;
   if (dual_join) {
     // the reversed-time problem was factored on the second stream
@@ -725,6 +739,7 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
     launch_merge_dual_bits(status, v.dstatus, ECLQR_DUAL_FAILED, kDualStructural, B, s);
     launch_backward_error(v.P, in, x, u, lam, mu, at<unsigned long long>(v.ws, p.o_wmax), v.omega, s);
     launch_accept(v.omega, v.dstatus, p.opt.accept_tol, v.gate, B, s);
+    if (!replay) launch_dp_hold(dpflag, v.gate, B, s);
   }
   Inputs cin = in;
   cin.f[IN_q] = v.cp.q;
@@ -1180,6 +1195,10 @@ const char* eclqr_status_string(int32_t status) {
     case ECLQR_INVALID_INPUT: return "invalid_input";
     case ECLQR_CAPACITY: return "capacity";
     case ECLQR_DUAL_FAILED: return "dual_failed";
+    case ECLQR_NOT_DIFFERENTIABLE: return "not_differentiable";
+    case ECLQR_TIMEOUT: return "timeout";
+    case ECLQR_NO_MINIMIZER: return "no_minimizer";
+    case ECLQR_NOT_UNIQUE: return "not_unique";
     default: return "multiple";
   }
 }
@@ -1301,6 +1320,8 @@ eclqr_status eclqr_backward(eclqr_plan* plan, const eclqr_problem* prob, const e
   // pass's reduced input dims (kept in the workspace by that solve)
   int32_t* gst = grads->status ? grads->status : at<int32_t>(ws, p.o_gstat);
   launch_licq(v.P, v.psbase, sol->status, gst, s);
+  // instances solved by the sequential fallback have no factorizations to replay
+  launch_flag_where(at<int32_t>(ws, p.o_dpflag), gst, ECLQR_NOT_DIFFERENTIABLE, E.B, s);
   // adjoint outputs live in the caller's gradient buffers q, r until assembly
   double* ax = grads->q;
   double* au = grads->r;

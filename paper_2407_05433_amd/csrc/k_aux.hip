@@ -482,7 +482,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(DevEngine p, const int32_t*
   const double nan = __builtin_nan("");
   for (int64_t s = blockIdx.x; s < p.S; s += gridDim.x) {
     const StageInfo st = p.st[s];
-    if (status[st.inst] == 0) continue;
+    if ((status[st.inst] & ~ECLQR_NOT_UNIQUE) == 0) continue;  // a minimiser, not unique, is kept
     for (int i = ECLQR_TID; i < st.n; i += ECLQR_NT) {
       x[st.in[IN_q] + i] = nan;
       if (lam) lam[st.in[IN_q] + i] = nan;

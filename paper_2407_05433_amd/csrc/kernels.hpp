@@ -154,6 +154,18 @@ void launch_ipm_step(const DevEngine& p, const IpmBounds& bd, double* x, double*
                      const int32_t* nstatus, const int32_t* cstatus, int32_t* status, double tau,
                      unsigned long long* alpha, int32_t* act, int32_t* steps, hipStream_t s);
 
+// Sequential fallback for instances the scan rejects as not convex: doubles
+// of work arrays per workgroup; the solve (classification, x, u, the value
+// functions and z of the scans' suffix slots) of every eligible instance;
+// their gates held out of refinement.
+size_t dp_stride(int maxn, int maxm);
+void launch_dp_fallback(const DevEngine& e, const Inputs& in, const int64_t* sbase, double* x, double* u,
+                        int32_t* status, int32_t* info, int32_t* dpflag, double* scratch, int64_t stride,
+                        int32_t blocks, int maxn, int maxm, hipStream_t s);
+void launch_dp_hold(const int32_t* dpflag, int32_t* gate, int32_t B, hipStream_t s);
+// out[b] |= bit where flag[b] != 0
+void launch_flag_where(const int32_t* flag, int32_t* out, int32_t bit, int32_t B, hipStream_t s);
+
 // vector-only replays of the kernels above (factors logged by the full pass)
 void launch_base_relation_vec(const DevEngine& e, const Inputs& in, int64_t logmax, hipStream_t s);
 void launch_rel_compose_vec(const DevEngine& e, int64_t first, int64_t ntasks, int64_t logmax, hipStream_t s);

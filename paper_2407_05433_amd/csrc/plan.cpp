@@ -692,6 +692,10 @@ std::string build_plan(Plan& p, const eclqr_dims* d, const eclqr_options* opt) {
   p.o_live = o; o = align256(o + sizeof(int32_t));
   p.o_omega = o; o = align256(o + sizeof(double) * std::max<int32_t>(1, P.B));
   p.o_wmax = o; o = align256(o + sizeof(double) * std::max<int32_t>(1, P.B));
+  p.dp_stride = (int64_t)dp_stride(std::max(1, P.maxn), std::max(1, P.maxm));
+  p.dp_blocks = std::max<int32_t>(1, std::min<int32_t>(P.B, 64));
+  p.o_dp = o; o = align256(o + sizeof(double) * (size_t)p.dp_stride * p.dp_blocks);
+  p.o_dpflag = o; o = align256(o + sizeof(int32_t) * std::max<int32_t>(1, P.B));
   p.o_info = o; o = align256(o + sizeof(int32_t) * std::max<int32_t>(1, P.B));
   p.o_gstat = o; o = align256(o + sizeof(int32_t) * std::max<int32_t>(1, P.B));
   p.o_adjc = o; o = align256(o + sizeof(double) * std::max<int64_t>(1, P.total[ECLQR_F_c]));

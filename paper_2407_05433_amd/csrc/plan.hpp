@@ -134,6 +134,10 @@ struct Plan {
   size_t o_live = 0;   // instances still refining (one int)
   size_t o_omega = 0;  // per-instance backward error after the first solve (double bits)
   size_t o_wmax = 0;   // per-instance scale of the unknowns of the backward error (double bits)
+  size_t o_dp = 0;     // work arrays of the sequential fallback (dp_blocks x dp_stride doubles)
+  size_t o_dpflag = 0; // per instance: solved by the sequential fallback
+  int64_t dp_stride = 0;
+  int32_t dp_blocks = 1;
   size_t o_info = 0;   // per-instance failing stage of the last solve (when the caller passes no info buffer)
   size_t o_adjc = 0, o_adjx0 = 0;  // adjoint offsets from dL/dlam (layouts of c and x0)
   size_t o_gstat = 0;  // per-instance outcome of the last backward (when the caller passes no status buffer)

@@ -447,3 +447,66 @@ def test_rows_independent_matches_dense_rank():
         assert a == b, (a, b)
         seen.add(a)
     assert seen == {True, False}
+
+
+# ---------------------------------------------------------------------------
+# existence and uniqueness for arbitrary symmetric costs (Section II)
+# ---------------------------------------------------------------------------
+
+def _flat_input_problem(seed, slope):
+    """An instance whose input 1 of stage 2 acts on nothing (zero column of
+    B and F) and costs nothing quadratically (R_2 zero in that row and
+    column): a flat feasible direction, with linear cost `slope` along it."""
+    from tests._util import tiny_problem
+    p = tiny_problem(seed, N=4, n=3, m=2, kinds=[["mixed"]] * 4, terminal_rows=0)
+    p.B[2][:, 1] = 0.0
+    p.F[2][:, 1] = 0.0
+    p.R[2][1, :] = 0.0
+    p.R[2][:, 1] = 0.0
+    p.r[2][1] = slope
+    return p
+
+
+def test_classify_against_the_definition():
+    """The classifier reproduces what the definition fixes on instances built
+    to be in each class, and each answer is witnessed on the objective
+    itself: the unique minimiser is the dense KKT solution; along the
+    unbounded direction the objective falls without bound; along the flat
+    direction it is constant and the two points satisfy the optimality
+    conditions; a convex instance is unique."""
+    from oracle.dense import solve_dense
+    from oracle.existence import as_trajectory, classify, objective_dense
+    from tests._util import indefinite_cost_problems, tiny_problem
+    p1, p2, p3 = indefinite_cost_problems()
+    convex = tiny_problem(4001, N=6, n=3, m=2, terminal_rows=1)
+    for p in (convex, p1, p2):
+        c = classify(p)
+        assert c["kind"] == "unique", c["kind"]
+        d = solve_dense(p)
+        t = as_trajectory(p, c)
+        assert rel_err(t["x"], d["x"]) <= 1e-9 and rel_err(t["u"], d["u"]) <= 1e-9
+    for p, want in ((p3, None), (_flat_input_problem(4002, 0.7), "unbounded")):
+        c = classify(p)
+        if want:
+            assert c["kind"] == want
+        if c["kind"] == "unbounded":
+            from oracle.dense import dense_kkt
+            H, h, J, b, _ = dense_kkt(p)
+            w0 = -np.linalg.pinv(J) @ b
+            dvec = c["direction"]
+            assert np.linalg.norm(J @ dvec) <= 1e-9  # feasible direction
+            f = [objective_dense(p, w0 + t * dvec) for t in (0.0, 1e3, 1e6)]
+            assert f[2] < f[1] < f[0]
+    c = classify(_flat_input_problem(4002, 0.0))
+    assert c["kind"] == "not_unique"
+    from oracle.dense import dense_kkt
+    H, h, J, b, _ = dense_kkt(_flat_input_problem(4002, 0.0))
+    w, dvec = c["w"], c["direction"]
+    assert np.linalg.norm(J @ dvec) <= 1e-9 and np.linalg.norm(J @ w + b) <= 1e-9
+    f0 = objective_dense(_flat_input_problem(4002, 0.0), w)
+    f1 = objective_dense(_flat_input_problem(4002, 0.0), w + 5.0 * dvec)
+    assert abs(f1 - f0) <= 1e-9 * max(1.0, abs(f0))
+    # both points are stationary on the feasible set
+    Wn = __import__("scipy.linalg", fromlist=["null_space"]).null_space(J)
+    for pt in (w, w + 5.0 * dvec):
+        assert np.linalg.norm(Wn.T @ (H @ pt + h)) <= 1e-9
