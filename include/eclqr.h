@@ -298,7 +298,7 @@ typedef struct {
   const double *u_lo, *u_hi, *x_lo, *x_hi;
 } eclqr_bounds;
 
-/* Method parameters (eclqr_ipm_default_params: 30, 1e-8, 0.995, 100, 0.25, 1). */
+/* Method parameters (eclqr_ipm_default_params: 30, 1e-8, 0.995, 100, 0.25, 1, 2). */
 typedef struct {
   int32_t iterations; /* predictor-corrector iterations at most (every instance is solved in each; >= 0) */
   double mu_stop;     /* an instance stops once its mean complementarity is below this (the Newton
@@ -310,6 +310,10 @@ typedef struct {
                        * max(1, |bound|)) inside each finite bound, in (0, 0.5) */
   int32_t corrector_replay; /* 1: the corrector replays the predictor's factorizations (its matrices are
                              * the same); 0: the corrector is a full solve */
+  int32_t newton_refine;    /* refinement steps of each Newton solve (0..4; the plan's refine applies to the
+                             * start solve only).  Fewer steps are faster, but near the solution the Newton
+                             * matrices are ill-conditioned and the multipliers of an unrefined pass leave
+                             * stationarity residuals of about 1e-5 on the test instances; 2 */
 } eclqr_ipm_params;
 
 /* Device outputs: the last iterate of each instance. */

@@ -73,7 +73,7 @@ class BoundPtrs(C.Structure):
 
 class IpmParams(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("mu_stop", C.c_double), ("tau", C.c_double), ("mu0", C.c_double),
-                ("interior", C.c_double), ("corrector_replay", C.c_int32)]
+                ("interior", C.c_double), ("corrector_replay", C.c_int32), ("newton_refine", C.c_int32)]
 
 
 class IpmSolutionPtrs(C.Structure):

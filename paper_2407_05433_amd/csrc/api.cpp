@@ -1613,6 +1613,7 @@ void eclqr_ipm_default_params(eclqr_ipm_params* prm) {
   prm->mu0 = 100.0;
   prm->interior = 0.25;
   prm->corrector_replay = 1;
+  prm->newton_refine = 2;
 }
 
 eclqr_status eclqr_ipm_workspace_size(const eclqr_plan* plan, size_t* bytes) {
@@ -1633,9 +1634,10 @@ eclqr_status eclqr_ipm_solve(eclqr_plan* plan, const eclqr_problem* prob, const 
   if (p.opt.multipliers == 0)
     return fail(ECLQR_INVALID_ARGUMENT, "the interior-point driver needs a plan with multipliers (1, 2 or 3)");
   if (prm->iterations < 0 || !(prm->tau > 0.0 && prm->tau < 1.0) || !(prm->mu0 > 0.0) ||
-      !(prm->interior > 0.0 && prm->interior < 0.5) || !(prm->mu_stop >= 0.0))
+      !(prm->interior > 0.0 && prm->interior < 0.5) || !(prm->mu_stop >= 0.0) || prm->newton_refine < 0 ||
+      prm->newton_refine > 4)
     return fail(ECLQR_INVALID_ARGUMENT, "parameters: iterations >= 0, 0 < tau < 1, mu0 > 0, 0 < interior < 0.5, "
-                                        "mu_stop >= 0");
+                                        "mu_stop >= 0, 0 <= newton_refine <= 4");
   const int64_t nq = E.total[ECLQR_F_q], nr = E.total[ECLQR_F_r], ng = E.total[ECLQR_F_g];
   const void* req[] = {sol->x, sol->u, sol->lam, sol->mu, sol->z_ulo, sol->z_uhi, sol->z_xlo, sol->z_xhi, sol->status};
   const int64_t need[] = {nq, nr, nq, ng, nr, nr, nq, nq, 1};
@@ -1725,15 +1727,23 @@ eclqr_status eclqr_ipm_solve(eclqr_plan* plan, const eclqr_problem* prob, const 
   // stops short of dual_cons_tol still takes its step
   struct Inexact {
     Plan& p;
-    explicit Inexact(Plan& q) : p(q) { p.inexact_newton = true; }
-    ~Inexact() { p.inexact_newton = false; }
-  } inexact(p);
+    int32_t refine;
+    Inexact(Plan& q, int32_t r) : p(q), refine(q.opt.refine) {
+      p.inexact_newton = true;
+      p.opt.refine = r;
+    }
+    ~Inexact() {
+      p.inexact_newton = false;
+      p.opt.refine = refine;
+    }
+  } inexact(p, prm->newton_refine);
   if (p.opt.use_graph && !p.profiling && prm->iterations > 0) {
     std::vector<const void*> key = {ws, prob->Q, prob->q, prob->R, prob->r, prob->M, prob->A, prob->B, prob->c,
                                     prob->E, prob->F, prob->g, prob->x0, bounds->u_lo, bounds->u_hi, bounds->x_lo,
                                     bounds->x_hi, c.x, c.u, c.lam, c.mu, c.z.ul, c.z.uh, c.z.xl, c.z.xh, c.status,
                                     c.steps, c.comp, bits_key(c.tau), bits_key(c.mu_stop),
-                                    reinterpret_cast<const void*>(static_cast<uintptr_t>(c.replay))};
+                                    reinterpret_cast<const void*>(static_cast<uintptr_t>(c.replay)),
+                                    reinterpret_cast<const void*>(static_cast<uintptr_t>(prm->newton_refine))};
     for (int it = 0; it < prm->iterations; ++it)
       if ((st = ipm_iteration_graph(p, v, c, key, s)) != ECLQR_SUCCESS) return st;
   } else {

@@ -288,7 +288,8 @@ def test_ipm_structs_defaults_and_argument_errors():
     assert [f for f, _ in _lib.IpmParams._fields_] == fields("eclqr_ipm_params")
     assert [f for f, _ in _lib.IpmSolutionPtrs._fields_] == fields("eclqr_ipm_solution")
     d = ecl.ipm_default_params()
-    assert d == {"iterations": 30, "mu_stop": 1e-8, "tau": 0.995, "mu0": 100.0, "interior": 0.25, "corrector_replay": 1}
+    assert d == {"iterations": 30, "mu_stop": 1e-8, "tau": 0.995, "mu0": 100.0, "interior": 0.25, "corrector_replay": 1,
+                 "newton_refine": 2}
     L = _lib.lib()
     dims = [([3, 3, 3, 3], [2, 2, 2], [1, 0, 1, 0])]
     plan = ecl.Plan(dims)
@@ -307,7 +308,8 @@ def test_ipm_structs_defaults_and_argument_errors():
 
     assert call(ecl.Plan(dims, multipliers=0)) == 1
     assert b"multipliers" in L.eclqr_last_error()
-    for bad in ({"tau": 1.0}, {"tau": 0.0}, {"mu0": 0.0}, {"interior": 0.5}, {"iterations": -1}, {"mu_stop": -1.0}):
+    for bad in ({"tau": 1.0}, {"tau": 0.0}, {"mu0": 0.0}, {"interior": 0.5}, {"iterations": -1}, {"mu_stop": -1.0},
+                {"newton_refine": 5}):
         assert call(plan, **bad) == 1, bad
     assert call(plan) == 1 and b"NULL output" in L.eclqr_last_error()
     assert L.eclqr_ipm_solve(plan.handle, C.byref(pp), C.byref(bp), None, C.byref(sp), fake_ws, big, None) == 1
