@@ -157,6 +157,15 @@ def roofline(prof, work, replay_b, passes):
     return out
 
 
+def paper_context(ms):
+    """The paper's own number for the same shape (Table I, N = 8192: one
+    instance, n = 8, m = 4, two state-only rows per stage, primal and
+    multipliers, FP64), quoted with its hardware: context, not a target."""
+    return {"source": "Table I, N=8192", "hardware": "NVIDIA Tesla P100 PCIe 16 GiB, CUDA 12.8; CPU: one thread of "
+            "a virtualized 2.0 GHz Xeon", "gpu_kernel_ms": 10.518, "gpu_wall_ms": 17.274, "cpu_1thread_ms": 106.424,
+            "this_ms_per_solve": ms, "paper_gpu_kernel_ms_over_this": 10.518 / ms}
+
+
 def measure(ecl, torch, workload, problems, steps, warmup, graph=1, autotune=1, scan_schedule=0, tuning=None):
     """Autotuned solve of one workload: wall ms per solve (graph replay),
     per-class profile, method-work roofline of the dominant class.  With
@@ -494,13 +503,15 @@ def main():
         log(f"[bench]   {line['batched_vs_single']}")
     if not args.no_secondary:
         sec = {}
-        for w in ("c1", "c2", "c4"):
+        for w in ("c1", "c2", "c4", "paper"):
             if w == args.workload:
                 continue
             log(f"[bench] secondary: {w}")
             r, pl, dt = measure(ecl, torch, w, make(w), max(3, min(args.steps, 10)), 2)
             del pl, dt
             torch.cuda.empty_cache()
+            if w == "paper":
+                r["paper_context"] = paper_context(r["ms_per_solve"])
             sec[w] = r
         log("[bench] secondary: c4 forward + backward")
         sec["c4_fwd_bwd"] = differentiable(ecl, torch, max(2, min(args.steps, 5)))

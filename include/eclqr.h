@@ -379,14 +379,16 @@ typedef struct {
   int32_t use_graph;      /* replay the solve as a captured hipGraph */
   int32_t level_buckets;  /* relation-scan levels with >= 2048 tasks launch in LDS-size buckets */
   int32_t pool_in_lds;    /* value-function combines: 0 work pool in global scratch, 1 pool in LDS, 2 operands,
-                             result and pool in LDS (default); a mode whose LDS does not fit falls back to the
-                             next lower one */
+                             result and pool in LDS, 3 (default) the operands read more than once staged in LDS
+                             with a compact pool, the result written once to global memory (the same bits in
+                             every mode); a mode whose LDS does not fit falls back to the next lower one */
   int32_t grid_divisor;   /* grid of the stage-parallel kernels = its maximum / grid_divisor (1..64) */
   double ms_per_solve;    /* time of the configuration chosen by eclqr_plan_autotune (0 if never tuned) */
   int32_t register_compose; /* relation compositions that fit (<= 64 stacked rows, <= 128 columns) keep the
                              * stacked system in registers instead of LDS */
   int32_t stage_lds;      /* stage eliminations and feedback gains keep their working arrays in LDS when these
-                             need at most 32 KiB per workgroup (1, default), else in global scratch (0) */
+                             need at most 32 KiB per workgroup (1, default), only the feedback gains do (2), or
+                             neither (0: global scratch) */
   int32_t overlap_dual;   /* with the minimum-norm multipliers, 1: the multiplier route's problem is factored
                            * (matrix data only) on a second stream while the primal pass runs, and its vector-only
                            * replay at the primal solution gives the multipliers; 0: one stream, full pass after

@@ -70,7 +70,7 @@ T* at(void* ws, size_t off) {
 // an earlier solve of the plan created it.
 thread_local bool g_noalloc = false;
 
-int32_t g_pool_lds = 2, g_grid_div = 1, g_buckets = 1, g_reg = 1, g_stage_lds = 1,
+int32_t g_pool_lds = 3, g_grid_div = 1, g_buckets = 1, g_reg = 1, g_stage_lds = 1,
         g_split = 1;  // tuning of the plan being launched
 
 DevEngine dev_engine(const Engine& E, void* ws, size_t base) {
@@ -104,6 +104,7 @@ DevEngine dev_engine(const Engine& E, void* ws, size_t base) {
   d.B = E.B;
   d.nslots = E.nslots;
   d.nblocks = std::max<int32_t>(1, E.nblocks / std::max<int32_t>(1, g_grid_div));
+  d.task_grid = (g_grid_div <= 1) ? (1 << 30) : d.nblocks;
   d.pool_lds = g_pool_lds;
   d.reg_compose = g_reg;
   d.elim_lds = g_stage_lds;
@@ -560,12 +561,10 @@ eclqr_status theta_multipliers(Plan& p, const Views& v, const Inputs& in, const 
     if (T.lvl_count[l] == 0) continue;
     if (full) {
       Timed tm(ECLQR_K_RIC_COMBINE, s);
-      // theta dims are mostly <= 4: one lane per combine.  On a wide level
-      // the larger combines go to a second launch, one per wavefront, instead
-      // of being run one after another by the wavefront that found them.
-      const bool wide = T.lvl_count[l] > 4096;
-      launch_ric_combine_lane(v.T, T.lvl_begin[l], T.lvl_count[l], wide ? defer + l : nullptr,
-                              wide ? defer + 2 * T.D + 4 : nullptr, s);
+      // theta dims are mostly <= 4: one lane per combine.  The larger
+      // combines go to a second launch, one per wavefront, instead of being
+      // run one after another by the wavefront that found them.
+      launch_ric_combine_lane(v.T, T.lvl_begin[l], T.lvl_count[l], defer + l, defer + 2 * T.D + 4, s);
     } else {
       Timed tm(ECLQR_K_REPLAY, s);
       launch_ric_combine_vec(v.T, T.lvl_begin[l], T.lvl_count[l], std::max(1, T.lvl_dim[l]), s);
@@ -630,9 +629,7 @@ eclqr_status theta_prefactor_step(Plan& p, const Views& v, const Inputs& in, hip
     launch_fill_i32(defer, 0, 2 * T.D, s2);
   } else if (step == 1 && T.lvl_count[l] > 0) {
     Timed tm(ECLQR_K_RIC_COMBINE, s2);
-    const bool wide = T.lvl_count[l] > 4096;
-    launch_ric_combine_lane(Th, T.lvl_begin[l], T.lvl_count[l], wide ? defer + l : nullptr,
-                            wide ? defer + 2 * T.D + 4 : nullptr, s2);
+    launch_ric_combine_lane(Th, T.lvl_begin[l], T.lvl_count[l], defer + l, defer + 2 * T.D + 4, s2);
   } else if (step == 2) {
     {
       Timed tm(ECLQR_K_GAINS, s2);
@@ -1508,14 +1505,15 @@ eclqr_status eclqr_plan_get_tuning(const eclqr_plan* plan, eclqr_tuning* out) {
 eclqr_status eclqr_plan_set_tuning(eclqr_plan* plan, const eclqr_tuning* t) {
   if (!plan || !t) return fail(ECLQR_INVALID_ARGUMENT, "NULL argument");
   if (t->grid_divisor < 1 || t->grid_divisor > 64) return fail(ECLQR_INVALID_ARGUMENT, "grid_divisor out of [1, 64]");
-  if (t->pool_in_lds < 0 || t->pool_in_lds > 2) return fail(ECLQR_INVALID_ARGUMENT, "pool_in_lds out of [0, 2]");
+  if (t->pool_in_lds < 0 || t->pool_in_lds > 3) return fail(ECLQR_INVALID_ARGUMENT, "pool_in_lds out of [0, 3]");
+  if (t->stage_lds < 0 || t->stage_lds > 2) return fail(ECLQR_INVALID_ARGUMENT, "stage_lds out of [0, 2]");
   Plan& p = plan->p;
   p.opt.use_graph = t->use_graph != 0;
   p.level_buckets = t->level_buckets != 0;
   p.pool_lds = t->pool_in_lds;
   p.grid_divisor = t->grid_divisor;
   p.reg_compose = t->register_compose != 0;
-  p.stage_lds = t->stage_lds != 0;
+  p.stage_lds = t->stage_lds;
   p.overlap_dual = t->overlap_dual != 0;
   p.mult_route = (p.theta_ok && (t->multiplier_route != 0 || !p.has_dual)) ? 1 : 0;
   p.split_combine = t->split_combine != 0;
@@ -1558,8 +1556,10 @@ eclqr_status eclqr_plan_autotune(eclqr_plan* plan, const eclqr_problem* prob, ec
     int32_t alt;
   };
   int32_t graph = p.opt.use_graph;
-  Knob knobs[] = {{&p.reg_compose, p.reg_compose ? 0 : 1}, {&p.stage_lds, p.stage_lds ? 0 : 1},
-                  {&p.level_buckets, p.level_buckets ? 0 : 1}, {&p.pool_lds, p.pool_lds == 2 ? 1 : 2},
+  // (a knob listed twice tries two alternatives, each against the best so far)
+  Knob knobs[] = {{&p.reg_compose, p.reg_compose ? 0 : 1}, {&p.stage_lds, p.stage_lds ? 0 : 1}, {&p.stage_lds, 2},
+                  {&p.level_buckets, p.level_buckets ? 0 : 1}, {&p.pool_lds, p.pool_lds == 3 ? 1 : 3},
+                  {&p.pool_lds, 2},
                   {&p.grid_divisor, p.grid_divisor == 1 ? 4 : 1}, {&graph, graph ? 0 : 1},
                   {&p.overlap_dual, p.overlap_dual ? 0 : 1}, {&p.mult_route, p.mult_route ? 0 : 1},
                   {&p.split_combine, p.split_combine ? 0 : 1}};
@@ -1567,6 +1567,7 @@ eclqr_status eclqr_plan_autotune(eclqr_plan* plan, const eclqr_problem* prob, ec
     if (st != ECLQR_SUCCESS) break;
     if (k.v == &p.mult_route && !(p.theta_ok && p.has_dual)) continue;
     if (k.v == &p.overlap_dual && !p.has_dual && !theta_route(p)) continue;
+    if (*k.v == k.alt) continue;
     const int32_t old = *k.v;
     *k.v = k.alt;
     p.opt.use_graph = graph;

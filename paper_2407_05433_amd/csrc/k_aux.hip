@@ -1,6 +1,9 @@
 // Multipliers (paper Section VII), refinement, residual (Section IX) and the
 // adjoint gradient assembly.  All kernels are stage-parallel and memory-bound.
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "dense.hpp"
 #include "device_util.hpp"
@@ -704,6 +707,34 @@ static int grid_for(int64_t n) {
   if (g < 1) g = 1;
   if (g > 4096) g = 4096;
   return (int)g;
+}
+
+int fit_grid(const void* fn, int block, size_t lds, int64_t want) {
+  if (want < 1) return 1;
+  const int cap_want = (int)std::min<int64_t>(want, 1 << 30);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return cap_want;
+  static std::mutex mu;
+  static std::map<std::tuple<int, const void*, int, size_t>, int> cache;
+  const auto key = std::make_tuple(dev, fn, block, lds);
+  int cap = 0;
+  {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) cap = it->second;
+  }
+  if (cap == 0) {
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, lds) != hipSuccess || per_cu < 1 ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) {
+      (void)hipGetLastError();
+      return cap_want;
+    }
+    cap = per_cu * cus;
+    std::lock_guard<std::mutex> g(mu);
+    cache[key] = cap;
+  }
+  return std::min(cap_want, cap);
 }
 
 void launch_dual_matrices(const DevEngine& p, const Inputs& in, const DevEngine& d, const DualPtrs& dp,

@@ -58,7 +58,11 @@ __global__ void __launch_bounds__(kBlock) k_eliminate(DevEngine e, Inputs in, To
     const double* tv = base + ar.t;
     const double* Q = in.f[IN_Q] + st.in[IN_Q];
     const double* qv = in.f[IN_q] + st.in[IN_q];
-    Bump bump{kLS ? lscr : block_scratch(e)};
+    // working arrays: one region, reused phase by phase (QR and maps; reduced
+    // dynamics; reduced costs; value-function element), each phase starting
+    // after a barrier that ends the previous one's reads
+    double* const scr0 = kLS ? lscr : block_scratch(e);
+    Bump bump{scr0};
     double* ric = slot_ptr(e, SCAN_RIC, st.elem[SCAN_RIC]);
     if (st.terminal) {
       const RicLayout rl = ric_layout(n, 0);
@@ -211,6 +215,8 @@ __global__ void __launch_bounds__(kBlock) k_eliminate(DevEngine e, Inputs in, To
     }
 
     // ---- reduced dynamics ---------------------------------------------------
+    wg_sync();
+    bump.p = scr0;
     double* Ab = base + ar.Ab;
     double* Bb = base + ar.Bb;
     double* cb = base + ar.cb;
@@ -232,6 +238,7 @@ __global__ void __launch_bounds__(kBlock) k_eliminate(DevEngine e, Inputs in, To
     wg_gemv(cb, T1, nb1, true, cvv, nb1, np, 1.0, 0.0);
 
     // ---- reduced costs --------------------------------------------------------
+    bump.p = scr0;  // wg_gemv ends with a barrier
     double* QT = bump.take((int64_t)n * n);
     double* Mz = bump.take((int64_t)n * m);
     double* RY = bump.take((int64_t)m * n);
@@ -314,6 +321,7 @@ __global__ void __launch_bounds__(kBlock) k_eliminate(DevEngine e, Inputs in, To
 
     // ---- value-function element -----------------------------------------------
     const RicLayout rl = ric_layout(n, np);
+    bump.p = scr0;  // after the barrier above
     double* Wt = bump.take((int64_t)m * np);
     double* V = bump.take((int64_t)m * n);
     double* w2 = bump.take(m);
@@ -377,12 +385,15 @@ void launch_eliminate(const DevEngine& e, const Inputs& in, Tols t, int32_t* sta
   const size_t with = base + sizeof(double) * (size_t)elim_scratch(maxn, maxn, maxm, maxk);
   // LDS only while a workgroup needs at most 32 KiB: above that the lost
   // occupancy costs more than the faster accesses gain
-  if (e.elim_lds && with <= 32768 && with <= (size_t)g_elim_max_lds)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_eliminate<true>), dim3(e.nblocks), dim3(kBlock), with, s, e, in, t, status,
-                       maxm, maxq);
-  else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_eliminate<false>), dim3(e.nblocks), dim3(kBlock), base, s, e, in, t, status,
-                       maxm, maxq);
+  if (e.elim_lds == 1 && with <= 32768 && with <= (size_t)g_elim_max_lds) {
+    const int grid = task_grid(e, e.S);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_eliminate<true>), dim3(grid), dim3(kBlock), with, s, e, in, t, status, maxm,
+                       maxq);
+  } else {
+    const int grid = fit_grid(reinterpret_cast<const void*>(k_eliminate<false>), kBlock, base, e.nblocks);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_eliminate<false>), dim3(grid), dim3(kBlock), base, s, e, in, t, status, maxm,
+                       maxq);
+  }
 }
 
 }  // namespace eclqr

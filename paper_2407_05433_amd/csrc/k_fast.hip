@@ -249,7 +249,8 @@ bool launch_mult_local(const DevEngine& e, const Inputs& in, const double* x, co
                        int32_t* status, int maxrow, int ldw, hipStream_t s) {
   const size_t lds = mult_local_lds_bytes(maxrow, ldw);
   if (lds > (size_t)g_fast_max_lds) return false;
-  hipLaunchKernelGGL(k_mult_local, dim3(e.nblocks), dim3(kBlock), lds, s, e, in, x, u, t, status, maxrow, ldw);
+  const int grid = task_grid(e, e.S);
+  hipLaunchKernelGGL(k_mult_local, dim3(grid), dim3(kBlock), lds, s, e, in, x, u, t, status, maxrow, ldw);
   return true;
 }
 void launch_theta_combine(const DevEngine& e, int64_t first, int64_t ntasks, hipStream_t s) {
@@ -633,15 +634,16 @@ bool launch_theta_local(const DevEngine& p, const DevEngine& th, const Inputs& i
                         Tols t, int32_t* status, int maxq, int ldw, int maxr, int mode, hipStream_t s) {
   const size_t lds = theta_local_lds_bytes(maxq, ldw, maxr);
   if (lds > (size_t)g_theta_max_lds) return false;
+  const int grid = task_grid(p, p.S);
   if (mode == 1)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_theta_local<1>), dim3(p.nblocks), dim3(kBlock), lds, s, p, th, in, x, u, t,
-                       status, maxq, ldw, maxr);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_theta_local<1>), dim3(grid), dim3(kBlock), lds, s, p, th, in, x, u, t, status,
+                       maxq, ldw, maxr);
   else if (mode == 2)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_theta_local<2>), dim3(p.nblocks), dim3(kBlock), lds, s, p, th, in, x, u, t,
-                       status, maxq, ldw, maxr);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_theta_local<2>), dim3(grid), dim3(kBlock), lds, s, p, th, in, x, u, t, status,
+                       maxq, ldw, maxr);
   else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_theta_local<0>), dim3(p.nblocks), dim3(kBlock), lds, s, p, th, in, x, u, t,
-                       status, maxq, ldw, maxr);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_theta_local<0>), dim3(grid), dim3(kBlock), lds, s, p, th, in, x, u, t, status,
+                       maxq, ldw, maxr);
   return true;
 }
 void launch_theta_init(const DevEngine& th, hipStream_t s) {

@@ -629,6 +629,118 @@ __device__ __forceinline__ bool lane_combine(const double* E1, const RicLayout& 
   return true;
 }
 
+// The factored combine with A1, C1, J2 and A2 (read more than once) staged in
+// LDS and the other operands read from global memory once; J and C are formed
+// in the pool and written out once, so global data is only read, or written
+// and not read back, and every barrier is LDS-only.  Same operations in the
+// same order as combine_factored, so the same bits.  Pool, with d the largest
+// dim of the task: P0 (d x d) L, then K, then the C update; P1 (d x d) G, then
+// Rg, then G2, then R2; P2 (d x d) C1 L, then Rg^{-1} L', then the J update,
+// then J2 K, then A2 K R2^{-T}; P3 (d x (d + 1)) Yb, then R2^{-1} K'; four
+// vectors.
+template <int NMAX>
+__device__ __forceinline__ bool combine_staged(const double* A1, const double* b1, const double* C1, const double* et1,
+                                               const double* J1, const double* A2, const double* b2, const double* C2,
+                                               const double* et2, const double* J2, double* Eo, const RicLayout& lo,
+                                               int ds, int dm, int de, bool binary, double* pool, int* used, double* sh,
+                                               double* rlog, double* buf) {
+  int d = ds > dm ? ds : dm;
+  d = d > de ? d : de;
+  const int64_t dd = rup4((int64_t)d * d);
+  double* P0 = pool;
+  double* P1 = P0 + dd;
+  double* P2 = P1 + dd;
+  double* P3 = P2 + dd;
+  double* xi = P3 + rup4((int64_t)d * (d + 1));
+  double* tv = xi + rup4(d);
+  double* wv = tv + rup4(d);
+  double* rem = wv + rup4(d);
+  double mx = 0.0;
+  for (int i = 0; i < dm; ++i) mx = fmax(mx, J2[i * dm + i]);
+  if (!(mx > 0.0)) return false;
+  double* Lj = P0;
+  double* Gm = P1;
+  wg_copy<true>(Lj, dm, J2, dm, dm, dm);
+  if (d_cholesky<true, NMAX>(Lj, dm, dm, sh, 1e-15 * mx, buf)) return false;
+  // G = I + L'(C1 L)
+  wg_gemm<true>(P2, dm, C1, dm, false, Lj, dm, false, dm, dm, dm, 1.0, 0.0);
+  wg_gemm<true>(Gm, dm, Lj, dm, true, P2, dm, false, dm, dm, dm, 1.0, 0.0);
+  for (int i = ECLQR_TID; i < dm; i += ECLQR_NT) Gm[i * dm + i] += 1.0;
+  bsync<true>();
+  wg_symmetrize<true>(Gm, dm, dm);
+  if (d_cholesky<true, NMAX>(Gm, dm, dm, sh, 0.0, buf)) return false;
+  for (int idx = ECLQR_TID; idx < dm * dm; idx += ECLQR_NT) {
+    rlog[4 + idx] = Lj[idx];
+    rlog[4 + dm * dm + idx] = Gm[idx];
+  }
+  if (ECLQR_TID == 0) rlog[0] = 1.0;
+  {
+    const int lane = ECLQR_TID;
+    double xv = (lane < dm) ? et2[lane] : 0.0;
+    xv = lane_trsv_lower(Lj, dm, xv, dm);
+    double dv = xv;
+    if (lane < dm) dv = lane_chain<true>(dv, Lj + lane * dm + lane, dm, b1 + lane, 1, dm - lane);
+    dv = lane_trsv_lower(Gm, dm, dv, dm);
+    dv = lane_trsv_lower_t(Gm, dm, dv, dm);
+    if (lane < dm) {
+      xi[lane] = xv;
+      tv[lane] = dv;
+    }
+  }
+  bsync<true>();
+  for (int i = ECLQR_TID; i < dm; i += ECLQR_NT) wv[i] = lane_chain<false>(0.0, Lj + i * dm, 1, tv, 1, i + 1);
+  bsync<true>();
+  for (int i = ECLQR_TID; i < ds; i += ECLQR_NT) Eo[lo.eta + i] = lane_chain<false>(et1[i], A1 + i, ds, wv, 1, dm);
+  // Rg^{-1} L' ; Yb[:, :ds] = (Rg^{-1} L') A1 ; J = J1 + Yb'Yb
+  double* Mm = P2;
+  wg_copy_t<true>(Mm, dm, Lj, dm, dm, dm);
+  d_trsm_lower<true, NMAX>(Gm, dm, Mm, dm, dm, dm, buf);
+  const int ly = ds + 1;
+  double* Yb = P3;
+  wg_gemm<true>(Yb, ly, Mm, dm, false, A1, ds, false, dm, ds, dm, 1.0, 0.0);
+  double* Jt = P2;
+  wg_gemm<true>(Jt, ds, Yb, ly, true, Yb, ly, false, ds, ds, dm, 1.0, 0.0);
+  for (int idx = ECLQR_TID; idx < ds * ds; idx += ECLQR_NT) Jt[idx] += J1[idx];
+  bsync<true>();
+  wg_symmetrize<true>(Jt, ds, ds);
+  for (int idx = ECLQR_TID; idx < ds * ds; idx += ECLQR_NT) Eo[lo.J + idx] = Jt[idx];
+  if (!binary) return true;
+  // Yb = L^{-T} [Rg^{-T} Mm A1 | xi - d] ; A = A2 Yb[:, :ds] ; b = A2 Yb[:, ds] + b2
+  for (int i = ECLQR_TID; i < dm; i += ECLQR_NT) Yb[i * ly + ds] = xi[i] - tv[i];
+  bsync<true>();
+  d_trsm_lower_t<true, NMAX>(Gm, dm, Yb, ly, dm, ds, buf);
+  d_trsm_lower_t<true, NMAX>(Lj, dm, Yb, ly, dm, ly, buf);
+  wg_gemm<true>(Eo + lo.A, ds, A2, dm, false, Yb, ly, false, de, ds, dm, 1.0, 0.0);
+  for (int i = ECLQR_TID; i < de; i += ECLQR_NT) Eo[lo.b + i] = lane_chain<false>(b2[i], A2 + i * dm, 1, Yb + ds, ly, dm);
+  bsync<true>();
+  // C = C2 + (A2 K R2^{-T})(A2 K R2^{-T})'
+  double* Km = P0;
+  double* Ct = P0;
+  const int r = d_pchol<true, NMAX>(C1, dm, dm, 1e-15, Km, dm, rem, used, sh, buf);
+  if (r > 0) {
+    double* G2 = P1;
+    double* M2 = P3;
+    wg_gemm<true>(P2, r, J2, dm, false, Km, dm, false, dm, r, dm, 1.0, 0.0);
+    wg_gemm<true>(G2, r, Km, dm, true, P2, r, false, r, r, dm, 1.0, 0.0);
+    for (int i = ECLQR_TID; i < r; i += ECLQR_NT) G2[i * r + i] += 1.0;
+    bsync<true>();
+    wg_symmetrize<true>(G2, r, r);
+    if (d_cholesky<true, NMAX>(G2, r, r, sh, 0.0, buf)) return false;
+    wg_copy_t<true>(M2, dm, Km, dm, dm, r);  // K' (r x dm)
+    d_trsm_lower<true, NMAX>(G2, r, M2, dm, r, dm, buf);
+    double* AN = P2;
+    wg_gemm<true>(AN, r, A2, dm, false, M2, dm, true, de, r, dm, 1.0, 0.0);
+    wg_gemm<true>(Ct, de, AN, r, false, AN, r, true, de, de, r, 1.0, 0.0);
+  } else {
+    wg_fill<true>(Ct, de, de, de, 0.0);
+  }
+  for (int idx = ECLQR_TID; idx < de * de; idx += ECLQR_NT) Ct[idx] += C2[idx];
+  bsync<true>();
+  wg_symmetrize<true>(Ct, de, de);
+  for (int idx = ECLQR_TID; idx < de * de; idx += ECLQR_NT) Eo[lo.C + idx] = Ct[idx];
+  return true;
+}
+
 }  // namespace
 
 // Copy the used part of a value-function element with reduced dims (na, nb)
@@ -670,26 +782,54 @@ __device__ __forceinline__ void ric_move(double* dst, const RicLayout& ld, const
   }
 }
 
+// Stage the operands of a combine that it reads more than once, compactly in
+// LDS at S: A1 (dm x ds), C1 (dm x dm), J2 (dm x dm), A2 (de x dm); all loads
+// of a round are issued before its stores.
+__device__ __forceinline__ void ric_stage(double* S, const double* A1, const double* C1, const double* J2,
+                                          const double* A2, int ds, int dm, int de) {
+  const int64_t n0 = (int64_t)dm * ds, n1 = n0 + (int64_t)dm * dm, n2 = n1 + (int64_t)dm * dm,
+                n3 = n2 + (int64_t)de * dm;
+  for (int64_t f0 = ECLQR_TID; f0 < n3; f0 += 8 * ECLQR_NT) {
+    double v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int64_t f = f0 + (int64_t)t * ECLQR_NT;
+      const double* src = (f < n0) ? A1 + f : (f < n1) ? C1 + (f - n0) : (f < n2) ? J2 + (f - n1) : A2 + (f - n2);
+      v[t] = (f < n3) ? *src : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int64_t f = f0 + (int64_t)t * ECLQR_NT;
+      if (f < n3) S[f] = v[t];
+    }
+  }
+}
+
 // Task of position t of a value-function combine launch (the plan's dim-bucket
 // order, else the level's own order).
 __device__ __forceinline__ int64_t ric_task(const DevEngine& e, int64_t t) { return e.ric_perm ? e.ric_perm[t] : t; }
 
 // kMode 0: work pool in per-block global scratch; 1: pool in LDS; 2: both
 // operands, the result and the pool in LDS (operands staged in, result
-// written out in bulk), every barrier LDS-only.
-// LDS: [operand 1 | operand 2 | result (mode 2)] [pool (modes 1, 2)] | piv/used ints | sh
-// NMAX > 0 (mode 2 only): factorizations and solves of size <= NMAX run
+// written out in bulk), every barrier LDS-only; 3: the operands read more than
+// once staged in LDS, a compact pool in LDS, the result written once to
+// global memory (combine_staged), every barrier of the factored form LDS-only,
+// the LU form in the global scratch.
+// LDS: [operand 1 | operand 2 | result (mode 2); staged operands (mode 3)]
+// [pool (modes 1, 2, 3)] | piv/used ints | sh
+// NMAX > 0 (modes 2, 3): factorizations and solves of size <= NMAX run
 // register-resident.
 template <int kMode, int NMAX>
 __global__ void __launch_bounds__(kBlock, 1) k_ric_combine(DevEngine e, int64_t first, int64_t ntasks, int32_t* status,
                                                         int maxd) {
   extern __shared__ double lds[];
   const int64_t esz = (kMode == 2) ? ric_layout(maxd, maxd).size : 0;
-  const int64_t pool_sz = (kMode >= 1) ? ric_pool(maxd) : 0;
+  const int64_t head = (kMode == 3) ? ric_stage_size(maxd) : 3 * esz;
+  const int64_t pool_sz = (kMode == 3) ? ric_pool_staged(maxd) : (kMode >= 1) ? ric_pool(maxd) : 0;
   double* S1 = lds;
   double* S2 = S1 + esz;
   double* So = S2 + esz;
-  int* piv = (int*)(lds + 3 * esz + pool_sz);
+  int* piv = (int*)(lds + head + pool_sz);
   double* sh = (double*)(piv + kMaxDim);
   double* buf = sh + 16;
   for (int64_t ti = blockIdx.x; ti < ntasks; ti += gridDim.x) {
@@ -706,7 +846,24 @@ __global__ void __launch_bounds__(kBlock, 1) k_ric_combine(DevEngine e, int64_t 
     double* Eo = slot_ptr(e, SCAN_RIC, o);
     const bool binary = se >= 0;
     double* rlog = e.ric_log + e.ric_log_off[o];
-    if constexpr (kMode == 2) {
+    if constexpr (kMode == 3) {
+      double* St = lds;
+      ric_stage(St, E1 + l1.A, E1 + l1.C, E2 + l2.J, E2 + l2.A, ds, dm, de);
+      lds_sync();
+      const double* A1s = St;
+      const double* C1s = A1s + (int64_t)dm * ds;
+      const double* J2s = C1s + (int64_t)dm * dm;
+      const double* A2s = J2s + (int64_t)dm * dm;
+      // the LU form, when a factorization fails, works in the block's global
+      // scratch (the grid is capped at the plan's workgroups in this mode)
+      if (!combine_staged<NMAX>(A1s, E1 + l1.b, C1s, E1 + l1.eta, E1 + l1.J, A2s, E2 + l2.b, E2 + l2.C, E2 + l2.eta,
+                                J2s, Eo, lo, ds, dm, de, binary, lds + head, piv, sh, rlog, buf)) {
+        wg_sync();
+        combine_lu<false>(A1s, E1 + l1.b, C1s, E1 + l1.eta, E1 + l1.J, A2s, E2 + l2.b, E2 + l2.C, E2 + l2.eta, J2s, Eo,
+                          lo, ds, dm, de, binary, block_scratch(e), piv, sh, rlog);
+      }
+      wg_sync();
+    } else if constexpr (kMode == 2) {
       const RicLayout s1 = ric_layout(ds, dm), s2 = ric_layout(dm, de), so = ric_layout(ds, de);
       ric_move(S1, s1, E1, l1, ds, dm);
       ric_move(S2, s2, E2, l2, dm, de);
@@ -1053,9 +1210,9 @@ void lqr_set_max_lds(int bytes) {
 
 // LDS bytes of a value-function combine launch in mode m at middle dim bound d.
 static size_t ric_mode_bytes(int m, int d) {
-  const size_t esz = (m == 2) ? (size_t)ric_layout(d, d).size : 0;
-  const size_t pool = (m >= 1) ? (size_t)ric_pool(d) : 0;
-  return sizeof(double) * (3 * esz + pool + 16 + kMaxDim) + sizeof(int) * kMaxDim + 64;
+  const size_t head = (m == 3) ? (size_t)ric_stage_size(d) : (m == 2) ? 3 * (size_t)ric_layout(d, d).size : 0;
+  const size_t pool = (m == 3) ? (size_t)ric_pool_staged(d) : (m >= 1) ? (size_t)ric_pool(d) : 0;
+  return sizeof(double) * (head + pool + 16 + kMaxDim) + sizeof(int) * kMaxDim + 64;
 }
 // Mode actually used for a requested mode: the largest one <= requested whose
 // LDS fits.
@@ -1080,7 +1237,7 @@ static size_t ric_split_bytes(int d) {
 void launch_ric_combine(const DevEngine& e, int64_t first, int64_t ntasks, int32_t* status, int maxd,
                         hipStream_t s) {
   if (ntasks <= 0) return;
-  const int grid = (int)(ntasks < e.nblocks ? ntasks : e.nblocks);
+  const int grid = task_grid(e, ntasks);  // modes 1 and 2 and the split kernel keep their pool in LDS
   const int mode = ric_mode(e.pool_lds, maxd);
   // two wavefronts per combine while the level still fits the device at once
   if (e.split_combine && mode == 2 && maxd <= 32) {
@@ -1097,21 +1254,20 @@ void launch_ric_combine(const DevEngine& e, int64_t first, int64_t ntasks, int32
     }
   }
   const size_t lds = ric_mode_bytes(mode, maxd);
-  if (mode == 2 && maxd <= 16)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ric_combine<2, 16>), dim3(grid), dim3(kBlock), lds, s, e, first, ntasks,
-                       status, maxd);
-  else if (mode == 2 && maxd <= 32)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ric_combine<2, 32>), dim3(grid), dim3(kBlock), lds, s, e, first, ntasks,
-                       status, maxd);
-  else if (mode == 2)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ric_combine<2, 0>), dim3(grid), dim3(kBlock), lds, s, e, first, ntasks,
-                       status, maxd);
-  else if (mode == 1)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ric_combine<1, 0>), dim3(grid), dim3(kBlock), lds, s, e, first, ntasks,
-                       status, maxd);
-  else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ric_combine<0, 0>), dim3(grid), dim3(kBlock), lds, s, e, first, ntasks,
-                       status, maxd);
+  const void* fn = (mode == 3 && maxd <= 16)   ? reinterpret_cast<const void*>(k_ric_combine<3, 16>)
+                   : (mode == 3 && maxd <= 32) ? reinterpret_cast<const void*>(k_ric_combine<3, 32>)
+                   : (mode == 3)               ? reinterpret_cast<const void*>(k_ric_combine<3, 0>)
+                   : (mode == 2 && maxd <= 16) ? reinterpret_cast<const void*>(k_ric_combine<2, 16>)
+                   : (mode == 2 && maxd <= 32) ? reinterpret_cast<const void*>(k_ric_combine<2, 32>)
+                   : (mode == 2)               ? reinterpret_cast<const void*>(k_ric_combine<2, 0>)
+                   : (mode == 1)               ? reinterpret_cast<const void*>(k_ric_combine<1, 0>)
+                                               : reinterpret_cast<const void*>(k_ric_combine<0, 0>);
+  // modes 0 and 3 use the per-workgroup global scratch (nblocks of them): as
+  // the pool, or for the LU form
+  const int g = (mode == 0 || mode == 3) ? fit_grid(fn, kBlock, lds, ntasks < e.nblocks ? ntasks : e.nblocks) : grid;
+  DevEngine ev = e;
+  void* args[] = {&ev, &first, &ntasks, &status, &maxd};
+  (void)hipLaunchKernel(fn, dim3(g), dim3(kBlock), args, lds, s);
 }
 
 void launch_ric_combine_lane(const DevEngine& e, int64_t first, int64_t ntasks, int32_t* defer_count,
@@ -1129,10 +1285,13 @@ void launch_ric_combine_lane(const DevEngine& e, int64_t first, int64_t ntasks, 
 void launch_gains(const DevEngine& e, int32_t* status, int maxm, int maxn, hipStream_t s) {
   const size_t base = gains_lds_bytes(maxm);
   const size_t with = base + sizeof(double) * (size_t)gains_scratch(maxn, maxn, maxm);
-  if (e.elim_lds && with <= 32768 && with <= (size_t)g_lqr_max_lds)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gains<true>), dim3(e.nblocks), dim3(kBlock), with, s, e, status, maxm);
-  else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gains<false>), dim3(e.nblocks), dim3(kBlock), base, s, e, status, maxm);
+  if (e.elim_lds && with <= 32768 && with <= (size_t)g_lqr_max_lds) {
+    const int grid = task_grid(e, e.S);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gains<true>), dim3(grid), dim3(kBlock), with, s, e, status, maxm);
+  } else {
+    const int grid = fit_grid(reinterpret_cast<const void*>(k_gains<false>), kBlock, base, e.nblocks);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gains<false>), dim3(grid), dim3(kBlock), base, s, e, status, maxm);
+  }
 }
 
 void launch_fwd_combine(const DevEngine& e, int64_t first, int64_t ntasks, hipStream_t s) {

@@ -646,8 +646,10 @@ void launch_base_relation(const DevEngine& e, const Inputs& in, Tols t, int32_t*
                        rel_lds_bytes(maxp, ldw) - rel_tile_bytes(maxp, ldw), s, e, in, t, status, maxp, ldw);
     return;
   }
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_base_relation<false>), dim3(e.nblocks), dim3(kBlock), rel_lds_bytes(maxp, ldw),
-                     s, e, in, t, status, maxp, ldw);
+  const size_t lds = rel_lds_bytes(maxp, ldw);
+  const int grid = task_grid(e, e.S);
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_base_relation<false>), dim3(grid), dim3(kBlock), lds, s, e, in, t, status, maxp,
+                     ldw);
 }
 
 bool rel_fits(const DevEngine& e, int maxp, int ldw) {
@@ -657,12 +659,13 @@ bool rel_fits(const DevEngine& e, int maxp, int ldw) {
 void launch_rel_compose(const DevEngine& e, int64_t first, int64_t ntasks, Tols t, int32_t* status, int maxp, int ldw,
                         int maxkc, hipStream_t s) {
   if (ntasks <= 0) return;
-  const int grid = (int)(ntasks < e.nblocks ? ntasks : e.nblocks);
+  const int grid = (int)(ntasks < e.nblocks ? ntasks : e.nblocks);  // the global-tile variant
+  const int tg = task_grid(e, ntasks);
   // register-resident variant when every task of the launch fits it
   if (e.reg_compose && maxp <= 64 && ldw <= 128 && maxkc <= 64) {
     const bool r32 = maxp <= 32, r48 = maxp <= 48, c1 = ldw <= 64, k32 = maxkc <= 32;
 #define ECLQR_REG(PRV, NCV, KCV) \
-  hipLaunchKernelGGL((k_rel_compose_reg<PRV, NCV, KCV>), dim3(grid), dim3(kBlock), 0, s, e, first, ntasks, t, status)
+  hipLaunchKernelGGL((k_rel_compose_reg<PRV, NCV, KCV>), dim3(tg), dim3(kBlock), 0, s, e, first, ntasks, t, status)
     if (r32 && c1 && k32) ECLQR_REG(32, 1, 32);
     else if (r32 && c1) ECLQR_REG(32, 1, 64);
     else if (r32 && k32) ECLQR_REG(32, 2, 32);
@@ -682,12 +685,15 @@ void launch_rel_compose(const DevEngine& e, int64_t first, int64_t ntasks, Tols 
                        rel_lds_bytes(maxp, ldw) - rel_tile_bytes(maxp, ldw), s, e, first, ntasks, t, status, maxp, ldw);
     return;
   }
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rel_compose<false>), dim3(grid), dim3(kBlock), rel_lds_bytes(maxp, ldw), s, e,
-                     first, ntasks, t, status, maxp, ldw);
+  const size_t lds = rel_lds_bytes(maxp, ldw);
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rel_compose<false>), dim3(tg), dim3(kBlock), lds, s, e, first, ntasks, t, status,
+                     maxp, ldw);
 }
 
 void launch_domain(const DevEngine& e, const Inputs& in, Tols t, int32_t* status, int maxn, hipStream_t s) {
-  hipLaunchKernelGGL(k_domain, dim3(e.nblocks), dim3(kBlock), domain_lds_bytes(maxn), s, e, in, t, status, maxn);
+  const size_t lds = domain_lds_bytes(maxn);
+  const int grid = task_grid(e, e.S);
+  hipLaunchKernelGGL(k_domain, dim3(grid), dim3(kBlock), lds, s, e, in, t, status, maxn);
 }
 
 }  // namespace eclqr

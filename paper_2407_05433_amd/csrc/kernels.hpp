@@ -41,9 +41,13 @@ struct DevEngine {
   int32_t B;
   int32_t nslots;
   int32_t nblocks;            // grid size of the stage-parallel kernels (grid-stride)
-  int32_t pool_lds;           // value-function combine LDS mode (0 global pool, 1 LDS pool, 2 all in LDS)
+  int32_t task_grid;          // grid cap of the kernels without per-workgroup global scratch: large (one workgroup
+                              // per task, so the dispatcher balances tasks of unequal cost) or nblocks
+  int32_t pool_lds;           // value-function combine LDS mode (0 global pool, 1 LDS pool, 2 all in LDS,
+                              // 3 staged operands and compact pool in LDS)
   int32_t reg_compose;        // 1: relation compositions that fit run register-resident
-  int32_t elim_lds;           // 1: stage eliminations keep their working arrays in LDS when they fit
+  int32_t elim_lds;           // working arrays in LDS when they fit: 1 stage eliminations and feedback gains,
+                              // 2 feedback gains only, 0 neither
   int32_t split_combine;      // 1: value-function combines of a level that fits the device run on two wavefronts
 };
 
@@ -65,6 +69,18 @@ void eliminate_set_max_lds(int bytes);
 void lqr_set_max_lds(int bytes);
 void lqr_set_device(int lds_per_cu, int num_cu);
 void replay_set_max_lds(int bytes);
+// Grid of a grid-stride launch of `fn` (workgroups of `block` lanes, `lds`
+// bytes of dynamic LDS): `want`, capped at the workgroups the current device
+// runs at once for that kernel (a grid a little above that capacity runs its
+// surplus as a second round of the whole per-workgroup loop on an almost idle
+// device).  Cached per device, kernel and LDS size.
+int fit_grid(const void* fn, int block, size_t lds, int64_t want);
+// Grid of `ntasks` independent tasks for a kernel that needs no per-workgroup
+// global scratch (e.task_grid caps it).
+inline int task_grid(const DevEngine& e, int64_t ntasks) {
+  const int64_t g = ntasks < e.task_grid ? ntasks : e.task_grid;
+  return (int)(g < 1 ? 1 : g);
+}
 size_t rel_lds_bytes(int maxp, int ldw);
 size_t domain_lds_bytes(int maxn);
 size_t elim_lds_bytes(int maxm, int maxq);

@@ -151,7 +151,8 @@ struct Plan {
   // tuning (eclqr_plan_autotune / eclqr_plan_set_tuning)
   int32_t level_buckets = 1;  // relation levels launch in LDS-size buckets
   int32_t stage_lds = 1;      // stage kernels' working arrays in LDS when <= 32 KiB
-  int32_t pool_lds = 2;       // value-function combine LDS mode (0 global pool, 1 LDS pool, 2 all in LDS)
+  int32_t pool_lds = 3;       // value-function combine LDS mode (0 global pool, 1 LDS pool, 2 all in LDS,
+                              // 3 staged operands and compact pool in LDS)
   int32_t grid_divisor = 1;   // grid of the stage-parallel kernels = nblocks / divisor
   int32_t reg_compose = 1;    // register-resident relation compositions where they fit
   int32_t overlap_dual = 1;   // factor the multiplier route's problem on a second stream beside the primal pass

@@ -8,19 +8,22 @@ namespace eclqr {
 
 ECLQR_HD inline int64_t rup4(int64_t x) { return (x + 3) & ~int64_t(3); }
 
-// stage elimination: dims of the stage (n, n', m, k) at capacity
+// stage elimination: dims of the stage (n, n', m, k) at capacity.  The
+// kernel reuses one region phase by phase, so the size is the largest phase.
 ECLQR_HD inline int64_t elim_scratch(int n, int np, int m, int k) {
   const int64_t q = k + np;
-  int64_t s = 0;
-  s += rup4(q * m) + rup4(q * n) + rup4(q) + rup4(q * n) + rup4(q);  // Gs Ps gs Phi gam
-  s += rup4((int64_t)m * m) + rup4((int64_t)m * (n + 1));             // Qg X
-  s += rup4((int64_t)np * n) + rup4((int64_t)np * m) + rup4(np);      // AT BZ cv
-  s += rup4((int64_t)n * n) + rup4((int64_t)n * m);                   // QT Mz
-  s += rup4((int64_t)m * n) + rup4((int64_t)m * m) + rup4((int64_t)n * n);  // RY RZ MzY
-  s += rup4(m) + rup4(n) + rup4(m);                                   // w qz rz
-  s += rup4((int64_t)m * m) + rup4((int64_t)m * np) + rup4((int64_t)m * n) + rup4(m);  // L Wt V w2
-  s += rup4(q) + 64;                                                  // row scales, misc
-  return s;
+  // QR of Gamma^T and the maps Y, y, Z: Gs Ps gs Phi gam Qg X rsc
+  const int64_t p1 = rup4(q * m) + rup4(q * n) + rup4(q) + rup4(q * n) + rup4(q) + rup4((int64_t)m * m) +
+                     rup4((int64_t)m * (n + 1)) + rup4(q);
+  const int64_t p2 = rup4((int64_t)np * n) + rup4((int64_t)np * m) + rup4(np);  // AT BZ cv
+  // QT Mz RY RZ MzY w qz rz (the terminal stage's QT and v fit in it)
+  const int64_t p3 = rup4((int64_t)n * n) + rup4((int64_t)n * m) + rup4((int64_t)m * n) + rup4((int64_t)m * m) +
+                     rup4((int64_t)n * n) + rup4(m) + rup4(n) + rup4(m);
+  const int64_t p4 = rup4((int64_t)m * np) + rup4((int64_t)m * n) + rup4(m);  // Wt V w2
+  int64_t s = p1 > p2 ? p1 : p2;
+  s = s > p3 ? s : p3;
+  s = s > p4 ? s : p4;
+  return s + 64;
 }
 
 // Working pool of one value-function combine with every endpoint dim <= d:
@@ -29,6 +32,16 @@ ECLQR_HD inline int64_t elim_scratch(int n, int np, int m, int k) {
 ECLQR_HD inline int64_t ric_pool(int d) {
   const int64_t dd = rup4((int64_t)d * d);
   return 7 * dd + rup4((int64_t)d * (d + 1)) + 4 * rup4(d) + 64;
+}
+
+// Value-function combine with staged operands (every endpoint dim <= d): the
+// operands read more than once (four d x d blocks at most), and a pool that
+// holds the factored form (three d x d blocks, d x (d + 1), four vectors; the
+// LU fallback uses the global scratch).
+ECLQR_HD inline int64_t ric_stage_size(int d) { return rup4(4 * (int64_t)d * d); }
+ECLQR_HD inline int64_t ric_pool_staged(int d) {
+  const int64_t dd = rup4((int64_t)d * d);
+  return 3 * dd + rup4((int64_t)d * (d + 1)) + 4 * rup4(d) + 64;
 }
 
 // gains: dims at capacity (n, n', m)

@@ -234,6 +234,21 @@ def test_route_decided_at_plan_creation_from_the_lds_bound():
     assert ecl.get_tuning(ecl.Plan(small))["multiplier_route"] == 1
 
 
+def test_tuning_defaults_and_ranges():
+    """Launch configuration of a new plan (staged-operand combines, LDS work
+    arrays for eliminations and gains) and the accepted range of each
+    multi-valued field: pool_in_lds 0..3, stage_lds 0..2 (2: gains only)."""
+    plan = ecl.Plan([([6] * 5, [3] * 4, [1] * 5)])
+    t = ecl.get_tuning(plan)
+    assert t["pool_in_lds"] == 3 and t["stage_lds"] == 1 and t["grid_divisor"] == 1
+    for k, v in (("pool_in_lds", 0), ("pool_in_lds", 2), ("stage_lds", 2), ("stage_lds", 0)):
+        ecl.set_tuning(plan, **{k: v})
+        assert ecl.get_tuning(plan)[k] == v
+    for k, v in (("pool_in_lds", 4), ("pool_in_lds", -1), ("stage_lds", 3), ("grid_divisor", 0)):
+        with pytest.raises(RuntimeError):
+            ecl.set_tuning(plan, **{k: v})
+
+
 def test_ctypes_structs_follow_the_header():
     """The ctypes mirrors of eclqr_solution, eclqr_cotangent and eclqr_grads
     list the header's fields in the header's order."""

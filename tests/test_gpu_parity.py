@@ -172,6 +172,41 @@ def test_singular_state_costs():
     check_parity(probs, gpu_solve(probs))
 
 
+def test_combine_modes_same_bits():
+    """Every LDS mode of the value-function combine (work pool in global
+    scratch, pool in LDS, everything in LDS, staged operands with a compact
+    pool; one or two wavefronts per combine) gives the same bits, on batches
+    whose combines take the factored form and the LU form (Q = 0)."""
+    _need_gpu()
+    import paper_2407_05433_amd as ecl
+    from tests._util import tiny_problem
+    from workloads import config_c3
+    zero = tiny_problem(710, N=9, n=4, m=2, terminal_rows=1)
+    for i in range(zero.N + 1):
+        zero.Q[i] = np.zeros_like(zero.Q[i])
+    probs = config_c3(B=6, N_range=(32, 70)) + [zero, tiny_problem(711, N=11, n=5, m=3, terminal_rows=1)]
+    plan = ecl.Plan.for_problems(probs)
+    data = ecl.pack(plan, probs)
+    ws = plan.workspace()
+    base = {k: v for k, v in ecl.get_tuning(plan).items() if k != "ms_per_solve"}
+    ref = None
+    for pool in (1, 0, 2, 3):
+        for split in (0, 1):
+            ecl.set_tuning(plan, **dict(base, pool_in_lds=pool, split_combine=split))
+            sol = ecl.solve(plan, data, ws)
+            torch.cuda.synchronize()
+            got = {f: getattr(sol, f).clone() for f in ("x", "u", "lam", "mu", "status")}
+            print(f"[modes] pool {pool} split {split}: status {got['status'].tolist()}", flush=True)
+            if ref is None:
+                ref = got
+                assert int(got["status"].abs().sum()) == 0
+                check_parity(probs, {"x": ecl.unpack(plan, sol.x, "q", probs), "u": ecl.unpack(plan, sol.u, "r", probs),
+                                     "lam": ecl.unpack(plan, sol.lam, "q", probs),
+                                     "mu": ecl.unpack(plan, sol.mu, "g", probs), "status": got["status"].tolist()})
+            for f in got:
+                assert torch.equal(got[f], ref[f]), (pool, split, f)
+
+
 def test_c1_full_size():
     _need_gpu()
     from workloads import config_c1
@@ -358,7 +393,8 @@ def test_autotune_keeps_results():
     base = ecl.get_tuning(plan)
     tuned = ecl.autotune(plan, data, ws)
     assert tuned["ms_per_solve"] > 0
-    for cfg in ({"level_buckets": 0}, {"pool_in_lds": 0}, {"pool_in_lds": 1}, {"stage_lds": 0}, {"grid_divisor": 4},
+    for cfg in ({"level_buckets": 0}, {"pool_in_lds": 0}, {"pool_in_lds": 1}, {"pool_in_lds": 2}, {"pool_in_lds": 3},
+                {"stage_lds": 0}, {"stage_lds": 2}, {"grid_divisor": 4},
                 {"overlap_dual": 1 - base["overlap_dual"]}, {"multiplier_route": 1 - base["multiplier_route"]},
                 {"multiplier_route": 1 - base["multiplier_route"], "overlap_dual": 1 - base["overlap_dual"]},
                 {"split_combine": 0}, {"fused_scans": 0},
