@@ -252,14 +252,101 @@ __device__ __forceinline__ void lane_axpy(double* y, int sy, const double* x, in
   if (i < n) y[i * sy] = fma(alpha, x[i * sx], y[i * sy]);
 }
 
+// wg_gemm for outputs of at least 8 x 8: lanes on an 8 x 8 grid, lane (gr, gc)
+// computing the R x R outputs (gr + 8a, gc + 8b) of each 8R x 8R tile, so a k
+// step loads R values of op(A) and R of op(B) for R * R FMAs (instead of two
+// loads per FMA).  Every output is the same FMA chain in ascending k as in
+// wg_gemm's other form, with the same final expression, so the same bits.
+template <int R>
+__device__ __forceinline__ void wg_gemm_grid(double* C, int ldc, const double* A, int lda, bool tA, const double* B,
+                                             int ldb, bool tB, int M, int N, int K, double alpha, double beta) {
+  const int gr = ECLQR_TID >> 3, gc = ECLQR_TID & 7;
+  const int sa = tA ? lda : 1, sb = tB ? 1 : ldb;  // k strides
+  const int ra = tA ? 1 : lda, cb = tB ? ldb : 1;  // strides between rows of op(A), columns of op(B)
+  for (int i0 = 0; i0 < M; i0 += 8 * R)
+    for (int j0 = 0; j0 < N; j0 += 8 * R) {
+      const double* ap[R];
+      const double* bp[R];
+      bool rv[R], cv[R];
+#pragma unroll
+      for (int a = 0; a < R; ++a) {
+        const int i = i0 + gr + 8 * a;
+        rv[a] = i < M;
+        ap[a] = A + (int64_t)(rv[a] ? i : 0) * ra;  // rows past M read row 0 and are dropped
+      }
+#pragma unroll
+      for (int b = 0; b < R; ++b) {
+        const int j = j0 + gc + 8 * b;
+        cv[b] = j < N;
+        bp[b] = B + (int64_t)(cv[b] ? j : 0) * cb;
+      }
+      double acc[R][R];
+#pragma unroll
+      for (int a = 0; a < R; ++a)
+#pragma unroll
+        for (int b = 0; b < R; ++b) acc[a][b] = 0.0;
+      int k = 0;
+      for (; k + 2 <= K; k += 2) {
+        double av[R][2], bv[R][2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+#pragma unroll
+          for (int a = 0; a < R; ++a) av[a][q] = ap[a][(k + q) * sa];
+#pragma unroll
+          for (int b = 0; b < R; ++b) bv[b][q] = bp[b][(k + q) * sb];
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+          for (int a = 0; a < R; ++a)
+#pragma unroll
+            for (int b = 0; b < R; ++b) acc[a][b] = fma(av[a][q], bv[b][q], acc[a][b]);
+      }
+      for (; k < K; ++k) {
+        double av[R], bv[R];
+#pragma unroll
+        for (int a = 0; a < R; ++a) av[a] = ap[a][k * sa];
+#pragma unroll
+        for (int b = 0; b < R; ++b) bv[b] = bp[b][k * sb];
+#pragma unroll
+        for (int a = 0; a < R; ++a)
+#pragma unroll
+          for (int b = 0; b < R; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+      }
+#pragma unroll
+      for (int a = 0; a < R; ++a)
+#pragma unroll
+        for (int b = 0; b < R; ++b) {
+          if (rv[a] && cv[b]) {
+            const int co = (i0 + gr + 8 * a) * ldc + (j0 + gc + 8 * b);
+            const double prev = (beta != 0.0) ? beta * C[co] : 0.0;
+            C[co] = alpha * acc[a][b] + prev;
+          }
+        }
+    }
+}
+
 // C(MxN) = alpha * op(A) * op(B) + beta * C.  op(A) is MxK, op(B) is KxN.
-// beta == 0 never reads C.  Each lane computes up to four outputs per round
-// with their accumulations interleaved (the loads of four k steps of all four
-// are independent and in flight together); every output is one FMA chain in
-// ascending k.
-template <bool kL = false>
+// beta == 0 never reads C.  With kGrid (default: operands in LDS), outputs of
+// at least 8 x 8 go to wg_gemm_grid; its accumulators and operand registers
+// raise a kernel's VGPR count, which costs the latency-bound kernels on
+// global memory more occupancy than the fewer loads gain them (the stage
+// elimination: 139 -> 169 VGPRs, 11.5 -> 12.2 ms).  Otherwise each lane computes
+// up to four outputs per round with their
+// accumulations interleaved (the loads of four k steps of all four are
+// independent and in flight together).  Either way every output is one FMA
+// chain in ascending k.
+template <bool kL = false, bool kGrid = kL>
 __device__ __forceinline__ void wg_gemm(double* C, int ldc, const double* A, int lda, bool tA, const double* B, int ldb,
                                bool tB, int M, int N, int K, double alpha, double beta) {
+  if (kGrid && M >= 8 && N >= 8) {
+    if (M <= 16 && N <= 16)
+      wg_gemm_grid<2>(C, ldc, A, lda, tA, B, ldb, tB, M, N, K, alpha, beta);
+    else
+      wg_gemm_grid<3>(C, ldc, A, lda, tA, B, ldb, tB, M, N, K, alpha, beta);
+    bsync<kL>();
+    return;
+  }
   const int sa = tA ? lda : 1, sb = tB ? 1 : ldb;
   const int total = M * N;
   for (int r0 = ECLQR_TID; r0 < total; r0 += 4 * ECLQR_NT) {

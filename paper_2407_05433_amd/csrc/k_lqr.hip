@@ -818,9 +818,11 @@ __device__ __forceinline__ int64_t ric_task(const DevEngine& e, int64_t t) { ret
 // LDS: [operand 1 | operand 2 | result (mode 2); staged operands (mode 3)]
 // [pool (modes 1, 2, 3)] | piv/used ints | sh
 // NMAX > 0 (modes 2, 3): factorizations and solves of size <= NMAX run
-// register-resident.
+// register-resident.  With NMAX = 16 (every dim <= 16, where LDS leaves room
+// for several workgroups per compute unit) registers are capped for three
+// waves per SIMD (at most 168 VGPRs; four would spill).
 template <int kMode, int NMAX>
-__global__ void __launch_bounds__(kBlock, 1) k_ric_combine(DevEngine e, int64_t first, int64_t ntasks, int32_t* status,
+__global__ void __launch_bounds__(kBlock, (NMAX == 16) ? 3 : 1) k_ric_combine(DevEngine e, int64_t first, int64_t ntasks, int32_t* status,
                                                         int maxd) {
   extern __shared__ double lds[];
   const int64_t esz = (kMode == 2) ? ric_layout(maxd, maxd).size : 0;
@@ -1070,18 +1072,18 @@ __global__ void __launch_bounds__(kBlock) k_gains(DevEngine e, int32_t* status, 
     double* Hux = PA + rup4((int64_t)nb1 * nb);        // mb x nb
     double* pc = Hux + rup4((int64_t)mb * nb);         // nb1
     double* hu = pc + rup4(nb1);                       // mb
-    wg_gemm(PB, mb, P1, nb1, false, Bb, mb, false, nb1, mb, nb1, 1.0, 0.0);
-    wg_gemm(PA, nb, P1, nb1, false, Ab, nb, false, nb1, nb, nb1, 1.0, 0.0);
+    wg_gemm<false, true>(PB, mb, P1, nb1, false, Bb, mb, false, nb1, mb, nb1, 1.0, 0.0);
+    wg_gemm<false, true>(PA, nb, P1, nb1, false, Ab, nb, false, nb1, nb, nb1, 1.0, 0.0);
     for (int i = ECLQR_TID; i < nb1; i += ECLQR_NT) {
       double v = -et1[i];
       v = lane_chain<false>(v, P1 + i * nb1, 1, cb, 1, nb1);
       pc[i] = v;
     }
     wg_copy(Huu, mb, Rb, mb, mb, mb);
-    wg_gemm(Huu, mb, Bb, mb, true, PB, mb, false, mb, mb, nb1, 1.0, 1.0);
+    wg_gemm<false, true>(Huu, mb, Bb, mb, true, PB, mb, false, mb, mb, nb1, 1.0, 1.0);
     wg_symmetrize(Huu, mb, mb);
     wg_copy_t(Hux, nb, Mb, mb, nb, mb);
-    wg_gemm(Hux, nb, Bb, mb, true, PA, nb, false, mb, nb, nb1, 1.0, 1.0);
+    wg_gemm<false, true>(Hux, nb, Bb, mb, true, PA, nb, false, mb, nb, nb1, 1.0, 1.0);
     for (int i = ECLQR_TID; i < mb; i += ECLQR_NT) {
       double v = rb[i];
       v = lane_chain<false>(v, Bb + i, mb, pc, 1, nb1);
@@ -1106,7 +1108,7 @@ __global__ void __launch_bounds__(kBlock) k_gains(DevEngine e, int32_t* status, 
     double* Fs = slot_ptr(e, SCAN_FWD, st.elem[SCAN_FWD]);
     double* fs = Fs + (int64_t)np * n;
     wg_copy(Fs, nb, Ab, nb, nb1, nb);
-    wg_gemm(Fs, nb, Bb, mb, false, K, nb, false, nb1, nb, mb, 1.0, 1.0);
+    wg_gemm<false, true>(Fs, nb, Bb, mb, false, K, nb, false, nb1, nb, mb, 1.0, 1.0);
     for (int i = ECLQR_TID; i < nb1; i += ECLQR_NT) {
       double v = cb[i];
       v = lane_chain<false>(v, Bb + i * mb, 1, kk, 1, mb);
