@@ -84,6 +84,7 @@ DevEngine dev_engine(const Engine& E, void* ws, size_t base) {
   d.slot_rows = reinterpret_cast<int32_t*>(b + E.o_slot_rows);
   d.tasks = reinterpret_cast<const int32_t*>(b + E.o_tasks);
   d.ric_perm = E.ric_perm.empty() ? nullptr : reinterpret_cast<const int32_t*>(b + E.o_ric_perm);
+  d.stage_perm = E.stage_perm.empty() ? nullptr : reinterpret_cast<const int32_t*>(b + E.o_stage_perm);
   d.nbar = reinterpret_cast<int32_t*>(b + E.o_nbar);
   d.mbar = reinterpret_cast<int32_t*>(b + E.o_mbar);
   d.arena = reinterpret_cast<double*>(b + E.o_arena);
@@ -140,6 +141,9 @@ eclqr_status upload_engine(const Engine& E, void* ws, size_t base, hipStream_t s
     HIP_OK(hipMemcpyAsync(b + E.o_tasks, E.tasks.data(), sizeof(int32_t) * E.tasks.size(), hipMemcpyHostToDevice, s));
   if (!E.ric_perm.empty())
     HIP_OK(hipMemcpyAsync(b + E.o_ric_perm, E.ric_perm.data(), sizeof(int32_t) * E.ric_perm.size(),
+                          hipMemcpyHostToDevice, s));
+  if (!E.stage_perm.empty())
+    HIP_OK(hipMemcpyAsync(b + E.o_stage_perm, E.stage_perm.data(), sizeof(int32_t) * E.stage_perm.size(),
                           hipMemcpyHostToDevice, s));
   HIP_OK(hipMemcpyAsync(b + E.o_sbase, E.sbase.data(), sizeof(int64_t) * E.B, hipMemcpyHostToDevice, s));
   if (E.nslots > 0) {
@@ -251,6 +255,47 @@ eclqr_status bind(Plan& p, void* ws, hipStream_t s) {
 // 3 after forward level `level`.
 using SideLaunch = std::function<eclqr_status(int step, int level)>;
 
+// The stage buckets a stage kernel launches over: the plan's (stages in size
+// order, each range with its own sizes) or, without buckets (or `whole`),
+// one range over every stage with the plan-wide sizes.  Buckets pay for the
+// kernels whose LDS tile bounds the workgroups a compute unit holds (base
+// relations, local systems of the theta route: c3 6.8 -> 5.9 and 5.2 -> 4.0
+// ms); the others run one launch (the elimination in global scratch is
+// bounded by registers, and five launches cost it five tails, 11.5 -> 12.1 ms).
+std::vector<Engine::StageBucket> stage_buckets(const Engine& E, bool whole = false) {
+  if (g_buckets && !whole) return E.sbk;
+  Engine::StageBucket all;
+  all.begin = 0;
+  all.count = E.S;
+  all.maxn = std::max(1, E.maxn);
+  all.maxm = std::max(1, E.maxm);
+  all.maxk = E.maxk;
+  all.base_maxp = E.base_maxp;
+  all.base_ldw = E.base_ldw;
+  all.elim_maxq = E.elim_maxq;
+  return {all};
+}
+
+// The minimum-norm local systems of the theta route over the problem's stage
+// buckets, each with its own LDS tile (false: a tile exceeds the device's LDS).
+bool theta_local_all(const Plan& p, const DevEngine& P, const DevEngine& Th, const Inputs& in, const double* x,
+                     const double* u, Tols td, int32_t* status, int mode, hipStream_t s) {
+  if (!g_buckets)
+    return launch_theta_local(P, Th, in, x, u, td, status, p.th_q, p.th_ldw, p.th_r, mode, 0, p.primal.S, s);
+  for (size_t b = 0; b < p.primal.sbk.size(); ++b) {
+    const auto& sb = p.primal.sbk[b];
+    const auto& tb = p.th_bk[b];
+    if (!launch_theta_local(P, Th, in, x, u, td, status, tb[0], tb[1], tb[2], mode, sb.begin, sb.count, s))
+      return false;
+  }
+  return true;
+}
+
+// Feedback gains of an engine, one launch over every stage.
+void gains_all(const Engine& E, const DevEngine& d, int32_t* status, hipStream_t s) {
+  for (const auto& b : stage_buckets(E, true)) launch_gains(d, status, b.maxm, b.maxn, b.begin, b.count, s);
+}
+
 // One pass of the primal method of Algorithm 1 on the data `in`, writing x, u.
 eclqr_status run_engine(const Engine& E, const DevEngine& d, const Inputs& in, double* x, double* u,
                         int32_t* status, Tols t, hipStream_t s, const SideLaunch& side = {}) {
@@ -263,7 +308,11 @@ eclqr_status run_engine(const Engine& E, const DevEngine& d, const Inputs& in, d
     launch_fill_i32(vac, 1, E.B, s);
     launch_vacuous(d, in, t, vac, std::max(1, E.maxk), std::max(1, E.maxm), s);
   }
-  { Timed tm(ECLQR_K_BASE_RELATION, s); launch_base_relation(d, in, t, status, E.base_maxp, E.base_ldw, s); }
+  const std::vector<Engine::StageBucket> sb = stage_buckets(E);
+  for (const auto& b : sb) {
+    Timed tm(ECLQR_K_BASE_RELATION, s);
+    launch_base_relation(d, in, t, status, b.base_maxp, b.base_ldw, b.begin, b.count, s);
+  }
   for (int l = 0; l < 2 * E.D; ++l) {
     // one launch per bucket, or (without buckets) per run of buckets of the
     // same register fit: a task's kernel depends only on its own sizes
@@ -289,9 +338,16 @@ eclqr_status run_engine(const Engine& E, const DevEngine& d, const Inputs& in, d
       k = k1;
     }
   }
-  { Timed tm(ECLQR_K_DOMAIN, s); launch_domain(d, in, t, status, std::max(1, E.maxn), s); }
+  const std::vector<Engine::StageBucket> one = stage_buckets(E, true);
+  for (const auto& b : one) {
+    Timed tm(ECLQR_K_DOMAIN, s);
+    launch_domain(d, in, t, status, b.maxn, b.begin, b.count, s);
+  }
   if ((sst = at_step(0, 0)) != ECLQR_SUCCESS) return sst;
-  { Timed tm(ECLQR_K_ELIMINATE, s); launch_eliminate(d, in, t, status, std::max(1, E.maxm), E.elim_maxq, std::max(1, E.maxn), E.maxk, s); }
+  for (const auto& b : one) {
+    Timed tm(ECLQR_K_ELIMINATE, s);
+    launch_eliminate(d, in, t, status, b.maxm, b.elim_maxq, b.maxn, b.maxk, b.begin, b.count, s);
+  }
   for (int l = 0; l < 2 * E.D; ++l) {
     if (E.lvl_count[l] == 0) continue;
     // one launch per dim bucket (tasks in ric_perm order), or the whole level
@@ -306,7 +362,10 @@ eclqr_status run_engine(const Engine& E, const DevEngine& d, const Inputs& in, d
     }
     if ((sst = at_step(1, l)) != ECLQR_SUCCESS) return sst;
   }
-  { Timed tm(ECLQR_K_GAINS, s); launch_gains(d, status, std::max(1, E.maxm), std::max(1, E.maxn), s); }
+  for (const auto& b : one) {
+    Timed tm(ECLQR_K_GAINS, s);
+    launch_gains(d, status, b.maxm, b.maxn, b.begin, b.count, s);
+  }
   if ((sst = at_step(2, 0)) != ECLQR_SUCCESS) return sst;
   for (int l = 0; l < 2 * E.D; ++l) {
     if (E.lvl_count[l] == 0) continue;
@@ -542,7 +601,7 @@ eclqr_status theta_multipliers(Plan& p, const Views& v, const Inputs& in, const 
   const Tols td{p.opt.rank_tol, p.opt.dual_cons_tol, 0};
   {
     Timed tm(ECLQR_K_MULT_THETA, s);
-    if (!launch_theta_local(v.P, v.T, in, x, u, td, status, p.th_q, p.th_ldw, p.th_r, full ? 0 : 1, s))
+    if (!theta_local_all(p, v.P, v.T, in, x, u, td, status, full ? 0 : 1, s))
       return fail(ECLQR_UNSUPPORTED, "stage too large for the LDS tile of the minimum-norm local systems");
   }
   int32_t* defer = at<int32_t>(v.ws, p.o_defer);
@@ -572,7 +631,7 @@ eclqr_status theta_multipliers(Plan& p, const Views& v, const Inputs& in, const 
   }
   if (full) {
     Timed tm(ECLQR_K_GAINS, s);
-    launch_gains(v.T, status, std::max(1, T.maxm), std::max(1, T.maxn), s);
+    gains_all(T, v.T, status, s);
   } else {
     Timed tm(ECLQR_K_REPLAY, s);
     launch_gains_vec(v.T, s);
@@ -624,7 +683,7 @@ eclqr_status theta_prefactor_step(Plan& p, const Views& v, const Inputs& in, hip
     const Tols td{p.opt.rank_tol, p.opt.dual_cons_tol, 0};
     Timed tm(ECLQR_K_MULT_THETA, s2);
     launch_fill_i32(v.dstatus, 0, p.primal.B, s2);
-    if (!launch_theta_local(P, Th, in, nullptr, nullptr, td, v.dstatus, p.th_q, p.th_ldw, p.th_r, 2, s2))
+    if (!theta_local_all(p, P, Th, in, nullptr, nullptr, td, v.dstatus, 2, s2))
       return fail(ECLQR_UNSUPPORTED, "stage too large for the LDS tile of the minimum-norm local systems");
     launch_fill_i32(defer, 0, 2 * T.D, s2);
   } else if (step == 1 && T.lvl_count[l] > 0) {
@@ -633,7 +692,7 @@ eclqr_status theta_prefactor_step(Plan& p, const Views& v, const Inputs& in, hip
   } else if (step == 2) {
     {
       Timed tm(ECLQR_K_GAINS, s2);
-      launch_gains(Th, v.dstatus, std::max(1, T.maxm), std::max(1, T.maxn), s2);
+      gains_all(T, Th, v.dstatus, s2);
     }
     Timed tm(ECLQR_K_MULT_THETA, s2);
     launch_theta_init(Th, s2);

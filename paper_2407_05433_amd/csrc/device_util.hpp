@@ -40,6 +40,12 @@ __device__ __forceinline__ bool gated(const DevEngine& e, int inst) { return e.g
 // would be gated, so the kernel returns before reading its task list
 __device__ __forceinline__ bool none_live(const DevEngine& e) { return e.live && *e.live == 0; }
 
+// Stage at position t of a stage-kernel launch over [first, first + count) of
+// the plan's size order.
+__device__ __forceinline__ int64_t stage_at(const DevEngine& e, int64_t first, int64_t t) {
+  return e.stage_perm ? (int64_t)e.stage_perm[first + t] : first + t;
+}
+
 __device__ __forceinline__ double* block_scratch(const DevEngine& e) {
   return e.scratch + (int64_t)blockIdx.x * e.scratch_per_block;
 }

@@ -37,7 +37,7 @@ struct Bump {
 // on L2)]
 template <bool kLS>
 __global__ void __launch_bounds__(kBlock) k_eliminate(DevEngine e, Inputs in, Tols t, int32_t* status, int maxm,
-                                                      int maxq) {
+                                                      int maxq, int64_t first, int64_t count) {
   extern __shared__ double lds[];
   double* Wq = lds;
   double* tau = Wq + (int64_t)maxm * maxq;
@@ -47,7 +47,8 @@ __global__ void __launch_bounds__(kBlock) k_eliminate(DevEngine e, Inputs in, To
   double* sh = Lc + (int64_t)maxm * maxm;
   double* red = sh + 16;
   double* lscr = red + kBlock;
-  for (int64_t s = blockIdx.x; s < e.S; s += gridDim.x) {
+  for (int64_t ti = blockIdx.x; ti < count; ti += gridDim.x) {
+    const int64_t s = stage_at(e, first, ti);
     const StageInfo st = e.st[s];
     if (gated(e, st.inst)) continue;
     const int n = st.n, np = st.np, m = st.m, k = st.k;
@@ -380,19 +381,21 @@ size_t elim_lds_bytes(int maxm, int maxq) {
 }
 
 void launch_eliminate(const DevEngine& e, const Inputs& in, Tols t, int32_t* status, int maxm, int maxq, int maxn,
-                      int maxk, hipStream_t s) {
+                      int maxk, int64_t first, int64_t count, hipStream_t s) {
+  if (count <= 0) return;
   const size_t base = elim_lds_bytes(maxm, maxq);
   const size_t with = base + sizeof(double) * (size_t)elim_scratch(maxn, maxn, maxm, maxk);
   // LDS only while a workgroup needs at most 32 KiB: above that the lost
   // occupancy costs more than the faster accesses gain
   if (e.elim_lds == 1 && with <= 32768 && with <= (size_t)g_elim_max_lds) {
-    const int grid = task_grid(e, e.S);
+    const int grid = task_grid(e, count);
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_eliminate<true>), dim3(grid), dim3(kBlock), with, s, e, in, t, status, maxm,
-                       maxq);
+                       maxq, first, count);
   } else {
-    const int grid = fit_grid(reinterpret_cast<const void*>(k_eliminate<false>), kBlock, base, e.nblocks);
+    const int grid =
+        fit_grid(reinterpret_cast<const void*>(k_eliminate<false>), kBlock, base, count < e.nblocks ? count : e.nblocks);
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_eliminate<false>), dim3(grid), dim3(kBlock), base, s, e, in, t, status, maxm,
-                       maxq);
+                       maxq, first, count);
   }
 }
 

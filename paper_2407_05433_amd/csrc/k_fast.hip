@@ -309,7 +309,7 @@ size_t theta_local_lds_bytes(int maxq, int ldw, int maxr) { return (size_t)theta
 template <int kMode>
 __global__ void __launch_bounds__(kBlock) k_theta_local(DevEngine p, DevEngine th, Inputs in, const double* x,
                                                         const double* u, Tols t, int32_t* status, int maxq, int ldw,
-                                                        int maxr) {
+                                                        int maxr, int64_t first, int64_t count) {
   constexpr bool kVec = kMode == 1;
   constexpr bool kMat = kMode == 2;
   extern __shared__ double lds[];
@@ -327,7 +327,8 @@ __global__ void __launch_bounds__(kBlock) k_theta_local(DevEngine p, DevEngine t
   double* tmp = gu + kMaxDim;
   int* perm = (int*)(tmp + kMaxDim);
   if (none_live(p)) return;
-  for (int64_t s = blockIdx.x; s < p.S; s += gridDim.x) {
+  for (int64_t ti = blockIdx.x; ti < count; ti += gridDim.x) {
+    const int64_t s = stage_at(p, first, ti);
     const StageInfo st = p.st[s];
     if (gated(p, st.inst)) continue;
     const StageInfo ts = th.st[s];
@@ -631,19 +632,21 @@ void theta_set_max_lds(int bytes) {
                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 bool launch_theta_local(const DevEngine& p, const DevEngine& th, const Inputs& in, const double* x, const double* u,
-                        Tols t, int32_t* status, int maxq, int ldw, int maxr, int mode, hipStream_t s) {
+                        Tols t, int32_t* status, int maxq, int ldw, int maxr, int mode, int64_t first,
+                        int64_t count, hipStream_t s) {
   const size_t lds = theta_local_lds_bytes(maxq, ldw, maxr);
   if (lds > (size_t)g_theta_max_lds) return false;
-  const int grid = task_grid(p, p.S);
+  if (count <= 0) return true;
+  const int grid = task_grid(p, count);
   if (mode == 1)
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_theta_local<1>), dim3(grid), dim3(kBlock), lds, s, p, th, in, x, u, t, status,
-                       maxq, ldw, maxr);
+                       maxq, ldw, maxr, first, count);
   else if (mode == 2)
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_theta_local<2>), dim3(grid), dim3(kBlock), lds, s, p, th, in, x, u, t, status,
-                       maxq, ldw, maxr);
+                       maxq, ldw, maxr, first, count);
   else
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_theta_local<0>), dim3(grid), dim3(kBlock), lds, s, p, th, in, x, u, t, status,
-                       maxq, ldw, maxr);
+                       maxq, ldw, maxr, first, count);
   return true;
 }
 void launch_theta_init(const DevEngine& th, hipStream_t s) {

@@ -1046,12 +1046,14 @@ __global__ void __launch_bounds__(kBlock) k_ric_combine_deferred(DevEngine e, in
 // LDS: Huu (maxm x maxm) | sh [| working arrays, kLS: in LDS instead of the
 // workgroup's global scratch]
 template <bool kLS>
-__global__ void __launch_bounds__(kBlock) k_gains(DevEngine e, int32_t* status, int maxm) {
+__global__ void __launch_bounds__(kBlock) k_gains(DevEngine e, int32_t* status, int maxm, int64_t first,
+                                                  int64_t count) {
   extern __shared__ double lds[];
   double* Huu = lds;
   double* sh = Huu + (int64_t)maxm * maxm;
   double* lscr = sh + 16;
-  for (int64_t s = blockIdx.x; s < e.S; s += gridDim.x) {
+  for (int64_t ti = blockIdx.x; ti < count; ti += gridDim.x) {
+    const int64_t s = stage_at(e, first, ti);
     const StageInfo st = e.st[s];
     if (st.terminal || gated(e, st.inst)) continue;
     const int n = st.n, np = st.np, m = st.m;
@@ -1284,15 +1286,20 @@ void launch_ric_combine_lane(const DevEngine& e, int64_t first, int64_t ntasks, 
   }
 }
 
-void launch_gains(const DevEngine& e, int32_t* status, int maxm, int maxn, hipStream_t s) {
+void launch_gains(const DevEngine& e, int32_t* status, int maxm, int maxn, int64_t first, int64_t count,
+                  hipStream_t s) {
+  if (count <= 0) return;
   const size_t base = gains_lds_bytes(maxm);
   const size_t with = base + sizeof(double) * (size_t)gains_scratch(maxn, maxn, maxm);
   if (e.elim_lds && with <= 32768 && with <= (size_t)g_lqr_max_lds) {
-    const int grid = task_grid(e, e.S);
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gains<true>), dim3(grid), dim3(kBlock), with, s, e, status, maxm);
+    const int grid = task_grid(e, count);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gains<true>), dim3(grid), dim3(kBlock), with, s, e, status, maxm, first,
+                       count);
   } else {
-    const int grid = fit_grid(reinterpret_cast<const void*>(k_gains<false>), kBlock, base, e.nblocks);
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gains<false>), dim3(grid), dim3(kBlock), base, s, e, status, maxm);
+    const int grid =
+        fit_grid(reinterpret_cast<const void*>(k_gains<false>), kBlock, base, count < e.nblocks ? count : e.nblocks);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gains<false>), dim3(grid), dim3(kBlock), base, s, e, status, maxm, first,
+                       count);
   }
 }
 

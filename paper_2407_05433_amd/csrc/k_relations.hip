@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(kBlock) k_vacuous(DevEngine e, Inputs in, Tols
 // arrays stay in LDS.
 template <bool kGW>
 __global__ void __launch_bounds__(kBlock) k_base_relation(DevEngine e, Inputs in, Tols t, int32_t* status, int maxp,
-                                                          int ldw) {
+                                                          int ldw, int64_t first, int64_t count) {
   extern __shared__ double lds[];
   double* W = kGW ? e.gw + (int64_t)blockIdx.x * e.gw_stride : lds;
   double* tau = kGW ? lds : W + (int64_t)maxp * (ldw | 1);
@@ -134,7 +134,8 @@ __global__ void __launch_bounds__(kBlock) k_base_relation(DevEngine e, Inputs in
   int* perm = (int*)(qd + kMaxDim + 8);
   double* rbs = (double*)(perm + kMaxDim);
   double* sh = rbs + 2 * maxp + 8 + 64;
-  for (int64_t s = blockIdx.x; s < e.S; s += gridDim.x) {
+  for (int64_t ti = blockIdx.x; ti < count; ti += gridDim.x) {
+    const int64_t s = stage_at(e, first, ti);
     const StageInfo st = e.st[s];
     if (gated(e, st.inst)) continue;
     const int n = st.n, np = st.np, m = st.m, k = st.k;
@@ -536,7 +537,8 @@ __global__ void __launch_bounds__(kBlock) k_rel_compose_reg(DevEngine e, int64_t
 // T_i^T.  On stage 0 also eq. (initial-feasibility) and z_0 (eq.
 // (reduced-initial)), written as the constant leaf of the forward scan.
 // LDS: Ht (maxn x maxn) | X (maxn x maxn) | tau | qr scratch | perm
-__global__ void __launch_bounds__(kBlock) k_domain(DevEngine e, Inputs in, Tols t, int32_t* status, int maxn) {
+__global__ void __launch_bounds__(kBlock) k_domain(DevEngine e, Inputs in, Tols t, int32_t* status, int maxn,
+                                                   int64_t first, int64_t count) {
   extern __shared__ double lds[];
   double* Ht = lds;
   double* X = Ht + maxn * maxn;
@@ -544,7 +546,8 @@ __global__ void __launch_bounds__(kBlock) k_domain(DevEngine e, Inputs in, Tols 
   double* qd = tau + kMaxDim;
   int* perm = (int*)(qd + kMaxDim + 8);
   double* sh = (double*)(perm + kMaxDim);
-  for (int64_t s = blockIdx.x; s < e.S; s += gridDim.x) {
+  for (int64_t ti = blockIdx.x; ti < count; ti += gridDim.x) {
+    const int64_t s = stage_at(e, first, ti);
     const StageInfo st = e.st[s];
     if (gated(e, st.inst)) continue;
     const int n = st.n;
@@ -639,17 +642,20 @@ static bool rel_global(const DevEngine& e, int maxp, int ldw) {
 static size_t rel_tile_bytes(int maxp, int ldw) { return sizeof(double) * (size_t)maxp * (ldw | 1); }
 
 void launch_base_relation(const DevEngine& e, const Inputs& in, Tols t, int32_t* status, int maxp, int ldw,
-                          hipStream_t s) {
+                          int64_t first, int64_t count, hipStream_t s) {
+  if (count <= 0) return;
   if (rel_global(e, maxp, ldw)) {
-    const int grid = e.nblocks < e.gw_blocks ? e.nblocks : e.gw_blocks;
+    int grid = e.nblocks < e.gw_blocks ? e.nblocks : e.gw_blocks;
+    grid = (int)(count < grid ? count : grid);
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_base_relation<true>), dim3(grid), dim3(kBlock),
-                       rel_lds_bytes(maxp, ldw) - rel_tile_bytes(maxp, ldw), s, e, in, t, status, maxp, ldw);
+                       rel_lds_bytes(maxp, ldw) - rel_tile_bytes(maxp, ldw), s, e, in, t, status, maxp, ldw, first,
+                       count);
     return;
   }
   const size_t lds = rel_lds_bytes(maxp, ldw);
-  const int grid = task_grid(e, e.S);
+  const int grid = task_grid(e, count);
   hipLaunchKernelGGL(HIP_KERNEL_NAME(k_base_relation<false>), dim3(grid), dim3(kBlock), lds, s, e, in, t, status, maxp,
-                     ldw);
+                     ldw, first, count);
 }
 
 bool rel_fits(const DevEngine& e, int maxp, int ldw) {
@@ -690,10 +696,12 @@ void launch_rel_compose(const DevEngine& e, int64_t first, int64_t ntasks, Tols 
                      maxp, ldw);
 }
 
-void launch_domain(const DevEngine& e, const Inputs& in, Tols t, int32_t* status, int maxn, hipStream_t s) {
+void launch_domain(const DevEngine& e, const Inputs& in, Tols t, int32_t* status, int maxn, int64_t first,
+                   int64_t count, hipStream_t s) {
+  if (count <= 0) return;
   const size_t lds = domain_lds_bytes(maxn);
-  const int grid = task_grid(e, e.S);
-  hipLaunchKernelGGL(k_domain, dim3(grid), dim3(kBlock), lds, s, e, in, t, status, maxn);
+  const int grid = task_grid(e, count);
+  hipLaunchKernelGGL(k_domain, dim3(grid), dim3(kBlock), lds, s, e, in, t, status, maxn, first, count);
 }
 
 }  // namespace eclqr

@@ -40,6 +40,7 @@ struct DevEngine {
   int64_t S;
   int32_t B;
   int32_t nslots;
+  const int32_t* stage_perm;  // stages in the plan's size order (stage-kernel launch ranges), null = stage order
   int32_t nblocks;            // grid size of the stage-parallel kernels (grid-stride)
   int32_t task_grid;          // grid cap of the kernels without per-workgroup global scratch: large (one workgroup
                               // per task, so the dispatcher balances tasks of unequal cost) or nblocks
@@ -91,13 +92,15 @@ void launch_vacuous(const DevEngine& e, const Inputs& in, Tols t, int32_t* vac, 
 // a stacked relation system of maxp x ldw fits LDS or a global tile of the plan
 bool rel_fits(const DevEngine& e, int maxp, int ldw);
 void launch_base_relation(const DevEngine& e, const Inputs& in, Tols t, int32_t* status, int maxp, int ldw,
-                          hipStream_t s);
+                          int64_t first, int64_t count, hipStream_t s);
 // maxkc: most coefficient columns (n_a + n_c) of a result in the launch
 void launch_rel_compose(const DevEngine& e, int64_t first_task, int64_t ntasks, Tols t, int32_t* status, int maxp,
                         int ldw, int maxkc, hipStream_t s);
-void launch_domain(const DevEngine& e, const Inputs& in, Tols t, int32_t* status, int maxn, hipStream_t s);
+// stage kernels: the stages at positions [first, first + count) of the plan's size order
+void launch_domain(const DevEngine& e, const Inputs& in, Tols t, int32_t* status, int maxn, int64_t first,
+                   int64_t count, hipStream_t s);
 void launch_eliminate(const DevEngine& e, const Inputs& in, Tols t, int32_t* status, int maxm, int maxq, int maxn,
-                      int maxk, hipStream_t s);
+                      int maxk, int64_t first, int64_t count, hipStream_t s);
 void launch_ric_combine(const DevEngine& e, int64_t first_task, int64_t ntasks, int32_t* status, int maxd,
                         hipStream_t s);
 // the same combines, one lane per task where every reduced dim is <= 4 (the
@@ -106,7 +109,8 @@ void launch_ric_combine(const DevEngine& e, int64_t first_task, int64_t ntasks, 
 // wavefront); for engines whose reduced dims are mostly tiny
 void launch_ric_combine_lane(const DevEngine& e, int64_t first, int64_t ntasks, int32_t* defer_count,
                              int32_t* defer_list, hipStream_t s);
-void launch_gains(const DevEngine& e, int32_t* status, int maxm, int maxn, hipStream_t s);
+void launch_gains(const DevEngine& e, int32_t* status, int maxm, int maxn, int64_t first, int64_t count,
+                  hipStream_t s);
 void launch_fwd_combine(const DevEngine& e, int64_t first_task, int64_t ntasks, hipStream_t s);
 void launch_recover(const DevEngine& e, double* x, double* u, hipStream_t s);
 
@@ -263,7 +267,8 @@ size_t theta_local_lds_bytes(int maxq, int ldw, int maxr);
 // column's consistency is checked); 2: matrix pass (every vector zero; reads
 // neither x, u nor the primal's value-function and forward scans)
 bool launch_theta_local(const DevEngine& p, const DevEngine& th, const Inputs& in, const double* x, const double* u,
-                        Tols t, int32_t* status, int maxq, int ldw, int maxr, int mode, hipStream_t s);
+                        Tols t, int32_t* status, int maxq, int ldw, int maxr, int mode, int64_t first,
+                        int64_t count, hipStream_t s);
 void launch_theta_init(const DevEngine& th, hipStream_t s);
 void launch_theta_final(const DevEngine& p, const DevEngine& th, double* lam, double* mu, int accumulate,
                         hipStream_t s);

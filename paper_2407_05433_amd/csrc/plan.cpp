@@ -454,6 +454,63 @@ std::string Engine::build(const eclqr_dims* d) {
   }
   scratch_per_block = std::max(scratch_per_block, ric_pool(maxn));
   scratch_per_block = rup4(scratch_per_block);
+  // Stage buckets.  The LDS of the stage kernels grows with the stacked
+  // system of the stage's base relation ((n' + k) x (m + n + n' + 1)), and LDS
+  // bounds how many workgroups a compute unit holds; with at least 4096
+  // stages they are launched in ranges of one size class each (tile area
+  // <= 128, 256, 512, 1024, 2048, 4096 doubles, or more; ranges of fewer than
+  // 1024 stages join the next class) over the stages ordered by that area.
+  stage_perm.clear();
+  sbk.clear();
+  {
+    auto area = [&](int64_t s) -> int64_t {
+      const StageInfo& x = st[s];
+      return x.terminal ? (int64_t)x.k * (x.n + 1) : (int64_t)(x.np + x.k) * (x.m + x.n + x.np + 1);
+    };
+    auto size_class = [](int64_t a) -> int64_t {
+      for (int64_t b = 128; b <= 4096; b *= 2)
+        if (a <= b) return b;
+      return 1 << 30;
+    };
+    std::vector<std::pair<int64_t, int32_t>> sv((size_t)S);
+    for (int64_t s = 0; s < S; ++s) sv[s] = {area(s), (int32_t)s};
+    const bool split = S >= 4096;
+    if (split) {
+      std::stable_sort(sv.begin(), sv.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+      stage_perm.resize((size_t)S);
+      for (int64_t s = 0; s < S; ++s) stage_perm[s] = sv[s].second;
+    }
+    int64_t t = 0;
+    while (t < S) {
+      int64_t u = S;
+      if (split) {
+        u = t + 1;
+        while (u < S && size_class(sv[u].first) == size_class(sv[t].first)) ++u;
+        while (u < S && u - t < 1024) ++u;
+        if (S - u < 1024) u = S;
+      }
+      StageBucket b;
+      b.begin = t;
+      b.count = u - t;
+      for (int64_t v = t; v < u; ++v) {
+        const StageInfo& x = st[sv[v].second];
+        b.maxn = std::max(b.maxn, std::max(x.n, x.np));  // a stage kernel also sizes its successor's state
+        b.maxm = std::max(b.maxm, x.m);
+        b.maxk = std::max(b.maxk, x.k);
+        if (x.terminal) {
+          b.base_maxp = std::max(b.base_maxp, x.k);
+          b.base_ldw = std::max(b.base_ldw, x.n + 1);
+        } else {
+          b.base_maxp = std::max(b.base_maxp, x.np + x.k);
+          b.base_ldw = std::max(b.base_ldw, x.m + x.n + x.np + 1);
+          b.elim_maxq = std::max(b.elim_maxq, x.k + x.np);
+        }
+      }
+      sbk.push_back(b);
+      t = u;
+    }
+    if (S == 0) sbk.push_back(StageBucket{});
+  }
   nblocks = (int32_t)std::min<int64_t>(std::max<int64_t>(S, 1), 8192);
 
   // global tiles for stacked relation systems that may outgrow LDS (48 KiB
@@ -482,6 +539,7 @@ std::string Engine::build(const eclqr_dims* d) {
   o_slot_rows = o; o = align256(o + sizeof(int32_t) * nslots);
   o_tasks = o; o = align256(o + sizeof(int32_t) * tasks.size() + 16);
   o_ric_perm = o; o = align256(o + sizeof(int32_t) * ric_perm.size() + 16);
+  o_stage_perm = o; o = align256(o + sizeof(int32_t) * stage_perm.size() + 16);
   o_nbar = o; o = align256(o + sizeof(int32_t) * S);
   o_mbar = o; o = align256(o + sizeof(int32_t) * S);
   o_resid = o; o = align256(o + sizeof(double) * 4 * S);
@@ -568,13 +626,19 @@ std::string build_plan(Plan& p, const eclqr_dims* d, const eclqr_options* opt) {
     // batches (the autotuner tries it); the reversed-time one pays everywhere
     p.overlap_dual = ok ? 0 : 1;
     p.th_q = p.th_ldw = p.th_r = 1;
-    for (int64_t s = 0; s < P.S; ++s) {
-      const StageInfo& x = P.st[s];
-      const int q = x.terminal ? x.k : x.k + x.np, R = x.terminal ? x.n : x.n + x.m;
-      p.th_q = std::max(p.th_q, q);
-      p.th_ldw = std::max(p.th_ldw, R | 1);
-      p.th_r = std::max(p.th_r, x.n);
-    }
+    p.th_bk.assign(P.sbk.size(), {1, 1, 1});
+    for (size_t b = 0; b < P.sbk.size(); ++b)
+      for (int64_t t = P.sbk[b].begin; t < P.sbk[b].begin + P.sbk[b].count; ++t) {
+        const StageInfo& x = P.st[P.stage_perm.empty() ? t : P.stage_perm[t]];
+        const int q = x.terminal ? x.k : x.k + x.np, R = x.terminal ? x.n : x.n + x.m;
+        auto& tb = p.th_bk[b];
+        tb[0] = std::max(tb[0], q);
+        tb[1] = std::max(tb[1], R | 1);
+        tb[2] = std::max(tb[2], x.n);
+        p.th_q = std::max(p.th_q, q);
+        p.th_ldw = std::max(p.th_ldw, R | 1);
+        p.th_r = std::max(p.th_r, x.n);
+      }
     // the local systems are factored in one LDS tile per stage: where that
     // tile exceeds the device's LDS the reversed-time route is laid out
     // instead (decided here, so a plan never switches routes at solve time)

@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <array>
 #include <vector>
 
 #include "common.hpp"
@@ -54,6 +55,15 @@ struct Engine {
   std::vector<int64_t> rbk_begin, rbk_count;
   std::vector<int32_t> rbk_dim;
   std::vector<int32_t> lvl_rbk_first, lvl_rbk_n;
+  // stage buckets: the stages ordered by size (stage_perm: absolute stage
+  // indices, in launch order; empty = stage order, one bucket) and cut into
+  // ranges whose stage kernels size their LDS to the range's largest stage
+  struct StageBucket {
+    int64_t begin = 0, count = 0;
+    int32_t maxn = 1, maxm = 1, maxk = 0, base_maxp = 1, base_ldw = 1, elim_maxq = 1;
+  };
+  std::vector<int32_t> stage_perm;
+  std::vector<StageBucket> sbk;
 
   // factor logs replayed by the vector-only pass, per output slot
   std::vector<int64_t> rel_log_off, ric_log_off;
@@ -77,7 +87,7 @@ struct Engine {
   size_t o_stage = 0, o_slot_off = 0, o_slot_na = 0, o_slot_nb = 0, o_slot_cap = 0, o_slot_rows = 0,
          o_tasks = 0, o_nbar = 0, o_mbar = 0, o_arena = 0, o_scan[SCAN_COUNT] = {0, 0, 0}, o_resid = 0,
          o_sbase = 0, o_scratch = 0, o_rel_log_off = 0, o_ric_log_off = 0, o_rel_log = 0, o_ric_log = 0,
-         o_theta = 0, o_vac = 0, o_gw = 0, o_ric_perm = 0;
+         o_theta = 0, o_vac = 0, o_gw = 0, o_ric_perm = 0, o_stage_perm = 0;
   size_t bytes = 0;
 
   std::string build(const eclqr_dims* d);
@@ -108,6 +118,7 @@ struct Plan {
   size_t o_theta_eng = 0;
   size_t o_defer = 0;         // per level: count of deferred combines (2 D ints), then one task list
   int32_t th_q = 1, th_ldw = 1, th_r = 1;  // LDS tile of the local minimum-norm systems
+  std::vector<std::array<int32_t, 3>> th_bk;  // the same over each stage bucket of the problem (q, ldw, r)
   int32_t mult_route = 1;     // 1: theta LQR (when theta_ok), 0: reversed-time problem
   // What each workspace holds: the factorizations of the last solve made in
   // it (multiplier route, problem and solution pointers).  eclqr_backward
