@@ -276,33 +276,27 @@ __global__ void __launch_bounds__(kBlock) k_refine_decide(DevEngine p, const int
   }
 }
 
-// v += sum_l a[l sa] b[l sb], mag += sum_l |a[l sa] b[l sb]| and
-// an += sum_l |a[l sa]| in ascending l (the same sums as a plain loop), with
-// the loads of each batch of 8 issued before its additions.
-__device__ __forceinline__ void acc_terms(const double* a, int sa, const double* b, int sb, int n, double& v,
-                                          double& mag, double& an) {
-  int l = 0;
-  for (; l + 8 <= n; l += 8) {
-    double av[8], t[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      av[j] = a[(l + j) * sa];
-      t[j] = av[j] * b[(l + j) * sb];
-    }
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      v += t[j];
-      mag += fabs(t[j]);
-      an += fabs(av[j]);
-    }
-  }
-  for (; l < n; ++l) {
+// The share of one lane of an 8-lane row group of v += sum_l a[l sa] b[l],
+// mag += sum_l |a[l sa] b[l]|, an += sum_l |a[l sa]|: the terms l = c, c + 8,
+// ... (c the lane's place in its group), so the group's loads of one step
+// are 8 consecutive elements of a row-major row, or of 8 rows at one column.
+__device__ __forceinline__ void acc_part(const double* a, int sa, const double* b, int n, int c, double& v, double& mag,
+                                         double& an) {
+  for (int l = c; l < n; l += 8) {
     const double av = a[l * sa];
-    const double t = av * b[l * sb];
+    const double t = av * b[l];
     v += t;
     mag += fabs(t);
     an += fabs(av);
   }
+}
+
+// Sum over the 8 lanes of a row group (every lane ends with the group's sum).
+__device__ __forceinline__ double group8_sum(double v) {
+  v += __shfl_xor(v, 4, 8);
+  v += __shfl_xor(v, 2, 8);
+  v += __shfl_xor(v, 1, 8);
+  return v;
 }
 
 // Largest |entry| of x, u, lambda, mu per instance (the scale of the
@@ -333,7 +327,9 @@ __global__ void __launch_bounds__(kBlock) k_unknown_scale(DevEngine p, const dou
 // of Arioli, Demmel and Duff (SIAM J. Matrix Anal. Appl. 10(2), 1989).  Rows
 // whose data and solution are near zero (an offset of rounding size, as in a
 // Newton step at a feasible point) would otherwise demand a relative accuracy
-// no solver reaches.  The maximum over rows; one wavefront per stage; the
+// no solver reaches.  The maximum over rows; one wavefront per stage, eight
+// rows at a time, each split over 8 lanes (coalesced 8-element segments of
+// the row-major blocks instead of a row per lane); the
 // per-instance maximum is accumulated with an integer atomic max on the bit
 // pattern (order independent, so deterministic).
 __global__ void __launch_bounds__(kBlock) k_backward_error(DevEngine p, Inputs in, const double* x, const double* u,
@@ -341,6 +337,7 @@ __global__ void __launch_bounds__(kBlock) k_backward_error(DevEngine p, Inputs i
                                                            const unsigned long long* wmax,
                                                            unsigned long long* omega) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
+  const int g = lane >> 3, c = lane & 7;  // row group (a row per group at a time), place in the group
   constexpr double kEps = 2.220446049250313e-16;
   for (int64_t s = (int64_t)blockIdx.x * waves + wave; s < p.S; s += (int64_t)gridDim.x * waves) {
     const StageInfo st = p.st[s];
@@ -353,7 +350,7 @@ __global__ void __launch_bounds__(kBlock) k_backward_error(DevEngine p, Inputs i
     const double* Q = in.f[IN_Q] + st.in[IN_Q];
     const double* q = in.f[IN_q] + st.in[IN_q];
     const double* E = in.f[IN_E] + st.in[IN_E];
-    const double* g = in.f[IN_g] + st.in[IN_g];
+    const double* gv = in.f[IN_g] + st.in[IN_g];
     const bool term = st.terminal;
     const double* us = term ? nullptr : u + st.in[IN_r];
     const double* F = term ? nullptr : in.f[IN_F] + st.in[IN_F];
@@ -362,7 +359,7 @@ __global__ void __launch_bounds__(kBlock) k_backward_error(DevEngine p, Inputs i
     const double* B = term ? nullptr : in.f[IN_B] + st.in[IN_B];
     const double* R = term ? nullptr : in.f[IN_R] + st.in[IN_R];
     const double* r = term ? nullptr : in.f[IN_r] + st.in[IN_r];
-    const double* c = term ? nullptr : in.f[IN_c] + st.in[IN_c];
+    const double* cv = term ? nullptr : in.f[IN_c] + st.in[IN_c];
     const double* x1 = term ? nullptr : x + p.st[s + 1].in[IN_q];
     const double* l1 = term ? nullptr : lam + p.st[s + 1].in[IN_q];
     double w = 0.0;
@@ -374,38 +371,65 @@ __global__ void __launch_bounds__(kBlock) k_backward_error(DevEngine p, Inputs i
       const double e = (den > 0.0) ? fabs(res) / den : (res == 0.0 ? 0.0 : HUGE_VAL);
       w = (e > w || e != e) ? e : w;
     };
-    for (int i = lane; i < n; i += 64) {  // stationarity in x_i
-      double v = q[i] - ls[i], a = fabs(q[i]) + fabs(ls[i]), an = 1.0;
-      acc_terms(Q + i * n, 1, xs, 1, n, v, a, an);
-      acc_terms(E + i, n, ms, 1, k, v, a, an);
-      int len = 2 + n + k;
-      if (!term) {
-        if (M) acc_terms(M + i * m, 1, us, 1, m, v, a, an);
-        acc_terms(A + i, n, l1, 1, np, v, a, an);
-        len += (M ? m : 0) + np;
+    // every family of rows: each row group takes rows g, g + 8, ...; its 8
+    // lanes split the row's terms, then sum them (all lanes of the wave run
+    // the group sums)
+    for (int i0 = 0; i0 < n; i0 += 8) {  // stationarity in x_i
+      const int i = i0 + g;
+      double v = 0.0, a = 0.0, an = 0.0;
+      if (i < n) {
+        acc_part(Q + i * n, 1, xs, n, c, v, a, an);
+        acc_part(E + i, n, ms, k, c, v, a, an);
+        if (!term) {
+          if (M) acc_part(M + i * m, 1, us, m, c, v, a, an);
+          acc_part(A + i, n, l1, np, c, v, a, an);
+        }
       }
-      acc(v, a, an, q[i], len);
+      v = group8_sum(v);
+      a = group8_sum(a);
+      an = group8_sum(an);
+      if (i < n)
+        acc((q[i] - ls[i]) + v, (fabs(q[i]) + fabs(ls[i])) + a, 1.0 + an, q[i],
+            2 + n + k + (term ? 0 : (M ? m : 0) + np));
     }
-    for (int i = lane; i < k; i += 64) {  // equality rows
-      double v = g[i], a = fabs(g[i]), an = 0.0;
-      acc_terms(E + i * n, 1, xs, 1, n, v, a, an);
-      if (!term) acc_terms(F + i * m, 1, us, 1, m, v, a, an);
-      acc(v, a, an, g[i], 1 + n + (term ? 0 : m));
+    for (int i0 = 0; i0 < k; i0 += 8) {  // equality rows
+      const int i = i0 + g;
+      double v = 0.0, a = 0.0, an = 0.0;
+      if (i < k) {
+        acc_part(E + i * n, 1, xs, n, c, v, a, an);
+        if (!term) acc_part(F + i * m, 1, us, m, c, v, a, an);
+      }
+      v = group8_sum(v);
+      a = group8_sum(a);
+      an = group8_sum(an);
+      if (i < k) acc(gv[i] + v, fabs(gv[i]) + a, an, gv[i], 1 + n + (term ? 0 : m));
     }
     if (!term) {
-      for (int i = lane; i < m; i += 64) {  // stationarity in u_i
-        double v = r[i], a = fabs(r[i]), an = 0.0;
-        acc_terms(R + i * m, 1, us, 1, m, v, a, an);
-        if (M) acc_terms(M + i, m, xs, 1, n, v, a, an);
-        acc_terms(B + i, m, l1, 1, np, v, a, an);
-        acc_terms(F + i, m, ms, 1, k, v, a, an);
-        acc(v, a, an, r[i], 1 + m + (M ? n : 0) + np + k);
+      for (int i0 = 0; i0 < m; i0 += 8) {  // stationarity in u_i
+        const int i = i0 + g;
+        double v = 0.0, a = 0.0, an = 0.0;
+        if (i < m) {
+          acc_part(R + i * m, 1, us, m, c, v, a, an);
+          if (M) acc_part(M + i, m, xs, n, c, v, a, an);
+          acc_part(B + i, m, l1, np, c, v, a, an);
+          acc_part(F + i, m, ms, k, c, v, a, an);
+        }
+        v = group8_sum(v);
+        a = group8_sum(a);
+        an = group8_sum(an);
+        if (i < m) acc(r[i] + v, fabs(r[i]) + a, an, r[i], 1 + m + (M ? n : 0) + np + k);
       }
-      for (int i = lane; i < np; i += 64) {  // dynamics
-        double v = c[i] - x1[i], a = fabs(c[i]) + fabs(x1[i]), an = 1.0;
-        acc_terms(A + i * n, 1, xs, 1, n, v, a, an);
-        acc_terms(B + i * m, 1, us, 1, m, v, a, an);
-        acc(v, a, an, c[i], 2 + n + m);
+      for (int i0 = 0; i0 < np; i0 += 8) {  // dynamics
+        const int i = i0 + g;
+        double v = 0.0, a = 0.0, an = 0.0;
+        if (i < np) {
+          acc_part(A + i * n, 1, xs, n, c, v, a, an);
+          acc_part(B + i * m, 1, us, m, c, v, a, an);
+        }
+        v = group8_sum(v);
+        a = group8_sum(a);
+        an = group8_sum(an);
+        if (i < np) acc((cv[i] - x1[i]) + v, (fabs(cv[i]) + fabs(x1[i])) + a, 1.0 + an, cv[i], 2 + n + m);
       }
     }
     if (st.i == 0)

@@ -36,7 +36,7 @@ struct Bump {
 // workgroup's global scratch (every dependent access then waits on LDS, not
 // on L2)]
 template <bool kLS>
-__global__ void __launch_bounds__(kBlock) k_eliminate(DevEngine e, Inputs in, Tols t, int32_t* status, int maxm,
+__global__ void __launch_bounds__(kBlock, kLS ? 1 : 4) k_eliminate(DevEngine e, Inputs in, Tols t, int32_t* status, int maxm,
                                                       int maxq, int64_t first, int64_t count) {
   extern __shared__ double lds[];
   double* Wq = lds;
