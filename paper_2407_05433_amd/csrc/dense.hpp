@@ -144,6 +144,57 @@ __device__ __forceinline__ double lane_trsv_lower_t(const double* L, int ld, dou
   }
   return v;
 }
+// lane_trsv_lower and lane_trsv_lower_t for n <= NM with the lane's row
+// (column) of L loaded into registers before the first step, so the solve
+// waits on memory once instead of once a step (L in global memory).  Same
+// operations in the same order, so the same bits.
+template <int NM>
+__device__ __forceinline__ double lane_trsv_lower_pre(const double* L, int ld, double v, int n) {
+  const int lane = ECLQR_TID;
+  const int r = (lane < n) ? lane : 0;
+  double row[NM];
+#pragma unroll
+  for (int i = 0; i < NM; ++i) row[i] = L[r * ld + ((i < n) ? i : 0)];
+  const double rd = (lane < n) ? 1.0 / L[lane * ld + lane] : 0.0;
+#pragma unroll
+  for (int i = 0; i < NM; ++i) {
+    if (i < n) {
+      if (lane == i) v *= rd;
+      const double xi = wave_bcast(v, i);
+      if (lane > i && lane < n) v = fma(-row[i], xi, v);
+    }
+  }
+  return v;
+}
+template <int NM>
+__device__ __forceinline__ double lane_trsv_lower_t_pre(const double* L, int ld, double v, int n) {
+  const int lane = ECLQR_TID;
+  const int cl = (lane < n) ? lane : 0;
+  double col[NM];
+#pragma unroll
+  for (int i = 0; i < NM; ++i) col[i] = L[((i < n) ? i : 0) * ld + cl];
+  const double rd = (lane < n) ? 1.0 / L[lane * ld + lane] : 0.0;
+#pragma unroll
+  for (int i = NM - 1; i >= 0; --i) {
+    if (i < n) {
+      if (lane == i) v *= rd;
+      const double yi = wave_bcast(v, i);
+      if (lane < i) v = fma(-col[i], yi, v);
+    }
+  }
+  return v;
+}
+// Dispatch on n: preloaded for n <= 32, else the plain form.
+__device__ __forceinline__ double lane_trsv_lower_any(const double* L, int ld, double v, int n) {
+  if (n <= 16) return lane_trsv_lower_pre<16>(L, ld, v, n);
+  if (n <= 32) return lane_trsv_lower_pre<32>(L, ld, v, n);
+  return lane_trsv_lower(L, ld, v, n);
+}
+__device__ __forceinline__ double lane_trsv_lower_t_any(const double* L, int ld, double v, int n) {
+  if (n <= 16) return lane_trsv_lower_t_pre<16>(L, ld, v, n);
+  if (n <= 32) return lane_trsv_lower_t_pre<32>(L, ld, v, n);
+  return lane_trsv_lower_t(L, ld, v, n);
+}
 // U' y = x, U upper triangular.
 __device__ __forceinline__ double lane_trsv_upper_t(const double* U, int ld, double v, int n) {
   const int lane = ECLQR_TID;

@@ -501,20 +501,16 @@ __device__ inline void ric_combine_vec_task(const DevEngine& e, int64_t task, in
     const double* Lj = rlog + 4;
     const double* Rg = rlog + 4 + (int64_t)dm * dm;
     // xi = L^{-1} eta2 ; d = G^{-1}(xi - L'b1) ; eta = eta1 + A1' L d ; b = A2 L^{-T}(xi - d) + b2
+    // (with the log in global memory each solve preloads its operand rows)
     double xi = (ECLQR_TID < dm) ? et2[ECLQR_TID] : 0.0;
-    xi = lane_trsv_lower(Lj, dm, xi, dm);
+    xi = lane_trsv_lower_any(Lj, dm, xi, dm);
     double tvv = xi;
-    if (ECLQR_TID < dm)
-      for (int l = ECLQR_TID; l < dm; ++l) tvv = fma(-Lj[l * dm + ECLQR_TID], b1[l], tvv);
-    tvv = lane_trsv_lower(Rg, dm, tvv, dm);
-    tvv = lane_trsv_lower_t(Rg, dm, tvv, dm);
+    if (ECLQR_TID < dm) tvv = lane_chain<true>(tvv, Lj + ECLQR_TID * dm + ECLQR_TID, dm, b1 + ECLQR_TID, 1, dm - ECLQR_TID);
+    tvv = lane_trsv_lower_any(Rg, dm, tvv, dm);
+    tvv = lane_trsv_lower_t_any(Rg, dm, tvv, dm);
     if (ECLQR_TID < dm) v1[ECLQR_TID] = tvv;
     lds_sync();
-    if (ECLQR_TID < dm) {
-      double w = 0.0;
-      for (int l = 0; l <= ECLQR_TID; ++l) w = fma(Lj[ECLQR_TID * dm + l], v1[l], w);
-      v2[ECLQR_TID] = w;
-    }
+    if (ECLQR_TID < dm) v2[ECLQR_TID] = lane_chain<false>(0.0, Lj + ECLQR_TID * dm, 1, v1, 1, ECLQR_TID + 1);
     lds_sync();
     for (int i = ECLQR_TID; i < ds; i += ECLQR_NT) {
       double v = et1[i];
@@ -522,7 +518,7 @@ __device__ inline void ric_combine_vec_task(const DevEngine& e, int64_t task, in
       Eo[lo.eta + i] = v;
     }
     if (binary) {
-      double yl = lane_trsv_lower_t(Lj, dm, xi - tvv, dm);
+      double yl = lane_trsv_lower_t_any(Lj, dm, xi - tvv, dm);
       if (ECLQR_TID < dm) v3[ECLQR_TID] = yl;
       lds_sync();
       for (int i = ECLQR_TID; i < de; i += ECLQR_NT) {
