@@ -70,6 +70,49 @@ __device__ inline void stage_rel_log(double* dst, const double* lg, const RelLog
 // rows eliminated (rho) and kept (rr); the new offsets are o[rho .. rho+rr).
 // o lives in LDS and the log is read only, so LDS-only barriers order every
 // exchange.
+// The logged Householder reflectors applied to the offsets o (LDS, p rows):
+// step j takes w = (o_j + v_j'o_{j+1:}) tau_j, o_j -= w, o_{j+1:} -= w v_j.
+// With at most one row per lane the next step's reflector entry and tau are
+// loaded while this step runs (a log left in global memory then costs one
+// round trip per step less); same rows per lane and order, so the same bits.
+__device__ inline void apply_reflectors(double* o, const double* lg, const RelLog& L, int P, int p, int rho) {
+  const int lane = ECLQR_TID;
+  if (p <= ECLQR_NT) {
+    double vn = 0.0, tn = 0.0;
+    if (rho > 0) {
+      vn = (1 + lane < p) ? lg[L.V + 1 + lane] : 0.0;
+      tn = lg[L.tau];
+    }
+    for (int j = 0; j < rho; ++j) {
+      const int row = j + 1 + lane;
+      const double vj = vn, tj = tn;
+      if (j + 1 < rho) {
+        const int rn = row + 1;
+        vn = (rn < p) ? lg[L.V + (int64_t)(j + 1) * P + rn] : 0.0;
+        tn = lg[L.tau + j + 1];
+      }
+      double part = 0.0;
+      if (row < p) part = fma(vj, o[row], part);
+      const double w = (o[j] + wave_sum(part)) * tj;
+      lds_sync();
+      if (lane == 0) o[j] -= w;
+      if (row < p) o[row] = fma(-w, vj, o[row]);
+      lds_sync();
+    }
+    return;
+  }
+  for (int j = 0; j < rho; ++j) {
+    const double* v = lg + L.V + (int64_t)j * P;
+    double part = 0.0;
+    for (int row = j + 1 + lane; row < p; row += ECLQR_NT) part = fma(v[row], o[row], part);
+    const double w = (o[j] + wave_sum(part)) * lg[L.tau + j];
+    lds_sync();
+    if (lane == 0) o[j] -= w;
+    for (int row = j + 1 + lane; row < p; row += ECLQR_NT) o[row] = fma(-w, v[row], o[row]);
+    lds_sync();
+  }
+}
+
 __device__ inline void rel_replay(double* o, const double* lg, const RelLog& L, int P, int R, int C, bool scaled,
                                   int* rho_out, int* rr_out) {
   const RelHdr h = rel_header(lg, P, R, C);
@@ -78,16 +121,7 @@ __device__ inline void rel_replay(double* o, const double* lg, const RelLog& L, 
     for (int r = ECLQR_TID; r < p; r += ECLQR_NT) o[r] *= lg[L.scale + r];
     lds_sync();
   }
-  for (int j = 0; j < rho; ++j) {
-    const double* v = lg + L.V + (int64_t)j * P;
-    double part = 0.0;
-    for (int row = j + 1 + ECLQR_TID; row < p; row += ECLQR_NT) part = fma(v[row], o[row], part);
-    const double w = (o[j] + wave_sum(part)) * lg[L.tau + j];
-    lds_sync();
-    if (ECLQR_TID == 0) o[j] -= w;
-    for (int row = j + 1 + ECLQR_TID; row < p; row += ECLQR_NT) o[row] = fma(-w, v[row], o[row]);
-    lds_sync();
-  }
+  apply_reflectors(o, lg, L, P, p, rho);
   for (int sel = 0; sel < rr; ++sel) {
     const double* rec = lg + L.gs + (int64_t)sel * L.step;
     const int base = rho + sel;
@@ -126,29 +160,32 @@ __device__ inline void rel_replay_reg(double* o, const double* lg, const RelLog&
   int rr = h.rr;
   rr = (rr > q) ? q : rr;
   rr = (rr > 64) ? 64 : rr;
-  for (int j = 0; j < rho; ++j) {
-    const double* v = lg + L.V + (int64_t)j * P;
-    double part = 0.0;
-    for (int row = j + 1 + lane; row < p; row += ECLQR_NT) part = fma(v[row], o[row], part);
-    const double w = (o[j] + wave_sum(part)) * lg[L.tau + j];
-    lds_sync();
-    if (lane == 0) o[j] -= w;
-    for (int row = j + 1 + lane; row < p; row += ECLQR_NT) o[row] = fma(-w, v[row], o[row]);
-    lds_sync();
-  }
+  apply_reflectors(o, lg, L, P, p, rho);
   double v = (lane < q) ? o[rho + lane] : 0.0;
   bool chosen = lane >= q;
   double qoff = 0.0;
-  for (int sel = 0; sel < rr; ++sel) {
+  // each record (pivot, 1 / norm, coefficients on the chosen rows, on the
+  // remaining rows) is loaded one step ahead
+  auto load = [&](int sel, double& r0, double& r1, double& ra, double& rb) {
     const double* rec = lg + L.gs + (int64_t)sel * L.step;
-    int piv = (int)rec[0];
+    r0 = rec[0];
+    r1 = rec[1];
+    ra = (lane < sel) ? rec[2 + lane] : 0.0;
+    rb = (lane < q) ? rec[2 + C + lane] : 0.0;
+  };
+  double n0 = 0.0, n1 = 0.0, na = 0.0, nb = 0.0;
+  if (rr > 0) load(0, n0, n1, na, nb);
+  for (int sel = 0; sel < rr; ++sel) {
+    const double r0 = n0, r1 = n1, ra = na, rb = nb;
+    if (sel + 1 < rr) load(sel + 1, n0, n1, na, nb);
+    int piv = (int)r0;
     piv = (piv < 0 || piv >= q) ? 0 : piv;
     const double vp = wave_bcast(v, piv);
-    const double part = (lane < sel) ? rec[2 + lane] * qoff : 0.0;
-    const double nv = (vp - wave_sum(part)) * rec[1];
+    const double part = (lane < sel) ? ra * qoff : 0.0;
+    const double nv = (vp - wave_sum(part)) * r1;
     if (lane == sel) qoff = nv;
     if (lane == piv) chosen = true;
-    if (!chosen) v = fma(-rec[2 + C + lane], nv, v);
+    if (!chosen) v = fma(-rb, nv, v);
   }
   lds_sync();
   if (lane < rr) o[rho + lane] = qoff;
