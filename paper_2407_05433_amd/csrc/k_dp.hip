@@ -325,11 +325,6 @@ __global__ void k_flag_where(const int32_t* flag, int32_t* out, int32_t bit, int
     if (flag[b]) out[b] |= bit;
 }
 
-size_t dp_stride(int maxn, int maxm) {
-  const size_t nn = (size_t)maxn * maxn, mm2 = (size_t)maxm * maxm, nm = (size_t)maxn * maxm;
-  return 3 * nn + 3 * nm + 2 * mm2 + 3 * (size_t)maxn + 2 * (size_t)maxm + 16;
-}
-
 void launch_dp_fallback(const DevEngine& e, const Inputs& in, const int64_t* sbase, double* x, double* u,
                         int32_t* status, int32_t* info, int32_t* dpflag, double* scratch, int64_t stride,
                         int32_t blocks, int maxn, int maxm, hipStream_t s) {

@@ -178,7 +178,6 @@ void launch_ipm_step(const DevEngine& p, const IpmBounds& bd, double* x, double*
 // of work arrays per workgroup; the solve (classification, x, u, the value
 // functions and z of the scans' suffix slots) of every eligible instance;
 // their gates held out of refinement.
-size_t dp_stride(int maxn, int maxm);
 void launch_dp_fallback(const DevEngine& e, const Inputs& in, const int64_t* sbase, double* x, double* u,
                         int32_t* status, int32_t* info, int32_t* dpflag, double* scratch, int64_t stride,
                         int32_t blocks, int maxn, int maxm, hipStream_t s);

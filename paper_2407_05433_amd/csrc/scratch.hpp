@@ -44,6 +44,12 @@ ECLQR_HD inline int64_t ric_pool_staged(int d) {
   return 3 * dd + rup4((int64_t)d * (d + 1)) + 4 * rup4(d) + 64;
 }
 
+// Work arrays of one instance of the sequential fallback (doubles).
+ECLQR_HD inline int64_t dp_stride(int maxn, int maxm) {
+  const int64_t nn = (int64_t)maxn * maxn, mm2 = (int64_t)maxm * maxm, nm = (int64_t)maxn * maxm;
+  return 3 * nn + 3 * nm + 2 * mm2 + 3 * (int64_t)maxn + 2 * (int64_t)maxm + 16;
+}
+
 // gains: dims at capacity (n, n', m)
 ECLQR_HD inline int64_t gains_scratch(int n, int np, int m) {
   int64_t s = 0;
