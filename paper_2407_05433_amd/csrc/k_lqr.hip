@@ -1244,7 +1244,7 @@ void launch_ric_combine(const DevEngine& e, int64_t first, int64_t ntasks, int32
   const int grid = task_grid(e, ntasks);  // modes 1 and 2 and the split kernel keep their pool in LDS
   const int mode = ric_mode(e.pool_lds, maxd);
   // two wavefronts per combine while the level still fits the device at once
-  if (e.split_combine && mode == 2 && maxd <= 32) {
+  if (e.split_combine && mode >= 2 && maxd <= 32) {
     const size_t lds = ric_split_bytes(maxd);
     const int64_t per_cu = (int64_t)g_lds_per_cu / (int64_t)lds;
     if (lds <= (size_t)g_lqr_max_lds && ntasks <= per_cu * g_num_cu) {

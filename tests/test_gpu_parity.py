@@ -207,6 +207,36 @@ def test_combine_modes_same_bits():
                 assert torch.equal(got[f], ref[f]), (pool, split, f)
 
 
+def test_buckets_same_bits():
+    """A batch of more than 4096 stages launches its LDS-bound stage kernels
+    per stage bucket (stages in size order, LDS sized to each range) and its
+    wide scan levels per dim or size bucket; with buckets off every kernel
+    runs one launch over its whole range.  Both give the same bits, and agree
+    with the oracle on sampled instances."""
+    _need_gpu()
+    import paper_2407_05433_amd as ecl
+    from workloads import config_c3
+    probs = config_c3(B=24)
+    assert sum(p.N + 1 for p in probs) > 4096
+    plan = ecl.Plan.for_problems(probs)
+    data = ecl.pack(plan, probs)
+    ws = plan.workspace()
+    base = {k: v for k, v in ecl.get_tuning(plan).items() if k != "ms_per_solve"}
+    out = []
+    for buckets in (1, 0):
+        ecl.set_tuning(plan, **dict(base, level_buckets=buckets))
+        sol = ecl.solve(plan, data, ws)
+        torch.cuda.synchronize()
+        out.append({f: getattr(sol, f).clone() for f in ("x", "u", "lam", "mu", "status")})
+        print(f"[buckets] {buckets}: status {int((sol.status != 0).sum())} nonzero", flush=True)
+    for f in out[0]:
+        assert torch.equal(out[0][f], out[1][f]), f
+    res = {"status": out[0]["status"].cpu().tolist(), "x": ecl.unpack(plan, out[0]["x"], "q", probs),
+           "u": ecl.unpack(plan, out[0]["u"], "r", probs), "lam": ecl.unpack(plan, out[0]["lam"], "q", probs),
+           "mu": ecl.unpack(plan, out[0]["mu"], "g", probs)}
+    check_parity(probs, res, idx=[0, 7, 15, 23])
+
+
 def test_c1_full_size():
     _need_gpu()
     from workloads import config_c1
