@@ -259,8 +259,8 @@ using SideLaunch = std::function<eclqr_status(int step, int level)>;
 // order, each range with its own sizes) or, without buckets (or `whole`),
 // one range over every stage with the plan-wide sizes.  Buckets pay for the
 // kernels whose LDS tile bounds the workgroups a compute unit holds (base
-// relations, local systems of the theta route: c3 6.8 -> 5.9 and 5.2 -> 4.0
-// ms); the others run one launch (the elimination in global scratch is
+// relations, local systems of the theta route: 6.8 -> 5.9 and 5.2 -> 4.0 ms
+// on a batch of 512 instances of dims 6-24); the others run one launch (the elimination in global scratch is
 // bounded by registers, and five launches cost it five tails, 11.5 -> 12.1 ms).
 std::vector<Engine::StageBucket> stage_buckets(const Engine& E, bool whole = false) {
   if (g_buckets && !whole) return E.sbk;
