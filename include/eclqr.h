@@ -387,8 +387,8 @@ typedef struct {
   int32_t register_compose; /* relation compositions that fit (<= 64 stacked rows, <= 128 columns) keep the
                              * stacked system in registers instead of LDS */
   int32_t stage_lds;      /* stage eliminations and feedback gains keep their working arrays in LDS when these
-                             need at most 32 KiB per workgroup (1, default), only the feedback gains do (2), or
-                             neither (0: global scratch) */
+                             need at most 20 KiB (eliminations) or 32 KiB (gains) per workgroup (1, default), only
+                             the feedback gains do (2), or neither (0: global scratch) */
   int32_t overlap_dual;   /* with the minimum-norm multipliers, 1: the multiplier route's problem is factored
                            * (matrix data only) on a second stream while the primal pass runs, and its vector-only
                            * replay at the primal solution gives the multipliers; 0: one stream, full pass after

@@ -385,9 +385,11 @@ void launch_eliminate(const DevEngine& e, const Inputs& in, Tols t, int32_t* sta
   if (count <= 0) return;
   const size_t base = elim_lds_bytes(maxm, maxq);
   const size_t with = base + sizeof(double) * (size_t)elim_scratch(maxn, maxn, maxm, maxk);
-  // LDS only while a workgroup needs at most 32 KiB: above that the lost
-  // occupancy costs more than the faster accesses gain
-  if (e.elim_lds == 1 && with <= 32768 && with <= (size_t)g_elim_max_lds) {
+  // LDS only while a workgroup needs at most 20 KiB: above that the lost
+  // occupancy costs more than the faster accesses gain (measured: 26 KiB
+  // tiles, six workgroups per compute unit, 13.8 ms against 11.1 ms in global
+  // scratch at four waves per SIMD; tiles up to 13 KiB faster in LDS)
+  if (e.elim_lds == 1 && with <= 20480 && with <= (size_t)g_elim_max_lds) {
     const int grid = task_grid(e, count);
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_eliminate<true>), dim3(grid), dim3(kBlock), with, s, e, in, t, status, maxm,
                        maxq, first, count);

@@ -161,7 +161,7 @@ struct Plan {
   // pointers it was captured with
   // tuning (eclqr_plan_autotune / eclqr_plan_set_tuning)
   int32_t level_buckets = 1;  // relation levels launch in LDS-size buckets
-  int32_t stage_lds = 1;      // stage kernels' working arrays in LDS when <= 32 KiB
+  int32_t stage_lds = 1;      // stage kernels' working arrays in LDS when small (20 KiB eliminations, 32 KiB gains)
   int32_t pool_lds = 3;       // value-function combine LDS mode (0 global pool, 1 LDS pool, 2 all in LDS,
                               // 3 staged operands and compact pool in LDS)
   int32_t grid_divisor = 1;   // grid of the stage-parallel kernels = nblocks / divisor
