@@ -40,7 +40,7 @@ struct StageInfo {
 // pivot order, Q1 and R11 of the QR of Gamma^T, the Cholesky factors of
 // R-bar and of H_uu.
 struct Arena {
-  int64_t T, t, Y, Z, y, Ab, Bb, cb, Qb, Mb, Rb, qb, rb, K, kk, v, kap;
+  int64_t T, t, Y, Z, y, Ab, Bb, cb, Qb, Mb, Rb, qb, rb, K, kk, v;
   int64_t rsc, prm, Q1, R11, Lc, Hc, wl, Ym, ym, size;
 };
 
@@ -63,7 +63,6 @@ ECLQR_HD inline Arena arena_layout(int n, int np, int m, int k) {
   a.K = o; o += (int64_t)m * n;
   a.kk = o; o += m;
   a.v = o; o += m;
-  a.kap = o; o += 1;
   a.rsc = o; o += k + np;
   a.prm = o; o += m;
   a.Q1 = o; o += (int64_t)m * m;

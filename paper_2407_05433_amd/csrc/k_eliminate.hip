@@ -24,7 +24,9 @@ struct Bump {
 // inverse: a pivoted Householder QR of Gamma^T gives rank rho, the null-space
 // basis Z = Q[:, rho:], and Y = -Q1 R11^{-T} P^T Phi, y = -Q1 R11^{-T} P^T gamma.
 // Reduced data: eqs. (reduced-dynamics-data), (state-cost-data),
-// (reduced-cost-data), (stage-constant).  The value-function element of the
+// (reduced-cost-data); the stage constant of eq. (stage-constant) is not
+// formed, since no solution, multiplier or gradient depends on it.  The
+// value-function element of the
 // reduced stage (cross term removed with R-bar = L L^T):
 //   A_e = A-bar - W^T V, b_e = c-bar - W^T w, C_e = W^T W,
 //   J_e = Q-bar - V^T V, eta_e = -(q-bar - V^T w),
@@ -79,16 +81,6 @@ __global__ void __launch_bounds__(kBlock, kLS ? 1 : 4) k_eliminate(DevEngine e, 
       }
       wg_sync();
       wg_gemv(ric + rl.eta, T, nb, true, v, nb, n, -1.0, 0.0);
-      if (ECLQR_TID == 0) {
-        double kap = 0.0;
-        for (int i = 0; i < n; ++i) {
-          double qi = 0.0;
-          qi = lane_chain<false>(qi, Q + i * n, 1, tv, 1, n);
-          kap += tv[i] * (0.5 * qi + qv[i]);
-        }
-        base[ar.kap] = kap;
-      }
-      wg_sync();
       continue;
     }
     const int inst = st.inst;
@@ -304,21 +296,6 @@ __global__ void __launch_bounds__(kBlock, kLS ? 1 : 4) k_eliminate(DevEngine e, 
       qb[i] = a;
     }
     wg_gemv(rb, Z, mb, true, w, mb, m, 1.0, 0.0);
-    if (ECLQR_TID == 0) {
-      double kap = 0.0;
-      for (int i = 0; i < n; ++i) {
-        double a = 0.0;
-        a = lane_chain<false>(a, Q + i * n, 1, tv, 1, n);
-        kap += tv[i] * (0.5 * a + qv[i]);
-      }
-      for (int i = 0; i < m; ++i) {
-        double a = 0.0;
-        a = lane_chain<false>(a, R + i * m, 1, y, 1, m);
-        kap += y[i] * (0.5 * a + rz[i]);
-      }
-      base[ar.kap] = kap;
-    }
-    wg_sync();
 
     // ---- value-function element -----------------------------------------------
     const RicLayout rl = ric_layout(n, np);

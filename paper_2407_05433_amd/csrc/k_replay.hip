@@ -350,8 +350,6 @@ __global__ void __launch_bounds__(kBlock) k_eliminate_vec(DevEngine e, Inputs in
       qt[i] = a;
     }
     wg_sync();
-    double kap = 0.0;
-    for (int i = ECLQR_TID; i < n; i += ECLQR_NT) kap += tvs[i] * (0.5 * (qt[i] - qv[i]) + qv[i]);
     if (st.terminal) {
       const RicLayout rl = ric_layout(n, 0);
       double* qb = base + ar.qb;
@@ -361,8 +359,6 @@ __global__ void __launch_bounds__(kBlock) k_eliminate_vec(DevEngine e, Inputs in
         qb[i] = a;
         ric[rl.eta + i] = -a;
       }
-      kap = wave_sum(kap);
-      if (ECLQR_TID == 0) base[ar.kap] = kap;
       wg_sync();
       continue;
     }
@@ -440,12 +436,6 @@ __global__ void __launch_bounds__(kBlock) k_eliminate_vec(DevEngine e, Inputs in
       b = lane_chain<false>(b, R + i * m, 1, yv, 1, m);
       wv[i] = b;
     }
-    for (int i = ECLQR_TID; i < m; i += ECLQR_NT) {
-      double a = 0.0;
-      a = lane_chain<false>(a, R + i * m, 1, yv, 1, m);
-      kap += yv[i] * (0.5 * a + rz[i]);
-    }
-    kap = wave_sum(kap);
     // (Q t + q) + M y, reused for q-bar
     if (Mm) {
       wg_sync();
@@ -477,7 +467,6 @@ __global__ void __launch_bounds__(kBlock) k_eliminate_vec(DevEngine e, Inputs in
       rbl = lane_chain<false>(rbl, Z + ECLQR_TID, mb, wv, 1, m);
       rb[ECLQR_TID] = rbl;
     }
-    if (ECLQR_TID == 0) base[ar.kap] = kap;
     // element: s = R-bar^{-1} r-bar, b_e = c-bar - B-bar s, eta_e = -(q-bar - M-bar s)
     double sl = lane_trsv_lower(base + ar.Lc, mb, rbl, mb);
     sl = lane_trsv_lower_t(base + ar.Lc, mb, sl, mb);
