@@ -442,17 +442,14 @@ __device__ __forceinline__ void wg_gemm(double* C, int ldc, const double* A, int
   bsync<kL>();
 }
 
-// y(M) = alpha * op(A) x + beta * y.   op(A) is MxK.
+// y(M) = alpha * op(A) x + beta * y.   op(A) is MxK.  Each entry is one FMA
+// chain in ascending k (lane_chain: eight k steps' loads in flight).
 template <bool kL = false>
 __device__ __forceinline__ void wg_gemv(double* y, const double* A, int lda, bool tA, const double* x, int M, int K,
                                double alpha, double beta) {
   for (int i = ECLQR_TID; i < M; i += ECLQR_NT) {
-    double acc = 0.0;
-    if (!tA) {
-      for (int k = 0; k < K; ++k) acc = fma(A[i * lda + k], x[k], acc);
-    } else {
-      for (int k = 0; k < K; ++k) acc = fma(A[k * lda + i], x[k], acc);
-    }
+    const double acc = tA ? lane_chain<false>(0.0, A + i, lda, x, 1, K)
+                          : lane_chain<false>(0.0, A + (int64_t)i * lda, 1, x, 1, K);
     const double prev = (beta == 0.0) ? 0.0 : beta * y[i];
     y[i] = alpha * acc + prev;
   }

@@ -109,7 +109,10 @@ __global__ void __launch_bounds__(kBlock, kLS ? 1 : 4) k_eliminate(DevEngine e, 
     double* gs = bump.take(q);
     double* Phi = bump.take((int64_t)q * n);
     double* gam = bump.take(q);
-    double* Qg = bump.take((int64_t)m * m);
+    // Q of the QR of Gamma^T is formed in LDS, in the Cholesky factor's
+    // place (that factor is first needed by the value-function element): its
+    // reflector updates then wait on LDS instead of global memory
+    double* Qg = Lc;
     double* X = bump.take((int64_t)m * (n + 1));
     double* rsc = bump.take(q);
 
@@ -195,7 +198,7 @@ __global__ void __launch_bounds__(kBlock, kLS ? 1 : 4) k_eliminate(DevEngine e, 
         const int j = idx / (nb + 1), l = idx % (nb + 1);
         double a = (l < nb) ? Phi[j * nb + l] : gam[j];
         if (l < nb) mphi = fmax(mphi, fabs(a)); else mg = fmax(mg, fabs(a));
-        for (int c2 = 0; c2 < m; ++c2) a = fma(Gs[j * m + c2], (l < nb) ? Y[c2 * nb + l] : y[c2], a);
+        a = (l < nb) ? lane_chain<false>(a, Gs + j * m, 1, Y + l, nb, m) : lane_chain<false>(a, Gs + j * m, 1, y, 1, m);
         if (l < nb) mres = fmax(mres, fabs(a)); else mres2 = fmax(mres2, fabs(a));
       }
       mres = wg_reduce_max(mres, red);
@@ -300,9 +303,12 @@ __global__ void __launch_bounds__(kBlock, kLS ? 1 : 4) k_eliminate(DevEngine e, 
     // ---- value-function element -----------------------------------------------
     const RicLayout rl = ric_layout(n, np);
     bump.p = scr0;  // after the barrier above
-    double* Wt = bump.take((int64_t)m * np);
-    double* V = bump.take((int64_t)m * n);
-    double* w2 = bump.take(m);
+    // [W | V | w] side by side (ld lv), so that one triangular solve, one
+    // chain of dependent rows, serves all three
+    const int lv = nb1 + nb + 1;
+    double* Wt = bump.take((int64_t)m * lv);
+    double* V = Wt + nb1;
+    double* w2 = Wt + nb1 + nb;
     wg_copy(Lc, mb, Rb, mb, mb, mb);
     if (wg_cholesky(Lc, mb, mb, sh + 8)) {
       if (ECLQR_TID == 0) flag_at(e, status, inst, ECLQR_NOT_CONVEX, st.i);
@@ -310,33 +316,31 @@ __global__ void __launch_bounds__(kBlock, kLS ? 1 : 4) k_eliminate(DevEngine e, 
       continue;
     }
     wg_copy(base + ar.Lc, mb, Lc, mb, mb, mb);
-    wg_copy_t(Wt, nb1, Bb, mb, nb1, mb);  // Wt = Bb^T  (mb x nb1)
-    wg_copy_t(V, nb, Mb, mb, nb, mb);     // V = Mb^T  (mb x nb)
-    for (int i = ECLQR_TID; i < mb; i += ECLQR_NT) w2[i] = rb[i];
+    wg_copy_t(Wt, lv, Bb, mb, nb1, mb);  // Wt = Bb^T  (mb x nb1)
+    wg_copy_t(V, lv, Mb, mb, nb, mb);    // V = Mb^T  (mb x nb)
+    for (int i = ECLQR_TID; i < mb; i += ECLQR_NT) w2[(int64_t)i * lv] = rb[i];
     wg_sync();
-    wg_trsm_lower(Lc, mb, Wt, nb1, mb, nb1);
-    wg_trsm_lower(Lc, mb, V, nb, mb, nb);
-    wg_trsm_lower(Lc, mb, w2, 1, mb, 1);
+    wg_trsm_lower(Lc, mb, Wt, lv, mb, lv);
     double* Ae = ric + rl.A;
     double* be = ric + rl.b;
     double* Ce = ric + rl.C;
     double* ee = ric + rl.eta;
     double* Je = ric + rl.J;
     wg_copy(Ae, nb, Ab, nb, nb1, nb);
-    wg_gemm(Ae, nb, Wt, nb1, true, V, nb, false, nb1, nb, mb, -1.0, 1.0);
+    wg_gemm(Ae, nb, Wt, lv, true, V, lv, false, nb1, nb, mb, -1.0, 1.0);
     for (int i = ECLQR_TID; i < nb1; i += ECLQR_NT) {
       double a = cb[i];
-      a = lane_chain<true>(a, Wt + i, nb1, w2, 1, mb);
+      a = lane_chain<true>(a, Wt + i, lv, w2, lv, mb);
       be[i] = a;
     }
-    wg_gemm(Ce, nb1, Wt, nb1, true, Wt, nb1, false, nb1, nb1, mb, 1.0, 0.0);
+    wg_gemm(Ce, nb1, Wt, lv, true, Wt, lv, false, nb1, nb1, mb, 1.0, 0.0);
     wg_symmetrize(Ce, nb1, nb1);
     wg_copy(Je, nb, Qb, nb, nb, nb);
-    wg_gemm(Je, nb, V, nb, true, V, nb, false, nb, nb, mb, -1.0, 1.0);
+    wg_gemm(Je, nb, V, lv, true, V, lv, false, nb, nb, mb, -1.0, 1.0);
     wg_symmetrize(Je, nb, nb);
     for (int i = ECLQR_TID; i < nb; i += ECLQR_NT) {
       double a = qb[i];
-      a = lane_chain<true>(a, V + i, nb, w2, 1, mb);
+      a = lane_chain<true>(a, V + i, lv, w2, lv, mb);
       ee[i] = -a;
     }
     wg_sync();

@@ -12,14 +12,14 @@ ECLQR_HD inline int64_t rup4(int64_t x) { return (x + 3) & ~int64_t(3); }
 // kernel reuses one region phase by phase, so the size is the largest phase.
 ECLQR_HD inline int64_t elim_scratch(int n, int np, int m, int k) {
   const int64_t q = k + np;
-  // QR of Gamma^T and the maps Y, y, Z: Gs Ps gs Phi gam Qg X rsc
-  const int64_t p1 = rup4(q * m) + rup4(q * n) + rup4(q) + rup4(q * n) + rup4(q) + rup4((int64_t)m * m) +
-                     rup4((int64_t)m * (n + 1)) + rup4(q);
+  // QR of Gamma^T and the maps Y, y, Z: Gs Ps gs Phi gam X rsc (Q in LDS)
+  const int64_t p1 = rup4(q * m) + rup4(q * n) + rup4(q) + rup4(q * n) + rup4(q) + rup4((int64_t)m * (n + 1)) +
+                     rup4(q);
   const int64_t p2 = rup4((int64_t)np * n) + rup4((int64_t)np * m) + rup4(np);  // AT BZ cv
   // QT Mz RY RZ MzY w qz rz (the terminal stage's QT and v fit in it)
   const int64_t p3 = rup4((int64_t)n * n) + rup4((int64_t)n * m) + rup4((int64_t)m * n) + rup4((int64_t)m * m) +
                      rup4((int64_t)n * n) + rup4(m) + rup4(n) + rup4(m);
-  const int64_t p4 = rup4((int64_t)m * np) + rup4((int64_t)m * n) + rup4(m);  // Wt V w2
+  const int64_t p4 = rup4((int64_t)m * (np + n + 1));  // [Wt V w2]
   int64_t s = p1 > p2 ? p1 : p2;
   s = s > p3 ? s : p3;
   s = s > p4 ? s : p4;
