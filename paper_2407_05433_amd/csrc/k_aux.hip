@@ -280,13 +280,40 @@ __global__ void __launch_bounds__(kBlock) k_refine_decide(DevEngine p, const int
 // mag += sum_l |a[l sa] b[l]|, an += sum_l |a[l sa]|: the terms l = c, c + 8,
 // ... (c the lane's place in its group), so the group's loads of one step
 // are 8 consecutive elements of a row-major row, or of 8 rows at one column.
-__device__ __forceinline__ void acc_part(const double* a, int sa, const double* b, int n, int c, double& v, double& mag,
-                                         double& an) {
-  for (int l = c; l < n; l += 8) {
+// part_load fetches a share's first four terms (every row of up to 32 terms)
+// so that the loads of all of a row's families are in flight together;
+// part_acc adds them, then any further terms, in ascending l.  Masked terms
+// are zeros, which leave the sums' bits unchanged.
+struct Part4 {
+  double a[4], b[4];
+};
+
+__device__ __forceinline__ Part4 part_load(const double* a, int sa, const double* b, int n, int c) {
+  Part4 P;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int l = c + 8 * t;
+    const bool ok = l < n;
+    P.a[t] = ok ? a[l * sa] : 0.0;
+    P.b[t] = ok ? b[l] : 0.0;
+  }
+  return P;
+}
+
+__device__ __forceinline__ void part_acc(const Part4& P, const double* a, int sa, const double* b, int n, int c,
+                                         double& v, double& mag, double& an) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const double tt = P.a[t] * P.b[t];
+    v += tt;
+    mag += fabs(tt);
+    an += fabs(P.a[t]);
+  }
+  for (int l = c + 32; l < n; l += 8) {
     const double av = a[l * sa];
-    const double t = av * b[l];
-    v += t;
-    mag += fabs(t);
+    const double tt = av * b[l];
+    v += tt;
+    mag += fabs(tt);
     an += fabs(av);
   }
 }
@@ -378,11 +405,15 @@ __global__ void __launch_bounds__(kBlock) k_backward_error(DevEngine p, Inputs i
       const int i = i0 + g;
       double v = 0.0, a = 0.0, an = 0.0;
       if (i < n) {
-        acc_part(Q + i * n, 1, xs, n, c, v, a, an);
-        acc_part(E + i, n, ms, k, c, v, a, an);
+        const Part4 p0 = part_load(Q + i * n, 1, xs, n, c);
+        const Part4 p1 = part_load(E + i, n, ms, k, c);
+        const Part4 p2 = (!term && M) ? part_load(M + i * m, 1, us, m, c) : Part4{};
+        const Part4 p3 = !term ? part_load(A + i, n, l1, np, c) : Part4{};
+        part_acc(p0, Q + i * n, 1, xs, n, c, v, a, an);
+        part_acc(p1, E + i, n, ms, k, c, v, a, an);
         if (!term) {
-          if (M) acc_part(M + i * m, 1, us, m, c, v, a, an);
-          acc_part(A + i, n, l1, np, c, v, a, an);
+          if (M) part_acc(p2, M + i * m, 1, us, m, c, v, a, an);
+          part_acc(p3, A + i, n, l1, np, c, v, a, an);
         }
       }
       v = group8_sum(v);
@@ -396,8 +427,10 @@ __global__ void __launch_bounds__(kBlock) k_backward_error(DevEngine p, Inputs i
       const int i = i0 + g;
       double v = 0.0, a = 0.0, an = 0.0;
       if (i < k) {
-        acc_part(E + i * n, 1, xs, n, c, v, a, an);
-        if (!term) acc_part(F + i * m, 1, us, m, c, v, a, an);
+        const Part4 p0 = part_load(E + i * n, 1, xs, n, c);
+        const Part4 p1 = !term ? part_load(F + i * m, 1, us, m, c) : Part4{};
+        part_acc(p0, E + i * n, 1, xs, n, c, v, a, an);
+        if (!term) part_acc(p1, F + i * m, 1, us, m, c, v, a, an);
       }
       v = group8_sum(v);
       a = group8_sum(a);
@@ -409,10 +442,14 @@ __global__ void __launch_bounds__(kBlock) k_backward_error(DevEngine p, Inputs i
         const int i = i0 + g;
         double v = 0.0, a = 0.0, an = 0.0;
         if (i < m) {
-          acc_part(R + i * m, 1, us, m, c, v, a, an);
-          if (M) acc_part(M + i, m, xs, n, c, v, a, an);
-          acc_part(B + i, m, l1, np, c, v, a, an);
-          acc_part(F + i, m, ms, k, c, v, a, an);
+          const Part4 p0 = part_load(R + i * m, 1, us, m, c);
+          const Part4 p1 = M ? part_load(M + i, m, xs, n, c) : Part4{};
+          const Part4 p2 = part_load(B + i, m, l1, np, c);
+          const Part4 p3 = part_load(F + i, m, ms, k, c);
+          part_acc(p0, R + i * m, 1, us, m, c, v, a, an);
+          if (M) part_acc(p1, M + i, m, xs, n, c, v, a, an);
+          part_acc(p2, B + i, m, l1, np, c, v, a, an);
+          part_acc(p3, F + i, m, ms, k, c, v, a, an);
         }
         v = group8_sum(v);
         a = group8_sum(a);
@@ -423,8 +460,10 @@ __global__ void __launch_bounds__(kBlock) k_backward_error(DevEngine p, Inputs i
         const int i = i0 + g;
         double v = 0.0, a = 0.0, an = 0.0;
         if (i < np) {
-          acc_part(A + i * n, 1, xs, n, c, v, a, an);
-          acc_part(B + i * m, 1, us, m, c, v, a, an);
+          const Part4 p0 = part_load(A + i * n, 1, xs, n, c);
+          const Part4 p1 = part_load(B + i * m, 1, us, m, c);
+          part_acc(p0, A + i * n, 1, xs, n, c, v, a, an);
+          part_acc(p1, B + i * m, 1, us, m, c, v, a, an);
         }
         v = group8_sum(v);
         a = group8_sum(a);
