@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define ECLQR_ABI_VERSION 2
+#define ECLQR_ABI_VERSION 3
 
 /* synchronous return codes */
 typedef enum {
@@ -413,6 +413,13 @@ typedef struct {
                            * before theirs.  0 (default): one launch per level.  Experimental: on the device the
                            * persistent form did not complete its waits (see the design notes); the autotuner does
                            * not select it */
+  int32_t refine_gate;    /* 1: eclqr_solve reads back, after the first pass, how many instances still need a
+                           * refinement step (their backward error above accept_tol) and enqueues the refinement
+                           * steps only if some does; the calling thread then waits for that first pass.  A
+                           * solve enqueued on a stream under capture, eclqr_solve_noalloc and the interior-point
+                           * driver never wait (they run as with 0).  0 (default): every step is enqueued and its
+                           * launches return at once for instances that are done; eclqr_solve never waits.  Same
+                           * results either way */
 } eclqr_tuning;
 
 /* Time the caller's problem under alternative launch configurations

@@ -47,7 +47,7 @@ class Tuning(C.Structure):
     _fields_ = [("use_graph", C.c_int32), ("level_buckets", C.c_int32), ("pool_in_lds", C.c_int32),
                 ("grid_divisor", C.c_int32), ("ms_per_solve", C.c_double), ("register_compose", C.c_int32),
                 ("stage_lds", C.c_int32), ("overlap_dual", C.c_int32), ("multiplier_route", C.c_int32),
-                ("split_combine", C.c_int32), ("fused_scans", C.c_int32)]
+                ("split_combine", C.c_int32), ("fused_scans", C.c_int32), ("refine_gate", C.c_int32)]
 
 
 class ProblemPtrs(C.Structure):

@@ -20,8 +20,10 @@ using namespace eclqr;
 namespace eclqr {
 
 void release_graph(Plan& p) {
-  if (p.graph_exec) (void)hipGraphExecDestroy(reinterpret_cast<hipGraphExec_t>(p.graph_exec));
-  p.graph_exec = nullptr;
+  for (void** g : {&p.graph_exec, &p.graph_ref, &p.graph_tail}) {
+    if (*g) (void)hipGraphExecDestroy(reinterpret_cast<hipGraphExec_t>(*g));
+    *g = nullptr;
+  }
   p.graph_key.clear();
 }
 
@@ -40,6 +42,7 @@ Plan::~Plan() {
   if (ev_fork) (void)hipEventDestroy(reinterpret_cast<hipEvent_t>(ev_fork));
   if (ev_join) (void)hipEventDestroy(reinterpret_cast<hipEvent_t>(ev_join));
   for (void* e : event_pool) (void)hipEventDestroy(reinterpret_cast<hipEvent_t>(e));
+  if (gate_host) (void)hipHostFree(gate_host);
 }
 
 }  // namespace eclqr
@@ -717,10 +720,21 @@ constexpr int32_t kDualStructural = ECLQR_CAPACITY | ECLQR_NOT_CONVEX | ECLQR_IN
 //      updated point;
 //   4. the backward error of the returned point is recomputed; a refined
 //      instance whose error exceeds dual_cons_tol reports a multiplier failure.
+// Parts of a solve that the host may enqueue separately (refine_gate): the
+// first pass up to the accept test, the refinement steps, the rest.
+constexpr int kPartHead = 1, kPartRefine = 2, kPartTail = 4, kPartAll = 7;
+
 eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, double* u, double* lam, double* mu,
-                       int32_t* status, bool want_mult, bool replay, hipStream_t s, hipEvent_t dual_join = nullptr) {
+                       int32_t* status, bool want_mult, bool replay, hipStream_t s, hipEvent_t dual_join = nullptr,
+                       int part = kPartAll) {
   const Tols tp{p.opt.rank_tol, p.opt.cons_tol, 1};
   const int32_t B = p.primal.B;
+  const bool fast = p.opt.multipliers == 2;
+  const bool theta = theta_route(p);
+  const int nref = p.opt.refine;
+  eclqr_status st = ECLQR_SUCCESS;
+  // a split solve has multipliers and refinement steps (the caller checks)
+  if (part & kPartHead) {
   {
     Timed tm(ECLQR_K_REFINE_IO, s);
     launch_fill_i32(v.gate, kGateActive, B, s);
@@ -729,8 +743,6 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
     launch_fill_u64(v.omega, 0ull, B, s);
     launch_fill_i32(at<int32_t>(v.ws, p.o_abort), 0, 1, s);
   }
-  const bool fast = p.opt.multipliers == 2;
-  const bool theta = theta_route(p);
   // theta route: its factorizations run on the second stream once the
   // primal pass has the domains, beside the rest of that pass
   hipEvent_t theta_join = nullptr;
@@ -745,8 +757,8 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
       }
       return theta_prefactor_step(p, v, in, s2, step, level);
     };
-  eclqr_status st = replay ? run_engine_vec(p.primal, v.P, in, x, u, s, v.scP)
-                           : run_engine(p.primal, v.P, in, x, u, status, tp, s, side);
+  st = replay ? run_engine_vec(p.primal, v.P, in, x, u, s, v.scP)
+              : run_engine(p.primal, v.P, in, x, u, status, tp, s, side);
   if (theta_join) {  // also after a failed pass: the second stream is joined before anything returns
     HIP_OK(hipEventRecord(theta_join, reinterpret_cast<hipStream_t>(p.aux_stream)));
     HIP_OK(hipStreamWaitEvent(s, theta_join, 0));
@@ -783,7 +795,6 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
   else
     st = multipliers(p, v, in, x, u, lam, mu, s, replay || dual_join != nullptr);
   if (st != ECLQR_SUCCESS) return st;
-  const int nref = p.opt.refine;
   if (nref == 0) {
     Timed tm(ECLQR_K_REFINE_IO, s);
     launch_merge_status(status, v.dstatus, ECLQR_DUAL_FAILED, B, nullptr, 0, s);
@@ -796,7 +807,11 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
     launch_backward_error(v.P, in, x, u, lam, mu, at<unsigned long long>(v.ws, p.o_wmax), v.omega, s);
     launch_accept(v.omega, v.dstatus, p.opt.accept_tol, v.gate, B, s);
     if (!replay) launch_dp_hold(dpflag, v.gate, B, s);
+    // the count of instances still refining, for the host's decision
+    if (part != kPartAll) launch_gate_advance(v.gate, v.live, B, s);
   }
+  }  // kPartHead
+  if (part & kPartRefine) {
   Inputs cin = in;
   cin.f[IN_q] = v.cp.q;
   cin.f[IN_r] = v.cp.r;
@@ -828,7 +843,8 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
       if (st != ECLQR_SUCCESS) return st;
     }
   }
-  {
+  }  // kPartRefine
+  if (part & kPartTail) {
     Timed tm(ECLQR_K_REFINE_IO, s);
     launch_fill_i32(v.gate, kGateActive, B, s);  // later launches on this workspace run every instance
     launch_fill_i32(v.live, 1, 1, s);
@@ -914,12 +930,15 @@ eclqr_status cx_multipliers(Plan& p, const Views& v, const Inputs& in, const dou
   return ECLQR_SUCCESS;
 }
 
-// The whole launch sequence of one solve.
-eclqr_status solve_sequence(Plan& p, const Views& v, const Inputs& in, eclqr_solution* sol, bool want, hipStream_t s) {
+// The launch sequence of one solve (part: all of it, or one of the parts a
+// gated solve enqueues separately).
+eclqr_status solve_sequence(Plan& p, const Views& v, const Inputs& in, eclqr_solution* sol, bool want, hipStream_t s,
+                            int part = kPartAll) {
   const Engine& E = p.primal;
+  hipEvent_t join = nullptr;
+  if (part & kPartHead) {
   launch_fill_i32(sol->status, 0, E.B, s);
   launch_fill_i32(v.P.info, -1, E.B, s);
-  hipEvent_t join = nullptr;
   if (want && minnorm_route(p) && !theta_route(p)) {
     if (p.overlap_dual && p.aux_stream) {
       hipStream_t s2 = reinterpret_cast<hipStream_t>(p.aux_stream);
@@ -936,25 +955,67 @@ eclqr_status solve_sequence(Plan& p, const Views& v, const Inputs& in, eclqr_sol
       launch_dual_matrices(v.P, in, v.D, v.dp, s);
     }
   }
-  eclqr_status st = solve_all(p, v, in, sol->x, sol->u, sol->lam, sol->mu, sol->status, want, false, s, join);
+  }  // kPartHead
+  eclqr_status st = solve_all(p, v, in, sol->x, sol->u, sol->lam, sol->mu, sol->status, want, false, s, join, part);
   if (st != ECLQR_SUCCESS) return st;
-  if (want && p.opt.multipliers == 3) {
-    st = cx_multipliers(p, v, in, sol->x, sol->u, sol->lam, sol->mu, sol->status, s);
-    if (st != ECLQR_SUCCESS) return st;
+  if (part & kPartTail) {
+    if (want && p.opt.multipliers == 3) {
+      st = cx_multipliers(p, v, in, sol->x, sol->u, sol->lam, sol->mu, sol->status, s);
+      if (st != ECLQR_SUCCESS) return st;
+    }
+    launch_finalize(v.P, sol->status, sol->x, sol->u, want ? sol->lam : nullptr, want ? sol->mu : nullptr, s);
   }
-  launch_finalize(v.P, sol->status, sol->x, sol->u, want ? sol->lam : nullptr, want ? sol->mu : nullptr, s);
   HIP_OK(hipGetLastError());
   return ECLQR_SUCCESS;
 }
 
+// refine_gate applies: multipliers and refinement steps requested, launches
+// that may allocate, and a stream not under capture (the host waits on it).
+bool gate_applies(const Plan& p, bool want, bool noalloc, hipStream_t s) {
+  if (!p.refine_gate || !want || p.opt.refine == 0 || noalloc) return false;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return cs == hipStreamCaptureStatusNone;
+}
+
+// Waits for the work enqueued on s and returns the count of instances still
+// refining (written by the first pass's gate advance).
+eclqr_status read_live(Plan& p, const Views& v, hipStream_t s, int32_t* live) {
+  if (!p.gate_host) {
+    void* h = nullptr;
+    HIP_OK(hipHostMalloc(&h, sizeof(int32_t), hipHostMallocDefault));
+    p.gate_host = static_cast<int32_t*>(h);
+  }
+  HIP_OK(hipMemcpyAsync(p.gate_host, v.live, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  *live = *p.gate_host;
+  return ECLQR_SUCCESS;
+}
+
+// Eager gated solve: first pass, refinement steps only when an instance
+// still needs one, then the rest.
+eclqr_status solve_gated(Plan& p, const Views& v, const Inputs& in, eclqr_solution* sol, hipStream_t s) {
+  eclqr_status st = solve_sequence(p, v, in, sol, true, s, kPartHead);
+  if (st != ECLQR_SUCCESS) return st;
+  int32_t live = 1;
+  if ((st = read_live(p, v, s, &live)) != ECLQR_SUCCESS) return st;
+  if (live > 0 && (st = solve_sequence(p, v, in, sol, true, s, kPartRefine)) != ECLQR_SUCCESS) return st;
+  return solve_sequence(p, v, in, sol, true, s, kPartTail);
+}
+
 // Graph path of eclqr_solve: the launch sequence is captured once per set of
-// pointers and replayed; every memory clear in it is a fill kernel.
+// pointers and replayed; every memory clear in it is a fill kernel.  Gated:
+// three graphs (first pass, refinement steps, the rest), the second
+// launched only when the count read back after the first is positive.
 eclqr_status solve_graph(Plan& p, const Views& v, const Inputs& in, const eclqr_problem* prob, eclqr_solution* sol,
-                         void* ws, bool want, hipStream_t s) {
+                         void* ws, bool want, bool gated, hipStream_t s) {
   std::vector<const void*> key = {ws, prob->Q, prob->q, prob->R, prob->r, prob->M, prob->A, prob->B, prob->c,
                                   prob->E, prob->F, prob->g, prob->x0, sol->x, sol->u, sol->lam, sol->mu,
                                   sol->status, sol->info};
-  if (!p.graph_exec || p.graph_key != key) {
+  if (!p.graph_exec || p.graph_key != key || gated != (p.graph_tail != nullptr)) {
     release_graph(p);
     // captured on a plan-owned stream (the caller's may be the null stream,
     // which cannot be captured); nothing runs during the capture
@@ -964,23 +1025,44 @@ eclqr_status solve_graph(Plan& p, const Views& v, const Inputs& in, const eclqr_
       p.capture_stream = reinterpret_cast<void*>(cs);
     }
     hipStream_t cs = reinterpret_cast<hipStream_t>(p.capture_stream);
-    HIP_OK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    const eclqr_status cst = solve_sequence(p, v, in, sol, want, cs);
-    hipGraph_t g = nullptr;
-    const hipError_t ce = hipStreamEndCapture(cs, &g);
+    auto capture = [&](int part, void** out) -> eclqr_status {
+      HIP_OK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      const eclqr_status cst = solve_sequence(p, v, in, sol, want, cs, part);
+      hipGraph_t g = nullptr;
+      const hipError_t ce = hipStreamEndCapture(cs, &g);
+      if (cst != ECLQR_SUCCESS) {
+        if (g) (void)hipGraphDestroy(g);
+        return cst;
+      }
+      if (ce != hipSuccess) return fail(ECLQR_HIP_ERROR, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
+      hipGraphExec_t ex = nullptr;
+      const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ie != hipSuccess) return fail(ECLQR_HIP_ERROR, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+      *out = reinterpret_cast<void*>(ex);
+      return ECLQR_SUCCESS;
+    };
+    eclqr_status cst = ECLQR_SUCCESS;
+    if (gated) {
+      if ((cst = capture(kPartHead, &p.graph_exec)) == ECLQR_SUCCESS &&
+          (cst = capture(kPartRefine, &p.graph_ref)) == ECLQR_SUCCESS)
+        cst = capture(kPartTail, &p.graph_tail);
+    } else {
+      cst = capture(kPartAll, &p.graph_exec);
+    }
     if (cst != ECLQR_SUCCESS) {
-      if (g) (void)hipGraphDestroy(g);
+      release_graph(p);
       return cst;
     }
-    if (ce != hipSuccess) return fail(ECLQR_HIP_ERROR, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
-    hipGraphExec_t ex = nullptr;
-    const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (ie != hipSuccess) return fail(ECLQR_HIP_ERROR, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
-    p.graph_exec = reinterpret_cast<void*>(ex);
     p.graph_key = key;
   }
   HIP_OK(hipGraphLaunch(reinterpret_cast<hipGraphExec_t>(p.graph_exec), s));
+  if (!gated) return ECLQR_SUCCESS;
+  int32_t live = 1;
+  const eclqr_status st = read_live(p, v, s, &live);
+  if (st != ECLQR_SUCCESS) return st;
+  if (live > 0) HIP_OK(hipGraphLaunch(reinterpret_cast<hipGraphExec_t>(p.graph_ref), s));
+  HIP_OK(hipGraphLaunch(reinterpret_cast<hipGraphExec_t>(p.graph_tail), s));
   return ECLQR_SUCCESS;
 }
 
@@ -1048,12 +1130,13 @@ eclqr_status solve_impl(eclqr_plan* plan, const eclqr_problem* prob, eclqr_solut
   Views v = views(p, ws);
   v.P.info = sol->info ? sol->info : at<int32_t>(ws, p.o_info);
   Inputs in = inputs_of(prob);
+  const bool gated = gate_applies(p, want, noalloc, s);
   if (noalloc || !p.opt.use_graph || p.profiling) {
     g_noalloc = noalloc;
-    st = solve_sequence(p, v, in, sol, want, s);
+    st = gated ? solve_gated(p, v, in, sol, s) : solve_sequence(p, v, in, sol, want, s);
     g_noalloc = false;
   } else {
-    st = solve_graph(p, v, in, prob, sol, ws, want, s);
+    st = solve_graph(p, v, in, prob, sol, ws, want, gated, s);
   }
   record_solve(p, ws, route, prob, sol, st == ECLQR_SUCCESS);
   return st;
@@ -1557,6 +1640,7 @@ eclqr_status eclqr_plan_get_tuning(const eclqr_plan* plan, eclqr_tuning* out) {
   out->multiplier_route = p.theta_ok ? p.mult_route : 0;
   out->split_combine = p.split_combine;
   out->fused_scans = p.fused_scans;
+  out->refine_gate = p.refine_gate;
   out->ms_per_solve = p.tuned_ms;
   return ECLQR_SUCCESS;
 }
@@ -1577,6 +1661,7 @@ eclqr_status eclqr_plan_set_tuning(eclqr_plan* plan, const eclqr_tuning* t) {
   p.mult_route = (p.theta_ok && (t->multiplier_route != 0 || !p.has_dual)) ? 1 : 0;
   p.split_combine = t->split_combine != 0;
   p.fused_scans = t->fused_scans != 0;
+  p.refine_gate = t->refine_gate != 0;
   release_graphs(p);
   return ECLQR_SUCCESS;
 }
@@ -1621,7 +1706,7 @@ eclqr_status eclqr_plan_autotune(eclqr_plan* plan, const eclqr_problem* prob, ec
                   {&p.pool_lds, 2},
                   {&p.grid_divisor, p.grid_divisor == 1 ? 4 : 1}, {&graph, graph ? 0 : 1},
                   {&p.overlap_dual, p.overlap_dual ? 0 : 1}, {&p.mult_route, p.mult_route ? 0 : 1},
-                  {&p.split_combine, p.split_combine ? 0 : 1}};
+                  {&p.split_combine, p.split_combine ? 0 : 1}, {&p.refine_gate, p.refine_gate ? 0 : 1}};
   for (Knob& k : knobs) {
     if (st != ECLQR_SUCCESS) break;
     if (k.v == &p.mult_route && !(p.theta_ok && p.has_dual)) continue;

@@ -170,8 +170,14 @@ struct Plan {
                               // (plan default: 0 with the theta route, 1 without)
   int32_t split_combine = 1;  // two wavefronts per value-function combine on levels that fit the device
   int32_t fused_scans = 0;    // vector-only replays run each scan as one persistent launch (else one per level)
+  int32_t refine_gate = 0;    // the host reads the count of instances still refining and skips unneeded steps
   double tuned_ms = 0.0;
   void* graph_exec = nullptr;
+  // with refine_gate: graph_exec holds the first pass up to the accept test,
+  // graph_ref the refinement steps, graph_tail the rest of the solve
+  void* graph_ref = nullptr;
+  void* graph_tail = nullptr;
+  int32_t* gate_host = nullptr;    // pinned host word the count of instances still refining is read into
   void* capture_stream = nullptr;  // plan-owned stream the sequence is captured on
   void* aux_stream = nullptr;      // plan-owned stream of the overlapped reversed-time factorization
   void* ev_fork = nullptr;         // fork / join events between the two streams

@@ -465,6 +465,7 @@ def _tuning_dict(t: _lib.Tuning) -> Dict[str, float]:
             "grid_divisor": int(t.grid_divisor), "register_compose": int(t.register_compose),
             "stage_lds": int(t.stage_lds), "overlap_dual": int(t.overlap_dual), "multiplier_route": int(t.multiplier_route),
             "split_combine": int(t.split_combine), "fused_scans": int(t.fused_scans),
+            "refine_gate": int(t.refine_gate),
             "ms_per_solve": float(t.ms_per_solve)}
 
 

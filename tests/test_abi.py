@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
     assert len(names) >= 12
     for n in names:
         assert hasattr(L, n), n
-    assert L.eclqr_abi_version() == 2
+    assert L.eclqr_abi_version() == 3
 
 
 def test_status_strings_and_defaults():
@@ -240,8 +240,8 @@ def test_tuning_defaults_and_ranges():
     multi-valued field: pool_in_lds 0..3, stage_lds 0..2 (2: gains only)."""
     plan = ecl.Plan([([6] * 5, [3] * 4, [1] * 5)])
     t = ecl.get_tuning(plan)
-    assert t["pool_in_lds"] == 3 and t["stage_lds"] == 1 and t["grid_divisor"] == 1
-    for k, v in (("pool_in_lds", 0), ("pool_in_lds", 2), ("stage_lds", 2), ("stage_lds", 0)):
+    assert t["pool_in_lds"] == 3 and t["stage_lds"] == 1 and t["grid_divisor"] == 1 and t["refine_gate"] == 0
+    for k, v in (("pool_in_lds", 0), ("pool_in_lds", 2), ("stage_lds", 2), ("stage_lds", 0), ("refine_gate", 1)):
         ecl.set_tuning(plan, **{k: v})
         assert ecl.get_tuning(plan)[k] == v
     for k, v in (("pool_in_lds", 4), ("pool_in_lds", -1), ("stage_lds", 3), ("grid_divisor", 0)):

@@ -407,6 +407,45 @@ def test_graph_replay_matches_eager():
             assert torch.equal(getattr(sol2, f), getattr(ref2, f)), ("new buffers", f)
 
 
+def test_refine_gate_same_results():
+    """refine_gate: the host reads back how many instances still refine after
+    the first pass and enqueues the refinement steps only when some does.
+    Eager and graph forms (graph replayed with eager work in between) give
+    the ungated solve's bits, refinement counts and backward errors, on a
+    single instance that takes no step and on batches where some instances
+    refine (the steps are then launched)."""
+    _need_gpu()
+    import paper_2407_05433_amd as ecl
+    from workloads import config_c1, config_c2, config_c3
+    cases = (("c1 N=200", config_c1(N=200)), ("c3 B=6", config_c3(B=6, N_range=(32, 70))),
+             ("c2 N=512", config_c2(N=512)))
+    took_step = False
+    for name, probs in cases:
+        ref_plan = ecl.Plan.for_problems(probs)
+        data = ecl.pack(ref_plan, probs)
+        ws_r = ref_plan.workspace()
+        ref = ecl.solve(ref_plan, data, ws_r)
+        torch.cuda.synchronize()
+        ref_steps, ref_omega = ref_plan.refine_steps(ws_r), ref_plan.backward_error(ws_r)
+        took_step |= bool((ref_steps > 0).any())
+        for graph in (0, 1):
+            plan = ecl.Plan.for_problems(probs, use_graph=graph)
+            ecl.set_tuning(plan, refine_gate=1)
+            assert ecl.get_tuning(plan)["refine_gate"] == 1
+            ws = plan.workspace()
+            sol = ecl.allocate_solution(plan)
+            for rep in range(3):
+                ecl.solve(plan, data, ws, sol)
+                torch.cuda.synchronize()
+                for f in ("x", "u", "lam", "mu", "status"):
+                    assert torch.equal(getattr(sol, f), getattr(ref, f)), (name, graph, rep, f)
+                assert np.array_equal(plan.refine_steps(ws), ref_steps), (name, graph, rep)
+                assert np.array_equal(plan.backward_error(ws), ref_omega), (name, graph, rep)
+                ecl.solve(ref_plan, data, ws_r, ecl.allocate_solution(ref_plan))
+                torch.cuda.synchronize()
+    assert took_step, "no case took a refinement step"
+
+
 def test_autotune_keeps_results():
     """eclqr_plan_autotune picks a launch configuration by timing; every
     configuration it can choose computes the same solution (bitwise)."""
