@@ -846,10 +846,13 @@ eclqr_status solve_all(Plan& p, const Views& v, const Inputs& in, double* x, dou
   }  // kPartRefine
   if (part & kPartTail) {
     Timed tm(ECLQR_K_REFINE_IO, s);
+    // the backward error of the returned point, for the instances a step
+    // changed (the others keep the first pass's figure)
+    unsigned long long* wmax = at<unsigned long long>(v.ws, p.o_wmax);
+    launch_gate_refined(v.rsteps, v.gate, wmax, v.omega, B, s);
+    launch_backward_error(v.P, in, x, u, lam, mu, wmax, v.omega, s, false);
     launch_fill_i32(v.gate, kGateActive, B, s);  // later launches on this workspace run every instance
     launch_fill_i32(v.live, 1, 1, s);
-    launch_fill_u64(v.omega, 0ull, B, s);
-    launch_backward_error(v.P, in, x, u, lam, mu, at<unsigned long long>(v.ws, p.o_wmax), v.omega, s);
     if (!p.inexact_newton)
       launch_flag_unconverged(v.omega, v.rsteps, p.opt.dual_cons_tol, status, ECLQR_DUAL_FAILED, B, s);
     launch_apply_abort(status, at<int32_t>(v.ws, p.o_abort), ECLQR_TIMEOUT, B, s);

@@ -485,6 +485,23 @@ __global__ void __launch_bounds__(kBlock) k_backward_error(DevEngine p, Inputs i
   }
 }
 
+// Before the backward error of the returned point: an instance that took a
+// refinement step is measured again (active, its scale and error cleared);
+// the others are skipped and keep the first pass's figures, which are those
+// of their unchanged solution.
+__global__ void k_gate_refined(const int32_t* steps, int32_t* gate, unsigned long long* wmax,
+                               unsigned long long* omega, int32_t B) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < B; i += gridDim.x * blockDim.x) {
+    if (steps[i] > 0) {
+      gate[i] = kGateActive;
+      wmax[i] = 0ull;
+      omega[i] = 0ull;
+    } else {
+      gate[i] = kGateDone;
+    }
+  }
+}
+
 // Instances still refining whose backward error is <= tol and whose
 // reversed-time solve succeeded are final without a refinement step.
 __global__ void k_accept(const unsigned long long* omega, const int32_t* dstatus, double tol, int32_t* gate,
@@ -827,10 +844,15 @@ void launch_refine_decide(const DevEngine& p, const int64_t* sbase, const double
   hipLaunchKernelGGL(k_refine_decide, dim3(g), dim3(kBlock), 0, s, p, sbase, norms, tol, last, gate, steps);
 }
 void launch_backward_error(const DevEngine& p, const Inputs& in, const double* x, const double* u, const double* lam,
-                           const double* mu, unsigned long long* wmax, unsigned long long* omega, hipStream_t s) {
-  launch_fill_u64(wmax, 0ull, p.B, s);
+                           const double* mu, unsigned long long* wmax, unsigned long long* omega, hipStream_t s,
+                           bool clear) {
+  if (clear) launch_fill_u64(wmax, 0ull, p.B, s);
   hipLaunchKernelGGL(k_unknown_scale, dim3(p.nblocks), dim3(kBlock), 0, s, p, x, u, lam, mu, wmax);
   hipLaunchKernelGGL(k_backward_error, dim3(p.nblocks), dim3(kBlock), 0, s, p, in, x, u, lam, mu, wmax, omega);
+}
+void launch_gate_refined(const int32_t* steps, int32_t* gate, unsigned long long* wmax, unsigned long long* omega,
+                         int32_t B, hipStream_t s) {
+  hipLaunchKernelGGL(k_gate_refined, dim3(grid_for(B)), dim3(256), 0, s, steps, gate, wmax, omega, B);
 }
 void launch_accept(const unsigned long long* omega, const int32_t* dstatus, double tol, int32_t* gate, int32_t B,
                    hipStream_t s) {

@@ -229,8 +229,13 @@ void launch_gate_advance(int32_t* gate, int32_t* live, int32_t B, hipStream_t s)
 // non-negative double, max-accumulated: clear to 0 first)
 // max-accumulates the backward error per instance into omega (wmax: B
 // entries of scratch for the scale of the unknowns)
+// clear = false: the scales of the instances measured were cleared by
+// launch_gate_refined (the others keep theirs)
 void launch_backward_error(const DevEngine& p, const Inputs& in, const double* x, const double* u, const double* lam,
-                           const double* mu, unsigned long long* wmax, unsigned long long* omega, hipStream_t s);
+                           const double* mu, unsigned long long* wmax, unsigned long long* omega, hipStream_t s,
+                           bool clear = true);
+void launch_gate_refined(const int32_t* steps, int32_t* gate, unsigned long long* wmax, unsigned long long* omega,
+                         int32_t B, hipStream_t s);
 void launch_accept(const unsigned long long* omega, const int32_t* dstatus, double tol, int32_t* gate, int32_t B,
                    hipStream_t s);
 void launch_fill_u64(unsigned long long* y, unsigned long long v, int64_t n, hipStream_t s);
