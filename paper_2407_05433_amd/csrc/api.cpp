@@ -283,12 +283,18 @@ std::vector<Engine::StageBucket> stage_buckets(const Engine& E, bool whole = fal
 // buckets, each with its own LDS tile (false: a tile exceeds the device's LDS).
 bool theta_local_all(const Plan& p, const DevEngine& P, const DevEngine& Th, const Inputs& in, const double* x,
                      const double* u, Tols td, int32_t* status, int mode, hipStream_t s) {
+  // the vector-only pass (mode 1) factors terminal stages only: its tile
+  // is theirs, with the bucket's row width
+  const bool vec = mode == 1;
   if (!g_buckets)
-    return launch_theta_local(P, Th, in, x, u, td, status, p.th_q, p.th_ldw, p.th_r, mode, 0, p.primal.S, s);
+    return launch_theta_local(P, Th, in, x, u, td, status, vec ? p.th_vq : p.th_q, p.th_ldw, vec ? p.th_vr : p.th_r,
+                              mode, 0, p.primal.S, s);
   for (size_t b = 0; b < p.primal.sbk.size(); ++b) {
     const auto& sb = p.primal.sbk[b];
     const auto& tb = p.th_bk[b];
-    if (!launch_theta_local(P, Th, in, x, u, td, status, tb[0], tb[1], tb[2], mode, sb.begin, sb.count, s))
+    const auto& vb = p.th_vbk[b];
+    if (!launch_theta_local(P, Th, in, x, u, td, status, vec ? vb[0] : tb[0], tb[1], vec ? vb[1] : tb[2], mode,
+                            sb.begin, sb.count, s))
       return false;
   }
   return true;

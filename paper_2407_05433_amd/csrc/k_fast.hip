@@ -396,6 +396,9 @@ __global__ void __launch_bounds__(kBlock) k_theta_local(DevEngine p, DevEngine t
       const Arena at = arena_layout(ts.n, ts.np, ts.m, ts.k);
       double* tb = th.arena + ts.ws;
       const int f = th.mbar[s], rho = q - f;
+      // the q <= 64 multiplier values in the front of the tile (sized for the
+      // terminal stages this pass factors: at least 16 x 16 + 16 x 17 doubles)
+      double* const Yl = W;
       lds_sync();
       // z = R11^{-T} (P'c)_{1:rho}, y = Q1 z
       const int lane = ECLQR_TID;

@@ -627,6 +627,8 @@ std::string build_plan(Plan& p, const eclqr_dims* d, const eclqr_options* opt) {
     p.overlap_dual = ok ? 0 : 1;
     p.th_q = p.th_ldw = p.th_r = 1;
     p.th_bk.assign(P.sbk.size(), {1, 1, 1});
+    p.th_vq = p.th_vr = 16;
+    p.th_vbk.assign(P.sbk.size(), {16, 16});
     for (size_t b = 0; b < P.sbk.size(); ++b)
       for (int64_t t = P.sbk[b].begin; t < P.sbk[b].begin + P.sbk[b].count; ++t) {
         const StageInfo& x = P.st[P.stage_perm.empty() ? t : P.stage_perm[t]];
@@ -638,6 +640,13 @@ std::string build_plan(Plan& p, const eclqr_dims* d, const eclqr_options* opt) {
         p.th_q = std::max(p.th_q, q);
         p.th_ldw = std::max(p.th_ldw, R | 1);
         p.th_r = std::max(p.th_r, x.n);
+        if (x.terminal) {
+          auto& vb = p.th_vbk[b];
+          vb[0] = std::max(vb[0], q);
+          vb[1] = std::max(vb[1], x.n);
+          p.th_vq = std::max(p.th_vq, q);
+          p.th_vr = std::max(p.th_vr, x.n);
+        }
       }
     // the local systems are factored in one LDS tile per stage: where that
     // tile exceeds the device's LDS the reversed-time route is laid out

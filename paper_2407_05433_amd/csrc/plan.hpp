@@ -119,6 +119,11 @@ struct Plan {
   size_t o_defer = 0;         // per level: count of deferred combines (2 D ints), then one task list
   int32_t th_q = 1, th_ldw = 1, th_r = 1;  // LDS tile of the local minimum-norm systems
   std::vector<std::array<int32_t, 3>> th_bk;  // the same over each stage bucket of the problem (q, ldw, r)
+  // the vector-only pass factors only terminal stages: its tile's (q, r) are
+  // theirs (at least 16 each, so the tile's front also holds any stage's
+  // q <= 64 multiplier values), its ldw the bucket's
+  int32_t th_vq = 16, th_vr = 16;
+  std::vector<std::array<int32_t, 2>> th_vbk;
   int32_t mult_route = 1;     // 1: theta LQR (when theta_ok), 0: reversed-time problem
   // What each workspace holds: the factorizations of the last solve made in
   // it (multiplier route, problem and solution pointers).  eclqr_backward
