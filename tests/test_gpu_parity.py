@@ -444,6 +444,29 @@ def test_refine_gate_same_results():
                 ecl.solve(ref_plan, data, ws_r, ecl.allocate_solution(ref_plan))
                 torch.cuda.synchronize()
     assert took_step, "no case took a refinement step"
+    # the other multiplier routes and the overlapped factorizations, gated
+    probs = config_c3(B=6, N_range=(32, 70))
+    variants = (({}, {"overlap_dual": 1}), ({"reversed_time": 1}, {"multiplier_route": 0, "overlap_dual": 1}),
+                ({"reversed_time": 1}, {"multiplier_route": 0, "overlap_dual": 0}), ({"multipliers": 2}, {}),
+                ({"multipliers": 3}, {}))
+    for opts, tun in variants:
+        ref_plan = ecl.Plan.for_problems(probs, **opts)
+        ecl.set_tuning(ref_plan, **tun)
+        data = ecl.pack(ref_plan, probs)
+        ws_r = ref_plan.workspace()
+        ref = ecl.solve(ref_plan, data, ws_r)
+        torch.cuda.synchronize()
+        for graph in (0, 1):
+            plan = ecl.Plan.for_problems(probs, use_graph=graph, **opts)
+            ecl.set_tuning(plan, refine_gate=1, **tun)
+            ws = plan.workspace()
+            sol = ecl.allocate_solution(plan)
+            for rep in range(2):
+                ecl.solve(plan, data, ws, sol)
+                torch.cuda.synchronize()
+                for f in ("x", "u", "lam", "mu", "status"):
+                    assert torch.equal(getattr(sol, f), getattr(ref, f)), (opts, tun, graph, rep, f)
+                assert np.array_equal(plan.refine_steps(ws), ref_plan.refine_steps(ws_r)), (opts, tun, graph)
 
 
 def test_autotune_keeps_results():
