@@ -292,9 +292,19 @@ void launch_mult_final(const DevEngine& e, double* lam, double* mu, int accumula
 // (the terminal stage: Ym, ym), the reduced LQR data Ab Bb cb Qb Mb Rb qb rb,
 // the gains, and wl = w_i.
 
-// LDS: W (maxq x ldw) | Qg (maxq x maxq) | X (maxq x (maxr+1)) | Yl (maxq x (maxr+1)) |
-// tau (maxq) | qd (ldw + 8) | cr (ldw) | perm (ldw ints) | wi w1 gx gu tmp (kMaxDim each)
-size_t theta_local_lds_bytes(int maxq, int ldw, int maxr) { return (size_t)theta_local_lds(maxq, ldw, maxr); }
+// LDS: W (maxq x max(ldw, maxr + 1)) | Qg (maxq x maxq) | X (maxq x (maxr+1)) |
+// tau (maxq) | qd (ldw + 8) | cr (ldw) | perm (ldw ints) | wi w1 gx gu tmp (kMaxDim each).
+// Yl = Q1 X (q x (r_i + 1)) is formed in W's place once the factorization
+// in W has been read for the last time (the plan sizes the tile with a
+// separate Yl block, an upper bound of this).
+__host__ __device__ inline int64_t theta_w_doubles(int maxq, int ldw, int maxr) {
+  return (int64_t)maxq * (ldw > maxr + 1 ? ldw : maxr + 1);
+}
+size_t theta_local_lds_bytes(int maxq, int ldw, int maxr) {
+  return 8 * (theta_w_doubles(maxq, ldw, maxr) + (int64_t)maxq * maxq + (int64_t)maxq * (maxr + 1) + maxq +
+              2 * (int64_t)ldw + 8 + 5 * kMaxDim) +
+         4 * (int64_t)(ldw + 1) + 64;
+}
 
 // kMode 0: full pass.  kMode 1: vector-only pass for new vectors with the
 // same matrices (refinement corrections, the adjoint, the solution after a
@@ -314,10 +324,10 @@ __global__ void __launch_bounds__(kBlock) k_theta_local(DevEngine p, DevEngine t
   constexpr bool kMat = kMode == 2;
   extern __shared__ double lds[];
   double* W = lds;
-  double* Qg = W + (int64_t)maxq * ldw;
+  double* Qg = W + theta_w_doubles(maxq, ldw, maxr);
   double* X = Qg + (int64_t)maxq * maxq;
-  double* Yl = X + (int64_t)maxq * (maxr + 1);
-  double* tau = Yl + (int64_t)maxq * (maxr + 1);
+  double* const Yl = W;  // after the last read of the factorization in W
+  double* tau = X + (int64_t)maxq * (maxr + 1);
   double* qd = tau + maxq;
   double* cr = qd + ldw + 8;
   double* wi = cr + ldw;
@@ -396,9 +406,8 @@ __global__ void __launch_bounds__(kBlock) k_theta_local(DevEngine p, DevEngine t
       const Arena at = arena_layout(ts.n, ts.np, ts.m, ts.k);
       double* tb = th.arena + ts.ws;
       const int f = th.mbar[s], rho = q - f;
-      // the q <= 64 multiplier values in the front of the tile (sized for the
-      // terminal stages this pass factors: at least 16 x 16 + 16 x 17 doubles)
-      double* const Yl = W;
+      // Yl: the q <= 64 multiplier values in the front of the tile (sized
+      // for the terminal stages this pass factors: at least 16 x 17 doubles)
       lds_sync();
       // z = R11^{-T} (P'c)_{1:rho}, y = Q1 z
       const int lane = ECLQR_TID;
@@ -497,12 +506,18 @@ __global__ void __launch_bounds__(kBlock) k_theta_local(DevEngine p, DevEngine t
       }
       if (bad) flag(status, st.inst, ECLQR_RANK_INCONSISTENT);
     }
-    // Yl = Q1 X (q x (r_i + 1)): [Y | y]
-    wg_gemm(Yl, nc, Qg, q, false, X, nc, false, q, nc, rho, 1.0, 0.0);
     // theta engine arena
-    // [Y | y] in the fields Y, y (capacity k + n') of a stage, Ym, ym (k x n) at the terminal
     const Arena at = arena_layout(ts.n, ts.np, ts.m, ts.k);
     double* tb = th.arena + ts.ws;
+    if (!term)  // R11 of the minimum-norm solve, read before Yl takes W's place
+      for (int idx = ECLQR_TID; idx < rho * rho; idx += ECLQR_NT) {
+        const int i = idx / rho, j = idx - (idx / rho) * rho;
+        tb[at.R11 + idx] = (j >= i) ? W[i * ldw + j] : 0.0;
+      }
+    wg_sync();
+    // Yl = Q1 X (q x (r_i + 1)): [Y | y]
+    wg_gemm(Yl, nc, Qg, q, false, X, nc, false, q, nc, rho, 1.0, 0.0);
+    // [Y | y] in the fields Y, y (capacity k + n') of a stage, Ym, ym (k x n) at the terminal
     double* Ya = tb + (term ? at.Ym : at.Y);
     double* ya = tb + (term ? at.ym : at.y);
     for (int idx = ECLQR_TID; idx < q * ri; idx += ECLQR_NT) Ya[idx] = Yl[(idx / ri) * nc + idx % ri];
@@ -512,10 +527,6 @@ __global__ void __launch_bounds__(kBlock) k_theta_local(DevEngine p, DevEngine t
       for (int idx = ECLQR_TID; idx < q * f; idx += ECLQR_NT) Na[idx] = Qg[(idx / f) * q + rho + idx % f];
       // factors of the minimum-norm solve, for the vector-only passes
       for (int j = ECLQR_TID; j < rho; j += ECLQR_NT) tb[at.prm + j] = (double)perm[j];
-      for (int idx = ECLQR_TID; idx < rho * rho; idx += ECLQR_NT) {
-        const int i = idx / rho, j = idx - (idx / rho) * rho;
-        tb[at.R11 + idx] = (j >= i) ? W[i * ldw + j] : 0.0;
-      }
       for (int idx = ECLQR_TID; idx < q * rho; idx += ECLQR_NT) tb[at.Q1 + idx] = Qg[(idx / rho) * q + idx % rho];
     }
     for (int a = ECLQR_TID; a < n; a += ECLQR_NT) tb[at.wl + a] = wi[a];
