@@ -5,6 +5,7 @@
 #include "device_util.hpp"
 #include "eclqr.h"
 #include "relreg.hpp"
+#include "scratch.hpp"
 
 namespace eclqr {
 
@@ -640,6 +641,11 @@ static bool rel_global(const DevEngine& e, int maxp, int ldw) {
   return rel_lds_bytes(maxp, ldw) > (size_t)g_rel_max_lds && e.gw && (int64_t)maxp * (ldw | 1) <= e.gw_stride;
 }
 static size_t rel_tile_bytes(int maxp, int ldw) { return sizeof(double) * (size_t)maxp * (ldw | 1); }
+// compositions: the global tile already above kRelComposeLds
+static bool rel_global_compose(const DevEngine& e, int maxp, int ldw) {
+  return (rel_lds_bytes(maxp, ldw) > (size_t)kRelComposeLds && e.gw && (int64_t)maxp * (ldw | 1) <= e.gw_stride) ||
+         rel_global(e, maxp, ldw);
+}
 
 void launch_base_relation(const DevEngine& e, const Inputs& in, Tols t, int32_t* status, int maxp, int ldw,
                           int64_t first, int64_t count, hipStream_t s) {
@@ -685,7 +691,7 @@ void launch_rel_compose(const DevEngine& e, int64_t first, int64_t ntasks, Tols 
 #undef ECLQR_REG
     return;
   }
-  if (rel_global(e, maxp, ldw)) {
+  if (rel_global_compose(e, maxp, ldw)) {
     const int g2 = grid < e.gw_blocks ? grid : e.gw_blocks;
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rel_compose<true>), dim3(g2), dim3(kBlock),
                        rel_lds_bytes(maxp, ldw) - rel_tile_bytes(maxp, ldw), s, e, first, ntasks, t, status, maxp, ldw);

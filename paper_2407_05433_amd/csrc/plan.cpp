@@ -513,19 +513,26 @@ std::string Engine::build(const eclqr_dims* d) {
   }
   nblocks = (int32_t)std::min<int64_t>(std::max<int64_t>(S, 1), 8192);
 
-  // global tiles for stacked relation systems that may outgrow LDS (48 KiB
-  // and more: the device's LDS also holds the small work arrays)
+  // global tiles for stacked relation systems: base relations that may
+  // outgrow LDS (48 KiB and more: the device's LDS also holds the small work
+  // arrays), and compositions whose LDS tile would exceed kRelComposeLds
+  // (there a tile in global memory per workgroup, at many workgroups per
+  // compute unit, is faster than LDS at a few), one tile per workgroup of
+  // the widest launch (at most the stage-parallel grid)
   gw_stride = 0;
   gw_blocks = 0;
   if (need_rel) {
-    int64_t tile = (int64_t)base_maxp * (base_ldw | 1), widest = S;
+    const int64_t btile = (int64_t)base_maxp * (base_ldw | 1);
+    int64_t ctile = 0, widest = S;
     for (size_t l = 0; l < lvl_rows.size(); ++l) {
-      tile = std::max(tile, (int64_t)lvl_rows[l] * (lvl_ldw[l] | 1));
+      ctile = std::max(ctile, (int64_t)lvl_rows[l] * (lvl_ldw[l] | 1));
       widest = std::max(widest, lvl_count[l]);
     }
-    if ((int64_t)sizeof(double) * tile > 48 * 1024) {
-      gw_stride = rup4(tile);
-      gw_blocks = (int32_t)std::min<int64_t>(256, std::max<int64_t>(1, widest));
+    const bool big_base = (int64_t)sizeof(double) * btile > 48 * 1024;
+    const bool big_compose = (int64_t)sizeof(double) * ctile > kRelComposeLds;
+    if (big_base || big_compose) {
+      gw_stride = rup4(std::max(btile, ctile));
+      gw_blocks = (int32_t)std::min<int64_t>(big_compose ? 8192 : 256, std::max<int64_t>(1, widest));
     }
   }
 

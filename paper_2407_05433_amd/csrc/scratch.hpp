@@ -63,6 +63,12 @@ ECLQR_HD inline int64_t gains_scratch(int n, int np, int m) {
 // solve time rather than launched past its limit.
 constexpr int64_t kDeviceLdsBytes = 160 * 1024;
 
+// Stacked systems of relation compositions whose LDS tile would exceed this
+// run in a per-workgroup tile of global memory instead (measured on the
+// 512-instance batch: tiles of up to 56 KiB at two workgroups per compute
+// unit, 4.8 ms of compositions in LDS against 4.4 in global memory).
+constexpr int64_t kRelComposeLds = 24 * 1024;
+
 // LDS bytes of the minimum-norm local systems of the theta route
 // (k_theta_local): the stacked system maxq x ldw, its Q factor, two
 // maxq x (maxr + 1) blocks, vectors and pivots.
